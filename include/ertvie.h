@@ -1,0 +1,174 @@
+/*
+ * ertvie.h -- C ABI of the MI355X volume-integral solver for isotropic
+ * radiative transport (Ren, Zhang, Zhong, "A fast algorithm for radiative
+ * transport in isotropic media").
+ *
+ * Problem (Sec. 2): on a uniform cell-centred grid, the angular density U
+ * solves the second-kind integral equation (I - K) U = phi with
+ * K u = G(sigma_s u) and phi = G f (eq. EQ:ERT Intgrl U / EQ:ERT Intgrl FMM,
+ * Algorithm 1 step S.1 "analytically"), where G is the integral operator with
+ * the transport kernel
+ *
+ *     G(x,y) = exp(-tau(x,y)) / (|S^{d-1}| |x-y|^{d-1}),   |S^1| = 2 pi, |S^2| = 4 pi,
+ *
+ * and tau(x,y) the line integral of sigma_t along the segment (eq. EQ:Kernel
+ * without the sigma_s factor).  The discrete operator is the collocation
+ * matrix of Sec. 3.2, approach (M-iii): A_jk = h^d G(x_j,x_k) for j != k and
+ * an explicitly integrated singular diagonal A_jj = (1/|S^{d-1}|) * integral
+ * over the own cell of E(x_j,y)/|x_j-y|^{d-1} dy.
+ *
+ * Grid convention: dim 2 or 3, n[a] cells per axis, side h, domain
+ * [0, n[a] h]; cell (i0,i1,i2) has centre h (i + 1/2) and linear index
+ * j = i0 + n0 (i1 + n1 i2) (x fastest).  N = product of n[a].
+ * Vectors are FP64, N x nrhs, column-major (column b starts at b*N).
+ *
+ * Memory ownership: sigma_t / sigma_s passed to ert_vie_plan are HOST arrays
+ * that the plan copies; every vector passed to apply/solve is a DEVICE
+ * pointer owned by the caller (e.g. a torch tensor's data_ptr()).  The plan
+ * owns every internal buffer (grids, expansions, operators, caches,
+ * workspaces) and frees them in ert_vie_destroy.  All device work of a plan
+ * is ordered on the HIP stream given at plan time; apply returns without
+ * synchronising, solve synchronises (it needs scalars on the host).
+ * A plan is not thread-safe: one host thread at a time per plan.
+ *
+ * Errors: every call returns an ert_status; nothing throws across the ABI.
+ * Invalid arguments return ERT_EINVAL and leave outputs untouched.
+ */
+#ifndef ERTVIE_H
+#define ERTVIE_H
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ERT_API __attribute__((visibility("default")))
+#else
+#define ERT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ert_vie_plan_s* ert_vie_plan_t;
+
+typedef enum {
+    ERT_OK = 0,
+    ERT_EINVAL = -1,        /* bad argument: dim, sizes, h, coefficients, nrhs, null pointer */
+    ERT_ENOMEM = -2,        /* device or host allocation failed */
+    ERT_EDEVICE = -3,       /* a HIP call failed (no device, launch error, ...) */
+    ERT_ENOCONV = -4,       /* solve stopped at max_iter; best iterate and info are written */
+    ERT_EUNSUPPORTED = -5   /* valid request this build does not provide */
+} ert_status;
+
+typedef enum {
+    /* tau = sigma_t |x-y| with constant sigma_t (eq. EQ:Kernel Cons); every
+     * sigma_t value must be equal */
+    ERT_K_HOMOGENEOUS = 0,
+    /* tau by the midpoint rule with m = smallest integer such that |x-y|/m <= h/2,
+     * sampling the d-linear interpolant of the cell-centred sigma_t with each
+     * coordinate clamped to [h/2, n_a h - h/2] (Sec. 4.2: a local second-order
+     * rule for the line integral of gridded sigma_t) */
+    ERT_K_RAY_MIDPOINT = 1
+} ert_kernel;
+
+typedef enum {
+    ERT_DIRECT = 0,   /* dense O(N^2) summation of the collocation matrix */
+    ERT_FMM = 1       /* Chebyshev-interpolation fast multipole method (Sec. 3.3) */
+} ert_method;
+
+typedef enum {
+    ERT_FP64 = 0,     /* everything in FP64 */
+    ERT_FP32 = 1,     /* near and far field in FP32, self term and assembly in FP64 */
+    ERT_BF16X3 = 2    /* as FP32, with the far-field translations as split-BF16x3 MFMA */
+} ert_prec;
+
+typedef enum {
+    ERT_OP_G = 0,     /* y = A x             (phi = A f: Algorithm 1, step S.1) */
+    ERT_OP_GS = 1,    /* y = A (sigma_s x)   (the paper's K applied to x) */
+    ERT_OP_A = 2      /* y = x - A (sigma_s x)  (the operator I - K of step S.2) */
+} ert_op;
+
+typedef struct {
+    int dim;          /* 2 or 3 */
+    int n[3];         /* cells per axis (n[2] ignored for dim 2), each >= 1, N >= 2 */
+    double h;         /* cell side, > 0 */
+    int kernel;       /* ert_kernel */
+    int method;       /* ert_method used by ert_vie_apply and the solver */
+    int prec;         /* ert_prec used by ert_vie_apply and the solver */
+    int cheb_n;       /* FMM: Chebyshev nodes per axis (Sec. 3.3, n); 0 -> 6; 2..8 */
+    int leaf;         /* FMM: cells per leaf-box side; 0 -> 4 (3D) / 8 (2D) */
+    int nrhs_max;     /* largest nrhs later passed to apply/solve; 0 -> 1 */
+    int flags;        /* reserved, must be 0 */
+} ert_vie_opts;
+
+typedef struct {
+    double tol;       /* stop when ||phi - (I - K) U||_2 <= tol ||phi||_2 (true residual); 0 -> 1e-8 */
+    int max_iter;     /* total Arnoldi steps (all restarts / inner solves); 0 -> 500 */
+    int restart;      /* Krylov dimension per cycle; 0 -> unrestarted (max_iter) */
+    int mixed;        /* 1: iterative refinement -- FP64 outer residual with the plan's
+                         FP64 operator, inner GMRES on the FP32 operator */
+    double inner_tol; /* mixed: relative tolerance of each inner solve; 0 -> 1e-5 */
+    int rhs_is_phi;   /* 1: the f argument already holds phi (skip step S.1) */
+    int reserved[4];  /* must be 0 */
+} ert_solve_opts;
+
+typedef struct {
+    int iters;            /* Arnoldi steps taken (inner steps for mixed) */
+    int matvecs;          /* operator applications, including phi and true residuals */
+    int converged;        /* 1 if the true relative residual met tol */
+    int restarts;         /* GMRES cycles after the first (refinement steps for mixed) */
+    double rel_resid_est; /* last Arnoldi estimate */
+    double rel_resid_true;/* ||phi - (I - K) U|| / ||phi|| with the plan's operator */
+    double t_solve;       /* seconds, host wall clock, phi included */
+} ert_solve_info;
+
+/* Build a plan: validate and copy the media, place the collocation grid and
+ * integrate the singular diagonal (FP64, on the device).  FMM data (tree,
+ * translation operators, caches) are built on first FMM use of each precision.
+ *   opts     : host pointer, read only.
+ *   sigma_t  : host, N values, finite and > 0 (total attenuation, Sec. 2 mu).
+ *   sigma_s  : host, N values, 0 <= sigma_s <= sigma_t (1 + 1e-12) (scattering, mu_s;
+ *              absorption mu_a = sigma_t - sigma_s >= 0).
+ *   hip_stream: hipStream_t for all work of the plan (NULL = default stream).
+ *   out      : receives the plan handle.
+ * Returns ERT_EINVAL for dim not 2/3, n < 1, N < 2, h <= 0, bad coefficients,
+ * non-constant sigma_t with ERT_K_HOMOGENEOUS, cheb_n outside 2..8 or flags != 0. */
+ERT_API ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const double* sigma_s,
+                        void* hip_stream, ert_vie_plan_t* out);
+
+/* y = op(x) with the plan's method and precision (Sec. 3.2 eq. EQ: LINEAR SYSTEM;
+ * FMM per Sec. 3.3).  x, y: device, N x nrhs column-major FP64, must not
+ * overlap.  1 <= nrhs <= nrhs_max.  Stream-ordered, asynchronous. */
+ERT_API ert_status ert_vie_apply(ert_vie_plan_t plan, int op, const double* x, double* y, int nrhs);
+
+/* As ert_vie_apply with an explicit method (ert_method) and precision (ert_prec). */
+ERT_API ert_status ert_vie_apply_ex(ert_vie_plan_t plan, int op, int method, int prec,
+                            const double* x, double* y, int nrhs);
+
+/* Algorithm 1 steps S.1-S.2: phi = A f, then GMRES (x0 = 0) for (I - K) U = phi.
+ *   f, U : device, N x nrhs column-major FP64 (nrhs columns solved one after another).
+ *   opts : host, may be NULL for defaults.  info: host, may be NULL (last column's info).
+ * Returns ERT_ENOCONV when max_iter is reached first; U then holds the best iterate. */
+ERT_API ert_status ert_vie_solve(ert_vie_plan_t plan, const double* f, double* U, int nrhs,
+                         const ert_solve_opts* opts, ert_solve_info* info);
+
+/* Copy the diagonal A_jj (N values, FP64) to host memory `d` (synchronises). */
+ERT_API ert_status ert_vie_diag(ert_vie_plan_t plan, double* d);
+
+/* Number of collocation points N of a plan, or -1 for a null plan. */
+ERT_API long ert_vie_size(ert_vie_plan_t plan);
+
+/* Release the plan and everything it owns.  NULL is a no-op. */
+ERT_API void ert_vie_destroy(ert_vie_plan_t plan);
+
+/* Text describing the most recent failure in this thread (the failing HIP call
+ * and its error string, or the argument check that rejected a call); "" if none.
+ * The pointer stays valid until the next failing call in the same thread. */
+ERT_API const char* ert_vie_last_error(void);
+
+/* Static, human-readable text for a status code. */
+ERT_API const char* ert_vie_strerror(ert_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ERTVIE_H */

@@ -409,26 +409,30 @@ void oracle_matrix(int dim, const long* n, double h, int kernel, const double* s
 /* ---- the apply ------------------------------------------------------------ */
 
 /* One row of the apply for every right-hand side.  x is N x nrhs column-major;
- * the sum over k runs in index order with Neumaier compensation. */
+ * each entry A_jk is formed once and applied to all columns; the sum over k
+ * runs in index order with Neumaier compensation per column. */
 static void og_row(const og_t* g, const double* ss, int op, const double* x, long N, int nrhs,
                    const double* diag, long j, double* out /* nrhs, stride ostride */, long ostride)
 {
     double hd = (g->dim == 2) ? g->h * g->h : g->h * g->h * g->h;
-    for (int b = 0; b < nrhs; ++b) {
-        const double* xb = x + (long)b * N;
-        double sum = 0.0, comp = 0.0;
-        for (long k = 0; k < N; ++k) {
-            double wk = (op == 0) ? xb[k] : ss[k] * xb[k];
-            double a = (k == j) ? diag[j] : hd * og_kernel_cells(g, j, k);
-            double term = a * wk;
-            double t = sum + term;
-            if (fabs(sum) >= fabs(term)) comp += (sum - t) + term;
-            else comp += (term - t) + sum;
-            sum = t;
+    double* sum = (double*)calloc((size_t)nrhs * 2, sizeof(double));
+    double* comp = sum + nrhs;
+    for (long k = 0; k < N; ++k) {
+        double a = (k == j) ? diag[j] : hd * og_kernel_cells(g, j, k);
+        double sk = (op == 0) ? 1.0 : ss[k];
+        for (int b = 0; b < nrhs; ++b) {
+            double term = a * (sk * x[(long)b * N + k]);
+            double t = sum[b] + term;
+            if (fabs(sum[b]) >= fabs(term)) comp[b] += (sum[b] - t) + term;
+            else comp[b] += (term - t) + sum[b];
+            sum[b] = t;
         }
-        double y = sum + comp;
-        out[(long)b * ostride] = (op == 2) ? xb[j] - y : y;
     }
+    for (int b = 0; b < nrhs; ++b) {
+        double y = sum[b] + comp[b];
+        out[(long)b * ostride] = (op == 2) ? x[(long)b * N + j] - y : y;
+    }
+    free(sum);
 }
 
 void oracle_apply(int dim, const long* n, double h, int kernel, const double* st,

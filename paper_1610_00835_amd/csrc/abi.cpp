@@ -1,0 +1,466 @@
+// C ABI of the library (include/ertvie.h): plan construction and validation,
+// operator dispatch, and the Krylov solvers of Algorithm 1 step S.2 driven
+// from the host with FP64 device vectors.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ertvie {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void record_hip_error(const char* what, hipError_t e, const char* file, int line)
+{
+    g_last_error = std::string(what) + " failed: " + hipGetErrorString(e) + " (" + file + ":" +
+                   std::to_string(line) + ")";
+}
+
+void record_error(const char* msg) { g_last_error = msg; }
+
+// Gauss-Legendre rule on [-1,1]: Newton iteration on P_n from Chebyshev-like
+// initial guesses, weights 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double pn = 0.0, dpn = 1.0;
+        for (int it = 0; it < 200; ++it) {
+            double pm1 = 1.0, p = z;
+            for (int k = 1; k < n; ++k) {
+                double pk1 = ((2 * k + 1) * z * p - k * pm1) / (k + 1);
+                pm1 = p;
+                p = pk1;
+            }
+            pn = p;
+            dpn = n * (z * p - pm1) / (z * z - 1.0);
+            double dz = pn / dpn;
+            z -= dz;
+            if (std::fabs(dz) <= 1e-16 * std::fabs(z) + 1e-300) break;
+        }
+        {
+            double pm1 = 1.0, p = z;
+            for (int k = 1; k < n; ++k) {
+                double pk1 = ((2 * k + 1) * z * p - k * pm1) / (k + 1);
+                pm1 = p;
+                p = pk1;
+            }
+            dpn = n * (z * p - pm1) / (z * z - 1.0);
+        }
+        double wi = 2.0 / ((1.0 - z * z) * dpn * dpn);
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = wi;
+        w[n - 1 - i] = wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+namespace {
+
+ert_status apply_dispatch(ert_plan_impl* p, int op, int method, int prec, const double* x, double* y, int nrhs)
+{
+    if (method == ERT_DIRECT) return direct_apply(p, op, prec, x, y, nrhs);
+    return fmm_apply(p, op, prec, x, y, nrhs);
+}
+
+ert_status ensure_workspace(ert_plan_impl* p, size_t vec_elems, size_t red_elems)
+{
+    if (vec_elems > p->ws_elems) {
+        if (p->d_ws) (void)hipFree(p->d_ws);
+        p->d_ws = nullptr;
+        p->ws_elems = 0;
+        if (hipMalloc(&p->d_ws, vec_elems * sizeof(double)) != hipSuccess) return ERT_ENOMEM;
+        p->ws_elems = vec_elems;
+    }
+    if (red_elems > p->red_elems) {
+        if (p->d_red) (void)hipFree(p->d_red);
+        p->d_red = nullptr;
+        p->red_elems = 0;
+        if (hipMalloc(&p->d_red, red_elems * sizeof(double)) != hipSuccess) return ERT_ENOMEM;
+        p->red_elems = red_elems;
+    }
+    return ERT_OK;
+}
+
+constexpr int kPartials = 240;   // matches the reduction block count of blas.hip (upper bound)
+
+double dev_norm(ert_plan_impl* p, const double* v, double* partial, double* out_dev, ert_status* st)
+{
+    *st = dev_multidot(p->stream, v, p->N, 1, v, p->N, partial, out_dev);
+    if (*st != ERT_OK) return 0.0;
+    double h = 0.0;
+    if (hipMemcpyAsync(&h, out_dev, sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess) {
+        *st = ERT_EDEVICE;
+        return 0.0;
+    }
+    return std::sqrt(h);
+}
+
+struct RunStats {
+    int iters = 0, matvecs = 0, cycles = 0;
+    double est = 0.0, true_rel = -1.0;
+    bool converged = false;
+};
+
+// GMRES (x0 = 0) for (I - K) u = b with the operator (method, prec).  Arnoldi by
+// classical Gram-Schmidt with one re-orthogonalisation on the device, Givens
+// rotations and the small triangular solve on the host.  Stops when the
+// recurrence estimate reaches rtol ||b||; with check_true it then confirms the
+// true residual with the same operator and restarts from u if needed.
+ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, double* u, double rtol, int maxit,
+                     int restart, bool check_true, RunStats* rs)
+{
+    const long N = p->N;
+    const int m = (restart > 0 && restart < maxit) ? restart : maxit;
+    // workspace: V (m+1 vectors), w, r
+    ERT_TRY(ensure_workspace(p, (size_t)(m + 3) * N, (size_t)kPartials * (m + 2) + 4 * (size_t)(m + 2)));
+    double* V = p->d_ws;
+    double* w = V + (size_t)(m + 1) * N;
+    double* r = w + N;
+    double* partial = p->d_red;
+    double* dh = partial + (size_t)kPartials * (m + 2);    // h1 (m+1) then h2 (m+1) then norm
+    double* dh2 = dh + (m + 2);
+    double* dy = dh2 + (m + 2);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hh(m + 2);
+    ert_status st = ERT_OK;
+
+    ERT_TRY(dev_zero(p->stream, u, N));
+    double bnorm = dev_norm(p, b, partial, dh, &st);
+    ERT_TRY(st);
+    if (bnorm == 0.0) {
+        rs->converged = true;
+        rs->true_rel = 0.0;
+        return ERT_OK;
+    }
+    double beta = bnorm;
+    const double* rsrc = b;
+    for (int cycle = 0; rs->iters < maxit; ++cycle) {
+        rs->cycles = cycle + 1;
+        ERT_TRY(dev_scale(p->stream, V, rsrc, 1.0 / beta, N));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool done = false;
+        for (int j = 0; j < m && rs->iters < maxit; ++j) {
+            double* vj = V + (size_t)j * N;
+            ERT_TRY(apply_dispatch(p, ERT_OP_A, method, prec, vj, w, 1));
+            rs->matvecs++;
+            ERT_TRY(dev_multidot(p->stream, V, N, j + 1, w, N, partial, dh));
+            ERT_TRY(dev_gemv_sub(p->stream, V, N, j + 1, dh, w, N));
+            ERT_TRY(dev_multidot(p->stream, V, N, j + 1, w, N, partial, dh2));
+            ERT_TRY(dev_gemv_sub(p->stream, V, N, j + 1, dh2, w, N));
+            ERT_TRY(dev_small_add(p->stream, dh, dh2, j + 1));
+            ERT_TRY(dev_multidot(p->stream, w, N, 1, w, N, partial, dh + j + 1));
+            ERT_HIP(hipMemcpyAsync(hh.data(), dh, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, p->stream));
+            ERT_HIP(hipStreamSynchronize(p->stream));
+            const double hn = std::sqrt(hh[j + 1] > 0.0 ? hh[j + 1] : 0.0);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[(size_t)j * m + j];
+            double den = std::hypot(a, hn);
+            cs[j] = den == 0.0 ? 1.0 : a / den;
+            sn[j] = den == 0.0 ? 0.0 : hn / den;
+            H[(size_t)j * m + j] = den;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            rs->iters++;
+            k = j + 1;
+            rs->est = std::fabs(g[j + 1]) / bnorm;
+            if (rs->est <= rtol || hn == 0.0) { done = true; break; }
+            ERT_TRY(dev_scale(p->stream, V + (size_t)(j + 1) * N, w, 1.0 / hn, N));
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        ERT_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, p->stream));
+        ERT_TRY(dev_gemv_add(p->stream, V, N, k, dy, u, N));
+        if (!check_true) {
+            if (done) rs->converged = true;
+            if (done) break;
+            // restart from the recurrence residual direction: recompute r with the operator
+        }
+        ERT_TRY(apply_dispatch(p, ERT_OP_A, method, prec, u, w, 1));
+        rs->matvecs++;
+        ERT_TRY(dev_sub(p->stream, r, b, w, N));
+        beta = dev_norm(p, r, partial, dh, &st);
+        ERT_TRY(st);
+        rs->true_rel = beta / bnorm;
+        if (rs->true_rel <= rtol) { rs->converged = true; break; }
+        if (beta == 0.0) { rs->converged = true; break; }
+        rsrc = r;
+    }
+    ERT_HIP(hipStreamSynchronize(p->stream));
+    return ERT_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+}  // namespace ertvie
+
+using namespace ertvie;
+
+extern "C" {
+
+const char* ert_vie_last_error(void) { return g_last_error.c_str(); }
+
+const char* ert_vie_strerror(ert_status s)
+{
+    switch (s) {
+    case ERT_OK: return "ok";
+    case ERT_EINVAL: return "invalid argument";
+    case ERT_ENOMEM: return "out of memory";
+    case ERT_EDEVICE: return "HIP device error";
+    case ERT_ENOCONV: return "solver did not converge within max_iter";
+    case ERT_EUNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+long ert_vie_size(ert_vie_plan_t plan) { return plan ? plan->N : -1; }
+
+void ert_vie_destroy(ert_vie_plan_t p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    for (auto& f : p->fmm) {
+        if (f) fmm_destroy(f);
+        f = nullptr;
+    }
+    (void)hipFree(p->d_st);
+    (void)hipFree(p->d_st32);
+    (void)hipFree(p->d_ss);
+    (void)hipFree(p->d_diag);
+    (void)hipFree(p->d_ws);
+    (void)hipFree(p->d_red);
+    delete p;
+}
+
+ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const double* sigma_s, void* hip_stream,
+                        ert_vie_plan_t* out)
+{
+    record_error("ert_vie_plan: invalid argument");
+    if (!opts || !sigma_t || !sigma_s || !out) return ERT_EINVAL;
+    const ert_vie_opts& o = *opts;
+    if (o.dim != 2 && o.dim != 3) return ERT_EINVAL;
+    if (!finite_pos(o.h) || o.flags != 0) return ERT_EINVAL;
+    if (o.kernel != ERT_K_HOMOGENEOUS && o.kernel != ERT_K_RAY_MIDPOINT) return ERT_EINVAL;
+    if (o.method != ERT_DIRECT && o.method != ERT_FMM) return ERT_EINVAL;
+    if (o.prec != ERT_FP64 && o.prec != ERT_FP32 && o.prec != ERT_BF16X3) return ERT_EINVAL;
+    if (o.cheb_n != 0 && (o.cheb_n < 2 || o.cheb_n > 8)) return ERT_EINVAL;
+    if (o.leaf < 0 || o.leaf > 64 || o.nrhs_max < 0) return ERT_EINVAL;
+    long N = 1;
+    for (int a = 0; a < o.dim; ++a) {
+        if (o.n[a] < 1 || o.n[a] > (1 << 20)) return ERT_EINVAL;
+        N *= o.n[a];
+        if (N > (1L << 30)) return ERT_EINVAL;
+    }
+    if (N < 2) return ERT_EINVAL;
+    record_error("ert_vie_plan: invalid coefficients (need finite sigma_t > 0, 0 <= sigma_s <= sigma_t, "
+                 "constant sigma_t for the homogeneous kernel)");
+    for (long j = 0; j < N; ++j) {
+        const double t = sigma_t[j], s = sigma_s[j];
+        if (!finite_pos(t) || !std::isfinite(s) || s < 0.0 || s > t * (1.0 + 1e-12)) return ERT_EINVAL;
+        if (o.kernel == ERT_K_HOMOGENEOUS && t != sigma_t[0]) return ERT_EINVAL;
+    }
+    int ndev = 0;
+    hipError_t de = hipGetDeviceCount(&ndev);
+    if (de != hipSuccess || ndev < 1) {
+        record_hip_error("hipGetDeviceCount", de != hipSuccess ? de : hipErrorNoDevice, __FILE__, __LINE__);
+        return ERT_EDEVICE;
+    }
+
+    record_error("");
+    ert_vie_plan_s* p = new (std::nothrow) ert_vie_plan_s();
+    if (!p) return ERT_ENOMEM;
+    p->o = o;
+    if (p->o.dim == 2) p->o.n[2] = 1;
+    p->geo.dim = o.dim;
+    p->geo.n0 = o.n[0];
+    p->geo.n1 = o.n[1];
+    p->geo.n2 = o.dim > 2 ? o.n[2] : 1;
+    p->geo.h = o.h;
+    p->N = N;
+    p->nrhs_max = o.nrhs_max > 0 ? o.nrhs_max : 1;
+    p->stream = (hipStream_t)hip_stream;
+    p->sigma_const = sigma_t[0];
+    p->h_st.assign(sigma_t, sigma_t + N);
+    p->h_ss.assign(sigma_s, sigma_s + N);
+    std::vector<float> st32(N);
+    for (long j = 0; j < N; ++j) st32[j] = (float)sigma_t[j];
+
+    ert_status st = ERT_OK;
+    do {
+        if (hipMalloc(&p->d_st, N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&p->d_st32, N * sizeof(float)) != hipSuccess ||
+            hipMalloc(&p->d_ss, N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&p->d_diag, N * sizeof(double)) != hipSuccess) {
+            record_error("ert_vie_plan: device allocation failed");
+            st = ERT_ENOMEM;
+            break;
+        }
+        st = ERT_HIPST(hipMemcpyAsync(p->d_st, sigma_t, N * sizeof(double), hipMemcpyHostToDevice, p->stream));
+        if (st == ERT_OK)
+            st = ERT_HIPST(hipMemcpyAsync(p->d_st32, st32.data(), N * sizeof(float), hipMemcpyHostToDevice,
+                                          p->stream));
+        if (st == ERT_OK)
+            st = ERT_HIPST(hipMemcpyAsync(p->d_ss, sigma_s, N * sizeof(double), hipMemcpyHostToDevice, p->stream));
+        if (st != ERT_OK) break;
+        st = selfcell_compute(p);
+    } while (0);
+    if (st != ERT_OK) {
+        ert_vie_destroy(p);
+        return st;
+    }
+    *out = p;
+    return ERT_OK;
+}
+
+ert_status ert_vie_apply_ex(ert_vie_plan_t p, int op, int method, int prec, const double* x, double* y, int nrhs)
+{
+    if (!p || !x || !y) return ERT_EINVAL;
+    if (op < ERT_OP_G || op > ERT_OP_A) return ERT_EINVAL;
+    if (method != ERT_DIRECT && method != ERT_FMM) return ERT_EINVAL;
+    if (prec != ERT_FP64 && prec != ERT_FP32 && prec != ERT_BF16X3) return ERT_EINVAL;
+    if (nrhs < 1 || nrhs > p->nrhs_max) return ERT_EINVAL;
+    return apply_dispatch(p, op, method, prec, x, y, nrhs);
+}
+
+ert_status ert_vie_apply(ert_vie_plan_t p, int op, const double* x, double* y, int nrhs)
+{
+    if (!p) return ERT_EINVAL;
+    return ert_vie_apply_ex(p, op, p->o.method, p->o.prec, x, y, nrhs);
+}
+
+ert_status ert_vie_diag(ert_vie_plan_t p, double* d)
+{
+    if (!p || !d) return ERT_EINVAL;
+    ERT_HIP(hipMemcpyAsync(d, p->d_diag, p->N * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    ERT_HIP(hipStreamSynchronize(p->stream));
+    return ERT_OK;
+}
+
+ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs, const ert_solve_opts* sopts,
+                         ert_solve_info* info)
+{
+    if (!p || !f || !U) return ERT_EINVAL;
+    if (nrhs < 1 || nrhs > p->nrhs_max) return ERT_EINVAL;
+    ert_solve_opts so;
+    std::memset(&so, 0, sizeof(so));
+    if (sopts) so = *sopts;
+    if (so.tol == 0.0) so.tol = 1e-8;
+    if (so.max_iter == 0) so.max_iter = 500;
+    if (so.inner_tol == 0.0) so.inner_tol = 1e-5;
+    if (!(so.tol > 0.0) || so.max_iter < 1 || so.restart < 0 || !(so.inner_tol > 0.0) || so.inner_tol >= 1.0)
+        return ERT_EINVAL;
+    for (int r : so.reserved)
+        if (r != 0) return ERT_EINVAL;
+    const long N = p->N;
+    const int method = p->o.method;
+    const int prec_outer = so.mixed ? ERT_FP64 : p->o.prec;
+    const int prec_inner = (p->o.prec == ERT_FP64) ? ERT_FP32 : p->o.prec;
+
+    ert_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    ert_status result = ERT_OK;
+    auto t0 = std::chrono::steady_clock::now();
+    // vectors beyond the Krylov workspace: phi, r, d (per column, reused)
+    double* extra = nullptr;
+    ERT_HIP(hipMalloc(&extra, 3 * N * sizeof(double)));
+    double* phi = extra;
+    double* r = extra + N;
+    double* d = extra + 2 * N;
+    ert_status st = ERT_OK;
+    for (int c = 0; c < nrhs && st == ERT_OK; ++c) {
+        std::memset(&inf, 0, sizeof(inf));
+        const double* fc = f + (size_t)c * N;
+        double* Uc = U + (size_t)c * N;
+        if (so.rhs_is_phi) {
+            st = (hipMemcpyAsync(phi, fc, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream) == hipSuccess)
+                     ? ERT_OK : ERT_EDEVICE;
+        } else {
+            st = apply_dispatch(p, ERT_OP_G, method, prec_outer, fc, phi, 1);
+            inf.matvecs++;
+        }
+        if (st != ERT_OK) break;
+        if (!so.mixed) {
+            RunStats rs;
+            st = gmres_run(p, method, prec_outer, phi, Uc, so.tol, so.max_iter, so.restart, true, &rs);
+            inf.iters = rs.iters;
+            inf.matvecs += rs.matvecs;
+            inf.restarts = rs.cycles > 0 ? rs.cycles - 1 : 0;
+            inf.rel_resid_est = rs.est;
+            inf.rel_resid_true = rs.true_rel;
+            inf.converged = rs.converged ? 1 : 0;
+        } else {
+            // iterative refinement: r = phi - A64 U (FP64), inner GMRES on the FP32 operator
+            double* partial = nullptr;
+            (void)partial;
+            st = dev_zero(p->stream, Uc, N);
+            if (st != ERT_OK) break;
+            st = (hipMemcpyAsync(r, phi, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream) == hipSuccess)
+                     ? ERT_OK : ERT_EDEVICE;
+            if (st != ERT_OK) break;
+            st = ensure_workspace(p, 3 * N, (size_t)kPartials * 4 + 16);
+            if (st != ERT_OK) break;
+            double* dn = p->d_red + (size_t)kPartials * 4;
+            double pnorm = dev_norm(p, phi, p->d_red, dn, &st);
+            if (st != ERT_OK) break;
+            double rnorm = pnorm;
+            int used = 0;
+            for (int outer = 0; outer < 200; ++outer) {
+                inf.rel_resid_true = pnorm > 0 ? rnorm / pnorm : 0.0;
+                if (rnorm <= so.tol * pnorm) { inf.converged = 1; break; }
+                if (used >= so.max_iter) break;
+                RunStats rs;
+                // the inner solve only needs to reduce this residual by inner_tol
+                st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, so.max_iter - used, so.restart, false, &rs);
+                if (st != ERT_OK) break;
+                used += rs.iters;
+                inf.iters += rs.iters;
+                inf.matvecs += rs.matvecs;
+                inf.rel_resid_est = rs.est;
+                st = dev_add(p->stream, Uc, d, N);
+                if (st != ERT_OK) break;
+                st = apply_dispatch(p, ERT_OP_A, method, ERT_FP64, Uc, d, 1);
+                if (st != ERT_OK) break;
+                inf.matvecs++;
+                st = dev_sub(p->stream, r, phi, d, N);
+                if (st != ERT_OK) break;
+                st = ensure_workspace(p, 3 * N, (size_t)kPartials * 4 + 16);
+                if (st != ERT_OK) break;
+                dn = p->d_red + (size_t)kPartials * 4;
+                rnorm = dev_norm(p, r, p->d_red, dn, &st);
+                if (st != ERT_OK) break;
+                inf.restarts = outer + 1;
+            }
+            if (st == ERT_OK) inf.rel_resid_true = pnorm > 0 ? rnorm / pnorm : 0.0;
+            if (st == ERT_OK && rnorm <= so.tol * pnorm) inf.converged = 1;
+        }
+        if (st == ERT_OK && !inf.converged) result = ERT_ENOCONV;
+    }
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(extra);
+    inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st != ERT_OK ? st : result;
+}
+
+}  // extern "C"

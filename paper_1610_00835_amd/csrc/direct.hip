@@ -1,0 +1,275 @@
+// Dense summation of the collocation matrix (Sec. 3.2, approach (M-iii)) and
+// the singular diagonal entry, both on the GPU.
+//
+//   y_j = h^d sum_{k != j} G(x_j, x_k) w_k + A_jj w_j,   w = x or sigma_s x,
+//   G(x,y) = exp(-tau) / (|S^{d-1}| |x-y|^{d-1})            (eq. EQ:Kernel)
+//
+// One thread per target; source weights are staged through LDS in tiles of
+// 256 and the source cell coordinates advance incrementally (uniform across
+// the wave, so they live in scalar registers).  Offsets between collocation
+// points are integers, so |x-y|^2 = h^2 K with K exact and the ray step count
+// m = ceil(2 sqrt K) is exact as well.
+#include "common.hpp"
+
+namespace ertvie {
+
+namespace {
+
+constexpr int kTile = 256;
+
+// ---------------------------------------------------------- self cell -----
+
+// integral_0^rho E(x, x + r v) dr (same step rule as the off-diagonal kernel:
+// one midpoint step for r <= h/2, two beyond; rho < h always).
+__device__ double radial_integral(const Geo& g, int ray, double sigma, const double* __restrict__ st,
+                                  const double x[3], const double v[3], double rho,
+                                  const double* __restrict__ rx, const double* __restrict__ rw, int nrad)
+{
+    if (!ray) {
+        double a = sigma * rho;
+        return a < 1e-300 ? rho : -expm1(-a) / sigma;
+    }
+    const double half = 0.5 * g.h, inv_h = 1.0 / g.h;
+    double acc = 0.0;
+    double b0 = rho < half ? rho : half;
+    for (int q = 0; q < nrad; ++q) {
+        double r = 0.5 * b0 * (rx[q] + 1.0);
+        double s = sigma_at<double>(st, g, inv_h, x[0] + 0.5 * r * v[0], x[1] + 0.5 * r * v[1],
+                                    x[2] + 0.5 * r * v[2]);
+        acc += 0.5 * b0 * rw[q] * exp(-r * s);
+    }
+    if (rho > half) {
+        double len = rho - half;
+        for (int q = 0; q < nrad; ++q) {
+            double r = half + 0.5 * len * (rx[q] + 1.0);
+            double s1 = sigma_at<double>(st, g, inv_h, x[0] + 0.25 * r * v[0], x[1] + 0.25 * r * v[1],
+                                         x[2] + 0.25 * r * v[2]);
+            double s2 = sigma_at<double>(st, g, inv_h, x[0] + 0.75 * r * v[0], x[1] + 0.75 * r * v[1],
+                                         x[2] + 0.75 * r * v[2]);
+            acc += 0.5 * len * rw[q] * exp(-0.5 * r * (s1 + s2));
+        }
+    }
+    return acc;
+}
+
+// One workgroup per cell: the directions are split into patches on which the
+// integrand is smooth (2D: eight arcs of pi/4; 3D: six faces x four quadrants,
+// parametrised by the face point with solid-angle Jacobian (h/2)/R^3), with
+// tensor Gauss-Legendre per patch.  Fixed-order block reduction.
+__global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, const double* __restrict__ st,
+                                                  const double* __restrict__ ax, const double* __restrict__ aw,
+                                                  int nang, const double* __restrict__ rx,
+                                                  const double* __restrict__ rw, int nrad, long j0,
+                                                  double* __restrict__ diag)
+{
+    __shared__ double red[256];
+    const long j = j0 + blockIdx.x;
+    const int i0 = (int)(j % g.n0);
+    const int i1 = (int)((j / g.n0) % g.n1);
+    const int i2 = (int)(j / ((long)g.n0 * g.n1));
+    const double half = 0.5 * g.h;
+    const double x[3] = {g.h * (i0 + 0.5), g.h * (i1 + 0.5), g.dim > 2 ? g.h * (i2 + 0.5) : 0.0};
+    double acc = 0.0;
+    if (g.dim == 2) {
+        const int total = 8 * nang;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            int arc = t / nang, q = t % nang;
+            double t0 = arc * (kPi / 4.0);
+            double th = t0 + (kPi / 8.0) * (ax[q] + 1.0);
+            double v[3] = {cos(th), sin(th), 0.0};
+            double c = fabs(v[0]) > fabs(v[1]) ? fabs(v[0]) : fabs(v[1]);
+            acc += (kPi / 8.0) * aw[q] * radial_integral(g, ray, sigma, st, x, v, half / c, rx, rw, nrad);
+        }
+    } else {
+        const int per = nang * nang;
+        const int total = 24 * per;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            int patch = t / per, q = t % per;
+            int axis = patch / 8, sgn = ((patch / 4) & 1) ? 1 : -1, quad = patch & 3;
+            int qa = q / nang, qb = q % nang;
+            double u = ((quad & 1) ? 0.0 : -half) + 0.5 * half * (ax[qa] + 1.0);
+            double w = ((quad & 2) ? 0.0 : -half) + 0.5 * half * (ax[qb] + 1.0);
+            double R = sqrt(u * u + w * w + half * half);
+            double v[3];
+            v[axis] = sgn * half / R;
+            v[(axis + 1) % 3] = u / R;
+            v[(axis + 2) % 3] = w / R;
+            double wq = 0.25 * half * half * aw[qa] * aw[qb] * half / (R * R * R);
+            acc += wq * radial_integral(g, ray, sigma, st, x, v, R, rx, rw, nrad);
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) diag[j] = red[0] / surface_area(g.dim);
+}
+
+__global__ void k_fill(double* __restrict__ d, long N, const double* __restrict__ src)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < N) d[i] = src[0];
+}
+
+// ------------------------------------------------------- dense apply -----
+
+template <typename T, bool RAY, int RB>
+__global__ __launch_bounds__(kTile) void k_direct(Geo g, const T* __restrict__ st, T sigma, T hd_over_area,
+                                                  const double* __restrict__ x, const double* __restrict__ ss,
+                                                  int weighted, long N, const double* __restrict__ diag,
+                                                  int op, double* __restrict__ y)
+{
+    __shared__ T sw[kTile * RB];
+    const long j = blockIdx.x * (long)kTile + threadIdx.x;
+    const bool active = j < N;
+    const int j0 = active ? (int)(j % g.n0) : 0;
+    const int j1 = active ? (int)((j / g.n0) % g.n1) : 0;
+    const int j2 = active ? (int)(j / ((long)g.n0 * g.n1)) : 0;
+    const T h = T(g.h), inv_h = T(1.0 / g.h);
+    T acc[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[b] = T(0);
+
+    for (long k0 = 0; k0 < N; k0 += kTile) {
+        const long k = k0 + threadIdx.x;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            double v = 0.0;
+            if (k < N) v = weighted ? ss[k] * x[k + b * N] : x[k + b * N];
+            sw[threadIdx.x * RB + b] = T(v);
+        }
+        __syncthreads();
+        const int cnt = (N - k0) < kTile ? (int)(N - k0) : kTile;
+        int c0 = (int)(k0 % g.n0), c1 = (int)((k0 / g.n0) % g.n1), c2 = (int)(k0 / ((long)g.n0 * g.n1));
+        if (active) {
+            for (int t = 0; t < cnt; ++t) {
+                const long kk = k0 + t;
+                if (kk != j) {
+                    const int d0 = j0 - c0, d1 = j1 - c1, d2 = j2 - c2;
+                    const int K = d0 * d0 + d1 * d1 + d2 * d2;
+                    const T r = h * sqrt(T(K));
+                    T tau;
+                    if (RAY) {
+                        const bool lo = j < kk;
+                        const T a0 = h * (T(lo ? j0 : c0) + T(0.5)), a1 = h * (T(lo ? j1 : c1) + T(0.5));
+                        const T a2 = h * (T(lo ? j2 : c2) + T(0.5));
+                        const T b0 = h * (T(lo ? c0 : j0) + T(0.5)), b1 = h * (T(lo ? c1 : j1) + T(0.5));
+                        const T b2 = h * (T(lo ? c2 : j2) + T(0.5));
+                        tau = tau_march<T>(st, g, inv_h, a0, a1, a2, b0, b1, b2, steps_grid(K), r);
+                    } else {
+                        tau = sigma * r;
+                    }
+                    const T rp = (g.dim == 2) ? T(sqrt(T(K))) : T(K);
+                    const T gk = exp(-tau) / rp;
+#pragma unroll
+                    for (int b = 0; b < RB; ++b) acc[b] += gk * sw[t * RB + b];
+                }
+                if (++c0 == g.n0) {
+                    c0 = 0;
+                    if (++c1 == g.n1) { c1 = 0; ++c2; }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        // entries are h^d G = h^d exp(-tau) / (area h^{d-1} K^{(d-1)/2}) = (h / area) exp(-tau)/rp
+        const double wself_scale = weighted ? ss[j] : 1.0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const double xj = x[j + b * N];
+            double v = (double)hd_over_area * (double)acc[b] + diag[j] * wself_scale * xj;
+            y[j + b * N] = (op == ERT_OP_A) ? xj - v : v;
+        }
+    }
+}
+
+template <typename T, bool RAY>
+ert_status launch_direct(ert_plan_impl* p, const T* st, int op, const double* x, double* y, int nrhs)
+{
+    const long N = p->N;
+    const int weighted = (op != ERT_OP_G);
+    const T sigma = T(p->sigma_const);
+    const T scale = T(p->geo.h / surface_area(p->geo.dim));
+    dim3 grid((unsigned)((N + kTile - 1) / kTile));
+    int b = 0;
+    while (b < nrhs) {
+        const int left = nrhs - b;
+        const double* xb = x + (long)b * N;
+        double* yb = y + (long)b * N;
+        if (left >= 4) {
+            hipLaunchKernelGGL((k_direct<T, RAY, 4>), grid, dim3(kTile), 0, p->stream, p->geo, st, sigma, scale,
+                               xb, p->d_ss, weighted, N, p->d_diag, op, yb);
+            b += 4;
+        } else if (left >= 2) {
+            hipLaunchKernelGGL((k_direct<T, RAY, 2>), grid, dim3(kTile), 0, p->stream, p->geo, st, sigma, scale,
+                               xb, p->d_ss, weighted, N, p->d_diag, op, yb);
+            b += 2;
+        } else {
+            hipLaunchKernelGGL((k_direct<T, RAY, 1>), grid, dim3(kTile), 0, p->stream, p->geo, st, sigma, scale,
+                               xb, p->d_ss, weighted, N, p->d_diag, op, yb);
+            b += 1;
+        }
+        ERT_HIP(hipGetLastError());
+    }
+    return ERT_OK;
+}
+
+}  // namespace
+
+ert_status selfcell_compute(ert_plan_impl* p)
+{
+    const int nang = 16, nrad = 10;
+    std::vector<double> ax, aw, rx, rw;
+    gauss_legendre(nang, ax, aw);
+    gauss_legendre(nrad, rx, rw);
+    std::vector<double> pack;
+    pack.insert(pack.end(), ax.begin(), ax.end());
+    pack.insert(pack.end(), aw.begin(), aw.end());
+    pack.insert(pack.end(), rx.begin(), rx.end());
+    pack.insert(pack.end(), rw.begin(), rw.end());
+    double* d = nullptr;
+    ERT_HIP(hipMalloc(&d, pack.size() * sizeof(double)));
+    ert_status st = ERT_OK;
+    do {
+        st = ERT_HIPST(hipMemcpyAsync(d, pack.data(), pack.size() * sizeof(double), hipMemcpyHostToDevice,
+                                      p->stream));
+        if (st != ERT_OK) break;
+        const int ray = p->o.kernel == ERT_K_RAY_MIDPOINT;
+        const long ncell = ray ? p->N : 1;
+        // chunk the launch so one dispatch never holds the GPU for long
+        const long chunk = 65536;
+        for (long j0 = 0; j0 < ncell && st == ERT_OK; j0 += chunk) {
+            long cnt = (ncell - j0) < chunk ? (ncell - j0) : chunk;
+            hipLaunchKernelGGL(k_selfcell, dim3((unsigned)cnt), dim3(256), 0, p->stream, p->geo, ray,
+                               p->sigma_const, p->d_st, d, d + nang, nang, d + 2 * nang, d + 2 * nang + nrad, nrad,
+                               j0, p->d_diag);
+            st = ERT_HIPST(hipGetLastError());
+        }
+        if (st != ERT_OK) break;
+        if (!ray) {
+            hipLaunchKernelGGL(k_fill, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, p->stream, p->d_diag,
+                               p->N, p->d_diag);
+            st = ERT_HIPST(hipGetLastError());
+            if (st != ERT_OK) break;
+        }
+        st = ERT_HIPST(hipStreamSynchronize(p->stream));
+    } while (0);
+    (void)hipFree(d);
+    return st;
+}
+
+ert_status direct_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs)
+{
+    const bool ray = p->o.kernel == ERT_K_RAY_MIDPOINT;
+    if (prec == ERT_FP64) {
+        return ray ? launch_direct<double, true>(p, p->d_st, op, x, y, nrhs)
+                   : launch_direct<double, false>(p, p->d_st, op, x, y, nrhs);
+    }
+    return ray ? launch_direct<float, true>(p, p->d_st32, op, x, y, nrhs)
+               : launch_direct<float, false>(p, p->d_st32, op, x, y, nrhs);
+}
+
+}  // namespace ertvie

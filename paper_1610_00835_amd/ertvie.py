@@ -1,0 +1,233 @@
+"""Thin ctypes binding of the C ABI in include/ertvie.h (argument marshalling only).
+
+Every step of the computation runs in libertvie.so.  Vectors are torch CUDA
+(HIP) float64 tensors: shape (N,) for one right-hand side or (nrhs, N) for
+several -- row b of a contiguous (nrhs, N) tensor is column b of the
+column-major N x nrhs array the ABI expects.  If the library is missing the
+import of this module fails loudly; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libertvie.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+K_HOMOGENEOUS, K_RAY_MIDPOINT = 0, 1
+DIRECT, FMM = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
+OP_G, OP_GS, OP_A = 0, 1, 2
+
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+_METHOD = {"direct": DIRECT, "fmm": FMM}
+
+
+class VieOpts(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
+                ("cheb_n", ctypes.c_int), ("leaf", ctypes.c_int), ("nrhs_max", ctypes.c_int),
+                ("flags", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
+                ("mixed", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_is_phi", ctypes.c_int),
+                ("reserved", ctypes.c_int * 4)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("rel_resid_est", ctypes.c_double),
+                ("rel_resid_true", ctypes.c_double), ("t_solve", ctypes.c_double)]
+
+
+class ErtError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        detail = load().ert_vie_last_error().decode()
+        super().__init__("%s: %s (status %d)%s" % (where, strerror(status), status,
+                                                  (": " + detail) if detail else ""))
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_lib = None
+
+
+def load():
+    """Open libertvie.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libertvie.so is not built (run paper_1610_00835_amd/build.py)")
+    # torch ships its own HIP runtime; load it first so that libertvie.so binds to the
+    # same libamdhip64 / libhsa-runtime64 (matched by soname) instead of a second copy
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    L.ert_vie_plan.restype = ctypes.c_int
+    L.ert_vie_plan.argtypes = [ctypes.POINTER(VieOpts), _dp, _dp, _vp, ctypes.POINTER(_vp)]
+    L.ert_vie_apply.restype = ctypes.c_int
+    L.ert_vie_apply.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
+    L.ert_vie_apply_ex.restype = ctypes.c_int
+    L.ert_vie_apply_ex.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int]
+    L.ert_vie_solve.restype = ctypes.c_int
+    L.ert_vie_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(SolveOpts),
+                                ctypes.POINTER(SolveInfo)]
+    L.ert_vie_diag.restype = ctypes.c_int
+    L.ert_vie_diag.argtypes = [_vp, _dp]
+    L.ert_vie_size.restype = ctypes.c_long
+    L.ert_vie_size.argtypes = [_vp]
+    L.ert_vie_destroy.restype = None
+    L.ert_vie_destroy.argtypes = [_vp]
+    L.ert_vie_last_error.restype = ctypes.c_char_p
+    L.ert_vie_last_error.argtypes = []
+    L.ert_vie_strerror.restype = ctypes.c_char_p
+    L.ert_vie_strerror.argtypes = [ctypes.c_int]
+    _lib = L
+    return L
+
+
+def strerror(status):
+    return load().ert_vie_strerror(int(status)).decode()
+
+
+def _check(status, where):
+    if status != OK:
+        raise ErtError(status, where)
+
+
+def _f64_host(a, N):
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if a.size != N:
+        raise ValueError("expected %d values, got %d" % (N, a.size))
+    return a
+
+
+def _dev_ptr(t, N, name):
+    """Validate a torch CUDA float64 tensor of shape (N,) or (nrhs, N); return (ptr, nrhs)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.dim() == 1 and t.shape[0] == N:
+        return t.data_ptr(), 1
+    if t.dim() == 2 and t.shape[1] == N:
+        return t.data_ptr(), int(t.shape[0])
+    raise ValueError("%s must have shape (N,) or (nrhs, N) with N=%d" % (name, N))
+
+
+class Plan:
+    """An ert_vie plan: the grid, its media and the operator data on the GPU.
+
+    dim, n, h: grid (cell-centred, x fastest); sigma_t, sigma_s: host arrays of N values.
+    kernel: 0 homogeneous / 1 midpoint ray rule; method 'direct' | 'fmm';
+    prec 'fp64' | 'fp32' | 'bf16x3'.
+    """
+
+    def __init__(self, dim, n, h, sigma_t, sigma_s, kernel=K_HOMOGENEOUS, method="direct", prec="fp64",
+                 cheb_n=0, leaf=0, nrhs_max=1, stream=None):
+        L = load()
+        n = list(n)[:dim]
+        self.dim = int(dim)
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        o = VieOpts()
+        o.dim = self.dim
+        for a in range(3):
+            o.n[a] = self.n[a] if a < dim else 1
+        o.h = float(h)
+        o.kernel = int(kernel)
+        o.method = _METHOD[method] if isinstance(method, str) else int(method)
+        o.prec = _PREC[prec] if isinstance(prec, str) else int(prec)
+        o.cheb_n = int(cheb_n)
+        o.leaf = int(leaf)
+        o.nrhs_max = int(nrhs_max)
+        o.flags = 0
+        self.opts = o
+        st_h = _f64_host(sigma_t, self.N)
+        ss_h = _f64_host(sigma_s, self.N)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        handle = _vp()
+        _check(L.ert_vie_plan(ctypes.byref(o), st_h.ctypes.data_as(_dp), ss_h.ctypes.data_as(_dp), sp,
+                              ctypes.byref(handle)), "ert_vie_plan")
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def apply(self, x, y, op=OP_GS, method=None, prec=None):
+        """y = op(x) on the plan's stream (asynchronous)."""
+        xp, nx = _dev_ptr(x, self.N, "x")
+        yp, ny = _dev_ptr(y, self.N, "y")
+        if nx != ny:
+            raise ValueError("x and y differ in nrhs")
+        if method is None and prec is None:
+            st = load().ert_vie_apply(self.handle, int(op), xp, yp, nx)
+        else:
+            m = self.opts.method if method is None else (_METHOD[method] if isinstance(method, str) else method)
+            p = self.opts.prec if prec is None else (_PREC[prec] if isinstance(prec, str) else prec)
+            st = load().ert_vie_apply_ex(self.handle, int(op), int(m), int(p), xp, yp, nx)
+        _check(st, "ert_vie_apply")
+        return y
+
+    def solve(self, f, U, tol=1e-8, max_iter=500, restart=0, mixed=False, inner_tol=1e-5, rhs_is_phi=False,
+              allow_noconv=False):
+        fp, nf = _dev_ptr(f, self.N, "f")
+        up, nu = _dev_ptr(U, self.N, "U")
+        if nf != nu:
+            raise ValueError("f and U differ in nrhs")
+        so = SolveOpts()
+        so.tol = float(tol)
+        so.max_iter = int(max_iter)
+        so.restart = int(restart)
+        so.mixed = 1 if mixed else 0
+        so.inner_tol = float(inner_tol)
+        so.rhs_is_phi = 1 if rhs_is_phi else 0
+        info = SolveInfo()
+        st = load().ert_vie_solve(self.handle, fp, up, nf, ctypes.byref(so), ctypes.byref(info))
+        out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+        out["status"] = st
+        if not (st == OK or (allow_noconv and st == ENOCONV)):
+            _check(st, "ert_vie_solve")
+        return out
+
+    def diag(self):
+        d = np.empty(self.N)
+        _check(load().ert_vie_diag(self.handle, d.ctypes.data_as(_dp)), "ert_vie_diag")
+        return d
+
+    def size(self):
+        return int(load().ert_vie_size(self.handle))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().ert_vie_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None):
+    return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
+                method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream)
