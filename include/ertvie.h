@@ -93,7 +93,7 @@ typedef struct {
     int kernel;       /* ert_kernel */
     int method;       /* ert_method used by ert_vie_apply and the solver */
     int prec;         /* ert_prec used by ert_vie_apply and the solver */
-    int cheb_n;       /* FMM: Chebyshev nodes per axis (Sec. 3.3, n); 0 -> 6; 2..8 */
+    int cheb_n;       /* FMM: Chebyshev nodes per axis (Sec. 3.3, n); 0 -> 8; 2..8 */
     int leaf;         /* FMM: cells per leaf-box side; 0 -> 4 (3D) / 8 (2D) */
     int nrhs_max;     /* largest nrhs later passed to apply/solve; 0 -> 1 */
     int flags;        /* reserved, must be 0 */
@@ -149,6 +149,28 @@ ERT_API ert_status ert_vie_apply_ex(ert_vie_plan_t plan, int op, int method, int
  * Returns ERT_ENOCONV when max_iter is reached first; U then holds the best iterate. */
 ERT_API ert_status ert_vie_solve(ert_vie_plan_t plan, const double* f, double* U, int nrhs,
                          const ert_solve_opts* opts, ert_solve_info* info);
+
+/* Stages of one FMM apply, for ert_vie_profile. */
+typedef enum {
+    ERT_STAGE_GATHER = 0,   /* weights into leaf-major order */
+    ERT_STAGE_NEAR = 1,     /* near field over neighbouring leaves (P2P) */
+    ERT_STAGE_P2M = 2,
+    ERT_STAGE_M2M = 3,
+    ERT_STAGE_M2L = 4,      /* far-field translations (Sec. 3.3 eq. EQ: M2L) */
+    ERT_STAGE_L2L = 5,
+    ERT_STAGE_L2P = 6,
+    ERT_STAGE_ASSEMBLE = 7, /* scaling, self term, I - K */
+    ERT_STAGE_DIRECT = 8,   /* dense apply */
+    ERT_NSTAGES = 9
+} ert_stage;
+
+/* Device timing of applies by stage, with HIP events recorded on the plan's
+ * stream around every kernel launch of a stage.
+ *   enable = 1: clear the totals and start recording; 0: stop recording.
+ *   stage_ms / stage_launches (host, ERT_NSTAGES entries each, may be NULL):
+ *   receive the totals recorded so far (synchronises the stream).
+ * Recording adds an event pair per launch; leave it off for timed runs. */
+ERT_API ert_status ert_vie_profile(ert_vie_plan_t plan, int enable, double* stage_ms, int* stage_launches);
 
 /* Copy the diagonal A_jj (N values, FP64) to host memory `d` (synchronises). */
 ERT_API ert_status ert_vie_diag(ert_vie_plan_t plan, double* d);

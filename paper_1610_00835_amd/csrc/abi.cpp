@@ -64,11 +64,77 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
     if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
+hipEvent_t Profiler::get()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ert_status Profiler::begin(hipStream_t s, int stage, hipEvent_t* ev)
+{
+    (void)stage;
+    *ev = get();
+    if (!*ev) return ERT_EDEVICE;
+    ERT_HIP(hipEventRecord(*ev, s));
+    return ERT_OK;
+}
+
+ert_status Profiler::end(hipStream_t s, int stage, hipEvent_t ev0)
+{
+    hipEvent_t e1 = get();
+    if (!e1) return ERT_EDEVICE;
+    ERT_HIP(hipEventRecord(e1, s));
+    recs.push_back({stage, ev0, e1});
+    return ERT_OK;
+}
+
+ert_status Profiler::resolve()
+{
+    for (auto& r : recs) {
+        ERT_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        ERT_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.stage] += t;
+        launches[r.stage] += 1;
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    recs.clear();
+    return ERT_OK;
+}
+
+void Profiler::clear()
+{
+    (void)resolve();
+    for (int i = 0; i < ERT_NSTAGES; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+}
+
+Profiler::~Profiler()
+{
+    for (auto& r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 namespace {
 
 ert_status apply_dispatch(ert_plan_impl* p, int op, int method, int prec, const double* x, double* y, int nrhs)
 {
-    if (method == ERT_DIRECT) return direct_apply(p, op, prec, x, y, nrhs);
+    if (method == ERT_DIRECT) {
+        StageTimer t(&p->prof, p->stream, ERT_STAGE_DIRECT);
+        return direct_apply(p, op, prec, x, y, nrhs);
+    }
     return fmm_apply(p, op, prec, x, y, nrhs);
 }
 
@@ -347,6 +413,19 @@ ert_status ert_vie_apply(ert_vie_plan_t p, int op, const double* x, double* y, i
 {
     if (!p) return ERT_EINVAL;
     return ert_vie_apply_ex(p, op, p->o.method, p->o.prec, x, y, nrhs);
+}
+
+ert_status ert_vie_profile(ert_vie_plan_t p, int enable, double* stage_ms, int* stage_launches)
+{
+    if (!p) return ERT_EINVAL;
+    ERT_TRY(p->prof.resolve());
+    if (stage_ms)
+        for (int i = 0; i < ERT_NSTAGES; ++i) stage_ms[i] = p->prof.ms[i];
+    if (stage_launches)
+        for (int i = 0; i < ERT_NSTAGES; ++i) stage_launches[i] = p->prof.launches[i];
+    if (enable && !p->prof.on) p->prof.clear();
+    p->prof.on = enable != 0;
+    return ERT_OK;
 }
 
 ert_status ert_vie_diag(ert_vie_plan_t p, double* d)

@@ -115,6 +115,38 @@ __device__ __forceinline__ T tau_march(const T* __restrict__ st, const Geo& g, T
 
 struct FmmData;   // fmm.hip
 
+// Per-stage event timing (ert_vie_profile).
+struct Profiler {
+    bool on = false;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    double ms[ERT_NSTAGES] = {};
+    int launches[ERT_NSTAGES] = {};
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    ert_status begin(hipStream_t s, int stage, hipEvent_t* ev);
+    ert_status end(hipStream_t s, int stage, hipEvent_t ev0);
+    ert_status resolve();
+    void clear();
+    ~Profiler();
+};
+
+// RAII bracket for one stage of an apply
+struct StageTimer {
+    Profiler* p;
+    hipStream_t s;
+    int stage;
+    hipEvent_t ev0 = nullptr;
+    StageTimer(Profiler* p_, hipStream_t s_, int st) : p(p_), s(s_), stage(st)
+    {
+        if (p && p->on) p->begin(s, stage, &ev0);
+    }
+    ~StageTimer()
+    {
+        if (p && p->on && ev0) p->end(s, stage, ev0);
+    }
+};
+
 struct ert_plan_impl {
     ert_vie_opts o;
     Geo geo;
@@ -133,6 +165,7 @@ struct ert_plan_impl {
     double* d_red = nullptr;     // reduction partials / small vectors
     size_t red_elems = 0;
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
+    Profiler prof;
 };
 
 // ------------------------------------------------------ launchers (.hip) ---

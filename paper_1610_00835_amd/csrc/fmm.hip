@@ -1,14 +1,900 @@
-// Chebyshev-interpolation fast multipole method (Sec. 3.3): placeholder until
-// the tree and translation kernels land.
-#include "common.hpp"
+// Chebyshev-interpolation fast multipole method for the collocation apply
+// (Sec. 3.3 with the multilevel tree of Sec. 4.2).
+//
+//   y_j = h^d * sum_{k != j} G(x_j, x_k) w_k + A_jj w_j
+//
+// Points are reordered leaf-major (leaf boxes of leaf^d cells, lexicographic);
+// far-field interactions go through tensor Chebyshev interpolants with
+// S_n(p,q) = prod_i (1/n + 2/n sum_{k=1}^{n-1} T_k(p_i) T_k(q_i))
+// (eq. EQ: CHEB), nodes at the roots of T_n:
+//   P2M  f1(q_m) = sum_{x_j in box} S_n(R^{-1} x_j, q_m) w_j        (step 1)
+//   M2M  parent multipoles by re-anterpolating the children's node charges
+//   M2L  f2(p_m) = sum_m' K(L p_m, R q_m') f1(q_m')                 (step 2, m2l.hip)
+//   L2L  children's locals by interpolating the parent's local values
+//   L2P  phi(x_i) = sum_m S_n(L^{-1} x_i, p_m) f2(p_m)              (step 3)
+//   P2P  direct sums over the 3^d neighbouring leaves
+// Every transfer is separable, so P2M/M2M/L2L/L2P are three (two in 2D) small
+// 1D contractions done in LDS.  The interaction list of a box is the set of
+// children of its parent's neighbours that are not its own neighbours
+// (at most 6^d - 3^d, Sec. 4.2).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fmm.hpp"
 
 namespace ertvie {
 
 struct FmmData {
-    int dummy;
+    virtual ~FmmData() {}
+    virtual ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) = 0;
+    virtual ert_status setup(ert_plan_impl* p) = 0;
+    FmmTree tr;
 };
 
-ert_status fmm_apply(ert_plan_impl*, int, int, const double*, double*, int) { return ERT_EUNSUPPORTED; }
+namespace {
+
+constexpr int kB = 256;
+
+// ------------------------------------------------------------ geometry ----
+
+__host__ __device__ inline void unravel3(long i, const int n[3], int out[3])
+{
+    out[0] = (int)(i % n[0]);
+    long r = i / n[0];
+    out[1] = (int)(r % n[1]);
+    out[2] = (int)(r / n[1]);
+}
+
+struct DevTree {
+    int D, nc, K, Kp, leaf, S;
+    int nb[3];
+    long nleaf, nslot;
+    int n[3];       // grid cells per axis
+};
+
+// slot -> grid cell (or -1 when the slot lies outside the grid)
+__device__ __forceinline__ long slot_cell(const DevTree& t, long slot, int c[3])
+{
+    long leafi = slot / t.S;
+    int li = (int)(slot - leafi * t.S);
+    int b[3], l[3];
+    unravel3(leafi, t.nb, b);
+    int ls[3] = {t.leaf, t.D > 1 ? t.leaf : 1, t.D > 2 ? t.leaf : 1};
+    unravel3(li, ls, l);
+    for (int a = 0; a < 3; ++a) {
+        c[a] = (a < t.D) ? b[a] * t.leaf + l[a] : 0;
+        if (c[a] >= t.n[a]) return -1;
+    }
+    return c[0] + (long)t.n[0] * (c[1] + (long)t.n[1] * c[2]);
+}
+
+// ---------------------------------------------------- gather / assemble ----
+
+template <typename T>
+__global__ void k_gather(DevTree t, const double* __restrict__ x, const double* __restrict__ ss, int weighted,
+                         long N, int B, T* __restrict__ q)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= t.nslot * B) return;
+    int b = (int)(i / t.nslot);
+    long slot = i - (long)b * t.nslot;
+    int c[3];
+    long j = slot_cell(t, slot, c);
+    double v = 0.0;
+    if (j >= 0) v = weighted ? ss[j] * x[j + (long)b * N] : x[j + (long)b * N];
+    q[i] = T(v);
+}
+
+// y_j = h^d pot_j + A_jj w_j (FP64), op A: x_j - y_j; natural order
+template <typename T>
+__global__ void k_assemble(DevTree t, const T* __restrict__ pot, const double* __restrict__ x,
+                           const double* __restrict__ ss, const double* __restrict__ diag, int op, double hd, long N,
+                           int B, double* __restrict__ y)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= N * B) return;
+    int b = (int)(i / N);
+    long j = i - (long)b * N;
+    int c[3];
+    c[0] = (int)(j % t.n[0]);
+    long r = j / t.n[0];
+    c[1] = (int)(r % t.n[1]);
+    c[2] = (int)(r / t.n[1]);
+    int bl[3], l[3];
+    for (int a = 0; a < 3; ++a) {
+        bl[a] = (a < t.D) ? c[a] / t.leaf : 0;
+        l[a] = (a < t.D) ? c[a] - bl[a] * t.leaf : 0;
+    }
+    long leafi = bl[0] + (long)t.nb[0] * (bl[1] + (long)t.nb[1] * bl[2]);
+    long li = l[0] + (long)t.leaf * (l[1] + (long)(t.D > 1 ? t.leaf : 1) * l[2]);
+    long slot = leafi * t.S + li;
+    const double xj = x[i];
+    const double w = (op == ERT_OP_G) ? xj : ss[j] * xj;
+    double v = hd * (double)pot[(long)b * t.nslot + slot] + diag[j] * w;
+    y[i] = (op == ERT_OP_A) ? xj - v : v;
+}
+
+template <typename T>
+__global__ void k_zero_t(T* __restrict__ p, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+// --------------------------------------------------- separable transfers ----
+
+// out = contraction of `in` (dims d0 x d1 x d2, x fastest) along `axis` with a
+// 1D matrix: out[.., m, ..] = sum_i M(m, i) in[.., i, ..].  M(m,i) = mat[m*nin + i],
+// or mat[i*nout + m] when `tr`.  Cooperative over the block; ends with a barrier.
+template <typename T>
+__device__ void sep_axis(const T* in, T* out, int d0, int d1, int d2, int axis, int nout, const T* mat, bool tr)
+{
+    int od[3] = {d0, d1, d2};
+    const int nin = od[axis];
+    od[axis] = nout;
+    const int total = od[0] * od[1] * od[2];
+    for (int tix = threadIdx.x; tix < total; tix += blockDim.x) {
+        int c[3] = {tix % od[0], (tix / od[0]) % od[1], tix / (od[0] * od[1])};
+        const int m = c[axis];
+        T acc = T(0);
+        for (int i = 0; i < nin; ++i) {
+            c[axis] = i;
+            const T mv = tr ? mat[i * nout + m] : mat[m * nin + i];
+            acc += mv * in[c[0] + d0 * (c[1] + d1 * c[2])];
+        }
+        out[tix] = acc;
+    }
+    __syncthreads();
+}
+
+// apply the 1D matrices along every axis: input extent nin per axis, output nout
+template <typename T>
+__device__ const T* sep_all(const T* in, T* b0, T* b1, int D, int nin, int nout, const T* m0, const T* m1,
+                            const T* m2, bool tr)
+{
+    int d[3] = {nin, D > 1 ? nin : 1, D > 2 ? nin : 1};
+    sep_axis<T>(in, b0, d[0], d[1], d[2], 0, nout, m0, tr);
+    d[0] = nout;
+    if (D == 1) return b0;
+    sep_axis<T>(b0, b1, d[0], d[1], d[2], 1, nout, m1, tr);
+    d[1] = nout;
+    if (D == 2) return b1;
+    sep_axis<T>(b1, b0, d[0], d[1], d[2], 2, nout, m2, tr);
+    return b0;
+}
+
+constexpr int kSepBuf = 512;   // largest tensor in a transfer: max(nc, leaf)^3 <= 8^3
+
+// P2M: one block per (leaf, rhs).  P1[m][i] = S_n(xi_i, p_m).
+template <typename T>
+__global__ __launch_bounds__(kB) void k_p2m(DevTree t, const T* __restrict__ q, const T* __restrict__ P1,
+                                            T* __restrict__ W)
+{
+    __shared__ T in[kSepBuf], b0[kSepBuf], b1[kSepBuf], mat[64];
+    const long leafi = blockIdx.x;
+    const int b = blockIdx.y;
+    for (int i = threadIdx.x; i < t.nc * t.leaf; i += blockDim.x) mat[i] = P1[i];
+    for (int i = threadIdx.x; i < t.S; i += blockDim.x) in[i] = q[(long)b * t.nslot + leafi * t.S + i];
+    __syncthreads();
+    const T* r = sep_all<T>(in, b0, b1, t.D, t.leaf, t.nc, mat, mat, mat, false);
+    T* dst = W + ((long)b * t.nleaf + leafi) * t.Kp;
+    for (int i = threadIdx.x; i < t.K; i += blockDim.x) dst[i] = r[i];
+}
+
+// M2M: one block per (parent box, rhs); sums the transfers of its 2^d children.
+// M1[c][m][m'] = S_n(child node m' in the parent frame, p_m).
+template <typename T>
+__global__ __launch_bounds__(kB) void k_m2m(int D, int nc, int K, int Kp, int nlp0, int nlp1, int nlp2, long nboxp,
+                                            int nlc0, int nlc1, int nlc2, long nboxc, const T* __restrict__ Wc,
+                                            const T* __restrict__ M1, T* __restrict__ Wp)
+{
+    __shared__ T in[kSepBuf], b0[kSepBuf], b1[kSepBuf], acc[kSepBuf], mat[128];
+    const long pbox = blockIdx.x;
+    const int b = blockIdx.y;
+    const int nlp[3] = {nlp0, nlp1, nlp2}, nlc[3] = {nlc0, nlc1, nlc2};
+    int pc[3];
+    unravel3(pbox, nlp, pc);
+    for (int i = threadIdx.x; i < 2 * nc * nc; i += blockDim.x) mat[i] = M1[i];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) acc[i] = T(0);
+    __syncthreads();
+    for (int ch = 0; ch < (1 << D); ++ch) {
+        int cc[3], off[3];
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+            off[a] = (a < D) ? (ch >> a) & 1 : 0;
+            cc[a] = 2 * pc[a] + off[a];
+            if (a < D && cc[a] >= nlc[a]) inside = false;
+        }
+        if (!inside) continue;   // uniform over the block
+        long cb = cc[0] + (long)nlc[0] * (cc[1] + (long)nlc[1] * cc[2]);
+        const T* src = Wc + ((long)b * nboxc + cb) * Kp;
+        for (int i = threadIdx.x; i < K; i += blockDim.x) in[i] = src[i];
+        __syncthreads();
+        const T* r = sep_all<T>(in, b0, b1, D, nc, nc, mat + off[0] * nc * nc, mat + off[1] * nc * nc,
+                                mat + off[2] * nc * nc, false);
+        for (int i = threadIdx.x; i < K; i += blockDim.x) acc[i] += r[i];
+        __syncthreads();
+    }
+    T* dst = Wp + ((long)b * nboxp + pbox) * Kp;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) dst[i] = acc[i];
+}
+
+// L2L: one block per (child box, rhs): the child's locals are the parent's
+// local interpolant evaluated at the child nodes (written, not accumulated:
+// the far-field translations of the child level are added afterwards).
+template <typename T>
+__global__ __launch_bounds__(kB) void k_l2l(int D, int nc, int K, int Kp, int nlp0, int nlp1, int nlp2, long nboxp,
+                                            int nlc0, int nlc1, int nlc2, long nboxc, const T* __restrict__ Lp,
+                                            const T* __restrict__ M1, T* __restrict__ Lc)
+{
+    __shared__ T in[kSepBuf], b0[kSepBuf], b1[kSepBuf], mat[128];
+    const long cbox = blockIdx.x;
+    const int b = blockIdx.y;
+    const int nlp[3] = {nlp0, nlp1, nlp2}, nlc[3] = {nlc0, nlc1, nlc2};
+    int cc[3];
+    unravel3(cbox, nlc, cc);
+    for (int i = threadIdx.x; i < 2 * nc * nc; i += blockDim.x) mat[i] = M1[i];
+    long pb = (cc[0] >> 1) + (long)nlp[0] * ((cc[1] >> 1) + (long)nlp[1] * (cc[2] >> 1));
+    const T* src = Lp + ((long)b * nboxp + pb) * Kp;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) in[i] = src[i];
+    __syncthreads();
+    const T* r = sep_all<T>(in, b0, b1, D, nc, nc, mat + (cc[0] & 1) * nc * nc, mat + (cc[1] & 1) * nc * nc,
+                            mat + (cc[2] & 1) * nc * nc, true);
+    T* dst = Lc + ((long)b * nboxc + cbox) * Kp;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) dst[i] = r[i];
+}
+
+// L2P: one block per (leaf, rhs); adds the far field to the potential.
+template <typename T>
+__global__ __launch_bounds__(kB) void k_l2p(DevTree t, const T* __restrict__ Lc, const T* __restrict__ P1,
+                                            T* __restrict__ pot)
+{
+    __shared__ T in[kSepBuf], b0[kSepBuf], b1[kSepBuf], mat[64];
+    const long leafi = blockIdx.x;
+    const int b = blockIdx.y;
+    for (int i = threadIdx.x; i < t.nc * t.leaf; i += blockDim.x) mat[i] = P1[i];
+    const T* src = Lc + ((long)b * t.nleaf + leafi) * t.Kp;
+    for (int i = threadIdx.x; i < t.K; i += blockDim.x) in[i] = src[i];
+    __syncthreads();
+    const T* r = sep_all<T>(in, b0, b1, t.D, t.nc, t.leaf, mat, mat, mat, true);
+    T* dst = pot + (long)b * t.nslot + leafi * t.S;
+    for (int i = threadIdx.x; i < t.S; i += blockDim.x) dst[i] += r[i];
+}
+
+// ---------------------------------------------------------- near field ----
+
+// Homogeneous media: G between two collocation points depends only on the
+// integer K = |offset|^2, so the near field reads a table g[K] (g[0] = 0 drops
+// the self pair).  One block per (target leaf, rhs); the 3^d neighbour leaves'
+// charges are staged in LDS; threads = targets x source groups.
+template <typename T>
+__global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__ q, const T* __restrict__ tab,
+                                                int ntab, T* __restrict__ pot)
+{
+    extern __shared__ unsigned char smem[];
+    T* stab = (T*)smem;                          // [ntab]
+    const int nn = (t.D == 3) ? 27 : 9;
+    T* sq = stab + ntab;                         // [nn][S]
+    int* nbr = (int*)(sq + nn * t.S);            // [nn] neighbour leaf (or -1), 32 slots
+    const long leafi = blockIdx.x;
+    const int b = blockIdx.y;
+    int lb[3];
+    unravel3(leafi, t.nb, lb);
+    if (threadIdx.x < nn) {
+        int k = threadIdx.x, o[3] = {k % 3 - 1, (k / 3) % 3 - 1, t.D == 3 ? k / 9 - 1 : 0};
+        int s[3];
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            s[a] = lb[a] + ((a < t.D) ? o[a] : 0);
+            if (s[a] < 0 || s[a] >= t.nb[a]) ok = false;
+        }
+        nbr[k] = ok ? (int)(s[0] + (long)t.nb[0] * (s[1] + (long)t.nb[1] * s[2])) : -1;
+    }
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) stab[i] = tab[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nn * t.S; i += blockDim.x) {
+        int k = i / t.S, li = i - k * t.S;
+        sq[i] = nbr[k] >= 0 ? q[(long)b * t.nslot + (long)nbr[k] * t.S + li] : T(0);
+    }
+    __syncthreads();
+    const int ls1 = t.D > 1 ? t.leaf : 1;
+    const int tpp = t.S < (int)blockDim.x ? t.S : (int)blockDim.x;     // targets per pass
+    const int groups = blockDim.x / tpp;
+    const int grp = threadIdx.x / tpp;
+    T* red = (T*)(nbr + 32);                     // [groups][tpp]
+    for (int tb = 0; tb < t.S; tb += tpp) {
+        const int ti = tb + (threadIdx.x % tpp);
+        T acc = T(0);
+        if (grp < groups && ti < t.S) {
+            const int tx = ti % t.leaf, ty = (ti / t.leaf) % ls1, tz = ti / (t.leaf * ls1);
+            for (int k = grp; k < nn; k += groups) {
+                if (nbr[k] < 0) continue;
+                const int ox = (k % 3 - 1) * t.leaf, oy = ((k / 3) % 3 - 1) * t.leaf;
+                const int oz = (t.D == 3) ? (k / 9 - 1) * t.leaf : 0;
+                const T* qs = sq + k * t.S;
+                for (int sz = 0; sz < (t.D == 3 ? t.leaf : 1); ++sz) {
+                    const int dz = tz - (sz + oz);
+                    for (int sy = 0; sy < ls1; ++sy) {
+                        const int dy = ty - (sy + oy);
+                        const int ayz = dz * dz + dy * dy;
+                        const T* qrow = qs + t.leaf * (sy + ls1 * sz);
+                        for (int sx = 0; sx < t.leaf; ++sx) {
+                            const int dx = tx - (sx + ox);
+                            acc += stab[ayz + dx * dx] * qrow[sx];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (grp < groups) red[grp * tpp + (threadIdx.x % tpp)] = acc;
+        __syncthreads();
+        if (threadIdx.x < tpp && tb + (int)threadIdx.x < t.S) {
+            T s = red[threadIdx.x];
+            for (int g2 = 1; g2 < groups; ++g2) s += red[g2 * tpp + threadIdx.x];
+            pot[(long)b * t.nslot + leafi * t.S + tb + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Heterogeneous media: near-field kernel values cached per (target leaf,
+// neighbour position): blk[leaf][k][source i][target i] (target fastest).
+template <typename T>
+__global__ __launch_bounds__(kB) void k_p2p_cached(DevTree t, const T* __restrict__ q, const T* __restrict__ blk,
+                                                   T* __restrict__ pot)
+{
+    extern __shared__ unsigned char smem[];
+    T* sq = (T*)smem;                         // [S]
+    const long leafi = blockIdx.x;
+    const int b = blockIdx.y;
+    int lb[3];
+    unravel3(leafi, t.nb, lb);
+    const int nn = (t.D == 3) ? 27 : 9;
+    for (int tb = 0; tb < t.S; tb += blockDim.x) {
+        const int ti = tb + threadIdx.x;
+        T acc = T(0);
+        for (int k = 0; k < nn; ++k) {
+            int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, t.D == 3 ? k / 9 - 1 : 0};
+            int s[3];
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                s[a] = lb[a] + ((a < t.D) ? o[a] : 0);
+                if (s[a] < 0 || s[a] >= t.nb[a]) ok = false;
+            }
+            if (!ok) continue;   // uniform
+            long sl = s[0] + (long)t.nb[0] * (s[1] + (long)t.nb[1] * s[2]);
+            __syncthreads();
+            for (int i = threadIdx.x; i < t.S; i += blockDim.x) sq[i] = q[(long)b * t.nslot + sl * t.S + i];
+            __syncthreads();
+            if (ti < t.S) {
+                const T* col = blk + ((size_t)leafi * nn + k) * t.S * t.S + ti;
+                for (int si = 0; si < t.S; ++si) acc += col[(size_t)si * t.S] * sq[si];
+            }
+        }
+        if (ti < t.S) pot[(long)b * t.nslot + leafi * t.S + ti] = acc;
+    }
+}
+
+// Cached near-field blocks for the ray kernel, FP64 arithmetic: the same rule
+// as the dense apply (exact integer step count, marched from the lower index).
+// blk points at the block of leaf leaf0.
+template <typename T>
+__global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, long leaf0, long nleaves,
+                              T* __restrict__ blk)
+{
+    const int nn = (t.D == 3) ? 27 : 9;
+    const long per = (long)nn * t.S * t.S;
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= nleaves * per) return;
+    long leafi = leaf0 + i / per;
+    long rem = i % per;
+    int k = (int)(rem / ((long)t.S * t.S));
+    rem -= (long)k * t.S * t.S;
+    int si = (int)(rem / t.S), ti = (int)(rem % t.S);
+    int lb[3];
+    unravel3(leafi, t.nb, lb);
+    int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, t.D == 3 ? k / 9 - 1 : 0};
+    int sb[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        sb[a] = lb[a] + ((a < t.D) ? o[a] : 0);
+        if (sb[a] < 0 || sb[a] >= t.nb[a]) ok = false;
+    }
+    double v = 0.0;
+    if (ok) {
+        long sl = sb[0] + (long)t.nb[0] * (sb[1] + (long)t.nb[1] * sb[2]);
+        int ct[3], cs[3];
+        long jt = slot_cell(t, leafi * t.S + ti, ct);
+        long js = slot_cell(t, sl * t.S + si, cs);
+        if (jt >= 0 && js >= 0 && jt != js) {
+            int K = 0;
+            for (int a = 0; a < 3; ++a) K += (ct[a] - cs[a]) * (ct[a] - cs[a]);
+            const double r = g.h * sqrt((double)K);
+            const int* lo = (jt < js) ? ct : cs;
+            const int* hi = (jt < js) ? cs : ct;
+            const double inv_h = 1.0 / g.h;
+            const bool d3 = t.D > 2;
+            double tau = tau_march<double>(st, g, inv_h, g.h * (lo[0] + 0.5), g.h * (lo[1] + 0.5),
+                                           d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5),
+                                           g.h * (hi[1] + 0.5), d3 ? g.h * (hi[2] + 0.5) : 0.0,
+                                           steps_grid(K), r);
+            const double rp = (t.D == 2) ? r : r * r;
+            v = exp(-tau) / (surface_area(t.D) * rp);
+        }
+    }
+    blk[i] = T(v);
+}
+
+// ----------------------------------------------- far-field operators ----
+
+__device__ __forceinline__ void node_multi(int m, int nc, int D, int out[3])
+{
+    out[0] = m % nc;
+    out[1] = D > 1 ? (m / nc) % nc : 0;
+    out[2] = D > 2 ? m / (nc * nc) : 0;
+}
+
+// Homogeneous translation matrices of one level: ops[o][r][c] =
+// G(target node r, source node c) for box offset o (FP64 arithmetic).
+template <typename T>
+__global__ void k_ops_hom(int D, int nc, int K, int Kp, double w, double sigma, const double* __restrict__ cheb,
+                          T* __restrict__ ops, __bf16* __restrict__ lo)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = (long)Kp * Kp;
+    int noff = 1;
+    for (int a = 0; a < D; ++a) noff *= kOffSide;
+    if (i >= noff * per) return;
+    int oi = (int)(i / per);
+    long rem = i - (long)oi * per;
+    int r = (int)(rem / Kp), c = (int)(rem % Kp);
+    double v = 0.0;
+    int o[3] = {oi % kOffSide - 3, (oi / kOffSide) % kOffSide - 3, D > 2 ? oi / (kOffSide * kOffSide) - 3 : 0};
+    bool far = false;
+    for (int a = 0; a < D; ++a)
+        if (o[a] < -1 || o[a] > 1) far = true;
+    if (far && r < K && c < K) {
+        int mr[3], mc[3];
+        node_multi(r, nc, D, mr);
+        node_multi(c, nc, D, mc);
+        double r2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double d = w * (o[a] + 0.5 * (cheb[mc[a]] - cheb[mr[a]]));
+            r2 += d * d;
+        }
+        double rr = sqrt(r2);
+        double rp = (D == 2) ? rr : r2;
+        v = exp(-sigma * rr) / (surface_area(D) * rp);
+    }
+    if (lo) {
+        __bf16 hi = (__bf16)(float)v;
+        ((__bf16*)ops)[i] = hi;
+        lo[i] = (__bf16)((float)v - (float)hi);
+    } else {
+        ops[i] = T(v);
+    }
+}
+
+// Heterogeneous translation matrices, one per (target, source) pair of a
+// level, stored source-node major: opsT[pair][c][r] (opsT points at pair p0).  Midpoint ray rule with
+// step <= h/2 between the Chebyshev nodes (FP64 arithmetic).
+template <typename T>
+__global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, int K, int Kp, double w,
+                          int nl0, int nl1, int nl2, const double* __restrict__ cheb, const long* __restrict__ pair_t,
+                          const int* __restrict__ pair_s, long p0, long np, T* __restrict__ opsT)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = (long)Kp * Kp;
+    if (i >= np * per) return;
+    long p = p0 + i / per;
+    long rem = i % per;
+    int c = (int)(rem / Kp), r = (int)(rem % Kp);
+    double v = 0.0;
+    if (r < K && c < K) {
+        const int nl[3] = {nl0, nl1, nl2};
+        int tb[3], sb[3], mr[3], mc[3];
+        unravel3(pair_t[p], nl, tb);
+        unravel3(pair_s[p], nl, sb);
+        node_multi(r, nc, D, mr);
+        node_multi(c, nc, D, mc);
+        double X[3] = {0, 0, 0}, Y[3] = {0, 0, 0};
+        double r2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            X[a] = w * (tb[a] + 0.5) + 0.5 * w * cheb[mr[a]];
+            Y[a] = w * (sb[a] + 0.5) + 0.5 * w * cheb[mc[a]];
+            r2 += (Y[a] - X[a]) * (Y[a] - X[a]);
+        }
+        double rr = sqrt(r2);
+        double q = ceil(rr / (0.5 * g.h));
+        int m = q < 1.0 ? 1 : (int)q;
+        double tau = tau_march<double>(st, g, 1.0 / g.h, X[0], X[1], X[2], Y[0], Y[1], Y[2], m, rr);
+        double rp = (D == 2) ? rr : r2;
+        v = exp(-tau) / (surface_area(D) * rp);
+    }
+    opsT[i] = T(v);
+}
+
+// ---------------------------------------------------------- host helpers ----
+
+double cheb_T(int k, double x)
+{
+    double t0 = 1.0, t1 = x;
+    if (k == 0) return 1.0;
+    for (int i = 1; i < k; ++i) {
+        double t2 = 2.0 * x * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+    }
+    return t1;
+}
+
+// S_n(p, q) for one axis
+double cheb_S(int n, double p, double q)
+{
+    double s = 1.0 / n;
+    for (int k = 1; k < n; ++k) s += 2.0 / n * cheb_T(k, p) * cheb_T(k, q);
+    return s;
+}
+
+template <typename T>
+ert_status upload(hipStream_t s, T** dst, const std::vector<double>& src)
+{
+    std::vector<T> tmp(src.size());
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = T(src[i]);
+    ERT_HIP(hipMalloc(dst, std::max<size_t>(1, tmp.size()) * sizeof(T)));
+    ERT_HIP(hipMemcpyAsync(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    ERT_HIP(hipStreamSynchronize(s));
+    return ERT_OK;
+}
+
+inline unsigned blocks(long n) { return (unsigned)((n + kB - 1) / kB); }
+
+template <typename T>
+struct FmmImpl : FmmData {
+    int prec = ERT_FP64;
+    bool hetero = false;
+    int B = 0;                      // rhs capacity of the work buffers
+    DevTree dt{};
+    T* P1 = nullptr;                // [nc][leaf]
+    T* M1 = nullptr;                // [2][nc][nc]
+    double* cheb = nullptr;         // nodes (FP64, for operator generation)
+    void* ops[kMaxLevels + 1] = {};     // homogeneous: [7^d][Kp][Kp] (bf16 hi for BF16X3)
+    __bf16* ops_lo[kMaxLevels + 1] = {};
+    T* hops[kMaxLevels + 1] = {};       // heterogeneous per-pair, source-node major
+    long* pstart[kMaxLevels + 1] = {};
+    int* psrc[kMaxLevels + 1] = {};
+    T* tab = nullptr;
+    int ntab = 0;
+    T* nearblk = nullptr;
+    T* q = nullptr;
+    T* pot = nullptr;
+    T* W[kMaxLevels + 1] = {};
+    T* Lc[kMaxLevels + 1] = {};
+
+    ~FmmImpl() override
+    {
+        auto f = [](void* p) { if (p) (void)hipFree(p); };
+        f(P1); f(M1); f(cheb); f(tab); f(nearblk); f(q); f(pot);
+        for (int l = 0; l <= kMaxLevels; ++l) {
+            f(ops[l]); f(ops_lo[l]); f(hops[l]); f(pstart[l]); f(psrc[l]); f(W[l]); f(Lc[l]);
+        }
+    }
+
+    ert_status setup(ert_plan_impl* p) override;
+    ert_status ensure_buffers(int nrhs);
+    ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) override;
+};
+
+// Build the tree geometry for a plan.
+FmmTree make_tree(const ert_plan_impl* p)
+{
+    FmmTree t;
+    t.D = p->o.dim;
+    t.nc = p->o.cheb_n > 0 ? p->o.cheb_n : 8;
+    t.K = 1;
+    for (int a = 0; a < t.D; ++a) t.K *= t.nc;
+    t.Kp = (t.K + 31) / 32 * 32;
+    t.leaf = p->o.leaf > 0 ? p->o.leaf : (t.D == 3 ? 4 : 8);
+    t.S = 1;
+    for (int a = 0; a < t.D; ++a) t.S *= t.leaf;
+    const int n[3] = {p->geo.n0, p->geo.n1, p->geo.n2};
+    int mx = 1;
+    t.nleaf = 1;
+    for (int a = 0; a < 3; ++a) {
+        t.nb[a] = (a < t.D) ? (n[a] + t.leaf - 1) / t.leaf : 1;
+        mx = std::max(mx, t.nb[a]);
+        t.nleaf *= t.nb[a];
+    }
+    t.nslot = t.nleaf * t.S;
+    t.L = 0;
+    while ((1 << t.L) < mx) ++t.L;
+    for (int l = 0; l <= t.L; ++l) {
+        t.nbox[l] = 1;
+        for (int a = 0; a < 3; ++a) {
+            int f = 1 << (t.L - l);
+            t.nl[l][a] = (a < t.D) ? (t.nb[a] + f - 1) / f : 1;
+            t.nbox[l] *= t.nl[l][a];
+        }
+        t.width[l] = p->geo.h * t.leaf * (double)(1 << (t.L - l));
+    }
+    return t;
+}
+
+template <typename T>
+ert_status FmmImpl<T>::setup(ert_plan_impl* p)
+{
+    tr = make_tree(p);
+    hetero = p->o.kernel == ERT_K_RAY_MIDPOINT;
+    if (tr.L > kMaxLevels) {
+        record_error("FMM: grid too large for the tree depth limit");
+        return ERT_EUNSUPPORTED;
+    }
+    if (tr.leaf > 8 || tr.nc > 8) {
+        record_error("FMM: leaf side and Chebyshev order must be <= 8");
+        return ERT_EUNSUPPORTED;
+    }
+    dt.D = tr.D; dt.nc = tr.nc; dt.K = tr.K; dt.Kp = tr.Kp; dt.leaf = tr.leaf; dt.S = tr.S;
+    for (int a = 0; a < 3; ++a) dt.nb[a] = tr.nb[a];
+    dt.nleaf = tr.nleaf;
+    dt.nslot = tr.nslot;
+    dt.n[0] = p->geo.n0; dt.n[1] = p->geo.n1; dt.n[2] = p->geo.n2;
+    hipStream_t s = p->stream;
+
+    // 1D interpolation matrices (FP64 on the host)
+    const int nc = tr.nc, leaf = tr.leaf;
+    std::vector<double> node(nc), P1h((size_t)nc * leaf), M1h((size_t)2 * nc * nc);
+    for (int m = 0; m < nc; ++m) node[m] = std::cos((2.0 * m + 1.0) * kPi / (2.0 * nc));
+    for (int m = 0; m < nc; ++m)
+        for (int i = 0; i < leaf; ++i) P1h[(size_t)m * leaf + i] = cheb_S(nc, (2.0 * i + 1.0) / leaf - 1.0, node[m]);
+    for (int c = 0; c < 2; ++c)
+        for (int m = 0; m < nc; ++m)
+            for (int mp = 0; mp < nc; ++mp) {
+                double xi = 0.5 * node[mp] + (c ? 0.5 : -0.5);
+                M1h[((size_t)c * nc + m) * nc + mp] = cheb_S(nc, xi, node[m]);
+            }
+    ERT_TRY(upload<T>(s, &P1, P1h));
+    ERT_TRY(upload<T>(s, &M1, M1h));
+    ERT_TRY(upload<double>(s, &cheb, node));
+
+    const long KpKp = (long)tr.Kp * tr.Kp;
+    if (!hetero) {
+        // near-field table over K = |offset|^2 <= D (2 leaf - 1)^2
+        const int span = 2 * leaf - 1;
+        ntab = tr.D * span * span + 1;
+        std::vector<double> tb(ntab, 0.0);
+        const double sigma = p->sigma_const, h = p->geo.h;
+        for (int K = 1; K < ntab; ++K) {
+            double r = h * std::sqrt((double)K);
+            double rp = (tr.D == 2) ? r : r * r;
+            tb[K] = std::exp(-sigma * r) / (surface_area(tr.D) * rp);
+        }
+        ERT_TRY(upload<T>(s, &tab, tb));
+        int noff = 1;
+        for (int a = 0; a < tr.D; ++a) noff *= kOffSide;
+        for (int l = 2; l <= tr.L; ++l) {
+            const long n = (long)noff * KpKp;
+            if (prec == ERT_BF16X3) {
+                ERT_HIP(hipMalloc(&ops[l], n * sizeof(__bf16)));
+                ERT_HIP(hipMalloc(&ops_lo[l], n * sizeof(__bf16)));
+                hipLaunchKernelGGL(k_ops_hom<float>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, nc, tr.K, tr.Kp,
+                                   tr.width[l], sigma, cheb, (float*)ops[l], ops_lo[l]);
+            } else {
+                ERT_HIP(hipMalloc(&ops[l], n * sizeof(T)));
+                hipLaunchKernelGGL(k_ops_hom<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, nc, tr.K, tr.Kp,
+                                   tr.width[l], sigma, cheb, (T*)ops[l], (__bf16*)nullptr);
+            }
+            ERT_HIP(hipGetLastError());
+        }
+    } else {
+        // near-field cache
+        const int nn = tr.D == 3 ? 27 : 9;
+        const long per = (long)nn * tr.S * tr.S;
+        ERT_HIP(hipMalloc(&nearblk, (size_t)tr.nleaf * per * sizeof(T)));
+        const long chunk = std::max<long>(1, (1L << 26) / per);
+        for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
+            long cnt = std::min(chunk, tr.nleaf - l0);
+            hipLaunchKernelGGL(k_near_blocks<T>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, l0, cnt,
+                               nearblk + (size_t)l0 * per);
+            ERT_HIP(hipGetLastError());
+        }
+        // per-pair translation matrices
+        for (int l = 2; l <= tr.L; ++l) {
+            std::vector<long> start(tr.nbox[l] + 1, 0), ptgt;
+            std::vector<int> src;
+            const int* nl = tr.nl[l];
+            for (long tb = 0; tb < tr.nbox[l]; ++tb) {
+                int t3[3];
+                unravel3(tb, nl, t3);
+                start[tb] = (long)src.size();
+                for (int oz = (tr.D > 2 ? -3 : 0); oz <= (tr.D > 2 ? 3 : 0); ++oz)
+                    for (int oy = -3; oy <= 3; ++oy)
+                        for (int ox = -3; ox <= 3; ++ox) {
+                            int o[3] = {ox, oy, oz}, s3[3];
+                            bool ok = true, adjacent = true;
+                            for (int a = 0; a < 3; ++a) {
+                                s3[a] = t3[a] + o[a];
+                                if (s3[a] < 0 || s3[a] >= nl[a]) ok = false;
+                                if ((t3[a] >> 1) - (s3[a] >> 1) > 1 || (s3[a] >> 1) - (t3[a] >> 1) > 1) ok = false;
+                                if (o[a] < -1 || o[a] > 1) adjacent = false;
+                            }
+                            if (!ok || adjacent) continue;
+                            src.push_back((int)(s3[0] + (long)nl[0] * (s3[1] + (long)nl[1] * s3[2])));
+                            ptgt.push_back(tb);
+                        }
+            }
+            start[tr.nbox[l]] = (long)src.size();
+            const long np = (long)src.size();
+            ERT_HIP(hipMalloc(&pstart[l], start.size() * sizeof(long)));
+            ERT_HIP(hipMalloc(&psrc[l], std::max<long>(1, np) * sizeof(int)));
+            long* ptd = nullptr;
+            ERT_HIP(hipMalloc(&ptd, std::max<long>(1, np) * sizeof(long)));
+            ERT_HIP(hipMemcpyAsync(pstart[l], start.data(), start.size() * sizeof(long), hipMemcpyHostToDevice, s));
+            ERT_HIP(hipMemcpyAsync(psrc[l], src.data(), np * sizeof(int), hipMemcpyHostToDevice, s));
+            ERT_HIP(hipMemcpyAsync(ptd, ptgt.data(), np * sizeof(long), hipMemcpyHostToDevice, s));
+            size_t bytes = (size_t)np * KpKp * sizeof(T);
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
+                (void)hipFree(ptd);
+                record_error("FMM: heterogeneous translation cache does not fit in device memory");
+                return ERT_ENOMEM;
+            }
+            if (hipMalloc(&hops[l], std::max<size_t>(1, bytes)) != hipSuccess) {
+                (void)hipFree(ptd);
+                record_error("FMM: heterogeneous translation cache allocation failed");
+                return ERT_ENOMEM;
+            }
+            const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
+            for (long p0 = 0; p0 < np; p0 += pchunk) {
+                long cnt = std::min(pchunk, np - p0);
+                hipLaunchKernelGGL(k_ops_het<T>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, nc,
+                                   tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, psrc[l], p0, cnt,
+                                   hops[l] + (size_t)p0 * KpKp);
+                ERT_HIP(hipGetLastError());
+            }
+            ERT_HIP(hipStreamSynchronize(s));
+            (void)hipFree(ptd);
+        }
+    }
+    ERT_HIP(hipStreamSynchronize(s));
+    return ensure_buffers(1);
+}
+
+template <typename T>
+ert_status FmmImpl<T>::ensure_buffers(int nrhs)
+{
+    if (nrhs <= B) return ERT_OK;
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(q); f(pot);
+    q = pot = nullptr;
+    for (int l = 0; l <= kMaxLevels; ++l) { f(W[l]); f(Lc[l]); W[l] = Lc[l] = nullptr; }
+    B = 0;
+    ERT_HIP(hipMalloc(&q, (size_t)nrhs * tr.nslot * sizeof(T)));
+    ERT_HIP(hipMalloc(&pot, (size_t)nrhs * tr.nslot * sizeof(T)));
+    for (int l = 2; l <= tr.L; ++l) {
+        size_t n = (size_t)nrhs * tr.nbox[l] * tr.Kp;
+        ERT_HIP(hipMalloc(&W[l], n * sizeof(T)));
+        ERT_HIP(hipMalloc(&Lc[l], n * sizeof(T)));
+        // node padding (K..Kp) stays zero: the transfers never write it
+        ERT_HIP(hipMemset(W[l], 0, n * sizeof(T)));
+        ERT_HIP(hipMemset(Lc[l], 0, n * sizeof(T)));
+    }
+    B = nrhs;
+    return ERT_OK;
+}
+
+template <typename T>
+ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs)
+{
+    ERT_TRY(ensure_buffers(nrhs));
+    hipStream_t s = p->stream;
+    const long N = p->N;
+    const int nn = tr.D == 3 ? 27 : 9;
+    Profiler* pf = &p->prof;
+    // a4: weights into leaf-major order
+    { StageTimer st_(pf, s, ERT_STAGE_GATHER);
+    hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, x, p->d_ss,
+                       op != ERT_OP_G ? 1 : 0, N, nrhs, q);
+    ERT_HIP(hipGetLastError()); }
+    // a10: near field (writes pot)
+    { StageTimer st_(pf, s, ERT_STAGE_NEAR);
+    if (!hetero) {
+        const int tpp = std::min(tr.S, kB);
+        const int groups = kB / tpp;
+        size_t sh = (size_t)(ntab + nn * tr.S) * sizeof(T) + 32 * sizeof(int) + (size_t)groups * tpp * sizeof(T);
+        hipLaunchKernelGGL(k_p2p_hom<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), sh, s, dt, q, tab, ntab, pot);
+    } else {
+        hipLaunchKernelGGL(k_p2p_cached<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), tr.S * sizeof(T), s, dt, q,
+                           nearblk, pot);
+    }
+    ERT_HIP(hipGetLastError()); }
+    if (tr.L >= 2) {
+        const int L = tr.L;
+        // a5: P2M on the leaves
+        { StageTimer st_(pf, s, ERT_STAGE_P2M);
+        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, q, P1, W[L]);
+        ERT_HIP(hipGetLastError()); }
+        // a6: M2M up to level 2
+        for (int l = L - 1; l >= 2; --l) {
+            StageTimer st_(pf, s, ERT_STAGE_M2M);
+            hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)tr.nbox[l], nrhs), dim3(kB), 0, s, tr.D, tr.nc, tr.K, tr.Kp,
+                               tr.nl[l][0], tr.nl[l][1], tr.nl[l][2], tr.nbox[l], tr.nl[l + 1][0], tr.nl[l + 1][1],
+                               tr.nl[l + 1][2], tr.nbox[l + 1], W[l + 1], M1, W[l]);
+            ERT_HIP(hipGetLastError());
+        }
+        // a7/a8: downward pass
+        for (int l = 2; l <= L; ++l) {
+            { StageTimer st_(pf, s, ERT_STAGE_L2L);
+            if (l == 2) {
+                long n = (long)nrhs * tr.nbox[2] * tr.Kp;
+                hipLaunchKernelGGL(k_zero_t<T>, dim3(blocks(n)), dim3(kB), 0, s, Lc[2], n);
+            } else {
+                hipLaunchKernelGGL(k_l2l<T>, dim3((unsigned)tr.nbox[l], nrhs), dim3(kB), 0, s, tr.D, tr.nc, tr.K,
+                                   tr.Kp, tr.nl[l - 1][0], tr.nl[l - 1][1], tr.nl[l - 1][2], tr.nbox[l - 1],
+                                   tr.nl[l][0], tr.nl[l][1], tr.nl[l][2], tr.nbox[l], Lc[l - 1], M1, Lc[l]);
+            }
+            ERT_HIP(hipGetLastError()); }
+            M2LArgs a;
+            a.D = tr.D;
+            for (int d = 0; d < 3; ++d) a.nl[d] = tr.nl[l][d];
+            a.nbox = tr.nbox[l];
+            a.Kp = tr.Kp;
+            a.B = nrhs;
+            a.ops = hetero ? (const void*)hops[l] : ops[l];
+            a.ops_lo = ops_lo[l];
+            a.W = W[l];
+            a.L = Lc[l];
+            a.pair_start = pstart[l];
+            a.pair_src = psrc[l];
+            StageTimer st_(pf, s, ERT_STAGE_M2L);
+            ERT_TRY(m2l_launch(s, prec, hetero, a));
+        }
+        // a9: L2P adds the far field
+        StageTimer st_(pf, s, ERT_STAGE_L2P);
+        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, Lc[L], P1, pot);
+        ERT_HIP(hipGetLastError());
+    }
+    // a11: scale, self term, operator
+    const double hd = std::pow(p->geo.h, tr.D);
+    StageTimer st_(pf, s, ERT_STAGE_ASSEMBLE);
+    hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, x, p->d_ss, p->d_diag, op, hd,
+                       N, nrhs, y);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+}  // namespace
+
+ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs)
+{
+    if (prec < 0 || prec > 2) return ERT_EINVAL;
+    if (!p->fmm[prec]) {
+        FmmData* f = nullptr;
+        if (prec == ERT_FP64) {
+            auto* g = new (std::nothrow) FmmImpl<double>();
+            if (g) g->prec = ERT_FP64;
+            f = g;
+        } else {
+            auto* g = new (std::nothrow) FmmImpl<float>();
+            if (g) g->prec = prec;
+            f = g;
+        }
+        if (!f) return ERT_ENOMEM;
+        if (prec == ERT_BF16X3 && p->o.kernel == ERT_K_RAY_MIDPOINT) {
+            // the heterogeneous far field streams per-pair matrices: FP32 it is
+            static_cast<FmmImpl<float>*>(f)->prec = ERT_FP32;
+        }
+        ert_status st = f->setup(p);
+        if (st != ERT_OK) {
+            delete f;
+            return st;
+        }
+        p->fmm[prec] = f;
+    }
+    return p->fmm[prec]->apply(p, op, x, y, nrhs);
+}
 
 void fmm_destroy(FmmData* f) { delete f; }
 

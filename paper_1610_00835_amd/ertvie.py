@@ -20,6 +20,9 @@ DIRECT, FMM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
 OP_G, OP_GS, OP_A = 0, 1, 2
 
+STAGES = ("gather", "near", "p2m", "m2m", "m2l", "l2l", "l2p", "assemble", "direct")
+NSTAGES = len(STAGES)
+
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 _METHOD = {"direct": DIRECT, "fmm": FMM}
 
@@ -82,6 +85,8 @@ def load():
     L.ert_vie_size.argtypes = [_vp]
     L.ert_vie_destroy.restype = None
     L.ert_vie_destroy.argtypes = [_vp]
+    L.ert_vie_profile.restype = ctypes.c_int
+    L.ert_vie_profile.argtypes = [_vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]
     L.ert_vie_last_error.restype = ctypes.c_char_p
     L.ert_vie_last_error.argtypes = []
     L.ert_vie_strerror.restype = ctypes.c_char_p
@@ -201,6 +206,13 @@ class Plan:
         if not (st == OK or (allow_noconv and st == ENOCONV)):
             _check(st, "ert_vie_solve")
         return out
+
+    def profile(self, enable):
+        """Toggle per-stage event timing; returns {stage: (ms, launches)} recorded so far."""
+        ms = (ctypes.c_double * NSTAGES)()
+        ln = (ctypes.c_int * NSTAGES)()
+        _check(load().ert_vie_profile(self.handle, int(bool(enable)), ms, ln), "ert_vie_profile")
+        return {STAGES[i]: (ms[i], ln[i]) for i in range(NSTAGES)}
 
     def diag(self):
         d = np.empty(self.N)
