@@ -94,9 +94,13 @@ typedef struct {
     int method;       /* ert_method used by ert_vie_apply and the solver */
     int prec;         /* ert_prec used by ert_vie_apply and the solver */
     int cheb_n;       /* FMM: Chebyshev nodes per axis (Sec. 3.3, n); 0 -> 8; 2..8 */
-    int leaf;         /* FMM: cells per leaf-box side; 0 -> 4 (3D) / 8 (2D) */
+    int leaf;         /* FMM: cells per leaf-box side; 0 -> 8; 1..8 */
     int nrhs_max;     /* largest nrhs later passed to apply/solve; 0 -> 1 */
     int flags;        /* reserved, must be 0 */
+    double svd_tol;   /* FMM, homogeneous media: relative singular-value cutoff of the
+                         compressed far-field translations (shared orthonormal basis per
+                         level from the SVD of all translation matrices); 0 -> 1e-7,
+                         < 0 -> no compression */
 } ert_vie_opts;
 
 typedef struct {
@@ -161,8 +165,21 @@ typedef enum {
     ERT_STAGE_L2P = 6,
     ERT_STAGE_ASSEMBLE = 7, /* scaling, self term, I - K */
     ERT_STAGE_DIRECT = 8,   /* dense apply */
-    ERT_NSTAGES = 9
+    ERT_STAGE_BASIS = 9,    /* change of basis of the compressed translations */
+    ERT_NSTAGES = 10
 } ert_stage;
+
+/* Shape of a plan's FMM for one precision (built on first use). */
+typedef struct {
+    int levels;           /* leaf level L of the tree; far field on levels 2..L */
+    int leaf;             /* cells per leaf side */
+    int cheb_n;           /* Chebyshev nodes per axis */
+    int nodes;            /* nodes per box (cheb_n^dim) */
+    int nodes_padded;     /* nodes per box as stored (multiple of 32) */
+    int rank[16];         /* per level: compressed translation rank as stored, 0 = uncompressed */
+    long far_pairs[16];   /* per level: (target, source) box pairs of the interaction lists */
+    long near_pairs;      /* point pairs of the near field (self pairs excluded) */
+} ert_fmm_info;
 
 /* Device timing of applies by stage, with HIP events recorded on the plan's
  * stream around every kernel launch of a stage.
@@ -171,6 +188,9 @@ typedef enum {
  *   receive the totals recorded so far (synchronises the stream).
  * Recording adds an event pair per launch; leave it off for timed runs. */
 ERT_API ert_status ert_vie_profile(ert_vie_plan_t plan, int enable, double* stage_ms, int* stage_launches);
+
+/* Build (if needed) the FMM of precision `prec` and describe it (host struct). */
+ERT_API ert_status ert_vie_fmm_info(ert_vie_plan_t plan, int prec, ert_fmm_info* info);
 
 /* Copy the diagonal A_jj (N values, FP64) to host memory `d` (synchronises). */
 ERT_API ert_status ert_vie_diag(ert_vie_plan_t plan, double* d);

@@ -331,7 +331,8 @@ ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const d
     if (o.method != ERT_DIRECT && o.method != ERT_FMM) return ERT_EINVAL;
     if (o.prec != ERT_FP64 && o.prec != ERT_FP32 && o.prec != ERT_BF16X3) return ERT_EINVAL;
     if (o.cheb_n != 0 && (o.cheb_n < 2 || o.cheb_n > 8)) return ERT_EINVAL;
-    if (o.leaf < 0 || o.leaf > 64 || o.nrhs_max < 0) return ERT_EINVAL;
+    if (o.leaf < 0 || o.leaf > 8 || o.nrhs_max < 0 || !std::isfinite(o.svd_tol) || o.svd_tol >= 1.0)
+        return ERT_EINVAL;
     long N = 1;
     for (int a = 0; a < o.dim; ++a) {
         if (o.n[a] < 1 || o.n[a] > (1 << 20)) return ERT_EINVAL;
@@ -426,6 +427,12 @@ ert_status ert_vie_profile(ert_vie_plan_t p, int enable, double* stage_ms, int* 
     if (enable && !p->prof.on) p->prof.clear();
     p->prof.on = enable != 0;
     return ERT_OK;
+}
+
+ert_status ert_vie_fmm_info(ert_vie_plan_t p, int prec, ert_fmm_info* info)
+{
+    if (!p || !info || prec < ERT_FP64 || prec > ERT_BF16X3) return ERT_EINVAL;
+    return fmm_info(p, prec, info);
 }
 
 ert_status ert_vie_diag(ert_vie_plan_t p, double* d)

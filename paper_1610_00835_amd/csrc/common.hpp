@@ -141,6 +141,12 @@ struct StageTimer {
     {
         if (p && p->on) p->begin(s, stage, &ev0);
     }
+    // drop the bracket (an inner bracket takes over)
+    void pause()
+    {
+        if (p && p->on && ev0) p->pool.push_back(ev0);
+        ev0 = nullptr;
+    }
     ~StageTimer()
     {
         if (p && p->on && ev0) p->end(s, stage, ev0);
@@ -173,6 +179,7 @@ struct ert_plan_impl {
 ert_status selfcell_compute(ert_plan_impl* p);
 ert_status direct_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
 ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
+ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info);
 void fmm_destroy(FmmData* f);
 
 // BLAS-1 helpers for GMRES (blas.hip); all stream-ordered on `s`.

@@ -19,6 +19,7 @@
 // (at most 6^d - 3^d, Sec. 4.2).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -28,6 +29,7 @@ namespace ertvie {
 
 struct FmmData {
     virtual ~FmmData() {}
+    virtual int rank_of(int l) const = 0;
     virtual ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) = 0;
     virtual ert_status setup(ert_plan_impl* p) = 0;
     FmmTree tr;
@@ -517,6 +519,110 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, i
     opsT[i] = T(v);
 }
 
+
+// Near-field blocks of a homogeneous medium: on a uniform grid the block
+// between a target leaf and its neighbour at leaf offset o depends only on o.
+// ops[o][target i][source i] = G, zero for the self pair.
+template <typename T>
+__global__ void k_near_ops(int D, int leaf, int S, double h, double sigma, T* __restrict__ ops)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = (long)S * S;
+    const int nop = (D == 3) ? 27 : 9;
+    if (i >= nop * per) return;
+    int oi = (int)(i / per);
+    long rem = i - (long)oi * per;
+    int it = (int)(rem / S), is = (int)(rem % S);
+    int o[3] = {oi % 3 - 1, (oi / 3) % 3 - 1, D == 3 ? oi / 9 - 1 : 0};
+    int ls1 = D > 1 ? leaf : 1;
+    int lt[3] = {it % leaf, (it / leaf) % ls1, it / (leaf * ls1)};
+    int lsr[3] = {is % leaf, (is / leaf) % ls1, is / (leaf * ls1)};
+    int K = 0;
+    for (int a = 0; a < D; ++a) {
+        int d = o[a] * leaf + lsr[a] - lt[a];
+        K += d * d;
+    }
+    double v = 0.0;
+    if (K > 0) {
+        double r = h * sqrt((double)K);
+        double rp = (D == 2) ? r : r * r;
+        v = exp(-sigma * r) / (surface_area(D) * rp);
+    }
+    ops[i] = T(v);
+}
+
+// Batched FP64 GEMM with B transposed, for plan-time work:
+//   sumbatch: C(i,j) = sum_b sum_k A_b(i,k) B_b(j,k);  else C_b(i,j) = sum_k A_b(i,k) B_b(j,k)
+// with arbitrary strides.  64x64 tiles, 4x4 outputs per thread, k-chunks of 16 in LDS.
+struct GemmBT {
+    int M, N, Kd, nb, sumbatch;
+    const double* A; long sAb, sAi, sAk;
+    const double* B; long sBb, sBj, sBk;
+    double* C; long sCb, sCi, sCj;
+};
+
+__global__ __launch_bounds__(256) void k_gemm_bt(GemmBT g)
+{
+    __shared__ double As[16][65], Bs[16][65];
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    const int b_lo = g.sumbatch ? 0 : blockIdx.z, b_hi = g.sumbatch ? g.nb : blockIdx.z + 1;
+    for (int b = b_lo; b < b_hi; ++b) {
+        const double* A = g.A + (long)b * g.sAb;
+        const double* Bm = g.B + (long)b * g.sBb;
+        for (int k0 = 0; k0 < g.Kd; k0 += 16) {
+            for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+                int kk = e / 64, r = e % 64;
+                int i = i0 + r, j = j0 + r, k = k0 + kk;
+                As[kk][r] = (i < g.M && k < g.Kd) ? A[i * g.sAi + k * g.sAk] : 0.0;
+                Bs[kk][r] = (j < g.N && k < g.Kd) ? Bm[j * g.sBj + k * g.sBk] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                double a[4], bb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = As[kk][ty * 4 + u];
+                    bb[u] = Bs[kk][tx * 4 + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+            }
+            __syncthreads();
+        }
+    }
+    double* C = g.C + (g.sumbatch ? 0 : (long)blockIdx.z * g.sCb);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+            if (i < g.M && j < g.N) C[i * g.sCi + j * g.sCj] = acc[u][v];
+        }
+}
+
+template <typename T>
+__global__ void k_cvt(const double* __restrict__ src, T* __restrict__ dst, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = T(src[i]);
+}
+
+__global__ void k_cvt_bf16x2(const double* __restrict__ src, __bf16* __restrict__ hi, __bf16* __restrict__ lo, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) {
+        float v = (float)src[i];
+        __bf16 h = (__bf16)v;
+        hi[i] = h;
+        lo[i] = (__bf16)(v - (float)h);
+    }
+}
+
 // ---------------------------------------------------------- host helpers ----
 
 double cheb_T(int k, double x)
@@ -531,7 +637,7 @@ double cheb_T(int k, double x)
     return t1;
 }
 
-// S_n(p, q) for one axis
+// S_n(p, q) for one axis (eq. EQ: CHEB)
 double cheb_S(int n, double p, double q)
 {
     double s = 1.0 / n;
@@ -540,52 +646,119 @@ double cheb_S(int n, double p, double q)
 }
 
 template <typename T>
-ert_status upload(hipStream_t s, T** dst, const std::vector<double>& src)
+ert_status upload(hipStream_t s, T** dst, const std::vector<T>& src)
 {
-    std::vector<T> tmp(src.size());
-    for (size_t i = 0; i < src.size(); ++i) tmp[i] = T(src[i]);
-    ERT_HIP(hipMalloc(dst, std::max<size_t>(1, tmp.size()) * sizeof(T)));
-    ERT_HIP(hipMemcpyAsync(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    ERT_HIP(hipMalloc(dst, std::max<size_t>(1, src.size()) * sizeof(T)));
+    ERT_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
     ERT_HIP(hipStreamSynchronize(s));
     return ERT_OK;
 }
 
+template <typename T>
+ert_status upload_cvt(hipStream_t s, T** dst, const std::vector<double>& src)
+{
+    std::vector<T> tmp(src.size());
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = T(src[i]);
+    return upload<T>(s, dst, tmp);
+}
+
 inline unsigned blocks(long n) { return (unsigned)((n + kB - 1) / kB); }
+
+ert_status gemm_bt(hipStream_t s, const GemmBT& g)
+{
+    dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64), g.sumbatch ? 1u : (unsigned)g.nb);
+    hipLaunchKernelGGL(k_gemm_bt, grid, dim3(256), 0, s, g);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+struct DevPtrs {
+    std::vector<void*> p;
+    ~DevPtrs()
+    {
+        for (void* q : p)
+            if (q) (void)hipFree(q);
+    }
+    template <typename T>
+    ert_status alloc(T** out, size_t n)
+    {
+        *out = nullptr;
+        if (hipMalloc(out, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) {
+            record_error("FMM: device allocation failed during setup");
+            return ERT_ENOMEM;
+        }
+        p.push_back(*out);
+        return ERT_OK;
+    }
+};
+
+}  // namespace
+
+void sym_eig(int n, const std::vector<double>& A, std::vector<double>& w, std::vector<double>& Z);
+
+namespace {
 
 template <typename T>
 struct FmmImpl : FmmData {
     int prec = ERT_FP64;
     bool hetero = false;
+    bool compress = false;
     int B = 0;                      // rhs capacity of the work buffers
     DevTree dt{};
     T* P1 = nullptr;                // [nc][leaf]
     T* M1 = nullptr;                // [2][nc][nc]
     double* cheb = nullptr;         // nodes (FP64, for operator generation)
-    void* ops[kMaxLevels + 1] = {};     // homogeneous: [7^d][Kp][Kp] (bf16 hi for BF16X3)
+    BoxOffset* m2l_offs = nullptr;  // [2^d classes][noff]
+    int m2l_noff = 0;
+    BoxOffset* near_offs = nullptr; // [3^d]
+    BoxOffset* id_off = nullptr;    // [1]: the zero offset
+    void* ops[kMaxLevels + 1] = {};     // far translations [7^d][M][M] (bf16 high parts for BF16X3)
     __bf16* ops_lo[kMaxLevels + 1] = {};
+    int rp[kMaxLevels + 1] = {};        // compressed rank (padded), 0 = uncompressed
+    T* Ut[kMaxLevels + 1] = {};         // [rp][Kp]: multipoles -> compressed
+    T* Um[kMaxLevels + 1] = {};         // [Kp][rp]: compressed locals -> locals
     T* hops[kMaxLevels + 1] = {};       // heterogeneous per-pair, source-node major
     long* pstart[kMaxLevels + 1] = {};
     int* psrc[kMaxLevels + 1] = {};
-    T* tab = nullptr;
+    T* nearops = nullptr;               // homogeneous near blocks [3^d][S][S]
+    T* tab = nullptr;                   // homogeneous near table (S not a multiple of 32)
     int ntab = 0;
-    T* nearblk = nullptr;
+    T* nearblk = nullptr;               // heterogeneous near cache
     T* q = nullptr;
     T* pot = nullptr;
     T* W[kMaxLevels + 1] = {};
     T* Lc[kMaxLevels + 1] = {};
+    T* Wc[kMaxLevels + 1] = {};         // compressed multipoles
+    T* Lh[kMaxLevels + 1] = {};         // compressed locals
 
     ~FmmImpl() override
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(P1); f(M1); f(cheb); f(tab); f(nearblk); f(q); f(pot);
+        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(nearblk); f(q); f(pot);
         for (int l = 0; l <= kMaxLevels; ++l) {
-            f(ops[l]); f(ops_lo[l]); f(hops[l]); f(pstart[l]); f(psrc[l]); f(W[l]); f(Lc[l]);
+            f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]); f(hops[l]); f(pstart[l]); f(psrc[l]);
+            f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
         }
     }
 
+    int rank_of(int l) const override { return rp[l]; }
     ert_status setup(ert_plan_impl* p) override;
+    ert_status setup_far_hom(ert_plan_impl* p, int l, double svd_tol);
+    ert_status setup_far_het(ert_plan_impl* p, int l);
     ert_status ensure_buffers(int nrhs);
     ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) override;
+
+    BoxGemm gemm_desc(int l, int Mrows, int Kd, int nrhs) const
+    {
+        BoxGemm g{};
+        g.D = tr.D;
+        for (int d = 0; d < 3; ++d) g.nl[d] = tr.nl[l][d];
+        g.nbox = tr.nbox[l];
+        g.B = nrhs;
+        g.M = Mrows;
+        g.Kd = Kd;
+        return g;
+    }
 };
 
 // Build the tree geometry for a plan.
@@ -597,7 +770,7 @@ FmmTree make_tree(const ert_plan_impl* p)
     t.K = 1;
     for (int a = 0; a < t.D; ++a) t.K *= t.nc;
     t.Kp = (t.K + 31) / 32 * 32;
-    t.leaf = p->o.leaf > 0 ? p->o.leaf : (t.D == 3 ? 4 : 8);
+    t.leaf = p->o.leaf > 0 ? p->o.leaf : 8;
     t.S = 1;
     for (int a = 0; a < t.D; ++a) t.S *= t.leaf;
     const int n[3] = {p->geo.n0, p->geo.n1, p->geo.n2};
@@ -611,7 +784,7 @@ FmmTree make_tree(const ert_plan_impl* p)
     t.nslot = t.nleaf * t.S;
     t.L = 0;
     while ((1 << t.L) < mx) ++t.L;
-    for (int l = 0; l <= t.L; ++l) {
+    for (int l = 0; l <= t.L && l <= kMaxLevels; ++l) {
         t.nbox[l] = 1;
         for (int a = 0; a < 3; ++a) {
             int f = 1 << (t.L - l);
@@ -621,6 +794,138 @@ FmmTree make_tree(const ert_plan_impl* p)
         t.width[l] = p->geo.h * t.leaf * (double)(1 << (t.L - l));
     }
     return t;
+}
+
+// Homogeneous far field of level l: translation matrices for every box offset
+// in [-3,3]^d (FP64 on the GPU); optionally compressed with the orthonormal
+// basis U of the dominant left singular vectors of [M_o1 M_o2 ...] (which are
+// also the right ones, the kernel being symmetric): M_o ~ U (U^T M_o U) U^T.
+template <typename T>
+ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
+{
+    hipStream_t s = p->stream;
+    const int Kp = tr.Kp;
+    int noff = 1;
+    for (int a = 0; a < tr.D; ++a) noff *= kOffSide;
+    const long KpKp = (long)Kp * Kp;
+    DevPtrs tmp;
+    double* M64 = nullptr;
+    ERT_TRY(tmp.alloc(&M64, (size_t)noff * KpKp));
+    hipLaunchKernelGGL(k_ops_hom<double>, dim3(blocks(noff * KpKp)), dim3(kB), 0, s, tr.D, tr.nc, tr.K, Kp,
+                       tr.width[l], p->sigma_const, cheb, M64, (__bf16*)nullptr);
+    ERT_HIP(hipGetLastError());
+    const double* Cd = M64;
+    int M = Kp;
+    if (svd_tol >= 0.0) {
+        // Gram matrix sum_o M_o M_o^T (near offsets are zero matrices)
+        double* gram = nullptr;
+        ERT_TRY(tmp.alloc(&gram, (size_t)KpKp));
+        GemmBT g{Kp, Kp, Kp, noff, 1, M64, KpKp, Kp, 1, M64, KpKp, Kp, 1, gram, 0, Kp, 1};
+        ERT_TRY(gemm_bt(s, g));
+        std::vector<double> G((size_t)KpKp), w, Z;
+        ERT_HIP(hipMemcpyAsync(G.data(), gram, KpKp * sizeof(double), hipMemcpyDeviceToHost, s));
+        ERT_HIP(hipStreamSynchronize(s));
+        sym_eig(Kp, G, w, Z);
+        const double wmax = w.empty() ? 0.0 : w[0];
+        int r = 0;
+        while (r < Kp && w[r] > 0.0 && std::sqrt(w[r] / wmax) > svd_tol) ++r;
+        if (r < 1) r = 1;
+        const int R = std::min(Kp, (r + 31) / 32 * 32);
+        std::vector<double> Uh((size_t)Kp * R, 0.0);
+        for (int i = 0; i < Kp; ++i)
+            for (int c = 0; c < r; ++c) Uh[(size_t)i * R + c] = Z[(size_t)i * Kp + c];
+        double* U64 = nullptr;
+        ERT_TRY(tmp.alloc(&U64, Uh.size()));
+        ERT_HIP(hipMemcpyAsync(U64, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        // T_o = M_o U (Kp x R), C_o = U^T T_o (R x R)
+        double *T1 = nullptr, *C64 = nullptr;
+        ERT_TRY(tmp.alloc(&T1, (size_t)noff * Kp * R));
+        ERT_TRY(tmp.alloc(&C64, (size_t)noff * R * R));
+        GemmBT g1{Kp, R, Kp, noff, 0, M64, KpKp, Kp, 1, U64, 0, 1, R, T1, (long)Kp * R, R, 1};
+        ERT_TRY(gemm_bt(s, g1));
+        GemmBT g2{R, R, Kp, noff, 0, U64, 0, 1, R, T1, (long)Kp * R, 1, R, C64, (long)R * R, R, 1};
+        ERT_TRY(gemm_bt(s, g2));
+        // change-of-basis matrices in the working precision
+        std::vector<double> Ut_h((size_t)R * Kp);
+        for (int c = 0; c < R; ++c)
+            for (int i = 0; i < Kp; ++i) Ut_h[(size_t)c * Kp + i] = Uh[(size_t)i * R + c];
+        ERT_TRY(upload_cvt<T>(s, &Ut[l], Ut_h));
+        ERT_TRY(upload_cvt<T>(s, &Um[l], Uh));
+        rp[l] = R;
+        Cd = C64;
+        M = R;
+    }
+    const long n = (long)noff * M * M;
+    if (prec == ERT_BF16X3) {
+        ERT_HIP(hipMalloc(&ops[l], n * sizeof(__bf16)));
+        ERT_HIP(hipMalloc(&ops_lo[l], n * sizeof(__bf16)));
+        hipLaunchKernelGGL(k_cvt_bf16x2, dim3(blocks(n)), dim3(kB), 0, s, Cd, (__bf16*)ops[l], ops_lo[l], n);
+    } else {
+        ERT_HIP(hipMalloc(&ops[l], n * sizeof(T)));
+        hipLaunchKernelGGL(k_cvt<T>, dim3(blocks(n)), dim3(kB), 0, s, Cd, (T*)ops[l], n);
+    }
+    ERT_HIP(hipGetLastError());
+    ERT_HIP(hipStreamSynchronize(s));
+    return ERT_OK;
+}
+
+// Heterogeneous far field of level l: one matrix per (target, source) pair.
+template <typename T>
+ert_status FmmImpl<T>::setup_far_het(ert_plan_impl* p, int l)
+{
+    hipStream_t s = p->stream;
+    const long KpKp = (long)tr.Kp * tr.Kp;
+    std::vector<long> start(tr.nbox[l] + 1, 0), ptgt;
+    std::vector<int> src;
+    const int* nl = tr.nl[l];
+    for (long tb = 0; tb < tr.nbox[l]; ++tb) {
+        int t3[3];
+        unravel3(tb, nl, t3);
+        start[tb] = (long)src.size();
+        for (int oz = (tr.D > 2 ? -3 : 0); oz <= (tr.D > 2 ? 3 : 0); ++oz)
+            for (int oy = -3; oy <= 3; ++oy)
+                for (int ox = -3; ox <= 3; ++ox) {
+                    int o[3] = {ox, oy, oz}, s3[3];
+                    bool ok = true, adjacent = true;
+                    for (int a = 0; a < 3; ++a) {
+                        s3[a] = t3[a] + o[a];
+                        if (s3[a] < 0 || s3[a] >= nl[a]) ok = false;
+                        if ((t3[a] >> 1) - (s3[a] >> 1) > 1 || (s3[a] >> 1) - (t3[a] >> 1) > 1) ok = false;
+                        if (o[a] < -1 || o[a] > 1) adjacent = false;
+                    }
+                    if (!ok || adjacent) continue;
+                    src.push_back((int)(s3[0] + (long)nl[0] * (s3[1] + (long)nl[1] * s3[2])));
+                    ptgt.push_back(tb);
+                }
+    }
+    start[tr.nbox[l]] = (long)src.size();
+    const long np = (long)src.size();
+    ERT_TRY(upload<long>(s, &pstart[l], start));
+    ERT_TRY(upload<int>(s, &psrc[l], src));
+    DevPtrs tmp;
+    long* ptd = nullptr;
+    ERT_TRY(tmp.alloc(&ptd, (size_t)np));
+    ERT_HIP(hipMemcpyAsync(ptd, ptgt.data(), np * sizeof(long), hipMemcpyHostToDevice, s));
+    size_t bytes = (size_t)np * KpKp * sizeof(T);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
+        record_error("FMM: heterogeneous translation cache does not fit in device memory");
+        return ERT_ENOMEM;
+    }
+    if (hipMalloc(&hops[l], std::max<size_t>(1, bytes)) != hipSuccess) {
+        record_error("FMM: heterogeneous translation cache allocation failed");
+        return ERT_ENOMEM;
+    }
+    const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
+    for (long p0 = 0; p0 < np; p0 += pchunk) {
+        long cnt = std::min(pchunk, np - p0);
+        hipLaunchKernelGGL(k_ops_het<T>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, tr.nc,
+                           tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, psrc[l], p0, cnt,
+                           hops[l] + (size_t)p0 * KpKp);
+        ERT_HIP(hipGetLastError());
+    }
+    ERT_HIP(hipStreamSynchronize(s));
+    return ERT_OK;
 }
 
 template <typename T>
@@ -655,44 +960,83 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
                 double xi = 0.5 * node[mp] + (c ? 0.5 : -0.5);
                 M1h[((size_t)c * nc + m) * nc + mp] = cheb_S(nc, xi, node[m]);
             }
-    ERT_TRY(upload<T>(s, &P1, P1h));
-    ERT_TRY(upload<T>(s, &M1, M1h));
+    ERT_TRY(upload_cvt<T>(s, &P1, P1h));
+    ERT_TRY(upload_cvt<T>(s, &M1, M1h));
     ERT_TRY(upload<double>(s, &cheb, node));
 
-    const long KpKp = (long)tr.Kp * tr.Kp;
-    if (!hetero) {
-        // near-field table over K = |offset|^2 <= D (2 leaf - 1)^2
-        const int span = 2 * leaf - 1;
-        ntab = tr.D * span * span + 1;
-        std::vector<double> tb(ntab, 0.0);
-        const double sigma = p->sigma_const, h = p->geo.h;
-        for (int K = 1; K < ntab; ++K) {
-            double r = h * std::sqrt((double)K);
-            double rp = (tr.D == 2) ? r : r * r;
-            tb[K] = std::exp(-sigma * r) / (surface_area(tr.D) * rp);
+    // offset tables: far-field interaction offsets per parity class, near offsets, identity
+    {
+        const int classes = 1 << tr.D;
+        std::vector<BoxOffset> far;
+        int per = 0;
+        for (int c = 0; c < classes; ++c) {
+            int pc[3] = {c & 1, tr.D > 1 ? (c >> 1) & 1 : 0, tr.D > 2 ? (c >> 2) & 1 : 0};
+            int cnt = 0;
+            for (int oz = (tr.D > 2 ? -2 - pc[2] : 0); oz <= (tr.D > 2 ? 3 - pc[2] : 0); ++oz)
+                for (int oy = -2 - pc[1]; oy <= 3 - pc[1]; ++oy)
+                    for (int ox = -2 - pc[0]; ox <= 3 - pc[0]; ++ox) {
+                        if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) continue;
+                        // operator slot: lexicographic in [-3,3]^d (no z term in 2D)
+                        int op = (ox + 3) + kOffSide * ((oy + 3) + (tr.D > 2 ? kOffSide * (oz + 3) : 0));
+                        far.push_back({ox, oy, oz, op});
+                        ++cnt;
+                    }
+            per = cnt;
         }
-        ERT_TRY(upload<T>(s, &tab, tb));
-        int noff = 1;
-        for (int a = 0; a < tr.D; ++a) noff *= kOffSide;
-        for (int l = 2; l <= tr.L; ++l) {
-            const long n = (long)noff * KpKp;
-            if (prec == ERT_BF16X3) {
-                ERT_HIP(hipMalloc(&ops[l], n * sizeof(__bf16)));
-                ERT_HIP(hipMalloc(&ops_lo[l], n * sizeof(__bf16)));
-                hipLaunchKernelGGL(k_ops_hom<float>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, nc, tr.K, tr.Kp,
-                                   tr.width[l], sigma, cheb, (float*)ops[l], ops_lo[l]);
-            } else {
-                ERT_HIP(hipMalloc(&ops[l], n * sizeof(T)));
-                hipLaunchKernelGGL(k_ops_hom<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, nc, tr.K, tr.Kp,
-                                   tr.width[l], sigma, cheb, (T*)ops[l], (__bf16*)nullptr);
+        m2l_noff = per;
+        std::vector<BoxOffset> nr;
+        const int nn = tr.D == 3 ? 27 : 9;
+        for (int k = 0; k < nn; ++k) nr.push_back({k % 3 - 1, (k / 3) % 3 - 1, tr.D == 3 ? k / 9 - 1 : 0, k});
+        // every operator slot must exist: 7^d far matrices, 3^d near blocks
+        int nfar = 1;
+        for (int a = 0; a < tr.D; ++a) nfar *= kOffSide;
+        for (const BoxOffset& o : far)
+            if (o.op < 0 || o.op >= nfar || (tr.D < 3 && o.o2 != 0)) {
+                record_error("FMM: far-field offset table out of range");
+                return ERT_EINVAL;
             }
+        for (const BoxOffset& o : nr)
+            if (o.op < 0 || o.op >= nn || (tr.D < 3 && o.o2 != 0)) {
+                record_error("FMM: near-field offset table out of range");
+                return ERT_EINVAL;
+            }
+        ERT_TRY(upload<BoxOffset>(s, &m2l_offs, far));
+        ERT_TRY(upload<BoxOffset>(s, &near_offs, nr));
+        std::vector<BoxOffset> id{{0, 0, 0, 0}};
+        ERT_TRY(upload<BoxOffset>(s, &id_off, id));
+    }
+
+    if (!hetero) {
+        const double sigma = p->sigma_const, h = p->geo.h;
+        if (tr.S % 32 == 0) {
+            const int nn = tr.D == 3 ? 27 : 9;
+            const long n = (long)nn * tr.S * tr.S;
+            ERT_HIP(hipMalloc(&nearops, n * sizeof(T)));
+            hipLaunchKernelGGL(k_near_ops<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, leaf, tr.S, h, sigma, nearops);
             ERT_HIP(hipGetLastError());
+        } else {
+            // near-field table over K = |offset|^2 <= D (2 leaf - 1)^2
+            const int span = 2 * leaf - 1;
+            ntab = tr.D * span * span + 1;
+            std::vector<double> tb(ntab, 0.0);
+            for (int K = 1; K < ntab; ++K) {
+                double r = h * std::sqrt((double)K);
+                double rpw = (tr.D == 2) ? r : r * r;
+                tb[K] = std::exp(-sigma * r) / (surface_area(tr.D) * rpw);
+            }
+            ERT_TRY(upload_cvt<T>(s, &tab, tb));
         }
+        const double svd_tol = p->o.svd_tol == 0.0 ? 1e-7 : p->o.svd_tol;
+        compress = svd_tol >= 0.0;
+        for (int l = 2; l <= tr.L; ++l) ERT_TRY(setup_far_hom(p, l, svd_tol));
     } else {
-        // near-field cache
         const int nn = tr.D == 3 ? 27 : 9;
         const long per = (long)nn * tr.S * tr.S;
-        ERT_HIP(hipMalloc(&nearblk, (size_t)tr.nleaf * per * sizeof(T)));
+        size_t bytes = (size_t)tr.nleaf * per * sizeof(T);
+        if (hipMalloc(&nearblk, bytes) != hipSuccess) {
+            record_error("FMM: near-field cache allocation failed");
+            return ERT_ENOMEM;
+        }
         const long chunk = std::max<long>(1, (1L << 26) / per);
         for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
             long cnt = std::min(chunk, tr.nleaf - l0);
@@ -700,63 +1044,7 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
                                nearblk + (size_t)l0 * per);
             ERT_HIP(hipGetLastError());
         }
-        // per-pair translation matrices
-        for (int l = 2; l <= tr.L; ++l) {
-            std::vector<long> start(tr.nbox[l] + 1, 0), ptgt;
-            std::vector<int> src;
-            const int* nl = tr.nl[l];
-            for (long tb = 0; tb < tr.nbox[l]; ++tb) {
-                int t3[3];
-                unravel3(tb, nl, t3);
-                start[tb] = (long)src.size();
-                for (int oz = (tr.D > 2 ? -3 : 0); oz <= (tr.D > 2 ? 3 : 0); ++oz)
-                    for (int oy = -3; oy <= 3; ++oy)
-                        for (int ox = -3; ox <= 3; ++ox) {
-                            int o[3] = {ox, oy, oz}, s3[3];
-                            bool ok = true, adjacent = true;
-                            for (int a = 0; a < 3; ++a) {
-                                s3[a] = t3[a] + o[a];
-                                if (s3[a] < 0 || s3[a] >= nl[a]) ok = false;
-                                if ((t3[a] >> 1) - (s3[a] >> 1) > 1 || (s3[a] >> 1) - (t3[a] >> 1) > 1) ok = false;
-                                if (o[a] < -1 || o[a] > 1) adjacent = false;
-                            }
-                            if (!ok || adjacent) continue;
-                            src.push_back((int)(s3[0] + (long)nl[0] * (s3[1] + (long)nl[1] * s3[2])));
-                            ptgt.push_back(tb);
-                        }
-            }
-            start[tr.nbox[l]] = (long)src.size();
-            const long np = (long)src.size();
-            ERT_HIP(hipMalloc(&pstart[l], start.size() * sizeof(long)));
-            ERT_HIP(hipMalloc(&psrc[l], std::max<long>(1, np) * sizeof(int)));
-            long* ptd = nullptr;
-            ERT_HIP(hipMalloc(&ptd, std::max<long>(1, np) * sizeof(long)));
-            ERT_HIP(hipMemcpyAsync(pstart[l], start.data(), start.size() * sizeof(long), hipMemcpyHostToDevice, s));
-            ERT_HIP(hipMemcpyAsync(psrc[l], src.data(), np * sizeof(int), hipMemcpyHostToDevice, s));
-            ERT_HIP(hipMemcpyAsync(ptd, ptgt.data(), np * sizeof(long), hipMemcpyHostToDevice, s));
-            size_t bytes = (size_t)np * KpKp * sizeof(T);
-            size_t fr = 0, tot = 0;
-            if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
-                (void)hipFree(ptd);
-                record_error("FMM: heterogeneous translation cache does not fit in device memory");
-                return ERT_ENOMEM;
-            }
-            if (hipMalloc(&hops[l], std::max<size_t>(1, bytes)) != hipSuccess) {
-                (void)hipFree(ptd);
-                record_error("FMM: heterogeneous translation cache allocation failed");
-                return ERT_ENOMEM;
-            }
-            const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
-            for (long p0 = 0; p0 < np; p0 += pchunk) {
-                long cnt = std::min(pchunk, np - p0);
-                hipLaunchKernelGGL(k_ops_het<T>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, nc,
-                                   tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, psrc[l], p0, cnt,
-                                   hops[l] + (size_t)p0 * KpKp);
-                ERT_HIP(hipGetLastError());
-            }
-            ERT_HIP(hipStreamSynchronize(s));
-            (void)hipFree(ptd);
-        }
+        for (int l = 2; l <= tr.L; ++l) ERT_TRY(setup_far_het(p, l));
     }
     ERT_HIP(hipStreamSynchronize(s));
     return ensure_buffers(1);
@@ -769,7 +1057,10 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(q); f(pot);
     q = pot = nullptr;
-    for (int l = 0; l <= kMaxLevels; ++l) { f(W[l]); f(Lc[l]); W[l] = Lc[l] = nullptr; }
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
+        W[l] = Lc[l] = Wc[l] = Lh[l] = nullptr;
+    }
     B = 0;
     ERT_HIP(hipMalloc(&q, (size_t)nrhs * tr.nslot * sizeof(T)));
     ERT_HIP(hipMalloc(&pot, (size_t)nrhs * tr.nslot * sizeof(T)));
@@ -780,6 +1071,11 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
         // node padding (K..Kp) stays zero: the transfers never write it
         ERT_HIP(hipMemset(W[l], 0, n * sizeof(T)));
         ERT_HIP(hipMemset(Lc[l], 0, n * sizeof(T)));
+        if (rp[l] > 0) {
+            size_t m = (size_t)nrhs * tr.nbox[l] * rp[l];
+            ERT_HIP(hipMalloc(&Wc[l], m * sizeof(T)));
+            ERT_HIP(hipMalloc(&Lh[l], m * sizeof(T)));
+        }
     }
     B = nrhs;
     return ERT_OK;
@@ -792,30 +1088,49 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
     hipStream_t s = p->stream;
     const long N = p->N;
     const int nn = tr.D == 3 ? 27 : 9;
+    const int dprec = (prec == ERT_FP64) ? ERT_FP64 : ERT_FP32;   // precision of the dense transforms
     Profiler* pf = &p->prof;
     // a4: weights into leaf-major order
-    { StageTimer st_(pf, s, ERT_STAGE_GATHER);
-    hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, x, p->d_ss,
-                       op != ERT_OP_G ? 1 : 0, N, nrhs, q);
-    ERT_HIP(hipGetLastError()); }
-    // a10: near field (writes pot)
-    { StageTimer st_(pf, s, ERT_STAGE_NEAR);
-    if (!hetero) {
-        const int tpp = std::min(tr.S, kB);
-        const int groups = kB / tpp;
-        size_t sh = (size_t)(ntab + nn * tr.S) * sizeof(T) + 32 * sizeof(int) + (size_t)groups * tpp * sizeof(T);
-        hipLaunchKernelGGL(k_p2p_hom<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), sh, s, dt, q, tab, ntab, pot);
-    } else {
-        hipLaunchKernelGGL(k_p2p_cached<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), tr.S * sizeof(T), s, dt, q,
-                           nearblk, pot);
+    {
+        StageTimer st_(pf, s, ERT_STAGE_GATHER);
+        hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, x, p->d_ss,
+                           op != ERT_OP_G ? 1 : 0, N, nrhs, q);
+        ERT_HIP(hipGetLastError());
     }
-    ERT_HIP(hipGetLastError()); }
+    // a10: near field (writes pot)
+    {
+        StageTimer st_(pf, s, ERT_STAGE_NEAR);
+        if (hetero) {
+            hipLaunchKernelGGL(k_p2p_cached<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), tr.S * sizeof(T), s, dt, q,
+                               nearblk, pot);
+            ERT_HIP(hipGetLastError());
+        } else if (nearops) {
+            BoxGemm g = gemm_desc(tr.L, tr.S, tr.S, nrhs);
+            g.stride = 1;
+            g.nclass = 1;
+            g.noff = nn;
+            g.offs = near_offs;
+            g.ops = nearops;
+            g.W = q;
+            g.L = pot;
+            g.accumulate = 0;
+            ERT_TRY(box_gemm(s, dprec, g));
+        } else {
+            const int tpp = std::min(tr.S, kB);
+            const int groups = kB / tpp;
+            size_t sh = (size_t)(ntab + nn * tr.S) * sizeof(T) + 32 * sizeof(int) + (size_t)groups * tpp * sizeof(T);
+            hipLaunchKernelGGL(k_p2p_hom<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), sh, s, dt, q, tab, ntab, pot);
+            ERT_HIP(hipGetLastError());
+        }
+    }
     if (tr.L >= 2) {
         const int L = tr.L;
         // a5: P2M on the leaves
-        { StageTimer st_(pf, s, ERT_STAGE_P2M);
-        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, q, P1, W[L]);
-        ERT_HIP(hipGetLastError()); }
+        {
+            StageTimer st_(pf, s, ERT_STAGE_P2M);
+            hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, q, P1, W[L]);
+            ERT_HIP(hipGetLastError());
+        }
         // a6: M2M up to level 2
         for (int l = L - 1; l >= 2; --l) {
             StageTimer st_(pf, s, ERT_STAGE_M2M);
@@ -826,30 +1141,60 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
         }
         // a7/a8: downward pass
         for (int l = 2; l <= L; ++l) {
-            { StageTimer st_(pf, s, ERT_STAGE_L2L);
-            if (l == 2) {
-                long n = (long)nrhs * tr.nbox[2] * tr.Kp;
-                hipLaunchKernelGGL(k_zero_t<T>, dim3(blocks(n)), dim3(kB), 0, s, Lc[2], n);
-            } else {
-                hipLaunchKernelGGL(k_l2l<T>, dim3((unsigned)tr.nbox[l], nrhs), dim3(kB), 0, s, tr.D, tr.nc, tr.K,
-                                   tr.Kp, tr.nl[l - 1][0], tr.nl[l - 1][1], tr.nl[l - 1][2], tr.nbox[l - 1],
-                                   tr.nl[l][0], tr.nl[l][1], tr.nl[l][2], tr.nbox[l], Lc[l - 1], M1, Lc[l]);
+            {
+                StageTimer st_(pf, s, ERT_STAGE_L2L);
+                if (l == 2) {
+                    long n = (long)nrhs * tr.nbox[2] * tr.Kp;
+                    hipLaunchKernelGGL(k_zero_t<T>, dim3(blocks(n)), dim3(kB), 0, s, Lc[2], n);
+                } else {
+                    hipLaunchKernelGGL(k_l2l<T>, dim3((unsigned)tr.nbox[l], nrhs), dim3(kB), 0, s, tr.D, tr.nc, tr.K,
+                                       tr.Kp, tr.nl[l - 1][0], tr.nl[l - 1][1], tr.nl[l - 1][2], tr.nbox[l - 1],
+                                       tr.nl[l][0], tr.nl[l][1], tr.nl[l][2], tr.nbox[l], Lc[l - 1], M1, Lc[l]);
+                }
+                ERT_HIP(hipGetLastError());
             }
-            ERT_HIP(hipGetLastError()); }
-            M2LArgs a;
-            a.D = tr.D;
-            for (int d = 0; d < 3; ++d) a.nl[d] = tr.nl[l][d];
-            a.nbox = tr.nbox[l];
-            a.Kp = tr.Kp;
-            a.B = nrhs;
-            a.ops = hetero ? (const void*)hops[l] : ops[l];
-            a.ops_lo = ops_lo[l];
-            a.W = W[l];
-            a.L = Lc[l];
-            a.pair_start = pstart[l];
-            a.pair_src = psrc[l];
             StageTimer st_(pf, s, ERT_STAGE_M2L);
-            ERT_TRY(m2l_launch(s, prec, hetero, a));
+            if (hetero) {
+                PairGemm a;
+                a.nbox = tr.nbox[l];
+                a.B = nrhs;
+                a.M = a.Kd = tr.Kp;
+                a.pair_start = pstart[l];
+                a.pair_src = psrc[l];
+                a.opsT = hops[l];
+                a.W = W[l];
+                a.L = Lc[l];
+                ERT_TRY(pair_gemm(s, prec, a));
+            } else if (rp[l] > 0) {
+                const int R = rp[l];
+                st_.pause();
+                {
+                    StageTimer sb_(pf, s, ERT_STAGE_BASIS);
+                    BoxGemm c = gemm_desc(l, R, tr.Kp, nrhs);   // compress
+                    c.stride = 1; c.nclass = 1; c.noff = 1; c.offs = id_off;
+                    c.ops = Ut[l]; c.W = W[l]; c.L = Wc[l]; c.accumulate = 0;
+                    ERT_TRY(box_gemm(s, dprec, c));
+                }
+                {
+                    StageTimer sm_(pf, s, ERT_STAGE_M2L);
+                    BoxGemm g = gemm_desc(l, R, R, nrhs);       // translate
+                    g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
+                    g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
+                    ERT_TRY(box_gemm(s, prec, g));
+                }
+                {
+                    StageTimer sb_(pf, s, ERT_STAGE_BASIS);
+                    BoxGemm u = gemm_desc(l, tr.Kp, R, nrhs);   // back to the node basis, added to the locals
+                    u.stride = 1; u.nclass = 1; u.noff = 1; u.offs = id_off;
+                    u.ops = Um[l]; u.W = Lh[l]; u.L = Lc[l]; u.accumulate = 1;
+                    ERT_TRY(box_gemm(s, dprec, u));
+                }
+            } else {
+                BoxGemm g = gemm_desc(l, tr.Kp, tr.Kp, nrhs);
+                g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
+                g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = W[l]; g.L = Lc[l]; g.accumulate = 1;
+                ERT_TRY(box_gemm(s, prec, g));
+            }
         }
         // a9: L2P adds the far field
         StageTimer st_(pf, s, ERT_STAGE_L2P);
@@ -867,7 +1212,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
 
 }  // namespace
 
-ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs)
+ert_status fmm_build(ert_plan_impl* p, int prec)
 {
     if (prec < 0 || prec > 2) return ERT_EINVAL;
     if (!p->fmm[prec]) {
@@ -878,14 +1223,11 @@ ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double
             f = g;
         } else {
             auto* g = new (std::nothrow) FmmImpl<float>();
-            if (g) g->prec = prec;
+            // the heterogeneous far field streams per-pair matrices with VALU: FP32 there
+            if (g) g->prec = (prec == ERT_BF16X3 && p->o.kernel == ERT_K_RAY_MIDPOINT) ? ERT_FP32 : prec;
             f = g;
         }
         if (!f) return ERT_ENOMEM;
-        if (prec == ERT_BF16X3 && p->o.kernel == ERT_K_RAY_MIDPOINT) {
-            // the heterogeneous far field streams per-pair matrices: FP32 it is
-            static_cast<FmmImpl<float>*>(f)->prec = ERT_FP32;
-        }
         ert_status st = f->setup(p);
         if (st != ERT_OK) {
             delete f;
@@ -893,7 +1235,61 @@ ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double
         }
         p->fmm[prec] = f;
     }
+    return ERT_OK;
+}
+
+ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs)
+{
+    ERT_TRY(fmm_build(p, prec));
     return p->fmm[prec]->apply(p, op, x, y, nrhs);
+}
+
+ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info)
+{
+    ERT_TRY(fmm_build(p, prec));
+    const FmmData* f = p->fmm[prec];
+    const FmmTree& t = f->tr;
+    std::memset(info, 0, sizeof(*info));
+    info->levels = t.L;
+    info->leaf = t.leaf;
+    info->cheb_n = t.nc;
+    info->nodes = t.K;
+    info->nodes_padded = t.Kp;
+    for (int l = 0; l <= t.L && l < 16; ++l) info->rank[l] = f->rank_of(l);
+    // interaction-list pairs per level (separable per axis) and near point pairs
+    for (int l = 2; l <= t.L && l < 16; ++l) {
+        long par = 1, nr = 1;
+        for (int a = 0; a < t.D; ++a) {
+            const int n = t.nl[l][a];
+            long pa = 0, na = 0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    if (std::abs(i / 2 - j / 2) <= 1) {
+                        ++pa;
+                        if (std::abs(i - j) <= 1) ++na;
+                    }
+                }
+            par *= pa;
+            nr *= na;
+        }
+        info->far_pairs[l] = par - nr;
+    }
+    {
+        const int n[3] = {p->geo.n0, p->geo.n1, p->geo.n2};
+        long tot = 1;
+        for (int a = 0; a < t.D; ++a) {
+            // point pairs along one axis whose leaves are adjacent
+            long c = 0;
+            for (int i = 0; i < n[a]; ++i) {
+                const int bi = i / t.leaf;
+                const int lo = std::max(0, (bi - 1) * t.leaf), hi = std::min(n[a], (bi + 2) * t.leaf);
+                c += hi - lo;
+            }
+            tot *= c;
+        }
+        info->near_pairs = tot - p->N;
+    }
+    return ERT_OK;
 }
 
 void fmm_destroy(FmmData* f) { delete f; }

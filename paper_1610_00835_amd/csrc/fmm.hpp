@@ -1,6 +1,6 @@
 // Internal interface of the fast multipole method (Sec. 3.3): tree geometry
-// and the launch descriptions shared by fmm.hip (tree, transfers, near field)
-// and m2l.hip (far-field translations on MFMA).
+// and the launch descriptions shared by fmm.hip (tree, transfers, operators)
+// and m2l.hip (the box-offset GEMMs on the matrix cores).
 #pragma once
 
 #include "common.hpp"
@@ -8,44 +8,72 @@
 namespace ertvie {
 
 constexpr int kMaxLevels = 14;
-// Offsets between far boxes lie in [-3,3]^d; operators are indexed by the
-// offset's lexicographic position in that cube (x fastest), 7^d slots.
+// Offsets between far boxes lie in [-3,3]^d; far-field operators are indexed
+// by the offset's lexicographic position in that cube (x fastest), 7^d slots.
 constexpr int kOffSide = 7;
 
 // Uniform 2^d-tree over the leaf lattice: level L holds the leaf boxes
 // (leaf^d cells each), level l has ceil(nb / 2^(L-l)) boxes per axis.
 struct FmmTree {
     int D = 3;        // dimension
-    int nc = 6;       // Chebyshev nodes per axis (the paper's n)
-    int K = 216;      // nodes per box, nc^D
-    int Kp = 224;     // K padded to a multiple of 32 (zero rows/columns)
-    int leaf = 4;     // cells per leaf side
-    int S = 64;       // cells per leaf, leaf^D
+    int nc = 8;       // Chebyshev nodes per axis (the paper's n)
+    int K = 512;      // nodes per box, nc^D
+    int Kp = 512;     // K padded to a multiple of 32 (zero rows/columns)
+    int leaf = 8;     // cells per leaf side
+    int S = 512;      // cells per leaf, leaf^D
     int L = 0;        // leaf level; far field exists on levels 2..L
     int nb[3] = {1, 1, 1};
-    long nleaf = 1, nslot = 64;
+    long nleaf = 1, nslot = 512;
     int nl[kMaxLevels + 1][3] = {};
     long nbox[kMaxLevels + 1] = {};
     double width[kMaxLevels + 1] = {};
 };
 
-// One level of far-field translations L_t += sum_{s in IL(t)} M(t,s) W_s.
-struct M2LArgs {
+// One offset of a box-offset GEMM: source box = target box + (o0,o1,o2);
+// `op` selects the operator matrix.
+struct BoxOffset {
+    int o0, o1, o2, op;
+};
+
+// Box-offset GEMM on a regular box lattice:
+//   L[b][t] (+)= sum_{o in list(class(t))} ops[o.op] * W[b][t + o]
+// for every target box t and right-hand side b; sources outside the lattice
+// contribute nothing.  With stride 2 the targets are split into the 2^d
+// parity classes (each class has its own offset list, as the far-field
+// interaction lists do); with stride 1 all targets form one class.
+struct BoxGemm {
     int D;
     int nl[3];
     long nbox;
-    int Kp;
     int B;               // right-hand sides
-    const void* ops;     // homogeneous: [7^d][Kp][Kp] row-major (FP64/FP32; BF16X3: high parts, bf16)
-    const void* ops_lo;  // BF16X3: low parts
-    const void* W;       // multipoles [B][nbox][Kp]
-    void* L;             // locals [B][nbox][Kp], accumulated into
-    // heterogeneous media: one operator per (target, source) pair, CSR over targets,
-    // stored transposed [pair][Kp (source node)][Kp (target node)]
-    const long* pair_start;
-    const int* pair_src;
+    int M;               // output rows per box (multiple of 32)
+    int Kd;              // reduction length per source box (multiple of 32)
+    int stride;          // 2: parity classes, 1: one class
+    int nclass;          // 2^d or 1
+    int noff;            // offsets per class
+    const BoxOffset* offs;   // device, [nclass][noff]
+    const void* ops;     // [nops][M][Kd] row-major (FP64/FP32; BF16X3: bf16 high parts)
+    const void* ops_lo;  // BF16X3: bf16 low parts
+    const void* W;       // [B][nbox][Kd]
+    void* L;             // [B][nbox][M]
+    int accumulate;      // 1: L += result, 0: L = result
 };
 
-ert_status m2l_launch(hipStream_t s, int prec, bool hetero, const M2LArgs& a);
+ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g);
+
+// Heterogeneous far field: one cached matrix per (target, source) pair,
+// stored source-node major [pair][Kd][M], CSR over targets.
+struct PairGemm {
+    long nbox;
+    int B;
+    int M, Kd;
+    const long* pair_start;
+    const int* pair_src;
+    const void* opsT;
+    const void* W;   // [B][nbox][Kd]
+    void* L;         // [B][nbox][M], accumulated into
+};
+
+ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& g);
 
 }  // namespace ertvie

@@ -1,23 +1,26 @@
-// Far-field translations of the Chebyshev FMM (Sec. 3.3, eq. EQ: M2L):
-// f2(p_m) = sum_{m'} K(L p_m, R q_m') f1(q_m'), summed over the interaction
-// list of every target box.
+// Box-offset GEMMs on the matrix cores, and the cached-pair far field.
 //
-// Homogeneous media: the translation matrix depends only on the level and the
-// box offset, so each level is one batched GEMM on the matrix cores.  Targets
-// are grouped in the 2^d classes of their index parity: all targets of a class
-// share the same 6^d - 3^d interaction offsets, so one workgroup owns a tile
-// of (target node rows) x (target box, right-hand side) columns and runs the
-// reduction over (offset, source node).  The four waves of a workgroup split
-// the offsets and their partial sums are combined in LDS in a fixed order, so
-// results are bitwise reproducible.  Operands go straight from global memory
-// (L2-resident operators, gathered multipoles) into MFMA registers: each lane
-// loads 16 contiguous bytes along the reduction dimension, and the order in
-// which the reduction index is fed to the MFMA steps is permuted accordingly
-// (the same permutation for both operands, so the product is unchanged).
+// On a uniform grid with a homogeneous medium every interaction between two
+// boxes depends only on their offset, so the far-field translations (Sec. 3.3,
+// eq. EQ: M2L: f2(p_m) = sum_m' K(L p_m, R q_m') f1(q_m')), the near field over
+// neighbouring leaves and the change of basis of the compressed translations
+// are all one kind of batched GEMM:
+//     L[b][t] (+)= sum_{o in list(class(t))} ops[o] * W[b][t + o].
+// A workgroup owns a tile of (output rows) x (target box, right-hand side)
+// columns; targets are grouped by index parity when the far-field interaction
+// lists are used (all targets of a parity class share one offset list).  The
+// four waves of a workgroup run the same offsets and split the reduction
+// chunks of each offset; their partial sums are combined in LDS in a fixed
+// order, so results are bitwise reproducible.  Operands go straight from
+// global memory into MFMA registers: each lane loads 16-32 contiguous bytes
+// along the reduction dimension and the order in which reduction indices are
+// fed to the MFMA steps is permuted to match (the same permutation for both
+// operands, so the product is unchanged).  Output register layouts (checked on
+// gfx950): 16x16x4 f32 and 16x16x32 bf16 hold rows 4*(lane/16)+i of column
+// lane%16; 16x16x4 f64 holds rows lane/16 + 4*i.
 //
-// Heterogeneous media: every (target, source) pair has its own matrix, cached
-// at plan time; the translation is a batched GEMV/GEMM that streams those
-// matrices once per apply (HBM-bound).
+// Heterogeneous media: every (target, source) pair has its own cached matrix;
+// the translation streams those matrices once per apply (HBM-bound).
 #include "fmm.hpp"
 
 namespace ertvie {
@@ -30,259 +33,14 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kWaves = 4;
 
-struct ClassInfo {
-    int pc[3];      // parity of the class
-    int ncl[3];     // targets of the class per axis
-    long nt;        // targets in the class
-};
-
-__device__ __forceinline__ ClassInfo class_info(const M2LArgs& a, int cls)
-{
-    ClassInfo ci;
-    ci.nt = 1;
-    for (int d = 0; d < 3; ++d) {
-        ci.pc[d] = (d < a.D) ? (cls >> d) & 1 : 0;
-        int n = (d < a.D) ? a.nl[d] : 1;
-        int c = (n - ci.pc[d] + 1) / 2;
-        ci.ncl[d] = c < 0 ? 0 : c;
-        ci.nt *= ci.ncl[d];
-    }
-    return ci;
-}
-
-// number of per-axis offset choices for one class (children of the parent's
-// neighbours): o in [-2 - p, 3 - p]
-constexpr int kSpan = 6;
-
-template <int TN>
-struct Cols {
-    int t[TN][3];
-    long tlin[TN];
-    int b[TN];
-    bool ok[TN];
-};
-
-template <int TN>
-__device__ __forceinline__ void column_setup(const M2LArgs& a, const ClassInfo& ci, long col0, int lane, Cols<TN>& c)
-{
-#pragma unroll
-    for (int tn = 0; tn < TN; ++tn) {
-        long col = col0 + 16 * tn + (lane & 15);
-        c.ok[tn] = col < ci.nt * a.B;
-        long cc = c.ok[tn] ? col : 0;
-        c.b[tn] = (int)(cc / (ci.nt > 0 ? ci.nt : 1));
-        long tp = cc - (long)c.b[tn] * ci.nt;
-        int t0 = (int)(tp % (ci.ncl[0] > 0 ? ci.ncl[0] : 1));
-        long r = tp / (ci.ncl[0] > 0 ? ci.ncl[0] : 1);
-        int t1 = (int)(r % (ci.ncl[1] > 0 ? ci.ncl[1] : 1));
-        int t2 = (int)(r / (ci.ncl[1] > 0 ? ci.ncl[1] : 1));
-        c.t[tn][0] = 2 * t0 + ci.pc[0];
-        c.t[tn][1] = 2 * t1 + ci.pc[1];
-        c.t[tn][2] = 2 * t2 + ci.pc[2];
-        c.tlin[tn] = c.t[tn][0] + (long)a.nl[0] * (c.t[tn][1] + (long)a.nl[1] * c.t[tn][2]);
-    }
-}
-
-// source box of column tn under offset o; -1 when outside the lattice
-template <int TN>
-__device__ __forceinline__ long source_box(const M2LArgs& a, const Cols<TN>& c, int tn, const int o[3])
-{
-    if (!c.ok[tn]) return -1;
-    long lin = 0, stride = 1;
-    for (int d = 0; d < 3; ++d) {
-        int n = (d < a.D) ? a.nl[d] : 1;
-        int s = c.t[tn][d] + o[d];
-        if (s < 0 || s >= n) return -1;
-        lin += stride * s;
-        stride *= n;
-    }
-    return lin;
-}
-
-__device__ __forceinline__ bool decode_offset(const M2LArgs& a, const ClassInfo& ci, int idx, int o[3], int* oidx)
-{
-    int near = 1;
-    int lin = 0, stride = 1;
-    int rem = idx;
-    for (int d = 0; d < 3; ++d) {
-        if (d < a.D) {
-            int k = rem % kSpan;
-            rem /= kSpan;
-            o[d] = k - 2 - ci.pc[d];
-            if (o[d] < -1 || o[d] > 1) near = 0;
-            lin += stride * (o[d] + 3);
-            stride *= kOffSide;
-        } else {
-            o[d] = 0;
-        }
-    }
-    *oidx = lin;
-    return !near;
-}
-
-// ------------------------------------------------------------------ FP32 ----
-
-template <int TM, int TN>
-__global__ __launch_bounds__(64 * kWaves) void k_m2l_f32(M2LArgs a, int row_tiles)
-{
-    __shared__ v4f red[(kWaves - 1) * TM * TN * 64];
-    const int cls = blockIdx.y;
-    const ClassInfo ci = class_info(a, cls);
-    const int rt = blockIdx.x % row_tiles;
-    const long ct = blockIdx.x / row_tiles;
-    const long col0 = ct * 16 * TN;
-    if (col0 >= ci.nt * a.B) return;                  // uniform over the block
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4;
-    const int row0 = rt * 16 * TM;
-    Cols<TN> cols;
-    column_setup<TN>(a, ci, col0, lane, cols);
-    const float* ops = (const float*)a.ops;
-    const float* W = (const float*)a.W;
-    v4f acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-
-    int total = 1;
-    for (int d = 0; d < a.D; ++d) total *= kSpan;
-    for (int idx = wave; idx < total; idx += kWaves) {
-        int o[3], oidx;
-        if (!decode_offset(a, ci, idx, o, &oidx)) continue;
-        const float* bp[TN];
-        bool any = false;
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-            long s = source_box<TN>(a, cols, tn, o);
-            bp[tn] = s >= 0 ? W + ((long)cols.b[tn] * a.nbox + s) * a.Kp + 4 * g : nullptr;
-            any |= (s >= 0);
-        }
-        if (!__any(any)) continue;
-        const float* ap[TM];
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-            ap[tm] = ops + ((long)oidx * a.Kp + row0 + 16 * tm + (lane & 15)) * a.Kp + 4 * g;
-        for (int kk = 0; kk < a.Kp; kk += 16) {
-            v4f av[TM], bv[TN];
-#pragma unroll
-            for (int tm = 0; tm < TM; ++tm) av[tm] = *(const v4f*)(ap[tm] + kk);
-#pragma unroll
-            for (int tn = 0; tn < TN; ++tn) bv[tn] = bp[tn] ? *(const v4f*)(bp[tn] + kk) : v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-                    for (int tn = 0; tn < TN; ++tn)
-                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
-        }
-    }
-    if (wave > 0) {
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-            for (int tn = 0; tn < TN; ++tn) red[(((wave - 1) * TM + tm) * TN + tn) * 64 + lane] = acc[tm][tn];
-    }
-    __syncthreads();
-    if (wave != 0) return;
-    float* Lo = (float*)a.L;
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-            v4f s = acc[tm][tn];
-            for (int w = 1; w < kWaves; ++w) s += red[(((w - 1) * TM + tm) * TN + tn) * 64 + lane];
-            if (!cols.ok[tn]) continue;
-            // output layout: lane holds rows 4*(lane/16) + i of column lane % 16
-            float* dst = Lo + ((long)cols.b[tn] * a.nbox + cols.tlin[tn]) * a.Kp + row0 + 16 * tm + 4 * g;
-            v4f cur = *(v4f*)dst;
-            *(v4f*)dst = cur + s;
-        }
-}
-
-// ------------------------------------------------------------------ FP64 ----
-
-template <int TM, int TN>
-__global__ __launch_bounds__(64 * kWaves) void k_m2l_f64(M2LArgs a, int row_tiles)
-{
-    __shared__ v4d red[(kWaves - 1) * TM * TN * 64];
-    const int cls = blockIdx.y;
-    const ClassInfo ci = class_info(a, cls);
-    const int rt = blockIdx.x % row_tiles;
-    const long ct = blockIdx.x / row_tiles;
-    const long col0 = ct * 16 * TN;
-    if (col0 >= ci.nt * a.B) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4;
-    const int row0 = rt * 16 * TM;
-    Cols<TN> cols;
-    column_setup<TN>(a, ci, col0, lane, cols);
-    const double* ops = (const double*)a.ops;
-    const double* W = (const double*)a.W;
-    v4d acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-
-    int total = 1;
-    for (int d = 0; d < a.D; ++d) total *= kSpan;
-    for (int idx = wave; idx < total; idx += kWaves) {
-        int o[3], oidx;
-        if (!decode_offset(a, ci, idx, o, &oidx)) continue;
-        const double* bp[TN];
-        bool any = false;
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-            long s = source_box<TN>(a, cols, tn, o);
-            bp[tn] = s >= 0 ? W + ((long)cols.b[tn] * a.nbox + s) * a.Kp + 4 * g : nullptr;
-            any |= (s >= 0);
-        }
-        if (!__any(any)) continue;
-        const double* ap[TM];
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-            ap[tm] = ops + ((long)oidx * a.Kp + row0 + 16 * tm + (lane & 15)) * a.Kp + 4 * g;
-        for (int kk = 0; kk < a.Kp; kk += 16) {
-            v4d av[TM], bv[TN];
-#pragma unroll
-            for (int tm = 0; tm < TM; ++tm) av[tm] = *(const v4d*)(ap[tm] + kk);
-#pragma unroll
-            for (int tn = 0; tn < TN; ++tn) bv[tn] = bp[tn] ? *(const v4d*)(bp[tn] + kk) : v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-                    for (int tn = 0; tn < TN; ++tn)
-                        acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
-        }
-    }
-    if (wave > 0) {
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-            for (int tn = 0; tn < TN; ++tn) red[(((wave - 1) * TM + tm) * TN + tn) * 64 + lane] = acc[tm][tn];
-    }
-    __syncthreads();
-    if (wave != 0) return;
-    double* Lo = (double*)a.L;
-#pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-            v4d s = acc[tm][tn];
-            for (int w = 1; w < kWaves; ++w) s += red[(((w - 1) * TM + tm) * TN + tn) * 64 + lane];
-            if (!cols.ok[tn]) continue;
-            // FP64 output layout: lane holds rows (lane/16) + 4*i of column lane % 16
-            double* dst = Lo + ((long)cols.b[tn] * a.nbox + cols.tlin[tn]) * a.Kp + row0 + 16 * tm + g;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) dst[4 * i] += s[i];
-        }
-}
-
-// --------------------------------------------------------------- BF16x3 ----
-// A = A_hi + A_lo (bf16 pair, split at plan time), B split the same way on the
-// fly; A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi accumulated in FP32.
+template <int PREC>
+struct Acc;
+template <>
+struct Acc<ERT_FP64> { typedef v4d V; typedef double T; };
+template <>
+struct Acc<ERT_FP32> { typedef v4f V; typedef float T; };
+template <>
+struct Acc<ERT_BF16X3> { typedef v4f V; typedef float T; };
 
 __device__ __forceinline__ void split_bf16(const v4f& x0, const v4f& x1, v8bf& hi, v8bf& lo)
 {
@@ -297,113 +55,184 @@ __device__ __forceinline__ void split_bf16(const v4f& x0, const v4f& x1, v8bf& h
     }
 }
 
-template <int TM, int TN>
-__global__ __launch_bounds__(64 * kWaves) void k_m2l_bf16x3(M2LArgs a, int row_tiles)
+template <int PREC, int TM, int TN>
+__global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_tiles)
 {
-    __shared__ v4f red[(kWaves - 1) * TM * TN * 64];
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    __shared__ V red[(kWaves - 1) * TM * TN * 64];
     const int cls = blockIdx.y;
-    const ClassInfo ci = class_info(a, cls);
+    int pc[3], ncl[3];
+    long nt = 1;
+    for (int d = 0; d < 3; ++d) {
+        pc[d] = (g.stride == 2 && d < g.D) ? (cls >> d) & 1 : 0;
+        int n = (d < g.D) ? g.nl[d] : 1;
+        int c = (n - pc[d] + g.stride - 1) / g.stride;
+        ncl[d] = c < 0 ? 0 : c;
+        nt *= ncl[d];
+    }
     const int rt = blockIdx.x % row_tiles;
-    const long ct = blockIdx.x / row_tiles;
-    const long col0 = ct * 16 * TN;
-    if (col0 >= ci.nt * a.B) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4;
+    const long col0 = (long)(blockIdx.x / row_tiles) * 16 * TN;
+    if (col0 >= nt * g.B) return;                      // uniform over the block
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4;
     const int row0 = rt * 16 * TM;
-    Cols<TN> cols;
-    column_setup<TN>(a, ci, col0, lane, cols);
-    const __bf16* ohi = (const __bf16*)a.ops;
-    const __bf16* olo = (const __bf16*)a.ops_lo;
-    const float* W = (const float*)a.W;
-    v4f acc[TM][TN];
+    constexpr int CW = (PREC == ERT_BF16X3) ? 32 : 16;  // reduction chunk per MFMA group
+    constexpr int LG = (PREC == ERT_BF16X3) ? 8 : 4;    // elements per lane per chunk
+
+    // columns of this lane
+    int tc[TN][3];
+    long tlin[TN];
+    int tb[TN];
+    bool ok[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+        long col = col0 + 16 * tn + (lane & 15);
+        ok[tn] = col < nt * g.B;
+        long cc = ok[tn] ? col : 0;
+        tb[tn] = (int)(cc / nt);
+        long tp = cc - (long)tb[tn] * nt;
+        int a0 = (int)(tp % ncl[0]);
+        long r = tp / ncl[0];
+        int a1 = (int)(r % ncl[1]);
+        int a2 = (int)(r / ncl[1]);
+        tc[tn][0] = g.stride * a0 + pc[0];
+        tc[tn][1] = g.stride * a1 + pc[1];
+        tc[tn][2] = g.stride * a2 + pc[2];
+        tlin[tn] = tc[tn][0] + (long)g.nl[0] * (tc[tn][1] + (long)g.nl[1] * tc[tn][2]);
+    }
+
+    // tot: sum over offsets of the per-offset partial sums in acc (shorter
+    // FP32 accumulation chains than one running sum)
+    V acc[TM][TN], tot[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j) tot[i][j] = V{0, 0, 0, 0};
 
-    int total = 1;
-    for (int d = 0; d < a.D; ++d) total *= kSpan;
-    for (int idx = wave; idx < total; idx += kWaves) {
-        int o[3], oidx;
-        if (!decode_offset(a, ci, idx, o, &oidx)) continue;
-        const float* bp[TN];
+    const BoxOffset* offs = g.offs + (long)cls * g.noff;
+    for (int oi = 0; oi < g.noff; ++oi) {
+        const BoxOffset o = offs[oi];
+        const T* bp[TN];
         bool any = false;
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) {
-            long s = source_box<TN>(a, cols, tn, o);
-            bp[tn] = s >= 0 ? W + ((long)cols.b[tn] * a.nbox + s) * a.Kp + 8 * g : nullptr;
-            any |= (s >= 0);
+            const int s0 = tc[tn][0] + o.o0, s1 = tc[tn][1] + o.o1, s2 = tc[tn][2] + o.o2;
+            const bool in = ok[tn] && s0 >= 0 && s0 < g.nl[0] && s1 >= 0 && s1 < g.nl[1] && s2 >= 0 &&
+                            s2 < g.nl[2];
+            const long sl = s0 + (long)g.nl[0] * (s1 + (long)g.nl[1] * s2);
+            bp[tn] = in ? (const T*)g.W + ((long)tb[tn] * g.nbox + sl) * g.Kd + LG * grp : nullptr;
+            any |= in;
         }
         if (!__any(any)) continue;
-        long arow[TM];
 #pragma unroll
-        for (int tm = 0; tm < TM; ++tm)
-            arow[tm] = ((long)oidx * a.Kp + row0 + 16 * tm + (lane & 15)) * a.Kp + 8 * g;
-        for (int kk = 0; kk < a.Kp; kk += 32) {
-            v8bf ah[TM], al[TM], bh[TN], bl[TN];
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int tm = 0; tm < TM; ++tm) {
-                ah[tm] = *(const v8bf*)(ohi + arow[tm] + kk);
-                al[tm] = *(const v8bf*)(olo + arow[tm] + kk);
-            }
+            for (int j = 0; j < TN; ++j) acc[i][j] = V{0, 0, 0, 0};
+        const long abase = ((long)o.op * g.M + row0 + (lane & 15)) * g.Kd + LG * grp;
+        for (int kk = wave * CW; kk < g.Kd; kk += kWaves * CW) {
+            if constexpr (PREC == ERT_BF16X3) {
+                const __bf16* ohi = (const __bf16*)g.ops;
+                const __bf16* olo = (const __bf16*)g.ops_lo;
+                v8bf ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-            for (int tn = 0; tn < TN; ++tn) {
-                v4f x0 = v4f{0.f, 0.f, 0.f, 0.f}, x1 = x0;
-                if (bp[tn]) {
-                    x0 = *(const v4f*)(bp[tn] + kk);
-                    x1 = *(const v4f*)(bp[tn] + kk + 4);
+                for (int tm = 0; tm < TM; ++tm) {
+                    const long a = abase + (long)16 * tm * g.Kd + kk;
+                    ah[tm] = *(const v8bf*)(ohi + a);
+                    al[tm] = *(const v8bf*)(olo + a);
                 }
-                split_bf16(x0, x1, bh[tn], bl[tn]);
-            }
-#pragma unroll
-            for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
                 for (int tn = 0; tn < TN; ++tn) {
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+                    v4f x0 = v4f{0.f, 0.f, 0.f, 0.f}, x1 = x0;
+                    if (bp[tn]) {
+                        x0 = *(const v4f*)(bp[tn] + kk);
+                        x1 = *(const v4f*)(bp[tn] + kk + 4);
+                    }
+                    split_bf16(x0, x1, bh[tn], bl[tn]);
                 }
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn) {
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+                    }
+            } else {
+                const T* A = (const T*)g.ops;
+                V av[TM], bv[TN];
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm) av[tm] = *(const V*)(A + abase + (long)16 * tm * g.Kd + kk);
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn) bv[tn] = bp[tn] ? *(const V*)(bp[tn] + kk) : V{0, 0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                        for (int tn = 0; tn < TN; ++tn) {
+                            if constexpr (PREC == ERT_FP64)
+                                acc[tm][tn] =
+                                    __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
+                            else
+                                acc[tm][tn] =
+                                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
+                        }
+            }
         }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) tot[i][j] += acc[i][j];
     }
     if (wave > 0) {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-            for (int tn = 0; tn < TN; ++tn) red[(((wave - 1) * TM + tm) * TN + tn) * 64 + lane] = acc[tm][tn];
+            for (int tn = 0; tn < TN; ++tn) red[(((wave - 1) * TM + tm) * TN + tn) * 64 + lane] = tot[tm][tn];
     }
     __syncthreads();
     if (wave != 0) return;
-    float* Lo = (float*)a.L;
+    T* Lo = (T*)g.L;
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) {
-            v4f s = acc[tm][tn];
+            V s = tot[tm][tn];
             for (int w = 1; w < kWaves; ++w) s += red[(((w - 1) * TM + tm) * TN + tn) * 64 + lane];
-            if (!cols.ok[tn]) continue;
-            float* dst = Lo + ((long)cols.b[tn] * a.nbox + cols.tlin[tn]) * a.Kp + row0 + 16 * tm + 4 * g;
-            v4f cur = *(v4f*)dst;
-            *(v4f*)dst = cur + s;
+            if (!ok[tn]) continue;
+            T* col = Lo + ((long)tb[tn] * g.nbox + tlin[tn]) * g.M + row0 + 16 * tm;
+            if constexpr (PREC == ERT_FP64) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    T* d = col + grp + 4 * i;
+                    *d = g.accumulate ? *d + s[i] : s[i];
+                }
+            } else {
+                V* d = (V*)(col + 4 * grp);
+                *d = g.accumulate ? *d + s : s;
+            }
         }
 }
 
 // ------------------------------------------------- heterogeneous (cached) ----
 // One workgroup per (target box, block of right-hand sides).  Thread r owns
-// target node r; for each source of the target's list the source multipoles of
-// the RHS block are staged in LDS and the cached matrix (stored source-node
-// major, so consecutive threads read consecutive rows) is streamed once.
+// output row r; for each source in the target's list the source vectors of the
+// RHS block are staged in LDS and the cached matrix (stored source-node major,
+// so consecutive threads read consecutive rows) is streamed once.
 
 template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_m2l_het(M2LArgs a, const T* __restrict__ opsT)
+__global__ __launch_bounds__(256) void k_pair_gemm(PairGemm a)
 {
     extern __shared__ unsigned char smem[];
-    T* ws = (T*)smem;                      // [RB][Kp]
+    T* ws = (T*)smem;                      // [RB][Kd]
     const long t = blockIdx.x;
     const int b0 = blockIdx.y * RB;
     const int nb = (a.B - b0) < RB ? (a.B - b0) : RB;
     const T* W = (const T*)a.W;
+    const T* opsT = (const T*)a.opsT;
     T* Lo = (T*)a.L;
     const long p0 = a.pair_start[t], p1 = a.pair_start[t + 1];
-    for (int r0 = 0; r0 < a.Kp; r0 += 256) {
+    for (int r0 = 0; r0 < a.M; r0 += 256) {
         const int r = r0 + threadIdx.x;
         T acc[RB];
 #pragma unroll
@@ -411,24 +240,24 @@ __global__ __launch_bounds__(256) void k_m2l_het(M2LArgs a, const T* __restrict_
         for (long p = p0; p < p1; ++p) {
             const long s = a.pair_src[p];
             __syncthreads();
-            for (int i = threadIdx.x; i < RB * a.Kp; i += 256) {
-                int b = i / a.Kp, k = i - b * a.Kp;
-                ws[i] = (b < nb) ? W[((long)(b0 + b) * a.nbox + s) * a.Kp + k] : T(0);
+            for (int i = threadIdx.x; i < RB * a.Kd; i += 256) {
+                int b = i / a.Kd, k = i - b * a.Kd;
+                ws[i] = (b < nb) ? W[((long)(b0 + b) * a.nbox + s) * a.Kd + k] : T(0);
             }
             __syncthreads();
-            if (r < a.Kp) {
-                const T* col = opsT + (size_t)p * a.Kp * a.Kp + r;
-                for (int k = 0; k < a.Kp; ++k) {
-                    const T m = col[(size_t)k * a.Kp];
+            if (r < a.M) {
+                const T* col = opsT + (size_t)p * a.M * a.Kd + r;
+                for (int k = 0; k < a.Kd; ++k) {
+                    const T m = col[(size_t)k * a.M];
 #pragma unroll
-                    for (int b = 0; b < RB; ++b) acc[b] += m * ws[b * a.Kp + k];
+                    for (int b = 0; b < RB; ++b) acc[b] += m * ws[b * a.Kd + k];
                 }
             }
         }
-        if (r < a.Kp) {
+        if (r < a.M) {
 #pragma unroll
             for (int b = 0; b < RB; ++b)
-                if (b < nb) Lo[((long)(b0 + b) * a.nbox + t) * a.Kp + r] += acc[b];
+                if (b < nb) Lo[((long)(b0 + b) * a.nbox + t) * a.M + r] += acc[b];
         }
     }
 }
@@ -437,46 +266,51 @@ constexpr int kTM = 2, kTN = 2;
 
 }  // namespace
 
-ert_status m2l_launch(hipStream_t s, int prec, bool hetero, const M2LArgs& a)
+ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g)
 {
-    if (hetero) {
-        const int rb = a.B >= 8 ? 8 : (a.B >= 4 ? 4 : 1);
-        dim3 grid((unsigned)a.nbox, (unsigned)((a.B + rb - 1) / rb));
-        if (prec == ERT_FP64) {
-            size_t sh = (size_t)rb * a.Kp * sizeof(double);
-            if (rb == 8) hipLaunchKernelGGL((k_m2l_het<double, 8>), grid, dim3(256), sh, s, a, (const double*)a.ops);
-            else if (rb == 4) hipLaunchKernelGGL((k_m2l_het<double, 4>), grid, dim3(256), sh, s, a, (const double*)a.ops);
-            else hipLaunchKernelGGL((k_m2l_het<double, 1>), grid, dim3(256), sh, s, a, (const double*)a.ops);
-        } else {
-            size_t sh = (size_t)rb * a.Kp * sizeof(float);
-            if (rb == 8) hipLaunchKernelGGL((k_m2l_het<float, 8>), grid, dim3(256), sh, s, a, (const float*)a.ops);
-            else if (rb == 4) hipLaunchKernelGGL((k_m2l_het<float, 4>), grid, dim3(256), sh, s, a, (const float*)a.ops);
-            else hipLaunchKernelGGL((k_m2l_het<float, 1>), grid, dim3(256), sh, s, a, (const float*)a.ops);
-        }
-        ERT_HIP(hipGetLastError());
-        return ERT_OK;
+    if (g.M % (16 * kTM) != 0 || g.Kd % 32 != 0) {
+        record_error("box_gemm: row count must be a multiple of 32 and the reduction length of 32");
+        return ERT_EINVAL;
     }
-    const int classes = 1 << a.D;
-    const int row_tiles = a.Kp / (16 * kTM);
+    const int row_tiles = g.M / (16 * kTM);
     long max_nt = 0;
-    for (int c = 0; c < classes; ++c) {
+    for (int c = 0; c < g.nclass; ++c) {
         long nt = 1;
-        for (int d = 0; d < a.D; ++d) {
-            int pc = (c >> d) & 1;
-            int n = (a.nl[d] - pc + 1) / 2;
+        for (int d = 0; d < g.D; ++d) {
+            int pc = (g.stride == 2) ? (c >> d) & 1 : 0;
+            int n = (g.nl[d] - pc + g.stride - 1) / g.stride;
             nt *= n > 0 ? n : 0;
         }
         max_nt = nt > max_nt ? nt : max_nt;
     }
-    const long col_tiles = (max_nt * a.B + 16 * kTN - 1) / (16 * kTN);
+    const long col_tiles = (max_nt * g.B + 16 * kTN - 1) / (16 * kTN);
     if (col_tiles == 0) return ERT_OK;
-    dim3 grid((unsigned)(row_tiles * col_tiles), (unsigned)classes);
+    dim3 grid((unsigned)(row_tiles * col_tiles), (unsigned)g.nclass);
     if (prec == ERT_FP64)
-        hipLaunchKernelGGL((k_m2l_f64<kTM, kTN>), grid, dim3(64 * kWaves), 0, s, a, row_tiles);
+        hipLaunchKernelGGL((k_box_gemm<ERT_FP64, kTM, kTN>), grid, dim3(64 * kWaves), 0, s, g, row_tiles);
     else if (prec == ERT_FP32)
-        hipLaunchKernelGGL((k_m2l_f32<kTM, kTN>), grid, dim3(64 * kWaves), 0, s, a, row_tiles);
+        hipLaunchKernelGGL((k_box_gemm<ERT_FP32, kTM, kTN>), grid, dim3(64 * kWaves), 0, s, g, row_tiles);
     else
-        hipLaunchKernelGGL((k_m2l_bf16x3<kTM, kTN>), grid, dim3(64 * kWaves), 0, s, a, row_tiles);
+        hipLaunchKernelGGL((k_box_gemm<ERT_BF16X3, kTM, kTN>), grid, dim3(64 * kWaves), 0, s, g, row_tiles);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& a)
+{
+    const int rb = a.B >= 8 ? 8 : (a.B >= 4 ? 4 : 1);
+    dim3 grid((unsigned)a.nbox, (unsigned)((a.B + rb - 1) / rb));
+    if (prec == ERT_FP64) {
+        size_t sh = (size_t)rb * a.Kd * sizeof(double);
+        if (rb == 8) hipLaunchKernelGGL((k_pair_gemm<double, 8>), grid, dim3(256), sh, s, a);
+        else if (rb == 4) hipLaunchKernelGGL((k_pair_gemm<double, 4>), grid, dim3(256), sh, s, a);
+        else hipLaunchKernelGGL((k_pair_gemm<double, 1>), grid, dim3(256), sh, s, a);
+    } else {
+        size_t sh = (size_t)rb * a.Kd * sizeof(float);
+        if (rb == 8) hipLaunchKernelGGL((k_pair_gemm<float, 8>), grid, dim3(256), sh, s, a);
+        else if (rb == 4) hipLaunchKernelGGL((k_pair_gemm<float, 4>), grid, dim3(256), sh, s, a);
+        else hipLaunchKernelGGL((k_pair_gemm<float, 1>), grid, dim3(256), sh, s, a);
+    }
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }

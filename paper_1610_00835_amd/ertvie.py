@@ -20,7 +20,7 @@ DIRECT, FMM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
 OP_G, OP_GS, OP_A = 0, 1, 2
 
-STAGES = ("gather", "near", "p2m", "m2m", "m2l", "l2l", "l2p", "assemble", "direct")
+STAGES = ("gather", "near", "p2m", "m2m", "m2l", "l2l", "l2p", "assemble", "direct", "basis")
 NSTAGES = len(STAGES)
 
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
@@ -31,7 +31,7 @@ class VieOpts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
                 ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
                 ("cheb_n", ctypes.c_int), ("leaf", ctypes.c_int), ("nrhs_max", ctypes.c_int),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("svd_tol", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -44,6 +44,12 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("rel_resid_est", ctypes.c_double),
                 ("rel_resid_true", ctypes.c_double), ("t_solve", ctypes.c_double)]
+
+
+class FmmInfo(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("leaf", ctypes.c_int), ("cheb_n", ctypes.c_int),
+                ("nodes", ctypes.c_int), ("nodes_padded", ctypes.c_int), ("rank", ctypes.c_int * 16),
+                ("far_pairs", ctypes.c_long * 16), ("near_pairs", ctypes.c_long)]
 
 
 class ErtError(RuntimeError):
@@ -87,6 +93,8 @@ def load():
     L.ert_vie_destroy.argtypes = [_vp]
     L.ert_vie_profile.restype = ctypes.c_int
     L.ert_vie_profile.argtypes = [_vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]
+    L.ert_vie_fmm_info.restype = ctypes.c_int
+    L.ert_vie_fmm_info.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(FmmInfo)]
     L.ert_vie_last_error.restype = ctypes.c_char_p
     L.ert_vie_last_error.argtypes = []
     L.ert_vie_strerror.restype = ctypes.c_char_p
@@ -134,7 +142,7 @@ class Plan:
     """
 
     def __init__(self, dim, n, h, sigma_t, sigma_s, kernel=K_HOMOGENEOUS, method="direct", prec="fp64",
-                 cheb_n=0, leaf=0, nrhs_max=1, stream=None):
+                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0):
         L = load()
         n = list(n)[:dim]
         self.dim = int(dim)
@@ -152,6 +160,7 @@ class Plan:
         o.leaf = int(leaf)
         o.nrhs_max = int(nrhs_max)
         o.flags = 0
+        o.svd_tol = float(svd_tol)
         self.opts = o
         st_h = _f64_host(sigma_t, self.N)
         ss_h = _f64_host(sigma_s, self.N)
@@ -214,6 +223,15 @@ class Plan:
         _check(load().ert_vie_profile(self.handle, int(bool(enable)), ms, ln), "ert_vie_profile")
         return {STAGES[i]: (ms[i], ln[i]) for i in range(NSTAGES)}
 
+    def fmm_info(self, prec=None):
+        p = self.opts.prec if prec is None else (_PREC[prec] if isinstance(prec, str) else prec)
+        inf = FmmInfo()
+        _check(load().ert_vie_fmm_info(self.handle, int(p), ctypes.byref(inf)), "ert_vie_fmm_info")
+        L = inf.levels
+        return {"levels": L, "leaf": inf.leaf, "cheb_n": inf.cheb_n, "nodes": inf.nodes,
+                "nodes_padded": inf.nodes_padded, "rank": [inf.rank[l] for l in range(L + 1)],
+                "far_pairs": [inf.far_pairs[l] for l in range(L + 1)], "near_pairs": inf.near_pairs}
+
     def diag(self):
         d = np.empty(self.N)
         _check(load().ert_vie_diag(self.handle, d.ctypes.data_as(_dp)), "ert_vie_diag")
@@ -240,6 +258,7 @@ class Plan:
             pass
 
 
-def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None):
+def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0):
     return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
-                method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream)
+                method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream,
+                svd_tol=svd_tol)

@@ -22,48 +22,52 @@ def ev():
     return ertvie
 
 
-def test_no_far_field_equals_dense(ev, oracle_mod):
-    """8^3 cells with 4^3-cell leaves: every leaf is a neighbour, so the FMM is the dense sum."""
-    case = inputs.make_case("c2", n=(8, 8, 8), seed=1)
+@pytest.mark.parametrize("n,leaf", [((8, 8, 8), 4), ((16, 16, 16), 8), ((10, 7, 12), 8)])
+def test_no_far_field_equals_dense(ev, oracle_mod, n, leaf):
+    """Every leaf is a neighbour of every other: the FMM is the dense sum (near-field GEMM)."""
+    case = inputs.make_case("c2", n=n, seed=1)
     P = oracle_problem(oracle_mod, case)
     x = inputs.random_vector(P.N, 2)
-    with ev.plan_from_case(case, method="fmm", prec="fp64") as plan:
-        yf = gpu_apply(plan, x, ev.OP_A)
-    err = rel_l2(yf, P.apply(x, op=2))
-    log("no far field: rel L2", err)
-    assert err <= 1e-13
+    yo = P.apply(x, op=2)
+    for prec, bar in (("fp64", 1e-13), ("fp32", 1e-6)):
+        with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf) as plan:
+            err = rel_l2(gpu_apply(plan, x, ev.OP_A), yo)
+        log("no far field", n, leaf, prec, "rel L2", err)
+        assert err <= bar
 
 
-@pytest.mark.parametrize("prec,bar", [("fp64", 1e-6), ("fp32", 1e-6)])
-def test_fmm_homogeneous_16cubed(ev, oracle_mod, prec, bar):
+@pytest.mark.parametrize("prec,svd_tol", [("fp64", -1.0), ("fp64", 0.0), ("fp32", -1.0), ("fp32", 0.0)])
+def test_fmm_homogeneous_16cubed(ev, oracle_mod, prec, svd_tol):
+    """16^3 with 4^3-cell leaves (far field on level 2), translations plain and compressed."""
+    bar = 1e-6
     case = inputs.make_case("c2", n=(16, 16, 16), seed=0)
     P = oracle_problem(oracle_mod, case)
     x = inputs.random_vector(P.N, 3)
-    with ev.plan_from_case(case, method="fmm", prec=prec) as plan:
+    with ev.plan_from_case(case, method="fmm", prec=prec, leaf=4, svd_tol=svd_tol) as plan:
         for op in (ev.OP_G, ev.OP_A):
             err = rel_l2(gpu_apply(plan, x, op), P.apply(x, op=op))
-            log("16^3 fmm", prec, "op", op, "rel L2", err)
+            log("16^3 fmm", prec, "svd_tol", svd_tol, "op", op, "rel L2", err)
             assert err <= bar
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_fmm_c2_full_size_rows(ev, oracle_mod, prec):
-    """32^3, sigma_t = 5, sigma_s = 4, leaf 4^3, n = 8: sampled rows vs the oracle."""
+@pytest.mark.parametrize("prec,leaf", [("fp64", 8), ("fp32", 8), ("fp32", 4), ("bf16x3", 8)])
+def test_fmm_c2_full_size_rows(ev, oracle_mod, prec, leaf):
+    """32^3, sigma_t = 5, sigma_s = 4, n = 8: sampled rows vs the oracle, all rows vs the dense GPU sum."""
     case = inputs.make_case("c2", seed=0)
     P = oracle_problem(oracle_mod, case)
     x = case["f"]
     rows = np.random.default_rng(1).choice(P.N, size=800, replace=False)
-    with ev.plan_from_case(case, method="fmm", prec=prec) as plan:
+    with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf) as plan:
         for op in (ev.OP_G, ev.OP_A):
             yg = gpu_apply(plan, x, op)
             err = rel_l2(yg[rows], P.apply_rows(x, rows, op=op))
-            log("c2 fmm", prec, "op", op, "rows rel L2", err)
+            log("c2 fmm", prec, "leaf", leaf, "op", op, "rows rel L2", err)
             assert err <= 1e-6
         # and the whole vector against the (oracle-pinned) FP64 dense apply on the GPU
         yd = gpu_apply(plan, x, ev.OP_A, method="direct", prec="fp64")
         yf = gpu_apply(plan, x, ev.OP_A)
         err = rel_l2(yf, yd)
-        log("c2 fmm", prec, "vs dense, all rows", err)
+        log("c2 fmm", prec, "leaf", leaf, "vs dense, all rows", err)
         assert err <= 1e-6
 
 
@@ -75,7 +79,7 @@ def test_fmm_error_decreases_with_order(ev, oracle_mod):
     ref = P.apply(x, op=1)
     errs = []
     for n in (3, 4, 6, 8):
-        with ev.plan_from_case(case, method="fmm", prec="fp64", cheb_n=n) as plan:
+        with ev.plan_from_case(case, method="fmm", prec="fp64", cheb_n=n, leaf=4, svd_tol=-1) as plan:
             errs.append(rel_l2(gpu_apply(plan, x, ev.OP_GS), ref))
     log("error vs n (3,4,6,8):", errs)
     assert errs[0] > errs[1] > errs[2] > errs[3]
@@ -93,12 +97,12 @@ def test_fmm_2d(ev, oracle_mod):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("n", [(20, 13, 9), (37, 5, 17)])
-def test_fmm_ragged(ev, oracle_mod, n):
+@pytest.mark.parametrize("n,leaf", [((20, 13, 9), 4), ((37, 5, 17), 4), ((41, 23, 30), 8)])
+def test_fmm_ragged(ev, oracle_mod, n, leaf):
     case = inputs.make_case("c2", n=n, seed=2)
     P = oracle_problem(oracle_mod, case)
     x = inputs.random_vector(P.N, 7)
-    with ev.plan_from_case(case, method="fmm", prec="fp64") as plan:
+    with ev.plan_from_case(case, method="fmm", prec="fp64", leaf=leaf) as plan:
         err = rel_l2(gpu_apply(plan, x, ev.OP_A), P.apply(x, op=2))
     log("ragged", n, err)
     assert err <= 1e-6
@@ -107,7 +111,7 @@ def test_fmm_ragged(ev, oracle_mod, n):
 def test_fmm_multi_rhs_and_determinism(ev, oracle_mod):
     case = inputs.make_case("c2", n=(16, 16, 16), seed=3)
     X = inputs.random_vector(4096, 9, nrhs=5)
-    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=5) as plan:
+    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=5, leaf=4) as plan:
         Y = gpu_apply(plan, X, ev.OP_A)
         Y2 = gpu_apply(plan, X, ev.OP_A)
         assert np.array_equal(Y, Y2)
@@ -142,7 +146,7 @@ def test_fmm_heterogeneous(ev, oracle_mod):
     x = inputs.random_vector(P.N, 4)
     ref = P.apply(x, op=2)
     for prec in ("fp64", "fp32"):
-        with ev.plan_from_case(case, method="fmm", prec=prec) as plan:
+        with ev.plan_from_case(case, method="fmm", prec=prec, leaf=4) as plan:
             err = rel_l2(gpu_apply(plan, x, ev.OP_A), ref)
         log("heterogeneous fmm", prec, "rel L2", err)
         assert err <= 1e-5
