@@ -698,6 +698,96 @@ void sym_eig(int n, const std::vector<double>& A, std::vector<double>& w, std::v
 
 namespace {
 
+// One box-offset product of the apply (near field, or the far field of a
+// level) with both execution forms and the autotuned choice between them.
+struct GemmSite {
+    bool used = false;
+    PairTiles pl;                         // device arrays of the offset-stationary form
+    std::vector<int> h_gstart;            // host copy, to rebuild tiles for a larger rhs capacity
+    int choice[2] = {-1, -1};             // per rhs bucket (1, >1): 0 class GEMM, 1 offset-stationary
+    float tuned_ms[2][2] = {{0, 0}, {0, 0}};
+    void release()
+    {
+        auto f = [](void* p) { if (p) (void)hipFree(p); };
+        f(pl.pt); f(pl.ps); f(pl.gstart); f(pl.gop); f(pl.tile_group); f(pl.tile_col0); f(pl.tstart); f(pl.tpairs);
+        pl = PairTiles();
+    }
+};
+
+// Pairs of a lattice grouped by offset (offsets in lexicographic order, targets
+// lexicographic within an offset).  far: offsets in [-3,3]^d outside the
+// neighbour cube with parent adjacency; otherwise the 3^d neighbour offsets.
+ert_status build_site(hipStream_t s, int D, const int nl[3], bool far, GemmSite& site)
+{
+    std::vector<int> pt, ps, gstart, gop;
+    const int lo = far ? -3 : -1, hi = far ? 3 : 1, side = far ? kOffSide : 3;
+    long nbox = (long)nl[0] * nl[1] * nl[2];
+    for (int oz = (D > 2 ? lo : 0); oz <= (D > 2 ? hi : 0); ++oz)
+        for (int oy = lo; oy <= hi; ++oy)
+            for (int ox = lo; ox <= hi; ++ox) {
+                const int o[3] = {ox, oy, oz};
+                if (far && ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) continue;
+                const int op = (ox - lo) + side * ((oy - lo) + (D > 2 ? side * (oz - lo) : 0));
+                const size_t before = pt.size();
+                for (long t = 0; t < nbox; ++t) {
+                    int t3[3];
+                    unravel3(t, nl, t3);
+                    bool ok = true;
+                    int s3[3];
+                    for (int a = 0; a < 3; ++a) {
+                        s3[a] = t3[a] + o[a];
+                        if (s3[a] < 0 || s3[a] >= nl[a]) ok = false;
+                        if (far && std::abs((t3[a] >> 1) - (s3[a] >> 1)) > 1) ok = false;
+                    }
+                    if (!ok) continue;
+                    pt.push_back((int)t);
+                    ps.push_back((int)(s3[0] + (long)nl[0] * (s3[1] + (long)nl[1] * s3[2])));
+                }
+                if (pt.size() > before) {
+                    gstart.push_back((int)before);
+                    gop.push_back(op);
+                }
+            }
+    gstart.push_back((int)pt.size());
+    const long np = (long)pt.size();
+    std::vector<int> tstart(nbox + 1, 0), tpairs(np), fill(nbox, 0);
+    for (long p = 0; p < np; ++p) tstart[pt[p] + 1]++;
+    for (long t = 0; t < nbox; ++t) tstart[t + 1] += tstart[t];
+    for (long p = 0; p < np; ++p) tpairs[tstart[pt[p]] + fill[pt[p]]++] = (int)p;
+    site.release();
+    site.pl.npairs = np;
+    site.pl.ngroups = (int)gop.size();
+    site.h_gstart = gstart;
+    ERT_TRY(upload<int>(s, &site.pl.pt, pt));
+    ERT_TRY(upload<int>(s, &site.pl.ps, ps));
+    ERT_TRY(upload<int>(s, &site.pl.gstart, gstart));
+    ERT_TRY(upload<int>(s, &site.pl.gop, gop));
+    ERT_TRY(upload<int>(s, &site.pl.tstart, tstart));
+    ERT_TRY(upload<int>(s, &site.pl.tpairs, tpairs));
+    site.used = true;
+    return ERT_OK;
+}
+
+// column tiles (16 pair-rhs columns each) for a rhs capacity B
+ert_status build_tiles(hipStream_t s, GemmSite& site, int B)
+{
+    std::vector<int> tg, tc;
+    for (int g = 0; g + 1 < (int)site.h_gstart.size(); ++g) {
+        const long ncols = (long)(site.h_gstart[g + 1] - site.h_gstart[g]) * B;
+        for (long c = 0; c < ncols; c += 16) {
+            tg.push_back(g);
+            tc.push_back((int)c);
+        }
+    }
+    if (site.pl.tile_group) (void)hipFree(site.pl.tile_group);
+    if (site.pl.tile_col0) (void)hipFree(site.pl.tile_col0);
+    site.pl.tile_group = site.pl.tile_col0 = nullptr;
+    ERT_TRY(upload<int>(s, &site.pl.tile_group, tg));
+    ERT_TRY(upload<int>(s, &site.pl.tile_col0, tc));
+    site.pl.ntiles = (long)tg.size();
+    return ERT_OK;
+}
+
 template <typename T>
 struct FmmImpl : FmmData {
     int prec = ERT_FP64;
@@ -730,6 +820,11 @@ struct FmmImpl : FmmData {
     T* Lc[kMaxLevels + 1] = {};
     T* Wc[kMaxLevels + 1] = {};         // compressed multipoles
     T* Lh[kMaxLevels + 1] = {};         // compressed locals
+    GemmSite far_site[kMaxLevels + 1];  // far field of level l >= 2 (homogeneous)
+    GemmSite near_site;                 // near field (homogeneous)
+    T* stage = nullptr;                 // staging rows of the offset-stationary form
+    T* tune = nullptr;                  // scratch output while autotuning
+    size_t stage_elems = 0, tune_elems = 0;
 
     ~FmmImpl() override
     {
@@ -738,14 +833,20 @@ struct FmmImpl : FmmData {
         for (int l = 0; l <= kMaxLevels; ++l) {
             f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]); f(hops[l]); f(pstart[l]); f(psrc[l]);
             f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
+            far_site[l].release();
         }
+        near_site.release();
+        f(stage); f(tune);
     }
+
+    ert_status run_site(ert_plan_impl* p, GemmSite& site, int gprec, const BoxGemm& g, int nrhs);
 
     int rank_of(int l) const override { return rp[l]; }
     ert_status setup(ert_plan_impl* p) override;
     ert_status setup_far_hom(ert_plan_impl* p, int l, double svd_tol);
     ert_status setup_far_het(ert_plan_impl* p, int l);
     ert_status ensure_buffers(int nrhs);
+    hipStream_t p_stream = nullptr;
     ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) override;
 
     BoxGemm gemm_desc(int l, int Mrows, int Kd, int nrhs) const
@@ -947,6 +1048,7 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
     dt.nslot = tr.nslot;
     dt.n[0] = p->geo.n0; dt.n[1] = p->geo.n1; dt.n[2] = p->geo.n2;
     hipStream_t s = p->stream;
+    p_stream = s;
 
     // 1D interpolation matrices (FP64 on the host)
     const int nc = tr.nc, leaf = tr.leaf;
@@ -1029,6 +1131,9 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
         const double svd_tol = p->o.svd_tol == 0.0 ? 1e-7 : p->o.svd_tol;
         compress = svd_tol >= 0.0;
         for (int l = 2; l <= tr.L; ++l) ERT_TRY(setup_far_hom(p, l, svd_tol));
+        // both execution forms of the box-offset products
+        if (nearops) ERT_TRY(build_site(s, tr.D, tr.nl[tr.L], false, near_site));
+        for (int l = 2; l <= tr.L; ++l) ERT_TRY(build_site(s, tr.D, tr.nl[l], true, far_site[l]));
     } else {
         const int nn = tr.D == 3 ? 27 : 9;
         const long per = (long)nn * tr.S * tr.S;
@@ -1077,8 +1182,84 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
             ERT_HIP(hipMalloc(&Lh[l], m * sizeof(T)));
         }
     }
+    // offset-stationary form: tiles for this capacity, staging and tuning scratch
+    size_t st_need = 0, tu_need = 0;
+    auto site_need = [&](GemmSite& gs, long nbox, int M) -> ert_status {
+        if (!gs.used) return ERT_OK;
+        ERT_TRY(build_tiles(p_stream, gs, nrhs));
+        st_need = std::max(st_need, (size_t)nrhs * gs.pl.npairs * M);
+        tu_need = std::max(tu_need, (size_t)nrhs * nbox * M);
+        return ERT_OK;
+    };
+    ERT_TRY(site_need(near_site, tr.nleaf, tr.S));
+    for (int l = 2; l <= tr.L; ++l) ERT_TRY(site_need(far_site[l], tr.nbox[l], rp[l] > 0 ? rp[l] : tr.Kp));
+    if (st_need > stage_elems) {
+        if (stage) (void)hipFree(stage);
+        stage = nullptr;
+        stage_elems = 0;
+        ERT_HIP(hipMalloc(&stage, st_need * sizeof(T)));
+        stage_elems = st_need;
+    }
+    if (tu_need > tune_elems) {
+        if (tune) (void)hipFree(tune);
+        tune = nullptr;
+        tune_elems = 0;
+        ERT_HIP(hipMalloc(&tune, tu_need * sizeof(T)));
+        tune_elems = tu_need;
+    }
     B = nrhs;
     return ERT_OK;
+}
+
+// Run one box-offset product in the form chosen for this rhs bucket; the first
+// call of a bucket times both forms (into scratch) and keeps the faster one.
+template <typename T>
+ert_status FmmImpl<T>::run_site(ert_plan_impl* p, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs)
+{
+    hipStream_t s = p->stream;
+    auto as_offset = [&](const BoxGemm& b) {
+        OffsetGemm o;
+        o.nbox = b.nbox;
+        o.B = b.B;
+        o.M = b.M;
+        o.Kd = b.Kd;
+        o.ops = b.ops;
+        o.ops_lo = b.ops_lo;
+        o.W = b.W;
+        o.L = b.L;
+        o.stage = stage;
+        o.accumulate = b.accumulate;
+        o.pl = gs.pl;
+        return o;
+    };
+    if (!gs.used) return box_gemm(s, gprec, g);
+    const int bucket = nrhs > 1 ? 1 : 0;
+    if (gs.choice[bucket] < 0) {
+        BoxGemm gt = g;
+        gt.L = tune;
+        gt.accumulate = 0;
+        const OffsetGemm ot = as_offset(gt);
+        hipEvent_t e[3];
+        for (auto& ev : e) ERT_HIP(hipEventCreate(&ev));
+        float ms[2] = {0.f, 0.f};
+        ert_status st = ERT_OK;
+        for (int form = 0; form < 2 && st == ERT_OK; ++form) {
+            st = form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot);   // warm-up
+            if (st != ERT_OK) break;
+            (void)hipEventRecord(e[0], s);
+            for (int r = 0; r < 3 && st == ERT_OK; ++r) st = form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot);
+            (void)hipEventRecord(e[1], s);
+            if (hipEventSynchronize(e[1]) != hipSuccess) st = ERT_EDEVICE;
+            else (void)hipEventElapsedTime(&ms[form], e[0], e[1]);
+        }
+        for (auto& ev : e) (void)hipEventDestroy(ev);
+        ERT_TRY(st);
+        gs.tuned_ms[bucket][0] = ms[0] / 3;
+        gs.tuned_ms[bucket][1] = ms[1] / 3;
+        gs.choice[bucket] = ms[1] < ms[0] ? 1 : 0;
+    }
+    if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
+    return offset_gemm(s, gprec, as_offset(g));
 }
 
 template <typename T>
@@ -1114,7 +1295,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
             g.W = q;
             g.L = pot;
             g.accumulate = 0;
-            ERT_TRY(box_gemm(s, dprec, g));
+            ERT_TRY(run_site(p, near_site, dprec, g, nrhs));
         } else {
             const int tpp = std::min(tr.S, kB);
             const int groups = kB / tpp;
@@ -1180,7 +1361,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
                     BoxGemm g = gemm_desc(l, R, R, nrhs);       // translate
                     g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                     g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
-                    ERT_TRY(box_gemm(s, prec, g));
+                    ERT_TRY(run_site(p, far_site[l], prec, g, nrhs));
                 }
                 {
                     StageTimer sb_(pf, s, ERT_STAGE_BASIS);
@@ -1193,7 +1374,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
                 BoxGemm g = gemm_desc(l, tr.Kp, tr.Kp, nrhs);
                 g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                 g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = W[l]; g.L = Lc[l]; g.accumulate = 1;
-                ERT_TRY(box_gemm(s, prec, g));
+                ERT_TRY(run_site(p, far_site[l], prec, g, nrhs));
             }
         }
         // a9: L2P adds the far field

@@ -61,6 +61,39 @@ struct BoxGemm {
 
 ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g);
 
+// Offset-stationary form of the same product, for lattices with few targets
+// per offset: the (target, source) pairs are grouped by offset so every
+// operator matrix is streamed once; each pair's product goes to a staging row
+// and a second pass sums the rows of each target in a fixed order.
+struct PairTiles {
+    long npairs = 0;
+    int ngroups = 0;
+    long ntiles = 0;          // column tiles over all groups, for the rhs capacity they were built for
+    int* pt = nullptr;        // [npairs] target box
+    int* ps = nullptr;        // [npairs] source box
+    int* gstart = nullptr;    // [ngroups + 1] pair range of each offset group
+    int* gop = nullptr;       // [ngroups] operator slot of the group
+    int* tile_group = nullptr;   // [ntiles]
+    int* tile_col0 = nullptr;    // [ntiles] first (pair, rhs) column of the tile
+    int* tstart = nullptr;    // [nbox + 1] pairs of each target (CSR, increasing group order)
+    int* tpairs = nullptr;    // [npairs]
+};
+
+struct OffsetGemm {
+    long nbox;
+    int B;
+    int M, Kd;
+    const void* ops;
+    const void* ops_lo;
+    const void* W;            // [B][nbox][Kd]
+    void* L;                  // [B][nbox][M]
+    void* stage;              // [B][npairs][M]
+    int accumulate;
+    PairTiles pl;
+};
+
+ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);
+
 // Heterogeneous far field: one cached matrix per (target, source) pair,
 // stored source-node major [pair][Kd][M], CSR over targets.
 struct PairGemm {

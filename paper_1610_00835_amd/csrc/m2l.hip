@@ -214,6 +214,133 @@ __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_til
         }
 }
 
+// ---------------------------------------------------- offset-stationary ----
+
+template <int PREC, int TM, int TN>
+__global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
+{
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    __shared__ V red[(kWaves - 1) * TM * TN * 64];
+    const int grpi = g.pl.tile_group[blockIdx.x];
+    const long col0 = g.pl.tile_col0[blockIdx.x];
+    const int p0 = g.pl.gstart[grpi], np = g.pl.gstart[grpi + 1] - p0;
+    if (col0 >= (long)np * g.B) return;                 // uniform over the block
+    const int op = g.pl.gop[grpi];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4;
+    const int row0 = blockIdx.y * 16 * TM;
+    constexpr int CW = (PREC == ERT_BF16X3) ? 32 : 16;
+    constexpr int LG = (PREC == ERT_BF16X3) ? 8 : 4;
+    long pidx[TN];
+    int pb[TN];
+    const T* bp[TN];
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) {
+        const long col = col0 + 16 * tn + (lane & 15);
+        const bool ok = col < (long)np * g.B;
+        const long cc = ok ? col : 0;
+        pb[tn] = (int)(cc / np);
+        pidx[tn] = ok ? p0 + (cc - (long)pb[tn] * np) : -1;
+        bp[tn] = ok ? (const T*)g.W + ((long)pb[tn] * g.nbox + g.pl.ps[pidx[tn]]) * g.Kd + LG * grp : nullptr;
+    }
+    V acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = V{0, 0, 0, 0};
+    const long abase = ((long)op * g.M + row0 + (lane & 15)) * g.Kd + LG * grp;
+    for (int kk = wave * CW; kk < g.Kd; kk += kWaves * CW) {
+        if constexpr (PREC == ERT_BF16X3) {
+            const __bf16* ohi = (const __bf16*)g.ops;
+            const __bf16* olo = (const __bf16*)g.ops_lo;
+            v8bf ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                const long a = abase + (long)16 * tm * g.Kd + kk;
+                ah[tm] = *(const v8bf*)(ohi + a);
+                al[tm] = *(const v8bf*)(olo + a);
+            }
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                v4f x0 = v4f{0.f, 0.f, 0.f, 0.f}, x1 = x0;
+                if (bp[tn]) {
+                    x0 = *(const v4f*)(bp[tn] + kk);
+                    x1 = *(const v4f*)(bp[tn] + kk + 4);
+                }
+                split_bf16(x0, x1, bh[tn], bl[tn]);
+            }
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn) {
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+                }
+        } else {
+            const T* A = (const T*)g.ops;
+            V av[TM], bv[TN];
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) av[tm] = *(const V*)(A + abase + (long)16 * tm * g.Kd + kk);
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) bv[tn] = bp[tn] ? *(const V*)(bp[tn] + kk) : V{0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn) {
+                        if constexpr (PREC == ERT_FP64)
+                            acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
+                        else
+                            acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
+                    }
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) red[(((wave - 1) * TM + tm) * TN + tn) * 64 + lane] = acc[tm][tn];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    T* St = (T*)g.stage;
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+            V s = acc[tm][tn];
+            for (int w = 1; w < kWaves; ++w) s += red[(((w - 1) * TM + tm) * TN + tn) * 64 + lane];
+            if (pidx[tn] < 0) continue;
+            T* col = St + ((long)pb[tn] * g.pl.npairs + pidx[tn]) * g.M + row0 + 16 * tm;
+            if constexpr (PREC == ERT_FP64) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) col[grp + 4 * i] = s[i];
+            } else {
+                *(V*)(col + 4 * grp) = s;
+            }
+        }
+}
+
+// per target: sum of its staged pair rows in increasing offset order
+template <typename T>
+__global__ void k_stage_reduce(OffsetGemm g)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = g.nbox * g.M;
+    if (i >= per * g.B) return;
+    const int b = (int)(i / per);
+    const long rem = i - (long)b * per;
+    const long t = rem / g.M;
+    const int r = (int)(rem - t * g.M);
+    const T* St = (const T*)g.stage + (long)b * g.pl.npairs * g.M + r;
+    T s = T(0);
+    for (int k = g.pl.tstart[t]; k < g.pl.tstart[t + 1]; ++k) s += St[(long)g.pl.tpairs[k] * g.M];
+    T* d = (T*)g.L + i;
+    *d = g.accumulate ? *d + s : s;
+}
+
 // ------------------------------------------------- heterogeneous (cached) ----
 // One workgroup per (target box, block of right-hand sides).  Thread r owns
 // output row r; for each source in the target's list the source vectors of the
@@ -292,6 +419,31 @@ ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g)
         hipLaunchKernelGGL((k_box_gemm<ERT_FP32, kTM, kTN>), grid, dim3(64 * kWaves), 0, s, g, row_tiles);
     else
         hipLaunchKernelGGL((k_box_gemm<ERT_BF16X3, kTM, kTN>), grid, dim3(64 * kWaves), 0, s, g, row_tiles);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
+{
+    if (g.M % (16 * kTM) != 0 || g.Kd % 32 != 0) {
+        record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
+        return ERT_EINVAL;
+    }
+    if (g.pl.ntiles > 0) {
+        dim3 grid((unsigned)g.pl.ntiles, (unsigned)(g.M / (16 * kTM)));
+        if (prec == ERT_FP64)
+            hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);
+        else if (prec == ERT_FP32)
+            hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);
+        else
+            hipLaunchKernelGGL((k_offset_gemm<ERT_BF16X3, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);
+        ERT_HIP(hipGetLastError());
+    }
+    const long n = g.nbox * g.M * g.B;
+    if (prec == ERT_FP64)
+        hipLaunchKernelGGL(k_stage_reduce<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL(k_stage_reduce<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }
