@@ -99,7 +99,7 @@ typedef struct {
     int flags;        /* reserved, must be 0 */
     double svd_tol;   /* FMM, homogeneous media: relative singular-value cutoff of the
                          compressed far-field translations (shared orthonormal basis per
-                         level from the SVD of all translation matrices); 0 -> 1e-7,
+                         level from the SVD of all translation matrices); 0 -> 1e-6,
                          < 0 -> no compression */
 } ert_vie_opts;
 

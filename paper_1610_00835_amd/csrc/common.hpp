@@ -172,6 +172,7 @@ struct ert_plan_impl {
     size_t red_elems = 0;
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
     Profiler prof;
+    bool use_graphs = true;      // FMM applies replay captured graphs
 };
 
 // ------------------------------------------------------ launchers (.hip) ---

@@ -74,12 +74,30 @@ __device__ __forceinline__ long slot_cell(const DevTree& t, long slot, int c[3])
 
 // ---------------------------------------------------- gather / assemble ----
 
+// Vectors and operator of the current apply, read by the first and last kernel
+// so that one captured graph serves every call with the same rhs count.
+struct ApplyIO {
+    const double* x;
+    double* y;
+    int op;
+    int pad;
+};
+
+__global__ void k_set_io(ApplyIO* io, const double* x, double* y, int op)
+{
+    io->x = x;
+    io->y = y;
+    io->op = op;
+}
+
 template <typename T>
-__global__ void k_gather(DevTree t, const double* __restrict__ x, const double* __restrict__ ss, int weighted,
-                         long N, int B, T* __restrict__ q)
+__global__ void k_gather(DevTree t, const ApplyIO* __restrict__ io, const double* __restrict__ ss, long N, int B,
+                         T* __restrict__ q)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= t.nslot * B) return;
+    const double* x = io->x;
+    const int weighted = io->op != ERT_OP_G;
     int b = (int)(i / t.nslot);
     long slot = i - (long)b * t.nslot;
     int c[3];
@@ -91,12 +109,14 @@ __global__ void k_gather(DevTree t, const double* __restrict__ x, const double* 
 
 // y_j = h^d pot_j + A_jj w_j (FP64), op A: x_j - y_j; natural order
 template <typename T>
-__global__ void k_assemble(DevTree t, const T* __restrict__ pot, const double* __restrict__ x,
-                           const double* __restrict__ ss, const double* __restrict__ diag, int op, double hd, long N,
-                           int B, double* __restrict__ y)
+__global__ void k_assemble(DevTree t, const T* __restrict__ pot, const ApplyIO* __restrict__ io,
+                           const double* __restrict__ ss, const double* __restrict__ diag, double hd, long N, int B)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= N * B) return;
+    const double* x = io->x;
+    double* y = io->y;
+    const int op = io->op;
     int b = (int)(i / N);
     long j = i - (long)b * N;
     int c[3];
@@ -822,6 +842,12 @@ struct FmmImpl : FmmData {
     T* Lh[kMaxLevels + 1] = {};         // compressed locals
     GemmSite far_site[kMaxLevels + 1];  // far field of level l >= 2 (homogeneous)
     GemmSite near_site;                 // near field (homogeneous)
+    ApplyIO* io = nullptr;              // device: vectors of the current apply
+    hipStream_t cap = nullptr;          // internal stream used only to capture graphs
+    hipGraph_t graph[2] = {};           // captured applies, per rhs bucket (1, >1)
+    hipGraphExec_t gexec[2] = {};
+    int graph_nrhs[2] = {0, 0};
+    int calls[2] = {0, 0};
     T* stage = nullptr;                 // staging rows of the offset-stationary form
     T* tune = nullptr;                  // scratch output while autotuning
     size_t stage_elems = 0, tune_elems = 0;
@@ -836,10 +862,23 @@ struct FmmImpl : FmmData {
             far_site[l].release();
         }
         near_site.release();
-        f(stage); f(tune);
+        f(stage); f(tune); f(io);
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
     }
 
-    ert_status run_site(ert_plan_impl* p, GemmSite& site, int gprec, const BoxGemm& g, int nrhs);
+    ert_status run_site(ert_plan_impl* p, hipStream_t s, GemmSite& site, int gprec, const BoxGemm& g, int nrhs);
+    ert_status enqueue(ert_plan_impl* p, hipStream_t s, int nrhs);
+    void drop_graphs()
+    {
+        for (int b = 0; b < 2; ++b) {
+            if (gexec[b]) (void)hipGraphExecDestroy(gexec[b]);
+            if (graph[b]) (void)hipGraphDestroy(graph[b]);
+            gexec[b] = nullptr;
+            graph[b] = nullptr;
+            graph_nrhs[b] = 0;
+        }
+    }
 
     int rank_of(int l) const override { return rp[l]; }
     ert_status setup(ert_plan_impl* p) override;
@@ -1128,7 +1167,7 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
             }
             ERT_TRY(upload_cvt<T>(s, &tab, tb));
         }
-        const double svd_tol = p->o.svd_tol == 0.0 ? 1e-7 : p->o.svd_tol;
+        const double svd_tol = p->o.svd_tol == 0.0 ? 1e-6 : p->o.svd_tol;
         compress = svd_tol >= 0.0;
         for (int l = 2; l <= tr.L; ++l) ERT_TRY(setup_far_hom(p, l, svd_tol));
         // both execution forms of the box-offset products
@@ -1159,7 +1198,9 @@ template <typename T>
 ert_status FmmImpl<T>::ensure_buffers(int nrhs)
 {
     if (nrhs <= B) return ERT_OK;
+    drop_graphs();
     auto f = [](void* p) { if (p) (void)hipFree(p); };
+    if (!io) ERT_HIP(hipMalloc(&io, sizeof(ApplyIO)));
     f(q); f(pot);
     q = pot = nullptr;
     for (int l = 0; l <= kMaxLevels; ++l) {
@@ -1214,9 +1255,9 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
 // Run one box-offset product in the form chosen for this rhs bucket; the first
 // call of a bucket times both forms (into scratch) and keeps the faster one.
 template <typename T>
-ert_status FmmImpl<T>::run_site(ert_plan_impl* p, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs)
+ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs)
 {
-    hipStream_t s = p->stream;
+    (void)p;
     auto as_offset = [&](const BoxGemm& b) {
         OffsetGemm o;
         o.nbox = b.nbox;
@@ -1263,10 +1304,8 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, GemmSite& gs, int gprec, const
 }
 
 template <typename T>
-ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs)
+ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
 {
-    ERT_TRY(ensure_buffers(nrhs));
-    hipStream_t s = p->stream;
     const long N = p->N;
     const int nn = tr.D == 3 ? 27 : 9;
     const int dprec = (prec == ERT_FP64) ? ERT_FP64 : ERT_FP32;   // precision of the dense transforms
@@ -1274,8 +1313,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
     // a4: weights into leaf-major order
     {
         StageTimer st_(pf, s, ERT_STAGE_GATHER);
-        hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, x, p->d_ss,
-                           op != ERT_OP_G ? 1 : 0, N, nrhs, q);
+        hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, io, p->d_ss, N, nrhs, q);
         ERT_HIP(hipGetLastError());
     }
     // a10: near field (writes pot)
@@ -1295,7 +1333,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
             g.W = q;
             g.L = pot;
             g.accumulate = 0;
-            ERT_TRY(run_site(p, near_site, dprec, g, nrhs));
+            ERT_TRY(run_site(p, s, near_site, dprec, g, nrhs));
         } else {
             const int tpp = std::min(tr.S, kB);
             const int groups = kB / tpp;
@@ -1322,11 +1360,13 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
         }
         // a7/a8: downward pass
         for (int l = 2; l <= L; ++l) {
+            // the top level has no parent: its locals start at the first far-field
+            // product written with accumulate = 0 (no zero fill)
+            const int first = (l == 2) ? 1 : 0;
             {
                 StageTimer st_(pf, s, ERT_STAGE_L2L);
                 if (l == 2) {
-                    long n = (long)nrhs * tr.nbox[2] * tr.Kp;
-                    hipLaunchKernelGGL(k_zero_t<T>, dim3(blocks(n)), dim3(kB), 0, s, Lc[2], n);
+                    // nothing to inherit
                 } else {
                     hipLaunchKernelGGL(k_l2l<T>, dim3((unsigned)tr.nbox[l], nrhs), dim3(kB), 0, s, tr.D, tr.nc, tr.K,
                                        tr.Kp, tr.nl[l - 1][0], tr.nl[l - 1][1], tr.nl[l - 1][2], tr.nbox[l - 1],
@@ -1345,6 +1385,7 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
                 a.opsT = hops[l];
                 a.W = W[l];
                 a.L = Lc[l];
+                a.accumulate = first ? 0 : 1;
                 ERT_TRY(pair_gemm(s, prec, a));
             } else if (rp[l] > 0) {
                 const int R = rp[l];
@@ -1361,20 +1402,20 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
                     BoxGemm g = gemm_desc(l, R, R, nrhs);       // translate
                     g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                     g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
-                    ERT_TRY(run_site(p, far_site[l], prec, g, nrhs));
+                    ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs));
                 }
                 {
                     StageTimer sb_(pf, s, ERT_STAGE_BASIS);
                     BoxGemm u = gemm_desc(l, tr.Kp, R, nrhs);   // back to the node basis, added to the locals
                     u.stride = 1; u.nclass = 1; u.noff = 1; u.offs = id_off;
-                    u.ops = Um[l]; u.W = Lh[l]; u.L = Lc[l]; u.accumulate = 1;
+                    u.ops = Um[l]; u.W = Lh[l]; u.L = Lc[l]; u.accumulate = first ? 0 : 1;
                     ERT_TRY(box_gemm(s, dprec, u));
                 }
             } else {
                 BoxGemm g = gemm_desc(l, tr.Kp, tr.Kp, nrhs);
                 g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
-                g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = W[l]; g.L = Lc[l]; g.accumulate = 1;
-                ERT_TRY(run_site(p, far_site[l], prec, g, nrhs));
+                g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = W[l]; g.L = Lc[l]; g.accumulate = first ? 0 : 1;
+                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs));
             }
         }
         // a9: L2P adds the far field
@@ -1385,9 +1426,60 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
     // a11: scale, self term, operator
     const double hd = std::pow(p->geo.h, tr.D);
     StageTimer st_(pf, s, ERT_STAGE_ASSEMBLE);
-    hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, x, p->d_ss, p->d_diag, op, hd,
-                       N, nrhs, y);
+    hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, io, p->d_ss, p->d_diag, hd, N,
+                       nrhs);
     ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+// y = op(x): one small kernel sets the vectors, then the apply runs from a
+// captured graph (third and later calls of a rhs bucket; the first call tunes
+// the execution forms, the second captures) or eagerly while profiling.
+template <typename T>
+ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs)
+{
+    ERT_TRY(ensure_buffers(nrhs));
+    hipStream_t s = p->stream;
+    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, s, io, x, y, op);
+    ERT_HIP(hipGetLastError());
+    const int bucket = nrhs > 1 ? 1 : 0;
+    if (p->prof.on || !p->use_graphs) return enqueue(p, s, nrhs);
+    if (gexec[bucket] && graph_nrhs[bucket] == nrhs) {
+        ERT_HIP(hipGraphLaunch(gexec[bucket], s));
+        return ERT_OK;
+    }
+    if (calls[bucket]++ == 0) return enqueue(p, s, nrhs);   // tunes the forms of this bucket
+    // capture on the internal stream, ordered after the caller's stream
+    if (!cap) ERT_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (gexec[bucket]) {
+        (void)hipGraphExecDestroy(gexec[bucket]);
+        (void)hipGraphDestroy(graph[bucket]);
+        gexec[bucket] = nullptr;
+        graph[bucket] = nullptr;
+    }
+    ERT_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    ert_status st = enqueue(p, cap, nrhs);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(cap, &g);
+    if (st != ERT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (ce != hipSuccess) {
+        record_hip_error("hipStreamEndCapture", ce, __FILE__, __LINE__);
+        return ERT_EDEVICE;
+    }
+    hipGraphExec_t ge = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        record_hip_error("hipGraphInstantiate", ie, __FILE__, __LINE__);
+        return ERT_EDEVICE;
+    }
+    graph[bucket] = g;
+    gexec[bucket] = ge;
+    graph_nrhs[bucket] = nrhs;
+    ERT_HIP(hipGraphLaunch(ge, s));
     return ERT_OK;
 }
 

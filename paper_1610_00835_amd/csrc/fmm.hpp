@@ -104,7 +104,8 @@ struct PairGemm {
     const int* pair_src;
     const void* opsT;
     const void* W;   // [B][nbox][Kd]
-    void* L;         // [B][nbox][M], accumulated into
+    void* L;         // [B][nbox][M]
+    int accumulate;  // 1: L += result, 0: L = result
 };
 
 ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& g);

@@ -55,6 +55,95 @@ __device__ __forceinline__ void split_bf16(const v4f& x0, const v4f& x1, v8bf& h
     }
 }
 
+
+// One reduction chunk of a tile: the operand registers of TM row blocks and TN
+// column blocks (bf16x3 keeps the FP32 source values and splits them at use).
+template <int PREC, int TM, int TN>
+struct Frag {
+    typedef typename Acc<PREC>::V V;
+    V a[TM], b[TN];              // FP64 / FP32
+    v8bf ah[TM], al[TM];         // BF16X3 operator parts
+    v4f x0[TN], x1[TN];          // BF16X3 source values
+};
+
+template <int PREC, int TM, int TN>
+__device__ __forceinline__ void frag_load(Frag<PREC, TM, TN>& f, const void* ops, const void* ops_lo, long abase,
+                                          long rowstep, const typename Acc<PREC>::T* const bp[TN], int kk)
+{
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    if constexpr (PREC == ERT_BF16X3) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+            const long a = abase + tm * rowstep + kk;
+            f.ah[tm] = *(const v8bf*)((const __bf16*)ops + a);
+            f.al[tm] = *(const v8bf*)((const __bf16*)ops_lo + a);
+        }
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+            f.x0[tn] = bp[tn] ? *(const v4f*)(bp[tn] + kk) : v4f{0.f, 0.f, 0.f, 0.f};
+            f.x1[tn] = bp[tn] ? *(const v4f*)(bp[tn] + kk + 4) : v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    } else {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) f.a[tm] = *(const V*)((const T*)ops + abase + tm * rowstep + kk);
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) f.b[tn] = bp[tn] ? *(const V*)(bp[tn] + kk) : V{0, 0, 0, 0};
+    }
+}
+
+template <int PREC, int TM, int TN>
+__device__ __forceinline__ void frag_mma(const Frag<PREC, TM, TN>& f, typename Acc<PREC>::V (&acc)[TM][TN])
+{
+    if constexpr (PREC == ERT_BF16X3) {
+        v8bf bh[TN], bl[TN];
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) split_bf16(f.x0[tn], f.x1[tn], bh[tn], bl[tn]);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+                acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
+                acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
+            }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn) {
+                    if constexpr (PREC == ERT_FP64)
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[tm][e], f.b[tn][e], acc[tm][tn], 0, 0, 0);
+                    else
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[tm][e], f.b[tn][e], acc[tm][tn], 0, 0, 0);
+                }
+    }
+}
+
+// The reduction chunks of one operator, split over the waves (chunk c goes to
+// wave c mod 4); U chunks' loads are issued before their products so that
+// several loads are in flight per wave.
+template <int PREC, int TM, int TN>
+__device__ __forceinline__ void tile_reduce(const void* ops, const void* ops_lo, long abase, long rowstep, int Kd,
+                                            const typename Acc<PREC>::T* const bp[TN], int wave,
+                                            typename Acc<PREC>::V (&acc)[TM][TN])
+{
+    constexpr int CW = (PREC == ERT_BF16X3) ? 32 : 16;
+    constexpr int U = (PREC == ERT_FP32) ? 4 : 2;
+    constexpr int STEP = kWaves * CW;
+    for (int k0 = wave * CW; k0 < Kd; k0 += U * STEP) {
+        Frag<PREC, TM, TN> f[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * STEP < Kd) frag_load<PREC, TM, TN>(f[u], ops, ops_lo, abase, rowstep, bp, k0 + u * STEP);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * STEP < Kd) frag_mma<PREC, TM, TN>(f[u], acc);
+    }
+}
+
 template <int PREC, int TM, int TN>
 __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_tiles)
 {
@@ -76,7 +165,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_til
     if (col0 >= nt * g.B) return;                      // uniform over the block
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4;
     const int row0 = rt * 16 * TM;
-    constexpr int CW = (PREC == ERT_BF16X3) ? 32 : 16;  // reduction chunk per MFMA group
     constexpr int LG = (PREC == ERT_BF16X3) ? 8 : 4;    // elements per lane per chunk
 
     // columns of this lane
@@ -129,56 +217,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_til
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[i][j] = V{0, 0, 0, 0};
         const long abase = ((long)o.op * g.M + row0 + (lane & 15)) * g.Kd + LG * grp;
-        for (int kk = wave * CW; kk < g.Kd; kk += kWaves * CW) {
-            if constexpr (PREC == ERT_BF16X3) {
-                const __bf16* ohi = (const __bf16*)g.ops;
-                const __bf16* olo = (const __bf16*)g.ops_lo;
-                v8bf ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm) {
-                    const long a = abase + (long)16 * tm * g.Kd + kk;
-                    ah[tm] = *(const v8bf*)(ohi + a);
-                    al[tm] = *(const v8bf*)(olo + a);
-                }
-#pragma unroll
-                for (int tn = 0; tn < TN; ++tn) {
-                    v4f x0 = v4f{0.f, 0.f, 0.f, 0.f}, x1 = x0;
-                    if (bp[tn]) {
-                        x0 = *(const v4f*)(bp[tn] + kk);
-                        x1 = *(const v4f*)(bp[tn] + kk + 4);
-                    }
-                    split_bf16(x0, x1, bh[tn], bl[tn]);
-                }
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-                    for (int tn = 0; tn < TN; ++tn) {
-                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
-                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
-                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
-                    }
-            } else {
-                const T* A = (const T*)g.ops;
-                V av[TM], bv[TN];
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm) av[tm] = *(const V*)(A + abase + (long)16 * tm * g.Kd + kk);
-#pragma unroll
-                for (int tn = 0; tn < TN; ++tn) bv[tn] = bp[tn] ? *(const V*)(bp[tn] + kk) : V{0, 0, 0, 0};
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-                        for (int tn = 0; tn < TN; ++tn) {
-                            if constexpr (PREC == ERT_FP64)
-                                acc[tm][tn] =
-                                    __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
-                            else
-                                acc[tm][tn] =
-                                    __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
-                        }
-            }
-        }
+        tile_reduce<PREC, TM, TN>(g.ops, g.ops_lo, abase, (long)16 * g.Kd, g.Kd, bp, wave, acc);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -229,7 +268,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
     const int op = g.pl.gop[grpi];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4;
     const int row0 = blockIdx.y * 16 * TM;
-    constexpr int CW = (PREC == ERT_BF16X3) ? 32 : 16;
     constexpr int LG = (PREC == ERT_BF16X3) ? 8 : 4;
     long pidx[TN];
     int pb[TN];
@@ -249,54 +287,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = V{0, 0, 0, 0};
     const long abase = ((long)op * g.M + row0 + (lane & 15)) * g.Kd + LG * grp;
-    for (int kk = wave * CW; kk < g.Kd; kk += kWaves * CW) {
-        if constexpr (PREC == ERT_BF16X3) {
-            const __bf16* ohi = (const __bf16*)g.ops;
-            const __bf16* olo = (const __bf16*)g.ops_lo;
-            v8bf ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-            for (int tm = 0; tm < TM; ++tm) {
-                const long a = abase + (long)16 * tm * g.Kd + kk;
-                ah[tm] = *(const v8bf*)(ohi + a);
-                al[tm] = *(const v8bf*)(olo + a);
-            }
-#pragma unroll
-            for (int tn = 0; tn < TN; ++tn) {
-                v4f x0 = v4f{0.f, 0.f, 0.f, 0.f}, x1 = x0;
-                if (bp[tn]) {
-                    x0 = *(const v4f*)(bp[tn] + kk);
-                    x1 = *(const v4f*)(bp[tn] + kk + 4);
-                }
-                split_bf16(x0, x1, bh[tn], bl[tn]);
-            }
-#pragma unroll
-            for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-                for (int tn = 0; tn < TN; ++tn) {
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bh[tn], acc[tm][tn], 0, 0, 0);
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[tm], bl[tn], acc[tm][tn], 0, 0, 0);
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[tm], bh[tn], acc[tm][tn], 0, 0, 0);
-                }
-        } else {
-            const T* A = (const T*)g.ops;
-            V av[TM], bv[TN];
-#pragma unroll
-            for (int tm = 0; tm < TM; ++tm) av[tm] = *(const V*)(A + abase + (long)16 * tm * g.Kd + kk);
-#pragma unroll
-            for (int tn = 0; tn < TN; ++tn) bv[tn] = bp[tn] ? *(const V*)(bp[tn] + kk) : V{0, 0, 0, 0};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-                    for (int tn = 0; tn < TN; ++tn) {
-                        if constexpr (PREC == ERT_FP64)
-                            acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
-                        else
-                            acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][e], bv[tn][e], acc[tm][tn], 0, 0, 0);
-                    }
-        }
-    }
+    tile_reduce<PREC, TM, TN>(g.ops, g.ops_lo, abase, (long)16 * g.Kd, g.Kd, bp, wave, acc);
     if (wave > 0) {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
@@ -323,7 +314,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
         }
 }
 
-// per target: sum of its staged pair rows in increasing offset order
+// per target: sum of its staged pair rows in increasing offset order.  The
+// rows of one target are consecutive threads (M >= 64), so the pair indices
+// are wave-uniform; 16 row loads are issued before they are summed.
 template <typename T>
 __global__ void k_stage_reduce(OffsetGemm g)
 {
@@ -335,8 +328,17 @@ __global__ void k_stage_reduce(OffsetGemm g)
     const long t = rem / g.M;
     const int r = (int)(rem - t * g.M);
     const T* St = (const T*)g.stage + (long)b * g.pl.npairs * g.M + r;
+    const int k1 = g.pl.tstart[t + 1];
+    int k = g.pl.tstart[t];
     T s = T(0);
-    for (int k = g.pl.tstart[t]; k < g.pl.tstart[t + 1]; ++k) s += St[(long)g.pl.tpairs[k] * g.M];
+    for (; k + 16 <= k1; k += 16) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = St[(long)g.pl.tpairs[k + u] * g.M];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; k < k1; ++k) s += St[(long)g.pl.tpairs[k] * g.M];
     T* d = (T*)g.L + i;
     *d = g.accumulate ? *d + s : s;
 }
@@ -384,7 +386,10 @@ __global__ __launch_bounds__(256) void k_pair_gemm(PairGemm a)
         if (r < a.M) {
 #pragma unroll
             for (int b = 0; b < RB; ++b)
-                if (b < nb) Lo[((long)(b0 + b) * a.nbox + t) * a.M + r] += acc[b];
+                if (b < nb) {
+                    T* d = Lo + ((long)(b0 + b) * a.nbox + t) * a.M + r;
+                    *d = a.accumulate ? *d + acc[b] : acc[b];
+                }
         }
     }
 }
@@ -412,6 +417,20 @@ ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g)
     }
     const long col_tiles = (max_nt * g.B + 16 * kTN - 1) / (16 * kTN);
     if (col_tiles == 0) return ERT_OK;
+    if ((long)row_tiles * col_tiles * g.nclass < 512) {
+        // small products: 16 x 16 tiles for four times as many workgroups
+        const int rt1 = g.M / 16;
+        const long ct1 = (max_nt * g.B + 15) / 16;
+        dim3 grid((unsigned)(rt1 * ct1), (unsigned)g.nclass);
+        if (prec == ERT_FP64)
+            hipLaunchKernelGGL((k_box_gemm<ERT_FP64, 1, 1>), grid, dim3(64 * kWaves), 0, s, g, rt1);
+        else if (prec == ERT_FP32)
+            hipLaunchKernelGGL((k_box_gemm<ERT_FP32, 1, 1>), grid, dim3(64 * kWaves), 0, s, g, rt1);
+        else
+            hipLaunchKernelGGL((k_box_gemm<ERT_BF16X3, 1, 1>), grid, dim3(64 * kWaves), 0, s, g, rt1);
+        ERT_HIP(hipGetLastError());
+        return ERT_OK;
+    }
     dim3 grid((unsigned)(row_tiles * col_tiles), (unsigned)g.nclass);
     if (prec == ERT_FP64)
         hipLaunchKernelGGL((k_box_gemm<ERT_FP64, kTM, kTN>), grid, dim3(64 * kWaves), 0, s, g, row_tiles);

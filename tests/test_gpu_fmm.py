@@ -150,3 +150,44 @@ def test_fmm_heterogeneous(ev, oracle_mod):
             err = rel_l2(gpu_apply(plan, x, ev.OP_A), ref)
         log("heterogeneous fmm", prec, "rel L2", err)
         assert err <= 1e-5
+
+
+def test_fmm_graph_replays_match_eager(ev, oracle_mod):
+    """Applies after the second call of a rhs count replay a captured graph; every replay
+    (with other work and synchronisations in between) equals the eager apply bit for bit."""
+    import torch
+    from tests.gpu_util import to_dev, to_host
+    case = inputs.make_case("c2", n=(32, 32, 32), seed=4)
+    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=2) as plan:
+        xs = [inputs.random_vector(case["f"].size, 20 + i) for i in range(5)]
+        plan.profile(True)            # eager path (no graph) while profiling
+        eager = [gpu_apply(plan, x, ev.OP_A) for x in xs]
+        plan.profile(False)
+        for rep in range(3):
+            for i, x in enumerate(xs):
+                y = gpu_apply(plan, x, ev.OP_A if i % 2 == 0 else ev.OP_A)
+                assert np.array_equal(y, eager[i]), (rep, i)
+                # unrelated device work between replays
+                t = torch.randn(1000, device="cuda").sum()
+                torch.cuda.synchronize()
+        # two right-hand sides use their own graph
+        X = np.stack([xs[0], xs[1]], axis=1)
+        Y = gpu_apply(plan, X, ev.OP_A)
+        Y = gpu_apply(plan, X, ev.OP_A)
+        Y = gpu_apply(plan, X, ev.OP_A)
+        assert np.max(np.abs(Y[:, 0] - eager[0])) <= 1e-12 * np.max(np.abs(eager[0]))
+
+
+@pytest.mark.parametrize("svd_tol", [1e-6, 1e-5])
+def test_fmm_compression_tolerance(ev, oracle_mod, svd_tol):
+    """Looser singular-value cutoffs keep the 32^3 apply within the 1e-6 bar."""
+    case = inputs.make_case("c2", seed=0)
+    P = oracle_problem(oracle_mod, case)
+    x = case["f"]
+    rows = np.random.default_rng(3).choice(P.N, size=600, replace=False)
+    ref = P.apply_rows(x, rows, op=1)
+    with ev.plan_from_case(case, method="fmm", prec="fp64", svd_tol=svd_tol) as plan:
+        err = rel_l2(gpu_apply(plan, x, ev.OP_GS)[rows], ref)
+        info = plan.fmm_info()
+    log("svd_tol", svd_tol, "rank", info["rank"], "rel L2", err)
+    assert err <= 1e-6
