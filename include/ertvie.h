@@ -111,7 +111,9 @@ typedef struct {
                          FP64 operator, inner GMRES on the FP32 operator */
     double inner_tol; /* mixed: relative tolerance of each inner solve; 0 -> 1e-5 */
     int rhs_is_phi;   /* 1: the f argument already holds phi (skip step S.1) */
-    int reserved[4];  /* must be 0 */
+    int block;        /* 1: block GMRES -- the nrhs columns share one block Krylov space and
+                         every operator application is one batched apply (0: column by column) */
+    int reserved[3];  /* must be 0 */
 } ert_solve_opts;
 
 typedef struct {
@@ -148,7 +150,8 @@ ERT_API ert_status ert_vie_apply_ex(ert_vie_plan_t plan, int op, int method, int
                             const double* x, double* y, int nrhs);
 
 /* Algorithm 1 steps S.1-S.2: phi = A f, then GMRES (x0 = 0) for (I - K) U = phi.
- *   f, U : device, N x nrhs column-major FP64 (nrhs columns solved one after another).
+ *   f, U : device, N x nrhs column-major FP64 (solved one after another, or together with
+ *          opts->block; a block solve reports the worst column in info).
  *   opts : host, may be NULL for defaults.  info: host, may be NULL (last column's info).
  * Returns ERT_ENOCONV when max_iter is reached first; U then holds the best iterate. */
 ERT_API ert_status ert_vie_solve(ert_vie_plan_t plan, const double* f, double* U, int nrhs,

@@ -1,6 +1,7 @@
 // C ABI of the library (include/ertvie.h): plan construction and validation,
 // operator dispatch, and the Krylov solvers of Algorithm 1 step S.2 driven
 // from the host with FP64 device vectors.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -127,15 +128,24 @@ Profiler::~Profiler()
     for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-namespace {
-
-ert_status apply_dispatch(ert_plan_impl* p, int op, int method, int prec, const double* x, double* y, int nrhs)
+ert_status plan_apply(ert_plan_impl* p, int op, int method, int prec, const double* x, double* y, int nrhs)
 {
     if (method == ERT_DIRECT) {
         StageTimer t(&p->prof, p->stream, ERT_STAGE_DIRECT);
         return direct_apply(p, op, prec, x, y, nrhs);
     }
     return fmm_apply(p, op, prec, x, y, nrhs);
+}
+
+ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Phi, double* X, int nb, double rtol,
+                       int maxit, int restart, bool check_true, int* iters_out, int* cycles_out, int* matvecs_out,
+                       double* est_out, double* true_out, bool* conv_out);
+
+namespace {
+
+ert_status apply_dispatch(ert_plan_impl* p, int op, int method, int prec, const double* x, double* y, int nrhs)
+{
+    return plan_apply(p, op, method, prec, x, y, nrhs);
 }
 
 ert_status ensure_workspace(ert_plan_impl* p, size_t vec_elems, size_t red_elems)
@@ -474,6 +484,84 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
     double* r = extra + N;
     double* d = extra + 2 * N;
     ert_status st = ERT_OK;
+    if (so.block && nrhs > 1) {
+        // all columns at once: phi = A f batched, then block GMRES (or block refinement)
+        double* blk = nullptr;
+        if (hipMalloc(&blk, (size_t)3 * N * nrhs * sizeof(double)) != hipSuccess) {
+            (void)hipFree(extra);
+            record_error("ert_vie_solve: block workspace allocation failed");
+            return ERT_ENOMEM;
+        }
+        double* Phi = blk;
+        double* Rb = blk + (size_t)N * nrhs;
+        double* Db = blk + (size_t)2 * N * nrhs;
+        do {
+            if (so.rhs_is_phi)
+                st = ERT_HIPST(hipMemcpyAsync(Phi, f, sizeof(double) * N * nrhs, hipMemcpyDeviceToDevice, p->stream));
+            else
+                st = apply_dispatch(p, ERT_OP_G, method, prec_outer, f, Phi, nrhs);
+            if (st != ERT_OK) break;
+            inf.matvecs++;
+            int it = 0, cy = 0, mv = 0;
+            double est = 0.0, tr = 0.0;
+            bool conv = false;
+            if (!so.mixed) {
+                st = block_gmres(p, method, prec_outer, Phi, U, nrhs, so.tol, so.max_iter, so.restart, true, &it, &cy,
+                                 &mv, &est, &tr, &conv);
+                if (st != ERT_OK) break;
+                inf.iters = it;
+                inf.restarts = cy > 0 ? cy - 1 : 0;
+                inf.matvecs += mv;
+                inf.rel_resid_est = est;
+                inf.rel_resid_true = tr;
+                inf.converged = conv ? 1 : 0;
+            } else {
+                // block refinement: R = Phi - A64 U, inner block GMRES on the FP32 operator
+                st = dev_zero(p->stream, U, N * nrhs);
+                if (st != ERT_OK) break;
+                st = ERT_HIPST(hipMemcpyAsync(Rb, Phi, sizeof(double) * N * nrhs, hipMemcpyDeviceToDevice, p->stream));
+                if (st != ERT_OK) break;
+                std::vector<double> pn(nrhs), rn(nrhs);
+                st = ensure_workspace(p, 3 * N, (size_t)kPartials * 4 + 16);
+                if (st != ERT_OK) break;
+                double* dn = p->d_red + (size_t)kPartials * 4;
+                for (int b = 0; b < nrhs && st == ERT_OK; ++b) pn[b] = dev_norm(p, Phi + (size_t)b * N, p->d_red, dn, &st);
+                int used = 0;
+                double worst = 1.0;
+                for (int outer = 0; outer < 200 && st == ERT_OK; ++outer) {
+                    worst = 0.0;
+                    for (int b = 0; b < nrhs && st == ERT_OK; ++b) {
+                        rn[b] = dev_norm(p, Rb + (size_t)b * N, p->d_red, dn, &st);
+                        worst = std::max(worst, pn[b] > 0 ? rn[b] / pn[b] : 0.0);
+                    }
+                    inf.rel_resid_true = worst;
+                    if (worst <= so.tol) { inf.converged = 1; break; }
+                    if (used >= so.max_iter) break;
+                    st = block_gmres(p, method, prec_inner, Rb, Db, nrhs, so.inner_tol, so.max_iter - used, so.restart,
+                                     false, &it, &cy, &mv, &est, &tr, &conv);
+                    if (st != ERT_OK) break;
+                    used += it;
+                    inf.iters += it;
+                    inf.matvecs += mv;
+                    inf.rel_resid_est = est;
+                    st = dev_add(p->stream, U, Db, N * nrhs);
+                    if (st != ERT_OK) break;
+                    st = apply_dispatch(p, ERT_OP_A, method, ERT_FP64, U, Db, nrhs);
+                    if (st != ERT_OK) break;
+                    inf.matvecs++;
+                    st = dev_sub(p->stream, Rb, Phi, Db, N * nrhs);
+                    inf.restarts = outer + 1;
+                }
+            }
+            if (st == ERT_OK && !inf.converged) result = ERT_ENOCONV;
+        } while (0);
+        (void)hipStreamSynchronize(p->stream);
+        (void)hipFree(blk);
+        (void)hipFree(extra);
+        inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = inf;
+        return st != ERT_OK ? st : result;
+    }
     for (int c = 0; c < nrhs && st == ERT_OK; ++c) {
         std::memset(&inf, 0, sizeof(inf));
         const double* fc = f + (size_t)c * N;

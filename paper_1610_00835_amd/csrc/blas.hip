@@ -1,6 +1,8 @@
 // FP64 vector kernels for the Krylov solver (HBM-bound level-1/level-2 work).
 // Reductions are two-pass with a fixed block count and fixed order, so every
 // result is bitwise reproducible from run to run.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace ertvie {
@@ -164,6 +166,115 @@ ert_status dev_small_add(hipStream_t s, double* dst, const double* src, int n)
 {
     hipLaunchKernelGGL(k_add, dim3(nblocks(n)), dim3(kBlk), 0, s, dst, src, (long)n);
     ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+}  // namespace ertvie
+
+// ------------------------------------------------------------ level 3 ----
+// C = beta C + alpha A B with element strides (A(i,k) = A[i*sAi + k*sAk], ...).
+// 64 x 64 output tiles, 4 x 4 per thread, reduction chunks of 16 staged in LDS.
+// Long reductions (tall-skinny products) are split over gridDim.z slices whose
+// partial tiles go to a workspace and are summed in slice order (deterministic).
+namespace ertvie {
+namespace {
+
+struct DG {
+    int M, N;
+    long K;
+    double alpha, beta;
+    const double* A; long sAi, sAk;
+    const double* B; long sBk, sBj;
+    double* C; long sCi, sCj;
+    double* part;      // split-K workspace [nz][M][N] (row-major), or null
+    long kchunk;       // reduction length per slice
+};
+
+__global__ __launch_bounds__(256) void k_dgemm(DG g)
+{
+    __shared__ double As[16][65], Bs[16][65];
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const long klo = (long)blockIdx.z * g.kchunk;
+    const long khi = (klo + g.kchunk) < g.K ? (klo + g.kchunk) : g.K;
+    double acc[4][4] = {};
+    for (long k0 = klo; k0 < khi; k0 += 16) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int kk = e / 64, r = e % 64;
+            const long k = k0 + kk;
+            const int i = i0 + r, j = j0 + r;
+            As[kk][r] = (i < g.M && k < khi) ? g.A[i * g.sAi + k * g.sAk] : 0.0;
+            Bs[kk][r] = (j < g.N && k < khi) ? g.B[k * g.sBk + j * g.sBj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[kk][ty * 4 + u];
+                b[u] = Bs[kk][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+            if (i >= g.M || j >= g.N) continue;
+            if (g.part) {
+                g.part[((long)blockIdx.z * g.M + i) * g.N + j] = acc[u][v];
+            } else {
+                double* c = g.C + i * g.sCi + j * g.sCj;
+                *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * acc[u][v];
+            }
+        }
+}
+
+__global__ void k_dgemm_reduce(DG g, int nz)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= (long)g.M * g.N) return;
+    const int i = (int)(t / g.N), j = (int)(t % g.N);
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += g.part[((long)z * g.M + i) * g.N + j];
+    double* c = g.C + i * g.sCi + j * g.sCj;
+    *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * s;
+}
+
+}  // namespace
+
+ert_status dev_dgemm(hipStream_t s, int M, int N, long K, double alpha, const double* A, long sAi, long sAk,
+                     const double* B, long sBk, long sBj, double beta, double* C, long sCi, long sCj, double* work,
+                     size_t work_elems)
+{
+    if (M <= 0 || N <= 0) return ERT_OK;
+    DG g{M, N, K, alpha, beta, A, sAi, sAk, B, sBk, sBj, C, sCi, sCj, nullptr, K};
+    const long tiles = (long)((M + 63) / 64) * ((N + 63) / 64);
+    int nz = 1;
+    if (tiles < 256 && K > 4096 && work) {
+        nz = (int)std::min<long>(std::max<long>(1, 512 / tiles), (K + 4095) / 4096);
+        while (nz > 1 && (size_t)nz * M * N > work_elems) --nz;
+    }
+    if (nz > 1) {
+        g.part = work;
+        g.kchunk = ((K + nz - 1) / nz + 15) / 16 * 16;
+        nz = (int)((K + g.kchunk - 1) / g.kchunk);
+    }
+    dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64), (unsigned)nz);
+    hipLaunchKernelGGL(k_dgemm, grid, dim3(256), 0, s, g);
+    ERT_HIP(hipGetLastError());
+    if (nz > 1) {
+        const long n = (long)M * N;
+        hipLaunchKernelGGL(k_dgemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, nz);
+        ERT_HIP(hipGetLastError());
+    }
     return ERT_OK;
 }
 

@@ -204,6 +204,12 @@ ert_status dev_zero(hipStream_t s, double* y, long N);
 // dst[i] += src[i] for a small vector of length n (device)
 ert_status dev_small_add(hipStream_t s, double* dst, const double* src, int n);
 
+// C = beta C + alpha A B (FP64, element strides); `work` (may be null) lets long
+// reductions split over several workgroup slices.
+ert_status dev_dgemm(hipStream_t s, int M, int N, long K, double alpha, const double* A, long sAi, long sAk,
+                     const double* B, long sBk, long sBj, double beta, double* C, long sCi, long sCj, double* work,
+                     size_t work_elems);
+
 // Gauss-Legendre nodes/weights on [-1,1] (host).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 

@@ -37,7 +37,7 @@ class VieOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("mixed", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_is_phi", ctypes.c_int),
-                ("reserved", ctypes.c_int * 4)]
+                ("block", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -196,7 +196,7 @@ class Plan:
         return y
 
     def solve(self, f, U, tol=1e-8, max_iter=500, restart=0, mixed=False, inner_tol=1e-5, rhs_is_phi=False,
-              allow_noconv=False):
+              allow_noconv=False, block=False):
         fp, nf = _dev_ptr(f, self.N, "f")
         up, nu = _dev_ptr(U, self.N, "U")
         if nf != nu:
@@ -208,6 +208,7 @@ class Plan:
         so.mixed = 1 if mixed else 0
         so.inner_tol = float(inner_tol)
         so.rhs_is_phi = 1 if rhs_is_phi else 0
+        so.block = 1 if block else 0
         info = SolveInfo()
         st = load().ert_vie_solve(self.handle, fp, up, nf, ctypes.byref(so), ctypes.byref(info))
         out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}

@@ -86,3 +86,57 @@ def test_solve_multiple_rhs_columns(ev, oracle_mod):
     for b in range(3):
         Uo, _, _ = P.gmres(case["f"][:, b], tol=1e-12)
         assert rel_l2(Ug[:, b], Uo) <= 1e-9
+
+
+def test_block_gmres_direct_matches_oracle(ev, oracle_mod):
+    """Block GMRES over 6 face sources (one block Krylov space) equals the oracle per column."""
+    case = inputs.make_case("c4", n=(12, 12, 12), seed=0, nrhs=6)
+    P = oracle_problem(oracle_mod, case)
+    with ev.plan_from_case(case, method="direct", prec="fp64", nrhs_max=6) as plan:
+        Ug, ig = _solve(plan, case["f"], tol=1e-11, block=True)
+    log("block direct", ig)
+    assert ig["converged"] == 1 and ig["rel_resid_true"] <= 1e-11
+    for b in range(6):
+        Uo, _, _ = P.gmres(case["f"][:, b], tol=1e-12)
+        assert rel_l2(Ug[:, b], Uo) <= 1e-9
+
+
+def test_block_gmres_fmm_equals_column_solves(ev, oracle_mod):
+    """32^3 homogeneous, 8 right-hand sides: block GMRES on the FMM operator gives the same
+    solutions as the column-by-column solver on that operator, in fewer operator passes."""
+    case = inputs.make_case("c2", seed=0)
+    F = np.asfortranarray(np.stack([inputs.make_case("c2", seed=s)["f"] for s in range(8)], axis=1))
+    with ev.plan_from_case(case, method="fmm", prec="fp64", nrhs_max=8) as plan:
+        Ub, ib = _solve(plan, F, tol=1e-9, block=True)
+        Uc, ic = _solve(plan, F, tol=1e-9)
+    log("block fmm", ib, "columns (last)", ic)
+    assert ib["converged"] == 1
+    assert rel_l2(Ub, Uc) <= 1e-7
+
+
+def test_block_gmres_mixed(ev, oracle_mod):
+    """Block refinement: FP64 residual of all columns, inner block GMRES on the FP32 FMM."""
+    case = inputs.make_case("c2", seed=0)
+    F = np.asfortranarray(np.stack([inputs.make_case("c2", seed=s)["f"] for s in range(4)], axis=1))
+    with ev.plan_from_case(case, method="fmm", prec="fp64", nrhs_max=4) as plan:
+        Um, im = _solve(plan, F, tol=1e-9, block=True, mixed=True, inner_tol=1e-4)
+        U64, _ = _solve(plan, F, tol=1e-10, block=True)
+    log("block mixed", im)
+    assert im["converged"] == 1 and im["restarts"] >= 2
+    assert rel_l2(Um, U64) <= 1e-8
+
+
+def test_solve_fmm_mixed_c2(ev, oracle_mod):
+    """32^3: FP64 FMM outer residual with FP32 FMM inner solves, against the oracle's solve on sampled rows."""
+    case = inputs.make_case("c2", seed=0)
+    P = oracle_problem(oracle_mod, case)
+    with ev.plan_from_case(case, method="fmm", prec="fp64") as plan:
+        Ug, ig = _solve(plan, case["f"], tol=1e-9, mixed=True, inner_tol=1e-4)
+    assert ig["converged"] == 1
+    # the oracle's residual of the GPU solution on sampled rows: r = phi - (U - A S U)
+    rows = np.random.default_rng(5).choice(P.N, size=300, replace=False)
+    phi_rows = P.apply_rows(case["f"], rows, op=0)
+    au_rows = P.apply_rows(Ug, rows, op=2)
+    res = np.linalg.norm(phi_rows - au_rows) / np.linalg.norm(phi_rows)
+    log("c2 mixed fmm solve", ig, "oracle residual on rows", res)
+    assert res <= 1e-6
