@@ -1,12 +1,13 @@
-"""Benchmark: FMM matvec throughput of the isotropic-ERT volume-integral operator
-on one MI355X, plus time-to-solution, roofline fraction and the CPU oracle baseline.
+"""Benchmark: FMM matvec throughput of the isotropic-ERT volume-integral operator on one
+MI355X, with the dominant kernel's roofline fraction, time-to-solution and the CPU oracle.
 
 One step = one application of (I - K) u = u - A (sigma_s u) through the whole FMM
-(gather, near field, P2M, M2M, M2L, L2L, L2P, assembly) on the 3D unit cube
-32^3 workload (sigma_t = 5, sigma_s = 4, leaf 4^3 cells, n = 6 Chebyshev nodes per
-axis), inputs resident in HBM.  Prints one JSON line.
+(gather, near field, P2M, compress, M2L, reduce, decompress, L2P, assembly) on the 3D unit
+cube 32^3 workload (sigma_t = 5, sigma_s = 4, four seeded Gaussian sources), inputs resident
+in HBM, FP32 bulk with FP64 assembly.  Prints one JSON line on stdout (progress on stderr).
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--prec fp32|fp64|bf16x3]
+                  [--no-cpu-baseline] [--no-solve] [--no-c3]
 """
 import argparse
 import json
@@ -19,34 +20,70 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "bf16_mfma": 2.5e15, "hbm": 8.0e12}
+PEAK_FLOPS = {"fp32": 157.3e12, "fp64": 78.6e12, "bf16x3": 2.5e15 / 3.0}   # bf16x3: three bf16 MFMA products
+HBM = 8.0e12
+SZ = {"fp32": 4, "fp64": 8, "bf16x3": 4}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def m2l_flops_per_apply(tree_counts, K):
-    """Algorithmic M2L work: 2 K^2 multiply-adds per (target box, source box) pair."""
-    return 2.0 * K * K * sum(tree_counts)
+def timed_applies(torch, plan, x, y, op, steps, warmup, **kw):
+    for _ in range(warmup):
+        plan.apply(x, y, op=op, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(x, y, op=op, **kw)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
 
 
-def interaction_pairs(nb, D):
-    """Far-field (M2L) pair count per level for a full 2^L tree over nb^D leaves."""
-    L = int(np.ceil(np.log2(nb)))
-    out = []
+def stage_profile(plan, x, y, op, steps):
+    plan.profile(True)
+    for _ in range(steps):
+        plan.apply(x, y, op=op)
+    prof = plan.profile(False)
+    ms = {k: v[0] / steps for k, v in prof.items() if v[1]}
+    n = {k: v[1] / steps for k, v in prof.items() if v[1]}
+    return ms, n
+
+
+def roofline_of(info, stage_ms, launches, prec, dim=3):
+    """Roofline of the dominant box-offset product (M2L or near field) from its algorithmic work:
+    M2L: 2 R^2 flops per far pair, bytes = translation matrices (one per box offset) + multipoles in
+    + locals out; near: 2 flops per point pair, bytes = the 3^d near blocks + charges in + potentials out."""
+    sz = SZ[prec]
+    L = info["levels"]
+    noff = 7 ** dim - 3 ** dim
+    m2l_flops = m2l_bytes = 0.0
     for l in range(2, L + 1):
-        n = int(np.ceil(nb / 2 ** (L - l)))
-        idx = np.arange(n)
-        cnt = 0
-        # per axis: targets t, sources s with |t//2 - s//2| <= 1 and |t - s| > 1 in some axis
-        near1 = np.abs(idx[:, None] - idx[None, :]) <= 1
-        par1 = np.abs(idx[:, None] // 2 - idx[None, :] // 2) <= 1
-        pa = par1.sum()
-        nr = (near1 & par1).sum()
-        cnt = pa ** D - nr ** D
-        out.append(int(cnt))
-    return out
+        R = info["rank"][l] or info["nodes_padded"]
+        pairs = info["far_pairs"][l]
+        nbox = (info["leaf_boxes"] / 2 ** (dim * (L - l)))
+        m2l_flops += 2.0 * R * R * pairs
+        m2l_bytes += (min(noff, pairs) * R * R + 2.0 * nbox * R) * sz
+    S = info["leaf"] ** dim
+    near_flops = 2.0 * info["near_pairs"]
+    near_bytes = (3 ** dim * S * S + 2.0 * info["leaf_boxes"] * S) * (8 if prec == "fp64" else 4)
+    cand = {"m2l": (m2l_flops, m2l_bytes, stage_ms.get("m2l", 0.0), launches.get("m2l", 1.0), prec),
+            "near": (near_flops, near_bytes, stage_ms.get("near", 0.0), launches.get("near", 1.0),
+                     "fp64" if prec == "fp64" else "fp32")}
+    dom = max(cand, key=lambda k: cand[k][2])
+    flops, nbytes, tms, nl, kprec = cand[dom]
+    ai = flops / nbytes
+    ridge = PEAK_FLOPS[kprec] / HBM
+    t = tms / nl * 1e-3
+    if ai < ridge:
+        achieved, peak, unit, bound, per = nbytes / nl / t / 1e9, HBM / 1e9, "GB/s", "hbm", nbytes / nl
+    else:
+        achieved, peak, unit, bound, per = flops / nl / t / 1e12, PEAK_FLOPS[kprec] / 1e12, "TFLOP/s", "mfma", flops / nl
+    return {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": None, "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
+            "arith_intensity_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
+            "m2l_tflops": m2l_flops / (stage_ms["m2l"] * 1e-3) / 1e12 if stage_ms.get("m2l") else None,
+            "near_tflops": near_flops / (stage_ms["near"] * 1e-3) / 1e12 if stage_ms.get("near") else None}
 
 
 def main():
@@ -57,105 +94,117 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run three 256 MiB device copies (reference for memory-traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the work would shard by right-hand sides or Morton leaf ranges; see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (the work would shard by "
+              "right-hand sides or by Morton-contiguous leaf ranges).", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    from oracle import oracle as O
     from paper_1610_00835_amd import ertvie, inputs
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
     case = inputs.make_case("c2", seed=0)
     N = int(np.prod(case["n"]))
     f = torch.from_numpy(case["f"]).to(dev)
     y = torch.empty_like(f)
 
-    stream = torch.cuda.current_stream()
-    t_plan0 = time.perf_counter()
-    plan = ertvie.plan_from_case(case, method="fmm", prec=args.prec, stream=stream)
-    plan.apply(f, y, op=ertvie.OP_A)          # builds the FMM operators on first use
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t_plan0
-    log("plan + first apply: %.3f s" % t_plan)
+    if args.calibrate_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
-    for _ in range(args.warmup):
-        plan.apply(f, y, op=ertvie.OP_A)
+    t = time.perf_counter()
+    plan = ertvie.plan_from_case(case, method="fmm", prec=args.prec, stream=stream)
+    plan.apply(f, y, op=ertvie.OP_A)          # builds the FMM operators, tunes the execution forms
+    plan.apply(f, y, op=ertvie.OP_A)          # captures the apply graph
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.apply(f, y, op=ertvie.OP_A)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
+    t_plan = time.perf_counter() - t
+    log("plan + tuning + capture: %.3f s" % t_plan)
+
+    ms = timed_applies(torch, plan, f, y, ertvie.OP_A, args.steps, args.warmup)
     value = N / (ms * 1e-3) / 1e6
     log("FMM apply (%s): %.4f ms/step, %.1f Mpts/s" % (args.prec, ms, value))
+    yg = y.cpu().numpy()
 
-    # per-stage device time (events on the plan's stream), separate pass
-    plan.profile(True)
-    for _ in range(args.steps):
-        plan.apply(f, y, op=ertvie.OP_A)
-    prof = plan.profile(False)
-    stage_ms = {k: v[0] / args.steps for k, v in prof.items() if v[1]}
-    launches = {k: v[1] / args.steps for k, v in prof.items() if v[1]}
+    stage_ms, launches = stage_profile(plan, f, y, ertvie.OP_A, args.steps)
     log("per-apply stage ms:", json.dumps({k: round(v, 5) for k, v in stage_ms.items()}))
-
     info = plan.fmm_info()
+    info["leaf_boxes"] = int(np.prod([-(-n // info["leaf"]) for n in case["n"]]))
     log("fmm:", json.dumps(info))
-    # algorithmic work of the box-offset GEMMs: 2 R^2 per far pair (R = stored translation rank, or the
-    # padded node count when uncompressed); 2 per near point pair
-    L = info["levels"]
-    m2l_flops = sum(2.0 * (info["rank"][l] or info["nodes_padded"]) ** 2 * info["far_pairs"][l]
-                    for l in range(2, L + 1))
-    near_flops = 2.0 * info["near_pairs"]
-    peak = {"fp32": PEAK["fp32_mfma"], "fp64": PEAK["fp64_mfma"], "bf16x3": PEAK["bf16_mfma"]}[args.prec]
-    # the dominant kernel of the apply
-    cand = {"m2l": (m2l_flops, stage_ms.get("m2l", 0.0), launches.get("m2l", 1)),
-            "near": (near_flops, stage_ms.get("near", 0.0), launches.get("near", 1))}
-    dom = max(cand, key=lambda k: cand[k][1])
-    flops, tms, nl = cand[dom]
-    dpeak = peak if dom == "m2l" else {"fp64": PEAK["fp64_mfma"]}.get(args.prec, PEAK["fp32_mfma"])
-    achieved = (flops / nl) / (tms / nl * 1e-3) if tms > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": dpeak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / dpeak, "traffic": None,
-                "flops_per_launch": flops / nl, "launch_ms": tms / nl, "launches_per_apply": nl,
-                "m2l_tflops": (m2l_flops / (stage_ms["m2l"] * 1e-3) / 1e12) if stage_ms.get("m2l") else None,
-                "near_tflops": (near_flops / (stage_ms["near"] * 1e-3) / 1e12) if stage_ms.get("near") else None}
+    roofline = roofline_of(info, stage_ms, launches, args.prec)
+    log("roofline:", json.dumps(roofline))
 
-    # accuracy of this apply against the oracle on sampled rows
-    extra = {"plan_s": t_plan, "stage_ms": stage_ms}
-    from oracle import oracle as O
     P = O.Problem(3, case["n"], case["h"], 0, case["sigma_t"], case["sigma_s"])
     rows = np.random.default_rng(0).choice(N, size=256, replace=False)
     yo = P.apply_rows(case["f"], rows, op=2)
-    yg = y.cpu().numpy()
-    extra["rel_l2_vs_oracle_rows"] = float(np.linalg.norm(yg[rows] - yo) / np.linalg.norm(yo))
+    extra = {"plan_s": t_plan, "stage_ms": stage_ms, "fmm": info,
+             "rel_l2_vs_oracle_rows": float(np.linalg.norm(yg[rows] - yo) / np.linalg.norm(yo))}
 
-    if not args.no_solve:
-        # time to 1e-8: plain FP64 GMRES on the FP64 FMM operator vs FP32-inner refinement
-        U = torch.empty_like(f)
-        with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream) as p64:
-            p64.apply(f, y, op=ertvie.OP_A)
-            torch.cuda.synchronize()
+    # the same operator in the other precisions and by dense summation
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream) as p64:
+        p64.apply(f, y, op=ertvie.OP_A)
+        p64.apply(f, y, op=ertvie.OP_A)
+        extra["fp64_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, args.steps, 2)
+        y64 = y.cpu().numpy()
+        extra["fp64_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(y64[rows] - yo) / np.linalg.norm(yo))
+        p64.apply(f, y, op=ertvie.OP_A, prec="bf16x3")
+        extra["bf16x3_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, args.steps, 2, prec="bf16x3")
+        y16 = y.cpu().numpy()
+        extra["bf16x3_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(y16[rows] - yo) / np.linalg.norm(yo))
+        extra["direct_fp64_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, 2, 1, method="direct")
+        log("fp64 %.4f ms, bf16x3 %.4f ms, dense fp64 %.2f ms" % (extra["fp64_apply_ms"], extra["bf16x3_apply_ms"],
+                                                                  extra["direct_fp64_apply_ms"]))
+        if not args.no_solve:
+            U = torch.empty_like(f)
             t = time.perf_counter()
             i64 = p64.solve(f, U, tol=1e-8)
             t_fp64 = time.perf_counter() - t
             U64 = U.cpu().numpy()
-            plan_f = p64
-            p64.apply(f, y, op=ertvie.OP_A, prec="fp32")
-            torch.cuda.synchronize()
             t = time.perf_counter()
-            imx = plan_f.solve(f, U, tol=1e-8, mixed=True, inner_tol=1e-4)
+            imx = p64.solve(f, U, tol=1e-8, mixed=True, inner_tol=1e-4)
             t_mixed = time.perf_counter() - t
             Umx = U.cpu().numpy()
-        extra["solve"] = {"tol": 1e-8, "fp64_gmres_s": t_fp64, "fp64_iters": i64["iters"],
-                          "mixed_s": t_mixed, "mixed_inner_iters": imx["iters"], "mixed_refinements": imx["restarts"],
-                          "mixed_rel_resid_true": imx["rel_resid_true"],
-                          "mixed_vs_fp64_rel_l2": float(np.linalg.norm(Umx - U64) / np.linalg.norm(U64))}
-        log("solve:", json.dumps(extra["solve"]))
+            extra["solve"] = {"tol": 1e-8, "fp64_gmres_s": t_fp64, "fp64_iters": i64["iters"],
+                              "fp64_rel_resid_true": i64["rel_resid_true"], "mixed_s": t_mixed,
+                              "mixed_inner_iters": imx["iters"], "mixed_refinements": imx["restarts"],
+                              "mixed_rel_resid_true": imx["rel_resid_true"],
+                              "mixed_vs_fp64_rel_l2": float(np.linalg.norm(Umx - U64) / np.linalg.norm(U64))}
+            log("solve:", json.dumps(extra["solve"]))
+    plan.close()
+
+    if not args.no_c3:
+        # 64^3 heterogeneous blob medium with the ray-quadrature kernel (cached pair translations)
+        c3 = inputs.make_case("c3", seed=0)
+        N3 = int(np.prod(c3["n"]))
+        x3 = inputs.random_vector(N3, 11)
+        xd = torch.from_numpy(x3).to(dev)
+        yd = torch.empty_like(xd)
+        t = time.perf_counter()
+        with ertvie.plan_from_case(c3, method="fmm", prec="fp32", stream=stream) as p3:
+            p3.apply(xd, yd, op=ertvie.OP_A)
+            p3.apply(xd, yd, op=ertvie.OP_A)
+            torch.cuda.synchronize()
+            t3plan = time.perf_counter() - t
+            ms3 = timed_applies(torch, p3, xd, yd, ertvie.OP_A, 5, 1)
+            st3, _ = stage_profile(p3, xd, yd, ertvie.OP_A, 3)
+            y3 = yd.cpu().numpy()
+        P3 = O.Problem(3, c3["n"], c3["h"], 1, c3["sigma_t"], c3["sigma_s"])
+        r3 = np.random.default_rng(7).choice(N3, size=24, replace=False)
+        y3o = P3.apply_rows(x3, r3, op=2)
+        extra["c3_64cubed_heterogeneous"] = {
+            "plan_s": t3plan, "apply_ms": ms3, "mpts_per_s": N3 / (ms3 * 1e-3) / 1e6, "stage_ms": st3,
+            "rel_l2_vs_oracle_rows": float(np.linalg.norm(y3[r3] - y3o) / np.linalg.norm(y3o))}
+        log("c3:", json.dumps(extra["c3_64cubed_heterogeneous"]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -173,11 +222,10 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32"}[args.prec],
            "data": "synthetic",
-           "config": {"workload": "3D unit cube 32^3 (N=32768), homogeneous sigma_t=5 sigma_s=4, "
-                                  "4 seeded Gaussian sources; FMM leaf 8^3 cells, n=8, compressed translations",
+           "config": {"workload": "3D unit cube 32^3 (N=32768), homogeneous sigma_t=5 sigma_s=4, four seeded "
+                                  "Gaussian sources; FMM leaf 8^3 cells, n=8, translations compressed at 1e-6",
                       "op": "u - K(sigma_s u)", "prec": args.prec, "nrhs": 1},
            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

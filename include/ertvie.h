@@ -169,7 +169,8 @@ typedef enum {
     ERT_STAGE_ASSEMBLE = 7, /* scaling, self term, I - K */
     ERT_STAGE_DIRECT = 8,   /* dense apply */
     ERT_STAGE_BASIS = 9,    /* change of basis of the compressed translations */
-    ERT_NSTAGES = 10
+    ERT_STAGE_REDUCE = 10,  /* fixed-order sums of staged pair products (offset-stationary form) */
+    ERT_NSTAGES = 11
 } ert_stage;
 
 /* Shape of a plan's FMM for one precision (built on first use). */

@@ -141,6 +141,12 @@ struct StageTimer {
     {
         if (p && p->on) p->begin(s, stage, &ev0);
     }
+    // close the bracket now
+    void stop()
+    {
+        if (p && p->on && ev0) p->end(s, stage, ev0);
+        ev0 = nullptr;
+    }
     // drop the bracket (an inner bracket takes over)
     void pause()
     {

@@ -867,7 +867,8 @@ struct FmmImpl : FmmData {
         if (cap) (void)hipStreamDestroy(cap);
     }
 
-    ert_status run_site(ert_plan_impl* p, hipStream_t s, GemmSite& site, int gprec, const BoxGemm& g, int nrhs);
+    ert_status run_site(ert_plan_impl* p, hipStream_t s, GemmSite& site, int gprec, const BoxGemm& g, int nrhs,
+                        StageTimer* outer);
     ert_status enqueue(ert_plan_impl* p, hipStream_t s, int nrhs);
     void drop_graphs()
     {
@@ -1255,9 +1256,9 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
 // Run one box-offset product in the form chosen for this rhs bucket; the first
 // call of a bucket times both forms (into scratch) and keeps the faster one.
 template <typename T>
-ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs)
+ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs,
+                                StageTimer* outer)
 {
-    (void)p;
     auto as_offset = [&](const BoxGemm& b) {
         OffsetGemm o;
         o.nbox = b.nbox;
@@ -1300,7 +1301,11 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         gs.choice[bucket] = ms[1] < ms[0] ? 1 : 0;
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
-    return offset_gemm(s, gprec, as_offset(g));
+    const OffsetGemm og = as_offset(g);
+    ERT_TRY(offset_gemm_products(s, gprec, og));
+    if (outer) outer->stop();
+    StageTimer sr_(&p->prof, s, ERT_STAGE_REDUCE);
+    return offset_gemm_reduce(s, gprec, og);
 }
 
 template <typename T>
@@ -1319,6 +1324,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
     // a10: near field (writes pot)
     {
         StageTimer st_(pf, s, ERT_STAGE_NEAR);
+        StageTimer* near_timer = &st_;
         if (hetero) {
             hipLaunchKernelGGL(k_p2p_cached<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), tr.S * sizeof(T), s, dt, q,
                                nearblk, pot);
@@ -1333,7 +1339,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             g.W = q;
             g.L = pot;
             g.accumulate = 0;
-            ERT_TRY(run_site(p, s, near_site, dprec, g, nrhs));
+            ERT_TRY(run_site(p, s, near_site, dprec, g, nrhs, near_timer));
         } else {
             const int tpp = std::min(tr.S, kB);
             const int groups = kB / tpp;
@@ -1402,7 +1408,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                     BoxGemm g = gemm_desc(l, R, R, nrhs);       // translate
                     g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                     g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
-                    ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs));
+                    ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &sm_));
                 }
                 {
                     StageTimer sb_(pf, s, ERT_STAGE_BASIS);
@@ -1415,7 +1421,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 BoxGemm g = gemm_desc(l, tr.Kp, tr.Kp, nrhs);
                 g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                 g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = W[l]; g.L = Lc[l]; g.accumulate = first ? 0 : 1;
-                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs));
+                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &st_));
             }
         }
         // a9: L2P adds the far field

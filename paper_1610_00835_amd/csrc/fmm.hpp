@@ -92,7 +92,9 @@ struct OffsetGemm {
     PairTiles pl;
 };
 
-ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);
+ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);           // products + reduction
+ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g);  // staged products only
+ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    // per-target sums only
 
 // Heterogeneous far field: one cached matrix per (target, source) pair,
 // stored source-node major [pair][Kd][M], CSR over targets.
@@ -109,5 +111,27 @@ struct PairGemm {
 };
 
 ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& g);
+
+// Streaming form of cached-pair products (heterogeneous far field and near
+// field): one workgroup per pair streams its matrix once (16-byte loads along
+// the output rows, the reduction split between thread groups) for up to 8
+// right-hand sides at a time and writes a staging row; a second pass sums the
+// contiguous pairs of every target.
+struct PairStream {
+    long npairs;
+    long ntarget;
+    int B;
+    int M, Kd;
+    const void* opsT;        // [npairs][Kd][M] (output rows fastest)
+    const int* src;          // [npairs] source box (-1: empty pair)
+    long nsrc;               // source boxes (W is [B][nsrc][Kd])
+    const long* tstart;      // [ntarget + 1] contiguous pair range of each target
+    const void* W;
+    void* stage;             // [B][npairs][M]
+    void* L;                 // [B][ntarget][M]
+    int accumulate;
+};
+
+ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
 
 }  // namespace ertvie

@@ -21,6 +21,9 @@
 //
 // Heterogeneous media: every (target, source) pair has its own cached matrix;
 // the translation streams those matrices once per apply (HBM-bound).
+#include <algorithm>
+#include <type_traits>
+
 #include "fmm.hpp"
 
 namespace ertvie {
@@ -343,6 +346,111 @@ __global__ void k_stage_reduce(OffsetGemm g)
     *d = g.accumulate ? *d + s : s;
 }
 
+// ----------------------------------------------------- streaming pairs ----
+
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
+{
+    typedef typename std::conditional<sizeof(T) == 4, v4f, double2>::type V16;
+    constexpr int RPT = 16 / sizeof(T);            // output rows per thread (one 16-byte load)
+    extern __shared__ unsigned char smem[];
+    T* ws = (T*)smem;                              // [RB][Kd]
+    const long p = blockIdx.x;
+    const int nb = (g.B - b0) < RB ? (g.B - b0) : RB;
+    const int s = g.src[p];
+    const int rthreads = g.M / RPT;                // threads along the rows
+    const int kgroups = blockDim.x / rthreads;     // groups splitting the reduction
+    const int tr = threadIdx.x % rthreads, kg = threadIdx.x / rthreads;
+    for (int i = threadIdx.x; i < RB * g.Kd; i += blockDim.x) {
+        const int b = i / g.Kd, k = i - b * g.Kd;
+        ws[i] = (s >= 0 && b < nb) ? ((const T*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k] : T(0);
+    }
+    __syncthreads();
+    T acc[RB][RPT];
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) acc[b][e] = T(0);
+    if (s >= 0 && kg < kgroups) {
+        const int kchunk = (g.Kd + kgroups - 1) / kgroups;
+        const int k0 = kg * kchunk, k1 = (k0 + kchunk) < g.Kd ? (k0 + kchunk) : g.Kd;
+        const T* col = (const T*)g.opsT + (size_t)p * g.Kd * g.M + (size_t)tr * RPT;
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            V16 m[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m[u] = *(const V16*)(col + (size_t)(k + u) * g.M);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    const T w = ws[b * g.Kd + k + u];
+#pragma unroll
+                    for (int e = 0; e < RPT; ++e) acc[b][e] += m[u][e] * w;
+                }
+        }
+        for (; k < k1; ++k) {
+            const V16 m = *(const V16*)(col + (size_t)k * g.M);
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) acc[b][e] += m[e] * ws[b * g.Kd + k];
+        }
+    }
+    // combine the reduction groups in a fixed order through LDS (reusing ws)
+    __syncthreads();
+    T* red = ws;                                   // [kgroups][RB][M] fits in RB * Kd when kgroups * M <= Kd * ...
+    for (int kgi = 1; kgi < kgroups; ++kgi) {
+        if (kg == kgi) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) red[b * g.M + tr * RPT + e] = acc[b][e];
+        }
+        __syncthreads();
+        if (kg == 0) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) acc[b][e] += red[b * g.M + tr * RPT + e];
+        }
+        __syncthreads();
+    }
+    if (kg == 0) {
+        for (int b = 0; b < nb; ++b) {
+            T* d = (T*)g.stage + ((long)(b0 + b) * g.npairs + p) * g.M + tr * RPT;
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) d[e] = acc[b][e];
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_pair_reduce(PairStream g)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long per = g.ntarget * g.M;
+    if (i >= per * g.B) return;
+    const int b = (int)(i / per);
+    const long rem = i - (long)b * per;
+    const long t = rem / g.M;
+    const int r = (int)(rem - t * g.M);
+    const T* St = (const T*)g.stage + (long)b * g.npairs * g.M + r;
+    const long k1 = g.tstart[t + 1];
+    long k = g.tstart[t];
+    T sum = T(0);
+    for (; k + 8 <= k1; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = St[(k + u) * g.M];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; k < k1; ++k) sum += St[k * g.M];
+    T* d = (T*)g.L + i;
+    *d = g.accumulate ? *d + sum : sum;
+}
+
 // ------------------------------------------------- heterogeneous (cached) ----
 // One workgroup per (target box, block of right-hand sides).  Thread r owns
 // output row r; for each source in the target's list the source vectors of the
@@ -442,7 +550,7 @@ ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g)
     return ERT_OK;
 }
 
-ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
+ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
 {
     if (g.M % (16 * kTM) != 0 || g.Kd % 32 != 0) {
         record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
@@ -458,6 +566,11 @@ ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
             hipLaunchKernelGGL((k_offset_gemm<ERT_BF16X3, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);
         ERT_HIP(hipGetLastError());
     }
+    return ERT_OK;
+}
+
+ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g)
+{
     const long n = g.nbox * g.M * g.B;
     if (prec == ERT_FP64)
         hipLaunchKernelGGL(k_stage_reduce<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
@@ -465,6 +578,44 @@ ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
         hipLaunchKernelGGL(k_stage_reduce<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
+}
+
+ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
+{
+    ERT_TRY(offset_gemm_products(s, prec, g));
+    return offset_gemm_reduce(s, prec, g);
+}
+
+template <typename T>
+ert_status pair_stream_t(hipStream_t s, const PairStream& g)
+{
+    constexpr int RPT = 16 / sizeof(T);
+    if (g.M % RPT != 0 || g.M / RPT > 256) {
+        record_error("pair_stream: unsupported row count");
+        return ERT_EINVAL;
+    }
+    for (int b0 = 0; b0 < g.B; b0 += 8) {
+        const int left = g.B - b0;
+        const int rb = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
+        // LDS: the rhs block of the source vector and the group combination buffer
+        const size_t sh = std::max((size_t)rb * g.Kd, (size_t)rb * g.M) * sizeof(T);
+        dim3 grid((unsigned)g.npairs);
+        if (rb == 8) hipLaunchKernelGGL((k_pair_stream<T, 8>), grid, dim3(256), sh, s, g, b0);
+        else if (rb == 4) hipLaunchKernelGGL((k_pair_stream<T, 4>), grid, dim3(256), sh, s, g, b0);
+        else if (rb == 2) hipLaunchKernelGGL((k_pair_stream<T, 2>), grid, dim3(256), sh, s, g, b0);
+        else hipLaunchKernelGGL((k_pair_stream<T, 1>), grid, dim3(256), sh, s, g, b0);
+        ERT_HIP(hipGetLastError());
+        b0 += rb - 8;    // advance by the block actually processed
+    }
+    const long n = g.ntarget * g.M * g.B;
+    hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
+{
+    return prec == ERT_FP64 ? pair_stream_t<double>(s, g) : pair_stream_t<float>(s, g);
 }
 
 ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& a)

@@ -20,7 +20,7 @@ DIRECT, FMM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
 OP_G, OP_GS, OP_A = 0, 1, 2
 
-STAGES = ("gather", "near", "p2m", "m2m", "m2l", "l2l", "l2p", "assemble", "direct", "basis")
+STAGES = ("gather", "near", "p2m", "m2m", "m2l", "l2l", "l2p", "assemble", "direct", "basis", "reduce")
 NSTAGES = len(STAGES)
 
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
