@@ -50,7 +50,14 @@ def stage_profile(plan, x, y, op, steps):
     return ms, n
 
 
-def roofline_of(info, stage_ms, launches, prec, dim=3):
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counter runs,
+# scaled by the readings of a 256 MiB device copy (profiles/m2l_c2_32cubed_fp32_hbm_traffic.md).
+# Keyed by (workload, precision, kernel); a kernel changed since its counters were taken has
+# no entry, and reports null.
+MEASURED_TRAFFIC = {("c2", "fp32", "m2l"): 101.18e6}
+
+
+def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None):
     """Roofline of the dominant box-offset product (M2L or near field) from its algorithmic work:
     M2L: 2 R^2 flops per far pair, bytes = translation matrices (one per box offset) + multipoles in
     + locals out; near: 2 flops per point pair, bytes = the 3^d near blocks + charges in + potentials out."""
@@ -80,7 +87,7 @@ def roofline_of(info, stage_ms, launches, prec, dim=3):
     else:
         achieved, peak, unit, bound, per = flops / nl / t / 1e12, PEAK_FLOPS[kprec] / 1e12, "TFLOP/s", "mfma", flops / nl
     return {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": None, "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
+            "traffic": MEASURED_TRAFFIC.get((workload, prec, dom)), "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
             "arith_intensity_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
             "m2l_tflops": m2l_flops / (stage_ms["m2l"] * 1e-3) / 1e12 if stage_ms.get("m2l") else None,
             "near_tflops": near_flops / (stage_ms["near"] * 1e-3) / 1e12 if stage_ms.get("near") else None}
@@ -141,7 +148,7 @@ def main():
     info = plan.fmm_info()
     info["leaf_boxes"] = int(np.prod([-(-n // info["leaf"]) for n in case["n"]]))
     log("fmm:", json.dumps(info))
-    roofline = roofline_of(info, stage_ms, launches, args.prec)
+    roofline = roofline_of(info, stage_ms, launches, args.prec, workload="c2")
     log("roofline:", json.dumps(roofline))
 
     P = O.Problem(3, case["n"], case["h"], 0, case["sigma_t"], case["sigma_s"])

@@ -362,44 +362,6 @@ __global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__
     }
 }
 
-// Heterogeneous media: near-field kernel values cached per (target leaf,
-// neighbour position): blk[leaf][k][source i][target i] (target fastest).
-template <typename T>
-__global__ __launch_bounds__(kB) void k_p2p_cached(DevTree t, const T* __restrict__ q, const T* __restrict__ blk,
-                                                   T* __restrict__ pot)
-{
-    extern __shared__ unsigned char smem[];
-    T* sq = (T*)smem;                         // [S]
-    const long leafi = blockIdx.x;
-    const int b = blockIdx.y;
-    int lb[3];
-    unravel3(leafi, t.nb, lb);
-    const int nn = (t.D == 3) ? 27 : 9;
-    for (int tb = 0; tb < t.S; tb += blockDim.x) {
-        const int ti = tb + threadIdx.x;
-        T acc = T(0);
-        for (int k = 0; k < nn; ++k) {
-            int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, t.D == 3 ? k / 9 - 1 : 0};
-            int s[3];
-            bool ok = true;
-            for (int a = 0; a < 3; ++a) {
-                s[a] = lb[a] + ((a < t.D) ? o[a] : 0);
-                if (s[a] < 0 || s[a] >= t.nb[a]) ok = false;
-            }
-            if (!ok) continue;   // uniform
-            long sl = s[0] + (long)t.nb[0] * (s[1] + (long)t.nb[1] * s[2]);
-            __syncthreads();
-            for (int i = threadIdx.x; i < t.S; i += blockDim.x) sq[i] = q[(long)b * t.nslot + sl * t.S + i];
-            __syncthreads();
-            if (ti < t.S) {
-                const T* col = blk + ((size_t)leafi * nn + k) * t.S * t.S + ti;
-                for (int si = 0; si < t.S; ++si) acc += col[(size_t)si * t.S] * sq[si];
-            }
-        }
-        if (ti < t.S) pot[(long)b * t.nslot + leafi * t.S + ti] = acc;
-    }
-}
-
 // Cached near-field blocks for the ray kernel, FP64 arithmetic: the same rule
 // as the dense apply (exact integer step count, marched from the lower index).
 // blk points at the block of leaf leaf0.
@@ -833,7 +795,10 @@ struct FmmImpl : FmmData {
     T* nearops = nullptr;               // homogeneous near blocks [3^d][S][S]
     T* tab = nullptr;                   // homogeneous near table (S not a multiple of 32)
     int ntab = 0;
-    T* nearblk = nullptr;               // heterogeneous near cache
+    T* nearblk = nullptr;               // heterogeneous near cache [leaf][3^d][S][S]
+    int* near_src = nullptr;            // heterogeneous near pairs: source leaf of (leaf, neighbour), -1 outside
+    long* near_tstart = nullptr;        // [nleaf + 1]: 3^d pairs per leaf
+    long hnp[kMaxLevels + 1] = {};      // heterogeneous far pairs per level
     T* q = nullptr;
     T* pot = nullptr;
     T* W[kMaxLevels + 1] = {};
@@ -855,7 +820,7 @@ struct FmmImpl : FmmData {
     ~FmmImpl() override
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(nearblk); f(q); f(pot);
+        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(nearblk); f(near_src); f(near_tstart); f(q); f(pot);
         for (int l = 0; l <= kMaxLevels; ++l) {
             f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]); f(hops[l]); f(pstart[l]); f(psrc[l]);
             f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
@@ -1041,6 +1006,7 @@ ert_status FmmImpl<T>::setup_far_het(ert_plan_impl* p, int l)
     }
     start[tr.nbox[l]] = (long)src.size();
     const long np = (long)src.size();
+    hnp[l] = np;
     ERT_TRY(upload<long>(s, &pstart[l], start));
     ERT_TRY(upload<int>(s, &psrc[l], src));
     DevPtrs tmp;
@@ -1189,6 +1155,26 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
                                nearblk + (size_t)l0 * per);
             ERT_HIP(hipGetLastError());
         }
+        std::vector<int> src((size_t)tr.nleaf * nn);
+        std::vector<long> ts(tr.nleaf + 1);
+        for (long lf = 0; lf < tr.nleaf; ++lf) {
+            int lb[3];
+            unravel3(lf, tr.nb, lb);
+            ts[lf] = lf * nn;
+            for (int k = 0; k < nn; ++k) {
+                const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, tr.D == 3 ? k / 9 - 1 : 0};
+                int sb[3];
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    sb[a] = lb[a] + ((a < tr.D) ? o[a] : 0);
+                    if (sb[a] < 0 || sb[a] >= tr.nb[a]) ok = false;
+                }
+                src[(size_t)lf * nn + k] = ok ? (int)(sb[0] + (long)tr.nb[0] * (sb[1] + (long)tr.nb[1] * sb[2])) : -1;
+            }
+        }
+        ts[tr.nleaf] = tr.nleaf * nn;
+        ERT_TRY(upload<int>(s, &near_src, src));
+        ERT_TRY(upload<long>(s, &near_tstart, ts));
         for (int l = 2; l <= tr.L; ++l) ERT_TRY(setup_far_het(p, l));
     }
     ERT_HIP(hipStreamSynchronize(s));
@@ -1234,6 +1220,11 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
         return ERT_OK;
     };
     ERT_TRY(site_need(near_site, tr.nleaf, tr.S));
+    if (hetero) {
+        const size_t rb = (size_t)std::min(nrhs, 8);
+        st_need = std::max(st_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
+        for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hnp[l] * tr.Kp);
+    }
     for (int l = 2; l <= tr.L; ++l) ERT_TRY(site_need(far_site[l], tr.nbox[l], rp[l] > 0 ? rp[l] : tr.Kp));
     if (st_need > stage_elems) {
         if (stage) (void)hipFree(stage);
@@ -1326,9 +1317,20 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         StageTimer st_(pf, s, ERT_STAGE_NEAR);
         StageTimer* near_timer = &st_;
         if (hetero) {
-            hipLaunchKernelGGL(k_p2p_cached<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), tr.S * sizeof(T), s, dt, q,
-                               nearblk, pot);
-            ERT_HIP(hipGetLastError());
+            PairStream a;
+            a.npairs = tr.nleaf * nn;
+            a.ntarget = tr.nleaf;
+            a.B = nrhs;
+            a.M = a.Kd = tr.S;
+            a.opsT = nearblk;
+            a.src = near_src;
+            a.nsrc = tr.nleaf;
+            a.tstart = near_tstart;
+            a.W = q;
+            a.stage = stage;
+            a.L = pot;
+            a.accumulate = 0;
+            ERT_TRY(pair_stream(s, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
         } else if (nearops) {
             BoxGemm g = gemm_desc(tr.L, tr.S, tr.S, nrhs);
             g.stride = 1;
@@ -1382,17 +1384,20 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             }
             StageTimer st_(pf, s, ERT_STAGE_M2L);
             if (hetero) {
-                PairGemm a;
-                a.nbox = tr.nbox[l];
+                PairStream a;
+                a.npairs = hnp[l];
+                a.ntarget = tr.nbox[l];
                 a.B = nrhs;
                 a.M = a.Kd = tr.Kp;
-                a.pair_start = pstart[l];
-                a.pair_src = psrc[l];
                 a.opsT = hops[l];
+                a.src = psrc[l];
+                a.nsrc = tr.nbox[l];
+                a.tstart = pstart[l];
                 a.W = W[l];
+                a.stage = stage;
                 a.L = Lc[l];
                 a.accumulate = first ? 0 : 1;
-                ERT_TRY(pair_gemm(s, prec, a));
+                ERT_TRY(pair_stream(s, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
             } else if (rp[l] > 0) {
                 const int R = rp[l];
                 st_.pause();

@@ -96,27 +96,12 @@ ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);           
 ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g);  // staged products only
 ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    // per-target sums only
 
-// Heterogeneous far field: one cached matrix per (target, source) pair,
-// stored source-node major [pair][Kd][M], CSR over targets.
-struct PairGemm {
-    long nbox;
-    int B;
-    int M, Kd;
-    const long* pair_start;
-    const int* pair_src;
-    const void* opsT;
-    const void* W;   // [B][nbox][Kd]
-    void* L;         // [B][nbox][M]
-    int accumulate;  // 1: L += result, 0: L = result
-};
-
-ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& g);
-
 // Streaming form of cached-pair products (heterogeneous far field and near
 // field): one workgroup per pair streams its matrix once (16-byte loads along
 // the output rows, the reduction split between thread groups) for up to 8
 // right-hand sides at a time and writes a staging row; a second pass sums the
-// contiguous pairs of every target.
+// contiguous pairs of every target in a fixed order.  The staging buffer holds
+// 8 right-hand sides (min(B, 8) x npairs x M elements).
 struct PairStream {
     long npairs;
     long ntarget;
@@ -127,7 +112,7 @@ struct PairStream {
     long nsrc;               // source boxes (W is [B][nsrc][Kd])
     const long* tstart;      // [ntarget + 1] contiguous pair range of each target
     const void* W;
-    void* stage;             // [B][npairs][M]
+    void* stage;             // [min(B,8)][npairs][M]
     void* L;                 // [B][ntarget][M]
     int accumulate;
 };

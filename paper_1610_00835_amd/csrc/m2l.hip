@@ -31,6 +31,7 @@ namespace ertvie {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
@@ -348,89 +349,127 @@ __global__ void k_stage_reduce(OffsetGemm g)
 
 // ----------------------------------------------------- streaming pairs ----
 
-template <typename T, int RB>
+template <typename T, int RPT>
+__device__ __forceinline__ void load_rows(const T* p, T (&o)[RPT])
+{
+    if constexpr (RPT == 4 && sizeof(T) == 4) {
+        const v4f v = *(const v4f*)p;
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+    } else if constexpr (RPT == 2 && sizeof(T) == 8) {
+        const v2d v = *(const v2d*)p;
+        o[0] = v[0]; o[1] = v[1];
+    } else {
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) o[e] = p[e];
+    }
+}
+
+template <typename T, int RPT>
+__device__ __forceinline__ void store_rows(T* p, const T (&o)[RPT])
+{
+    if constexpr (RPT == 4 && sizeof(T) == 4) {
+        v4f v;
+        v[0] = o[0]; v[1] = o[1]; v[2] = o[2]; v[3] = o[3];
+        *(v4f*)p = v;
+    } else if constexpr (RPT == 2 && sizeof(T) == 8) {
+        v2d v;
+        v[0] = o[0]; v[1] = o[1];
+        *(v2d*)p = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) p[e] = o[e];
+    }
+}
+
+// One workgroup (256 threads) per pair.  Each thread owns RPT consecutive
+// output rows (one 16-byte load per matrix row when the row count allows);
+// when the rows need fewer than 256 threads the reduction dimension is split
+// between thread groups, whose partial sums are combined in a fixed order.
+template <typename T, int RB, int RPT>
 __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
 {
-    typedef typename std::conditional<sizeof(T) == 4, v4f, double2>::type V16;
-    constexpr int RPT = 16 / sizeof(T);            // output rows per thread (one 16-byte load)
     extern __shared__ unsigned char smem[];
-    T* ws = (T*)smem;                              // [RB][Kd]
+    T* ws = (T*)smem;                              // [RB][Kd] source vectors
+    T* red = ws + RB * g.Kd;                       // [RB][M] group sums (only when the reduction is split)
     const long p = blockIdx.x;
     const int nb = (g.B - b0) < RB ? (g.B - b0) : RB;
     const int s = g.src[p];
-    const int rthreads = g.M / RPT;                // threads along the rows
-    const int kgroups = blockDim.x / rthreads;     // groups splitting the reduction
-    const int tr = threadIdx.x % rthreads, kg = threadIdx.x / rthreads;
+    const int rows = g.M / RPT;                    // row groups of RPT rows
+    const int rt = rows < 256 ? rows : 256;        // threads along the rows per chunk
+    const int kgroups = 256 / rt;
+    const int tr = threadIdx.x % rt, kg = threadIdx.x / rt;
     for (int i = threadIdx.x; i < RB * g.Kd; i += blockDim.x) {
         const int b = i / g.Kd, k = i - b * g.Kd;
         ws[i] = (s >= 0 && b < nb) ? ((const T*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k] : T(0);
     }
     __syncthreads();
-    T acc[RB][RPT];
+    const int kchunk = (g.Kd + kgroups - 1) / kgroups;
+    const int k0 = kg * kchunk, k1 = (k0 + kchunk) < g.Kd ? (k0 + kchunk) : g.Kd;
+    for (int rc = 0; rc < rows; rc += rt) {        // uniform over the workgroup
+        const int rg = rc + tr;
+        const bool act = s >= 0 && kg < kgroups && rg < rows;
+        T acc[RB][RPT];
 #pragma unroll
-    for (int b = 0; b < RB; ++b)
+        for (int b = 0; b < RB; ++b)
 #pragma unroll
-        for (int e = 0; e < RPT; ++e) acc[b][e] = T(0);
-    if (s >= 0 && kg < kgroups) {
-        const int kchunk = (g.Kd + kgroups - 1) / kgroups;
-        const int k0 = kg * kchunk, k1 = (k0 + kchunk) < g.Kd ? (k0 + kchunk) : g.Kd;
-        const T* col = (const T*)g.opsT + (size_t)p * g.Kd * g.M + (size_t)tr * RPT;
-        int k = k0;
-        for (; k + 8 <= k1; k += 8) {
-            V16 m[8];
+            for (int e = 0; e < RPT; ++e) acc[b][e] = T(0);
+        if (act) {
+            const T* col = (const T*)g.opsT + (size_t)p * g.Kd * g.M + (size_t)rg * RPT;
+            int k = k0;
+            for (; k + 8 <= k1; k += 8) {
+                T m[8][RPT];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) m[u] = *(const V16*)(col + (size_t)(k + u) * g.M);
+                for (int u = 0; u < 8; ++u) load_rows<T, RPT>(col + (size_t)(k + u) * g.M, m[u]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int b = 0; b < RB; ++b) {
-                    const T w = ws[b * g.Kd + k + u];
+                    for (int b = 0; b < RB; ++b) {
+                        const T w = ws[b * g.Kd + k + u];
 #pragma unroll
-                    for (int e = 0; e < RPT; ++e) acc[b][e] += m[u][e] * w;
-                }
+                        for (int e = 0; e < RPT; ++e) acc[b][e] += m[u][e] * w;
+                    }
+            }
+            for (; k < k1; ++k) {
+                T m[RPT];
+                load_rows<T, RPT>(col + (size_t)k * g.M, m);
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+#pragma unroll
+                    for (int e = 0; e < RPT; ++e) acc[b][e] += m[e] * ws[b * g.Kd + k];
+            }
         }
-        for (; k < k1; ++k) {
-            const V16 m = *(const V16*)(col + (size_t)k * g.M);
+        // kgroups > 1 only when all rows fit one chunk (rows < 256)
+        for (int kgi = 1; kgi < kgroups; ++kgi) {
+            if (kg == kgi && rg < rows) {
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+#pragma unroll
+                    for (int e = 0; e < RPT; ++e) red[b * g.M + rg * RPT + e] = acc[b][e];
+            }
+            __syncthreads();
+            if (kg == 0 && rg < rows) {
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+#pragma unroll
+                    for (int e = 0; e < RPT; ++e) acc[b][e] += red[b * g.M + rg * RPT + e];
+            }
+            __syncthreads();
+        }
+        if (kg == 0 && rg < rows) {
 #pragma unroll
             for (int b = 0; b < RB; ++b)
-#pragma unroll
-                for (int e = 0; e < RPT; ++e) acc[b][e] += m[e] * ws[b * g.Kd + k];
-        }
-    }
-    // combine the reduction groups in a fixed order through LDS (reusing ws)
-    __syncthreads();
-    T* red = ws;                                   // [kgroups][RB][M] fits in RB * Kd when kgroups * M <= Kd * ...
-    for (int kgi = 1; kgi < kgroups; ++kgi) {
-        if (kg == kgi) {
-#pragma unroll
-            for (int b = 0; b < RB; ++b)
-#pragma unroll
-                for (int e = 0; e < RPT; ++e) red[b * g.M + tr * RPT + e] = acc[b][e];
-        }
-        __syncthreads();
-        if (kg == 0) {
-#pragma unroll
-            for (int b = 0; b < RB; ++b)
-#pragma unroll
-                for (int e = 0; e < RPT; ++e) acc[b][e] += red[b * g.M + tr * RPT + e];
-        }
-        __syncthreads();
-    }
-    if (kg == 0) {
-        for (int b = 0; b < nb; ++b) {
-            T* d = (T*)g.stage + ((long)(b0 + b) * g.npairs + p) * g.M + tr * RPT;
-#pragma unroll
-            for (int e = 0; e < RPT; ++e) d[e] = acc[b][e];
+                if (b < nb) store_rows<T, RPT>((T*)g.stage + ((long)b * g.npairs + p) * g.M + rg * RPT, acc[b]);
         }
     }
 }
 
+// Sum of the contiguous staging rows of every target, for rhs b0..b0+nb-1.
 template <typename T>
-__global__ void k_pair_reduce(PairStream g)
+__global__ void k_pair_reduce(PairStream g, int b0, int nb)
 {
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long per = g.ntarget * g.M;
-    if (i >= per * g.B) return;
+    if (i >= per * nb) return;
     const int b = (int)(i / per);
     const long rem = i - (long)b * per;
     const long t = rem / g.M;
@@ -447,59 +486,8 @@ __global__ void k_pair_reduce(PairStream g)
         for (int u = 0; u < 8; ++u) sum += v[u];
     }
     for (; k < k1; ++k) sum += St[k * g.M];
-    T* d = (T*)g.L + i;
+    T* d = (T*)g.L + (long)(b0 + b) * per + rem;
     *d = g.accumulate ? *d + sum : sum;
-}
-
-// ------------------------------------------------- heterogeneous (cached) ----
-// One workgroup per (target box, block of right-hand sides).  Thread r owns
-// output row r; for each source in the target's list the source vectors of the
-// RHS block are staged in LDS and the cached matrix (stored source-node major,
-// so consecutive threads read consecutive rows) is streamed once.
-
-template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_pair_gemm(PairGemm a)
-{
-    extern __shared__ unsigned char smem[];
-    T* ws = (T*)smem;                      // [RB][Kd]
-    const long t = blockIdx.x;
-    const int b0 = blockIdx.y * RB;
-    const int nb = (a.B - b0) < RB ? (a.B - b0) : RB;
-    const T* W = (const T*)a.W;
-    const T* opsT = (const T*)a.opsT;
-    T* Lo = (T*)a.L;
-    const long p0 = a.pair_start[t], p1 = a.pair_start[t + 1];
-    for (int r0 = 0; r0 < a.M; r0 += 256) {
-        const int r = r0 + threadIdx.x;
-        T acc[RB];
-#pragma unroll
-        for (int b = 0; b < RB; ++b) acc[b] = T(0);
-        for (long p = p0; p < p1; ++p) {
-            const long s = a.pair_src[p];
-            __syncthreads();
-            for (int i = threadIdx.x; i < RB * a.Kd; i += 256) {
-                int b = i / a.Kd, k = i - b * a.Kd;
-                ws[i] = (b < nb) ? W[((long)(b0 + b) * a.nbox + s) * a.Kd + k] : T(0);
-            }
-            __syncthreads();
-            if (r < a.M) {
-                const T* col = opsT + (size_t)p * a.M * a.Kd + r;
-                for (int k = 0; k < a.Kd; ++k) {
-                    const T m = col[(size_t)k * a.M];
-#pragma unroll
-                    for (int b = 0; b < RB; ++b) acc[b] += m * ws[b * a.Kd + k];
-                }
-            }
-        }
-        if (r < a.M) {
-#pragma unroll
-            for (int b = 0; b < RB; ++b)
-                if (b < nb) {
-                    T* d = Lo + ((long)(b0 + b) * a.nbox + t) * a.M + r;
-                    *d = a.accumulate ? *d + acc[b] : acc[b];
-                }
-        }
-    }
 }
 
 constexpr int kTM = 2, kTN = 2;
@@ -586,55 +574,45 @@ ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
     return offset_gemm_reduce(s, prec, g);
 }
 
+template <typename T, int RPT>
+void launch_pair_stream(hipStream_t s, const PairStream& g, int b0, int rb)
+{
+    const int rows = g.M / RPT;
+    const size_t sh = (size_t)rb * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T);
+    const dim3 grid((unsigned)g.npairs);
+    if (rb == 8) hipLaunchKernelGGL((k_pair_stream<T, 8, RPT>), grid, dim3(256), sh, s, g, b0);
+    else if (rb == 4) hipLaunchKernelGGL((k_pair_stream<T, 4, RPT>), grid, dim3(256), sh, s, g, b0);
+    else if (rb == 2) hipLaunchKernelGGL((k_pair_stream<T, 2, RPT>), grid, dim3(256), sh, s, g, b0);
+    else hipLaunchKernelGGL((k_pair_stream<T, 1, RPT>), grid, dim3(256), sh, s, g, b0);
+}
+
 template <typename T>
 ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 {
-    constexpr int RPT = 16 / sizeof(T);
-    if (g.M % RPT != 0 || g.M / RPT > 256) {
-        record_error("pair_stream: unsupported row count");
+    constexpr int VEC = 16 / sizeof(T);
+    const int rows = g.M % VEC == 0 ? g.M / VEC : g.M;
+    if (g.M < 1 || g.Kd < 1 || (size_t)8 * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T) > 64 * 1024) {
+        record_error("pair_stream: unsupported operator shape");
         return ERT_EINVAL;
     }
-    for (int b0 = 0; b0 < g.B; b0 += 8) {
+    if (g.npairs < 1 || g.B < 1) return ERT_OK;
+    for (int b0 = 0; b0 < g.B;) {
         const int left = g.B - b0;
         const int rb = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
-        // LDS: the rhs block of the source vector and the group combination buffer
-        const size_t sh = std::max((size_t)rb * g.Kd, (size_t)rb * g.M) * sizeof(T);
-        dim3 grid((unsigned)g.npairs);
-        if (rb == 8) hipLaunchKernelGGL((k_pair_stream<T, 8>), grid, dim3(256), sh, s, g, b0);
-        else if (rb == 4) hipLaunchKernelGGL((k_pair_stream<T, 4>), grid, dim3(256), sh, s, g, b0);
-        else if (rb == 2) hipLaunchKernelGGL((k_pair_stream<T, 2>), grid, dim3(256), sh, s, g, b0);
-        else hipLaunchKernelGGL((k_pair_stream<T, 1>), grid, dim3(256), sh, s, g, b0);
+        if (g.M % VEC == 0) launch_pair_stream<T, VEC>(s, g, b0, rb);
+        else launch_pair_stream<T, 1>(s, g, b0, rb);
         ERT_HIP(hipGetLastError());
-        b0 += rb - 8;    // advance by the block actually processed
+        const long n = g.ntarget * g.M * rb;
+        hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, rb);
+        ERT_HIP(hipGetLastError());
+        b0 += rb;
     }
-    const long n = g.ntarget * g.M * g.B;
-    hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
-    ERT_HIP(hipGetLastError());
     return ERT_OK;
 }
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
 {
     return prec == ERT_FP64 ? pair_stream_t<double>(s, g) : pair_stream_t<float>(s, g);
-}
-
-ert_status pair_gemm(hipStream_t s, int prec, const PairGemm& a)
-{
-    const int rb = a.B >= 8 ? 8 : (a.B >= 4 ? 4 : 1);
-    dim3 grid((unsigned)a.nbox, (unsigned)((a.B + rb - 1) / rb));
-    if (prec == ERT_FP64) {
-        size_t sh = (size_t)rb * a.Kd * sizeof(double);
-        if (rb == 8) hipLaunchKernelGGL((k_pair_gemm<double, 8>), grid, dim3(256), sh, s, a);
-        else if (rb == 4) hipLaunchKernelGGL((k_pair_gemm<double, 4>), grid, dim3(256), sh, s, a);
-        else hipLaunchKernelGGL((k_pair_gemm<double, 1>), grid, dim3(256), sh, s, a);
-    } else {
-        size_t sh = (size_t)rb * a.Kd * sizeof(float);
-        if (rb == 8) hipLaunchKernelGGL((k_pair_gemm<float, 8>), grid, dim3(256), sh, s, a);
-        else if (rb == 4) hipLaunchKernelGGL((k_pair_gemm<float, 4>), grid, dim3(256), sh, s, a);
-        else hipLaunchKernelGGL((k_pair_gemm<float, 1>), grid, dim3(256), sh, s, a);
-    }
-    ERT_HIP(hipGetLastError());
-    return ERT_OK;
 }
 
 }  // namespace ertvie

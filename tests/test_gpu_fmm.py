@@ -191,3 +191,58 @@ def test_fmm_compression_tolerance(ev, oracle_mod, svd_tol):
         info = plan.fmm_info()
     log("svd_tol", svd_tol, "rank", info["rank"], "rel L2", err)
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("n,leaf,prec", [((12, 10, 9), 3, "fp32"), ((12, 10, 9), 3, "fp64"),
+                                         ((20, 17, 6), 5, "fp32")])
+def test_fmm_heterogeneous_odd_leaf(ev, oracle_mod, n, leaf, prec):
+    """Cached near blocks and per-pair translations with leaf sizes whose cell count is not a
+    multiple of the 16-byte row group (27 and 125 cells per leaf): scalar row loads, the
+    reduction split between thread groups, ragged box lattices.  Bar 2e-5: on grids this small
+    the far pairs take as few as 12 ray steps and the jumps of the step count with the segment
+    length set the interpolation floor (1.49e-5 measured at 12 x 10 x 9, the same in FP64 and
+    FP32); it falls as the grid grows (2.6e-7 at 64^3)."""
+    case = inputs.make_case("c3", n=n, seed=5)
+    P = oracle_problem(oracle_mod, case)
+    x = inputs.random_vector(P.N, 12)
+    ref = P.apply(x, op=2)
+    with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf) as plan:
+        info = plan.fmm_info()
+        err = rel_l2(gpu_apply(plan, x, ev.OP_A), ref)
+    log("heterogeneous odd leaf", n, leaf, prec, "rel L2", err, info)
+    assert sum(info["far_pairs"]) > 0
+    assert err <= 2e-5
+
+
+def test_fmm_heterogeneous_2d(ev, oracle_mod):
+    """2D ray-quadrature kernel through a smooth medium (varying sigma_t), 40 x 33 cells."""
+    n = (40, 33)
+    h = 1.0 / 40
+    x = inputs.centres(n, h)
+    st = 1.5 + 6.0 * np.exp(-((x[:, 0] - 0.4) ** 2 + (x[:, 1] - 0.55) ** 2) / (2 * 0.15 ** 2))
+    case = {"name": "het2d", "dim": 2, "n": n, "h": h, "kernel": inputs.KERNEL_RAY,
+            "sigma_t": st, "sigma_s": 0.8 * st, "f": np.zeros(len(st))}
+    P = oracle_problem(oracle_mod, case)
+    v = inputs.random_vector(P.N, 13)
+    ref = P.apply(v, op=2)
+    for prec in ("fp64", "fp32"):
+        with ev.plan_from_case(case, method="fmm", prec=prec, leaf=4) as plan:
+            err = rel_l2(gpu_apply(plan, v, ev.OP_A), ref)
+        log("heterogeneous 2d", prec, "rel L2", err)
+        assert err <= 1e-5
+
+
+def test_fmm_heterogeneous_many_rhs(ev, oracle_mod):
+    """11 right-hand sides (rhs blocks of 8, 2 and 1 in the streaming products): every column
+    equals its single-column apply, and the batch equals the oracle (bar 2e-5 as for the other
+    small heterogeneous grids; 1.01e-5 measured)."""
+    case = inputs.make_case("c3", n=(16, 16, 16), seed=6)
+    P = oracle_problem(oracle_mod, case)
+    X = inputs.random_vector(P.N, 14, nrhs=11)
+    with ev.plan_from_case(case, method="fmm", prec="fp32", leaf=4, nrhs_max=11) as plan:
+        Y = gpu_apply(plan, X, ev.OP_A)
+        for b in (0, 7, 8, 10):
+            yb = gpu_apply(plan, X[:, b], ev.OP_A)
+            assert np.max(np.abs(yb - Y[:, b])) <= 1e-12 * np.max(np.abs(yb))
+    for b in (0, 9):
+        assert rel_l2(Y[:, b], P.apply(X[:, b], op=2)) <= 2e-5
