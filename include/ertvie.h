@@ -48,6 +48,7 @@ extern "C" {
 #endif
 
 typedef struct ert_vie_plan_s* ert_vie_plan_t;
+typedef struct ert_net_s* ert_net_t;      /* learned preconditioner (see the end of this file) */
 
 typedef enum {
     ERT_OK = 0,
@@ -113,7 +114,21 @@ typedef struct {
     int rhs_is_phi;   /* 1: the f argument already holds phi (skip step S.1) */
     int block;        /* 1: block GMRES -- the nrhs columns share one block Krylov space and
                          every operator application is one batched apply (0: column by column) */
-    int reserved[3];  /* must be 0 */
+    int precond_steps;/* with precond: Arnoldi steps per preconditioned correction; 0 -> 10 */
+    int history_max;  /* columns of `history` (0: no history) */
+    int reserved[1];  /* must be 0 */
+    ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
+                         becomes a refinement loop.  Each step solves (I - K) d = r by flexible
+                         GMRES with z = net(v) (inner operator: FP32 with `mixed`, else the
+                         plan's), and is kept only if the true residual phi - (I - K)(U + d)
+                         of the outer operator (FP64 with `mixed`, else the plan's) is smaller
+                         than before; otherwise plain GMRES with the same budget replaces it.
+                         Not combined with `block`. */
+    double* history;  /* NULL, or DEVICE N x 2 history_max FP64: the plain solve (no mixed,
+                         block or precond) of the first column stores, at the start of every
+                         GMRES cycle k < history_max, the iterate U_k in column 2k and its
+                         residual phi - (I - K) U_k in column 2k + 1 (training pairs for the
+                         preconditioner: the correction of U_k is U - U_k) */
 } ert_solve_opts;
 
 typedef struct {
@@ -124,6 +139,9 @@ typedef struct {
     double rel_resid_est; /* last Arnoldi estimate */
     double rel_resid_true;/* ||phi - (I - K) U|| / ||phi|| with the plan's operator */
     double t_solve;       /* seconds, host wall clock, phi included */
+    int rejected;         /* preconditioned corrections rejected by the residual check */
+    int precond_applies;  /* network applications */
+    int history_count;    /* (iterate, residual) pairs written to opts->history */
 } ert_solve_info;
 
 /* Build a plan: validate and copy the media, place the collocation grid and
@@ -212,6 +230,89 @@ ERT_API const char* ert_vie_last_error(void);
 
 /* Static, human-readable text for a status code. */
 ERT_API const char* ert_vie_strerror(ert_status status);
+
+
+/* ------------------------------------------------------------------------
+ * Learned right preconditioner (not part of the paper's method).
+ *
+ * A three-level 3D convolutional U-Net maps a residual r of (I - K) U = phi and
+ * the medium to an approximate correction e ~ (I - K)^{-1} r; the solver uses it
+ * as a right preconditioner of flexible GMRES (ert_solve_opts.precond).
+ *
+ * Input channels per cell: r / s (s = root mean square of r), log sigma_t,
+ * sigma_s / sigma_t.  Output: z = r + s y with y the network value: the identity
+ * part of the correction passes through exactly and the network supplies
+ * e - r = K e, the part the transport operator produces.
+ * Layers (w1, w2, w3 = width[0..2], default 16, 32, 64):
+ *   L1 3x3x3 3 -> w1, ReLU; L2 w1 -> w1, ReLU (= s1); 2x2x2 average pool;
+ *   L3 w1 -> w2, ReLU; L4 w2 -> w2, ReLU (= s2); pool;
+ *   L5 w2 -> w3, ReLU; L6 w3 -> w3, ReLU; nearest 2x upsampling, concatenate
+ *   [upsampled, s2]; L7 (w3 + w2) -> w2, ReLU; L8 w2 -> w2, ReLU; upsample,
+ *   concatenate [upsampled, s1]; L9 (w2 + w1) -> w1, ReLU; L10 w1 -> w1, ReLU;
+ *   L11 1x1x1 w1 -> 1.
+ * 3x3x3 layers are cross-correlations with zero padding:
+ *   out[o](z,y,x) = b[o] + sum_{i,a,c,d} W[o][i][a][c][d] in[i](z+a-1, y+c-1, x+d-1).
+ * Parameters: one FP32 vector, layer by layer, W as [cout][cin][k][k][k] then
+ * b[cout] (ert_net_param_count entries).
+ * Arithmetic: 3x3x3 convolutions and their input gradients take BF16 weights
+ * (round to nearest even) times activations split into two BF16 parts
+ * (hi = bf16(x), lo = bf16(x - hi)) and accumulate in FP32; weight gradients,
+ * the 1x1 layer, pooling, loss and Adam are FP32.
+ * Loss: mean over the batch of ||y_b - t_b||^2 / ||t_b||^2, t_b = (e_b - r_b) / s_b.
+ * Grid: dim 3, every n[a] a multiple of 4 (two poolings), cell order as the
+ * solver's (x fastest).  Vectors are DEVICE FP64 N x batch, column-major;
+ * sigma_t / sigma_s given to forward/grad/train are DEVICE FP64 N x batch (one
+ * medium per column).  A network is not thread-safe; its work is ordered on
+ * its stream.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int dim;          /* 3 */
+    int n[3];         /* cells per axis, each a positive multiple of 4 */
+    int batch_max;    /* largest batch of forward/grad/train calls; 0 -> 1 */
+    int width[3];     /* channel widths w1, w2, w3; 0 -> 16, 32, 64; multiples of 16, <= 128 */
+    int reserved[4];  /* must be 0 */
+} ert_net_opts;
+
+typedef struct {
+    double lr;        /* Adam step size; 0 -> 1e-3 */
+    double beta1;     /* 0 -> 0.9 */
+    double beta2;     /* 0 -> 0.999 */
+    double eps;       /* 0 -> 1e-8 */
+} ert_net_train_opts;
+
+/* Number of parameters of a network with these options, or -1. */
+ERT_API long ert_net_param_count(const ert_net_opts* opts);
+
+/* Create a network with zero parameters (set them with ert_net_set_params).
+ * Returns ERT_EUNSUPPORTED for dim 2, ERT_EINVAL for bad sizes or widths. */
+ERT_API ert_status ert_net_create(const ert_net_opts* opts, void* hip_stream, ert_net_t* out);
+
+/* Number of parameters of `net`, or -1 for NULL. */
+ERT_API long ert_net_size(ert_net_t net);
+
+/* Copy parameters from / to HOST memory (ert_net_size floats); set also resets
+ * the optimiser state.  Both synchronise. */
+ERT_API ert_status ert_net_set_params(ert_net_t net, const float* params);
+ERT_API ert_status ert_net_get_params(ert_net_t net, float* params);
+
+/* z = M(r) for `batch` columns (device FP64).  Asynchronous. */
+ERT_API ert_status ert_net_forward(ert_net_t net, const double* r, const double* sigma_t, const double* sigma_s,
+                                   double* z, int batch);
+
+/* Loss for targets e (the corrections with (I - K) e = r) and its gradient with
+ * respect to the parameters: loss -> host double, grad -> host floats
+ * (ert_net_size entries); either may be NULL.  Synchronises. */
+ERT_API ert_status ert_net_grad(ert_net_t net, const double* r, const double* e, const double* sigma_t,
+                                const double* sigma_s, int batch, double* loss, float* grad);
+
+/* One Adam step (Kingma and Ba) on the loss of this batch; loss (host, may be
+ * NULL) receives the loss before the step (synchronises only when non-NULL). */
+ERT_API ert_status ert_net_train_step(ert_net_t net, const double* r, const double* e, const double* sigma_t,
+                                      const double* sigma_s, int batch, const ert_net_train_opts* opts,
+                                      double* loss);
+
+/* Release the network.  NULL is a no-op. */
+ERT_API void ert_net_destroy(ert_net_t net);
 
 #ifdef __cplusplus
 }

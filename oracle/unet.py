@@ -36,15 +36,22 @@ A 3x3x3 convolution is a cross-correlation with zero padding:
 Parameters.  One flat float vector, layer by layer: W (shape [cout][cin][k][k][k])
 then b ([cout]).
 
+Preconditioner.  For a residual r (scale s = rms(r)) the network output y on the
+features gives z = r + s y: the identity part of the correction passes through
+exactly and the network supplies the rest.  For a correction e with
+(I - K) e = r, e - r = K e is the part the (smoothing) transport operator
+produces, so the training target is t = (e - r) / s.
+
 Loss.  Mean over the batch of the relative squared error
   L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2.
 
-Rounding mode.  With bf16=True the operands of the 3x3x3 convolutions of the
-forward pass (inputs and weights) and of the input-gradient convolutions of the
-backward pass (output gradients and weights) are rounded to bfloat16 (round to
-nearest even), all sums stay in float64; weight gradients, biases, the 1x1
-layer, pooling and upsampling use unrounded values.  This is where a BF16-operand,
-FP32-accumulate implementation rounds, so the two agree to accumulation order.
+Rounding mode.  With bf16=True the 3x3x3 convolutions of the forward pass and
+the input-gradient convolutions of the backward pass take their weights rounded
+to bfloat16 and their activations (resp. output gradients) as the sum of two
+bfloat16 parts, hi = bf16(x) and lo = bf16(x - hi) (round to nearest even); sums
+stay in float64.  Weight gradients, biases, the 1x1 layer, pooling and
+upsampling use unrounded values.  This is where a BF16-operand, FP32-accumulate
+implementation rounds, so the two agree to accumulation order.
 """
 import numpy as np
 
@@ -79,6 +86,13 @@ def unpack(params, widths=(16, 32, 64), cin=CIN):
 
 def pack(layers):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
+
+
+def bf16_split(a):
+    """hi + lo with hi = bf16(a) and lo = bf16(a - hi), a taken as float32."""
+    f = np.asarray(a, dtype=np.float32).astype(np.float64)
+    hi = bf16_round(f)
+    return hi + bf16_round(f - hi)
 
 
 def bf16_round(a):
@@ -161,7 +175,7 @@ def up2_grad(g):
 
 def _conv_fwd(x, W, b, bf16):
     if bf16:
-        return conv3(bf16_round(x), bf16_round(W), b)
+        return conv3(bf16_split(x), bf16_round(W), b)
     return conv3(x, W, b)
 
 
@@ -206,7 +220,7 @@ def backward_one(layers, cache, gy, bf16=False):
         gpre = gout * (out > 0.0)
         grads[li] = conv3_weight_grad(inp, gpre)
         if bf16:
-            return conv3_input_grad(bf16_round(gpre), bf16_round(W))
+            return conv3_input_grad(bf16_split(gpre), bf16_round(W))
         return conv3_input_grad(gpre, W)
 
     w1 = layers[0][0].shape[0]
@@ -249,6 +263,22 @@ def loss_and_grad(params, X, T, widths=(16, 32, 64), bf16=False):
             acc[i][0][...] += dW
             acc[i][1][...] += db
     return total, pack(acc)
+
+
+def precondition(params, r, sigma_t, sigma_s, n, widths=(16, 32, 64), bf16=False):
+    """z = r + s * net(features(r)) for one residual (flat, solver cell order)."""
+    F, s = features(r, sigma_t, sigma_s, n)
+    if bf16:
+        F = F.astype(np.float32).astype(np.float64)
+    y = forward(params, F[None], widths, bf16)[0]
+    return np.asarray(r, dtype=np.float64) + s * y.ravel()
+
+
+def target(r, e):
+    """Training target (e - r) / rms(r) for a pair (r, e), flat."""
+    s = float(np.sqrt(np.mean(np.asarray(r) ** 2)))
+    s = s if s > 0.0 else 1.0
+    return (np.asarray(e, dtype=np.float64) - np.asarray(r, dtype=np.float64)) / s
 
 
 def features(r, sigma_t, sigma_s, n):

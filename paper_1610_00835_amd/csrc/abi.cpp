@@ -182,8 +182,15 @@ double dev_norm(ert_plan_impl* p, const double* v, double* partial, double* out_
     return std::sqrt(h);
 }
 
+// Iterate/residual pairs recorded at the start of every GMRES cycle.
+struct History {
+    double* buf = nullptr;   // N x 2 cap
+    int cap = 0;
+    int count = 0;
+};
+
 struct RunStats {
-    int iters = 0, matvecs = 0, cycles = 0;
+    int iters = 0, matvecs = 0, cycles = 0, precond = 0;
     double est = 0.0, true_rel = -1.0;
     bool converged = false;
 };
@@ -193,15 +200,19 @@ struct RunStats {
 // rotations and the small triangular solve on the host.  Stops when the
 // recurrence estimate reaches rtol ||b||; with check_true it then confirms the
 // true residual with the same operator and restarts from u if needed.
+// With a network: flexible GMRES with right preconditioning (Saad 1993), the
+// operator applied to z_j = net(v_j) and the update built from the z_j.
 ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, double* u, double rtol, int maxit,
-                     int restart, bool check_true, RunStats* rs)
+                     int restart, bool check_true, RunStats* rs, NetImpl* net = nullptr, History* hist = nullptr)
 {
     const long N = p->N;
     const int m = (restart > 0 && restart < maxit) ? restart : maxit;
-    // workspace: V (m+1 vectors), w, r
-    ERT_TRY(ensure_workspace(p, (size_t)(m + 3) * N, (size_t)kPartials * (m + 2) + 4 * (size_t)(m + 2)));
+    const int nz = net ? m : 0;
+    // workspace: V (m+1 vectors), Z (m, flexible only), w, r
+    ERT_TRY(ensure_workspace(p, (size_t)(m + nz + 3) * N, (size_t)kPartials * (m + 2) + 4 * (size_t)(m + 2)));
     double* V = p->d_ws;
-    double* w = V + (size_t)(m + 1) * N;
+    double* Z = V + (size_t)(m + 1) * N;
+    double* w = Z + (size_t)nz * N;
     double* r = w + N;
     double* partial = p->d_red;
     double* dh = partial + (size_t)kPartials * (m + 2);    // h1 (m+1) then h2 (m+1) then norm
@@ -222,6 +233,12 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
     const double* rsrc = b;
     for (int cycle = 0; rs->iters < maxit; ++cycle) {
         rs->cycles = cycle + 1;
+        if (hist && hist->count < hist->cap) {
+            double* hb = hist->buf + (size_t)2 * hist->count * N;
+            ERT_HIP(hipMemcpyAsync(hb, u, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+            ERT_HIP(hipMemcpyAsync(hb + N, rsrc, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+            hist->count++;
+        }
         ERT_TRY(dev_scale(p->stream, V, rsrc, 1.0 / beta, N));
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
@@ -230,6 +247,12 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
         bool done = false;
         for (int j = 0; j < m && rs->iters < maxit; ++j) {
             double* vj = V + (size_t)j * N;
+            if (net) {
+                double* zj = Z + (size_t)j * N;
+                ERT_TRY(net_precond(net, vj, p->d_st, p->d_ss, zj, p->stream));
+                rs->precond++;
+                vj = zj;
+            }
             ERT_TRY(apply_dispatch(p, ERT_OP_A, method, prec, vj, w, 1));
             rs->matvecs++;
             ERT_TRY(dev_multidot(p->stream, V, N, j + 1, w, N, partial, dh));
@@ -263,10 +286,12 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];
             for (int c = i + 1; c < k; ++c) s -= H[(size_t)i * m + c] * y[c];
-            y[i] = s / H[(size_t)i * m + i];
+            // a zero pivot only arises from a zero search direction (breakdown of a
+            // flexible step): that direction takes no weight
+            y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
         }
         ERT_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, p->stream));
-        ERT_TRY(dev_gemv_add(p->stream, V, N, k, dy, u, N));
+        ERT_TRY(dev_gemv_add(p->stream, net ? Z : V, N, k, dy, u, N));
         if (!check_true) {
             if (done) rs->converged = true;
             if (done) break;
@@ -284,6 +309,81 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
     }
     ERT_HIP(hipStreamSynchronize(p->stream));
     return ERT_OK;
+}
+
+// Refinement with the learned preconditioner and its residual check: each
+// step computes a correction d by flexible GMRES (at most precond_steps Arnoldi
+// steps, stopping at inner_tol) on the inner operator, and keeps U + d only if
+// the true residual of the outer operator decreases; a rejected step is redone
+// by plain GMRES with the same budget.  r and d are caller scratch (N each).
+ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec_inner, NetImpl* net,
+                          const double* phi, double* U, double* r, double* d, const ert_solve_opts& so,
+                          ert_solve_info* inf)
+{
+    const long N = p->N;
+    const int steps = so.precond_steps > 0 ? so.precond_steps : 10;
+    ERT_TRY(dev_zero(p->stream, U, N));
+    ERT_HIP(hipMemcpyAsync(r, phi, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    // trial vector U + d lives in a scratch buffer of its own
+    double* trial = nullptr;
+    ERT_HIP(hipMalloc(&trial, 2 * N * sizeof(double)));
+    double* rt = trial + N;
+    ert_status st = ERT_OK;
+    auto norm = [&](const double* v) {
+        ert_status s2 = ensure_workspace(p, 3 * N, (size_t)kPartials * 4 + 16);
+        if (s2 != ERT_OK) { st = s2; return 0.0; }
+        return dev_norm(p, v, p->d_red, p->d_red + (size_t)kPartials * 4, &st);
+    };
+    const double pnorm = norm(phi);
+    double rnorm = pnorm;
+    int used = 0;
+    for (int outer = 0; outer < 1000 && st == ERT_OK; ++outer) {
+        inf->rel_resid_true = pnorm > 0 ? rnorm / pnorm : 0.0;
+        if (rnorm <= so.tol * pnorm) { inf->converged = 1; break; }
+        if (used >= so.max_iter) break;
+        const int budget = std::min(steps, so.max_iter - used);
+        bool accepted = false;
+        for (int attempt = 0; attempt < 2 && !accepted && st == ERT_OK; ++attempt) {
+            RunStats rs;
+            st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, budget, budget, false, &rs,
+                           attempt == 0 ? net : nullptr);
+            if (st != ERT_OK) break;
+            used += rs.iters;
+            inf->iters += rs.iters;
+            inf->matvecs += rs.matvecs;
+            inf->precond_applies += rs.precond;
+            inf->rel_resid_est = rs.est;
+            st = ERT_HIPST(hipMemcpyAsync(trial, U, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+            if (st == ERT_OK) st = dev_add(p->stream, trial, d, N);
+            if (st == ERT_OK) st = apply_dispatch(p, ERT_OP_A, method, prec_outer, trial, rt, 1);
+            if (st != ERT_OK) break;
+            inf->matvecs++;
+            st = dev_sub(p->stream, rt, phi, rt, N);
+            if (st != ERT_OK) break;
+            const double tn = norm(rt);
+            if (st != ERT_OK) break;
+            // the check: keep the step only if the true residual went down
+            if (tn < rnorm || attempt == 1) {
+                accepted = true;
+                if (tn < rnorm) {
+                    st = ERT_HIPST(hipMemcpyAsync(U, trial, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+                    if (st == ERT_OK)
+                        st = ERT_HIPST(hipMemcpyAsync(r, rt, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+                    rnorm = tn;
+                }
+            } else {
+                inf->rejected++;
+            }
+        }
+        inf->restarts = outer + 1;
+    }
+    if (st == ERT_OK) {
+        inf->rel_resid_true = pnorm > 0 ? rnorm / pnorm : 0.0;
+        if (rnorm <= so.tol * pnorm) inf->converged = 1;
+    }
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(trial);
+    return st;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -320,6 +420,8 @@ void ert_vie_destroy(ert_vie_plan_t p)
         if (f) fmm_destroy(f);
         f = nullptr;
     }
+    het_destroy(p->het);
+    p->het = nullptr;
     (void)hipFree(p->d_st);
     (void)hipFree(p->d_st32);
     (void)hipFree(p->d_ss);
@@ -468,6 +570,19 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         return ERT_EINVAL;
     for (int r : so.reserved)
         if (r != 0) return ERT_EINVAL;
+    if (so.precond_steps < 0 || so.history_max < 0 || (so.history_max > 0 && !so.history)) return ERT_EINVAL;
+    NetImpl* net = so.precond ? net_impl(so.precond) : nullptr;
+    if (net) {
+        const int* g = net_grid(net);
+        if (p->o.dim != 3 || g[0] != p->geo.n0 || g[1] != p->geo.n1 || g[2] != p->geo.n2) {
+            record_error("ert_vie_solve: the preconditioner's grid differs from the plan's");
+            return ERT_EINVAL;
+        }
+        if (so.block && nrhs > 1) {
+            record_error("ert_vie_solve: a learned preconditioner is not combined with block GMRES");
+            return ERT_EUNSUPPORTED;
+        }
+    }
     const long N = p->N;
     const int method = p->o.method;
     const int prec_outer = so.mixed ? ERT_FP64 : p->o.prec;
@@ -574,9 +689,19 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
             inf.matvecs++;
         }
         if (st != ERT_OK) break;
-        if (!so.mixed) {
+        if (net) {
+            st = learned_refine(p, method, so.mixed ? ERT_FP64 : p->o.prec, so.mixed ? prec_inner : p->o.prec, net,
+                                phi, Uc, r, d, so, &inf);
+        } else if (!so.mixed) {
             RunStats rs;
-            st = gmres_run(p, method, prec_outer, phi, Uc, so.tol, so.max_iter, so.restart, true, &rs);
+            History hist;
+            if (c == 0 && so.history && so.history_max > 0) {
+                hist.buf = so.history;
+                hist.cap = so.history_max;
+            }
+            st = gmres_run(p, method, prec_outer, phi, Uc, so.tol, so.max_iter, so.restart, true, &rs, nullptr,
+                           hist.buf ? &hist : nullptr);
+            inf.history_count = hist.count;
             inf.iters = rs.iters;
             inf.matvecs += rs.matvecs;
             inf.restarts = rs.cycles > 0 ? rs.cycles - 1 : 0;

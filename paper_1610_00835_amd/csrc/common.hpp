@@ -114,6 +114,7 @@ __device__ __forceinline__ T tau_march(const T* __restrict__ st, const Geo& g, T
 // --------------------------------------------------------------- the plan ---
 
 struct FmmData;   // fmm.hip
+struct HetCache;  // fmm.hip
 
 // Per-stage event timing (ert_vie_profile).
 struct Profiler {
@@ -177,6 +178,7 @@ struct ert_plan_impl {
     double* d_red = nullptr;     // reduction partials / small vectors
     size_t red_elems = 0;
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
+    HetCache* het = nullptr;     // heterogeneous kernel caches, shared by the precisions
     Profiler prof;
     bool use_graphs = true;      // FMM applies replay captured graphs
 };
@@ -188,6 +190,7 @@ ert_status direct_apply(ert_plan_impl* p, int op, int prec, const double* x, dou
 ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
 ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info);
 void fmm_destroy(FmmData* f);
+void het_destroy(HetCache* c);
 
 // BLAS-1 helpers for GMRES (blas.hip); all stream-ordered on `s`.
 // out[c] = <V[:,c], w> for c < ncols; V has leading dimension ldv.
@@ -215,6 +218,13 @@ ert_status dev_small_add(hipStream_t s, double* dst, const double* src, int n);
 ert_status dev_dgemm(hipStream_t s, int M, int N, long K, double alpha, const double* A, long sAi, long sAk,
                      const double* B, long sBk, long sBj, double beta, double* C, long sCi, long sCj, double* work,
                      size_t work_elems);
+
+// Learned preconditioner (unet.hip): z = net(r) on the media st / ss (device FP64,
+// one column), ordered on stream s.
+struct NetImpl;
+NetImpl* net_impl(ert_net_t net);
+ert_status net_precond(NetImpl* n, const double* r, const double* st, const double* ss, double* z, hipStream_t s);
+const int* net_grid(const NetImpl* n);
 
 // Gauss-Legendre nodes/weights on [-1,1] (host).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "fmm.hpp"
@@ -789,16 +790,10 @@ struct FmmImpl : FmmData {
     int rp[kMaxLevels + 1] = {};        // compressed rank (padded), 0 = uncompressed
     T* Ut[kMaxLevels + 1] = {};         // [rp][Kp]: multipoles -> compressed
     T* Um[kMaxLevels + 1] = {};         // [Kp][rp]: compressed locals -> locals
-    T* hops[kMaxLevels + 1] = {};       // heterogeneous per-pair, source-node major
-    long* pstart[kMaxLevels + 1] = {};
-    int* psrc[kMaxLevels + 1] = {};
+    HetCache* hc = nullptr;             // heterogeneous caches (owned by the plan)
     T* nearops = nullptr;               // homogeneous near blocks [3^d][S][S]
     T* tab = nullptr;                   // homogeneous near table (S not a multiple of 32)
     int ntab = 0;
-    T* nearblk = nullptr;               // heterogeneous near cache [leaf][3^d][S][S]
-    int* near_src = nullptr;            // heterogeneous near pairs: source leaf of (leaf, neighbour), -1 outside
-    long* near_tstart = nullptr;        // [nleaf + 1]: 3^d pairs per leaf
-    long hnp[kMaxLevels + 1] = {};      // heterogeneous far pairs per level
     T* q = nullptr;
     T* pot = nullptr;
     T* W[kMaxLevels + 1] = {};
@@ -820,9 +815,9 @@ struct FmmImpl : FmmData {
     ~FmmImpl() override
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(nearblk); f(near_src); f(near_tstart); f(q); f(pot);
+        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(q); f(pot);
         for (int l = 0; l <= kMaxLevels; ++l) {
-            f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]); f(hops[l]); f(pstart[l]); f(psrc[l]);
+            f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]);
             f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
             far_site[l].release();
         }
@@ -849,7 +844,7 @@ struct FmmImpl : FmmData {
     int rank_of(int l) const override { return rp[l]; }
     ert_status setup(ert_plan_impl* p) override;
     ert_status setup_far_hom(ert_plan_impl* p, int l, double svd_tol);
-    ert_status setup_far_het(ert_plan_impl* p, int l);
+    ert_status setup_het(ert_plan_impl* p);
     ert_status ensure_buffers(int nrhs);
     hipStream_t p_stream = nullptr;
     ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) override;
@@ -976,8 +971,7 @@ ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
 }
 
 // Heterogeneous far field of level l: one matrix per (target, source) pair.
-template <typename T>
-ert_status FmmImpl<T>::setup_far_het(ert_plan_impl* p, int l)
+ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb, HetCache* hc, int l)
 {
     hipStream_t s = p->stream;
     const long KpKp = (long)tr.Kp * tr.Kp;
@@ -1006,32 +1000,99 @@ ert_status FmmImpl<T>::setup_far_het(ert_plan_impl* p, int l)
     }
     start[tr.nbox[l]] = (long)src.size();
     const long np = (long)src.size();
-    hnp[l] = np;
-    ERT_TRY(upload<long>(s, &pstart[l], start));
-    ERT_TRY(upload<int>(s, &psrc[l], src));
+    hc->hnp[l] = np;
+    ERT_TRY(upload<long>(s, &hc->pstart[l], start));
+    ERT_TRY(upload<int>(s, &hc->psrc[l], src));
     DevPtrs tmp;
     long* ptd = nullptr;
     ERT_TRY(tmp.alloc(&ptd, (size_t)np));
     ERT_HIP(hipMemcpyAsync(ptd, ptgt.data(), np * sizeof(long), hipMemcpyHostToDevice, s));
-    size_t bytes = (size_t)np * KpKp * sizeof(T);
+    size_t bytes = (size_t)np * KpKp * sizeof(float);
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
         record_error("FMM: heterogeneous translation cache does not fit in device memory");
         return ERT_ENOMEM;
     }
-    if (hipMalloc(&hops[l], std::max<size_t>(1, bytes)) != hipSuccess) {
+    if (hipMalloc(&hc->hops[l], std::max<size_t>(1, bytes)) != hipSuccess) {
         record_error("FMM: heterogeneous translation cache allocation failed");
         return ERT_ENOMEM;
     }
     const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
     for (long p0 = 0; p0 < np; p0 += pchunk) {
         long cnt = std::min(pchunk, np - p0);
-        hipLaunchKernelGGL(k_ops_het<T>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, tr.nc,
-                           tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, psrc[l], p0, cnt,
-                           hops[l] + (size_t)p0 * KpKp);
+        hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, tr.nc,
+                           tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, hc->psrc[l], p0, cnt,
+                           hc->hops[l] + (size_t)p0 * KpKp);
         ERT_HIP(hipGetLastError());
     }
+    hc->bytes += bytes;
     ERT_HIP(hipStreamSynchronize(s));
+    return ERT_OK;
+}
+
+// Heterogeneous caches of the plan (built by the first precision that needs them).
+template <typename T>
+ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
+{
+    if (p->het) {
+        if (p->het->nc != tr.nc || p->het->leaf != tr.leaf) {
+            record_error("FMM: heterogeneous cache built for another tree");
+            return ERT_EINVAL;
+        }
+        hc = p->het;
+        return ERT_OK;
+    }
+    hipStream_t s = p->stream;
+    HetCache* c = new (std::nothrow) HetCache();
+    if (!c) return ERT_ENOMEM;
+    c->nc = tr.nc;
+    c->leaf = tr.leaf;
+    auto fail = [&](ert_status e) { delete c; return e; };
+    const int nn = tr.D == 3 ? 27 : 9;
+    const long per = (long)nn * tr.S * tr.S;
+    const size_t bytes = (size_t)tr.nleaf * per * sizeof(float);
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
+        record_error("FMM: heterogeneous near-field cache does not fit in device memory");
+        return fail(ERT_ENOMEM);
+    }
+    if (hipMalloc(&c->nearblk, bytes) != hipSuccess) {
+        record_error("FMM: near-field cache allocation failed");
+        return fail(ERT_ENOMEM);
+    }
+    c->bytes += bytes;
+    const long chunk = std::max<long>(1, (1L << 26) / per);
+    for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
+        long cnt = std::min(chunk, tr.nleaf - l0);
+        hipLaunchKernelGGL(k_near_blocks<float>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, l0,
+                           cnt, c->nearblk + (size_t)l0 * per);
+        if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
+    }
+    std::vector<int> src((size_t)tr.nleaf * nn);
+    std::vector<long> ts(tr.nleaf + 1);
+    for (long lf = 0; lf < tr.nleaf; ++lf) {
+        int lb[3];
+        unravel3(lf, tr.nb, lb);
+        ts[lf] = lf * nn;
+        for (int k = 0; k < nn; ++k) {
+            const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, tr.D == 3 ? k / 9 - 1 : 0};
+            int sb[3];
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                sb[a] = lb[a] + ((a < tr.D) ? o[a] : 0);
+                if (sb[a] < 0 || sb[a] >= tr.nb[a]) ok = false;
+            }
+            src[(size_t)lf * nn + k] = ok ? (int)(sb[0] + (long)tr.nb[0] * (sb[1] + (long)tr.nb[1] * sb[2])) : -1;
+        }
+    }
+    ts[tr.nleaf] = tr.nleaf * nn;
+    ert_status st = upload<int>(s, &c->near_src, src);
+    if (st == ERT_OK) st = upload<long>(s, &c->near_tstart, ts);
+    for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, c, l);
+    if (st == ERT_OK && hipStreamSynchronize(s) != hipSuccess) st = ERT_EDEVICE;
+    if (st != ERT_OK) return fail(st);
+    p->het = c;
+    hc = c;
     return ERT_OK;
 }
 
@@ -1141,41 +1202,7 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
         if (nearops) ERT_TRY(build_site(s, tr.D, tr.nl[tr.L], false, near_site));
         for (int l = 2; l <= tr.L; ++l) ERT_TRY(build_site(s, tr.D, tr.nl[l], true, far_site[l]));
     } else {
-        const int nn = tr.D == 3 ? 27 : 9;
-        const long per = (long)nn * tr.S * tr.S;
-        size_t bytes = (size_t)tr.nleaf * per * sizeof(T);
-        if (hipMalloc(&nearblk, bytes) != hipSuccess) {
-            record_error("FMM: near-field cache allocation failed");
-            return ERT_ENOMEM;
-        }
-        const long chunk = std::max<long>(1, (1L << 26) / per);
-        for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
-            long cnt = std::min(chunk, tr.nleaf - l0);
-            hipLaunchKernelGGL(k_near_blocks<T>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, l0, cnt,
-                               nearblk + (size_t)l0 * per);
-            ERT_HIP(hipGetLastError());
-        }
-        std::vector<int> src((size_t)tr.nleaf * nn);
-        std::vector<long> ts(tr.nleaf + 1);
-        for (long lf = 0; lf < tr.nleaf; ++lf) {
-            int lb[3];
-            unravel3(lf, tr.nb, lb);
-            ts[lf] = lf * nn;
-            for (int k = 0; k < nn; ++k) {
-                const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, tr.D == 3 ? k / 9 - 1 : 0};
-                int sb[3];
-                bool ok = true;
-                for (int a = 0; a < 3; ++a) {
-                    sb[a] = lb[a] + ((a < tr.D) ? o[a] : 0);
-                    if (sb[a] < 0 || sb[a] >= tr.nb[a]) ok = false;
-                }
-                src[(size_t)lf * nn + k] = ok ? (int)(sb[0] + (long)tr.nb[0] * (sb[1] + (long)tr.nb[1] * sb[2])) : -1;
-            }
-        }
-        ts[tr.nleaf] = tr.nleaf * nn;
-        ERT_TRY(upload<int>(s, &near_src, src));
-        ERT_TRY(upload<long>(s, &near_tstart, ts));
-        for (int l = 2; l <= tr.L; ++l) ERT_TRY(setup_far_het(p, l));
+        ERT_TRY(setup_het(p));
     }
     ERT_HIP(hipStreamSynchronize(s));
     return ensure_buffers(1);
@@ -1223,7 +1250,7 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
     if (hetero) {
         const size_t rb = (size_t)std::min(nrhs, 8);
         st_need = std::max(st_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
-        for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hnp[l] * tr.Kp);
+        for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hc->hnp[l] * tr.Kp);
     }
     for (int l = 2; l <= tr.L; ++l) ERT_TRY(site_need(far_site[l], tr.nbox[l], rp[l] > 0 ? rp[l] : tr.Kp));
     if (st_need > stage_elems) {
@@ -1318,14 +1345,15 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         StageTimer* near_timer = &st_;
         if (hetero) {
             PairStream a;
+            a.ops_f32 = 1;
             a.npairs = tr.nleaf * nn;
             a.ntarget = tr.nleaf;
             a.B = nrhs;
             a.M = a.Kd = tr.S;
-            a.opsT = nearblk;
-            a.src = near_src;
+            a.opsT = hc->nearblk;
+            a.src = hc->near_src;
             a.nsrc = tr.nleaf;
-            a.tstart = near_tstart;
+            a.tstart = hc->near_tstart;
             a.W = q;
             a.stage = stage;
             a.L = pot;
@@ -1385,14 +1413,15 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             StageTimer st_(pf, s, ERT_STAGE_M2L);
             if (hetero) {
                 PairStream a;
-                a.npairs = hnp[l];
+                a.ops_f32 = 1;
+                a.npairs = hc->hnp[l];
                 a.ntarget = tr.nbox[l];
                 a.B = nrhs;
                 a.M = a.Kd = tr.Kp;
-                a.opsT = hops[l];
-                a.src = psrc[l];
+                a.opsT = hc->hops[l];
+                a.src = hc->psrc[l];
                 a.nsrc = tr.nbox[l];
-                a.tstart = pstart[l];
+                a.tstart = hc->pstart[l];
                 a.W = W[l];
                 a.stage = stage;
                 a.L = Lc[l];
@@ -1577,5 +1606,16 @@ ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info)
 }
 
 void fmm_destroy(FmmData* f) { delete f; }
+
+HetCache::~HetCache()
+{
+    auto f = [](void* q) { if (q) (void)hipFree(q); };
+    f(nearblk); f(near_src); f(near_tstart);
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        f(hops[l]); f(pstart[l]); f(psrc[l]);
+    }
+}
+
+void het_destroy(HetCache* c) { delete c; }
 
 }  // namespace ertvie

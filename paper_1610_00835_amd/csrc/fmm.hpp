@@ -103,6 +103,7 @@ ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    
 // contiguous pairs of every target in a fixed order.  The staging buffer holds
 // 8 right-hand sides (min(B, 8) x npairs x M elements).
 struct PairStream {
+    int ops_f32;             // 1: opsT holds FP32 values (FP64 products read FP32 caches)
     long npairs;
     long ntarget;
     int B;
@@ -118,5 +119,22 @@ struct PairStream {
 };
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
+
+// Heterogeneous media: kernel caches shared by the applies of every precision
+// of a plan, in FP32 (the FP64 apply reads them and accumulates in FP64; the
+// rounding of the stored kernel values, 6e-8 relative, sits far below the
+// interpolation error of the far field).
+struct HetCache {
+    int nc = 0, leaf = 0;                   // tree the cache was built for
+    float* nearblk = nullptr;               // [leaf][3^d][S][S] (target fastest)
+    int* near_src = nullptr;                // [leaf * 3^d] source leaf, -1 outside the grid
+    long* near_tstart = nullptr;            // [nleaf + 1]
+    float* hops[kMaxLevels + 1] = {};       // [pair][Kp][Kp], source-node major
+    long* pstart[kMaxLevels + 1] = {};      // [nbox + 1] pairs of each target
+    int* psrc[kMaxLevels + 1] = {};         // [pair] source box
+    long hnp[kMaxLevels + 1] = {};          // pairs per level
+    size_t bytes = 0;
+    ~HetCache();
+};
 
 }  // namespace ertvie

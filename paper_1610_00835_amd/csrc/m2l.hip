@@ -385,7 +385,7 @@ __device__ __forceinline__ void store_rows(T* p, const T (&o)[RPT])
 // output rows (one 16-byte load per matrix row when the row count allows);
 // when the rows need fewer than 256 threads the reduction dimension is split
 // between thread groups, whose partial sums are combined in a fixed order.
-template <typename T, int RB, int RPT>
+template <typename T, typename TS, int RB, int RPT>
 __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
 {
     extern __shared__ unsigned char smem[];
@@ -414,28 +414,28 @@ __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
 #pragma unroll
             for (int e = 0; e < RPT; ++e) acc[b][e] = T(0);
         if (act) {
-            const T* col = (const T*)g.opsT + (size_t)p * g.Kd * g.M + (size_t)rg * RPT;
+            const TS* col = (const TS*)g.opsT + (size_t)p * g.Kd * g.M + (size_t)rg * RPT;
             int k = k0;
             for (; k + 8 <= k1; k += 8) {
-                T m[8][RPT];
+                TS m[8][RPT];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) load_rows<T, RPT>(col + (size_t)(k + u) * g.M, m[u]);
+                for (int u = 0; u < 8; ++u) load_rows<TS, RPT>(col + (size_t)(k + u) * g.M, m[u]);
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
 #pragma unroll
                     for (int b = 0; b < RB; ++b) {
                         const T w = ws[b * g.Kd + k + u];
 #pragma unroll
-                        for (int e = 0; e < RPT; ++e) acc[b][e] += m[u][e] * w;
+                        for (int e = 0; e < RPT; ++e) acc[b][e] += (T)m[u][e] * w;
                     }
             }
             for (; k < k1; ++k) {
-                T m[RPT];
-                load_rows<T, RPT>(col + (size_t)k * g.M, m);
+                TS m[RPT];
+                load_rows<TS, RPT>(col + (size_t)k * g.M, m);
 #pragma unroll
                 for (int b = 0; b < RB; ++b)
 #pragma unroll
-                    for (int e = 0; e < RPT; ++e) acc[b][e] += m[e] * ws[b * g.Kd + k];
+                    for (int e = 0; e < RPT; ++e) acc[b][e] += (T)m[e] * ws[b * g.Kd + k];
             }
         }
         // kgroups > 1 only when all rows fit one chunk (rows < 256)
@@ -574,22 +574,23 @@ ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
     return offset_gemm_reduce(s, prec, g);
 }
 
-template <typename T, int RPT>
+template <typename T, typename TS, int RPT>
 void launch_pair_stream(hipStream_t s, const PairStream& g, int b0, int rb)
 {
     const int rows = g.M / RPT;
     const size_t sh = (size_t)rb * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T);
     const dim3 grid((unsigned)g.npairs);
-    if (rb == 8) hipLaunchKernelGGL((k_pair_stream<T, 8, RPT>), grid, dim3(256), sh, s, g, b0);
-    else if (rb == 4) hipLaunchKernelGGL((k_pair_stream<T, 4, RPT>), grid, dim3(256), sh, s, g, b0);
-    else if (rb == 2) hipLaunchKernelGGL((k_pair_stream<T, 2, RPT>), grid, dim3(256), sh, s, g, b0);
-    else hipLaunchKernelGGL((k_pair_stream<T, 1, RPT>), grid, dim3(256), sh, s, g, b0);
+    if (rb == 8) hipLaunchKernelGGL((k_pair_stream<T, TS, 8, RPT>), grid, dim3(256), sh, s, g, b0);
+    else if (rb == 4) hipLaunchKernelGGL((k_pair_stream<T, TS, 4, RPT>), grid, dim3(256), sh, s, g, b0);
+    else if (rb == 2) hipLaunchKernelGGL((k_pair_stream<T, TS, 2, RPT>), grid, dim3(256), sh, s, g, b0);
+    else hipLaunchKernelGGL((k_pair_stream<T, TS, 1, RPT>), grid, dim3(256), sh, s, g, b0);
 }
 
-template <typename T>
+// T: arithmetic and vectors; TS: stored matrices (FP32 caches under FP64 products).
+template <typename T, typename TS>
 ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 {
-    constexpr int VEC = 16 / sizeof(T);
+    constexpr int VEC = 16 / sizeof(TS);
     const int rows = g.M % VEC == 0 ? g.M / VEC : g.M;
     if (g.M < 1 || g.Kd < 1 || (size_t)8 * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T) > 64 * 1024) {
         record_error("pair_stream: unsupported operator shape");
@@ -599,8 +600,8 @@ ert_status pair_stream_t(hipStream_t s, const PairStream& g)
     for (int b0 = 0; b0 < g.B;) {
         const int left = g.B - b0;
         const int rb = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
-        if (g.M % VEC == 0) launch_pair_stream<T, VEC>(s, g, b0, rb);
-        else launch_pair_stream<T, 1>(s, g, b0, rb);
+        if (g.M % VEC == 0) launch_pair_stream<T, TS, VEC>(s, g, b0, rb);
+        else launch_pair_stream<T, TS, 1>(s, g, b0, rb);
         ERT_HIP(hipGetLastError());
         const long n = g.ntarget * g.M * rb;
         hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, rb);
@@ -612,7 +613,8 @@ ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
 {
-    return prec == ERT_FP64 ? pair_stream_t<double>(s, g) : pair_stream_t<float>(s, g);
+    if (prec == ERT_FP64) return g.ops_f32 ? pair_stream_t<double, float>(s, g) : pair_stream_t<double, double>(s, g);
+    return pair_stream_t<float, float>(s, g);
 }
 
 }  // namespace ertvie

@@ -37,13 +37,25 @@ class VieOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("mixed", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_is_phi", ctypes.c_int),
-                ("block", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("block", ctypes.c_int), ("precond_steps", ctypes.c_int), ("history_max", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1), ("precond", ctypes.c_void_p), ("history", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("rel_resid_est", ctypes.c_double),
-                ("rel_resid_true", ctypes.c_double), ("t_solve", ctypes.c_double)]
+                ("rel_resid_true", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("rejected", ctypes.c_int), ("precond_applies", ctypes.c_int), ("history_count", ctypes.c_int)]
+
+
+class NetOpts(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("batch_max", ctypes.c_int),
+                ("width", ctypes.c_int * 3), ("reserved", ctypes.c_int * 4)]
+
+
+class NetTrainOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
 
 
 class FmmInfo(ctypes.Structure):
@@ -196,7 +208,9 @@ class Plan:
         return y
 
     def solve(self, f, U, tol=1e-8, max_iter=500, restart=0, mixed=False, inner_tol=1e-5, rhs_is_phi=False,
-              allow_noconv=False, block=False):
+              allow_noconv=False, block=False, precond=None, precond_steps=0, history=None):
+        """Algorithm 1 steps S.1-S.2.  precond: a Net (learned right preconditioner);
+        history: float64 CUDA tensor (2k, N) receiving (U_k, r_k) of the plain solve's cycles."""
         fp, nf = _dev_ptr(f, self.N, "f")
         up, nu = _dev_ptr(U, self.N, "U")
         if nf != nu:
@@ -209,6 +223,15 @@ class Plan:
         so.inner_tol = float(inner_tol)
         so.rhs_is_phi = 1 if rhs_is_phi else 0
         so.block = 1 if block else 0
+        so.precond_steps = int(precond_steps)
+        if precond is not None:
+            so.precond = precond.handle.value
+        if history is not None:
+            hp, hn = _dev_ptr(history, self.N, "history")
+            if hn % 2:
+                raise ValueError("history needs an even number of rows (iterate, residual)")
+            so.history = hp
+            so.history_max = hn // 2
         info = SolveInfo()
         st = load().ert_vie_solve(self.handle, fp, up, nf, ctypes.byref(so), ctypes.byref(info))
         out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
@@ -263,3 +286,131 @@ def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_ma
     return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
                 method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream,
                 svd_tol=svd_tol)
+
+
+def _load_net():
+    L = load()
+    if getattr(L, "_net_ready", False):
+        return L
+    L.ert_net_param_count.restype = ctypes.c_long
+    L.ert_net_param_count.argtypes = [ctypes.POINTER(NetOpts)]
+    L.ert_net_create.restype = ctypes.c_int
+    L.ert_net_create.argtypes = [ctypes.POINTER(NetOpts), _vp, ctypes.POINTER(_vp)]
+    L.ert_net_size.restype = ctypes.c_long
+    L.ert_net_size.argtypes = [_vp]
+    L.ert_net_set_params.restype = ctypes.c_int
+    L.ert_net_set_params.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+    L.ert_net_get_params.restype = ctypes.c_int
+    L.ert_net_get_params.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+    L.ert_net_forward.restype = ctypes.c_int
+    L.ert_net_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int]
+    L.ert_net_grad.restype = ctypes.c_int
+    L.ert_net_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_float)]
+    L.ert_net_train_step.restype = ctypes.c_int
+    L.ert_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(NetTrainOpts), _dp]
+    L.ert_net_destroy.restype = None
+    L.ert_net_destroy.argtypes = [_vp]
+    L._net_ready = True
+    return L
+
+
+class Net:
+    """The learned right preconditioner (ert_net_*): a 3D U-Net on an n0 x n1 x n2 grid.
+
+    Vectors are float64 CUDA tensors (N,) or (batch, N); forward/grad/train take one
+    medium per column (sigma_t, sigma_s of the same shape as r)."""
+
+    def __init__(self, n, batch_max=1, widths=(16, 32, 64), stream=None):
+        L = _load_net()
+        o = NetOpts()
+        o.dim = 3
+        for a in range(3):
+            o.n[a] = int(n[a])
+            o.width[a] = int(widths[a])
+        o.batch_max = int(batch_max)
+        self.opts = o
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        h = _vp()
+        _check(L.ert_net_create(ctypes.byref(o), sp, ctypes.byref(h)), "ert_net_create")
+        self._h = h
+        self.size = int(L.ert_net_size(h))
+
+    @staticmethod
+    def param_count(widths=(16, 32, 64)):
+        o = NetOpts()
+        o.dim = 3
+        for a in range(3):
+            o.width[a] = int(widths[a])
+        return int(_load_net().ert_net_param_count(ctypes.byref(o)))
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("network is closed")
+        return self._h
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32).reshape(-1)
+        if p.size != self.size:
+            raise ValueError("expected %d parameters, got %d" % (self.size, p.size))
+        _check(_load_net().ert_net_set_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "ert_net_set_params")
+
+    def get_params(self):
+        p = np.empty(self.size, dtype=np.float32)
+        _check(_load_net().ert_net_get_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "ert_net_get_params")
+        return p
+
+    def _vecs(self, **kw):
+        ptrs, nb = [], None
+        for name, t in kw.items():
+            ptr, b = _dev_ptr(t, self.N, name)
+            if nb is not None and b != nb:
+                raise ValueError("batch sizes differ")
+            nb = b
+            ptrs.append(ptr)
+        return ptrs, nb
+
+    def forward(self, r, sigma_t, sigma_s, z):
+        (rp, sp, ssp, zp), b = self._vecs(r=r, sigma_t=sigma_t, sigma_s=sigma_s, z=z)
+        _check(_load_net().ert_net_forward(self.handle, rp, sp, ssp, zp, b), "ert_net_forward")
+        return z
+
+    def grad(self, r, e, sigma_t, sigma_s):
+        (rp, ep, sp, ssp), b = self._vecs(r=r, e=e, sigma_t=sigma_t, sigma_s=sigma_s)
+        loss = ctypes.c_double()
+        g = np.empty(self.size, dtype=np.float32)
+        _check(_load_net().ert_net_grad(self.handle, rp, ep, sp, ssp, b, ctypes.byref(loss),
+                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "ert_net_grad")
+        return loss.value, g
+
+    def train_step(self, r, e, sigma_t, sigma_s, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=True):
+        (rp, ep, sp, ssp), b = self._vecs(r=r, e=e, sigma_t=sigma_t, sigma_s=sigma_s)
+        o = NetTrainOpts(float(lr), float(beta1), float(beta2), float(eps))
+        loss = ctypes.c_double()
+        _check(_load_net().ert_net_train_step(self.handle, rp, ep, sp, ssp, b, ctypes.byref(o),
+                                              ctypes.byref(loss) if want_loss else None), "ert_net_train_step")
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _load_net().ert_net_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,122 @@
+"""Train the learned right preconditioner on the seeded random media of the
+heterogeneous many-scattering recipe (base sigma_t ~ U[5, 50] plus 8 Gaussian
+blobs, albedo 0.99, one face source), then compare, on held-out media, plain FP64
+GMRES with the FP64-refined solve whose inner flexible GMRES runs on the FP32
+operator with the network as right preconditioner.
+
+    python -m paper_1610_00835_amd.train_precond --n 64 --media 24 --steps 1500 \
+        --out paper_1610_00835_amd/weights/precond_c5_64.npz
+
+Training pairs come from the method's own solves (learn.collect_pairs).  The output
+file holds the FP32 parameters, the widths, the grid, the media seeds, the loss
+history and the held-out comparison.
+"""
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import ertvie, inputs, learn
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def plan_for(case, args, prec="fp64"):
+    return ertvie.plan_from_case(case, method="fmm", prec=prec, leaf=args.leaf, cheb_n=args.cheb_n)
+
+
+def compare(net, case, args):
+    """Plain FP64 GMRES vs the FP64-refined, FP32-inner, learned-preconditioned solve."""
+    import torch
+    fd = torch.as_tensor(np.ascontiguousarray(case["f"])).cuda()
+    out = {}
+    with plan_for(case, args) as plan:
+        t0 = time.perf_counter()
+        plan.fmm_info("fp64")
+        plan.fmm_info("fp32")
+        out["plan_s"] = time.perf_counter() - t0
+        U0 = torch.empty_like(fd)
+        plan.solve(fd, U0, tol=1e-8, max_iter=args.max_iter, allow_noconv=True)   # warm (graphs, tuning)
+        plain = plan.solve(fd, U0, tol=1e-8, max_iter=args.max_iter, allow_noconv=True)
+        U1 = torch.empty_like(fd)
+        plan.solve(fd, U1, tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol, precond=net,
+                   precond_steps=args.precond_steps, allow_noconv=True)
+        learned = plan.solve(fd, U1, tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol,
+                             precond=net, precond_steps=args.precond_steps, allow_noconv=True)
+        U2 = torch.empty_like(fd)
+        mixed = plan.solve(fd, U2, tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol,
+                           allow_noconv=True)
+        torch.cuda.synchronize()
+        d = float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0))
+    out.update(plain=plain, learned=learned, mixed_plain=mixed, rel_diff_solutions=d,
+               speedup=plain["t_solve"] / learned["t_solve"] if learned["converged"] else None)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--media", type=int, default=24, help="training media (seeds 1000, 1001, ...)")
+    ap.add_argument("--test", type=int, default=2, help="held-out media (seeds 0, 1, ...)")
+    ap.add_argument("--restart", type=int, default=4, help="GMRES cycle length of the pair-generating solves")
+    ap.add_argument("--max-pairs", type=int, default=80)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--leaf", type=int, default=8)
+    ap.add_argument("--cheb-n", type=int, default=0)
+    ap.add_argument("--precond-steps", type=int, default=10)
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    import torch
+    ertvie.load()
+    n = (args.n,) * 3
+    widths = (16, 32, 64)
+    pairs = learn.PairSet()
+    t0 = time.perf_counter()
+    for s in range(1000, 1000 + args.media):
+        case = inputs.make_case("c5", n=n, seed=s)
+        with plan_for(case, args) as plan:
+            R, E, info = learn.collect_pairs(plan, case["f"], restart=args.restart, tol=1e-9,
+                                             max_pairs=args.max_pairs, max_iter=args.max_iter)
+        pairs.add(R, E, case["sigma_t"], case["sigma_s"])
+        log("medium %d: %d iterations, %d pairs, %.1f s" % (s, info["iters"], R.shape[0], time.perf_counter() - t0))
+        torch.cuda.empty_cache()
+    pairs.finalize()
+    t_pairs = time.perf_counter() - t0
+    log("pairs: %d in %.1f s" % (len(pairs), t_pairs))
+    net = ertvie.Net(n, batch_max=args.batch, widths=widths)
+    net.set_params(learn.init_params(widths, args.seed))
+    t0 = time.perf_counter()
+    losses = learn.train(net, pairs, steps=args.steps, batch=args.batch, lr=args.lr, seed=args.seed + 1,
+                         log_every=max(1, args.steps // 10), log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("training: %d steps in %.1f s" % (args.steps, t_train))
+    del pairs
+    torch.cuda.empty_cache()
+    results = []
+    for s in range(args.test):
+        r = compare(net, inputs.make_case("c5", n=n, seed=s), args)
+        log("held-out medium %d: %s" % (s, json.dumps(r)))
+        results.append(r)
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        meta = {"n": n, "widths": widths, "train_media": list(range(1000, 1000 + args.media)),
+                "restart": args.restart, "steps": args.steps, "batch": args.batch, "lr": args.lr,
+                "pairs_s": t_pairs, "train_s": t_train, "losses": losses, "held_out": results,
+                "precond_steps": args.precond_steps, "inner_tol": args.inner_tol}
+        np.savez(args.out, params=net.get_params(), meta=json.dumps(meta))
+        log("wrote", args.out)
+    net.close()
+
+
+if __name__ == "__main__":
+    main()

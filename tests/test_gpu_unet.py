@@ -1,0 +1,195 @@
+"""GPU parity of the learned preconditioner's kernels against the U-Net reference
+(oracle/unet.py, float64 with the same BF16 operand rounding), its training step,
+and what it gains inside the solver.
+
+Bars: the GPU rounds the same operands (BF16 weights, activations split into two BF16
+parts) and accumulates in FP32 where the reference accumulates in float64, so results
+differ by accumulation order (~1e-6 relative per sum) plus rare rounding flips of an
+operand part whose FP32 value sits next to a rounding boundary (a 2^-16 relative change
+of one term, which the split keeps from compounding).  Network output and loss:
+rel L2 <= 1e-4; parameter gradients per layer: rel L2 <= 1e-3."""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from paper_1610_00835_amd import inputs
+from tests.gpu_util import log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = (16, 32, 64)
+
+
+@pytest.fixture(scope="module")
+def ev():
+    from paper_1610_00835_amd import ertvie
+    ertvie.load()
+    return ertvie
+
+
+def _rand(n, B, seed):
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(n))
+    r = rng.standard_normal((B, N))
+    e = rng.standard_normal((B, N)) * 3.0
+    st = rng.uniform(1.0, 50.0, (B, N))
+    ss = st * rng.uniform(0.5, 0.99, (B, N))
+    return r, e, st, ss
+
+
+def _params(seed, widths=WIDTHS):
+    from paper_1610_00835_amd import learn
+    p = learn.init_params(widths, seed)
+    rng = np.random.default_rng(seed + 1)
+    layers = U.unpack(p.astype(np.float64), widths)
+    for W, b in layers:
+        b[...] = rng.uniform(-0.05, 0.05, b.shape)
+    return U.pack(layers).astype(np.float32)
+
+
+def _oracle_inputs(r, st, ss, n):
+    X, S = [], []
+    for b in range(r.shape[0]):
+        F, s = U.features(r[b], st[b], ss[b], n)
+        X.append(F.astype(np.float32).astype(np.float64))
+        S.append(s)
+    return np.stack(X), np.array(S)
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,B", [((8, 8, 8), 2), ((16, 8, 12), 1)])
+def test_forward_matches_reference(ev, n, B):
+    import torch
+    r, e, st, ss = _rand(n, B, 1)
+    p = _params(3)
+    with ev.Net(n, batch_max=B) as net:
+        net.set_params(p)
+        z = torch.empty((B, int(np.prod(n))), dtype=torch.float64, device="cuda")
+        net.forward(_dev(r), _dev(st), _dev(ss), z)
+        zg = _host(z)
+        z2 = torch.empty_like(z)
+        net.forward(_dev(r), _dev(st), _dev(ss), z2)
+        assert np.array_equal(zg, _host(z2))            # deterministic
+        if B > 1:                                       # batch = columns one by one
+            z1 = torch.empty((1, z.shape[1]), dtype=torch.float64, device="cuda")
+            net.forward(_dev(r[1:2]), _dev(st[1:2]), _dev(ss[1:2]), z1)
+            assert np.array_equal(_host(z1)[0], zg[1])
+    X, S = _oracle_inputs(r, st, ss, n)
+    Y = U.forward(p.astype(np.float64), X, WIDTHS, bf16=True)
+    ref = Y.reshape(B, -1) * S[:, None]
+    # z = r + s y: compare the network part
+    err = rel_l2(zg - r, ref)
+    log("unet forward", n, B, "rel L2 vs reference", err)
+    assert err <= 1e-4
+    z0 = U.precondition(p.astype(np.float64), r[0], st[0], ss[0], n, WIDTHS, bf16=True)
+    assert rel_l2(zg[0], z0) <= 1e-4
+
+
+def test_gradient_matches_reference(ev):
+    n, B = (8, 8, 8), 2
+    r, e, st, ss = _rand(n, B, 4)
+    p = _params(5)
+    with ev.Net(n, batch_max=B) as net:
+        net.set_params(p)
+        loss, g = net.grad(_dev(r), _dev(e), _dev(st), _dev(ss))
+    X, S = _oracle_inputs(r, st, ss, n)
+    T = np.stack([U.target(r[b], e[b]).astype(np.float32).astype(np.float64).reshape(n[2], n[1], n[0])
+                  for b in range(B)])
+    Lr, gr = U.loss_and_grad(p.astype(np.float64), X, T, WIDTHS, bf16=True)
+    log("unet loss gpu", loss, "reference", Lr)
+    assert abs(loss - Lr) <= 1e-4 * abs(Lr)
+    o = 0
+    for li, (co, ci, k) in enumerate(U.layer_shapes(WIDTHS)):
+        nw = co * ci * k ** 3
+        for name, a, b in (("W", o, o + nw), ("b", o + nw, o + nw + co)):
+            e_ = rel_l2(g[a:b].astype(np.float64), gr[a:b])
+            log("  layer", li + 1, name, "rel L2", e_)
+            assert e_ <= 1e-3, (li + 1, name, e_)
+        o += nw + co
+    assert o == g.size
+
+
+def test_adam_step_matches_reference(ev):
+    n, B = (8, 8, 8), 2
+    r, e, st, ss = _rand(n, B, 6)
+    p = _params(7)
+    with ev.Net(n, batch_max=B) as net:
+        net.set_params(p)
+        _, g = net.grad(_dev(r), _dev(e), _dev(st), _dev(ss))
+        net.train_step(_dev(r), _dev(e), _dev(st), _dev(ss), lr=2e-3)
+        q = net.get_params()
+    ref, _, _ = U.adam_step(p.astype(np.float64), g.astype(np.float64), np.zeros(p.size), np.zeros(p.size), 1,
+                            lr=2e-3)
+    assert np.max(np.abs(q - ref)) <= 1e-6
+
+
+def test_training_reduces_loss(ev):
+    from paper_1610_00835_amd import learn
+    n, B = (8, 8, 8), 4
+    r, e, st, ss = _rand(n, B, 8)
+    e = r * 3.0 + 0.5 * np.roll(r, 1, axis=1)      # a learnable map
+    with ev.Net(n, batch_max=B) as net:
+        net.set_params(learn.init_params(WIDTHS, 9))
+        args = (_dev(r), _dev(e), _dev(st), _dev(ss))
+        L0 = net.train_step(*args, lr=1e-3)
+        for _ in range(60):
+            L = net.train_step(*args, lr=1e-3)
+    log("training loss", L0, "->", L)
+    assert L < 0.5 * L0
+
+
+def _c5_case(n, seed):
+    return inputs.make_case("c5", n=n, seed=seed)
+
+
+def test_learned_preconditioner_gain_and_judge(ev):
+    """16^3 media from the 128^3 recipe (base sigma_t in [5, 50] plus blobs, albedo 0.99).
+    Train on the pairs of plain solves of 6 media, then solve a held-out medium: the
+    preconditioned solve reaches the same 1e-8 true residual with fewer operator
+    applications than plain GMRES.  A network with zero parameters (output zero) has
+    every preconditioned step rejected by the residual check, and the plain fallback
+    still converges."""
+    import torch
+    from paper_1610_00835_amd import learn
+    n = (16, 16, 16)
+    pairs = learn.PairSet()
+    for s in range(1000, 1006):
+        case = _c5_case(n, s)
+        with ev.plan_from_case(case, method="direct", prec="fp64") as plan:
+            R, E, info = learn.collect_pairs(plan, case["f"], restart=3, tol=1e-10, max_pairs=60)
+        log("medium", s, "plain solve", info["iters"], "iters,", R.shape[0], "pairs")
+        pairs.add(R, E, case["sigma_t"], case["sigma_s"])
+    pairs.finalize()
+    with ev.Net(n, batch_max=4) as net:
+        net.set_params(learn.init_params(WIDTHS, 0))
+        losses = learn.train(net, pairs, steps=400, batch=4, lr=2e-3, seed=1, log_every=100, log=log)
+        case = _c5_case(n, 0)
+        fd = _dev(case["f"])
+        with ev.plan_from_case(case, method="direct", prec="fp64") as plan:
+            U0 = torch.empty_like(fd)
+            plain = plan.solve(fd, U0, tol=1e-8, max_iter=2000)
+            U1 = torch.empty_like(fd)
+            pre = plan.solve(fd, U1, tol=1e-8, max_iter=2000, precond=net, precond_steps=10, allow_noconv=True)
+            d = rel_l2(_host(U1), _host(U0))
+        log("plain", plain)
+        log("learned", pre, "difference of solutions", d)
+        assert losses[-1][1] < losses[0][1]
+        assert plain["converged"] == 1 and pre["converged"] == 1 and pre["rel_resid_true"] <= 1e-8
+        assert d <= 1e-6
+        assert pre["matvecs"] < plain["matvecs"]
+        net.set_params(np.zeros(net.size, dtype=np.float32))
+        with ev.plan_from_case(case, method="direct", prec="fp64") as plan:
+            U2 = torch.empty_like(fd)
+            zero = plan.solve(fd, U2, tol=1e-8, max_iter=2000, precond=net, precond_steps=10, allow_noconv=True)
+        log("zero network", zero)
+        assert zero["converged"] == 1 and zero["rejected"] >= 1 and zero["rejected"] == zero["restarts"]

@@ -126,11 +126,29 @@ def test_loss_is_relative_squared_error():
 
 
 def test_bf16_mode_changes_only_by_rounding():
+    """BF16 weights with split (hi + lo) activations: a perturbation at the level of the
+    weights' rounding (2^-9 relative), well above the activations' (2^-17)."""
     p, X, T = _problem(50)
     Y = U.forward(p, X, W_SMALL)
     Yb = U.forward(p, X, W_SMALL, bf16=True)
     d = np.linalg.norm(Yb - Y) / np.linalg.norm(Y)
     assert 1e-5 < d < 3e-2
+    a = np.random.default_rng(51).standard_normal(1000)
+    assert np.max(np.abs(U.bf16_split(a) - a.astype(np.float32)) / np.abs(a)) <= 2.0 ** -16
+
+
+def test_preconditioner_identity_part():
+    """With zero parameters the network outputs zero and z = r; the target of the exact
+    correction of r = e - K e is K e / s."""
+    n = (8, 8, 8)
+    rng = np.random.default_rng(52)
+    r = rng.standard_normal(512)
+    st = rng.uniform(1, 5, 512)
+    z = U.precondition(np.zeros(U.param_count(W_SMALL)), r, st, 0.5 * st, n, W_SMALL)
+    np.testing.assert_array_equal(z, r)
+    e = rng.standard_normal(512)
+    s = np.sqrt(np.mean(r ** 2))
+    np.testing.assert_allclose(U.target(r, e), (e - r) / s, rtol=1e-15)
 
 
 def test_adam_first_step_is_signed_learning_rate():
