@@ -93,6 +93,49 @@ def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None):
             "near_tflops": near_flops / (stage_ms["near"] * 1e-3) / 1e12 if stage_ms.get("near") else None}
 
 
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
+                       "precond_c5_64.npz")
+
+
+def many_scattering_solves(torch, ertvie, inputs, stream, args):
+    """Time to a 1e-8 true residual on the 64^3 many-scattering medium (base sigma_t ~ U[5,50]
+    plus blobs, albedo 0.99, one face source; held-out seed 0): plain FP64 GMRES on the FP64
+    FMM, the FP64-refined solve with FP32 inner GMRES on the order-4 FMM, and the same with the
+    trained network as right preconditioner (flexible GMRES) when its weights are present."""
+    case = inputs.make_case("c5", n=(64, 64, 64), seed=0)
+    fd = torch.from_numpy(case["f"]).cuda()
+    out = {"workload": "64^3 many-scattering medium, seed 0, tol 1e-8", "inner_cheb_n": 4}
+    t = time.perf_counter()
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, inner_cheb_n=4) as plan:
+        plan.fmm_info("fp64")
+        plan.fmm_info("fp32")
+        torch.cuda.synchronize()
+        out["plan_s"] = time.perf_counter() - t
+        U = torch.empty_like(fd)
+        keys = ("iters", "matvecs", "restarts", "t_solve", "rel_resid_true", "rejected", "precond_applies")
+        plan.solve(fd, U, tol=1e-8)                           # graphs and tuning of both operators
+        plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2)
+        r = plan.solve(fd, U, tol=1e-8)
+        out["plain_fp64_gmres"] = {k: r[k] for k in keys}
+        U0 = U.clone()
+        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2)
+        out["mixed"] = {k: r[k] for k in keys}
+        out["mixed_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        if os.path.exists(WEIGHTS):
+            w = np.load(WEIGHTS)
+            with ertvie.Net((64, 64, 64), stream=stream) as net:
+                net.set_params(w["params"])
+                plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, precond=net)
+                r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, precond=net)
+                out["mixed_learned"] = {k: r[k] for k in keys}
+                out["mixed_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        for k in ("mixed", "mixed_learned"):
+            if k in out:
+                out[k]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / out[k]["t_solve"]
+    log("many-scattering solves:", json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +232,9 @@ def main():
             log("solve:", json.dumps(extra["solve"]))
     plan.close()
 
+    if not args.no_solve and not args.no_c3:
+        extra["solve_many_scattering_64cubed"] = many_scattering_solves(torch, ertvie, inputs, stream, args)
+
     if not args.no_c3:
         # 64^3 heterogeneous blob medium with the ray-quadrature kernel (cached pair translations)
         c3 = inputs.make_case("c3", seed=0)
@@ -225,7 +271,8 @@ def main():
                "sample": "%d full dense FP64 applies of (I - K) on the 32^3 workload, %.2f s each" % (reps, dt)}
         log("cpu oracle:", json.dumps(cpu))
 
-    out = {"metric": "FMM matvec Mpts/s", "value": value, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
+    out = {"metric": "FMM matvec Mpts/s; time to 1e-8 solve, plain FP64 GMRES vs mixed+learned (1 GPU)",
+           "value": value, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32"}[args.prec],
            "data": "synthetic",

@@ -102,6 +102,11 @@ typedef struct {
                          compressed far-field translations (shared orthonormal basis per
                          level from the SVD of all translation matrices); 0 -> 1e-6,
                          < 0 -> no compression */
+    int inner_cheb_n; /* FMM: Chebyshev nodes per axis of the FP32 and BF16x3 applies (the
+                         inner operator of mixed solves); 0 -> cheb_n; 2..8.  The far-field
+                         translations cost n^(2d) per box pair, so a lower order makes the inner
+                         solves cheaper; the FP64 outer residual keeps the accuracy */
+    int reserved0;    /* must be 0 */
 } ert_vie_opts;
 
 typedef struct {
@@ -119,7 +124,7 @@ typedef struct {
     int reserved[1];  /* must be 0 */
     ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
                          becomes a refinement loop.  Each step solves (I - K) d = r by flexible
-                         GMRES with z = net(v) (inner operator: FP32 with `mixed`, else the
+                         GMRES with z_j = net(v_j) (inner operator: FP32 with `mixed`, else the
                          plan's), and is kept only if the true residual phi - (I - K)(U + d)
                          of the outer operator (FP64 with `mixed`, else the plan's) is smaller
                          than before; otherwise plain GMRES with the same budget replaces it.

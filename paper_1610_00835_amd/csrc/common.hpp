@@ -178,7 +178,7 @@ struct ert_plan_impl {
     double* d_red = nullptr;     // reduction partials / small vectors
     size_t red_elems = 0;
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
-    HetCache* het = nullptr;     // heterogeneous kernel caches, shared by the precisions
+    HetCache* het[2] = {nullptr, nullptr};   // heterogeneous kernel caches (per Chebyshev order)
     Profiler prof;
     bool use_graphs = true;      // FMM applies replay captured graphs
 };

@@ -863,11 +863,12 @@ struct FmmImpl : FmmData {
 };
 
 // Build the tree geometry for a plan.
-FmmTree make_tree(const ert_plan_impl* p)
+FmmTree make_tree(const ert_plan_impl* p, int prec)
 {
     FmmTree t;
     t.D = p->o.dim;
     t.nc = p->o.cheb_n > 0 ? p->o.cheb_n : 8;
+    if (prec != ERT_FP64 && p->o.inner_cheb_n > 0) t.nc = p->o.inner_cheb_n;
     t.K = 1;
     for (int a = 0; a < t.D; ++a) t.K *= t.nc;
     t.Kp = (t.K + 31) / 32 * 32;
@@ -1034,13 +1035,27 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
 template <typename T>
 ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
 {
-    if (p->het) {
-        if (p->het->nc != tr.nc || p->het->leaf != tr.leaf) {
-            record_error("FMM: heterogeneous cache built for another tree");
+    HetCache* other = nullptr;
+    int slot = -1;
+    for (int i = 0; i < 2; ++i) {
+        HetCache* c = p->het[i];
+        if (!c) {
+            if (slot < 0) slot = i;
+            continue;
+        }
+        if (c->leaf != tr.leaf) {
+            record_error("FMM: heterogeneous cache built for another leaf size");
             return ERT_EINVAL;
         }
-        hc = p->het;
-        return ERT_OK;
+        if (c->nc == tr.nc) {
+            hc = c;
+            return ERT_OK;
+        }
+        other = c;
+    }
+    if (slot < 0) {
+        record_error("FMM: no free heterogeneous cache slot");
+        return ERT_EINVAL;
     }
     hipStream_t s = p->stream;
     HetCache* c = new (std::nothrow) HetCache();
@@ -1049,6 +1064,21 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     c->leaf = tr.leaf;
     auto fail = [&](ert_status e) { delete c; return e; };
     const int nn = tr.D == 3 ? 27 : 9;
+    if (other) {
+        // the near field does not depend on the Chebyshev order: share it
+        c->owns_near = false;
+        c->nearblk = other->nearblk;
+        c->near_src = other->near_src;
+        c->near_tstart = other->near_tstart;
+        for (int l = 2; l <= tr.L; ++l) {
+            ert_status st = het_far_level(p, tr, cheb, c, l);
+            if (st != ERT_OK) return fail(st);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(ERT_EDEVICE);
+        p->het[slot] = c;
+        hc = c;
+        return ERT_OK;
+    }
     const long per = (long)nn * tr.S * tr.S;
     const size_t bytes = (size_t)tr.nleaf * per * sizeof(float);
     size_t fr = 0, tot = 0;
@@ -1091,7 +1121,7 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, c, l);
     if (st == ERT_OK && hipStreamSynchronize(s) != hipSuccess) st = ERT_EDEVICE;
     if (st != ERT_OK) return fail(st);
-    p->het = c;
+    p->het[slot] = c;
     hc = c;
     return ERT_OK;
 }
@@ -1099,7 +1129,7 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
 template <typename T>
 ert_status FmmImpl<T>::setup(ert_plan_impl* p)
 {
-    tr = make_tree(p);
+    tr = make_tree(p, prec);
     hetero = p->o.kernel == ERT_K_RAY_MIDPOINT;
     if (tr.L > kMaxLevels) {
         record_error("FMM: grid too large for the tree depth limit");
@@ -1610,7 +1640,9 @@ void fmm_destroy(FmmData* f) { delete f; }
 HetCache::~HetCache()
 {
     auto f = [](void* q) { if (q) (void)hipFree(q); };
-    f(nearblk); f(near_src); f(near_tstart);
+    if (owns_near) {
+        f(nearblk); f(near_src); f(near_tstart);
+    }
     for (int l = 0; l <= kMaxLevels; ++l) {
         f(hops[l]); f(pstart[l]); f(psrc[l]);
     }

@@ -126,6 +126,7 @@ ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
 // interpolation error of the far field).
 struct HetCache {
     int nc = 0, leaf = 0;                   // tree the cache was built for
+    bool owns_near = true;                  // false: the near part belongs to another order's cache
     float* nearblk = nullptr;               // [leaf][3^d][S][S] (target fastest)
     int* near_src = nullptr;                // [leaf * 3^d] source leaf, -1 outside the grid
     long* near_tstart = nullptr;            // [nleaf + 1]

@@ -318,32 +318,42 @@ __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
         }
 }
 
-// per target: sum of its staged pair rows in increasing offset order.  The
-// rows of one target are consecutive threads (M >= 64), so the pair indices
-// are wave-uniform; 16 row loads are issued before they are summed.
+// Per-target sums of the staged pair products, in a fixed order: one workgroup
+// per (target, 64-row slab, rhs); its four waves sum four consecutive quarters
+// of the target's pair list (8 row loads in flight per lane) and wave 0 adds
+// the quarters in order.
 template <typename T>
-__global__ void k_stage_reduce(OffsetGemm g)
+__global__ __launch_bounds__(256) void k_stage_reduce(OffsetGemm g, int rslabs)
 {
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const long per = g.nbox * g.M;
-    if (i >= per * g.B) return;
-    const int b = (int)(i / per);
-    const long rem = i - (long)b * per;
-    const long t = rem / g.M;
-    const int r = (int)(rem - t * g.M);
-    const T* St = (const T*)g.stage + (long)b * g.pl.npairs * g.M + r;
-    const int k1 = g.pl.tstart[t + 1];
-    int k = g.pl.tstart[t];
+    __shared__ T part[3][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    long blk = blockIdx.x;
+    const int rs = (int)(blk % rslabs);
+    blk /= rslabs;
+    const long t = blk % g.nbox;
+    const int b = (int)(blk / g.nbox);
+    const int r = rs * 64 + lane;
+    const bool ok = r < g.M;
+    const T* St = (const T*)g.stage + (long)b * g.pl.npairs * g.M + (ok ? r : 0);
+    const int k0 = g.pl.tstart[t], k1 = g.pl.tstart[t + 1];
+    const int per = (k1 - k0 + 3) / 4;
+    const int a0 = k0 + wave * per;
+    const int a1 = (a0 + per) < k1 ? (a0 + per) : k1;
     T s = T(0);
-    for (; k + 16 <= k1; k += 16) {
-        T v[16];
+    int k = a0;
+    for (; k + 8 <= a1; k += 8) {
+        T v[8];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = St[(long)g.pl.tpairs[k + u] * g.M];
+        for (int u = 0; u < 8; ++u) v[u] = St[(long)g.pl.tpairs[k + u] * g.M];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s += v[u];
+        for (int u = 0; u < 8; ++u) s += v[u];
     }
-    for (; k < k1; ++k) s += St[(long)g.pl.tpairs[k] * g.M];
-    T* d = (T*)g.L + i;
+    for (; k < a1; ++k) s += St[(long)g.pl.tpairs[k] * g.M];
+    if (wave > 0) part[wave - 1][lane] = s;
+    __syncthreads();
+    if (wave != 0 || !ok) return;
+    s = s + part[0][lane] + part[1][lane] + part[2][lane];
+    T* d = (T*)g.L + ((long)b * g.nbox + t) * g.M + r;
     *d = g.accumulate ? *d + s : s;
 }
 
@@ -559,11 +569,12 @@ ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
 
 ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g)
 {
-    const long n = g.nbox * g.M * g.B;
+    const int rslabs = (g.M + 63) / 64;
+    const long nblk = g.nbox * rslabs * g.B;
     if (prec == ERT_FP64)
-        hipLaunchKernelGGL(k_stage_reduce<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+        hipLaunchKernelGGL(k_stage_reduce<double>, dim3((unsigned)nblk), dim3(256), 0, s, g, rslabs);
     else
-        hipLaunchKernelGGL(k_stage_reduce<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+        hipLaunchKernelGGL(k_stage_reduce<float>, dim3((unsigned)nblk), dim3(256), 0, s, g, rslabs);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }

@@ -31,7 +31,8 @@ class VieOpts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
                 ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
                 ("cheb_n", ctypes.c_int), ("leaf", ctypes.c_int), ("nrhs_max", ctypes.c_int),
-                ("flags", ctypes.c_int), ("svd_tol", ctypes.c_double)]
+                ("flags", ctypes.c_int), ("svd_tol", ctypes.c_double), ("inner_cheb_n", ctypes.c_int),
+                ("reserved0", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -154,7 +155,7 @@ class Plan:
     """
 
     def __init__(self, dim, n, h, sigma_t, sigma_s, kernel=K_HOMOGENEOUS, method="direct", prec="fp64",
-                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0):
+                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0, inner_cheb_n=0):
         L = load()
         n = list(n)[:dim]
         self.dim = int(dim)
@@ -173,6 +174,7 @@ class Plan:
         o.nrhs_max = int(nrhs_max)
         o.flags = 0
         o.svd_tol = float(svd_tol)
+        o.inner_cheb_n = int(inner_cheb_n)
         self.opts = o
         st_h = _f64_host(sigma_t, self.N)
         ss_h = _f64_host(sigma_s, self.N)
@@ -282,10 +284,11 @@ class Plan:
             pass
 
 
-def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0):
+def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0,
+                   inner_cheb_n=0):
     return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
                 method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream,
-                svd_tol=svd_tol)
+                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n)
 
 
 def _load_net():

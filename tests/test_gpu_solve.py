@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1610_00835_amd import inputs
-from tests.gpu_util import log, oracle_problem, rel_l2, to_dev, to_host
+from tests.gpu_util import gpu_apply, log, oracle_problem, rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -140,3 +140,25 @@ def test_solve_fmm_mixed_c2(ev, oracle_mod):
     res = np.linalg.norm(phi_rows - au_rows) / np.linalg.norm(phi_rows)
     log("c2 mixed fmm solve", ig, "oracle residual on rows", res)
     assert res <= 1e-6
+
+
+@pytest.mark.parametrize("name,n,leaf", [("c3", (16, 16, 16), 4), ("c2", (32, 32, 32), 8)])
+def test_mixed_solve_low_order_inner_operator(ev, oracle_mod, name, n, leaf):
+    """FP32 inner operator at Chebyshev order 4 (the FP64 outer operator keeps order 8): the
+    inner applies are cheaper and coarser (error ~1e-4), and the refinement still reaches the
+    FP64 operator's solution at a 1e-9 true residual."""
+    case = inputs.make_case(name, n=n, seed=3)
+    P = oracle_problem(oracle_mod, case)
+    x = inputs.random_vector(P.N, 15)
+    rows = np.random.default_rng(9).choice(P.N, size=200, replace=False)
+    ref = P.apply_rows(x, rows, op=2)
+    with ev.plan_from_case(case, method="fmm", prec="fp64", leaf=leaf, inner_cheb_n=4) as plan:
+        assert plan.fmm_info("fp64")["cheb_n"] == 8 and plan.fmm_info("fp32")["cheb_n"] == 4
+        e64 = rel_l2(gpu_apply(plan, x, ev.OP_A)[rows], ref)
+        e32 = rel_l2(gpu_apply(plan, x, ev.OP_A, prec="fp32")[rows], ref)
+        Um, im = _solve(plan, case["f"], tol=1e-9, mixed=True, inner_tol=1e-3)
+        U64, i64 = _solve(plan, case["f"], tol=1e-10)
+    log(name, "inner order 4: fp64 apply", e64, "fp32 order-4 apply", e32, "mixed", im, "fp64", i64)
+    assert e64 <= 2e-5 and e32 <= 1e-2
+    assert im["converged"] == 1 and im["rel_resid_true"] <= 1e-9
+    assert rel_l2(Um, U64) <= 1e-7
