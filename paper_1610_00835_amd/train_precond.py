@@ -26,11 +26,13 @@ def log(*a):
 
 
 def plan_for(case, args, prec="fp64"):
-    return ertvie.plan_from_case(case, method="fmm", prec=prec, leaf=args.leaf, cheb_n=args.cheb_n)
+    return ertvie.plan_from_case(case, method="fmm", prec=prec, leaf=args.leaf, cheb_n=args.cheb_n,
+                                 inner_cheb_n=args.inner_cheb_n)
 
 
 def compare(net, case, args):
-    """Plain FP64 GMRES vs the FP64-refined, FP32-inner, learned-preconditioned solve."""
+    """Plain FP64 GMRES vs the FP64-refined solve with FP32 inner GMRES on the lower-order
+    operator, with and without the network as right preconditioner."""
     import torch
     fd = torch.as_tensor(np.ascontiguousarray(case["f"])).cuda()
     out = {}
@@ -69,6 +71,7 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--leaf", type=int, default=8)
     ap.add_argument("--cheb-n", type=int, default=0)
+    ap.add_argument("--inner-cheb-n", type=int, default=4, help="Chebyshev order of the FP32 inner operator")
     ap.add_argument("--precond-steps", type=int, default=10)
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=3000)
