@@ -93,6 +93,52 @@ def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None):
             "near_tflops": near_flops / (stage_ms["near"] * 1e-3) / 1e12 if stage_ms.get("near") else None}
 
 
+def many_scattering_128(torch, ertvie, inputs, O, stream, args):
+    """The many-scattering recipe at its full 128^3 size (N = 2,097,152): heterogeneous
+    caches for the FP64 operator at Chebyshev order 6 (at order 8 the far field alone would
+    need 640 GB) and for the order-4 FP32 inner operator, sharing the near blocks; apply
+    times, the apply error on sampled rows against the oracle, and time to 1e-8 for plain
+    FP64 GMRES and the mixed solve (with the network when weights for this grid exist)."""
+    case = inputs.make_case("c5", n=(128, 128, 128), seed=0)
+    N = int(np.prod(case["n"]))
+    fd = torch.from_numpy(case["f"]).cuda()
+    out = {"workload": "128^3 many-scattering medium, seed 0, leaf 8^3, n = 6 (FP64) / 4 (FP32 inner)"}
+    torch.cuda.empty_cache()
+    t = time.perf_counter()
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=6, inner_cheb_n=4) as plan:
+        out["fmm_fp64"] = plan.fmm_info("fp64")
+        log("128^3: FP64 operator built, %.1f s" % (time.perf_counter() - t))
+        plan.fmm_info("fp32")
+        torch.cuda.synchronize()
+        out["plan_s"] = time.perf_counter() - t
+        log("128^3: plan %.1f s" % out["plan_s"])
+        x = torch.from_numpy(inputs.random_vector(N, 21)).cuda()
+        y = torch.empty_like(x)
+        for prec in ("fp64", "fp32"):
+            out["apply_ms_" + prec] = timed_applies(torch, plan, x, y, ertvie.OP_A, 5, 2, prec=prec)
+            if prec == "fp64":
+                yh = y.cpu().numpy()
+        log("128^3 apply ms: fp64 %.2f, fp32 inner %.2f" % (out["apply_ms_fp64"], out["apply_ms_fp32"]))
+        P = O.Problem(3, case["n"], case["h"], 1, case["sigma_t"], case["sigma_s"])
+        rows = np.random.default_rng(3).choice(N, size=32, replace=False)
+        yo = P.apply_rows(inputs.random_vector(N, 21), rows, op=2)
+        out["fp64_apply_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(yh[rows] - yo) / np.linalg.norm(yo))
+        log("128^3 apply error on 32 rows: %.3e" % out["fp64_apply_rel_l2_vs_oracle_rows"])
+        U = torch.empty_like(fd)
+        keys = ("iters", "matvecs", "restarts", "t_solve", "rel_resid_true", "rejected", "precond_applies")
+        # the Krylov basis is allocated for max_iter vectors (16.8 MB each at this size)
+        r = plan.solve(fd, U, tol=1e-8, max_iter=150)
+        out["plain_fp64_gmres"] = {k: r[k] for k in keys}
+        log("128^3 plain:", json.dumps(out["plain_fp64_gmres"]))
+        U0 = U.clone()
+        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, max_iter=150)
+        out["mixed"] = {k: r[k] for k in keys}
+        out["mixed"]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / r["t_solve"]
+        out["mixed_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        log("128^3 mixed:", json.dumps(out["mixed"]))
+    return out
+
+
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
                        "precond_c5_64.npz")
 
@@ -145,6 +191,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--c5-128", action="store_true",
+                    help="also run the 128^3 many-scattering medium (plan ~1 min, ~250 GB of device memory)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three 256 MiB device copies (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -236,6 +284,9 @@ def main():
 
     if not args.no_solve and not args.no_c3:
         extra["solve_many_scattering_64cubed"] = many_scattering_solves(torch, ertvie, inputs, stream, args)
+
+    if args.c5_128:
+        extra["many_scattering_128cubed"] = many_scattering_128(torch, ertvie, inputs, O, stream, args)
 
     if not args.no_c3:
         # 64^3 heterogeneous blob medium with the ray-quadrature kernel (cached pair translations)

@@ -687,12 +687,15 @@ struct GemmSite {
     bool used = false;
     PairTiles pl;                         // device arrays of the offset-stationary form
     std::vector<int> h_gstart;            // host copy, to rebuild tiles for a larger rhs capacity
-    int choice[2] = {-1, -1};             // per rhs bucket (1, >1): 0 class GEMM, 1 offset-stationary
-    float tuned_ms[2][2] = {{0, 0}, {0, 0}};
+    // per rhs bucket (1, >1): 0 class GEMM, 1 offset-stationary with 16-column tiles,
+    // 2 offset-stationary with 64-column tiles
+    int choice[2] = {-1, -1};
+    float tuned_ms[2][3] = {{0, 0, 0}, {0, 0, 0}};
     void release()
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
         f(pl.pt); f(pl.ps); f(pl.gstart); f(pl.gop); f(pl.tile_group); f(pl.tile_col0); f(pl.tstart); f(pl.tpairs);
+        f(pl.tile_group4); f(pl.tile_col04);
         pl = PairTiles();
     }
 };
@@ -754,20 +757,24 @@ ert_status build_site(hipStream_t s, int D, const int nl[3], bool far, GemmSite&
 // column tiles (16 pair-rhs columns each) for a rhs capacity B
 ert_status build_tiles(hipStream_t s, GemmSite& site, int B)
 {
-    std::vector<int> tg, tc;
-    for (int g = 0; g + 1 < (int)site.h_gstart.size(); ++g) {
-        const long ncols = (long)(site.h_gstart[g + 1] - site.h_gstart[g]) * B;
-        for (long c = 0; c < ncols; c += 16) {
-            tg.push_back(g);
-            tc.push_back((int)c);
+    for (int width : {16, 64}) {
+        std::vector<int> tg, tc;
+        for (int g = 0; g + 1 < (int)site.h_gstart.size(); ++g) {
+            const long ncols = (long)(site.h_gstart[g + 1] - site.h_gstart[g]) * B;
+            for (long c = 0; c < ncols; c += width) {
+                tg.push_back(g);
+                tc.push_back((int)c);
+            }
         }
+        int** grp = width == 16 ? &site.pl.tile_group : &site.pl.tile_group4;
+        int** col = width == 16 ? &site.pl.tile_col0 : &site.pl.tile_col04;
+        if (*grp) (void)hipFree(*grp);
+        if (*col) (void)hipFree(*col);
+        *grp = *col = nullptr;
+        ERT_TRY(upload<int>(s, grp, tg));
+        ERT_TRY(upload<int>(s, col, tc));
+        (width == 16 ? site.pl.ntiles : site.pl.ntiles4) = (long)tg.size();
     }
-    if (site.pl.tile_group) (void)hipFree(site.pl.tile_group);
-    if (site.pl.tile_col0) (void)hipFree(site.pl.tile_col0);
-    site.pl.tile_group = site.pl.tile_col0 = nullptr;
-    ERT_TRY(upload<int>(s, &site.pl.tile_group, tg));
-    ERT_TRY(upload<int>(s, &site.pl.tile_col0, tc));
-    site.pl.ntiles = (long)tg.size();
     return ERT_OK;
 }
 
@@ -1319,6 +1326,7 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         o.L = b.L;
         o.stage = stage;
         o.accumulate = b.accumulate;
+        o.tn = 1;
         o.pl = gs.pl;
         return o;
     };
@@ -1328,28 +1336,36 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         BoxGemm gt = g;
         gt.L = tune;
         gt.accumulate = 0;
-        const OffsetGemm ot = as_offset(gt);
+        OffsetGemm ot = as_offset(gt), ot4 = as_offset(gt);
+        ot4.tn = 4;
         hipEvent_t e[3];
         for (auto& ev : e) ERT_HIP(hipEventCreate(&ev));
-        float ms[2] = {0.f, 0.f};
+        float ms[3] = {0.f, 0.f, 0.f};
         ert_status st = ERT_OK;
-        for (int form = 0; form < 2 && st == ERT_OK; ++form) {
-            st = form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot);   // warm-up
+        auto run = [&](int form) {
+            return form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, form == 1 ? ot : ot4);
+        };
+        for (int form = 0; form < 3 && st == ERT_OK; ++form) {
+            st = run(form);   // warm-up
             if (st != ERT_OK) break;
             (void)hipEventRecord(e[0], s);
-            for (int r = 0; r < 3 && st == ERT_OK; ++r) st = form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot);
+            for (int r = 0; r < 3 && st == ERT_OK; ++r) st = run(form);
             (void)hipEventRecord(e[1], s);
             if (hipEventSynchronize(e[1]) != hipSuccess) st = ERT_EDEVICE;
             else (void)hipEventElapsedTime(&ms[form], e[0], e[1]);
         }
         for (auto& ev : e) (void)hipEventDestroy(ev);
         ERT_TRY(st);
-        gs.tuned_ms[bucket][0] = ms[0] / 3;
-        gs.tuned_ms[bucket][1] = ms[1] / 3;
-        gs.choice[bucket] = ms[1] < ms[0] ? 1 : 0;
+        int best = 0;
+        for (int form = 0; form < 3; ++form) {
+            gs.tuned_ms[bucket][form] = ms[form] / 3;
+            if (ms[form] < ms[best]) best = form;
+        }
+        gs.choice[bucket] = best;
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
-    const OffsetGemm og = as_offset(g);
+    OffsetGemm og = as_offset(g);
+    og.tn = gs.choice[bucket] == 2 ? 4 : 1;
     ERT_TRY(offset_gemm_products(s, gprec, og));
     if (outer) outer->stop();
     StageTimer sr_(&p->prof, s, ERT_STAGE_REDUCE);

@@ -75,6 +75,9 @@ struct PairTiles {
     int* gop = nullptr;       // [ngroups] operator slot of the group
     int* tile_group = nullptr;   // [ntiles]
     int* tile_col0 = nullptr;    // [ntiles] first (pair, rhs) column of the tile
+    long ntiles4 = 0;            // the same with 64-column tiles (four column blocks per workgroup)
+    int* tile_group4 = nullptr;
+    int* tile_col04 = nullptr;
     int* tstart = nullptr;    // [nbox + 1] pairs of each target (CSR, increasing group order)
     int* tpairs = nullptr;    // [npairs]
 };
@@ -89,6 +92,7 @@ struct OffsetGemm {
     void* L;                  // [B][nbox][M]
     void* stage;              // [B][npairs][M]
     int accumulate;
+    int tn;                   // column blocks of 16 per workgroup: 1 or 4
     PairTiles pl;
 };
 

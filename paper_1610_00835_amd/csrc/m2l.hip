@@ -554,7 +554,21 @@ ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
         record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
         return ERT_EINVAL;
     }
-    if (g.pl.ntiles > 0) {
+    if (g.tn == 4) {
+        if (g.pl.ntiles4 > 0) {
+            OffsetGemm g4 = g;
+            g4.pl.tile_group = g.pl.tile_group4;
+            g4.pl.tile_col0 = g.pl.tile_col04;
+            dim3 grid((unsigned)g.pl.ntiles4, (unsigned)(g.M / (16 * kTM)));
+            if (prec == ERT_FP64)
+                hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, kTM, 4>), grid, dim3(64 * kWaves), 0, s, g4);
+            else if (prec == ERT_FP32)
+                hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, kTM, 4>), grid, dim3(64 * kWaves), 0, s, g4);
+            else
+                hipLaunchKernelGGL((k_offset_gemm<ERT_BF16X3, kTM, 4>), grid, dim3(64 * kWaves), 0, s, g4);
+            ERT_HIP(hipGetLastError());
+        }
+    } else if (g.pl.ntiles > 0) {
         dim3 grid((unsigned)g.pl.ntiles, (unsigned)(g.M / (16 * kTM)));
         if (prec == ERT_FP64)
             hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);

@@ -10,12 +10,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     with open(os.path.join(ROOT, "include", "ertvie.h")) as fh:
         src = fh.read()
-    return sorted(set(re.findall(r"ERT_API\s+[\w\s\*]+?\b(ert_vie_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"ERT_API\s+[\w\s\*]+?\b(ert_(?:vie|net)_\w+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for must in ("ert_vie_plan", "ert_vie_apply", "ert_vie_solve", "ert_vie_destroy", "ert_vie_strerror"):
+    for must in ("ert_vie_plan", "ert_vie_apply", "ert_vie_solve", "ert_vie_destroy", "ert_vie_strerror",
+                 "ert_net_create", "ert_net_forward", "ert_net_grad", "ert_net_train_step", "ert_net_destroy"):
         assert must in names
 
 
@@ -64,7 +65,41 @@ def test_plan_rejects_bad_arguments_before_device_use():
     assert plan(h=float("nan")) == ertvie.EINVAL
     assert plan(flags=1) == ertvie.EINVAL
     assert plan(cheb_n=12) == ertvie.EINVAL
+    assert plan(inner_cheb_n=1) == ertvie.EINVAL
+    assert plan(inner_cheb_n=9) == ertvie.EINVAL
+    assert plan(reserved0=1) == ertvie.EINVAL
     assert plan(st=np.where(np.arange(N) == 3, -1.0, 2.0)) == ertvie.EINVAL
     assert plan(ss=np.full(N, 2.5)) == ertvie.EINVAL           # absorption < 0
     assert plan(ss=np.full(N, -0.1)) == ertvie.EINVAL
     assert plan(st=np.linspace(1, 2, N)) == ertvie.EINVAL      # homogeneous kernel needs constant sigma_t
+
+
+def test_network_arguments_without_gpu():
+    """Parameter counts (the canonical layout) and argument checks of the network ABI."""
+    from oracle import unet as U
+    from paper_1610_00835_amd import ertvie
+    ertvie._load_net()
+    assert ertvie.Net.param_count() == U.param_count()
+    assert ertvie.Net.param_count((16, 16, 32)) == U.param_count((16, 16, 32))
+    L = ertvie.load()
+    h = ctypes.c_void_p()
+
+    def create(**kw):
+        o = ertvie.NetOpts()
+        o.dim = kw.pop("dim", 3)
+        n = kw.pop("n", (8, 8, 8))
+        for a in range(3):
+            o.n[a] = n[a]
+        for k, v in kw.items():
+            if k == "width":
+                for a in range(3):
+                    o.width[a] = v[a]
+            else:
+                setattr(o, k, v)
+        return L.ert_net_create(ctypes.byref(o), None, ctypes.byref(h))
+    assert create(dim=2) == ertvie.EUNSUPPORTED
+    assert create(n=(8, 6, 8)) == ertvie.EINVAL          # not a multiple of 4
+    assert create(width=(16, 24, 64)) == ertvie.EINVAL   # not a multiple of 16
+    assert L.ert_net_size(None) == -1
+    L.ert_net_destroy(None)
+    assert L.ert_net_forward(None, None, None, None, None, 1) == ertvie.EINVAL
