@@ -100,8 +100,10 @@ typedef struct {
     int flags;        /* reserved, must be 0 */
     double svd_tol;   /* FMM, homogeneous media: relative singular-value cutoff of the
                          compressed far-field translations (shared orthonormal basis per
-                         level from the SVD of all translation matrices); 0 -> 1e-6,
-                         < 0 -> no compression */
+                         level from the SVD of all translation matrices); 0 -> 1e-6
+                         (rank 256 of 512 at n = 8), < 0 -> no compression.  A looser cutoff
+                         lowers the rank (1e-5: rank 160) and the error grows with the number
+                         of compressed levels */
     int inner_cheb_n; /* FMM: Chebyshev nodes per axis of the FP32 and BF16x3 applies (the
                          inner operator of mixed solves); 0 -> cheb_n; 2..8.  The far-field
                          translations cost n^(2d) per box pair, so a lower order makes the inner

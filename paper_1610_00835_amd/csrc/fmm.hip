@@ -1285,7 +1285,7 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
     };
     ERT_TRY(site_need(near_site, tr.nleaf, tr.S));
     if (hetero) {
-        const size_t rb = (size_t)std::min(nrhs, 8);
+        const size_t rb = (size_t)std::min(nrhs, nrhs >= kPairMfmaMinRhs ? 64 : 8);
         st_need = std::max(st_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
         for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hc->hnp[l] * tr.Kp);
     }

@@ -117,10 +117,14 @@ struct PairStream {
     long nsrc;               // source boxes (W is [B][nsrc][Kd])
     const long* tstart;      // [ntarget + 1] contiguous pair range of each target
     const void* W;
-    void* stage;             // [min(B,8)][npairs][M]
+    void* stage;             // [min(B, 8)][npairs][M] (streaming) or [min(B, 64)][npairs][M] (matrix cores)
     void* L;                 // [B][ntarget][M]
     int accumulate;
 };
+
+// From this many right-hand sides on, cached-pair products run on the matrix cores
+// (64 right-hand sides per pass over the matrices; stage then holds min(B, 64) rows).
+constexpr int kPairMfmaMinRhs = 16;
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
 

@@ -473,6 +473,85 @@ __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
     }
 }
 
+// Many right-hand sides: per pair, stage[b][p][:] = opsT[p]^T-stored matrix times
+// W[b][src], i.e. an (M x Kd) x (Kd x 64) product on the matrix cores, reading the
+// FP32 matrix once for 64 right-hand sides (FP32 or FP64 accumulation; the FP64
+// form converts the stored FP32 values).  Workgroup: one pair and 64 RT rows per
+// wave-row block; the 64 source vectors are staged through LDS, 32 k at a time,
+// transposed so that lanes read consecutive columns.
+template <int PREC, int RT>
+__global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rblocks)
+{
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    constexpr int KC = 32;
+    constexpr int LDW = 80;                       // padded LDS row (columns)
+    __shared__ T wsh[KC * LDW];
+    const long p = blockIdx.x / rblocks;
+    const int rblk = (int)(blockIdx.x % rblocks);
+    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
+    const int s = g.src[p];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
+    const int row0 = (rblk * 4 + wave) * 16 * RT;
+    const float* A = (const float*)g.opsT + (size_t)p * g.Kd * g.M;
+    V acc[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
+    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * KC; i += 256) {
+            const int b = i / KC, kk = i - b * KC;
+            T v = T(0);
+            if (s >= 0 && b < nb && k0 + kk < g.Kd) v = ((const T*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k0 + kk];
+            wsh[kk * LDW + b] = v;
+        }
+        __syncthreads();
+        if (s < 0) continue;                      // empty pair: zero rows (uniform over the block)
+#pragma unroll 2
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int k = k0 + kk + grp;
+            T a[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const int row = row0 + 16 * rt + li;
+                a[rt] = (k < g.Kd && row < g.M) ? (T)A[(size_t)k * g.M + row] : T(0);
+            }
+            T bf[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) bf[ct] = wsh[(kk + grp) * LDW + 16 * ct + li];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    if constexpr (PREC == ERT_FP64)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+                    else
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+                }
+        }
+    }
+    // FP32 tiles: rows 4 grp + i; FP64 tiles: rows grp + 4 i (column li in both)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int b = 16 * ct + li;
+        if (b >= nb) continue;
+        T* dst = (T*)g.stage + ((long)b * g.npairs + p) * g.M;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int base = row0 + 16 * rt;
+            if constexpr (PREC == ERT_FP64) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (base + grp + 4 * i < g.M) dst[base + grp + 4 * i] = acc[rt][ct][i];
+            } else {
+                if (base + 4 * grp + 3 < g.M) *(V*)(dst + base + 4 * grp) = acc[rt][ct];
+            }
+        }
+    }
+}
+
 // Sum of the contiguous staging rows of every target, for rhs b0..b0+nb-1.
 template <typename T>
 __global__ void k_pair_reduce(PairStream g, int b0, int nb)
@@ -611,6 +690,25 @@ void launch_pair_stream(hipStream_t s, const PairStream& g, int b0, int rb)
     else hipLaunchKernelGGL((k_pair_stream<T, TS, 1, RPT>), grid, dim3(256), sh, s, g, b0);
 }
 
+// Matrix-core form for many right-hand sides (FP32 storage), 64 per pass.
+template <int PREC>
+ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
+{
+    constexpr int RT = (PREC == ERT_FP64) ? 4 : 8;
+    const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
+    for (int b0 = 0; b0 < g.B; b0 += 64) {
+        const int nb = std::min(64, g.B - b0);
+        hipLaunchKernelGGL((k_pair_mfma<PREC, RT>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s, g, b0,
+                           rblocks);
+        ERT_HIP(hipGetLastError());
+        const long n = g.ntarget * g.M * nb;
+        typedef typename Acc<PREC>::T T;
+        hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, nb);
+        ERT_HIP(hipGetLastError());
+    }
+    return ERT_OK;
+}
+
 // T: arithmetic and vectors; TS: stored matrices (FP32 caches under FP64 products).
 template <typename T, typename TS>
 ert_status pair_stream_t(hipStream_t s, const PairStream& g)
@@ -638,6 +736,8 @@ ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
 {
+    if (g.B >= kPairMfmaMinRhs && g.ops_f32 && g.M % 4 == 0 && g.npairs > 0)
+        return prec == ERT_FP64 ? pair_mfma_t<ERT_FP64>(s, g) : pair_mfma_t<ERT_FP32>(s, g);
     if (prec == ERT_FP64) return g.ops_f32 ? pair_stream_t<double, float>(s, g) : pair_stream_t<double, double>(s, g);
     return pair_stream_t<float, float>(s, g);
 }

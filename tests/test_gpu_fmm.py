@@ -246,3 +246,22 @@ def test_fmm_heterogeneous_many_rhs(ev, oracle_mod):
             assert np.max(np.abs(yb - Y[:, b])) <= 1e-12 * np.max(np.abs(yb))
     for b in (0, 9):
         assert rel_l2(Y[:, b], P.apply(X[:, b], op=2)) <= 2e-5
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp32", 20), ("fp64", 20), ("fp32", 70)])
+def test_fmm_heterogeneous_many_rhs_matrix_cores(ev, oracle_mod, prec, nrhs):
+    """From 16 right-hand sides on, the cached-pair products run on the matrix cores, 64
+    right-hand sides per pass (70 = 64 + 6).  Every column equals its single-column apply
+    (streaming form) to accumulation order, and the oracle to the heterogeneous bar."""
+    case = inputs.make_case("c3", n=(16, 16, 16), seed=7)
+    P = oracle_problem(oracle_mod, case)
+    X = inputs.random_vector(P.N, 16, nrhs=nrhs)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    with ev.plan_from_case(case, method="fmm", prec=prec, leaf=4, nrhs_max=nrhs) as plan:
+        Y = gpu_apply(plan, X, ev.OP_A)
+        for b in (0, 15, nrhs - 1):
+            yb = gpu_apply(plan, X[:, b], ev.OP_A)
+            d = np.max(np.abs(yb - Y[:, b])) / np.max(np.abs(yb))
+            log("many rhs", prec, nrhs, "column", b, "max rel diff vs single column", d)
+            assert d <= tol
+    assert rel_l2(Y[:, 3], P.apply(X[:, 3], op=2)) <= 2e-5
