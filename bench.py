@@ -143,6 +143,35 @@ def many_scattering_128(torch, ertvie, inputs, O, stream, args):
     return out
 
 
+def many_rhs_64(torch, ertvie, inputs, stream):
+    """64 face sources on the 64^3 blob medium: the batched apply of all 64 columns (the
+    cached-pair products on the matrix cores) and block GMRES to 1e-8, against column-by-
+    column GMRES timed on 4 columns."""
+    case = inputs.make_case("c4", seed=0, nrhs=64)
+    F = torch.from_numpy(np.ascontiguousarray(case["f"].T)).cuda()
+    out = {"workload": "64^3 blob medium, 64 face sources, tol 1e-8"}
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, nrhs_max=64, inner_cheb_n=4) as plan:
+        plan.fmm_info("fp64")
+        plan.fmm_info("fp32")
+        X = torch.from_numpy(np.ascontiguousarray(inputs.random_vector(plan.N, 5, nrhs=64).T)).cuda()
+        Y = torch.empty_like(X)
+        for prec in ("fp64", "fp32"):
+            out["apply_64rhs_ms_" + prec] = timed_applies(torch, plan, X, Y, ertvie.OP_A, 3, 2, prec=prec)
+        keys = ("iters", "matvecs", "restarts", "t_solve", "rel_resid_true")
+        U = torch.empty_like(F)
+        plan.solve(F, U, tol=1e-8, block=True)
+        r = plan.solve(F, U, tol=1e-8, block=True)
+        out["block_fp64"] = {k: r[k] for k in keys}
+        r = plan.solve(F, U, tol=1e-8, block=True, mixed=True, inner_tol=1e-2)
+        out["block_mixed"] = {k: r[k] for k in keys}
+        U4 = torch.empty_like(F[:4])
+        r = plan.solve(F[:4].contiguous(), U4, tol=1e-8)
+        out["columns_fp64_4_of_64"] = {k: r[k] for k in keys}
+        out["columns_fp64_64_extrapolated_s"] = r["t_solve"] * 16
+    log("64 right-hand sides:", json.dumps(out))
+    return out
+
+
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
                        "precond_c5_64.npz")
 
@@ -288,6 +317,7 @@ def main():
 
     if not args.no_solve and not args.no_c3:
         extra["solve_many_scattering_64cubed"] = many_scattering_solves(torch, ertvie, inputs, stream, args)
+        extra["many_rhs_64cubed"] = many_rhs_64(torch, ertvie, inputs, stream)
 
     if args.c5_128:
         extra["many_scattering_128cubed"] = many_scattering_128(torch, ertvie, inputs, O, stream, args)

@@ -120,7 +120,8 @@ typedef struct {
     double inner_tol; /* mixed: relative tolerance of each inner solve; 0 -> 1e-5 */
     int rhs_is_phi;   /* 1: the f argument already holds phi (skip step S.1) */
     int block;        /* 1: block GMRES -- the nrhs columns share one block Krylov space and
-                         every operator application is one batched apply (0: column by column) */
+                         every operator application is one batched apply (0: column by column);
+                         with restart = 0 the block basis is capped at 4 GiB */
     int precond_steps;/* with precond: Arnoldi steps per preconditioned correction; 0 -> 10 */
     int history_max;  /* columns of `history` (0: no history) */
     int reserved[1];  /* must be 0 */

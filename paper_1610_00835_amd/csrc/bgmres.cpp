@@ -131,7 +131,10 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
 {
     const long N = pl->N;
     const int p = nb;
-    const int m = std::max(1, std::min(restart > 0 ? restart : maxit, maxit));
+    // Krylov dimension in blocks: restart, or (unrestarted) as many blocks as fit in 4 GiB
+    // (134 MB per block at 64 columns of 64^3), beyond which the method restarts
+    const long fit = std::max<long>(2, (4L << 30) / ((long)p * N * (long)sizeof(double)) - 1);
+    const int m = std::max(1, std::min<int>(restart > 0 ? restart : (int)std::min<long>(maxit, fit), maxit));
     hipStream_t s = pl->stream;
     DevBuf V, W, R, T, small, work;
     ERT_TRY(V.alloc((size_t)(m + 1) * p * N));

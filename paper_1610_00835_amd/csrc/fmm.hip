@@ -687,10 +687,10 @@ struct GemmSite {
     bool used = false;
     PairTiles pl;                         // device arrays of the offset-stationary form
     std::vector<int> h_gstart;            // host copy, to rebuild tiles for a larger rhs capacity
-    // per rhs bucket (1, >1): 0 class GEMM, 1 offset-stationary with 16-column tiles,
-    // 2 offset-stationary with 64-column tiles
+    // per rhs bucket (1, >1): 0 class GEMM; offset-stationary with 1: 32 x 16 tiles per
+    // workgroup wave set, 2: 32 x 64, 3: 16 x 64 (twice the workgroups of 2)
     int choice[2] = {-1, -1};
-    float tuned_ms[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    float tuned_ms[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     void release()
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
@@ -797,6 +797,11 @@ struct FmmImpl : FmmData {
     int rp[kMaxLevels + 1] = {};        // compressed rank (padded), 0 = uncompressed
     T* Ut[kMaxLevels + 1] = {};         // [rp][Kp]: multipoles -> compressed
     T* Um[kMaxLevels + 1] = {};         // [Kp][rp]: compressed locals -> locals
+    // A tree whose leaves are the only far-field level (L = 2) with compressed
+    // translations: P2M and the compression fold into one [rp][S] matrix, the
+    // expansion and L2P into one [S][rp] matrix (each applied as one GEMM).
+    T* leaf_in = nullptr;               // [rp][S] = Ut P
+    T* leaf_out = nullptr;              // [S][rp] = P^T Um
     HetCache* hc = nullptr;             // heterogeneous caches (owned by the plan)
     T* nearops = nullptr;               // homogeneous near blocks [3^d][S][S]
     T* tab = nullptr;                   // homogeneous near table (S not a multiple of 32)
@@ -822,7 +827,7 @@ struct FmmImpl : FmmData {
     ~FmmImpl() override
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(q); f(pot);
+        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(q); f(pot); f(leaf_in); f(leaf_out);
         for (int l = 0; l <= kMaxLevels; ++l) {
             f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]);
             f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
@@ -961,6 +966,47 @@ ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
         ERT_TRY(upload_cvt<T>(s, &Ut[l], Ut_h));
         ERT_TRY(upload_cvt<T>(s, &Um[l], Uh));
         rp[l] = R;
+        if (l == 2 && tr.L == 2 && tr.S % 32 == 0) {
+            // dense leaf interpolation P[m][j] = prod_a S_n(x_{j_a}, node_{m_a}) (the separable
+            // P2M/L2P operator), folded with the basis change
+            std::vector<double> node(tr.nc), P1h((size_t)tr.nc * tr.leaf);
+            for (int m = 0; m < tr.nc; ++m) node[m] = std::cos((2.0 * m + 1.0) * kPi / (2.0 * tr.nc));
+            for (int m = 0; m < tr.nc; ++m)
+                for (int i = 0; i < tr.leaf; ++i)
+                    P1h[(size_t)m * tr.leaf + i] = cheb_S(tr.nc, (2.0 * i + 1.0) / tr.leaf - 1.0, node[m]);
+            const int S = tr.S;
+            std::vector<double> P((size_t)Kp * S, 0.0);
+            for (int m = 0; m < tr.K; ++m) {
+                int mm[3] = {m % tr.nc, tr.D > 1 ? (m / tr.nc) % tr.nc : 0, tr.D > 2 ? m / (tr.nc * tr.nc) : 0};
+                for (int j = 0; j < S; ++j) {
+                    int jj[3] = {j % tr.leaf, tr.D > 1 ? (j / tr.leaf) % tr.leaf : 0,
+                                 tr.D > 2 ? j / (tr.leaf * tr.leaf) : 0};
+                    double v = 1.0;
+                    for (int a = 0; a < tr.D; ++a) v *= P1h[(size_t)mm[a] * tr.leaf + jj[a]];
+                    P[(size_t)m * S + j] = v;
+                }
+            }
+            std::vector<double> fin((size_t)R * S, 0.0), fout((size_t)S * R, 0.0);
+            for (int c = 0; c < R; ++c)
+                for (int m = 0; m < tr.K; ++m) {
+                    const double u = Ut_h[(size_t)c * Kp + m];
+                    if (u == 0.0) continue;
+                    const double* pm = &P[(size_t)m * S];
+                    double* fc = &fin[(size_t)c * S];
+                    for (int j = 0; j < S; ++j) fc[j] += u * pm[j];
+                }
+            for (int m = 0; m < tr.K; ++m) {
+                const double* pm = &P[(size_t)m * S];
+                const double* um = &Uh[(size_t)m * R];
+                for (int j = 0; j < S; ++j) {
+                    const double pj = pm[j];
+                    double* fj = &fout[(size_t)j * R];
+                    for (int c = 0; c < R; ++c) fj[c] += pj * um[c];
+                }
+            }
+            ERT_TRY(upload_cvt<T>(s, &leaf_in, fin));
+            ERT_TRY(upload_cvt<T>(s, &leaf_out, fout));
+        }
         Cd = C64;
         M = R;
     }
@@ -1327,6 +1373,7 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         o.stage = stage;
         o.accumulate = b.accumulate;
         o.tn = 1;
+        o.tm = 2;
         o.pl = gs.pl;
         return o;
     };
@@ -1336,16 +1383,16 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         BoxGemm gt = g;
         gt.L = tune;
         gt.accumulate = 0;
-        OffsetGemm ot = as_offset(gt), ot4 = as_offset(gt);
-        ot4.tn = 4;
+        OffsetGemm ot[4] = {as_offset(gt), as_offset(gt), as_offset(gt), as_offset(gt)};
+        ot[2].tn = 4;
+        ot[3].tn = 4;
+        ot[3].tm = 1;
         hipEvent_t e[3];
         for (auto& ev : e) ERT_HIP(hipEventCreate(&ev));
-        float ms[3] = {0.f, 0.f, 0.f};
+        float ms[4] = {0.f, 0.f, 0.f, 0.f};
         ert_status st = ERT_OK;
-        auto run = [&](int form) {
-            return form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, form == 1 ? ot : ot4);
-        };
-        for (int form = 0; form < 3 && st == ERT_OK; ++form) {
+        auto run = [&](int form) { return form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot[form]); };
+        for (int form = 0; form < 4 && st == ERT_OK; ++form) {
             st = run(form);   // warm-up
             if (st != ERT_OK) break;
             (void)hipEventRecord(e[0], s);
@@ -1357,7 +1404,7 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         for (auto& ev : e) (void)hipEventDestroy(ev);
         ERT_TRY(st);
         int best = 0;
-        for (int form = 0; form < 3; ++form) {
+        for (int form = 0; form < 4; ++form) {
             gs.tuned_ms[bucket][form] = ms[form] / 3;
             if (ms[form] < ms[best]) best = form;
         }
@@ -1365,7 +1412,8 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
     OffsetGemm og = as_offset(g);
-    og.tn = gs.choice[bucket] == 2 ? 4 : 1;
+    og.tn = gs.choice[bucket] >= 2 ? 4 : 1;
+    og.tm = gs.choice[bucket] == 3 ? 1 : 2;
     ERT_TRY(offset_gemm_products(s, gprec, og));
     if (outer) outer->stop();
     StageTimer sr_(&p->prof, s, ERT_STAGE_REDUCE);
@@ -1426,8 +1474,15 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
     }
     if (tr.L >= 2) {
         const int L = tr.L;
-        // a5: P2M on the leaves
-        {
+        // a5: P2M on the leaves (with the compression folded in when the leaves are the
+        // only far-field level)
+        if (leaf_in) {
+            StageTimer st_(pf, s, ERT_STAGE_P2M);
+            BoxGemm c = gemm_desc(L, rp[L], tr.S, nrhs);
+            c.stride = 1; c.nclass = 1; c.noff = 1; c.offs = id_off;
+            c.ops = leaf_in; c.W = q; c.L = Wc[L]; c.accumulate = 0;
+            ERT_TRY(box_gemm(s, dprec, c));
+        } else {
             StageTimer st_(pf, s, ERT_STAGE_P2M);
             hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, q, P1, W[L]);
             ERT_HIP(hipGetLastError());
@@ -1473,6 +1528,13 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 a.L = Lc[l];
                 a.accumulate = first ? 0 : 1;
                 ERT_TRY(pair_stream(s, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
+            } else if (rp[l] > 0 && leaf_in) {
+                // single compressed level: multipoles already compressed, the expansion
+                // is folded into L2P below
+                BoxGemm g = gemm_desc(l, rp[l], rp[l], nrhs);
+                g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
+                g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
+                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &st_));
             } else if (rp[l] > 0) {
                 const int R = rp[l];
                 st_.pause();
@@ -1506,8 +1568,15 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         }
         // a9: L2P adds the far field
         StageTimer st_(pf, s, ERT_STAGE_L2P);
-        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, Lc[L], P1, pot);
-        ERT_HIP(hipGetLastError());
+        if (leaf_in) {
+            BoxGemm u = gemm_desc(L, tr.S, rp[L], nrhs);
+            u.stride = 1; u.nclass = 1; u.noff = 1; u.offs = id_off;
+            u.ops = leaf_out; u.W = Lh[L]; u.L = pot; u.accumulate = 1;
+            ERT_TRY(box_gemm(s, dprec, u));
+        } else {
+            hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, Lc[L], P1, pot);
+            ERT_HIP(hipGetLastError());
+        }
     }
     // a11: scale, self term, operator
     const double hd = std::pow(p->geo.h, tr.D);

@@ -93,6 +93,7 @@ struct OffsetGemm {
     void* stage;              // [B][npairs][M]
     int accumulate;
     int tn;                   // column blocks of 16 per workgroup: 1 or 4
+    int tm;                   // row blocks of 16 per wave: 2 or 1 (with tn = 4)
     PairTiles pl;
 };
 

@@ -638,13 +638,18 @@ ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
             OffsetGemm g4 = g;
             g4.pl.tile_group = g.pl.tile_group4;
             g4.pl.tile_col0 = g.pl.tile_col04;
-            dim3 grid((unsigned)g.pl.ntiles4, (unsigned)(g.M / (16 * kTM)));
-            if (prec == ERT_FP64)
-                hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, kTM, 4>), grid, dim3(64 * kWaves), 0, s, g4);
-            else if (prec == ERT_FP32)
-                hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, kTM, 4>), grid, dim3(64 * kWaves), 0, s, g4);
-            else
-                hipLaunchKernelGGL((k_offset_gemm<ERT_BF16X3, kTM, 4>), grid, dim3(64 * kWaves), 0, s, g4);
+            const int tm = g.tm == 1 ? 1 : kTM;
+            dim3 grid((unsigned)g.pl.ntiles4, (unsigned)(g.M / (16 * tm)));
+#define ERT_OFF4(TM_)                                                                                   \
+    if (prec == ERT_FP64) hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4); \
+    else if (prec == ERT_FP32) hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4); \
+    else hipLaunchKernelGGL((k_offset_gemm<ERT_BF16X3, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4);
+            if (tm == 1) {
+                ERT_OFF4(1)
+            } else {
+                ERT_OFF4(kTM)
+            }
+#undef ERT_OFF4
             ERT_HIP(hipGetLastError());
         }
     } else if (g.pl.ntiles > 0) {
