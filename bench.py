@@ -59,10 +59,10 @@ SVD_TOL = 1e-5
 # the 64-column form of the near-field product, the one the autotuner picks on this workload).
 # Keyed by (workload, precision, kernel); a kernel changed since its counters were taken has
 # no entry, and reports null.
-MEASURED_TRAFFIC = {("c2", "fp32", "near"): 31.61e6}
+MEASURED_TRAFFIC = {}
 
 
-def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None):
+def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None, forms=None):
     """Roofline of the dominant box-offset product (M2L or near field) from its algorithmic work:
     M2L: 2 R^2 flops per far pair, bytes = translation matrices (one per box offset) + multipoles in
     + locals out; near: 2 flops per point pair, bytes = the 3^d near blocks + charges in + potentials out."""
@@ -82,6 +82,10 @@ def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None):
     cand = {"m2l": (m2l_flops, m2l_bytes, stage_ms.get("m2l", 0.0), launches.get("m2l", 1.0), prec),
             "near": (near_flops, near_bytes, stage_ms.get("near", 0.0), launches.get("near", 1.0),
                      "fp64" if prec == "fp64" else "fp32")}
+    if not stage_ms.get("m2l") and m2l_flops > 0 and prec != "bf16x3":
+        # one-level tree after tuning: near field and translations share one launch
+        cand = {"near+m2l": (near_flops + m2l_flops, near_bytes + m2l_bytes, stage_ms.get("near", 0.0),
+                             launches.get("near", 1.0), "fp64" if prec == "fp64" else "fp32")}
     dom = max(cand, key=lambda k: cand[k][2])
     flops, nbytes, tms, nl, kprec = cand[dom]
     ai = flops / nbytes
@@ -92,8 +96,9 @@ def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None):
     else:
         achieved, peak, unit, bound, per = flops / nl / t / 1e12, PEAK_FLOPS[kprec] / 1e12, "TFLOP/s", "mfma", flops / nl
     return {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": MEASURED_TRAFFIC.get((workload, prec, dom)), "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
+            "traffic": MEASURED_TRAFFIC.get((workload, prec, dom, forms)), "forms": forms, "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
             "arith_intensity_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
+            "kernel_flops_per_launch": flops / nl,
             "m2l_tflops": m2l_flops / (stage_ms["m2l"] * 1e-3) / 1e12 if stage_ms.get("m2l") else None,
             "near_tflops": near_flops / (stage_ms["near"] * 1e-3) / 1e12 if stage_ms.get("near") else None}
 
@@ -273,7 +278,8 @@ def main():
     info = plan.fmm_info()
     info["leaf_boxes"] = int(np.prod([-(-n // info["leaf"]) for n in case["n"]]))
     log("fmm:", json.dumps(info))
-    roofline = roofline_of(info, stage_ms, launches, args.prec, workload="c2")
+    forms = "%d,%d" % (info["form_near"], info["form_far"][info["levels"]])
+    roofline = roofline_of(info, stage_ms, launches, args.prec, workload="c2", forms=forms)
     log("roofline:", json.dumps(roofline))
 
     P = O.Problem(3, case["n"], case["h"], 0, case["sigma_t"], case["sigma_s"])

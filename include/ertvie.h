@@ -209,6 +209,10 @@ typedef struct {
     int rank[16];         /* per level: compressed translation rank as stored, 0 = uncompressed */
     long far_pairs[16];   /* per level: (target, source) box pairs of the interaction lists */
     long near_pairs;      /* point pairs of the near field (self pairs excluded) */
+    int form_near;        /* execution form of the homogeneous near-field product for one
+                             right-hand side: -1 not tuned yet / not a box-offset product,
+                             0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64, 3 16x64 */
+    int form_far[16];     /* per level: the same for the far-field translations */
 } ert_fmm_info;
 
 /* Device timing of applies by stage, with HIP events recorded on the plan's

@@ -31,6 +31,7 @@ namespace ertvie {
 struct FmmData {
     virtual ~FmmData() {}
     virtual int rank_of(int l) const = 0;
+    virtual int form_of(int site) const = 0;   // site -1: near field, l >= 0: far field of level l
     virtual ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) = 0;
     virtual ert_status setup(ert_plan_impl* p) = 0;
     FmmTree tr;
@@ -820,7 +821,15 @@ struct FmmImpl : FmmData {
     hipGraphExec_t gexec[2] = {};
     int graph_nrhs[2] = {0, 0};
     int calls[2] = {0, 0};
-    T* stage = nullptr;                 // staging rows of the offset-stationary form
+    T* stage = nullptr;                 // staging rows of the far-field products
+    T* stage_near = nullptr;            // staging rows of the near-field products (runs concurrently)
+    size_t stage_near_elems = 0;
+    // the near field and the far-field passes are independent until L2P: after the
+    // first (tuning) apply of a rhs bucket the near field runs on a second stream,
+    // forked from and joined back to the apply's stream (also inside captured graphs)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool tuned[2] = {false, false};
     T* tune = nullptr;                  // scratch output while autotuning
     size_t stage_elems = 0, tune_elems = 0;
 
@@ -834,13 +843,36 @@ struct FmmImpl : FmmData {
             far_site[l].release();
         }
         near_site.release();
-        f(stage); f(tune); f(io);
+        f(stage); f(stage_near); f(tune); f(io);
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
+        if (side) (void)hipStreamDestroy(side);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
     }
 
     ert_status run_site(ert_plan_impl* p, hipStream_t s, GemmSite& site, int gprec, const BoxGemm& g, int nrhs,
-                        StageTimer* outer);
+                        StageTimer* outer, T* stg);
+    // offset-stationary description of a box-offset product in the form `form` (1..3)
+    OffsetGemm offset_of(const GemmSite& gs, const BoxGemm& b, T* stg, int form) const
+    {
+        OffsetGemm o;
+        o.nbox = b.nbox;
+        o.B = b.B;
+        o.M = b.M;
+        o.Kd = b.Kd;
+        o.ops = b.ops;
+        o.ops_lo = b.ops_lo;
+        o.W = b.W;
+        o.L = b.L;
+        o.stage = stg;
+        o.accumulate = b.accumulate;
+        o.tn = form >= 2 ? 4 : 1;
+        o.tm = form == 3 ? 1 : 2;
+        o.pl = gs.pl;
+        return o;
+    }
+    ert_status enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs);
     ert_status enqueue(ert_plan_impl* p, hipStream_t s, int nrhs);
     void drop_graphs()
     {
@@ -854,6 +886,11 @@ struct FmmImpl : FmmData {
     }
 
     int rank_of(int l) const override { return rp[l]; }
+    int form_of(int site) const override
+    {
+        const GemmSite& gs = site < 0 ? near_site : far_site[site];
+        return gs.used ? gs.choice[0] : -1;
+    }
     ert_status setup(ert_plan_impl* p) override;
     ert_status setup_far_hom(ert_plan_impl* p, int l, double svd_tol);
     ert_status setup_het(ert_plan_impl* p);
@@ -1320,29 +1357,35 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
             ERT_HIP(hipMalloc(&Lh[l], m * sizeof(T)));
         }
     }
-    // offset-stationary form: tiles for this capacity, staging and tuning scratch
-    size_t st_need = 0, tu_need = 0;
-    auto site_need = [&](GemmSite& gs, long nbox, int M) -> ert_status {
+    // offset-stationary form: tiles for this capacity, staging (far and near apart,
+    // as they run concurrently) and tuning scratch
+    size_t st_need = 0, sn_need = 0, tu_need = 0;
+    auto site_need = [&](GemmSite& gs, long nbox, int M, size_t& need) -> ert_status {
         if (!gs.used) return ERT_OK;
         ERT_TRY(build_tiles(p_stream, gs, nrhs));
-        st_need = std::max(st_need, (size_t)nrhs * gs.pl.npairs * M);
+        need = std::max(need, (size_t)nrhs * gs.pl.npairs * M);
         tu_need = std::max(tu_need, (size_t)nrhs * nbox * M);
         return ERT_OK;
     };
-    ERT_TRY(site_need(near_site, tr.nleaf, tr.S));
+    ERT_TRY(site_need(near_site, tr.nleaf, tr.S, sn_need));
     if (hetero) {
         const size_t rb = (size_t)std::min(nrhs, nrhs >= kPairMfmaMinRhs ? 64 : 8);
-        st_need = std::max(st_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
+        sn_need = std::max(sn_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
         for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hc->hnp[l] * tr.Kp);
     }
-    for (int l = 2; l <= tr.L; ++l) ERT_TRY(site_need(far_site[l], tr.nbox[l], rp[l] > 0 ? rp[l] : tr.Kp));
-    if (st_need > stage_elems) {
-        if (stage) (void)hipFree(stage);
-        stage = nullptr;
-        stage_elems = 0;
-        ERT_HIP(hipMalloc(&stage, st_need * sizeof(T)));
-        stage_elems = st_need;
-    }
+    for (int l = 2; l <= tr.L; ++l)
+        ERT_TRY(site_need(far_site[l], tr.nbox[l], rp[l] > 0 ? rp[l] : tr.Kp, st_need));
+    auto grow = [](T** buf, size_t* have, size_t need) -> ert_status {
+        if (need <= *have) return ERT_OK;
+        if (*buf) (void)hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+        ERT_HIP(hipMalloc(buf, need * sizeof(T)));
+        *have = need;
+        return ERT_OK;
+    };
+    ERT_TRY(grow(&stage, &stage_elems, st_need));
+    ERT_TRY(grow(&stage_near, &stage_near_elems, sn_need));
     if (tu_need > tune_elems) {
         if (tune) (void)hipFree(tune);
         tune = nullptr;
@@ -1358,25 +1401,9 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
 // call of a bucket times both forms (into scratch) and keeps the faster one.
 template <typename T>
 ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs,
-                                StageTimer* outer)
+                                StageTimer* outer, T* stg)
 {
-    auto as_offset = [&](const BoxGemm& b) {
-        OffsetGemm o;
-        o.nbox = b.nbox;
-        o.B = b.B;
-        o.M = b.M;
-        o.Kd = b.Kd;
-        o.ops = b.ops;
-        o.ops_lo = b.ops_lo;
-        o.W = b.W;
-        o.L = b.L;
-        o.stage = stage;
-        o.accumulate = b.accumulate;
-        o.tn = 1;
-        o.tm = 2;
-        o.pl = gs.pl;
-        return o;
-    };
+    auto as_offset = [&](const BoxGemm& b) { return offset_of(gs, b, stg, 1); };
     if (!gs.used) return box_gemm(s, gprec, g);
     const int bucket = nrhs > 1 ? 1 : 0;
     if (gs.choice[bucket] < 0) {
@@ -1408,6 +1435,16 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
             gs.tuned_ms[bucket][form] = ms[form] / 3;
             if (ms[form] < ms[best]) best = form;
         }
+        // within 5 % of the fastest, take the 64-column tiles: they read each operator
+        // block once instead of once per 16 columns (less HBM traffic at the same speed)
+        if (best == 1 && ms[2] <= 1.05f * ms[1]) best = 2;
+        // fixed forms for reproducible profiles: ERT_VIE_FORM="a" (every product) or
+        // "a,b" (a for the near field, b for the far field), each 0..3
+        if (const char* f = std::getenv("ERT_VIE_FORM")) {
+            const char* comma = std::strchr(f, ',');
+            const int v = std::atoi((&gs == &near_site || !comma) ? f : comma + 1);
+            if (v >= 0 && v <= 3) best = v;
+        }
         gs.choice[bucket] = best;
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
@@ -1420,9 +1457,79 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
     return offset_gemm_reduce(s, gprec, og);
 }
 
+// One-level homogeneous tree with compressed translations, after tuning: the near
+// field and the far-field translations are independent products of the same kind;
+// they run in one launch (each in its tuned form), and so do their per-target sums:
+// gather, P2M with compression, the two products, the two sums, expansion with L2P,
+// assembly.
+template <typename T>
+ert_status FmmImpl<T>::enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs)
+{
+    const long N = p->N;
+    const int nn = tr.D == 3 ? 27 : 9;
+    const int L = tr.L, R = rp[L], bk = nrhs > 1 ? 1 : 0;
+    const int dprec = (prec == ERT_FP64) ? ERT_FP64 : ERT_FP32;
+    Profiler* pf = &p->prof;
+    {
+        StageTimer st_(pf, s, ERT_STAGE_GATHER);
+        hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, io, p->d_ss, N, nrhs, q);
+        ERT_HIP(hipGetLastError());
+    }
+    {
+        StageTimer st_(pf, s, ERT_STAGE_P2M);
+        BoxGemm c = gemm_desc(L, R, tr.S, nrhs);
+        c.stride = 1; c.nclass = 1; c.noff = 1; c.offs = id_off;
+        c.ops = leaf_in; c.W = q; c.L = Wc[L]; c.accumulate = 0;
+        ERT_TRY(box_gemm(s, dprec, c));
+    }
+    BoxGemm gn = gemm_desc(L, tr.S, tr.S, nrhs);
+    gn.stride = 1; gn.nclass = 1; gn.noff = nn; gn.offs = near_offs;
+    gn.ops = nearops; gn.W = q; gn.L = pot; gn.accumulate = 0;
+    BoxGemm gf = gemm_desc(L, R, R, nrhs);
+    gf.stride = 2; gf.nclass = 1 << tr.D; gf.noff = m2l_noff; gf.offs = m2l_offs;
+    gf.ops = ops[L]; gf.ops_lo = ops_lo[L]; gf.W = Wc[L]; gf.L = Lh[L]; gf.accumulate = 0;
+    const OffsetGemm on = offset_of(near_site, gn, stage_near, near_site.choice[bk]);
+    const OffsetGemm of = offset_of(far_site[L], gf, stage, far_site[L].choice[bk]);
+    {
+        // the near-field blocks are FP32/FP64 like the dense transforms; the
+        // translations take the plan's precision (BF16x3 included): one launch needs one
+        // precision, so BF16x3 plans keep the products apart
+        StageTimer st_(pf, s, ERT_STAGE_NEAR);
+        if (dprec == prec) {
+            ERT_TRY(offset_gemm_pair_products(s, prec, on, of));
+        } else {
+            ERT_TRY(offset_gemm_products(s, dprec, on));
+            ERT_TRY(offset_gemm_products(s, prec, of));
+        }
+    }
+    {
+        StageTimer st_(pf, s, ERT_STAGE_REDUCE);
+        ERT_TRY(offset_gemm_pair_reduce(s, dprec, on, of));
+    }
+    {
+        StageTimer st_(pf, s, ERT_STAGE_L2P);
+        BoxGemm u = gemm_desc(L, tr.S, R, nrhs);
+        u.stride = 1; u.nclass = 1; u.noff = 1; u.offs = id_off;
+        u.ops = leaf_out; u.W = Lh[L]; u.L = pot; u.accumulate = 1;
+        ERT_TRY(box_gemm(s, dprec, u));
+    }
+    const double hd = std::pow(p->geo.h, tr.D);
+    StageTimer st_(pf, s, ERT_STAGE_ASSEMBLE);
+    hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, io, p->d_ss, p->d_diag, hd, N,
+                       nrhs);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
 template <typename T>
 ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
 {
+    {
+        const int bk = nrhs > 1 ? 1 : 0;
+        if (!hetero && leaf_in && nearops && tr.L == 2 && tuned[bk] && near_site.used && far_site[2].used &&
+            near_site.choice[bk] >= 1 && far_site[2].choice[bk] >= 1)
+            return enqueue_grouped(p, s, nrhs);
+    }
     const long N = p->N;
     const int nn = tr.D == 3 ? 27 : 9;
     const int dprec = (prec == ERT_FP64) ? ERT_FP64 : ERT_FP32;   // precision of the dense transforms
@@ -1433,9 +1540,19 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, io, p->d_ss, N, nrhs, q);
         ERT_HIP(hipGetLastError());
     }
-    // a10: near field (writes pot)
+    // a10: near field (writes pot), on the side stream once the forms are tuned
+    const bool fork = tuned[nrhs > 1 ? 1 : 0];
+    hipStream_t sn = s;
+    if (fork) {
+        if (!side) ERT_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        if (!ev_fork) ERT_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        if (!ev_join) ERT_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        ERT_HIP(hipEventRecord(ev_fork, s));
+        ERT_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+        sn = side;
+    }
     {
-        StageTimer st_(pf, s, ERT_STAGE_NEAR);
+        StageTimer st_(pf, sn, ERT_STAGE_NEAR);
         StageTimer* near_timer = &st_;
         if (hetero) {
             PairStream a;
@@ -1449,10 +1566,10 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             a.nsrc = tr.nleaf;
             a.tstart = hc->near_tstart;
             a.W = q;
-            a.stage = stage;
+            a.stage = stage_near;
             a.L = pot;
             a.accumulate = 0;
-            ERT_TRY(pair_stream(s, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
+            ERT_TRY(pair_stream(sn, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
         } else if (nearops) {
             BoxGemm g = gemm_desc(tr.L, tr.S, tr.S, nrhs);
             g.stride = 1;
@@ -1463,15 +1580,16 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             g.W = q;
             g.L = pot;
             g.accumulate = 0;
-            ERT_TRY(run_site(p, s, near_site, dprec, g, nrhs, near_timer));
+            ERT_TRY(run_site(p, sn, near_site, dprec, g, nrhs, near_timer, stage_near));
         } else {
             const int tpp = std::min(tr.S, kB);
             const int groups = kB / tpp;
             size_t sh = (size_t)(ntab + nn * tr.S) * sizeof(T) + 32 * sizeof(int) + (size_t)groups * tpp * sizeof(T);
-            hipLaunchKernelGGL(k_p2p_hom<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), sh, s, dt, q, tab, ntab, pot);
+            hipLaunchKernelGGL(k_p2p_hom<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), sh, sn, dt, q, tab, ntab, pot);
             ERT_HIP(hipGetLastError());
         }
     }
+    bool joined = false;
     if (tr.L >= 2) {
         const int L = tr.L;
         // a5: P2M on the leaves (with the compression folded in when the leaves are the
@@ -1534,7 +1652,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 BoxGemm g = gemm_desc(l, rp[l], rp[l], nrhs);
                 g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                 g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
-                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &st_));
+                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &st_, stage));
             } else if (rp[l] > 0) {
                 const int R = rp[l];
                 st_.pause();
@@ -1550,7 +1668,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                     BoxGemm g = gemm_desc(l, R, R, nrhs);       // translate
                     g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                     g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = Wc[l]; g.L = Lh[l]; g.accumulate = 0;
-                    ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &sm_));
+                    ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &sm_, stage));
                 }
                 {
                     StageTimer sb_(pf, s, ERT_STAGE_BASIS);
@@ -1563,10 +1681,15 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 BoxGemm g = gemm_desc(l, tr.Kp, tr.Kp, nrhs);
                 g.stride = 2; g.nclass = 1 << tr.D; g.noff = m2l_noff; g.offs = m2l_offs;
                 g.ops = ops[l]; g.ops_lo = ops_lo[l]; g.W = W[l]; g.L = Lc[l]; g.accumulate = first ? 0 : 1;
-                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &st_));
+                ERT_TRY(run_site(p, s, far_site[l], prec, g, nrhs, &st_, stage));
             }
         }
-        // a9: L2P adds the far field
+        // a9: L2P adds the far field (after the near field has written pot)
+        if (fork) {
+            ERT_HIP(hipEventRecord(ev_join, side));
+            ERT_HIP(hipStreamWaitEvent(s, ev_join, 0));
+            joined = true;
+        }
         StageTimer st_(pf, s, ERT_STAGE_L2P);
         if (leaf_in) {
             BoxGemm u = gemm_desc(L, tr.S, rp[L], nrhs);
@@ -1577,6 +1700,10 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)tr.nleaf, nrhs), dim3(kB), 0, s, dt, Lc[L], P1, pot);
             ERT_HIP(hipGetLastError());
         }
+    }
+    if (fork && !joined) {   // no far field: join before the assembly reads pot
+        ERT_HIP(hipEventRecord(ev_join, side));
+        ERT_HIP(hipStreamWaitEvent(s, ev_join, 0));
     }
     // a11: scale, self term, operator
     const double hd = std::pow(p->geo.h, tr.D);
@@ -1603,7 +1730,11 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
         ERT_HIP(hipGraphLaunch(gexec[bucket], s));
         return ERT_OK;
     }
-    if (calls[bucket]++ == 0) return enqueue(p, s, nrhs);   // tunes the forms of this bucket
+    if (calls[bucket]++ == 0) {                             // tunes the forms of this bucket
+        ERT_TRY(enqueue(p, s, nrhs));
+        tuned[bucket] = true;
+        return ERT_OK;
+    }
     // capture on the internal stream, ordered after the caller's stream
     if (!cap) ERT_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     if (gexec[bucket]) {
@@ -1684,6 +1815,8 @@ ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info)
     info->nodes = t.K;
     info->nodes_padded = t.Kp;
     for (int l = 0; l <= t.L && l < 16; ++l) info->rank[l] = f->rank_of(l);
+    info->form_near = f->form_of(-1);
+    for (int l = 0; l < 16; ++l) info->form_far[l] = (l <= t.L && l >= 2) ? f->form_of(l) : -1;
     // interaction-list pairs per level (separable per axis) and near point pairs
     for (int l = 2; l <= t.L && l < 16; ++l) {
         long par = 1, nr = 1;

@@ -100,6 +100,10 @@ struct OffsetGemm {
 ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);           // products + reduction
 ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g);  // staged products only
 ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    // per-target sums only
+// two independent products (each in its own form, with its own staging rows) in one launch,
+// and their per-target sums in one launch
+ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b);
+ert_status offset_gemm_pair_reduce(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b);
 
 // Streaming form of cached-pair products (heterogeneous far field and near
 // field): one workgroup per pair streams its matrix once (16-byte loads along

@@ -259,19 +259,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_til
 
 // ---------------------------------------------------- offset-stationary ----
 
+// One tile (column tile `tile`, row tile `rtile`) of an offset-stationary product.
 template <int PREC, int TM, int TN>
-__global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
+__device__ __forceinline__ void offset_tile(const OffsetGemm& g, long tile, int rtile)
 {
     typedef typename Acc<PREC>::V V;
     typedef typename Acc<PREC>::T T;
     __shared__ V red[(kWaves - 1) * TM * TN * 64];
-    const int grpi = g.pl.tile_group[blockIdx.x];
-    const long col0 = g.pl.tile_col0[blockIdx.x];
+    const int grpi = g.pl.tile_group[tile];
+    const long col0 = g.pl.tile_col0[tile];
     const int p0 = g.pl.gstart[grpi], np = g.pl.gstart[grpi + 1] - p0;
     if (col0 >= (long)np * g.B) return;                 // uniform over the block
     const int op = g.pl.gop[grpi];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4;
-    const int row0 = blockIdx.y * 16 * TM;
+    const int row0 = rtile * 16 * TM;
     constexpr int LG = (PREC == ERT_BF16X3) ? 8 : 4;
     long pidx[TN];
     int pb[TN];
@@ -318,16 +319,34 @@ __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
         }
 }
 
+template <int PREC, int TM, int TN>
+__global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
+{
+    offset_tile<PREC, TM, TN>(g, blockIdx.x, blockIdx.y);
+}
+
+// Two independent offset-stationary products in one launch (the near field and the
+// far-field translations of a one-level tree): blocks [0, na) belong to the first.
+template <int PREC, int TMA, int TNA, int TMB, int TNB>
+__global__ __launch_bounds__(64 * kWaves) void k_offset_gemm2(OffsetGemm a, int rows_a, long na, OffsetGemm b,
+                                                              int rows_b)
+{
+    const long bid = blockIdx.x;
+    if (bid < na)
+        offset_tile<PREC, TMA, TNA>(a, bid / rows_a, (int)(bid % rows_a));
+    else
+        offset_tile<PREC, TMB, TNB>(b, (bid - na) / rows_b, (int)((bid - na) % rows_b));
+}
+
 // Per-target sums of the staged pair products, in a fixed order: one workgroup
 // per (target, 64-row slab, rhs); its four waves sum four consecutive quarters
 // of the target's pair list (8 row loads in flight per lane) and wave 0 adds
 // the quarters in order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage_reduce(OffsetGemm g, int rslabs)
+__device__ __forceinline__ void stage_reduce_block(const OffsetGemm& g, int rslabs, long blk)
 {
     __shared__ T part[3][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    long blk = blockIdx.x;
     const int rs = (int)(blk % rslabs);
     blk /= rslabs;
     const long t = blk % g.nbox;
@@ -355,6 +374,23 @@ __global__ __launch_bounds__(256) void k_stage_reduce(OffsetGemm g, int rslabs)
     s = s + part[0][lane] + part[1][lane] + part[2][lane];
     T* d = (T*)g.L + ((long)b * g.nbox + t) * g.M + r;
     *d = g.accumulate ? *d + s : s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_reduce(OffsetGemm g, int rslabs)
+{
+    stage_reduce_block<T>(g, rslabs, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_reduce2(OffsetGemm a, int rslabs_a, long na, OffsetGemm b,
+                                                       int rslabs_b)
+{
+    const long bid = blockIdx.x;
+    if (bid < na)
+        stage_reduce_block<T>(a, rslabs_a, bid);
+    else
+        stage_reduce_block<T>(b, rslabs_b, bid - na);
 }
 
 // ----------------------------------------------------- streaming pairs ----
@@ -673,6 +709,75 @@ ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g)
         hipLaunchKernelGGL(k_stage_reduce<double>, dim3((unsigned)nblk), dim3(256), 0, s, g, rslabs);
     else
         hipLaunchKernelGGL(k_stage_reduce<float>, dim3((unsigned)nblk), dim3(256), 0, s, g, rslabs);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+namespace {
+
+// Tile arrays and row-tile count of the form a product runs in.
+OffsetGemm with_form(const OffsetGemm& g, int* rows, long* nblk)
+{
+    OffsetGemm o = g;
+    const int tm = (g.tn == 4 && g.tm == 1) ? 1 : kTM;
+    if (g.tn == 4) {
+        o.pl.tile_group = g.pl.tile_group4;
+        o.pl.tile_col0 = g.pl.tile_col04;
+    }
+    *rows = g.M / (16 * tm);
+    *nblk = (g.tn == 4 ? g.pl.ntiles4 : g.pl.ntiles) * (long)*rows;
+    return o;
+}
+
+template <int PREC, int TMA, int TNA>
+void launch_pair_b(hipStream_t s, const OffsetGemm& a, int ra, long na, const OffsetGemm& b, int rb, long nb,
+                   int fb)
+{
+    const dim3 grid((unsigned)(na + nb)), blk(64 * kWaves);
+    if (fb == 1) hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, kTM, 1>), grid, blk, 0, s, a, ra, na, b, rb);
+    else if (fb == 2) hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, kTM, 4>), grid, blk, 0, s, a, ra, na, b, rb);
+    else hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, 1, 4>), grid, blk, 0, s, a, ra, na, b, rb);
+}
+
+template <int PREC>
+void launch_pair(hipStream_t s, const OffsetGemm& a, int ra, long na, int fa, const OffsetGemm& b, int rb, long nb,
+                 int fb)
+{
+    if (fa == 1) launch_pair_b<PREC, kTM, 1>(s, a, ra, na, b, rb, nb, fb);
+    else if (fa == 2) launch_pair_b<PREC, kTM, 4>(s, a, ra, na, b, rb, nb, fb);
+    else launch_pair_b<PREC, 1, 4>(s, a, ra, na, b, rb, nb, fb);
+}
+
+int form_of(const OffsetGemm& g) { return g.tn == 4 ? (g.tm == 1 ? 3 : 2) : 1; }
+
+}  // namespace
+
+ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b)
+{
+    for (const OffsetGemm* g : {&a, &b})
+        if (g->M % (16 * kTM) != 0 || g->Kd % 32 != 0) {
+            record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
+            return ERT_EINVAL;
+        }
+    int ra, rb;
+    long na, nb;
+    const OffsetGemm ga = with_form(a, &ra, &na), gb = with_form(b, &rb, &nb);
+    if (na + nb == 0) return ERT_OK;
+    if (prec == ERT_FP64) launch_pair<ERT_FP64>(s, ga, ra, na, form_of(a), gb, rb, nb, form_of(b));
+    else if (prec == ERT_FP32) launch_pair<ERT_FP32>(s, ga, ra, na, form_of(a), gb, rb, nb, form_of(b));
+    else launch_pair<ERT_BF16X3>(s, ga, ra, na, form_of(a), gb, rb, nb, form_of(b));
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
+
+ert_status offset_gemm_pair_reduce(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b)
+{
+    const int sa = (a.M + 63) / 64, sb = (b.M + 63) / 64;
+    const long na = a.nbox * sa * a.B, nb = b.nbox * sb * b.B;
+    if (prec == ERT_FP64)
+        hipLaunchKernelGGL(k_stage_reduce2<double>, dim3((unsigned)(na + nb)), dim3(256), 0, s, a, sa, na, b, sb);
+    else
+        hipLaunchKernelGGL(k_stage_reduce2<float>, dim3((unsigned)(na + nb)), dim3(256), 0, s, a, sa, na, b, sb);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }

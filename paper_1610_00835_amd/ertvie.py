@@ -62,7 +62,8 @@ class NetTrainOpts(ctypes.Structure):
 class FmmInfo(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("leaf", ctypes.c_int), ("cheb_n", ctypes.c_int),
                 ("nodes", ctypes.c_int), ("nodes_padded", ctypes.c_int), ("rank", ctypes.c_int * 16),
-                ("far_pairs", ctypes.c_long * 16), ("near_pairs", ctypes.c_long)]
+                ("far_pairs", ctypes.c_long * 16), ("near_pairs", ctypes.c_long), ("form_near", ctypes.c_int),
+                ("form_far", ctypes.c_int * 16)]
 
 
 class ErtError(RuntimeError):
@@ -256,7 +257,8 @@ class Plan:
         L = inf.levels
         return {"levels": L, "leaf": inf.leaf, "cheb_n": inf.cheb_n, "nodes": inf.nodes,
                 "nodes_padded": inf.nodes_padded, "rank": [inf.rank[l] for l in range(L + 1)],
-                "far_pairs": [inf.far_pairs[l] for l in range(L + 1)], "near_pairs": inf.near_pairs}
+                "far_pairs": [inf.far_pairs[l] for l in range(L + 1)], "near_pairs": inf.near_pairs,
+                "form_near": inf.form_near, "form_far": [inf.form_far[l] for l in range(L + 1)]}
 
     def diag(self):
         d = np.empty(self.N)

@@ -162,3 +162,27 @@ def test_mixed_solve_low_order_inner_operator(ev, oracle_mod, name, n, leaf):
     assert e64 <= 2e-5 and e32 <= 1e-2
     assert im["converged"] == 1 and im["rel_resid_true"] <= 1e-9
     assert rel_l2(Um, U64) <= 1e-7
+
+
+def test_history_pairs_are_corrections(ev, oracle_mod):
+    """The iterate history of a restarted solve gives training pairs (r_k, e_k = U - U_k) with
+    (I - K) e_k = r_k up to the final residual; the first pair is (phi, U)."""
+    import torch
+    from paper_1610_00835_amd import learn
+    case = inputs.make_case("c3", n=(12, 12, 12), seed=4)
+    with ev.plan_from_case(case, method="direct", prec="fp64") as plan:
+        R, E, info = learn.collect_pairs(plan, case["f"], restart=3, tol=1e-11, max_pairs=40)
+        assert info["converged"] == 1 and info["history_count"] == R.shape[0] >= 3
+        phi = torch.empty_like(R[0])
+        plan.apply(torch.from_numpy(case["f"]).cuda(), phi, op=ev.OP_G)
+        AE = torch.empty_like(E)
+        for k in range(E.shape[0]):
+            plan.apply(E[k].contiguous(), AE[k], op=ev.OP_A)
+        torch.cuda.synchronize()
+        assert float(torch.linalg.norm(R[0] - phi) / torch.linalg.norm(phi)) <= 1e-14
+        pn = float(torch.linalg.norm(phi))
+        for k in range(R.shape[0]):
+            rk = float(torch.linalg.norm(R[k]))
+            d = float(torch.linalg.norm(AE[k] - R[k]))
+            log("pair", k, "||r_k||/||phi||", rk / pn, "||A e_k - r_k||/||phi||", d / pn)
+            assert d <= 2e-11 * pn
