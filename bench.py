@@ -55,11 +55,10 @@ def stage_profile(plan, x, y, op, steps):
 SVD_TOL = 1e-5
 
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counter runs,
-# scaled by the readings of a 256 MiB device copy (profiles/near_c2_32cubed_fp32_hbm_traffic.md;
-# the 64-column form of the near-field product, the one the autotuner picks on this workload).
-# Keyed by (workload, precision, kernel); a kernel changed since its counters were taken has
-# no entry, and reports null.
-MEASURED_TRAFFIC = {}
+# scaled by the readings of a 256 MiB device copy (profiles/near_m2l_c2_32cubed_fp32_hbm_traffic.md).
+# Keyed by (workload, precision, kernel, execution forms "near,far" the autotuner chose); a
+# combination without counters, or a kernel changed since they were taken, reports null.
+MEASURED_TRAFFIC = {("c2", "fp32", "near+m2l", "2,1"): 72.15e6, ("c2", "fp32", "near+m2l", "1,1"): 72.11e6}
 
 
 def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None, forms=None):
