@@ -124,7 +124,11 @@ typedef struct {
                          with restart = 0 the block basis is capped at 4 GiB */
     int precond_steps;/* with precond: Arnoldi steps per preconditioned correction; 0 -> 10 */
     int history_max;  /* columns of `history` (0: no history) */
-    int reserved[1];  /* must be 0 */
+    int precond_fft;  /* 1: right-precondition every GMRES solve (the inner solves with `mixed`,
+                         each correction with `precond`) by the FFT-based preconditioner of the
+                         mean medium (ert_vie_fft_precond), in flexible GMRES; with `precond`
+                         the network acts on its output, z_j = net(M v_j), and the fallback
+                         of a rejected step keeps M.  0: none.  Not combined with `block` */
     ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
                          becomes a refinement loop.  Each step solves (I - K) d = r by flexible
                          GMRES with z_j = net(v_j) (inner operator: FP32 with `mixed`, else the
@@ -182,6 +186,43 @@ ERT_API ert_status ert_vie_apply_ex(ert_vie_plan_t plan, int op, int method, int
  * Returns ERT_ENOCONV when max_iter is reached first; U then holds the best iterate. */
 ERT_API ert_status ert_vie_solve(ert_vie_plan_t plan, const double* f, double* U, int nrhs,
                          const ert_solve_opts* opts, ert_solve_info* info);
+
+/* FFT-based preconditioner (Sec. 4.4, eqs. EQ: FFT and EQ:SOL FFT): the solve
+ * of the same equation in the constant medium sigma_t_mean, sigma_s_mean (the
+ * means of the plan's coefficients over the cells), done by FFT on a periodic
+ * grid of m_a cells per axis with the residual extended by zeros and the
+ * result restricted to the grid:
+ *   z = P IDFT( DFT(E r) / c ),   c = 1 - sigma_s_mean DFT(w),
+ * w[i] = h^d G(h o(i)) for the constant-medium kernel G at the periodic offset
+ * o(i)_a = i_a (i_a <= m_a / 2) or i_a - m_a, and w[0] = the self-cell integral
+ * of that medium (the diagonal of its M-iii matrix).  m_a is the smallest
+ * integer >= 2 n_a with no prime factor above 7 (2 n_a, the paper's [0, 2]^d,
+ * whenever 2 n_a has none), at most 1024.  For a constant medium, P C E with C
+ * the periodic operator of symbol c is exactly the plan's I - K.
+ * Arithmetic: the symbol is computed in FP64 (kernel array and its DFT) and
+ * kept as 1/c in FP32 on the half-grid of distinct values (c is even along every
+ * axis); the per-residual transforms are FP32 with FP32 twiddles from FP64
+ * tables.  Built on the plan's stream on first use (symbol plus work buffers:
+ * about 24 bytes per periodic cell for the build, 8 per cell of the
+ * n_2 x m_1 x (m_0/2 + 1) work grid after it). */
+typedef struct {
+    int m[3];             /* periodic grid, cells per axis (1 beyond dim) */
+    double sigma_t_mean;  /* the constant medium */
+    double sigma_s_mean;
+    double self_cell;     /* diagonal of the constant medium's matrix */
+    double symbol_min;    /* extremes of c (positive for sigma_s <= sigma_t) */
+    double symbol_max;
+    long bytes;           /* device memory held by the preconditioner */
+} ert_fft_info;
+
+/* z = M r for nrhs columns: r, z device N x nrhs column-major FP64 (may be the
+ * same buffer), 1 <= nrhs <= nrhs_max.  Stream-ordered, asynchronous after the
+ * first call.  ERT_EUNSUPPORTED when a period would exceed 1024 or the symbol is
+ * not positive. */
+ERT_API ert_status ert_vie_fft_precond(ert_vie_plan_t plan, const double* r, double* z, int nrhs);
+
+/* Build (if needed) and describe the FFT-based preconditioner (host struct). */
+ERT_API ert_status ert_vie_fft_info(ert_vie_plan_t plan, ert_fft_info* info);
 
 /* Stages of one FMM apply, for ert_vie_profile. */
 typedef enum {

@@ -189,6 +189,14 @@ struct History {
     int count = 0;
 };
 
+// Right preconditioner of a GMRES run: the FFT-based one of the mean medium,
+// the network, or the network acting on the FFT-based one's output.
+struct Precond {
+    NetImpl* net = nullptr;
+    bool fft = false;
+    bool active() const { return net != nullptr || fft; }
+};
+
 struct RunStats {
     int iters = 0, matvecs = 0, cycles = 0, precond = 0;
     double est = 0.0, true_rel = -1.0;
@@ -200,14 +208,15 @@ struct RunStats {
 // rotations and the small triangular solve on the host.  Stops when the
 // recurrence estimate reaches rtol ||b||; with check_true it then confirms the
 // true residual with the same operator and restarts from u if needed.
-// With a network: flexible GMRES with right preconditioning (Saad 1993), the
-// operator applied to z_j = net(v_j) and the update built from the z_j.
+// With a preconditioner: flexible GMRES with right preconditioning (Saad 1993),
+// the operator applied to z_j = M(v_j) and the update built from the z_j.
 ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, double* u, double rtol, int maxit,
-                     int restart, bool check_true, RunStats* rs, NetImpl* net = nullptr, History* hist = nullptr)
+                     int restart, bool check_true, RunStats* rs, const Precond* pc = nullptr, History* hist = nullptr)
 {
     const long N = p->N;
     const int m = (restart > 0 && restart < maxit) ? restart : maxit;
-    const int nz = net ? m : 0;
+    const bool flex = pc && pc->active();
+    const int nz = flex ? m : 0;
     // workspace: V (m+1 vectors), Z (m, flexible only), w, r
     ERT_TRY(ensure_workspace(p, (size_t)(m + nz + 3) * N, (size_t)kPartials * (m + 2) + 4 * (size_t)(m + 2)));
     double* V = p->d_ws;
@@ -247,10 +256,17 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
         bool done = false;
         for (int j = 0; j < m && rs->iters < maxit; ++j) {
             double* vj = V + (size_t)j * N;
-            if (net) {
+            if (flex) {
                 double* zj = Z + (size_t)j * N;
-                ERT_TRY(net_precond(net, vj, p->d_st, p->d_ss, zj, p->stream));
-                rs->precond++;
+                if (pc->fft && pc->net) {
+                    ERT_TRY(fftpc_apply(p, vj, w, 1));
+                    ERT_TRY(net_precond(pc->net, w, p->d_st, p->d_ss, zj, p->stream));
+                } else if (pc->fft) {
+                    ERT_TRY(fftpc_apply(p, vj, zj, 1));
+                } else {
+                    ERT_TRY(net_precond(pc->net, vj, p->d_st, p->d_ss, zj, p->stream));
+                }
+                if (pc->net) rs->precond++;
                 vj = zj;
             }
             ERT_TRY(apply_dispatch(p, ERT_OP_A, method, prec, vj, w, 1));
@@ -291,7 +307,7 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
             y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
         }
         ERT_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, p->stream));
-        ERT_TRY(dev_gemv_add(p->stream, net ? Z : V, N, k, dy, u, N));
+        ERT_TRY(dev_gemv_add(p->stream, flex ? Z : V, N, k, dy, u, N));
         if (!check_true) {
             if (done) rs->converged = true;
             if (done) break;
@@ -315,8 +331,9 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
 // step computes a correction d by flexible GMRES (at most precond_steps Arnoldi
 // steps, stopping at inner_tol) on the inner operator, and keeps U + d only if
 // the true residual of the outer operator decreases; a rejected step is redone
-// by plain GMRES with the same budget.  r and d are caller scratch (N each).
-ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec_inner, NetImpl* net,
+// without the network (plain GMRES, or with the FFT-based preconditioner alone
+// when `fft`) with the same budget.  r and d are caller scratch (N each).
+ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec_inner, NetImpl* net, bool fft,
                           const double* phi, double* U, double* r, double* d, const ert_solve_opts& so,
                           ert_solve_info* inf)
 {
@@ -345,8 +362,10 @@ ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec
         bool accepted = false;
         for (int attempt = 0; attempt < 2 && !accepted && st == ERT_OK; ++attempt) {
             RunStats rs;
-            st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, budget, budget, false, &rs,
-                           attempt == 0 ? net : nullptr);
+            Precond pc;
+            pc.net = attempt == 0 ? net : nullptr;
+            pc.fft = fft;
+            st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, budget, budget, false, &rs, &pc);
             if (st != ERT_OK) break;
             used += rs.iters;
             inf->iters += rs.iters;
@@ -424,6 +443,8 @@ void ert_vie_destroy(ert_vie_plan_t p)
         het_destroy(c);
         c = nullptr;
     }
+    fftpc_destroy(p->fftpc);
+    p->fftpc = nullptr;
     (void)hipFree(p->d_st);
     (void)hipFree(p->d_st32);
     (void)hipFree(p->d_ss);
@@ -550,6 +571,18 @@ ert_status ert_vie_fmm_info(ert_vie_plan_t p, int prec, ert_fmm_info* info)
     return fmm_info(p, prec, info);
 }
 
+ert_status ert_vie_fft_precond(ert_vie_plan_t p, const double* r, double* z, int nrhs)
+{
+    if (!p || !r || !z || nrhs < 1 || nrhs > p->nrhs_max) return ERT_EINVAL;
+    return fftpc_apply(p, r, z, nrhs);
+}
+
+ert_status ert_vie_fft_info(ert_vie_plan_t p, ert_fft_info* info)
+{
+    if (!p || !info) return ERT_EINVAL;
+    return fftpc_info(p, info);
+}
+
 ert_status ert_vie_diag(ert_vie_plan_t p, double* d)
 {
     if (!p || !d) return ERT_EINVAL;
@@ -571,8 +604,11 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
     if (so.inner_tol == 0.0) so.inner_tol = 1e-5;
     if (!(so.tol > 0.0) || so.max_iter < 1 || so.restart < 0 || !(so.inner_tol > 0.0) || so.inner_tol >= 1.0)
         return ERT_EINVAL;
-    for (int r : so.reserved)
-        if (r != 0) return ERT_EINVAL;
+    if (so.precond_fft != 0 && so.precond_fft != 1) return ERT_EINVAL;
+    if (so.precond_fft && so.block && nrhs > 1) {
+        record_error("ert_vie_solve: the FFT-based preconditioner is not combined with block GMRES");
+        return ERT_EUNSUPPORTED;
+    }
     if (so.precond_steps < 0 || so.history_max < 0 || (so.history_max > 0 && !so.history)) return ERT_EINVAL;
     NetImpl* net = so.precond ? net_impl(so.precond) : nullptr;
     if (net) {
@@ -680,6 +716,9 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         if (info) *info = inf;
         return st != ERT_OK ? st : result;
     }
+    Precond pc;
+    pc.fft = so.precond_fft != 0;
+    if (pc.fft) st = fftpc_apply(p, nullptr, nullptr, 0);   // build the symbol before the first column
     for (int c = 0; c < nrhs && st == ERT_OK; ++c) {
         std::memset(&inf, 0, sizeof(inf));
         const double* fc = f + (size_t)c * N;
@@ -694,7 +733,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         if (st != ERT_OK) break;
         if (net) {
             st = learned_refine(p, method, so.mixed ? ERT_FP64 : p->o.prec, so.mixed ? prec_inner : p->o.prec, net,
-                                phi, Uc, r, d, so, &inf);
+                                so.precond_fft != 0, phi, Uc, r, d, so, &inf);
         } else if (!so.mixed) {
             RunStats rs;
             History hist;
@@ -702,7 +741,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
                 hist.buf = so.history;
                 hist.cap = so.history_max;
             }
-            st = gmres_run(p, method, prec_outer, phi, Uc, so.tol, so.max_iter, so.restart, true, &rs, nullptr,
+            st = gmres_run(p, method, prec_outer, phi, Uc, so.tol, so.max_iter, so.restart, true, &rs, &pc,
                            hist.buf ? &hist : nullptr);
             inf.history_count = hist.count;
             inf.iters = rs.iters;
@@ -733,7 +772,8 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
                 if (used >= so.max_iter) break;
                 RunStats rs;
                 // the inner solve only needs to reduce this residual by inner_tol
-                st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, so.max_iter - used, so.restart, false, &rs);
+                st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, so.max_iter - used, so.restart, false, &rs,
+                               &pc);
                 if (st != ERT_OK) break;
                 used += rs.iters;
                 inf.iters += rs.iters;

@@ -115,6 +115,7 @@ __device__ __forceinline__ T tau_march(const T* __restrict__ st, const Geo& g, T
 
 struct FmmData;   // fmm.hip
 struct HetCache;  // fmm.hip
+struct FftPc;     // fftpc.hip
 
 // Per-stage event timing (ert_vie_profile).
 struct Profiler {
@@ -179,6 +180,7 @@ struct ert_plan_impl {
     size_t red_elems = 0;
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
     HetCache* het[2] = {nullptr, nullptr};   // heterogeneous kernel caches (per Chebyshev order)
+    FftPc* fftpc = nullptr;      // FFT-based preconditioner (built on first use)
     Profiler prof;
     bool use_graphs = true;      // FMM applies replay captured graphs
 };
@@ -186,11 +188,18 @@ struct ert_plan_impl {
 // ------------------------------------------------------ launchers (.hip) ---
 
 ert_status selfcell_compute(ert_plan_impl* p);
+// A_jj of the constant medium sigma (homogeneous kernel), to host `value`.
+ert_status selfcell_constant(ert_plan_impl* p, double sigma, double* value);
 ert_status direct_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
 ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
 ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info);
 void fmm_destroy(FmmData* f);
 void het_destroy(HetCache* c);
+// FFT-based preconditioner of the mean medium (fftpc.hip): z = M r for nrhs
+// columns (device FP64), stream-ordered; builds the symbol on first use.
+ert_status fftpc_apply(ert_plan_impl* p, const double* r, double* z, int nrhs);
+ert_status fftpc_info(ert_plan_impl* p, ert_fft_info* info);
+void fftpc_destroy(FftPc* f);
 
 // BLAS-1 helpers for GMRES (blas.hip); all stream-ordered on `s`.
 // out[c] = <V[:,c], w> for c < ncols; V has leading dimension ldv.

@@ -219,7 +219,11 @@ ert_status launch_direct(ert_plan_impl* p, const T* st, int op, const double* x,
 
 }  // namespace
 
-ert_status selfcell_compute(ert_plan_impl* p)
+namespace {
+
+// Launch k_selfcell for cells [0, ncell) (ray rule: the plan's sigma_t; else
+// the constant `sigma`) into diag, with the plan's angular and radial rules.
+ert_status selfcell_launch(ert_plan_impl* p, int ray, double sigma, long ncell, double* diag)
 {
     const int nang = 16, nrad = 10;
     std::vector<double> ax, aw, rx, rw;
@@ -232,31 +236,42 @@ ert_status selfcell_compute(ert_plan_impl* p)
     pack.insert(pack.end(), rw.begin(), rw.end());
     double* d = nullptr;
     ERT_HIP(hipMalloc(&d, pack.size() * sizeof(double)));
-    ert_status st = ERT_OK;
-    do {
-        st = ERT_HIPST(hipMemcpyAsync(d, pack.data(), pack.size() * sizeof(double), hipMemcpyHostToDevice,
-                                      p->stream));
-        if (st != ERT_OK) break;
-        const int ray = p->o.kernel == ERT_K_RAY_MIDPOINT;
-        const long ncell = ray ? p->N : 1;
-        // chunk the launch so one dispatch never holds the GPU for long
-        const long chunk = 65536;
-        for (long j0 = 0; j0 < ncell && st == ERT_OK; j0 += chunk) {
-            long cnt = (ncell - j0) < chunk ? (ncell - j0) : chunk;
-            hipLaunchKernelGGL(k_selfcell, dim3((unsigned)cnt), dim3(256), 0, p->stream, p->geo, ray,
-                               p->sigma_const, p->d_st, d, d + nang, nang, d + 2 * nang, d + 2 * nang + nrad, nrad,
-                               j0, p->d_diag);
-            st = ERT_HIPST(hipGetLastError());
-        }
-        if (st != ERT_OK) break;
-        if (!ray) {
-            hipLaunchKernelGGL(k_fill, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, p->stream, p->d_diag,
-                               p->N, p->d_diag);
-            st = ERT_HIPST(hipGetLastError());
-            if (st != ERT_OK) break;
-        }
-        st = ERT_HIPST(hipStreamSynchronize(p->stream));
-    } while (0);
+    ert_status st = ERT_HIPST(hipMemcpyAsync(d, pack.data(), pack.size() * sizeof(double), hipMemcpyHostToDevice,
+                                             p->stream));
+    // chunk the launch so one dispatch never holds the GPU for long
+    const long chunk = 65536;
+    for (long j0 = 0; j0 < ncell && st == ERT_OK; j0 += chunk) {
+        long cnt = (ncell - j0) < chunk ? (ncell - j0) : chunk;
+        hipLaunchKernelGGL(k_selfcell, dim3((unsigned)cnt), dim3(256), 0, p->stream, p->geo, ray, sigma, p->d_st, d,
+                           d + nang, nang, d + 2 * nang, d + 2 * nang + nrad, nrad, j0, diag);
+        st = ERT_HIPST(hipGetLastError());
+    }
+    if (st == ERT_OK) st = ERT_HIPST(hipStreamSynchronize(p->stream));
+    (void)hipFree(d);
+    return st;
+}
+
+}  // namespace
+
+ert_status selfcell_compute(ert_plan_impl* p)
+{
+    const int ray = p->o.kernel == ERT_K_RAY_MIDPOINT;
+    ERT_TRY(selfcell_launch(p, ray, p->sigma_const, ray ? p->N : 1, p->d_diag));
+    if (!ray) {
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, p->stream, p->d_diag, p->N,
+                           p->d_diag);
+        ERT_HIP(hipGetLastError());
+        ERT_HIP(hipStreamSynchronize(p->stream));
+    }
+    return ERT_OK;
+}
+
+ert_status selfcell_constant(ert_plan_impl* p, double sigma, double* value)
+{
+    double* d = nullptr;
+    ERT_HIP(hipMalloc(&d, sizeof(double)));
+    ert_status st = selfcell_launch(p, 0, sigma, 1, d);
+    if (st == ERT_OK) st = ERT_HIPST(hipMemcpy(value, d, sizeof(double), hipMemcpyDeviceToHost));
     (void)hipFree(d);
     return st;
 }

@@ -39,7 +39,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("mixed", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_is_phi", ctypes.c_int),
                 ("block", ctypes.c_int), ("precond_steps", ctypes.c_int), ("history_max", ctypes.c_int),
-                ("reserved", ctypes.c_int * 1), ("precond", ctypes.c_void_p), ("history", ctypes.c_void_p)]
+                ("precond_fft", ctypes.c_int), ("precond", ctypes.c_void_p), ("history", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -64,6 +64,12 @@ class FmmInfo(ctypes.Structure):
                 ("nodes", ctypes.c_int), ("nodes_padded", ctypes.c_int), ("rank", ctypes.c_int * 16),
                 ("far_pairs", ctypes.c_long * 16), ("near_pairs", ctypes.c_long), ("form_near", ctypes.c_int),
                 ("form_far", ctypes.c_int * 16)]
+
+
+class FftInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int * 3), ("sigma_t_mean", ctypes.c_double), ("sigma_s_mean", ctypes.c_double),
+                ("self_cell", ctypes.c_double), ("symbol_min", ctypes.c_double), ("symbol_max", ctypes.c_double),
+                ("bytes", ctypes.c_long)]
 
 
 class ErtError(RuntimeError):
@@ -99,6 +105,10 @@ def load():
     L.ert_vie_solve.restype = ctypes.c_int
     L.ert_vie_solve.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(SolveOpts),
                                 ctypes.POINTER(SolveInfo)]
+    L.ert_vie_fft_precond.restype = ctypes.c_int
+    L.ert_vie_fft_precond.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+    L.ert_vie_fft_info.restype = ctypes.c_int
+    L.ert_vie_fft_info.argtypes = [_vp, ctypes.POINTER(FftInfo)]
     L.ert_vie_diag.restype = ctypes.c_int
     L.ert_vie_diag.argtypes = [_vp, _dp]
     L.ert_vie_size.restype = ctypes.c_long
@@ -210,9 +220,28 @@ class Plan:
         _check(st, "ert_vie_apply")
         return y
 
+    def fft_precond(self, r, z):
+        """z = M r with the FFT-based preconditioner of the mean medium (asynchronous
+        after the first call, which builds it)."""
+        rp, nr = _dev_ptr(r, self.N, "r")
+        zp, nz = _dev_ptr(z, self.N, "z")
+        if nr != nz:
+            raise ValueError("r and z differ in nrhs")
+        _check(load().ert_vie_fft_precond(self.handle, rp, zp, nr), "ert_vie_fft_precond")
+        return z
+
+    def fft_info(self):
+        inf = FftInfo()
+        _check(load().ert_vie_fft_info(self.handle, ctypes.byref(inf)), "ert_vie_fft_info")
+        return {"m": list(inf.m), "sigma_t_mean": inf.sigma_t_mean, "sigma_s_mean": inf.sigma_s_mean,
+                "self_cell": inf.self_cell, "symbol_min": inf.symbol_min, "symbol_max": inf.symbol_max,
+                "bytes": inf.bytes}
+
     def solve(self, f, U, tol=1e-8, max_iter=500, restart=0, mixed=False, inner_tol=1e-5, rhs_is_phi=False,
-              allow_noconv=False, block=False, precond=None, precond_steps=0, history=None):
+              allow_noconv=False, block=False, precond=None, precond_steps=0, history=None, precond_fft=False):
         """Algorithm 1 steps S.1-S.2.  precond: a Net (learned right preconditioner);
+        precond_fft: right-precondition by the FFT-based preconditioner of the mean medium
+        (with precond, the network acts on its output);
         history: float64 CUDA tensor (2k, N) receiving (U_k, r_k) of the plain solve's cycles."""
         fp, nf = _dev_ptr(f, self.N, "f")
         up, nu = _dev_ptr(U, self.N, "U")
@@ -227,6 +256,7 @@ class Plan:
         so.rhs_is_phi = 1 if rhs_is_phi else 0
         so.block = 1 if block else 0
         so.precond_steps = int(precond_steps)
+        so.precond_fft = 1 if precond_fft else 0
         if precond is not None:
             so.precond = precond.handle.value
         if history is not None:

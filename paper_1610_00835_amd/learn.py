@@ -29,9 +29,11 @@ def init_params(widths=(16, 32, 64), seed=0):
     return np.concatenate(out).astype(np.float32)
 
 
-def collect_pairs(plan, f, restart=5, tol=1e-10, max_pairs=64, max_iter=3000):
+def collect_pairs(plan, f, restart=5, tol=1e-10, max_pairs=64, max_iter=3000, fft=False):
     """Solve (I - K) U = A f with plain restarted GMRES and return (R, E, info): residuals
-    r_k and corrections e_k = U - U_k of the cycles, as (k, N) float64 CUDA tensors."""
+    r_k and corrections e_k = U - U_k of the cycles, as (k, N) float64 CUDA tensors.
+    With fft, R holds M r_k instead (M the FFT-based preconditioner of the mean medium):
+    the input a network sees when it acts on that preconditioner's output."""
     import torch
     N = plan.N
     fd = torch.as_tensor(np.ascontiguousarray(f, dtype=np.float64)).cuda()
@@ -42,6 +44,9 @@ def collect_pairs(plan, f, restart=5, tol=1e-10, max_pairs=64, max_iter=3000):
     Uk = hist[0:2 * k:2]
     R = hist[1:2 * k:2].clone()
     E = (U.unsqueeze(0) - Uk).contiguous()
+    if fft:
+        for i in range(k):
+            plan.fft_precond(R[i], R[i])
     return R, E, info
 
 
