@@ -142,10 +142,86 @@ def many_scattering_128(torch, ertvie, inputs, O, stream, args):
         U0 = U.clone()
         r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, max_iter=150)
         out["mixed"] = {k: r[k] for k in keys}
-        out["mixed"]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / r["t_solve"]
         out["mixed_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
         log("128^3 mixed:", json.dumps(out["mixed"]))
+        out["fft_precond"] = plan.fft_info()
+        out["fft_precond"]["apply_ms"] = timed_fft(torch, plan, x, y, 20)
+        plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, max_iter=150, precond_fft=True)   # warm
+        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, max_iter=150, precond_fft=True)
+        out["mixed_fft"] = {k: r[k] for k in keys}
+        out["mixed_fft_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        log("128^3 mixed + FFT-based preconditioner:", json.dumps(out["mixed_fft"]))
+        if os.path.exists(WEIGHTS_FFT):
+            w = np.load(WEIGHTS_FFT)
+            with ertvie.Net(case["n"], stream=stream) as net:
+                net.set_params(w["params"])
+                kw = dict(tol=1e-8, mixed=True, inner_tol=1e-3, max_iter=150, precond_fft=True, precond=net,
+                          precond_steps=int(json.loads(str(w["meta"]))["precond_steps"]))
+                plan.solve(fd, U, **kw)
+                r = plan.solve(fd, U, **kw)
+                out["mixed_fft_learned"] = {k: r[k] for k in keys}
+                out["mixed_fft_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+                log("128^3 mixed + FFT + network:", json.dumps(out["mixed_fft_learned"]))
+        for k in ("mixed", "mixed_fft", "mixed_fft_learned"):
+            if k in out:
+                out[k]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / out[k]["t_solve"]
     return out
+
+
+# Sec. 5.3, Experiments V and VI: GMRES iterations to 1e-12 without and with the
+# FFT-based preconditioner (Table TAB:EXP VI, the paper's MATLAB code on one laptop core).
+PAPER_EXP6_ITERS = {10.0: (21, 9), 20.0: (34, 11), 40.0: (78, 13), 80.0: (110, 15)}
+
+
+def paper_experiment_vi(torch, ertvie, inputs, stream):
+    """The paper's preconditioning experiment: 2D unit square, h = 1/512 (N = 262,144),
+    Chebyshev order 6, absorption 0.2 and scattering 10, 20, 40, 80 (homogeneous), GMRES to
+    1e-12, unpreconditioned and with the FFT-based preconditioner.  The paper's source exists
+    only as a figure; a Gaussian of width 0.1 at the centre stands in for it (far from the
+    boundary, the preconditioner's assumption)."""
+    n = (512, 512)
+    N = 512 * 512
+    x = inputs.centres(n, 1.0 / 512)
+    f = np.exp(-np.sum((x - 0.5) ** 2, axis=1) / (2 * 0.1 ** 2))
+    fd = torch.from_numpy(f).cuda()
+    out = {"workload": "2D 512^2, mu_a = 0.2, homogeneous, Gaussian source (width 0.1), tol 1e-12, FMM n = 6, FP64",
+           "paper_iters_plain_fft": {str(k): v for k, v in PAPER_EXP6_ITERS.items()}, "runs": {}}
+    keys = ("iters", "matvecs", "t_solve", "rel_resid_true")
+    for mus in sorted(PAPER_EXP6_ITERS):
+        case = {"dim": 2, "n": n, "h": 1.0 / 512, "kernel": ertvie.K_HOMOGENEOUS,
+                "sigma_t": np.full(N, mus + 0.2), "sigma_s": np.full(N, mus)}
+        with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=6) as plan:
+            U = torch.empty_like(fd)
+            plan.solve(fd, U, tol=1e-12, max_iter=300)                       # graphs, tuning
+            r0 = plan.solve(fd, U, tol=1e-12, max_iter=300)
+            U0 = U.clone()
+            plan.solve(fd, U, tol=1e-12, max_iter=300, precond_fft=True)
+            r1 = plan.solve(fd, U, tol=1e-12, max_iter=300, precond_fft=True)
+            d = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        run = {"plain": {k: r0[k] for k in keys}, "fft": {k: r1[k] for k in keys}, "fft_vs_plain_rel_l2": d,
+               "speedup": r0["t_solve"] / r1["t_solve"]}
+        for k in ("plain", "fft"):
+            run[k]["ms_per_iter"] = 1e3 * run[k]["t_solve"] / max(1, run[k]["matvecs"])
+        out["runs"][str(mus)] = run
+        log("experiment VI mu_s = %g: plain %d iterations (paper %d), FFT-preconditioned %d (paper %d), %.3f s vs %.3f s"
+            % (mus, r0["iters"], PAPER_EXP6_ITERS[mus][0], r1["iters"], PAPER_EXP6_ITERS[mus][1], r0["t_solve"],
+               r1["t_solve"]))
+    return out
+
+
+def timed_fft(torch, plan, x, z, steps):
+    """Mean device time of the FFT-based preconditioner on the plan's stream (events)."""
+    for _ in range(3):
+        plan.fft_precond(x, z)
+    s = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(steps):
+        plan.fft_precond(x, z)
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
 
 
 def many_rhs_64(torch, ertvie, inputs, stream):
@@ -179,6 +255,9 @@ def many_rhs_64(torch, ertvie, inputs, stream):
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
                        "precond_c5_64.npz")
+# network trained on the FFT-based preconditioner's output (it acts after that preconditioner)
+WEIGHTS_FFT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
+                           "precond_c5_64_fft.npz")
 
 
 def many_scattering_solves(torch, ertvie, inputs, stream, args):
@@ -213,7 +292,29 @@ def many_scattering_solves(torch, ertvie, inputs, stream, args):
                 r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, precond=net)
                 out["mixed_learned"] = {k: r[k] for k in keys}
                 out["mixed_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        for k in ("mixed", "mixed_learned"):
+        # the paper's FFT-based preconditioner (Sec. 4.4) of the mean medium
+        x = torch.from_numpy(inputs.random_vector(plan.N, 21)).cuda()
+        z = torch.empty_like(x)
+        out["fft_precond"] = plan.fft_info()
+        out["fft_precond"]["apply_ms"] = timed_fft(torch, plan, x, z, 50)
+        plan.solve(fd, U, tol=1e-8, precond_fft=True)
+        r = plan.solve(fd, U, tol=1e-8, precond_fft=True)
+        out["plain_fp64_fft"] = {k: r[k] for k in keys}
+        plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, precond_fft=True)
+        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, precond_fft=True)
+        out["mixed_fft"] = {k: r[k] for k in keys}
+        out["mixed_fft_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        if os.path.exists(WEIGHTS_FFT):
+            w = np.load(WEIGHTS_FFT)
+            with ertvie.Net((64, 64, 64), stream=stream) as net:
+                net.set_params(w["params"])
+                kw = dict(tol=1e-8, mixed=True, inner_tol=1e-3, precond_fft=True, precond=net,
+                          precond_steps=int(json.loads(str(w["meta"]))["precond_steps"]))
+                plan.solve(fd, U, **kw)
+                r = plan.solve(fd, U, **kw)
+                out["mixed_fft_learned"] = {k: r[k] for k in keys}
+                out["mixed_fft_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        for k in ("mixed", "mixed_learned", "plain_fp64_fft", "mixed_fft", "mixed_fft_learned"):
             if k in out:
                 out[k]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / out[k]["t_solve"]
     log("many-scattering solves:", json.dumps(out))
@@ -231,6 +332,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--c5-128", action="store_true",
                     help="also run the 128^3 many-scattering medium (plan ~1 min, ~250 GB of device memory)")
+    ap.add_argument("--paper-exp6", action="store_true",
+                    help="also run the paper's preconditioning experiment (2D 512^2, four media)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three 256 MiB device copies (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -324,6 +427,9 @@ def main():
     if not args.no_solve and not args.no_c3:
         extra["solve_many_scattering_64cubed"] = many_scattering_solves(torch, ertvie, inputs, stream, args)
         extra["many_rhs_64cubed"] = many_rhs_64(torch, ertvie, inputs, stream)
+
+    if args.paper_exp6:
+        extra["paper_experiment_vi"] = paper_experiment_vi(torch, ertvie, inputs, stream)
 
     if args.c5_128:
         extra["many_scattering_128cubed"] = many_scattering_128(torch, ertvie, inputs, O, stream, args)

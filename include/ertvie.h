@@ -108,7 +108,13 @@ typedef struct {
                          inner operator of mixed solves); 0 -> cheb_n; 2..8.  The far-field
                          translations cost n^(2d) per box pair, so a lower order makes the inner
                          solves cheaper; the FP64 outer residual keeps the accuracy */
-    int reserved0;    /* must be 0 */
+    int inner_near16; /* heterogeneous media, FMM: 1 -> the FP32 and BF16x3 applies (the inner
+                         operator of mixed solves) read the near-field kernel cache rounded to
+                         BF16 (2 bytes per value instead of 4; relative rounding <= 2^-9 per
+                         value).  The cache always holds each FP32 value as two 16-bit planes,
+                         the high half rounded to BF16 and the exact remainder: FP64 applies,
+                         and FP32 applies without this option, read both and rebuild the FP32
+                         value exactly.  0 or 1 */
 } ert_vie_opts;
 
 typedef struct {

@@ -468,7 +468,7 @@ ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const d
     if (o.cheb_n != 0 && (o.cheb_n < 2 || o.cheb_n > 8)) return ERT_EINVAL;
     if (o.leaf < 0 || o.leaf > 8 || o.nrhs_max < 0 || !std::isfinite(o.svd_tol) || o.svd_tol >= 1.0)
         return ERT_EINVAL;
-    if ((o.inner_cheb_n != 0 && (o.inner_cheb_n < 2 || o.inner_cheb_n > 8)) || o.reserved0 != 0) return ERT_EINVAL;
+    if ((o.inner_cheb_n != 0 && (o.inner_cheb_n < 2 || o.inner_cheb_n > 8)) || (o.inner_near16 != 0 && o.inner_near16 != 1)) return ERT_EINVAL;
     long N = 1;
     for (int a = 0; a < o.dim; ++a) {
         if (o.n[a] < 1 || o.n[a] > (1 << 20)) return ERT_EINVAL;

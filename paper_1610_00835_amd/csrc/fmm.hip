@@ -26,6 +26,8 @@
 
 #include "fmm.hpp"
 
+#include <type_traits>
+
 namespace ertvie {
 
 struct FmmData {
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__
 // blk points at the block of leaf leaf0.
 template <typename T>
 __global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, long leaf0, long nleaves,
-                              T* __restrict__ blk)
+                              T* __restrict__ blk, int16_t* __restrict__ lo_plane)
 {
     const int nn = (t.D == 3) ? 27 : 9;
     const long per = (long)nn * t.S * t.S;
@@ -411,7 +413,16 @@ __global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, l
             v = exp(-tau) / (surface_area(t.D) * rp);
         }
     }
-    blk[i] = T(v);
+    if constexpr (std::is_same<T, uint16_t>::value) {
+        // FP32 value X as the high half rounded to BF16 and the exact signed remainder:
+        // X = (hi << 16) + lo, lo in [-2^15, 2^15) (values are >= 0)
+        const unsigned X = __float_as_uint((float)v);
+        const unsigned hi = (X + 0x8000u) >> 16;
+        blk[i] = (uint16_t)hi;
+        lo_plane[i] = (int16_t)(int)(X - (hi << 16));
+    } else {
+        blk[i] = T(v);
+    }
 }
 
 // ----------------------------------------------- far-field operators ----
@@ -1157,7 +1168,8 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     if (other) {
         // the near field does not depend on the Chebyshev order: share it
         c->owns_near = false;
-        c->nearblk = other->nearblk;
+        c->near_hi = other->near_hi;
+        c->near_lo = other->near_lo;
         c->near_src = other->near_src;
         c->near_tstart = other->near_tstart;
         for (int l = 2; l <= tr.L; ++l) {
@@ -1170,13 +1182,14 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
         return ERT_OK;
     }
     const long per = (long)nn * tr.S * tr.S;
-    const size_t bytes = (size_t)tr.nleaf * per * sizeof(float);
+    const size_t plane = (size_t)tr.nleaf * per * sizeof(uint16_t);
+    const size_t bytes = 2 * plane;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
         record_error("FMM: heterogeneous near-field cache does not fit in device memory");
         return fail(ERT_ENOMEM);
     }
-    if (hipMalloc(&c->nearblk, bytes) != hipSuccess) {
+    if (hipMalloc(&c->near_hi, plane) != hipSuccess || hipMalloc(&c->near_lo, plane) != hipSuccess) {
         record_error("FMM: near-field cache allocation failed");
         return fail(ERT_ENOMEM);
     }
@@ -1184,8 +1197,8 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     const long chunk = std::max<long>(1, (1L << 26) / per);
     for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
         long cnt = std::min(chunk, tr.nleaf - l0);
-        hipLaunchKernelGGL(k_near_blocks<float>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, l0,
-                           cnt, c->nearblk + (size_t)l0 * per);
+        hipLaunchKernelGGL(k_near_blocks<uint16_t>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, l0,
+                           cnt, c->near_hi + (size_t)l0 * per, c->near_lo + (size_t)l0 * per);
         if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
     }
     std::vector<int> src((size_t)tr.nleaf * nn);
@@ -1556,12 +1569,14 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         StageTimer* near_timer = &st_;
         if (hetero) {
             PairStream a;
-            a.ops_f32 = 1;
+            // the FP32 applies of a plan with inner_near16 read the BF16-rounded plane alone
+            a.ops_fmt = (prec != ERT_FP64 && p->o.inner_near16) ? kOpsHi : kOpsSplit;
+            a.opsT_lo = hc->near_lo;
             a.npairs = tr.nleaf * nn;
             a.ntarget = tr.nleaf;
             a.B = nrhs;
             a.M = a.Kd = tr.S;
-            a.opsT = hc->nearblk;
+            a.opsT = hc->near_hi;
             a.src = hc->near_src;
             a.nsrc = tr.nleaf;
             a.tstart = hc->near_tstart;
@@ -1632,7 +1647,8 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             StageTimer st_(pf, s, ERT_STAGE_M2L);
             if (hetero) {
                 PairStream a;
-                a.ops_f32 = 1;
+                a.ops_fmt = kOpsF32;
+                a.opsT_lo = nullptr;
                 a.npairs = hc->hnp[l];
                 a.ntarget = tr.nbox[l];
                 a.B = nrhs;
@@ -1859,7 +1875,7 @@ HetCache::~HetCache()
 {
     auto f = [](void* q) { if (q) (void)hipFree(q); };
     if (owns_near) {
-        f(nearblk); f(near_src); f(near_tstart);
+        f(near_hi); f(near_lo); f(near_src); f(near_tstart);
     }
     for (int l = 0; l <= kMaxLevels; ++l) {
         f(hops[l]); f(pstart[l]); f(psrc[l]);

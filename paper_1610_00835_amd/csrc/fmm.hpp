@@ -111,8 +111,19 @@ ert_status offset_gemm_pair_reduce(hipStream_t s, int prec, const OffsetGemm& a,
 // right-hand sides at a time and writes a staging row; a second pass sums the
 // contiguous pairs of every target in a fixed order.  The staging buffer holds
 // 8 right-hand sides (min(B, 8) x npairs x M elements).
+// Storage of the cached matrices read by the pair products.
+enum {
+    kOpsNative = 0,          // values of the arithmetic type
+    kOpsF32 = 1,             // FP32 values (FP64 products read FP32 caches)
+    kOpsSplit = 2,           // FP32 values as two 16-bit planes: opsT = high halves rounded to
+                             // BF16 (bits (X + 0x8000) >> 16), opsT_lo = signed remainders; the
+                             // value is rebuilt exactly
+    kOpsHi = 3               // the high plane alone: the FP32 values rounded to BF16
+};
+
 struct PairStream {
-    int ops_f32;             // 1: opsT holds FP32 values (FP64 products read FP32 caches)
+    int ops_fmt;             // kOps*
+    const void* opsT_lo;     // kOpsSplit: remainder plane (same layout as opsT)
     long npairs;
     long ntarget;
     int B;
@@ -140,7 +151,8 @@ ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
 struct HetCache {
     int nc = 0, leaf = 0;                   // tree the cache was built for
     bool owns_near = true;                  // false: the near part belongs to another order's cache
-    float* nearblk = nullptr;               // [leaf][3^d][S][S] (target fastest)
+    uint16_t* near_hi = nullptr;            // [leaf][3^d][S][S] (target fastest), FP32 values as
+    int16_t* near_lo = nullptr;             // a BF16-rounded high plane and a remainder plane
     int* near_src = nullptr;                // [leaf * 3^d] source leaf, -1 outside the grid
     long* near_tstart = nullptr;            // [nleaf + 1]
     float* hops[kMaxLevels + 1] = {};       // [pair][Kp][Kp], source-node major

@@ -427,6 +427,67 @@ __device__ __forceinline__ void store_rows(T* p, const T (&o)[RPT])
     }
 }
 
+// Tags for the 16-bit plane storage of cached matrices (kOpsSplit, kOpsHi).
+struct OpsSplit {};
+struct OpsHi {};
+
+template <typename TS> struct OpsVal { typedef TS T; };
+template <> struct OpsVal<OpsSplit> { typedef float T; };
+template <> struct OpsVal<OpsHi> { typedef float T; };
+
+template <typename TS>
+constexpr bool ops_planes() { return std::is_same<TS, OpsSplit>::value || std::is_same<TS, OpsHi>::value; }
+
+// One value from 16-bit planes: high half (BF16 bits) plus, for the split form,
+// the signed remainder, i.e. the FP32 bit pattern (hi << 16) + lo.
+template <typename TS>
+__device__ __forceinline__ float plane_value(unsigned hi, int lo)
+{
+    const unsigned bits = std::is_same<TS, OpsSplit>::value ? (hi << 16) + (unsigned)lo : hi << 16;
+    return __uint_as_float(bits);
+}
+
+// RPT consecutive cached values starting at element idx.
+template <typename TS, int RPT>
+__device__ __forceinline__ void load_ops(const PairStream& g, size_t idx, typename OpsVal<TS>::T (&o)[RPT])
+{
+    if constexpr (ops_planes<TS>()) {
+        const unsigned short* hp = (const unsigned short*)g.opsT + idx;
+        const short* lp = (const short*)g.opsT_lo + idx;
+        if constexpr (RPT == 4) {
+            const uint2 h = *(const uint2*)hp;                 // four high halves, 8 bytes
+            unsigned hv[4] = {h.x & 0xffffu, h.x >> 16, h.y & 0xffffu, h.y >> 16};
+            int lv[4] = {0, 0, 0, 0};
+            if constexpr (std::is_same<TS, OpsSplit>::value) {
+                const uint2 l = *(const uint2*)lp;
+                lv[0] = (short)(l.x & 0xffffu);
+                lv[1] = (short)(l.x >> 16);
+                lv[2] = (short)(l.y & 0xffffu);
+                lv[3] = (short)(l.y >> 16);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = plane_value<TS>(hv[e], lv[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < RPT; ++e)
+                o[e] = plane_value<TS>(hp[e], std::is_same<TS, OpsSplit>::value ? (int)lp[e] : 0);
+        }
+    } else {
+        load_rows<TS, RPT>((const TS*)g.opsT + idx, o);
+    }
+}
+
+// One cached value as FP32 (the matrix-core form reads FP32-stored caches).
+template <typename TS>
+__device__ __forceinline__ float load_op1(const PairStream& g, size_t idx)
+{
+    if constexpr (ops_planes<TS>())
+        return plane_value<TS>(((const unsigned short*)g.opsT)[idx],
+                               std::is_same<TS, OpsSplit>::value ? (int)((const short*)g.opsT_lo)[idx] : 0);
+    else
+        return ((const float*)g.opsT)[idx];
+}
+
 // One workgroup (256 threads) per pair.  Each thread owns RPT consecutive
 // output rows (one 16-byte load per matrix row when the row count allows);
 // when the rows need fewer than 256 threads the reduction dimension is split
@@ -460,12 +521,13 @@ __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
 #pragma unroll
             for (int e = 0; e < RPT; ++e) acc[b][e] = T(0);
         if (act) {
-            const TS* col = (const TS*)g.opsT + (size_t)p * g.Kd * g.M + (size_t)rg * RPT;
+            typedef typename OpsVal<TS>::T TV;
+            const size_t col = (size_t)p * g.Kd * g.M + (size_t)rg * RPT;
             int k = k0;
             for (; k + 8 <= k1; k += 8) {
-                TS m[8][RPT];
+                TV m[8][RPT];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) load_rows<TS, RPT>(col + (size_t)(k + u) * g.M, m[u]);
+                for (int u = 0; u < 8; ++u) load_ops<TS, RPT>(g, col + (size_t)(k + u) * g.M, m[u]);
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -476,8 +538,8 @@ __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
                     }
             }
             for (; k < k1; ++k) {
-                TS m[RPT];
-                load_rows<TS, RPT>(col + (size_t)k * g.M, m);
+                TV m[RPT];
+                load_ops<TS, RPT>(g, col + (size_t)k * g.M, m);
 #pragma unroll
                 for (int b = 0; b < RB; ++b)
 #pragma unroll
@@ -515,7 +577,7 @@ __global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
 // form converts the stored FP32 values).  Workgroup: one pair and 64 RT rows per
 // wave-row block; the 64 source vectors are staged through LDS, 32 k at a time,
 // transposed so that lanes read consecutive columns.
-template <int PREC, int RT>
+template <int PREC, int RT, typename TS>
 __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rblocks)
 {
     typedef typename Acc<PREC>::V V;
@@ -529,7 +591,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rbl
     const int s = g.src[p];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
     const int row0 = (rblk * 4 + wave) * 16 * RT;
-    const float* A = (const float*)g.opsT + (size_t)p * g.Kd * g.M;
+    const size_t A = (size_t)p * g.Kd * g.M;
     V acc[RT][4];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -552,7 +614,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rbl
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int row = row0 + 16 * rt + li;
-                a[rt] = (k < g.Kd && row < g.M) ? (T)A[(size_t)k * g.M + row] : T(0);
+                a[rt] = (k < g.Kd && row < g.M) ? (T)load_op1<TS>(g, A + (size_t)k * g.M + row) : T(0);
             }
             T bf[4];
 #pragma unroll
@@ -800,16 +862,16 @@ void launch_pair_stream(hipStream_t s, const PairStream& g, int b0, int rb)
     else hipLaunchKernelGGL((k_pair_stream<T, TS, 1, RPT>), grid, dim3(256), sh, s, g, b0);
 }
 
-// Matrix-core form for many right-hand sides (FP32 storage), 64 per pass.
-template <int PREC>
+// Matrix-core form for many right-hand sides (FP32 storage, whole or in planes), 64 per pass.
+template <int PREC, typename TS>
 ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
 {
     constexpr int RT = (PREC == ERT_FP64) ? 4 : 8;
     const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
     for (int b0 = 0; b0 < g.B; b0 += 64) {
         const int nb = std::min(64, g.B - b0);
-        hipLaunchKernelGGL((k_pair_mfma<PREC, RT>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s, g, b0,
-                           rblocks);
+        hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s, g,
+                           b0, rblocks);
         ERT_HIP(hipGetLastError());
         const long n = g.ntarget * g.M * nb;
         typedef typename Acc<PREC>::T T;
@@ -823,7 +885,7 @@ ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
 template <typename T, typename TS>
 ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 {
-    constexpr int VEC = 16 / sizeof(TS);
+    constexpr int VEC = ops_planes<TS>() ? 4 : 16 / (int)sizeof(TS);
     const int rows = g.M % VEC == 0 ? g.M / VEC : g.M;
     if (g.M < 1 || g.Kd < 1 || (size_t)8 * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T) > 64 * 1024) {
         record_error("pair_stream: unsupported operator shape");
@@ -846,10 +908,24 @@ ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
 {
-    if (g.B >= kPairMfmaMinRhs && g.ops_f32 && g.M % 4 == 0 && g.npairs > 0)
-        return prec == ERT_FP64 ? pair_mfma_t<ERT_FP64>(s, g) : pair_mfma_t<ERT_FP32>(s, g);
-    if (prec == ERT_FP64) return g.ops_f32 ? pair_stream_t<double, float>(s, g) : pair_stream_t<double, double>(s, g);
-    return pair_stream_t<float, float>(s, g);
+    const bool f64 = prec == ERT_FP64;
+    if (f64 && g.ops_fmt == kOpsHi) {
+        record_error("pair_stream: FP64 products do not read the rounded plane alone");
+        return ERT_EINVAL;
+    }
+    if (g.B >= kPairMfmaMinRhs && g.ops_fmt != kOpsNative && g.M % 4 == 0 && g.npairs > 0) {
+        switch (g.ops_fmt) {
+        case kOpsSplit: return f64 ? pair_mfma_t<ERT_FP64, OpsSplit>(s, g) : pair_mfma_t<ERT_FP32, OpsSplit>(s, g);
+        case kOpsHi: return pair_mfma_t<ERT_FP32, OpsHi>(s, g);
+        default: return f64 ? pair_mfma_t<ERT_FP64, float>(s, g) : pair_mfma_t<ERT_FP32, float>(s, g);
+        }
+    }
+    switch (g.ops_fmt) {
+    case kOpsSplit: return f64 ? pair_stream_t<double, OpsSplit>(s, g) : pair_stream_t<float, OpsSplit>(s, g);
+    case kOpsHi: return pair_stream_t<float, OpsHi>(s, g);
+    case kOpsF32: return f64 ? pair_stream_t<double, float>(s, g) : pair_stream_t<float, float>(s, g);
+    default: return f64 ? pair_stream_t<double, double>(s, g) : pair_stream_t<float, float>(s, g);
+    }
 }
 
 }  // namespace ertvie

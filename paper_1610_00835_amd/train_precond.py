@@ -6,6 +6,8 @@ operator with the network as right preconditioner.
 
     python -m paper_1610_00835_amd.train_precond --n 64 --media 24 --steps 1500 \
         --out paper_1610_00835_amd/weights/precond_c5_64.npz
+    python -m paper_1610_00835_amd.train_precond --n 64 --media 24 --steps 1500 --fft \
+        --inner-tol 1e-3 --out paper_1610_00835_amd/weights/precond_c5_64_fft.npz
 
 Training pairs come from the method's own solves (learn.collect_pairs).  The output
 file holds the FP32 parameters, the widths, the grid, the media seeds, the loss
@@ -32,10 +34,13 @@ def plan_for(case, args, prec="fp64"):
 
 def compare(net, case, args):
     """Plain FP64 GMRES vs the FP64-refined solve with FP32 inner GMRES on the lower-order
-    operator, with and without the network as right preconditioner."""
+    operator, with and without the network as right preconditioner (with --fft, all inner
+    solves use the FFT-based preconditioner and the network acts on its output)."""
     import torch
     fd = torch.as_tensor(np.ascontiguousarray(case["f"])).cuda()
     out = {}
+    pre = dict(tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol, allow_noconv=True,
+               precond_fft=args.fft)
     with plan_for(case, args) as plan:
         t0 = time.perf_counter()
         plan.fmm_info("fp64")
@@ -45,13 +50,10 @@ def compare(net, case, args):
         plan.solve(fd, U0, tol=1e-8, max_iter=args.max_iter, allow_noconv=True)   # warm (graphs, tuning)
         plain = plan.solve(fd, U0, tol=1e-8, max_iter=args.max_iter, allow_noconv=True)
         U1 = torch.empty_like(fd)
-        plan.solve(fd, U1, tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol, precond=net,
-                   precond_steps=args.precond_steps, allow_noconv=True)
-        learned = plan.solve(fd, U1, tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol,
-                             precond=net, precond_steps=args.precond_steps, allow_noconv=True)
+        plan.solve(fd, U1, precond=net, precond_steps=args.precond_steps, **pre)
+        learned = plan.solve(fd, U1, precond=net, precond_steps=args.precond_steps, **pre)
         U2 = torch.empty_like(fd)
-        mixed = plan.solve(fd, U2, tol=1e-8, max_iter=args.max_iter, mixed=True, inner_tol=args.inner_tol,
-                           allow_noconv=True)
+        mixed = plan.solve(fd, U2, **pre)
         torch.cuda.synchronize()
         d = float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0))
     out.update(plain=plain, learned=learned, mixed_plain=mixed, rel_diff_solutions=d,
@@ -76,6 +78,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--fft", action="store_true",
+                    help="train the network to act on the FFT-based preconditioner's output")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     import torch
@@ -88,7 +92,7 @@ def main():
         case = inputs.make_case("c5", n=n, seed=s)
         with plan_for(case, args) as plan:
             R, E, info = learn.collect_pairs(plan, case["f"], restart=args.restart, tol=1e-9,
-                                             max_pairs=args.max_pairs, max_iter=args.max_iter)
+                                             max_pairs=args.max_pairs, max_iter=args.max_iter, fft=args.fft)
         pairs.add(R, E, case["sigma_t"], case["sigma_s"])
         log("medium %d: %d iterations, %d pairs, %.1f s" % (s, info["iters"], R.shape[0], time.perf_counter() - t0))
         torch.cuda.empty_cache()
@@ -115,7 +119,7 @@ def main():
         meta = {"n": n, "widths": widths, "train_media": list(range(1000, 1000 + args.media)),
                 "restart": args.restart, "steps": args.steps, "batch": args.batch, "lr": args.lr,
                 "pairs_s": t_pairs, "train_s": t_train, "losses": losses, "held_out": results,
-                "precond_steps": args.precond_steps, "inner_tol": args.inner_tol}
+                "precond_steps": args.precond_steps, "inner_tol": args.inner_tol, "fft": args.fft}
         np.savez(args.out, params=net.get_params(), meta=json.dumps(meta))
         log("wrote", args.out)
     net.close()
