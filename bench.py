@@ -111,10 +111,12 @@ def many_scattering_128(torch, ertvie, inputs, O, stream, args):
     case = inputs.make_case("c5", n=(128, 128, 128), seed=0)
     N = int(np.prod(case["n"]))
     fd = torch.from_numpy(case["f"]).cuda()
-    out = {"workload": "128^3 many-scattering medium, seed 0, leaf 8^3, n = 6 (FP64) / 4 (FP32 inner)"}
+    out = {"workload": "128^3 many-scattering medium, seed 0, leaf 8^3, n = 6 (FP64) / 4 (FP32 inner, near field "
+                       "read as BF16)"}
     torch.cuda.empty_cache()
     t = time.perf_counter()
-    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=6, inner_cheb_n=4) as plan:
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=6, inner_cheb_n=4,
+                               inner_near16=True) as plan:
         out["fmm_fp64"] = plan.fmm_info("fp64")
         log("128^3: FP64 operator built, %.1f s" % (time.perf_counter() - t))
         plan.fmm_info("fp32")
@@ -209,6 +211,39 @@ def paper_experiment_vi(torch, ertvie, inputs, stream):
     return out
 
 
+def fft_pass_bytes(n, m):
+    """Bytes each pass of one FFT-based preconditioner apply reads and writes (3D; FP64
+    vectors, complex FP32 work grids, FP32 folded 1/c)."""
+    n0, n1, n2 = n
+    m0, m1, m2 = m
+    H0, H1, H2 = m0 // 2 + 1, m1 // 2 + 1, m2 // 2 + 1
+    t1 = n2 * n1 * H0 * 8
+    t2 = n2 * m1 * H0 * 8
+    N = n0 * n1 * n2
+    return {"x_forward": N * 8 + t1, "y_forward": t1 + t2, "z_mid": 2 * t2 + H2 * H1 * H0 * 4,
+            "y_inverse": t2 + t1, "x_inverse": t1 + N * 8}
+
+
+def fft_only(torch, ertvie, inputs, stream, steps=50):
+    """The FFT-based preconditioner alone on the many-scattering media at 64^3 and 128^3:
+    device time per apply (events) and the bytes its five passes move."""
+    out = {}
+    for n in (64, 128):
+        case = inputs.make_case("c5", n=(n, n, n), seed=0)
+        with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream) as plan:
+            info = plan.fft_info()
+            x = torch.from_numpy(inputs.random_vector(plan.N, 21)).cuda()
+            z = torch.empty_like(x)
+            ms = timed_fft(torch, plan, x, z, steps)
+        pb = fft_pass_bytes((n, n, n), info["m"])
+        tot = sum(pb.values())
+        out["%d^3" % n] = {"apply_ms": ms, "periods": info["m"], "pass_bytes": pb, "bytes_per_apply": tot,
+                           "gb_per_s": tot / (ms * 1e-3) / 1e9}
+        log("FFT-based preconditioner %d^3: %.4f ms per apply, %.1f MB moved, %.0f GB/s" %
+            (n, ms, tot / 1e6, tot / (ms * 1e-3) / 1e9))
+    return out
+
+
 def timed_fft(torch, plan, x, z, steps):
     """Mean device time of the FFT-based preconditioner on the plan's stream (events)."""
     for _ in range(3):
@@ -267,9 +302,10 @@ def many_scattering_solves(torch, ertvie, inputs, stream, args):
     trained network as right preconditioner (flexible GMRES) when its weights are present."""
     case = inputs.make_case("c5", n=(64, 64, 64), seed=0)
     fd = torch.from_numpy(case["f"]).cuda()
-    out = {"workload": "64^3 many-scattering medium, seed 0, tol 1e-8", "inner_cheb_n": 4}
+    out = {"workload": "64^3 many-scattering medium, seed 0, tol 1e-8", "inner_cheb_n": 4, "inner_near16": 1}
     t = time.perf_counter()
-    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, inner_cheb_n=4) as plan:
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, inner_cheb_n=4,
+                               inner_near16=True) as plan:
         plan.fmm_info("fp64")
         plan.fmm_info("fp32")
         torch.cuda.synchronize()
@@ -332,6 +368,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--c5-128", action="store_true",
                     help="also run the 128^3 many-scattering medium (plan ~1 min, ~250 GB of device memory)")
+    ap.add_argument("--fft-only", action="store_true",
+                    help="time only the FFT-based preconditioner (64^3 and 128^3) and exit")
     ap.add_argument("--paper-exp6", action="store_true",
                     help="also run the paper's preconditioning experiment (2D 512^2, four media)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -349,6 +387,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.fft_only:
+        print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
+        return
     case = inputs.make_case("c2", seed=0)
     N = int(np.prod(case["n"]))
     f = torch.from_numpy(case["f"]).to(dev)
