@@ -33,6 +33,17 @@
  *       op 1: y = A (s .* x) (s = sigma_s)
  *       op 2: y = x - A (s .* x)   (the operator I - K of eq. EQ:ERT Intgrl FMM)
  *
+ *   Matrix, approach (M-ii) (Sec. 3.2 and Remark 3.1, selected by bit 1 of the
+ *   kernel argument): the kernel is split as a(x,y) |x-y|^{1-d} with
+ *   a = E / |S^{d-1}| and only the singular factor is integrated over the
+ *   source cell:  A_jk = E(x_j,x_k) / |S^{d-1}| * I(x_k - x_j)  for every j, k
+ *   (E(x,x) = 1), with I(t) = integral over the cell of side h centred at t of
+ *   |z|^{1-d} dz.  2D: the closed form of Remark 3.1.  3D: by the divergence
+ *   theorem (div(z / |z|^2) = 1 / |z|^2 in 3D) a sum over the six faces of
+ *   (signed face offset) * integral over the face of |z|^-2, each face integral
+ *   done in one variable in closed form (arctangent) and in the other by
+ *   composite Gauss-Legendre.
+ *
  *   Solve (Algorithm 1, step S.2): GMRES for (I - A S) U = A f with x0 = 0,
  *   modified Gram-Schmidt with one re-orthogonalisation, Givens rotations,
  *   stop on the recurrence estimate, then confirm with the true residual.
@@ -53,7 +64,9 @@ typedef struct {
     long n[3];
     double h;
     int kernel;            /* 0: homogeneous exp(-sigma r); 1: midpoint ray rule */
+    int scheme;            /* 0: (M-iii); 1: (M-ii) */
     const double* st;      /* sigma_t, one value per cell */
+    double* itab;          /* (M-ii): I(h o) for o_a = 0..n_a-1 (by symmetry |o_a|), or NULL */
 } og_t;
 
 static long og_count(const og_t* g)
@@ -162,9 +175,9 @@ static double og_kernel_points(const og_t* g, const double x[3], const double y[
     return exp(-tau) / (surface_area(g->dim) * rp);
 }
 
-/* G between collocation points j != k.  The ray is always marched from the
- * lower linear index so that G(x_j,x_k) == G(x_k,x_j) bit for bit. */
-static double og_kernel_cells(const og_t* g, long j, long k)
+/* E = exp(-tau) between collocation points j != k.  The ray is always marched
+ * from the lower linear index so that E(x_j,x_k) == E(x_k,x_j) bit for bit. */
+static double og_atten_cells(const og_t* g, long j, long k)
 {
     long ij[3], ik[3];
     og_index(g, j, ij);
@@ -190,8 +203,20 @@ static double og_kernel_cells(const og_t* g, long j, long k)
         }
         tau = r / (double)m * s;
     }
+    return exp(-tau);
+}
+
+/* G between collocation points j != k. */
+static double og_kernel_cells(const og_t* g, long j, long k)
+{
+    long ij[3], ik[3];
+    og_index(g, j, ij);
+    og_index(g, k, ik);
+    long K = 0;
+    for (int a = 0; a < g->dim; ++a) K += (ij[a] - ik[a]) * (ij[a] - ik[a]);
+    double r = g->h * sqrt((double)K);
     double rp = (g->dim == 2) ? r : r * r;
-    return exp(-tau) / (surface_area(g->dim) * rp);
+    return og_atten_cells(g, j, k) / (surface_area(g->dim) * rp);
 }
 
 /* ---- Gauss-Legendre nodes on [-1,1] by Newton's method -------------------- */
@@ -224,6 +249,111 @@ static void gauss_legendre(int n, double* x, double* w)
         x[i] = z;
         w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
+}
+
+/* ---- (M-ii): integral of |z|^{1-d} over a cell ---------------------------- */
+
+/* Remark 3.1's F(r, s), with 0 log 0 = 0. */
+static double og_F(double r, double s)
+{
+    if (r == 0.0 || s == 0.0) return 0.0;
+    double ar = fabs(r), as = fabs(s), q = sqrt(r * r + s * s);
+    double v = ar * log(as + q) + as * log(ar + q) - ar * log(ar) - as * log(as);
+    return ((r > 0) == (s > 0)) ? v : -v;
+}
+
+#define OR_FACE_PANELS 4
+#define OR_FACE_NODES 20
+
+/* integral over u in [u0,u1], v in [v0,v1] of 1 / (c^2 + u^2 + v^2), c != 0:
+ * the v integral in closed form, the u integral by composite Gauss-Legendre
+ * with panels split at u = 0 (where the integrand peaks). */
+static double og_face(double c, double u0, double u1, double v0, double v1, const double* gx, const double* gw)
+{
+    double cuts[3] = {u0, u1, u1};
+    int ncut = 2;
+    if (u0 < 0.0 && u1 > 0.0) { cuts[1] = 0.0; cuts[2] = u1; ncut = 3; }
+    double acc = 0.0;
+    for (int piece = 0; piece + 1 < ncut; ++piece) {
+        double a = cuts[piece], b = cuts[piece + 1];
+        for (int pnl = 0; pnl < OR_FACE_PANELS; ++pnl) {
+            double pa = a + (b - a) * pnl / OR_FACE_PANELS, pb = a + (b - a) * (pnl + 1) / OR_FACE_PANELS;
+            for (int q = 0; q < OR_FACE_NODES; ++q) {
+                double u = 0.5 * (pb - pa) * gx[q] + 0.5 * (pb + pa);
+                double qq = sqrt(c * c + u * u);
+                acc += 0.5 * (pb - pa) * gw[q] * (atan(v1 / qq) - atan(v0 / qq)) / qq;
+            }
+        }
+    }
+    return acc;
+}
+
+/* I(t) = integral over the cell of side h centred at t of |z|^{1-d} dz. */
+static double og_cell_integral(int dim, double h, const double t[3])
+{
+    double gx[OR_FACE_NODES], gw[OR_FACE_NODES];
+    gauss_legendre(OR_FACE_NODES, gx, gw);
+    double hh = 0.5 * h;
+    if (dim == 2) {
+        double acc = 0.0;
+        for (int i = -1; i <= 1; i += 2)
+            for (int j = -1; j <= 1; j += 2) acc += (double)(i * j) * og_F(t[0] + i * hh, t[1] + j * hh);
+        return acc;
+    }
+    /* sum over faces of (z . n) * integral_face |z|^-2; z . n is the face plane's offset */
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            double off = t[a] + sgn * hh;
+            if (off == 0.0) continue;
+            acc += sgn * off * og_face(off, t[b] - hh, t[b] + hh, t[c] - hh, t[c] + hh, gx, gw);
+        }
+    }
+    return acc;
+}
+
+/* Matrix entry A_jk of the selected approach (j != k). */
+static double og_entry(const og_t* g, long j, long k)
+{
+    if (g->scheme == 0) {
+        double hd = (g->dim == 2) ? g->h * g->h : g->h * g->h * g->h;
+        return hd * og_kernel_cells(g, j, k);
+    }
+    long ij[3], ik[3];
+    og_index(g, j, ij);
+    og_index(g, k, ik);
+    long o[3] = {0, 0, 0};
+    for (int a = 0; a < g->dim; ++a) o[a] = labs(ik[a] - ij[a]);
+    double I;
+    if (g->itab) {
+        I = g->itab[o[0] + g->n[0] * (o[1] + g->n[1] * o[2])];
+    } else {
+        double t[3] = {g->h * (double)o[0], g->h * (double)o[1], g->h * (double)o[2]};
+        I = og_cell_integral(g->dim, g->h, t);
+    }
+    return og_atten_cells(g, j, k) * I / surface_area(g->dim);
+}
+
+/* (M-ii): tabulate I over the grid's offsets (I is even in every component). */
+static void og_prepare(og_t* g)
+{
+    g->itab = NULL;
+    if (g->scheme != 1) return;
+    long M = g->n[0] * g->n[1] * g->n[2];
+    g->itab = (double*)malloc(sizeof(double) * (size_t)M);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long i = 0; i < M; ++i) {
+        long o0 = i % g->n[0], o1 = (i / g->n[0]) % g->n[1], o2 = i / (g->n[0] * g->n[1]);
+        double t[3] = {g->h * (double)o0, g->h * (double)o1, g->h * (double)o2};
+        g->itab[i] = og_cell_integral(g->dim, g->h, t);
+    }
+}
+
+static void og_release(og_t* g)
+{
+    free(g->itab);
+    g->itab = NULL;
 }
 
 #define OR_NANG 16   /* Gauss-Legendre nodes per angular patch axis */
@@ -273,6 +403,10 @@ static double og_radial(const og_t* g, const double x[3], const double v[3], dou
  * d-linear interpolant, so every integrand is smooth on its patch. */
 static double og_self(const og_t* g, long j)
 {
+    if (g->scheme == 1) {
+        double t0[3] = {0.0, 0.0, 0.0};
+        return og_cell_integral(g->dim, g->h, t0) / surface_area(g->dim);
+    }
     double ax[OR_NANG], aw[OR_NANG], rx[OR_NRAD], rw[OR_NRAD];
     gauss_legendre(OR_NANG, ax, aw);
     gauss_legendre(OR_NRAD, rx, rw);
@@ -329,9 +463,23 @@ static og_t og_make(int dim, const long* n, double h, int kernel, const double* 
     g.n[1] = dim > 1 ? n[1] : 1;
     g.n[2] = dim > 2 ? n[2] : 1;
     g.h = h;
-    g.kernel = kernel;
+    g.kernel = kernel & 1;
+    g.scheme = (kernel >> 1) & 1;
     g.st = st;
+    g.itab = NULL;
     return g;
+}
+
+double oracle_cell_integral(int dim, double h, const double* t)
+{
+    double tt[3] = {t[0], t[1], dim > 2 ? t[2] : 0.0};
+    return og_cell_integral(dim, h, tt);
+}
+
+double oracle_entry(int dim, const long* n, double h, int kernel, const double* st, long j, long k)
+{
+    og_t g = og_make(dim, n, h, kernel, st);
+    return j == k ? og_self(&g, j) : og_entry(&g, j, k);
 }
 
 double oracle_sigma_interp(int dim, const long* n, double h, const double* st, const double* p)
@@ -382,7 +530,7 @@ void oracle_diag(int dim, const long* n, double h, int kernel, const double* st,
 {
     og_t g = og_make(dim, n, h, kernel, st);
     long N = og_count(&g);
-    if (kernel == 0) {
+    if (g.kernel == 0 || g.scheme == 1) {
         double v = og_self(&g, 0);
         for (long j = 0; j < N; ++j) d[j] = v;
         return;
@@ -397,13 +545,14 @@ void oracle_matrix(int dim, const long* n, double h, int kernel, const double* s
                    const double* diag, double* A, int nthreads)
 {
     og_t g = og_make(dim, n, h, kernel, st);
+    og_prepare(&g);
     long N = og_count(&g);
-    double hd = (dim == 2) ? h * h : h * h * h;
     (void)nthreads;
 #pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
     for (long j = 0; j < N; ++j)
         for (long k = 0; k < N; ++k)
-            A[j * N + k] = (j == k) ? diag[j] : hd * og_kernel_cells(&g, j, k);
+            A[j * N + k] = (j == k) ? diag[j] : og_entry(&g, j, k);
+    og_release(&g);
 }
 
 /* ---- the apply ------------------------------------------------------------ */
@@ -414,11 +563,10 @@ void oracle_matrix(int dim, const long* n, double h, int kernel, const double* s
 static void og_row(const og_t* g, const double* ss, int op, const double* x, long N, int nrhs,
                    const double* diag, long j, double* out /* nrhs, stride ostride */, long ostride)
 {
-    double hd = (g->dim == 2) ? g->h * g->h : g->h * g->h * g->h;
     double* sum = (double*)calloc((size_t)nrhs * 2, sizeof(double));
     double* comp = sum + nrhs;
     for (long k = 0; k < N; ++k) {
-        double a = (k == j) ? diag[j] : hd * og_kernel_cells(g, j, k);
+        double a = (k == j) ? diag[j] : og_entry(g, j, k);
         double sk = (op == 0) ? 1.0 : ss[k];
         for (int b = 0; b < nrhs; ++b) {
             double term = a * (sk * x[(long)b * N + k]);
@@ -440,10 +588,12 @@ void oracle_apply(int dim, const long* n, double h, int kernel, const double* st
                   const double* x, double* y, int nrhs, int nthreads)
 {
     og_t g = og_make(dim, n, h, kernel, st);
+    og_prepare(&g);
     long N = og_count(&g);
     (void)nthreads;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
     for (long j = 0; j < N; ++j) og_row(&g, ss, op, x, N, nrhs, diag, j, y + j, N);
+    og_release(&g);
 }
 
 /* rows[i] of the apply, i < nrows; y_rows is nrows x nrhs column-major.
@@ -454,6 +604,7 @@ void oracle_apply_rows(int dim, const long* n, double h, int kernel, const doubl
                        double* y_rows, int nrhs, int nthreads)
 {
     og_t g = og_make(dim, n, h, kernel, st);
+    og_prepare(&g);
     long N = og_count(&g);
     (void)nthreads;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
@@ -471,6 +622,7 @@ void oracle_apply_rows(int dim, const long* n, double h, int kernel, const doubl
         og_row(&g, ss, op, x, N, nrhs, dptr, j, y_rows + i, nrows);
         free(tmp);
     }
+    og_release(&g);
 }
 
 /* ---- GMRES (Algorithm 1, step S.2) --------------------------------------- */

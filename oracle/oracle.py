@@ -6,8 +6,9 @@ CPU-baseline leg of bench.py.  The product library never imports it.
 Every function takes the problem as (dim, n, h, kernel, sigma_t[, sigma_s])
 with NumPy float64 arrays laid out x-fastest (cell index j = i0 + n0 (i1 + n1 i2)).
 kernel 0 = homogeneous exp(-sigma_t r) (sigma_t[0] is used), 1 = midpoint ray
-rule through the d-linear interpolant of sigma_t.  Operators: 0 -> A x,
-1 -> A (sigma_s x), 2 -> x - A (sigma_s x).
+rule through the d-linear interpolant of sigma_t; adding 2 selects approach
+(M-ii) of Sec. 3.2 (Remark 3.1) instead of (M-iii) (Problem(scheme=1) does this).
+Operators: 0 -> A x, 1 -> A (sigma_s x), 2 -> x - A (sigma_s x).
 """
 import ctypes
 import os
@@ -76,6 +77,11 @@ def lib():
         L.oracle_apply_rows.argtypes = [ctypes.c_int, _lp, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp,
                                         ctypes.c_int, _dp, _lp, ctypes.c_long, _dp, ctypes.c_int,
                                         ctypes.c_int]
+        L.oracle_cell_integral.restype = ctypes.c_double
+        L.oracle_cell_integral.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+        L.oracle_entry.restype = ctypes.c_double
+        L.oracle_entry.argtypes = [ctypes.c_int, _lp, ctypes.c_double, ctypes.c_int, _dp, ctypes.c_long,
+                                   ctypes.c_long]
         L.oracle_gmres.restype = ctypes.c_int
         L.oracle_gmres.argtypes = [ctypes.c_int, _lp, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp,
                                    _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -106,12 +112,13 @@ def _n3(n):
 class Problem:
     """A grid with its media.  sigma_t/sigma_s are flat float64 arrays of length N."""
 
-    def __init__(self, dim, n, h, kernel, sigma_t, sigma_s=None):
+    def __init__(self, dim, n, h, kernel, sigma_t, sigma_s=None, scheme=0):
         self.dim = int(dim)
         self.n = tuple(int(v) for v in n)[:dim]
         self.N = int(np.prod(self.n))
         self.h = float(h)
-        self.kernel = int(kernel)
+        self.scheme = int(scheme)
+        self.kernel = int(kernel) + 2 * self.scheme
         self.st = _f64(sigma_t).reshape(-1)
         assert self.st.size == self.N
         self.ss = _f64(sigma_s).reshape(-1) if sigma_s is not None else np.zeros(self.N)
@@ -133,6 +140,10 @@ class Problem:
 
     def kernel_cells(self, j, k):
         return lib().oracle_kernel_cells(self.dim, self._n, self.h, self.kernel, _p(self.st), int(j), int(k))
+
+    def entry(self, j, k):
+        """Matrix entry A_jk of the selected approach."""
+        return lib().oracle_entry(self.dim, self._n, self.h, self.kernel, _p(self.st), int(j), int(k))
 
     def self_cell(self, j):
         return lib().oracle_self_cell(self.dim, self._n, self.h, self.kernel, _p(self.st), int(j))
@@ -190,6 +201,13 @@ class Problem:
         out = {k: getattr(info, k) for k, _ in GmresInfo._fields_}
         out["status"] = st
         return U, phi, out
+
+
+def cell_integral(dim, h, t):
+    """I(t): integral of |z|^{1-d} over the cell of side h centred at t (Remark 3.1)."""
+    tt = np.zeros(3)
+    tt[:len(t)] = np.asarray(t, dtype=np.float64)
+    return lib().oracle_cell_integral(int(dim), float(h), _p(tt))
 
 
 def steps_real(r, h):
