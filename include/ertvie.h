@@ -134,7 +134,8 @@ typedef struct {
                          each correction with `precond`) by the FFT-based preconditioner of the
                          mean medium (ert_vie_fft_precond), in flexible GMRES; with `precond`
                          the network acts on its output, z_j = net(M v_j), and the fallback
-                         of a rejected step keeps M.  0: none.  Not combined with `block` */
+                         of a rejected step keeps M; with `block`, block GMRES on (I - K) M
+                         with U = M Y.  0: none */
     ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
                          becomes a refinement loop.  Each step solves (I - K) d = r by flexible
                          GMRES with z_j = net(v_j) (inner operator: FP32 with `mixed`, else the

@@ -139,7 +139,7 @@ ert_status plan_apply(ert_plan_impl* p, int op, int method, int prec, const doub
 
 ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Phi, double* X, int nb, double rtol,
                        int maxit, int restart, bool check_true, int* iters_out, int* cycles_out, int* matvecs_out,
-                       double* est_out, double* true_out, bool* conv_out);
+                       double* est_out, double* true_out, bool* conv_out, bool fft);
 
 namespace {
 
@@ -605,10 +605,6 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
     if (!(so.tol > 0.0) || so.max_iter < 1 || so.restart < 0 || !(so.inner_tol > 0.0) || so.inner_tol >= 1.0)
         return ERT_EINVAL;
     if (so.precond_fft != 0 && so.precond_fft != 1) return ERT_EINVAL;
-    if (so.precond_fft && so.block && nrhs > 1) {
-        record_error("ert_vie_solve: the FFT-based preconditioner is not combined with block GMRES");
-        return ERT_EUNSUPPORTED;
-    }
     if (so.precond_steps < 0 || so.history_max < 0 || (so.history_max > 0 && !so.history)) return ERT_EINVAL;
     NetImpl* net = so.precond ? net_impl(so.precond) : nullptr;
     if (net) {
@@ -661,7 +657,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
             bool conv = false;
             if (!so.mixed) {
                 st = block_gmres(p, method, prec_outer, Phi, U, nrhs, so.tol, so.max_iter, so.restart, true, &it, &cy,
-                                 &mv, &est, &tr, &conv);
+                                 &mv, &est, &tr, &conv, so.precond_fft != 0);
                 if (st != ERT_OK) break;
                 inf.iters = it;
                 inf.restarts = cy > 0 ? cy - 1 : 0;
@@ -692,7 +688,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
                     if (worst <= so.tol) { inf.converged = 1; break; }
                     if (used >= so.max_iter) break;
                     st = block_gmres(p, method, prec_inner, Rb, Db, nrhs, so.inner_tol, so.max_iter - used, so.restart,
-                                     false, &it, &cy, &mv, &est, &tr, &conv);
+                                     false, &it, &cy, &mv, &est, &tr, &conv, so.precond_fft != 0);
                     if (st != ERT_OK) break;
                     used += it;
                     inf.iters += it;
