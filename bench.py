@@ -387,14 +387,6 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    if args.fft_only:
-        print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
-        return
-    case = inputs.make_case("c2", seed=0)
-    N = int(np.prod(case["n"]))
-    f = torch.from_numpy(case["f"]).to(dev)
-    y = torch.empty_like(f)
-
     if args.calibrate_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -402,6 +394,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.fft_only:
+        print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
+        return
+    case = inputs.make_case("c2", seed=0)
+    N = int(np.prod(case["n"]))
+    f = torch.from_numpy(case["f"]).to(dev)
+    y = torch.empty_like(f)
 
     t = time.perf_counter()
     plan = ertvie.plan_from_case(case, method="fmm", prec=args.prec, stream=stream, svd_tol=SVD_TOL)
