@@ -47,6 +47,18 @@ def test_periodic_operator_is_solver_operator_for_constant_medium(oracle_mod, di
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("dim,n,kernel", [(2, (7, 6), 0), (3, (5, 4, 3), 1)])
+def test_periodic_operator_is_solver_operator_mii(oracle_mod, dim, n, kernel):
+    """The same identity with the (M-ii) entries (Sec. 3.2, Remark 3.1)."""
+    h = 1.0 / max(n)
+    st, ss = _const(dim, n, 3.5, 2.75)
+    P = oracle_mod.Problem(dim, n, h, kernel, st, ss, scheme=1)
+    x = np.random.default_rng(4).uniform(-1, 1, P.N)
+    ref = P.apply(x, op=2)
+    got = F.periodic_operator(x, dim, n, h, st, ss, scheme=1)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def _circulant(w, m, sbar_s):
     """Dense matrix of the periodic operator I - sbar_s (w * .) by brute force."""
     idx = np.stack(np.meshgrid(*[np.arange(v) for v in m[::-1]], indexing="ij"), -1).reshape(-1, len(m))
