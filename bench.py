@@ -244,6 +244,49 @@ def fft_only(torch, ertvie, inputs, stream, steps=50):
     return out
 
 
+def paper_experiment_iii(torch, ertvie, inputs, stream, kmax=12, mus_list=(2.0, 5.0, 10.0)):
+    """The paper's accuracy experiment (Sec. 5.2, Experiments III/IV): 2D unit square with
+    absorption 0.2 and scattering 2, 5, 10 (homogeneous), grids h = 1/(24 (2k - 1)),
+    k = 1..kmax, the k = kmax solution as reference, errors on the k = 1 collocation points
+    (shared by every grid: the refinement factors are odd), for approaches (M-ii) and (M-iii).
+    The paper's sources exist only as figures; a smooth ring (radius 0.25, width 0.05, centred)
+    stands in.  FMM of order 8 (the paper used 6) so that the interpolation error stays below
+    the discretisation error of the finest grids; GMRES to 1e-12."""
+    out = {"workload": "2D, mu_a = 0.2, h = 1/(24(2k-1)), k = 1..%d, ring source, FMM n = 8, FP64, tol 1e-12" % kmax,
+           "runs": {}}
+    for mus in mus_list:
+        for scheme, name in ((1, "M-ii"), (0, "M-iii")):
+            sols = {}
+            t0 = time.perf_counter()
+            for k in range(1, kmax + 1):
+                nn = 24 * (2 * k - 1)
+                n = (nn, nn)
+                N = nn * nn
+                h = 1.0 / nn
+                x = inputs.centres(n, h)
+                rr = np.sqrt(np.sum((x - 0.5) ** 2, axis=1))
+                f = torch.from_numpy(np.exp(-(rr - 0.25) ** 2 / (2 * 0.05 ** 2))).cuda()
+                case = {"dim": 2, "n": n, "h": h, "kernel": ertvie.K_HOMOGENEOUS,
+                        "sigma_t": np.full(N, mus + 0.2), "sigma_s": np.full(N, mus)}
+                with ertvie.plan_from_case(case, method="fmm" if nn > 72 else "direct", prec="fp64", stream=stream,
+                                           cheb_n=8, scheme=scheme) as plan:
+                    U = torch.empty_like(f)
+                    info = plan.solve(f, U, tol=1e-12, max_iter=400)
+                idx = np.arange(24)
+                sel = (idx * (2 * k - 1) + k - 1)
+                sols[k] = U.cpu().numpy().reshape(nn, nn)[np.ix_(sel, sel)].reshape(-1)
+                if info["converged"] != 1:
+                    log("experiment III: %s mu_s %g k %d did not converge" % (name, mus, k))
+            ref = sols[kmax]
+            errs = [float(np.linalg.norm(sols[k] - ref) / np.linalg.norm(ref)) for k in range(1, kmax)]
+            hs = [1.0 / (24 * (2 * k - 1)) for k in range(1, kmax)]
+            orders = [float(np.log(errs[i] / errs[i + 1]) / np.log(hs[i] / hs[i + 1])) for i in range(len(errs) - 1)]
+            out["runs"]["%s_mu_s_%g" % (name, mus)] = {"h": hs, "rel_l2_err": errs, "observed_order": orders,
+                                                       "seconds": time.perf_counter() - t0}
+            log("experiment III %s mu_s %g: errors %s" % (name, mus, " ".join("%.2e" % e for e in errs)))
+    return out
+
+
 def timed_fft(torch, plan, x, z, steps):
     """Mean device time of the FFT-based preconditioner on the plan's stream (events)."""
     for _ in range(3):
@@ -370,6 +413,8 @@ def main():
                     help="also run the 128^3 many-scattering medium (plan ~1 min, ~250 GB of device memory)")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT-based preconditioner (64^3 and 128^3) and exit")
+    ap.add_argument("--paper-exp3", action="store_true",
+                    help="also run the paper's accuracy experiment ((M-ii) vs (M-iii), 2D, 12 grids, three media)")
     ap.add_argument("--paper-exp6", action="store_true",
                     help="also run the paper's preconditioning experiment (2D 512^2, four media)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -470,6 +515,9 @@ def main():
 
     if args.paper_exp6:
         extra["paper_experiment_vi"] = paper_experiment_vi(torch, ertvie, inputs, stream)
+
+    if args.paper_exp3:
+        extra["paper_experiment_iii"] = paper_experiment_iii(torch, ertvie, inputs, stream)
 
     if args.c5_128:
         extra["many_scattering_128cubed"] = many_scattering_128(torch, ertvie, inputs, O, stream, args)

@@ -97,7 +97,14 @@ typedef struct {
     int cheb_n;       /* FMM: Chebyshev nodes per axis (Sec. 3.3, n); 0 -> 8; 2..8 */
     int leaf;         /* FMM: cells per leaf-box side; 0 -> 8; 1..8 */
     int nrhs_max;     /* largest nrhs later passed to apply/solve; 0 -> 1 */
-    int flags;        /* reserved, must be 0 */
+    int scheme;       /* discretisation of the integral operator (Sec. 3.2):
+                         0 (M-iii): A_jk = h^d G(x_j, x_k) for j != k, A_jj the singular
+                           self-cell integral of E / (|S^{d-1}| r^{d-1}) (polar quadrature);
+                         1 (M-ii), with Remark 3.1's smooth kernel: A_jk = E(x_j, x_k)
+                           / |S^{d-1}| * integral over the cell of side h centred at x_k - x_j
+                           of |z|^{1-d} dz, for every j, k (E(x, x) = 1).  The FMM evaluates
+                           the same kernel at its interpolation nodes.  Homogeneous FMM needs
+                           leaf^dim to be a multiple of 32 */
     double svd_tol;   /* FMM, homogeneous media: relative singular-value cutoff of the
                          compressed far-field translations (shared orthonormal basis per
                          level from the SVD of all translation matrices); 0 -> 1e-6
@@ -173,7 +180,7 @@ typedef struct {
  *   hip_stream: hipStream_t for all work of the plan (NULL = default stream).
  *   out      : receives the plan handle.
  * Returns ERT_EINVAL for dim not 2/3, n < 1, N < 2, h <= 0, bad coefficients,
- * non-constant sigma_t with ERT_K_HOMOGENEOUS, cheb_n outside 2..8 or flags != 0. */
+ * non-constant sigma_t with ERT_K_HOMOGENEOUS, cheb_n outside 2..8 or scheme not 0/1. */
 ERT_API ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const double* sigma_s,
                         void* hip_stream, ert_vie_plan_t* out);
 

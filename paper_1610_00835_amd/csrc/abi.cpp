@@ -449,6 +449,7 @@ void ert_vie_destroy(ert_vie_plan_t p)
     (void)hipFree(p->d_st32);
     (void)hipFree(p->d_ss);
     (void)hipFree(p->d_diag);
+    (void)hipFree(p->d_itab);
     (void)hipFree(p->d_ws);
     (void)hipFree(p->d_red);
     delete p;
@@ -461,7 +462,7 @@ ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const d
     if (!opts || !sigma_t || !sigma_s || !out) return ERT_EINVAL;
     const ert_vie_opts& o = *opts;
     if (o.dim != 2 && o.dim != 3) return ERT_EINVAL;
-    if (!finite_pos(o.h) || o.flags != 0) return ERT_EINVAL;
+    if (!finite_pos(o.h) || (o.scheme != 0 && o.scheme != 1)) return ERT_EINVAL;
     if (o.kernel != ERT_K_HOMOGENEOUS && o.kernel != ERT_K_RAY_MIDPOINT) return ERT_EINVAL;
     if (o.method != ERT_DIRECT && o.method != ERT_FMM) return ERT_EINVAL;
     if (o.prec != ERT_FP64 && o.prec != ERT_FP32 && o.prec != ERT_BF16X3) return ERT_EINVAL;

@@ -111,6 +111,92 @@ __device__ __forceinline__ T tau_march(const T* __restrict__ st, const Geo& g, T
     return r * inv_m * s;
 }
 
+// ------------------------------------------------- (M-ii) cell integrals ---
+
+// Approach (M-ii) (Sec. 3.2, Remark 3.1) replaces h^d |x - y|^{1-d} by the
+// integral of |z|^{1-d} over the source cell, centred at t = y - x.  For a
+// cell of side h this is h * cell_int(t / h), cell_int being the integral over
+// the unit cell:
+//   2D: the closed form of Remark 3.1, sum over corners of +-F(r, s);
+//   3D, |t|^2 >= 144: the Taylor expansion of the cell average of |z|^-2,
+//       1/r^2 + 1/(12 r^4) + P4/(240 r^10) + P6/(20160 r^14) (relative error
+//       below 2e-11, falling as r^-8);
+//   3D, closer: the divergence theorem (div(z / |z|^2) = 1/|z|^2) turns the
+//       cell integral into six face integrals of |z|^-2 times the face offset;
+//       each is done in closed form along one face axis (arctangent) and by
+//       12-point Gauss-Legendre panels growing by 3x away from the peak at the
+//       foot of the perpendicular along the other.
+__device__ __forceinline__ double mii_F(double r, double s)
+{
+    if (r == 0.0 || s == 0.0) return 0.0;
+    const double ar = fabs(r), as = fabs(s), q = sqrt(r * r + s * s);
+    const double v = ar * log(as + q) + as * log(ar + q) - ar * log(ar) - as * log(as);
+    return ((r > 0.0) == (s > 0.0)) ? v : -v;
+}
+
+__device__ __forceinline__ double mii_face_piece(double c, double a, double b, double v0, double v1)
+{
+    // integral over u in [a, b] (0 <= a < b) of (atan(v1/q) - atan(v0/q)) / q, q = sqrt(c^2 + u^2)
+    const double gx[6] = {0.12523340851146891, 0.36783149899818018, 0.58731795428661748, 0.76990267419430469,
+                          0.9041172563704748, 0.98156063424671924};
+    const double gw[6] = {0.24914704581340269, 0.23349253653835464, 0.20316742672306565, 0.16007832854334611,
+                          0.10693932599531888, 0.047175336386512022};
+    const double ac = fabs(c);
+    double acc = 0.0;
+    double lo = a;
+    for (int pnl = 0; pnl < 40 && lo < b; ++pnl) {
+        double hi = (lo < ac) ? ac : 3.0 * lo;
+        if (hi > b) hi = b;
+        const double m = 0.5 * (hi + lo), d = 0.5 * (hi - lo);
+        for (int q = 0; q < 6; ++q)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double u = m + sgn * d * gx[q];
+                const double qq = sqrt(c * c + u * u);
+                acc += d * gw[q] * (atan(v1 / qq) - atan(v0 / qq)) / qq;
+            }
+        lo = hi;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double mii_face(double c, double u0, double u1, double v0, double v1)
+{
+    // the integrand is even in u: fold [u0, u1] onto u >= 0
+    if (u0 >= 0.0) return mii_face_piece(c, u0, u1, v0, v1);
+    if (u1 <= 0.0) return mii_face_piece(c, -u1, -u0, v0, v1);
+    return mii_face_piece(c, 0.0, -u0, v0, v1) + mii_face_piece(c, 0.0, u1, v0, v1);
+}
+
+// far2: squared distance (in cells) from which the 3D expansion is used; the
+// far-field interpolation nodes use 64 (relative error below 3e-10 there).
+__device__ __forceinline__ double cell_int(int dim, double t0, double t1, double t2, double far2 = 144.0)
+{
+    if (dim == 2) {
+        return mii_F(t0 + 0.5, t1 + 0.5) - mii_F(t0 + 0.5, t1 - 0.5) - mii_F(t0 - 0.5, t1 + 0.5) +
+               mii_F(t0 - 0.5, t1 - 0.5);
+    }
+    const double x2 = t0 * t0, y2 = t1 * t1, z2 = t2 * t2, r2 = x2 + y2 + z2;
+    if (r2 >= far2) {
+        const double i2 = 1.0 / r2, i4 = i2 * i2, i8 = i4 * i4;
+        const double p4 = -9.0 * (x2 * x2 + y2 * y2 + z2 * z2) + 46.0 * (x2 * y2 + x2 * z2 + y2 * z2);
+        const double p6 = x2 * x2 * x2 + y2 * y2 * y2 + z2 * z2 * z2 -
+                          317.0 * (x2 * x2 * (y2 + z2) + y2 * y2 * (x2 + z2) + z2 * z2 * (x2 + y2)) +
+                          14406.0 * x2 * y2 * z2;
+        return i2 + i4 / 12.0 + p4 * i8 * i2 / 240.0 + p6 * i8 * i4 * i2 / 20160.0;
+    }
+    const double t[3] = {t0, t1, t2};
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const double off = t[a] + 0.5 * sgn;
+            if (off == 0.0) continue;
+            acc += sgn * off * mii_face(off, t[b] - 0.5, t[b] + 0.5, t[c] - 0.5, t[c] + 0.5);
+        }
+    }
+    return acc;
+}
+
 // --------------------------------------------------------------- the plan ---
 
 struct FmmData;   // fmm.hip
@@ -173,6 +259,7 @@ struct ert_plan_impl {
     float* d_st32 = nullptr;     // sigma_t FP32
     double* d_ss = nullptr;      // sigma_s FP64
     double* d_diag = nullptr;    // A_jj FP64
+    double* d_itab = nullptr;    // (M-ii): cell_int at integer offsets |o| (n0 x n1 x n2, FP64), else null
     // GMRES workspace (grown on demand)
     double* d_ws = nullptr;
     size_t ws_elems = 0;

@@ -113,13 +113,30 @@ __global__ void k_fill(double* __restrict__ d, long N, const double* __restrict_
     if (i < N) d[i] = src[0];
 }
 
+// (M-ii): cell integrals at the grid's integer offsets, itab[o0 + n0 (o1 + n1 o2)]
+// = cell_int(o) for 0 <= o_a < n_a (the integral is even in every component).
+__global__ void k_itab(int dim, int n0, int n1, int n2, double* __restrict__ itab)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= (long)n0 * n1 * n2) return;
+    const int o0 = (int)(i % n0), o1 = (int)((i / n0) % n1), o2 = (int)(i / ((long)n0 * n1));
+    itab[i] = cell_int(dim, o0, o1, dim > 2 ? o2 : 0);
+}
+
+// (M-ii) diagonal: h cell_int(0) / |S^{d-1}| for every cell.
+__global__ void k_fill_scaled(double* __restrict__ d, long N, const double* __restrict__ src, double scale)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < N) d[i] = src[0] * scale;
+}
+
 // ------------------------------------------------------- dense apply -----
 
 template <typename T, bool RAY, int RB>
 __global__ __launch_bounds__(kTile) void k_direct(Geo g, const T* __restrict__ st, T sigma, T hd_over_area,
                                                   const double* __restrict__ x, const double* __restrict__ ss,
                                                   int weighted, long N, const double* __restrict__ diag,
-                                                  int op, double* __restrict__ y)
+                                                  const double* __restrict__ itab, int op, double* __restrict__ y)
 {
     __shared__ T sw[kTile * RB];
     const long j = blockIdx.x * (long)kTile + threadIdx.x;
@@ -161,8 +178,15 @@ __global__ __launch_bounds__(kTile) void k_direct(Geo g, const T* __restrict__ s
                     } else {
                         tau = sigma * r;
                     }
-                    const T rp = (g.dim == 2) ? T(sqrt(T(K))) : T(K);
-                    const T gk = exp(-tau) / rp;
+                    T gk;
+                    if (itab) {
+                        // (M-ii): the cell integral replaces |offset|^{1-d}
+                        const int a0 = d0 < 0 ? -d0 : d0, a1 = d1 < 0 ? -d1 : d1, a2 = d2 < 0 ? -d2 : d2;
+                        gk = exp(-tau) * T(itab[a0 + (long)g.n0 * (a1 + (long)g.n1 * a2)]);
+                    } else {
+                        const T rp = (g.dim == 2) ? T(sqrt(T(K))) : T(K);
+                        gk = exp(-tau) / rp;
+                    }
 #pragma unroll
                     for (int b = 0; b < RB; ++b) acc[b] += gk * sw[t * RB + b];
                 }
@@ -201,15 +225,15 @@ ert_status launch_direct(ert_plan_impl* p, const T* st, int op, const double* x,
         double* yb = y + (long)b * N;
         if (left >= 4) {
             hipLaunchKernelGGL((k_direct<T, RAY, 4>), grid, dim3(kTile), 0, p->stream, p->geo, st, sigma, scale,
-                               xb, p->d_ss, weighted, N, p->d_diag, op, yb);
+                               xb, p->d_ss, weighted, N, p->d_diag, p->d_itab, op, yb);
             b += 4;
         } else if (left >= 2) {
             hipLaunchKernelGGL((k_direct<T, RAY, 2>), grid, dim3(kTile), 0, p->stream, p->geo, st, sigma, scale,
-                               xb, p->d_ss, weighted, N, p->d_diag, op, yb);
+                               xb, p->d_ss, weighted, N, p->d_diag, p->d_itab, op, yb);
             b += 2;
         } else {
             hipLaunchKernelGGL((k_direct<T, RAY, 1>), grid, dim3(kTile), 0, p->stream, p->geo, st, sigma, scale,
-                               xb, p->d_ss, weighted, N, p->d_diag, op, yb);
+                               xb, p->d_ss, weighted, N, p->d_diag, p->d_itab, op, yb);
             b += 1;
         }
         ERT_HIP(hipGetLastError());
@@ -255,6 +279,19 @@ ert_status selfcell_launch(ert_plan_impl* p, int ray, double sigma, long ncell, 
 
 ert_status selfcell_compute(ert_plan_impl* p)
 {
+    if (p->o.scheme == 1) {
+        // (M-ii): the table of cell integrals, and A_jj = h cell_int(0) / |S^{d-1}|
+        const long M = (long)p->geo.n0 * p->geo.n1 * p->geo.n2;
+        ERT_HIP(hipMalloc(&p->d_itab, M * sizeof(double)));
+        hipLaunchKernelGGL(k_itab, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, p->stream, p->geo.dim, p->geo.n0,
+                           p->geo.n1, p->geo.n2, p->d_itab);
+        ERT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_fill_scaled, dim3((unsigned)((p->N + 255) / 256)), dim3(256), 0, p->stream, p->d_diag,
+                           p->N, p->d_itab, p->geo.h / surface_area(p->geo.dim));
+        ERT_HIP(hipGetLastError());
+        ERT_HIP(hipStreamSynchronize(p->stream));
+        return ERT_OK;
+    }
     const int ray = p->o.kernel == ERT_K_RAY_MIDPOINT;
     ERT_TRY(selfcell_launch(p, ray, p->sigma_const, ray ? p->N : 1, p->d_diag));
     if (!ray) {

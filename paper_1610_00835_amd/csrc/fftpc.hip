@@ -285,9 +285,11 @@ __global__ __launch_bounds__(kThreads) void k_sum2_final(double* __restrict__ pa
     }
 }
 
-// Kernel array of the constant medium on the periodic grid [m2][m1][m0].
+// Kernel array of the constant medium on the periodic grid [m2][m1][m0]: the
+// matrix entry of the plan's discretisation at each periodic offset, (M-iii)
+// h^d G or (M-ii) h E cell_int / |S^{d-1}|.
 __global__ __launch_bounds__(kThreads) void k_kernel_array(int dim, int m0, int m1, int m2, double h, double sigma,
-                                                           double dself, double* __restrict__ w)
+                                                           double dself, int mii, double* __restrict__ w)
 {
     const long M = (long)m0 * m1 * m2;
     const long i = blockIdx.x * (long)kThreads + threadIdx.x;
@@ -302,6 +304,10 @@ __global__ __launch_bounds__(kThreads) void k_kernel_array(int dim, int m0, int 
         return;
     }
     const double r = h * sqrt(K);
+    if (mii) {
+        w[i] = h * exp(-sigma * r) * cell_int(dim, o0, o1, o2) / surface_area(dim);
+        return;
+    }
     const double hd = dim == 2 ? h * h : h * h * h;
     w[i] = hd * exp(-sigma * r) / (surface_area(dim) * (dim == 2 ? r : r * r));
 }
@@ -425,7 +431,7 @@ ert_status build_symbol(ert_plan_impl* p, FftPc* f)
         for (int a = 0; a < dim && st == ERT_OK; ++a) st = upload_twiddles<double>(s, f->m[a], &tw[a]);
         if (st != ERT_OK) break;
         hipLaunchKernelGGL(k_kernel_array, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, dim,
-                           m0, m1, m2, p->geo.h, f->sbar_t, f->dself, w);
+                           m0, m1, m2, p->geo.h, f->sbar_t, f->dself, p->o.scheme, w);
         st = ERT_HIPST(hipGetLastError());
         if (st != ERT_OK) break;
         // x: every row of w, real in, half spectrum out
@@ -521,7 +527,10 @@ ert_status fftpc_build(ert_plan_impl* p)
         if (st != ERT_OK) break;
         f->sbar_t = sums[0] / (double)p->N;
         f->sbar_s = sums[1] / (double)p->N;
-        st = selfcell_constant(p, f->sbar_t, &f->dself);
+        if (p->o.scheme == 1)   // (M-ii): the diagonal does not depend on the medium
+            st = ERT_HIPST(hipMemcpy(&f->dself, p->d_diag, sizeof(double), hipMemcpyDeviceToHost));
+        else
+            st = selfcell_constant(p, f->sbar_t, &f->dself);
         if (st != ERT_OK) break;
         const long nsym = (long)f->H[0] * f->H[1] * f->H[2];
         const long n1 = (long)f->n[2] * f->n[1] * f->H[0];

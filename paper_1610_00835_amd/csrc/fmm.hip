@@ -370,8 +370,8 @@ __global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__
 // as the dense apply (exact integer step count, marched from the lower index).
 // blk points at the block of leaf leaf0.
 template <typename T>
-__global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, long leaf0, long nleaves,
-                              T* __restrict__ blk, int16_t* __restrict__ lo_plane)
+__global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, const double* __restrict__ itab,
+                              long leaf0, long nleaves, T* __restrict__ blk, int16_t* __restrict__ lo_plane)
 {
     const int nn = (t.D == 3) ? 27 : 9;
     const long per = (long)nn * t.S * t.S;
@@ -409,8 +409,15 @@ __global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, l
                                            d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5),
                                            g.h * (hi[1] + 0.5), d3 ? g.h * (hi[2] + 0.5) : 0.0,
                                            steps_grid(K), r);
-            const double rp = (t.D == 2) ? r : r * r;
-            v = exp(-tau) / (surface_area(t.D) * rp);
+            if (itab) {
+                // (M-ii): cell integral at the integer offset, per unit cell, over h^{d-1}
+                const int a0 = abs(ct[0] - cs[0]), a1 = abs(ct[1] - cs[1]), a2 = abs(ct[2] - cs[2]);
+                const double hp = (t.D == 2) ? g.h : g.h * g.h;
+                v = exp(-tau) * itab[a0 + (long)g.n0 * (a1 + (long)g.n1 * a2)] / (surface_area(t.D) * hp);
+            } else {
+                const double rp = (t.D == 2) ? r : r * r;
+                v = exp(-tau) / (surface_area(t.D) * rp);
+            }
         }
     }
     if constexpr (std::is_same<T, uint16_t>::value) {
@@ -438,7 +445,7 @@ __device__ __forceinline__ void node_multi(int m, int nc, int D, int out[3])
 // G(target node r, source node c) for box offset o (FP64 arithmetic).
 template <typename T>
 __global__ void k_ops_hom(int D, int nc, int K, int Kp, double w, double sigma, const double* __restrict__ cheb,
-                          T* __restrict__ ops, __bf16* __restrict__ lo)
+                          T* __restrict__ ops, __bf16* __restrict__ lo, int mii, double h)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long per = (long)Kp * Kp;
@@ -457,14 +464,20 @@ __global__ void k_ops_hom(int D, int nc, int K, int Kp, double w, double sigma, 
         int mr[3], mc[3];
         node_multi(r, nc, D, mr);
         node_multi(c, nc, D, mc);
-        double r2 = 0.0;
+        double r2 = 0.0, dv[3] = {0.0, 0.0, 0.0};
         for (int a = 0; a < D; ++a) {
             double d = w * (o[a] + 0.5 * (cheb[mc[a]] - cheb[mr[a]]));
+            dv[a] = d;
             r2 += d * d;
         }
         double rr = sqrt(r2);
-        double rp = (D == 2) ? rr : r2;
-        v = exp(-sigma * rr) / (surface_area(D) * rp);
+        if (mii) {
+            const double hp = (D == 2) ? h : h * h;
+            v = exp(-sigma * rr) * cell_int(D, dv[0] / h, dv[1] / h, dv[2] / h, 64.0) / (surface_area(D) * hp);
+        } else {
+            double rp = (D == 2) ? rr : r2;
+            v = exp(-sigma * rr) / (surface_area(D) * rp);
+        }
     }
     if (lo) {
         __bf16 hi = (__bf16)(float)v;
@@ -481,7 +494,7 @@ __global__ void k_ops_hom(int D, int nc, int K, int Kp, double w, double sigma, 
 template <typename T>
 __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, int K, int Kp, double w,
                           int nl0, int nl1, int nl2, const double* __restrict__ cheb, const long* __restrict__ pair_t,
-                          const int* __restrict__ pair_s, long p0, long np, T* __restrict__ opsT)
+                          const int* __restrict__ pair_s, long p0, long np, T* __restrict__ opsT, int mii)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long per = (long)Kp * Kp;
@@ -508,8 +521,14 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, i
         double q = ceil(rr / (0.5 * g.h));
         int m = q < 1.0 ? 1 : (int)q;
         double tau = tau_march<double>(st, g, 1.0 / g.h, X[0], X[1], X[2], Y[0], Y[1], Y[2], m, rr);
-        double rp = (D == 2) ? rr : r2;
-        v = exp(-tau) / (surface_area(D) * rp);
+        if (mii) {
+            const double hp = (D == 2) ? g.h : g.h * g.h;
+            v = exp(-tau) * cell_int(D, (Y[0] - X[0]) / g.h, (Y[1] - X[1]) / g.h, (Y[2] - X[2]) / g.h, 64.0) /
+                (surface_area(D) * hp);
+        } else {
+            double rp = (D == 2) ? rr : r2;
+            v = exp(-tau) / (surface_area(D) * rp);
+        }
     }
     opsT[i] = T(v);
 }
@@ -519,7 +538,7 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, i
 // between a target leaf and its neighbour at leaf offset o depends only on o.
 // ops[o][target i][source i] = G, zero for the self pair.
 template <typename T>
-__global__ void k_near_ops(int D, int leaf, int S, double h, double sigma, T* __restrict__ ops)
+__global__ void k_near_ops(int D, int leaf, int S, double h, double sigma, T* __restrict__ ops, int mii)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long per = (long)S * S;
@@ -532,16 +551,22 @@ __global__ void k_near_ops(int D, int leaf, int S, double h, double sigma, T* __
     int ls1 = D > 1 ? leaf : 1;
     int lt[3] = {it % leaf, (it / leaf) % ls1, it / (leaf * ls1)};
     int lsr[3] = {is % leaf, (is / leaf) % ls1, is / (leaf * ls1)};
-    int K = 0;
+    int K = 0, dv[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) {
         int d = o[a] * leaf + lsr[a] - lt[a];
+        dv[a] = d;
         K += d * d;
     }
     double v = 0.0;
     if (K > 0) {
         double r = h * sqrt((double)K);
-        double rp = (D == 2) ? r : r * r;
-        v = exp(-sigma * r) / (surface_area(D) * rp);
+        if (mii) {
+            const double hp = (D == 2) ? h : h * h;
+            v = exp(-sigma * r) * cell_int(D, dv[0], dv[1], dv[2]) / (surface_area(D) * hp);
+        } else {
+            double rp = (D == 2) ? r : r * r;
+            v = exp(-sigma * r) / (surface_area(D) * rp);
+        }
     }
     ops[i] = T(v);
 }
@@ -974,7 +999,7 @@ ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
     double* M64 = nullptr;
     ERT_TRY(tmp.alloc(&M64, (size_t)noff * KpKp));
     hipLaunchKernelGGL(k_ops_hom<double>, dim3(blocks(noff * KpKp)), dim3(kB), 0, s, tr.D, tr.nc, tr.K, Kp,
-                       tr.width[l], p->sigma_const, cheb, M64, (__bf16*)nullptr);
+                       tr.width[l], p->sigma_const, cheb, M64, (__bf16*)nullptr, p->o.scheme, p->geo.h);
     ERT_HIP(hipGetLastError());
     const double* Cd = M64;
     int M = Kp;
@@ -1124,7 +1149,7 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
         long cnt = std::min(pchunk, np - p0);
         hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, tr.nc,
                            tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, hc->psrc[l], p0, cnt,
-                           hc->hops[l] + (size_t)p0 * KpKp);
+                           hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
         ERT_HIP(hipGetLastError());
     }
     hc->bytes += bytes;
@@ -1197,8 +1222,8 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     const long chunk = std::max<long>(1, (1L << 26) / per);
     for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
         long cnt = std::min(chunk, tr.nleaf - l0);
-        hipLaunchKernelGGL(k_near_blocks<uint16_t>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, l0,
-                           cnt, c->near_hi + (size_t)l0 * per, c->near_lo + (size_t)l0 * per);
+        hipLaunchKernelGGL(k_near_blocks<uint16_t>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st,
+                           p->d_itab, l0, cnt, c->near_hi + (size_t)l0 * per, c->near_lo + (size_t)l0 * per);
         if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
     }
     std::vector<int> src((size_t)tr.nleaf * nn);
@@ -1314,9 +1339,14 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
             const int nn = tr.D == 3 ? 27 : 9;
             const long n = (long)nn * tr.S * tr.S;
             ERT_HIP(hipMalloc(&nearops, n * sizeof(T)));
-            hipLaunchKernelGGL(k_near_ops<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, leaf, tr.S, h, sigma, nearops);
+            hipLaunchKernelGGL(k_near_ops<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, leaf, tr.S, h, sigma, nearops,
+                               p->o.scheme);
             ERT_HIP(hipGetLastError());
         } else {
+            if (p->o.scheme != 0) {
+                record_error("FMM: approach (M-ii) in homogeneous media needs leaf^dim to be a multiple of 32");
+                return ERT_EUNSUPPORTED;
+            }
             // near-field table over K = |offset|^2 <= D (2 leaf - 1)^2
             const int span = 2 * leaf - 1;
             ntab = tr.D * span * span + 1;

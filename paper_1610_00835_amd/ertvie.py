@@ -31,7 +31,7 @@ class VieOpts(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
                 ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
                 ("cheb_n", ctypes.c_int), ("leaf", ctypes.c_int), ("nrhs_max", ctypes.c_int),
-                ("flags", ctypes.c_int), ("svd_tol", ctypes.c_double), ("inner_cheb_n", ctypes.c_int),
+                ("scheme", ctypes.c_int), ("svd_tol", ctypes.c_double), ("inner_cheb_n", ctypes.c_int),
                 ("inner_near16", ctypes.c_int)]
 
 
@@ -166,7 +166,7 @@ class Plan:
     """
 
     def __init__(self, dim, n, h, sigma_t, sigma_s, kernel=K_HOMOGENEOUS, method="direct", prec="fp64",
-                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0, inner_cheb_n=0, inner_near16=False):
+                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0, inner_cheb_n=0, inner_near16=False, scheme=0):
         L = load()
         n = list(n)[:dim]
         self.dim = int(dim)
@@ -183,7 +183,7 @@ class Plan:
         o.cheb_n = int(cheb_n)
         o.leaf = int(leaf)
         o.nrhs_max = int(nrhs_max)
-        o.flags = 0
+        o.scheme = int(scheme)
         o.svd_tol = float(svd_tol)
         o.inner_cheb_n = int(inner_cheb_n)
         o.inner_near16 = 1 if inner_near16 else 0
@@ -318,10 +318,10 @@ class Plan:
 
 
 def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0,
-                   inner_cheb_n=0, inner_near16=False):
+                   inner_cheb_n=0, inner_near16=False, scheme=0):
     return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
                 method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream,
-                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n, inner_near16=inner_near16)
+                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n, inner_near16=inner_near16, scheme=scheme)
 
 
 def _load_net():

@@ -65,7 +65,7 @@ def test_plan_rejects_bad_arguments_before_device_use():
     assert plan(dim=4) == ertvie.EINVAL
     assert plan(h=0.0) == ertvie.EINVAL
     assert plan(h=float("nan")) == ertvie.EINVAL
-    assert plan(flags=1) == ertvie.EINVAL
+    assert plan(scheme=2) == ertvie.EINVAL
     assert plan(cheb_n=12) == ertvie.EINVAL
     assert plan(inner_cheb_n=1) == ertvie.EINVAL
     assert plan(inner_cheb_n=9) == ertvie.EINVAL
