@@ -214,3 +214,44 @@ def test_learned_preconditioner_gain_and_judge(ev):
             assert np.all(np.isfinite(_host(U2)))
         log("non-finite network", bad)
         assert bad["converged"] == 1 and bad["rejected"] >= 1 and bad["rejected"] == bad["restarts"]
+
+
+def test_network_after_fft_preconditioner_gain(ev):
+    """The network trained on the FFT-based preconditioner's output (the committed
+    64^3 weights, trained on media 1000-1023): on the residuals of a held-out medium's
+    solve (seed 0), one application of net(M r) leaves a smaller residual
+    ||r - (I - K) z|| than M r alone, and is closer to the exact correction."""
+    import os
+    import torch
+    from paper_1610_00835_amd import learn
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1610_00835_amd",
+                        "weights", "precond_c5_64_fft.npz")
+    w = np.load(path)
+    n = (64, 64, 64)
+    case = _c5_case(n, 0)
+    st = _dev(case["sigma_t"][None])
+    ss = _dev(case["sigma_s"][None])
+    with ev.plan_from_case(case, method="fmm", prec="fp64") as plan, ev.Net(n, batch_max=1) as net:
+        net.set_params(w["params"])
+        R, E, _ = learn.collect_pairs(plan, case["f"], restart=4, tol=1e-9, max_pairs=40)
+        res = []
+        for k in range(R.shape[0]):
+            r = R[k:k + 1].contiguous()
+            q = torch.empty_like(r)
+            plan.fft_precond(r, q)
+            z = torch.empty_like(r)
+            net.forward(q, st, ss, z)
+            aq = torch.empty_like(r)
+            plan.apply(q, aq, op=ev.OP_A)
+            az = torch.empty_like(r)
+            plan.apply(z, az, op=ev.OP_A)
+            torch.cuda.synchronize()
+            nr = float(torch.linalg.norm(r))
+            e = E[k:k + 1]
+            res.append((float(torch.linalg.norm(r - aq)) / nr, float(torch.linalg.norm(r - az)) / nr,
+                        float(torch.linalg.norm(e - q) / torch.linalg.norm(e)),
+                        float(torch.linalg.norm(e - z) / torch.linalg.norm(e))))
+    g = np.array(res)
+    log("residual left: FFT-based %.3f, network after it %.3f; error left: %.3f vs %.3f" % tuple(g.mean(0)))
+    assert g[:, 1].mean() < 0.8 * g[:, 0].mean()
+    assert g[:, 3].mean() < g[:, 2].mean()
