@@ -10,6 +10,7 @@ in HBM, FP32 bulk with FP64 assembly.  Prints one JSON line on stdout (progress 
                   [--no-cpu-baseline] [--no-solve] [--no-c3]
 """
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -167,6 +168,31 @@ def many_scattering_128(torch, ertvie, inputs, O, stream, args):
         for k in ("mixed", "mixed_fft", "mixed_fft_learned"):
             if k in out:
                 out[k]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / out[k]["t_solve"]
+        # Algorithm 1 S.3 from the solution: Phi for 26 directions (cube faces, edges, corners)
+        dirs = np.array([d for d in itertools.product((-1, 0, 1), repeat=3) if any(d)], dtype=np.float64)
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        phi = torch.empty((len(dirs), N), dtype=torch.float64, device="cuda")
+        plan.transport(U0, fd, dirs, phi)                    # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.transport(U0, fd, dirs, phi)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        # ray steps of the sweep (the same count rule as the kernel), for the per-step rate
+        xc = inputs.centres(case["n"], case["h"])
+        steps = 0
+        for v in dirs:
+            sb = np.full(N, np.inf)
+            for a in range(3):
+                if v[a] > 0:
+                    sb = np.minimum(sb, xc[:, a] / v[a])
+                elif v[a] < 0:
+                    sb = np.minimum(sb, (1.0 - xc[:, a]) / (-v[a]))
+            steps += int(np.maximum(1, np.ceil(sb / (0.5 / 128) * (1 - 1e-12))).sum())
+        out["recover_phi"] = {"directions": len(dirs), "seconds": ts, "cell_directions_per_s": N * len(dirs) / ts,
+                              "ray_steps": steps, "steps_per_s": steps / ts,
+                              "l2_gather_bytes_per_s": steps * 16 * 8 / ts}
+        log("128^3 S.3:", json.dumps(out["recover_phi"]))
     return out
 
 
@@ -284,6 +310,35 @@ def paper_experiment_iii(torch, ertvie, inputs, stream, kmax=12, mus_list=(2.0, 
             out["runs"]["%s_mu_s_%g" % (name, mus)] = {"h": hs, "rel_l2_err": errs, "observed_order": orders,
                                                        "seconds": time.perf_counter() - t0}
             log("experiment III %s mu_s %g: errors %s" % (name, mus, " ".join("%.2e" % e for e in errs)))
+    return out
+
+
+def homogeneous_64(torch, ertvie, inputs, O, stream):
+    """The 32^3 workload's medium on a 64^3 grid (N = 262,144; two far-field levels): FP32
+    FMM apply time, the box-offset products' throughput at this size, and the error on
+    sampled rows against the oracle."""
+    case = inputs.make_case("c2", n=(64, 64, 64), seed=0)
+    N = int(np.prod(case["n"]))
+    x = torch.from_numpy(inputs.random_vector(N, 13)).cuda()
+    y = torch.empty_like(x)
+    with ertvie.plan_from_case(case, method="fmm", prec="fp32", stream=stream) as plan:
+        plan.apply(x, y, op=ertvie.OP_A)
+        plan.apply(x, y, op=ertvie.OP_A)
+        ms = timed_applies(torch, plan, x, y, ertvie.OP_A, 20, 3)
+        yh = y.cpu().numpy()
+        st, ln = stage_profile(plan, x, y, ertvie.OP_A, 10)
+        info = plan.fmm_info()
+    info["leaf_boxes"] = int(np.prod([-(-n // info["leaf"]) for n in case["n"]]))
+    rf = roofline_of(info, st, ln, "fp32")
+    P = O.Problem(3, case["n"], case["h"], 0, case["sigma_t"], case["sigma_s"])
+    rows = np.random.default_rng(2).choice(N, size=24, replace=False)
+    yo = P.apply_rows(inputs.random_vector(N, 13), rows, op=2)
+    out = {"workload": "64^3 homogeneous sigma_t = 5, sigma_s = 4, FP32 FMM (leaf 8^3, n = 8, compression 1e-6)",
+           "apply_ms": ms, "mpts_per_s": N / (ms * 1e-3) / 1e6, "stage_ms": st, "fmm": info,
+           "near_tflops": rf["near_tflops"], "m2l_tflops": rf["m2l_tflops"], "dominant": rf["kernel"],
+           "dominant_frac": rf["frac"], "dominant_bound": rf["bound"],
+           "rel_l2_vs_oracle_rows": float(np.linalg.norm(yh[rows] - yo) / np.linalg.norm(yo))}
+    log("64^3 homogeneous:", json.dumps({k: v for k, v in out.items() if k not in ("fmm",)}))
     return out
 
 
@@ -523,6 +578,7 @@ def main():
         extra["many_scattering_128cubed"] = many_scattering_128(torch, ertvie, inputs, O, stream, args)
 
     if not args.no_c3:
+        extra["c2_recipe_64cubed_homogeneous"] = homogeneous_64(torch, ertvie, inputs, O, stream)
         # 64^3 heterogeneous blob medium with the ray-quadrature kernel (cached pair translations)
         c3 = inputs.make_case("c3", seed=0)
         N3 = int(np.prod(c3["n"]))

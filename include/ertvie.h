@@ -238,6 +238,23 @@ ERT_API ert_status ert_vie_fft_precond(ert_vie_plan_t plan, const double* r, dou
 /* Build (if needed) and describe the FFT-based preconditioner (host struct). */
 ERT_API ert_status ert_vie_fft_info(ert_vie_plan_t plan, ert_fft_info* info);
 
+/* Algorithm 1 step S.3: the angular solution Phi(x_j, v_k) from U, i.e. the
+ * scattering-free transport equation v . grad Phi + sigma_t Phi = Q with
+ * Q = sigma_s U + f and no inflow, solved along characteristics.  From each cell
+ * centre the ray is followed backwards to the boundary of [0, n_a h]^dim in
+ * m = ceil(s / (h/2) (1 - 1e-12)) equal steps; on each step sigma_t and Q take their values at
+ * the step midpoint (d-linear interpolation of the cell values, clamped to the
+ * cell-centre box, as the kernel's ray rule does) and the step is integrated
+ * exactly for those constants, so a constant medium and source give
+ * Q (1 - exp(-sigma_t s)) / sigma_t.  The angular average of Phi approximates U.
+ *   U, f : device, N values FP64; either may be NULL (taken as zero).
+ *   dirs : host, ndir x dim unit vectors (|v| = 1 within 1e-10), row per direction.
+ *   phi  : device, N x ndir column-major FP64 (column k for dirs[k]).
+ * FP64 throughout; stream-ordered, synchronises before returning (it frees its
+ * scratch).  ERT_EINVAL for a non-unit or non-finite direction or ndir < 1. */
+ERT_API ert_status ert_vie_transport(ert_vie_plan_t plan, const double* U, const double* f, const double* dirs,
+                                     int ndir, double* phi);
+
 /* Stages of one FMM apply, for ert_vie_profile. */
 typedef enum {
     ERT_STAGE_GATHER = 0,   /* weights into leaf-major order */

@@ -12,7 +12,9 @@ bench.py.  The product library never imports it.
 
 Discretisation (the paper leaves the transport solver open; this is the reading):
 the ray x - t v, 0 <= t <= s_b (s_b = distance to the boundary of the box
-[0, n_a h]^d) is cut into m = max(1, ceil(s_b / (h/2))) equal steps of length
+[0, n_a h]^d) is cut into m = max(1, ceil(s_b / (h/2) (1 - 1e-12))) equal steps
+(the relative margin keeps the count of an exact multiple of h/2, as on every
+axis-parallel ray, independent of the last bit of s_b) of length
 D; on step k sigma_t and Q take their values at the step midpoint t_k = (k - 1/2) D
 (d-linear interpolation of the cell values, clamped to the cell-centre box, as
 the kernel's ray rule does), and the step is integrated exactly for those
@@ -71,7 +73,7 @@ def sweep(q, sigma_t, n, h, v, cells=None):
     x = h * (idx + 0.5)
     v = np.asarray(v, dtype=np.float64)
     sb = boundary_distance(x, v, n, h)
-    m = np.maximum(1, np.ceil(sb / (0.5 * h))).astype(np.int64)
+    m = np.maximum(1, np.ceil(sb / (0.5 * h) * (1.0 - 1e-12))).astype(np.int64)
     D = sb / m
     phi = np.zeros(len(cells))
     tau = np.zeros(len(cells))

@@ -578,6 +578,13 @@ ert_status ert_vie_fft_precond(ert_vie_plan_t p, const double* r, double* z, int
     return fftpc_apply(p, r, z, nrhs);
 }
 
+ert_status ert_vie_transport(ert_vie_plan_t p, const double* U, const double* f, const double* dirs, int ndir,
+                             double* phi)
+{
+    if (!p || !dirs || !phi || ndir < 1) return ERT_EINVAL;
+    return transport_sweep(p, U, f, dirs, ndir, phi);
+}
+
 ert_status ert_vie_fft_info(ert_vie_plan_t p, ert_fft_info* info)
 {
     if (!p || !info) return ERT_EINVAL;

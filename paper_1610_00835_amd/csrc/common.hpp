@@ -285,6 +285,9 @@ void het_destroy(HetCache* c);
 // FFT-based preconditioner of the mean medium (fftpc.hip): z = M r for nrhs
 // columns (device FP64), stream-ordered; builds the symbol on first use.
 ert_status fftpc_apply(ert_plan_impl* p, const double* r, double* z, int nrhs);
+// Algorithm 1 S.3 (transport.hip): phi[:, d] = the angular solution for direction d.
+ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host, int ndir,
+                           double* phi);
 ert_status fftpc_info(ert_plan_impl* p, ert_fft_info* info);
 void fftpc_destroy(FftPc* f);
 
