@@ -199,12 +199,15 @@ def many_scattering_128(torch, ertvie, inputs, O, stream, args):
 # Sec. 5.3, Experiments V and VI: GMRES iterations to 1e-12 without and with the
 # FFT-based preconditioner (Table TAB:EXP VI, the paper's MATLAB code on one laptop core).
 PAPER_EXP6_ITERS = {10.0: (21, 9), 20.0: (34, 11), 40.0: (78, 13), 80.0: (110, 15)}
+# Experiment V: the same setting with the diffusion preconditioner (plain, preconditioned)
+PAPER_EXP5_ITERS = {10.0: (21, 36), 20.0: (34, 38), 40.0: (78, 42), 80.0: (110, 52)}
 
 
 def paper_experiment_vi(torch, ertvie, inputs, stream):
-    """The paper's preconditioning experiment: 2D unit square, h = 1/512 (N = 262,144),
-    Chebyshev order 6, absorption 0.2 and scattering 10, 20, 40, 80 (homogeneous), GMRES to
-    1e-12, unpreconditioned and with the FFT-based preconditioner.  The paper's source exists
+    """The paper's preconditioning experiments (V and VI): 2D unit square, h = 1/512
+    (N = 262,144), Chebyshev order 6, absorption 0.2 and scattering 10, 20, 40, 80
+    (homogeneous), GMRES to 1e-12, unpreconditioned, with the FFT-based preconditioner and
+    with the diffusion preconditioner.  The paper's source exists
     only as a figure; a Gaussian of width 0.1 at the centre stands in for it (far from the
     boundary, the preconditioner's assumption)."""
     n = (512, 512)
@@ -213,7 +216,8 @@ def paper_experiment_vi(torch, ertvie, inputs, stream):
     f = np.exp(-np.sum((x - 0.5) ** 2, axis=1) / (2 * 0.1 ** 2))
     fd = torch.from_numpy(f).cuda()
     out = {"workload": "2D 512^2, mu_a = 0.2, homogeneous, Gaussian source (width 0.1), tol 1e-12, FMM n = 6, FP64",
-           "paper_iters_plain_fft": {str(k): v for k, v in PAPER_EXP6_ITERS.items()}, "runs": {}}
+           "paper_iters_plain_fft": {str(k): v for k, v in PAPER_EXP6_ITERS.items()},
+           "paper_iters_plain_diffusion": {str(k): v for k, v in PAPER_EXP5_ITERS.items()}, "runs": {}}
     keys = ("iters", "matvecs", "t_solve", "rel_resid_true")
     for mus in sorted(PAPER_EXP6_ITERS):
         case = {"dim": 2, "n": n, "h": 1.0 / 512, "kernel": ertvie.K_HOMOGENEOUS,
@@ -226,14 +230,19 @@ def paper_experiment_vi(torch, ertvie, inputs, stream):
             plan.solve(fd, U, tol=1e-12, max_iter=300, precond_fft=True)
             r1 = plan.solve(fd, U, tol=1e-12, max_iter=300, precond_fft=True)
             d = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+            plan.solve(fd, U, tol=1e-12, max_iter=300, precond_diffusion=True)
+            r2 = plan.solve(fd, U, tol=1e-12, max_iter=300, precond_diffusion=True)
+            d2 = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
         run = {"plain": {k: r0[k] for k in keys}, "fft": {k: r1[k] for k in keys}, "fft_vs_plain_rel_l2": d,
-               "speedup": r0["t_solve"] / r1["t_solve"]}
-        for k in ("plain", "fft"):
+               "speedup": r0["t_solve"] / r1["t_solve"], "diffusion": {k: r2[k] for k in keys},
+               "diffusion_vs_plain_rel_l2": d2, "diffusion_speedup": r0["t_solve"] / r2["t_solve"]}
+        for k in ("plain", "fft", "diffusion"):
             run[k]["ms_per_iter"] = 1e3 * run[k]["t_solve"] / max(1, run[k]["matvecs"])
         out["runs"][str(mus)] = run
-        log("experiment VI mu_s = %g: plain %d iterations (paper %d), FFT-preconditioned %d (paper %d), %.3f s vs %.3f s"
-            % (mus, r0["iters"], PAPER_EXP6_ITERS[mus][0], r1["iters"], PAPER_EXP6_ITERS[mus][1], r0["t_solve"],
-               r1["t_solve"]))
+        log("experiments V/VI mu_s = %g: plain %d iterations (paper %d), FFT-preconditioned %d (paper %d), "
+            "diffusion-preconditioned %d (paper %d); %.3f s / %.3f s / %.3f s"
+            % (mus, r0["iters"], PAPER_EXP6_ITERS[mus][0], r1["iters"], PAPER_EXP6_ITERS[mus][1], r2["iters"],
+               PAPER_EXP5_ITERS[mus][1], r0["t_solve"], r1["t_solve"], r2["t_solve"]))
     return out
 
 

@@ -87,6 +87,12 @@ typedef enum {
     ERT_OP_A = 2      /* y = x - A (sigma_s x)  (the operator I - K of step S.2) */
 } ert_op;
 
+typedef enum {
+    ERT_PRECOND_NONE = 0,
+    ERT_PRECOND_FFT = 1,        /* FFT-based preconditioner of the mean medium (Sec. 4.4) */
+    ERT_PRECOND_DIFFUSION = 2   /* diffusion approximation, multigrid V-cycles (Sec. 4.4) */
+} ert_precond;
+
 typedef struct {
     int dim;          /* 2 or 3 */
     int n[3];         /* cells per axis (n[2] ignored for dim 2), each >= 1, N >= 2 */
@@ -137,12 +143,13 @@ typedef struct {
                          with restart = 0 the block basis is capped at 4 GiB */
     int precond_steps;/* with precond: Arnoldi steps per preconditioned correction; 0 -> 10 */
     int history_max;  /* columns of `history` (0: no history) */
-    int precond_fft;  /* 1: right-precondition every GMRES solve (the inner solves with `mixed`,
-                         each correction with `precond`) by the FFT-based preconditioner of the
-                         mean medium (ert_vie_fft_precond), in flexible GMRES; with `precond`
-                         the network acts on its output, z_j = net(M v_j), and the fallback
-                         of a rejected step keeps M; with `block`, block GMRES on (I - K) M
-                         with U = M Y.  0: none */
+    int precond_kind; /* ert_precond: right-precondition every GMRES solve (the inner solves
+                         with `mixed`, each correction with `precond`) by a fixed preconditioner
+                         M, in flexible GMRES: ERT_PRECOND_FFT (ert_vie_fft_precond) or
+                         ERT_PRECOND_DIFFUSION (ert_vie_diff_precond).  With `precond` the
+                         network acts on M's output, z_j = net(M v_j), and the fallback of a
+                         rejected step keeps M; with `block`, block GMRES on (I - K) M with
+                         U = M Y.  ERT_PRECOND_NONE (0): none */
     ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
                          becomes a refinement loop.  Each step solves (I - K) d = r by flexible
                          GMRES with z_j = net(v_j) (inner operator: FP32 with `mixed`, else the
@@ -254,6 +261,23 @@ ERT_API ert_status ert_vie_fft_info(ert_vie_plan_t plan, ert_fft_info* info);
  * scratch).  ERT_EINVAL for a non-unit or non-finite direction or ndir < 1. */
 ERT_API ert_status ert_vie_transport(ert_vie_plan_t plan, const double* U, const double* f, const double* dirs,
                                      int ndir, double* phi);
+
+/* Diffusion preconditioner (Sec. 4.4, eq. EQ:DA).  The diffusion approximation
+ *   -div(D grad U) + mu_a U = f,  U + l dU/dn = 0 on the boundary,
+ *   D = 1 / (dim sigma_t),  mu_a = sigma_t - sigma_s,  l = 2 / (dim sigma_t),
+ * models f -> U = (I - K)^{-1} A f, so (I - K)^{-1} = I + (I - K)^{-1} A S is
+ * approximated by  z = M r = r + L^{-1} (sigma_s r).  L: cell-centred finite
+ * differences per unit volume on the plan's grid (harmonic-mean face
+ * coefficients; each boundary face adds 2 D / (h (h + 2 l)) from the Robin
+ * condition with the boundary value extrapolated from the cell centre).
+ * L^{-1}: two multigrid V-cycles from zero (levels by halving every axis down to
+ * 4 cells per axis, coarse coefficients averaged over the children, red-black
+ * Gauss-Seidel with 2 + 2 sweeps, averaging restriction, constant prolongation,
+ * 60 sweeps on the coarsest level).  FP64.  r, z: device N x nrhs (may be the
+ * same buffer), 1 <= nrhs <= nrhs_max.  Built on the plan's stream on first use
+ * (about 9 vectors of N doubles over all levels).  The approximation holds for
+ * optically thin cells (sigma_t h well below 1) in optically thick domains. */
+ERT_API ert_status ert_vie_diff_precond(ert_vie_plan_t plan, const double* r, double* z, int nrhs);
 
 /* Stages of one FMM apply, for ert_vie_profile. */
 typedef enum {

@@ -139,7 +139,7 @@ ert_status plan_apply(ert_plan_impl* p, int op, int method, int prec, const doub
 
 ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Phi, double* X, int nb, double rtol,
                        int maxit, int restart, bool check_true, int* iters_out, int* cycles_out, int* matvecs_out,
-                       double* est_out, double* true_out, bool* conv_out, bool fft);
+                       double* est_out, double* true_out, bool* conv_out, int pk);
 
 namespace {
 
@@ -189,12 +189,12 @@ struct History {
     int count = 0;
 };
 
-// Right preconditioner of a GMRES run: the FFT-based one of the mean medium,
-// the network, or the network acting on the FFT-based one's output.
+// Right preconditioner of a GMRES run: a fixed one (kind: FFT-based of the mean
+// medium, or diffusion), the network, or the network acting on the fixed one's output.
 struct Precond {
     NetImpl* net = nullptr;
-    bool fft = false;
-    bool active() const { return net != nullptr || fft; }
+    int kind = ERT_PRECOND_NONE;
+    bool active() const { return net != nullptr || kind != ERT_PRECOND_NONE; }
 };
 
 struct RunStats {
@@ -258,11 +258,11 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
             double* vj = V + (size_t)j * N;
             if (flex) {
                 double* zj = Z + (size_t)j * N;
-                if (pc->fft && pc->net) {
-                    ERT_TRY(fftpc_apply(p, vj, w, 1));
+                if (pc->kind && pc->net) {
+                    ERT_TRY(precond_apply(p, pc->kind, vj, w, 1));
                     ERT_TRY(net_precond(pc->net, w, p->d_st, p->d_ss, zj, p->stream));
-                } else if (pc->fft) {
-                    ERT_TRY(fftpc_apply(p, vj, zj, 1));
+                } else if (pc->kind) {
+                    ERT_TRY(precond_apply(p, pc->kind, vj, zj, 1));
                 } else {
                     ERT_TRY(net_precond(pc->net, vj, p->d_st, p->d_ss, zj, p->stream));
                 }
@@ -331,9 +331,9 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
 // step computes a correction d by flexible GMRES (at most precond_steps Arnoldi
 // steps, stopping at inner_tol) on the inner operator, and keeps U + d only if
 // the true residual of the outer operator decreases; a rejected step is redone
-// without the network (plain GMRES, or with the FFT-based preconditioner alone
-// when `fft`) with the same budget.  r and d are caller scratch (N each).
-ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec_inner, NetImpl* net, bool fft,
+// without the network (plain GMRES, or with the fixed preconditioner `kind`
+// alone) with the same budget.  r and d are caller scratch (N each).
+ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec_inner, NetImpl* net, int kind,
                           const double* phi, double* U, double* r, double* d, const ert_solve_opts& so,
                           ert_solve_info* inf)
 {
@@ -364,7 +364,7 @@ ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec
             RunStats rs;
             Precond pc;
             pc.net = attempt == 0 ? net : nullptr;
-            pc.fft = fft;
+            pc.kind = kind;
             st = gmres_run(p, method, prec_inner, r, d, so.inner_tol, budget, budget, false, &rs, &pc);
             if (st != ERT_OK) break;
             used += rs.iters;
@@ -445,6 +445,8 @@ void ert_vie_destroy(ert_vie_plan_t p)
     }
     fftpc_destroy(p->fftpc);
     p->fftpc = nullptr;
+    diffpc_destroy(p->diffpc);
+    p->diffpc = nullptr;
     (void)hipFree(p->d_st);
     (void)hipFree(p->d_st32);
     (void)hipFree(p->d_ss);
@@ -585,6 +587,12 @@ ert_status ert_vie_transport(ert_vie_plan_t p, const double* U, const double* f,
     return transport_sweep(p, U, f, dirs, ndir, phi);
 }
 
+ert_status ert_vie_diff_precond(ert_vie_plan_t p, const double* r, double* z, int nrhs)
+{
+    if (!p || !r || !z || nrhs < 1 || nrhs > p->nrhs_max) return ERT_EINVAL;
+    return diffpc_apply(p, r, z, nrhs);
+}
+
 ert_status ert_vie_fft_info(ert_vie_plan_t p, ert_fft_info* info)
 {
     if (!p || !info) return ERT_EINVAL;
@@ -612,7 +620,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
     if (so.inner_tol == 0.0) so.inner_tol = 1e-5;
     if (!(so.tol > 0.0) || so.max_iter < 1 || so.restart < 0 || !(so.inner_tol > 0.0) || so.inner_tol >= 1.0)
         return ERT_EINVAL;
-    if (so.precond_fft != 0 && so.precond_fft != 1) return ERT_EINVAL;
+    if (so.precond_kind < ERT_PRECOND_NONE || so.precond_kind > ERT_PRECOND_DIFFUSION) return ERT_EINVAL;
     if (so.precond_steps < 0 || so.history_max < 0 || (so.history_max > 0 && !so.history)) return ERT_EINVAL;
     NetImpl* net = so.precond ? net_impl(so.precond) : nullptr;
     if (net) {
@@ -665,7 +673,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
             bool conv = false;
             if (!so.mixed) {
                 st = block_gmres(p, method, prec_outer, Phi, U, nrhs, so.tol, so.max_iter, so.restart, true, &it, &cy,
-                                 &mv, &est, &tr, &conv, so.precond_fft != 0);
+                                 &mv, &est, &tr, &conv, so.precond_kind);
                 if (st != ERT_OK) break;
                 inf.iters = it;
                 inf.restarts = cy > 0 ? cy - 1 : 0;
@@ -696,7 +704,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
                     if (worst <= so.tol) { inf.converged = 1; break; }
                     if (used >= so.max_iter) break;
                     st = block_gmres(p, method, prec_inner, Rb, Db, nrhs, so.inner_tol, so.max_iter - used, so.restart,
-                                     false, &it, &cy, &mv, &est, &tr, &conv, so.precond_fft != 0);
+                                     false, &it, &cy, &mv, &est, &tr, &conv, so.precond_kind);
                     if (st != ERT_OK) break;
                     used += it;
                     inf.iters += it;
@@ -721,8 +729,8 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         return st != ERT_OK ? st : result;
     }
     Precond pc;
-    pc.fft = so.precond_fft != 0;
-    if (pc.fft) st = fftpc_apply(p, nullptr, nullptr, 0);   // build the symbol before the first column
+    pc.kind = so.precond_kind;
+    if (pc.kind) st = precond_apply(p, pc.kind, nullptr, nullptr, 0);   // build it before the first column
     for (int c = 0; c < nrhs && st == ERT_OK; ++c) {
         std::memset(&inf, 0, sizeof(inf));
         const double* fc = f + (size_t)c * N;
@@ -737,7 +745,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         if (st != ERT_OK) break;
         if (net) {
             st = learned_refine(p, method, so.mixed ? ERT_FP64 : p->o.prec, so.mixed ? prec_inner : p->o.prec, net,
-                                so.precond_fft != 0, phi, Uc, r, d, so, &inf);
+                                so.precond_kind, phi, Uc, r, d, so, &inf);
         } else if (!so.mixed) {
             RunStats rs;
             History hist;

@@ -125,13 +125,14 @@ ert_status plan_apply(ert_plan_impl* p, int op, int method, int prec, const doub
 // Block GMRES with x0 = 0 for (I - K) X = Phi, all nb columns in one block.
 // Converged when every column's residual estimate reaches rtol ||Phi_b||; the
 // true residual (same operator) is then checked and the method restarts if needed.
-// With fft: right preconditioning by the FFT-based preconditioner M of the mean
-// medium (a fixed linear map), i.e. the Krylov space of (I - K) M and the update
+// With a preconditioner kind pk (FFT-based or diffusion, fixed linear maps):
+// right preconditioning, i.e. the Krylov space of (I - K) M and the update
 // X += M [V_0 .. V_j] Y.
 ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Phi, double* X, int nb, double rtol,
                        int maxit, int restart, bool check_true, int* iters_out, int* cycles_out, int* matvecs_out,
-                       double* est_out, double* true_out, bool* conv_out, bool fft)
+                       double* est_out, double* true_out, bool* conv_out, int pk)
 {
+    const bool fft = pk != 0;     // right preconditioner of that kind (ERT_PRECOND_*)
     const long N = pl->N;
     const int p = nb;
     // Krylov dimension in blocks: restart, or (unrestarted) as many blocks as fit in 4 GiB
@@ -183,7 +184,7 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
         for (int j = 0; j < m && iters < maxit; ++j) {
             double* Vj = V.p + (size_t)j * p * N;
             if (fft) {
-                ERT_TRY(fftpc_apply(pl, Vj, T.p, p));          // T is free until the block QR below
+                ERT_TRY(precond_apply(pl, pk, Vj, T.p, p));    // T is free until the block QR below
                 ERT_TRY(plan_apply(pl, ERT_OP_A, method, prec, T.p, W.p, p));
             } else {
                 ERT_TRY(plan_apply(pl, ERT_OP_A, method, prec, Vj, W.p, p));
@@ -288,7 +289,7 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
         ERT_HIP(hipMemcpyAsync(Yd.p, Y.data(), sizeof(double) * n * p, hipMemcpyHostToDevice, s));
         if (fft) {
             ERT_TRY(dev_dgemm(s, (int)N, p, n, 1.0, V.p, 1, N, Yd.p, p, 1, 0.0, T.p, 1, N, nullptr, 0));
-            ERT_TRY(fftpc_apply(pl, T.p, W.p, p));
+            ERT_TRY(precond_apply(pl, pk, T.p, W.p, p));
             ERT_TRY(dev_add(s, X, W.p, N * p));
         } else {
             ERT_TRY(dev_dgemm(s, (int)N, p, n, 1.0, V.p, 1, N, Yd.p, p, 1, 1.0, X, 1, N, nullptr, 0));

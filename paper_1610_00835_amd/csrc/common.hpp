@@ -202,6 +202,7 @@ __device__ __forceinline__ double cell_int(int dim, double t0, double t1, double
 struct FmmData;   // fmm.hip
 struct HetCache;  // fmm.hip
 struct FftPc;     // fftpc.hip
+struct DiffPc;    // diffpc.hip
 
 // Per-stage event timing (ert_vie_profile).
 struct Profiler {
@@ -268,6 +269,7 @@ struct ert_plan_impl {
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
     HetCache* het[2] = {nullptr, nullptr};   // heterogeneous kernel caches (per Chebyshev order)
     FftPc* fftpc = nullptr;      // FFT-based preconditioner (built on first use)
+    DiffPc* diffpc = nullptr;    // diffusion preconditioner (built on first use)
     Profiler prof;
     bool use_graphs = true;      // FMM applies replay captured graphs
 };
@@ -285,6 +287,14 @@ void het_destroy(HetCache* c);
 // FFT-based preconditioner of the mean medium (fftpc.hip): z = M r for nrhs
 // columns (device FP64), stream-ordered; builds the symbol on first use.
 ert_status fftpc_apply(ert_plan_impl* p, const double* r, double* z, int nrhs);
+// Diffusion preconditioner (diffpc.hip): z = r + (two V-cycles for L e = sigma_s r).
+ert_status diffpc_apply(ert_plan_impl* p, const double* r, double* z, int nrhs);
+void diffpc_destroy(DiffPc* d);
+// Right preconditioner by kind (ERT_PRECOND_FFT or ERT_PRECOND_DIFFUSION), nrhs columns.
+inline ert_status precond_apply(ert_plan_impl* p, int kind, const double* r, double* z, int nrhs)
+{
+    return kind == ERT_PRECOND_DIFFUSION ? diffpc_apply(p, r, z, nrhs) : fftpc_apply(p, r, z, nrhs);
+}
 // Algorithm 1 S.3 (transport.hip): phi[:, d] = the angular solution for direction d.
 ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host, int ndir,
                            double* phi);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libertvie.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 K_HOMOGENEOUS, K_RAY_MIDPOINT = 0, 1
+PRECOND_NONE, PRECOND_FFT, PRECOND_DIFFUSION = 0, 1, 2
 DIRECT, FMM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
 OP_G, OP_GS, OP_A = 0, 1, 2
@@ -39,7 +40,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("mixed", ctypes.c_int), ("inner_tol", ctypes.c_double), ("rhs_is_phi", ctypes.c_int),
                 ("block", ctypes.c_int), ("precond_steps", ctypes.c_int), ("history_max", ctypes.c_int),
-                ("precond_fft", ctypes.c_int), ("precond", ctypes.c_void_p), ("history", ctypes.c_void_p)]
+                ("precond_kind", ctypes.c_int), ("precond", ctypes.c_void_p), ("history", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -109,6 +110,8 @@ def load():
     L.ert_vie_fft_precond.argtypes = [_vp, _vp, _vp, ctypes.c_int]
     L.ert_vie_transport.restype = ctypes.c_int
     L.ert_vie_transport.argtypes = [_vp, _vp, _vp, _dp, ctypes.c_int, _vp]
+    L.ert_vie_diff_precond.restype = ctypes.c_int
+    L.ert_vie_diff_precond.argtypes = [_vp, _vp, _vp, ctypes.c_int]
     L.ert_vie_fft_info.restype = ctypes.c_int
     L.ert_vie_fft_info.argtypes = [_vp, ctypes.POINTER(FftInfo)]
     L.ert_vie_diag.restype = ctypes.c_int
@@ -247,6 +250,15 @@ class Plan:
         _check(load().ert_vie_transport(self.handle, up, fp, dirs.ctypes.data_as(_dp), nd, pp), "ert_vie_transport")
         return phi
 
+    def diff_precond(self, r, z):
+        """z = r + (two V-cycles for the diffusion approximation with source sigma_s r)."""
+        rp, nr = _dev_ptr(r, self.N, "r")
+        zp, nz = _dev_ptr(z, self.N, "z")
+        if nr != nz:
+            raise ValueError("r and z differ in nrhs")
+        _check(load().ert_vie_diff_precond(self.handle, rp, zp, nr), "ert_vie_diff_precond")
+        return z
+
     def fft_info(self):
         inf = FftInfo()
         _check(load().ert_vie_fft_info(self.handle, ctypes.byref(inf)), "ert_vie_fft_info")
@@ -255,10 +267,12 @@ class Plan:
                 "bytes": inf.bytes}
 
     def solve(self, f, U, tol=1e-8, max_iter=500, restart=0, mixed=False, inner_tol=1e-5, rhs_is_phi=False,
-              allow_noconv=False, block=False, precond=None, precond_steps=0, history=None, precond_fft=False):
+              allow_noconv=False, block=False, precond=None, precond_steps=0, history=None, precond_fft=False,
+              precond_diffusion=False):
         """Algorithm 1 steps S.1-S.2.  precond: a Net (learned right preconditioner);
-        precond_fft: right-precondition by the FFT-based preconditioner of the mean medium
-        (with precond, the network acts on its output);
+        precond_fft / precond_diffusion: right-precondition by the FFT-based preconditioner of
+        the mean medium, or by the diffusion preconditioner (with precond, the network acts on
+        its output);
         history: float64 CUDA tensor (2k, N) receiving (U_k, r_k) of the plain solve's cycles."""
         fp, nf = _dev_ptr(f, self.N, "f")
         up, nu = _dev_ptr(U, self.N, "U")
@@ -273,7 +287,9 @@ class Plan:
         so.rhs_is_phi = 1 if rhs_is_phi else 0
         so.block = 1 if block else 0
         so.precond_steps = int(precond_steps)
-        so.precond_fft = 1 if precond_fft else 0
+        if precond_fft and precond_diffusion:
+            raise ValueError("choose one fixed preconditioner")
+        so.precond_kind = PRECOND_FFT if precond_fft else (PRECOND_DIFFUSION if precond_diffusion else PRECOND_NONE)
         if precond is not None:
             so.precond = precond.handle.value
         if history is not None:

@@ -16,7 +16,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ("ert_vie_plan", "ert_vie_apply", "ert_vie_solve", "ert_vie_destroy", "ert_vie_strerror",
-                 "ert_vie_fft_precond", "ert_vie_fft_info", "ert_vie_transport", "ert_net_create", "ert_net_forward", "ert_net_grad", "ert_net_train_step", "ert_net_destroy"):
+                 "ert_vie_fft_precond", "ert_vie_fft_info", "ert_vie_transport", "ert_vie_diff_precond", "ert_net_create", "ert_net_forward", "ert_net_grad", "ert_net_train_step", "ert_net_destroy"):
         assert must in names
 
 
@@ -41,6 +41,7 @@ def test_strerror_and_null_plan_without_gpu():
     assert L.ert_vie_fft_precond(None, None, None, 1) == ertvie.EINVAL
     assert L.ert_vie_fft_info(None, None) == ertvie.EINVAL
     assert L.ert_vie_transport(None, None, None, None, 1, None) == ertvie.EINVAL
+    assert L.ert_vie_diff_precond(None, None, None, 1) == ertvie.EINVAL
 
 
 def test_plan_rejects_bad_arguments_before_device_use():
