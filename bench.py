@@ -59,13 +59,14 @@ SVD_TOL = 1e-5
 # scaled by the readings of a 256 MiB device copy (profiles/near_m2l_c2_32cubed_fp32_hbm_traffic.md).
 # Keyed by (workload, precision, kernel, execution forms "near,far" the autotuner chose); a
 # combination without counters, or a kernel changed since they were taken, reports null.
-MEASURED_TRAFFIC = {("c2", "fp32", "near+m2l", "2,1"): 72.15e6, ("c2", "fp32", "near+m2l", "1,1"): 72.11e6}
+MEASURED_TRAFFIC = {("c2", "fp32", "near+m2l", "2,1"): 46.88e6}
 
 
 def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None, forms=None):
     """Roofline of the dominant box-offset product (M2L or near field) from its algorithmic work:
     M2L: 2 R^2 flops per far pair, bytes = translation matrices (one per box offset) + multipoles in
-    + locals out; near: 2 flops per point pair, bytes = the 3^d near blocks + charges in + potentials out."""
+    + locals out; near: 2 flops per point pair, bytes = the 3^d near blocks (or the offset table the
+    offset-stationary forms read in a homogeneous medium) + charges in + potentials out."""
     sz = SZ[prec]
     L = info["levels"]
     noff = 7 ** dim - 3 ** dim
@@ -78,7 +79,10 @@ def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None, forms=None
         m2l_bytes += (min(noff, pairs) * R * R + 2.0 * nbox * R) * sz
     S = info["leaf"] ** dim
     near_flops = 2.0 * info["near_pairs"]
-    near_bytes = (3 ** dim * S * S + 2.0 * info["leaf_boxes"] * S) * (8 if prec == "fp64" else 4)
+    # the offset-stationary forms of a homogeneous near field read one table over cell
+    # offsets instead of the 3^d explicit S x S blocks
+    near_ops = info["near_table"] if (info.get("near_table") and info.get("form_near", 0) >= 1) else 3 ** dim * S * S
+    near_bytes = (near_ops + 2.0 * info["leaf_boxes"] * S) * (8 if prec == "fp64" else 4)
     cand = {"m2l": (m2l_flops, m2l_bytes, stage_ms.get("m2l", 0.0), launches.get("m2l", 1.0), prec),
             "near": (near_flops, near_bytes, stage_ms.get("near", 0.0), launches.get("near", 1.0),
                      "fp64" if prec == "fp64" else "fp32")}

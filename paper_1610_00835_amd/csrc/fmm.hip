@@ -34,6 +34,7 @@ struct FmmData {
     virtual ~FmmData() {}
     virtual int rank_of(int l) const = 0;
     virtual int form_of(int site) const = 0;   // site -1: near field, l >= 0: far field of level l
+    virtual long near_table() const = 0;       // entries of the near-field offset table, 0 = none
     virtual ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) = 0;
     virtual ert_status setup(ert_plan_impl* p) = 0;
     FmmTree tr;
@@ -140,6 +141,181 @@ __global__ void k_assemble(DevTree t, const T* __restrict__ pot, const ApplyIO* 
     const double w = (op == ERT_OP_G) ? xj : ss[j] * xj;
     double v = hd * (double)pot[(long)b * t.nslot + slot] + diag[j] * w;
     y[i] = (op == ERT_OP_A) ? xj - v : v;
+}
+
+// One-level homogeneous apply, first kernel.  Workgroup (leaf, 64 rows of the
+// compressed multipole, rhs): the leaf's weighted charges go to LDS (and, from
+// the first row chunk, to q in leaf order for the near-field products), then
+// W = leaf_in q (leaf_in = Ut P, R x S) with one lane per row, read through the
+// transposed copy [S][R] so that a wave's loads are contiguous; the eight waves
+// take consecutive eighths of the S charges and their partial sums are added in
+// wave order.
+constexpr int kLeafWaves = 8;
+
+constexpr int kLeafMaxPairs = 64;    // pairs per target on a one-level tree (at most 4^3 boxes)
+
+template <typename T>
+__global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(DevTree t, const ApplyIO* __restrict__ io,
+                                                             const double* __restrict__ ss, long N,
+                                                             const T* __restrict__ linT, int R, int rch,
+                                                             T* __restrict__ q, T* __restrict__ W)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* part = (T*)smem;                          // [kLeafWaves][64]
+    T* sq = part + kLeafWaves * 64;              // [S]
+    const long leafi = blockIdx.x / rch;
+    const int chunk = (int)(blockIdx.x % rch);
+    const int b = blockIdx.y;
+    const double* x = io->x;
+    const int weighted = io->op != ERT_OP_G;
+    for (int li = threadIdx.x; li < t.S; li += blockDim.x) {
+        const long slot = leafi * t.S + li;
+        int c[3];
+        const long j = slot_cell(t, slot, c);
+        double v = 0.0;
+        if (j >= 0) v = weighted ? ss[j] * x[j + (long)b * N] : x[j + (long)b * N];
+        const T tv = T(v);
+        sq[li] = tv;
+        if (chunk == 0) q[(long)b * t.nslot + slot] = tv;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = chunk * 64 + lane;
+    const int per = (t.S + kLeafWaves - 1) / kLeafWaves;
+    const int k0 = wave * per, k1 = min(t.S, k0 + per);
+    T acc = T(0);
+    if (r < R) {
+        const T* col = linT + r;
+        int k = k0;
+        for (; k + 16 <= k1; k += 16) {
+            T v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = col[(long)(k + u) * R];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u] * sq[k + u];
+        }
+        for (; k < k1; ++k) acc += col[(long)k * R] * sq[k];
+    }
+    part[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave != 0 || r >= R) return;
+    T s = part[lane];
+    for (int w = 1; w < kLeafWaves; ++w) s += part[w * 64 + lane];
+    W[((long)b * t.nleaf + leafi) * R + r] = s;
+}
+
+// sum over k in [k0, k1) of St[tp[k] * M], in order, eight loads in flight
+template <typename T>
+__device__ __forceinline__ T staged_sum(const T* __restrict__ St, int M, const int* tp, int k0, int k1)
+{
+    T s = T(0);
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = St[(long)tp[k + u] * M];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k < k1; ++k) s += St[(long)tp[k] * M];
+    return s;
+}
+
+// One-level homogeneous apply, last kernel.  Workgroup (leaf, 64 cells of the
+// leaf, rhs): the leaf's far-field local expansion is the sum of its staged
+// translation products (the pair list cut into as many consecutive parts as
+// the workgroup holds copies of the rank, parts added in order); each lane owns
+// one cell, whose potential is the sum of its staged near-field products plus
+// the expansion with L2P (leaf_out = P^T Um, S x R, read through the transposed
+// copy [R][S]).  The eight waves take consecutive eighths of the near pairs and
+// of the rank, partial sums are added in wave order, and wave 0 assembles
+// y = h^d pot + A_jj w (op A: x - y) in the natural cell order.
+template <typename T>
+__global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
+    DevTree t, const ApplyIO* __restrict__ io, const double* __restrict__ ss, const double* __restrict__ diag,
+    double hd, long N, const T* __restrict__ stn, const int* __restrict__ tsn, const int* __restrict__ tpn, long npn,
+    const T* __restrict__ stf, const int* __restrict__ tsf, const int* __restrict__ tpf, long npf, int R,
+    const T* __restrict__ loutT, int sch)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int pl_n[kLeafMaxPairs], pl_f[kLeafMaxPairs];
+    T* pn = (T*)smem;                            // [kLeafWaves][64] near partial sums
+    T* pf = pn + kLeafWaves * 64;                // [kLeafWaves][64] L2P partial sums
+    T* sl = pf + kLeafWaves * 64;                // [R] far-field local expansion
+    T* fpart = sl + R;                           // [G][R] far partial sums
+    const long leafi = blockIdx.x / sch;
+    const int chunk = (int)(blockIdx.x % sch);
+    const int b = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = chunk * 64 + lane;
+    const bool ok = li < t.S;
+    const int n0 = tsn[leafi], nn = tsn[leafi + 1] - n0;
+    const int f0 = tsf[leafi], nf = tsf[leafi + 1] - f0;
+    if (threadIdx.x < nn) pl_n[threadIdx.x] = tpn[n0 + threadIdx.x];
+    if (threadIdx.x < nf) pl_f[threadIdx.x] = tpf[f0 + threadIdx.x];
+    // the assembly's operands, loaded early
+    int c[3];
+    long j = -1;
+    double xj = 0.0, sj = 0.0, dj = 0.0;
+    if (wave == 0 && ok) {
+        j = slot_cell(t, leafi * t.S + li, c);
+        if (j >= 0) {
+            xj = io->x[j + (long)b * N];
+            sj = ss[j];
+            dj = diag[j];
+        }
+    }
+    __syncthreads();
+    const int G = (int)blockDim.x / R;           // copies of the rank in the workgroup (>= 1)
+    {
+        const int g = (int)threadIdx.x / R, r = (int)threadIdx.x - g * R;
+        const int per = (nf + G - 1) / G;
+        if (g < G) {
+            const int a0 = min(nf, g * per), a1 = min(nf, a0 + per);
+            fpart[g * R + r] = staged_sum(stf + (long)b * npf * R + r, R, pl_f, a0, a1);
+        }
+    }
+    {
+        const int per = (nn + kLeafWaves - 1) / kLeafWaves;
+        const int a0 = min(nn, wave * per), a1 = min(nn, a0 + per);
+        pn[wave * 64 + lane] = ok ? staged_sum(stn + (long)b * npn * t.S + li, t.S, pl_n, a0, a1) : T(0);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        T v = fpart[r];
+        for (int g = 1; g < G; ++g) v += fpart[g * R + r];
+        sl[r] = v;
+    }
+    __syncthreads();
+    {
+        const int per = (R + kLeafWaves - 1) / kLeafWaves;
+        const int r0 = min(R, wave * per), r1 = min(R, r0 + per);
+        T acc = T(0);
+        if (ok) {
+            const T* col = loutT + li;
+            int r = r0;
+            for (; r + 16 <= r1; r += 16) {
+                T v[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = col[(long)(r + u) * t.S];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc += v[u] * sl[r + u];
+            }
+            for (; r < r1; ++r) acc += col[(long)r * t.S] * sl[r];
+        }
+        pf[wave * 64 + lane] = acc;
+    }
+    __syncthreads();
+    if (wave != 0 || j < 0) return;
+    T near = pn[lane], far = pf[lane];
+    for (int w = 1; w < kLeafWaves; ++w) {
+        near += pn[w * 64 + lane];
+        far += pf[w * 64 + lane];
+    }
+    const int op = io->op;
+    const double w = (op == ERT_OP_G) ? xj : sj * xj;
+    const double v = hd * (double)(near + far) + dj * w;
+    io->y[j + (long)b * N] = (op == ERT_OP_A) ? xj - v : v;
 }
 
 template <typename T>
@@ -534,6 +710,43 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, i
 }
 
 
+// Near-field coupling of two cells of a homogeneous medium at cell offset dv
+// (zero for the self pair, whose term is the diagonal's).
+__device__ __forceinline__ double near_value(int D, const int dv[3], double h, double sigma, int mii)
+{
+    const int K = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+    if (K == 0) return 0.0;
+    const double r = h * sqrt((double)K);
+    if (mii) {
+        const double hp = (D == 2) ? h : h * h;
+        return exp(-sigma * r) * cell_int(D, dv[0], dv[1], dv[2]) / (surface_area(D) * hp);
+    }
+    const double rp = (D == 2) ? r : r * r;
+    return exp(-sigma * r) / (surface_area(D) * rp);
+}
+
+// The same values over all cell offsets of neighbouring leaves, d_a in
+// [-(2 leaf - 1), 2 leaf - 1], index sum_a (d_a + 2 leaf - 1) W^a with
+// W = 4 leaf - 1, as four copies: copy r holds entry i + r at position i (zero
+// past the end), so that any four consecutive entries are one aligned vector
+// of some copy.
+template <typename T>
+__global__ void k_near_tab(int D, int leaf, double h, double sigma, int mii, int tlen, T* __restrict__ tab)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= 4L * tlen) return;
+    const int r = (int)(i / tlen);
+    const long e = i - (long)r * tlen + r;          // table entry
+    const int W = 4 * leaf - 1, c = 2 * leaf - 1;
+    const long n = (D == 3) ? (long)W * W * W : (long)W * W;
+    double v = 0.0;
+    if (e < n) {
+        const int dv[3] = {(int)(e % W) - c, (int)((e / W) % W) - c, D == 3 ? (int)(e / ((long)W * W)) - c : 0};
+        v = near_value(D, dv, h, sigma, mii);
+    }
+    tab[i] = T(v);
+}
+
 // Near-field blocks of a homogeneous medium: on a uniform grid the block
 // between a target leaf and its neighbour at leaf offset o depends only on o.
 // ops[o][target i][source i] = G, zero for the self pair.
@@ -551,24 +764,9 @@ __global__ void k_near_ops(int D, int leaf, int S, double h, double sigma, T* __
     int ls1 = D > 1 ? leaf : 1;
     int lt[3] = {it % leaf, (it / leaf) % ls1, it / (leaf * ls1)};
     int lsr[3] = {is % leaf, (is / leaf) % ls1, is / (leaf * ls1)};
-    int K = 0, dv[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) {
-        int d = o[a] * leaf + lsr[a] - lt[a];
-        dv[a] = d;
-        K += d * d;
-    }
-    double v = 0.0;
-    if (K > 0) {
-        double r = h * sqrt((double)K);
-        if (mii) {
-            const double hp = (D == 2) ? h : h * h;
-            v = exp(-sigma * r) * cell_int(D, dv[0], dv[1], dv[2]) / (surface_area(D) * hp);
-        } else {
-            double rp = (D == 2) ? r : r * r;
-            v = exp(-sigma * r) / (surface_area(D) * rp);
-        }
-    }
-    ops[i] = T(v);
+    int dv[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) dv[a] = o[a] * leaf + lsr[a] - lt[a];
+    ops[i] = T(near_value(D, dv, h, sigma, mii));
 }
 
 // Batched FP64 GEMM with B transposed, for plan-time work:
@@ -839,8 +1037,12 @@ struct FmmImpl : FmmData {
     // expansion and L2P into one [S][rp] matrix (each applied as one GEMM).
     T* leaf_in = nullptr;               // [rp][S] = Ut P
     T* leaf_out = nullptr;              // [S][rp] = P^T Um
+    T* leaf_inT = nullptr;              // [S][rp], leaf_in transposed
+    T* leaf_outT = nullptr;             // [rp][S], leaf_out transposed
     HetCache* hc = nullptr;             // heterogeneous caches (owned by the plan)
     T* nearops = nullptr;               // homogeneous near blocks [3^d][S][S]
+    T* neartab = nullptr;               // the same values over cell offsets, [4][near_tlen]
+    int near_tlen = 0;
     T* tab = nullptr;                   // homogeneous near table (S not a multiple of 32)
     int ntab = 0;
     T* q = nullptr;
@@ -872,7 +1074,7 @@ struct FmmImpl : FmmData {
     ~FmmImpl() override
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(tab); f(q); f(pot); f(leaf_in); f(leaf_out);
+        f(P1); f(M1); f(cheb); f(m2l_offs); f(near_offs); f(id_off); f(nearops); f(neartab); f(tab); f(q); f(pot); f(leaf_in); f(leaf_out); f(leaf_inT); f(leaf_outT);
         for (int l = 0; l <= kMaxLevels; ++l) {
             f(ops[l]); f(ops_lo[l]); f(Ut[l]); f(Um[l]);
             f(W[l]); f(Lc[l]); f(Wc[l]); f(Lh[l]);
@@ -906,6 +1108,13 @@ struct FmmImpl : FmmData {
         o.tn = form >= 2 ? 4 : 1;
         o.tm = form == 3 ? 1 : 2;
         o.pl = gs.pl;
+        if (&gs == &near_site && neartab && b.ops == nearops) {
+            o.atab = neartab;
+            o.tlen = near_tlen;
+            o.tw = 4 * tr.leaf - 1;
+            o.leaf = tr.leaf;
+            o.dim = tr.D;
+        }
         return o;
     }
     ert_status enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs);
@@ -922,6 +1131,11 @@ struct FmmImpl : FmmData {
     }
 
     int rank_of(int l) const override { return rp[l]; }
+    long near_table() const override
+    {
+        const long W = 4L * tr.leaf - 1;
+        return neartab ? (tr.D == 3 ? W * W * W : W * W) : 0;
+    }
     int form_of(int site) const override
     {
         const GemmSite& gs = site < 0 ? near_site : far_site[site];
@@ -933,6 +1147,15 @@ struct FmmImpl : FmmData {
     ert_status ensure_buffers(int nrhs);
     hipStream_t p_stream = nullptr;
     ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) override;
+
+    // one-level homogeneous trees whose tuned near and far products are both
+    // offset-stationary run as three fused launches
+    bool grouped_form(int bk) const
+    {
+        return !hetero && leaf_inT && leaf_outT && nearops && tr.L == 2 && tr.nbox[2] <= kLeafMaxPairs &&
+               rp[2] <= 64 * kLeafWaves && near_site.used && far_site[2].used &&
+               near_site.choice[bk] >= 1 && far_site[2].choice[bk] >= 1;
+    }
 
     BoxGemm gemm_desc(int l, int Mrows, int Kd, int nrhs) const
     {
@@ -1079,6 +1302,15 @@ ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
             }
             ERT_TRY(upload_cvt<T>(s, &leaf_in, fin));
             ERT_TRY(upload_cvt<T>(s, &leaf_out, fout));
+            // transposed copies for the fused one-level apply (lanes over outputs)
+            std::vector<double> tin((size_t)S * R), tout((size_t)R * S);
+            for (int c = 0; c < R; ++c)
+                for (int j = 0; j < S; ++j) {
+                    tin[(size_t)j * R + c] = fin[(size_t)c * S + j];
+                    tout[(size_t)c * S + j] = fout[(size_t)j * R + c];
+                }
+            ERT_TRY(upload_cvt<T>(s, &leaf_inT, tin));
+            ERT_TRY(upload_cvt<T>(s, &leaf_outT, tout));
         }
         Cd = C64;
         M = R;
@@ -1342,6 +1574,15 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
             hipLaunchKernelGGL(k_near_ops<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, leaf, tr.S, h, sigma, nearops,
                                p->o.scheme);
             ERT_HIP(hipGetLastError());
+            if (leaf % 4 == 0) {
+                const int W = 4 * leaf - 1;
+                const long ne = (tr.D == 3) ? (long)W * W * W : (long)W * W;
+                near_tlen = (int)((ne + 3 + 3) / 4 * 4);
+                ERT_HIP(hipMalloc(&neartab, 4L * near_tlen * sizeof(T)));
+                hipLaunchKernelGGL(k_near_tab<T>, dim3(blocks(4L * near_tlen)), dim3(kB), 0, s, tr.D, leaf, h, sigma,
+                                   p->o.scheme, near_tlen, neartab);
+                ERT_HIP(hipGetLastError());
+            }
         } else {
             if (p->o.scheme != 0) {
                 record_error("FMM: approach (M-ii) in homogeneous media needs leaf^dim to be a multiple of 32");
@@ -1514,16 +1755,12 @@ ert_status FmmImpl<T>::enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs
     const int dprec = (prec == ERT_FP64) ? ERT_FP64 : ERT_FP32;
     Profiler* pf = &p->prof;
     {
+        // weighted charges into leaf order and P2M with the compression, one kernel
         StageTimer st_(pf, s, ERT_STAGE_GATHER);
-        hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, io, p->d_ss, N, nrhs, q);
+        const int rch = (R + 63) / 64;
+        hipLaunchKernelGGL(k_leaf_in<T>, dim3((unsigned)(tr.nbox[L] * rch), (unsigned)nrhs), dim3(64 * kLeafWaves),
+                           (kLeafWaves * 64 + tr.S) * sizeof(T), s, dt, io, p->d_ss, N, leaf_inT, R, rch, q, Wc[L]);
         ERT_HIP(hipGetLastError());
-    }
-    {
-        StageTimer st_(pf, s, ERT_STAGE_P2M);
-        BoxGemm c = gemm_desc(L, R, tr.S, nrhs);
-        c.stride = 1; c.nclass = 1; c.noff = 1; c.offs = id_off;
-        c.ops = leaf_in; c.W = q; c.L = Wc[L]; c.accumulate = 0;
-        ERT_TRY(box_gemm(s, dprec, c));
     }
     BoxGemm gn = gemm_desc(L, tr.S, tr.S, nrhs);
     gn.stride = 1; gn.nclass = 1; gn.noff = nn; gn.offs = near_offs;
@@ -1545,21 +1782,15 @@ ert_status FmmImpl<T>::enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs
             ERT_TRY(offset_gemm_products(s, prec, of));
         }
     }
-    {
-        StageTimer st_(pf, s, ERT_STAGE_REDUCE);
-        ERT_TRY(offset_gemm_pair_reduce(s, dprec, on, of));
-    }
-    {
-        StageTimer st_(pf, s, ERT_STAGE_L2P);
-        BoxGemm u = gemm_desc(L, tr.S, R, nrhs);
-        u.stride = 1; u.nclass = 1; u.noff = 1; u.offs = id_off;
-        u.ops = leaf_out; u.W = Lh[L]; u.L = pot; u.accumulate = 1;
-        ERT_TRY(box_gemm(s, dprec, u));
-    }
+    // sums of the staged products, expansion with L2P and assembly, one kernel
     const double hd = std::pow(p->geo.h, tr.D);
     StageTimer st_(pf, s, ERT_STAGE_ASSEMBLE);
-    hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, io, p->d_ss, p->d_diag, hd, N,
-                       nrhs);
+    const int sch = (tr.S + 63) / 64;
+    hipLaunchKernelGGL(k_leaf_out<T>, dim3((unsigned)(tr.nbox[L] * sch), (unsigned)nrhs), dim3(64 * kLeafWaves),
+                       (2 * kLeafWaves * 64 + R + (64 * kLeafWaves / R) * R) * sizeof(T), s, dt, io, p->d_ss,
+                       p->d_diag, hd, N,
+                       (const T*)on.stage, on.pl.tstart, on.pl.tpairs, on.pl.npairs, (const T*)of.stage,
+                       of.pl.tstart, of.pl.tpairs, of.pl.npairs, R, leaf_outT, sch);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }
@@ -1569,9 +1800,7 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
 {
     {
         const int bk = nrhs > 1 ? 1 : 0;
-        if (!hetero && leaf_in && nearops && tr.L == 2 && tuned[bk] && near_site.used && far_site[2].used &&
-            near_site.choice[bk] >= 1 && far_site[2].choice[bk] >= 1)
-            return enqueue_grouped(p, s, nrhs);
+        if (grouped_form(bk)) return enqueue_grouped(p, s, nrhs);
     }
     const long N = p->N;
     const int nn = tr.D == 3 ? 27 : 9;
@@ -1752,11 +1981,17 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         ERT_HIP(hipStreamWaitEvent(s, ev_join, 0));
     }
     // a11: scale, self term, operator
-    const double hd = std::pow(p->geo.h, tr.D);
-    StageTimer st_(pf, s, ERT_STAGE_ASSEMBLE);
-    hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, io, p->d_ss, p->d_diag, hd, N,
-                       nrhs);
-    ERT_HIP(hipGetLastError());
+    {
+        const double hd = std::pow(p->geo.h, tr.D);
+        StageTimer st_(pf, s, ERT_STAGE_ASSEMBLE);
+        hipLaunchKernelGGL(k_assemble<T>, dim3(blocks(N * nrhs)), dim3(kB), 0, s, dt, pot, io, p->d_ss, p->d_diag,
+                           hd, N, nrhs);
+        ERT_HIP(hipGetLastError());
+    }
+    // this call chose the forms and they make the fused one-level apply, which sums
+    // in another order: recompute with it (x and y do not overlap) so that every
+    // call of the bucket, eager or replayed, returns the same bits
+    if (grouped_form(nrhs > 1 ? 1 : 0)) return enqueue_grouped(p, s, nrhs);
     return ERT_OK;
 }
 
@@ -1862,6 +2097,7 @@ ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info)
     info->nodes_padded = t.Kp;
     for (int l = 0; l <= t.L && l < 16; ++l) info->rank[l] = f->rank_of(l);
     info->form_near = f->form_of(-1);
+    info->near_table = f->near_table();
     for (int l = 0; l < 16; ++l) info->form_far[l] = (l <= t.L && l >= 2) ? f->form_of(l) : -1;
     // interaction-list pairs per level (separable per axis) and near point pairs
     for (int l = 2; l <= t.L && l < 16; ++l) {

@@ -95,6 +95,12 @@ struct OffsetGemm {
     int tn;                   // column blocks of 16 per workgroup: 1 or 4
     int tm;                   // row blocks of 16 per wave: 2 or 1 (with tn = 4)
     PairTiles pl;
+    // operator from a table over cell offsets instead of ops (the near field of a
+    // homogeneous medium; FP32/FP64, leaf a multiple of 4): four copies of the
+    // table, copy r shifted by r entries, each tlen long; tw = 4 leaf - 1 entries
+    // per axis
+    const void* atab = nullptr;
+    int tlen = 0, tw = 0, leaf = 0, dim = 0;
 };
 
 ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);           // products + reduction

@@ -148,6 +148,57 @@ __device__ __forceinline__ void tile_reduce(const void* ops, const void* ops_lo,
     }
 }
 
+// Operator read from a table over cell offsets (the near field of a homogeneous
+// medium on a uniform grid: the block entry of target cell t and source cell s
+// at leaf offset o depends only on o leaf + s - t).  The table index of entry
+// (t, s) is tb(t) + lin(s), lin(c) = c0 + W c1 + W^2 c2; a lane's four
+// consecutive reduction indices lie on one grid line (leaf a multiple of 4), so
+// they are four consecutive table entries, read as one aligned vector from the
+// copy of the table shifted by the index modulo 4.
+__device__ __forceinline__ int tab_lin(const OffsetGemm& g, int c)
+{
+    const int l = g.leaf;
+    if (g.dim == 2) return c % l + g.tw * (c / l);
+    return c % l + g.tw * ((c / l) % l) + g.tw * g.tw * (c / (l * l));
+}
+
+template <int PREC, int TM, int TN>
+__device__ __forceinline__ void frag_load_tab(Frag<PREC, TM, TN>& f, const OffsetGemm& g, const int (&tb)[TM],
+                                              int kl, const typename Acc<PREC>::T* const bp[TN], int kk)
+{
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    const int ls = tab_lin(g, kk + kl);
+    const T* tab = (const T*)g.atab;
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) {
+        const int idx = tb[tm] + ls;
+        const int r = idx & 3;
+        f.a[tm] = *(const V*)(tab + r * g.tlen + (idx - r));
+    }
+#pragma unroll
+    for (int tn = 0; tn < TN; ++tn) f.b[tn] = bp[tn] ? *(const V*)(bp[tn] + kk) : V{0, 0, 0, 0};
+}
+
+template <int PREC, int TM, int TN>
+__device__ __forceinline__ void tile_reduce_tab(const OffsetGemm& g, const int (&tb)[TM], int kl,
+                                                const typename Acc<PREC>::T* const bp[TN], int wave,
+                                                typename Acc<PREC>::V (&acc)[TM][TN])
+{
+    constexpr int CW = 16;
+    constexpr int U = (PREC == ERT_FP32) ? 4 : 2;
+    constexpr int STEP = kWaves * CW;
+    for (int k0 = wave * CW; k0 < g.Kd; k0 += U * STEP) {
+        Frag<PREC, TM, TN> f[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * STEP < g.Kd) frag_load_tab<PREC, TM, TN>(f[u], g, tb, kl, bp, k0 + u * STEP);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * STEP < g.Kd) frag_mma<PREC, TM, TN>(f[u], acc);
+    }
+}
+
 template <int PREC, int TM, int TN>
 __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_tiles)
 {
@@ -260,7 +311,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_box_gemm(BoxGemm g, int row_til
 // ---------------------------------------------------- offset-stationary ----
 
 // One tile (column tile `tile`, row tile `rtile`) of an offset-stationary product.
-template <int PREC, int TM, int TN>
+template <int PREC, int TM, int TN, bool TAB = false>
 __device__ __forceinline__ void offset_tile(const OffsetGemm& g, long tile, int rtile)
 {
     typedef typename Acc<PREC>::V V;
@@ -291,8 +342,19 @@ __device__ __forceinline__ void offset_tile(const OffsetGemm& g, long tile, int 
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = V{0, 0, 0, 0};
-    const long abase = ((long)op * g.M + row0 + (lane & 15)) * g.Kd + LG * grp;
-    tile_reduce<PREC, TM, TN>(g.ops, g.ops_lo, abase, (long)16 * g.Kd, g.Kd, bp, wave, acc);
+    if constexpr (TAB) {
+        // op = (o0 + 1) + 3 (o1 + 1) + 9 (o2 + 1): the leaf offset of the group
+        const int o0 = op % 3 - 1, o1 = (op / 3) % 3 - 1, o2 = g.dim == 3 ? op / 9 - 1 : 0;
+        const int c = 2 * g.leaf - 1;
+        const int base = (c + g.leaf * o0) + g.tw * (c + g.leaf * o1) + g.tw * g.tw * (g.dim == 3 ? c + g.leaf * o2 : 0);
+        int tb[TM];
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) tb[tm] = base - tab_lin(g, row0 + 16 * tm + (lane & 15));
+        tile_reduce_tab<PREC, TM, TN>(g, tb, LG * grp, bp, wave, acc);
+    } else {
+        const long abase = ((long)op * g.M + row0 + (lane & 15)) * g.Kd + LG * grp;
+        tile_reduce<PREC, TM, TN>(g.ops, g.ops_lo, abase, (long)16 * g.Kd, g.Kd, bp, wave, acc);
+    }
     if (wave > 0) {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
@@ -319,21 +381,21 @@ __device__ __forceinline__ void offset_tile(const OffsetGemm& g, long tile, int 
         }
 }
 
-template <int PREC, int TM, int TN>
+template <int PREC, int TM, int TN, bool TAB = false>
 __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm(OffsetGemm g)
 {
-    offset_tile<PREC, TM, TN>(g, blockIdx.x, blockIdx.y);
+    offset_tile<PREC, TM, TN, TAB>(g, blockIdx.x, blockIdx.y);
 }
 
 // Two independent offset-stationary products in one launch (the near field and the
 // far-field translations of a one-level tree): blocks [0, na) belong to the first.
-template <int PREC, int TMA, int TNA, int TMB, int TNB>
+template <int PREC, int TMA, int TNA, int TMB, int TNB, bool TABA = false>
 __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm2(OffsetGemm a, int rows_a, long na, OffsetGemm b,
                                                               int rows_b)
 {
     const long bid = blockIdx.x;
     if (bid < na)
-        offset_tile<PREC, TMA, TNA>(a, bid / rows_a, (int)(bid % rows_a));
+        offset_tile<PREC, TMA, TNA, TABA>(a, bid / rows_a, (int)(bid % rows_a));
     else
         offset_tile<PREC, TMB, TNB>(b, (bid - na) / rows_b, (int)((bid - na) % rows_b));
 }
@@ -739,7 +801,9 @@ ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
             const int tm = g.tm == 1 ? 1 : kTM;
             dim3 grid((unsigned)g.pl.ntiles4, (unsigned)(g.M / (16 * tm)));
 #define ERT_OFF4(TM_)                                                                                   \
-    if (prec == ERT_FP64) hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4); \
+    if (prec == ERT_FP64 && g.atab) hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, TM_, 4, true>), grid, dim3(64 * kWaves), 0, s, g4); \
+    else if (prec == ERT_FP32 && g.atab) hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, TM_, 4, true>), grid, dim3(64 * kWaves), 0, s, g4); \
+    else if (prec == ERT_FP64) hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4); \
     else if (prec == ERT_FP32) hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4); \
     else hipLaunchKernelGGL((k_offset_gemm<ERT_BF16X3, TM_, 4>), grid, dim3(64 * kWaves), 0, s, g4);
             if (tm == 1) {
@@ -752,7 +816,11 @@ ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
         }
     } else if (g.pl.ntiles > 0) {
         dim3 grid((unsigned)g.pl.ntiles, (unsigned)(g.M / (16 * kTM)));
-        if (prec == ERT_FP64)
+        if (prec == ERT_FP64 && g.atab)
+            hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, kTM, 1, true>), grid, dim3(64 * kWaves), 0, s, g);
+        else if (prec == ERT_FP32 && g.atab)
+            hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, kTM, 1, true>), grid, dim3(64 * kWaves), 0, s, g);
+        else if (prec == ERT_FP64)
             hipLaunchKernelGGL((k_offset_gemm<ERT_FP64, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);
         else if (prec == ERT_FP32)
             hipLaunchKernelGGL((k_offset_gemm<ERT_FP32, kTM, 1>), grid, dim3(64 * kWaves), 0, s, g);
@@ -791,23 +859,40 @@ OffsetGemm with_form(const OffsetGemm& g, int* rows, long* nblk)
     return o;
 }
 
-template <int PREC, int TMA, int TNA>
+template <int PREC, int TMA, int TNA, bool TABA>
 void launch_pair_b(hipStream_t s, const OffsetGemm& a, int ra, long na, const OffsetGemm& b, int rb, long nb,
                    int fb)
 {
     const dim3 grid((unsigned)(na + nb)), blk(64 * kWaves);
-    if (fb == 1) hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, kTM, 1>), grid, blk, 0, s, a, ra, na, b, rb);
-    else if (fb == 2) hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, kTM, 4>), grid, blk, 0, s, a, ra, na, b, rb);
-    else hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, 1, 4>), grid, blk, 0, s, a, ra, na, b, rb);
+    if (fb == 1)
+        hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, kTM, 1, TABA>), grid, blk, 0, s, a, ra, na, b, rb);
+    else if (fb == 2)
+        hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, kTM, 4, TABA>), grid, blk, 0, s, a, ra, na, b, rb);
+    else
+        hipLaunchKernelGGL((k_offset_gemm2<PREC, TMA, TNA, 1, 4, TABA>), grid, blk, 0, s, a, ra, na, b, rb);
 }
 
+template <int PREC, bool TABA>
+void launch_pair_a(hipStream_t s, const OffsetGemm& a, int ra, long na, int fa, const OffsetGemm& b, int rb, long nb,
+                   int fb)
+{
+    if (fa == 1) launch_pair_b<PREC, kTM, 1, TABA>(s, a, ra, na, b, rb, nb, fb);
+    else if (fa == 2) launch_pair_b<PREC, kTM, 4, TABA>(s, a, ra, na, b, rb, nb, fb);
+    else launch_pair_b<PREC, 1, 4, TABA>(s, a, ra, na, b, rb, nb, fb);
+}
+
+// the first product may read its operator from an offset table (FP32/FP64)
 template <int PREC>
 void launch_pair(hipStream_t s, const OffsetGemm& a, int ra, long na, int fa, const OffsetGemm& b, int rb, long nb,
                  int fb)
 {
-    if (fa == 1) launch_pair_b<PREC, kTM, 1>(s, a, ra, na, b, rb, nb, fb);
-    else if (fa == 2) launch_pair_b<PREC, kTM, 4>(s, a, ra, na, b, rb, nb, fb);
-    else launch_pair_b<PREC, 1, 4>(s, a, ra, na, b, rb, nb, fb);
+    if constexpr (PREC != ERT_BF16X3) {
+        if (a.atab) {
+            launch_pair_a<PREC, true>(s, a, ra, na, fa, b, rb, nb, fb);
+            return;
+        }
+    }
+    launch_pair_a<PREC, false>(s, a, ra, na, fa, b, rb, nb, fb);
 }
 
 int form_of(const OffsetGemm& g) { return g.tn == 4 ? (g.tm == 1 ? 3 : 2) : 1; }
@@ -821,6 +906,10 @@ ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& 
             record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
             return ERT_EINVAL;
         }
+    if (b.atab || (a.atab && prec == ERT_BF16X3)) {
+        record_error("offset_gemm: only the first product of a pair, in FP32/FP64, reads an offset table");
+        return ERT_EINVAL;
+    }
     int ra, rb;
     long na, nb;
     const OffsetGemm ga = with_form(a, &ra, &na), gb = with_form(b, &rb, &nb);

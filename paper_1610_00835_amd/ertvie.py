@@ -64,7 +64,7 @@ class FmmInfo(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("leaf", ctypes.c_int), ("cheb_n", ctypes.c_int),
                 ("nodes", ctypes.c_int), ("nodes_padded", ctypes.c_int), ("rank", ctypes.c_int * 16),
                 ("far_pairs", ctypes.c_long * 16), ("near_pairs", ctypes.c_long), ("form_near", ctypes.c_int),
-                ("form_far", ctypes.c_int * 16)]
+                ("form_far", ctypes.c_int * 16), ("near_table", ctypes.c_long)]
 
 
 class FftInfo(ctypes.Structure):
@@ -321,7 +321,8 @@ class Plan:
         return {"levels": L, "leaf": inf.leaf, "cheb_n": inf.cheb_n, "nodes": inf.nodes,
                 "nodes_padded": inf.nodes_padded, "rank": [inf.rank[l] for l in range(L + 1)],
                 "far_pairs": [inf.far_pairs[l] for l in range(L + 1)], "near_pairs": inf.near_pairs,
-                "form_near": inf.form_near, "form_far": [inf.form_far[l] for l in range(L + 1)]}
+                "form_near": inf.form_near, "form_far": [inf.form_far[l] for l in range(L + 1)],
+                "near_table": inf.near_table}
 
     def diag(self):
         d = np.empty(self.N)
