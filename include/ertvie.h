@@ -309,7 +309,7 @@ typedef struct {
                              right-hand side: -1 not tuned yet / not a box-offset product,
                              0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64, 3 16x64 */
     int form_far[16];     /* per level: the same for the far-field translations */
-    long near_table;      /* homogeneous media, leaf a multiple of 4: the offset-stationary
+    long near_table;      /* homogeneous media, leaf a power of two >= 4: the offset-stationary
                              near-field products read one table of (4 leaf - 1)^dim values over
                              cell offsets (this count) instead of the 3^dim explicit blocks;
                              0 = no table */

@@ -163,8 +163,9 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(DevTree t, const Ap
     extern __shared__ __align__(16) unsigned char smem[];
     T* part = (T*)smem;                          // [kLeafWaves][64]
     T* sq = part + kLeafWaves * 64;              // [S]
-    const long leafi = blockIdx.x / rch;
-    const int chunk = (int)(blockIdx.x % rch);
+    const long pos = xcd_position(blockIdx.x, gridDim.x);
+    const long leafi = pos / rch;
+    const int chunk = (int)(pos % rch);
     const int b = blockIdx.y;
     const double* x = io->x;
     const int weighted = io->op != ERT_OP_G;
@@ -243,8 +244,9 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
     T* pf = pn + kLeafWaves * 64;                // [kLeafWaves][64] L2P partial sums
     T* sl = pf + kLeafWaves * 64;                // [R] far-field local expansion
     T* fpart = sl + R;                           // [G][R] far partial sums
-    const long leafi = blockIdx.x / sch;
-    const int chunk = (int)(blockIdx.x % sch);
+    const long pos = xcd_position(blockIdx.x, gridDim.x);
+    const long leafi = pos / sch;
+    const int chunk = (int)(pos % sch);
     const int b = blockIdx.y;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = chunk * 64 + lane;
@@ -1113,6 +1115,7 @@ struct FmmImpl : FmmData {
             o.tlen = near_tlen;
             o.tw = 4 * tr.leaf - 1;
             o.leaf = tr.leaf;
+            while ((1 << o.lshift) < tr.leaf) ++o.lshift;
             o.dim = tr.D;
         }
         return o;
@@ -1574,7 +1577,7 @@ ert_status FmmImpl<T>::setup(ert_plan_impl* p)
             hipLaunchKernelGGL(k_near_ops<T>, dim3(blocks(n)), dim3(kB), 0, s, tr.D, leaf, tr.S, h, sigma, nearops,
                                p->o.scheme);
             ERT_HIP(hipGetLastError());
-            if (leaf % 4 == 0) {
+            if (leaf >= 4 && (leaf & (leaf - 1)) == 0) {
                 const int W = 4 * leaf - 1;
                 const long ne = (tr.D == 3) ? (long)W * W * W : (long)W * W;
                 near_tlen = (int)((ne + 3 + 3) / 4 * 4);

@@ -82,6 +82,19 @@ struct PairTiles {
     int* tpairs = nullptr;    // [npairs]
 };
 
+// Workgroups are handed to the eight XCDs (each with its own L2) in turn by
+// linear id.  For the n workgroups with linear ids s + b, b in [0, n), this
+// bijection of [0, n) gives those that share an XCD consecutive positions, so
+// work items at consecutive positions share that XCD's L2.
+__device__ __forceinline__ long xcd_position(long b, long n, int s = 0)
+{
+    auto cnt = [](long x, int j) { return (x + 7 - j) >> 3; };   // t in [0, x) with t % 8 == j
+    const int k = (int)((b + s) & 7);
+    long p = cnt(b + s, k) - cnt(s, k);
+    for (int j = 0; j < k; ++j) p += cnt(s + n, j) - cnt(s, j);
+    return p;
+}
+
 struct OffsetGemm {
     long nbox;
     int B;
@@ -96,11 +109,11 @@ struct OffsetGemm {
     int tm;                   // row blocks of 16 per wave: 2 or 1 (with tn = 4)
     PairTiles pl;
     // operator from a table over cell offsets instead of ops (the near field of a
-    // homogeneous medium; FP32/FP64, leaf a multiple of 4): four copies of the
+    // homogeneous medium; FP32/FP64, leaf a power of two >= 4): four copies of the
     // table, copy r shifted by r entries, each tlen long; tw = 4 leaf - 1 entries
-    // per axis
+    // per axis; leaf = 2^lshift
     const void* atab = nullptr;
-    int tlen = 0, tw = 0, leaf = 0, dim = 0;
+    int tlen = 0, tw = 0, leaf = 0, lshift = 0, dim = 0;
 };
 
 ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);           // products + reduction

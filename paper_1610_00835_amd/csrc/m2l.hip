@@ -157,9 +157,9 @@ __device__ __forceinline__ void tile_reduce(const void* ops, const void* ops_lo,
 // copy of the table shifted by the index modulo 4.
 __device__ __forceinline__ int tab_lin(const OffsetGemm& g, int c)
 {
-    const int l = g.leaf;
-    if (g.dim == 2) return c % l + g.tw * (c / l);
-    return c % l + g.tw * ((c / l) % l) + g.tw * g.tw * (c / (l * l));
+    const int sh = g.lshift, m = (1 << sh) - 1;
+    if (g.dim == 2) return (c & m) + g.tw * (c >> sh);
+    return (c & m) + g.tw * ((c >> sh) & m) + g.tw * g.tw * (c >> (2 * sh));
 }
 
 template <int PREC, int TM, int TN>
@@ -393,11 +393,16 @@ template <int PREC, int TMA, int TNA, int TMB, int TNB, bool TABA = false>
 __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm2(OffsetGemm a, int rows_a, long na, OffsetGemm b,
                                                               int rows_b)
 {
+    // the row tiles of one column tile read the same source columns: keep them on one XCD
     const long bid = blockIdx.x;
-    if (bid < na)
-        offset_tile<PREC, TMA, TNA, TABA>(a, bid / rows_a, (int)(bid % rows_a));
-    else
-        offset_tile<PREC, TMB, TNB>(b, (bid - na) / rows_b, (int)((bid - na) % rows_b));
+    if (bid < na) {
+        const long p = xcd_position(bid, na);
+        offset_tile<PREC, TMA, TNA, TABA>(a, p / rows_a, (int)(p % rows_a));
+    } else {
+        const long nb = (long)gridDim.x - na;
+        const long p = xcd_position(bid - na, nb, (int)(na & 7));
+        offset_tile<PREC, TMB, TNB>(b, p / rows_b, (int)(p % rows_b));
+    }
 }
 
 // Per-target sums of the staged pair products, in a fixed order: one workgroup

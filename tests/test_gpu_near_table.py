@@ -1,5 +1,5 @@
 """Near-field products read from the offset table (homogeneous medium on a uniform grid,
-leaf a multiple of 4; Sec. 3.3's near field with the translation invariance of the
+leaf a power of two >= 4; Sec. 3.3's near field with the translation invariance of the
 kernel): every execution form, forced through ERT_VIE_FORM, against the oracle and
 against each other.
 
