@@ -88,21 +88,23 @@ struct ApplyIO {
     int pad;
 };
 
-__global__ void k_set_io(ApplyIO* io, const double* x, double* y, int op)
+// The first kernel of an apply receives the apply's vectors as an argument (the
+// argument of a replayed graph's root node is updated per call) and stores them
+// for the later kernels of the apply, which read them through io.
+__device__ __forceinline__ void store_io(const ApplyIO& a, ApplyIO* io)
 {
-    io->x = x;
-    io->y = y;
-    io->op = op;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *io = a;
 }
 
 template <typename T>
-__global__ void k_gather(DevTree t, const ApplyIO* __restrict__ io, const double* __restrict__ ss, long N, int B,
+__global__ void k_gather(ApplyIO a, ApplyIO* io, DevTree t, const double* __restrict__ ss, long N, int B,
                          T* __restrict__ q)
 {
+    store_io(a, io);
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= t.nslot * B) return;
-    const double* x = io->x;
-    const int weighted = io->op != ERT_OP_G;
+    const double* x = a.x;
+    const int weighted = a.op != ERT_OP_G;
     int b = (int)(i / t.nslot);
     long slot = i - (long)b * t.nslot;
     int c[3];
@@ -155,11 +157,12 @@ constexpr int kLeafWaves = 8;
 constexpr int kLeafMaxPairs = 64;    // pairs per target on a one-level tree (at most 4^3 boxes)
 
 template <typename T>
-__global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(DevTree t, const ApplyIO* __restrict__ io,
+__global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(ApplyIO a, ApplyIO* io, DevTree t,
                                                              const double* __restrict__ ss, long N,
                                                              const T* __restrict__ linT, int R, int rch,
                                                              T* __restrict__ q, T* __restrict__ W)
 {
+    store_io(a, io);
     extern __shared__ __align__(16) unsigned char smem[];
     T* part = (T*)smem;                          // [kLeafWaves][64]
     T* sq = part + kLeafWaves * 64;              // [S]
@@ -167,8 +170,8 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(DevTree t, const Ap
     const long leafi = pos / rch;
     const int chunk = (int)(pos % rch);
     const int b = blockIdx.y;
-    const double* x = io->x;
-    const int weighted = io->op != ERT_OP_G;
+    const double* x = a.x;
+    const int weighted = a.op != ERT_OP_G;
     for (int li = threadIdx.x; li < t.S; li += blockDim.x) {
         const long slot = leafi * t.S + li;
         int c[3];
@@ -1056,11 +1059,32 @@ struct FmmImpl : FmmData {
     GemmSite far_site[kMaxLevels + 1];  // far field of level l >= 2 (homogeneous)
     GemmSite near_site;                 // near field (homogeneous)
     ApplyIO* io = nullptr;              // device: vectors of the current apply
+    ApplyIO cur{};                      // host: vectors of the apply being enqueued
+    // the first kernel of an enqueued apply, with its arguments, so that the root node
+    // of a captured apply can be given the vectors of each replay
+    struct GatherArgs {
+        ApplyIO a; ApplyIO* io; DevTree t; const double* ss; long N; int B; T* q;
+    };
+    struct LeafInArgs {
+        ApplyIO a; ApplyIO* io; DevTree t; const double* ss; long N; const T* linT; int R; int rch; T* q; T* W;
+    };
+    struct FirstLaunch {
+        int kind = 0;                   // 1 k_gather, 2 k_leaf_in
+        const void* func = nullptr;
+        dim3 grid, block;
+        size_t shmem = 0;
+        GatherArgs g{};
+        LeafInArgs l{};
+    };
+    FirstLaunch first;                  // of the most recent enqueue
+    FirstLaunch gfirst[2];              // of the captured applies
+    hipGraphNode_t groot[2] = {};
     hipStream_t cap = nullptr;          // internal stream used only to capture graphs
     hipGraph_t graph[2] = {};           // captured applies, per rhs bucket (1, >1)
     hipGraphExec_t gexec[2] = {};
     int graph_nrhs[2] = {0, 0};
     int calls[2] = {0, 0};
+    bool no_graph[2] = {false, false};  // the captured apply had an unexpected root: run eagerly
     T* stage = nullptr;                 // staging rows of the far-field products
     T* stage_near = nullptr;            // staging rows of the near-field products (runs concurrently)
     size_t stage_near_elems = 0;
@@ -1121,6 +1145,7 @@ struct FmmImpl : FmmData {
         return o;
     }
     ert_status enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs);
+    ert_status set_root_args(int bucket);
     ert_status enqueue(ert_plan_impl* p, hipStream_t s, int nrhs);
     void drop_graphs()
     {
@@ -1130,6 +1155,7 @@ struct FmmImpl : FmmData {
             gexec[b] = nullptr;
             graph[b] = nullptr;
             graph_nrhs[b] = 0;
+            groot[b] = nullptr;
         }
     }
 
@@ -1761,8 +1787,15 @@ ert_status FmmImpl<T>::enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs
         // weighted charges into leaf order and P2M with the compression, one kernel
         StageTimer st_(pf, s, ERT_STAGE_GATHER);
         const int rch = (R + 63) / 64;
-        hipLaunchKernelGGL(k_leaf_in<T>, dim3((unsigned)(tr.nbox[L] * rch), (unsigned)nrhs), dim3(64 * kLeafWaves),
-                           (kLeafWaves * 64 + tr.S) * sizeof(T), s, dt, io, p->d_ss, N, leaf_inT, R, rch, q, Wc[L]);
+        first.kind = 2;
+        first.func = (const void*)k_leaf_in<T>;
+        first.grid = dim3((unsigned)(tr.nbox[L] * rch), (unsigned)nrhs);
+        first.block = dim3(64 * kLeafWaves);
+        first.shmem = (kLeafWaves * 64 + tr.S) * sizeof(T);
+        first.l = LeafInArgs{cur, io, dt, p->d_ss, N, leaf_inT, R, rch, q, Wc[L]};
+        const LeafInArgs& A = first.l;
+        hipLaunchKernelGGL(k_leaf_in<T>, first.grid, first.block, first.shmem, s, A.a, A.io, A.t, A.ss, A.N, A.linT,
+                           A.R, A.rch, A.q, A.W);
         ERT_HIP(hipGetLastError());
     }
     BoxGemm gn = gemm_desc(L, tr.S, tr.S, nrhs);
@@ -1812,7 +1845,14 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
     // a4: weights into leaf-major order
     {
         StageTimer st_(pf, s, ERT_STAGE_GATHER);
-        hipLaunchKernelGGL(k_gather<T>, dim3(blocks(tr.nslot * nrhs)), dim3(kB), 0, s, dt, io, p->d_ss, N, nrhs, q);
+        first.kind = 1;
+        first.func = (const void*)k_gather<T>;
+        first.grid = dim3(blocks(tr.nslot * nrhs));
+        first.block = dim3(kB);
+        first.shmem = 0;
+        first.g = GatherArgs{cur, io, dt, p->d_ss, N, nrhs, q};
+        const GatherArgs& A = first.g;
+        hipLaunchKernelGGL(k_gather<T>, first.grid, first.block, 0, s, A.a, A.io, A.t, A.ss, A.N, A.B, A.q);
         ERT_HIP(hipGetLastError());
     }
     // a10: near field (writes pot), on the side stream once the forms are tuned
@@ -2006,11 +2046,11 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
 {
     ERT_TRY(ensure_buffers(nrhs));
     hipStream_t s = p->stream;
-    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, s, io, x, y, op);
-    ERT_HIP(hipGetLastError());
+    cur = ApplyIO{x, y, op, 0};
     const int bucket = nrhs > 1 ? 1 : 0;
-    if (p->prof.on || !p->use_graphs) return enqueue(p, s, nrhs);
+    if (p->prof.on || !p->use_graphs || no_graph[bucket]) return enqueue(p, s, nrhs);
     if (gexec[bucket] && graph_nrhs[bucket] == nrhs) {
+        ERT_TRY(set_root_args(bucket));
         ERT_HIP(hipGraphLaunch(gexec[bucket], s));
         return ERT_OK;
     }
@@ -2039,6 +2079,23 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
         record_hip_error("hipStreamEndCapture", ce, __FILE__, __LINE__);
         return ERT_EDEVICE;
     }
+    // the root must be the recorded first kernel, whose vectors each replay replaces;
+    // otherwise this rhs bucket runs eagerly
+    hipGraphNode_t root = nullptr;
+    size_t nroot = 0;
+    bool root_ok = hipGraphGetRootNodes(g, nullptr, &nroot) == hipSuccess && nroot == 1;
+    if (root_ok) root_ok = hipGraphGetRootNodes(g, &root, &nroot) == hipSuccess && nroot == 1 && root;
+    if (root_ok) {
+        hipGraphNodeType ty;
+        hipKernelNodeParams kp{};
+        root_ok = hipGraphNodeGetType(root, &ty) == hipSuccess && ty == hipGraphNodeTypeKernel &&
+                  hipGraphKernelNodeGetParams(root, &kp) == hipSuccess && kp.func == first.func && first.kind != 0;
+    }
+    if (!root_ok) {
+        (void)hipGraphDestroy(g);
+        no_graph[bucket] = true;
+        return enqueue(p, s, nrhs);
+    }
     hipGraphExec_t ge = nullptr;
     hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
@@ -2049,7 +2106,36 @@ ert_status FmmImpl<T>::apply(ert_plan_impl* p, int op, const double* x, double* 
     graph[bucket] = g;
     gexec[bucket] = ge;
     graph_nrhs[bucket] = nrhs;
+    gfirst[bucket] = first;
+    groot[bucket] = root;
     ERT_HIP(hipGraphLaunch(ge, s));
+    return ERT_OK;
+}
+
+// Give the root kernel node of a captured apply the vectors of this call.
+template <typename T>
+ert_status FmmImpl<T>::set_root_args(int bucket)
+{
+    FirstLaunch& f = gfirst[bucket];
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(f.func);
+    kp.gridDim = f.grid;
+    kp.blockDim = f.block;
+    kp.sharedMemBytes = (unsigned int)f.shmem;
+    kp.extra = nullptr;
+    if (f.kind == 1) {
+        GatherArgs& A = f.g;
+        A.a = cur;
+        void* args[] = {&A.a, &A.io, &A.t, &A.ss, &A.N, &A.B, &A.q};
+        kp.kernelParams = args;
+        ERT_HIP(hipGraphExecKernelNodeSetParams(gexec[bucket], groot[bucket], &kp));
+    } else {
+        LeafInArgs& A = f.l;
+        A.a = cur;
+        void* args[] = {&A.a, &A.io, &A.t, &A.ss, &A.N, &A.linT, &A.R, &A.rch, &A.q, &A.W};
+        kp.kernelParams = args;
+        ERT_HIP(hipGraphExecKernelNodeSetParams(gexec[bucket], groot[bucket], &kp));
+    }
     return ERT_OK;
 }
 
