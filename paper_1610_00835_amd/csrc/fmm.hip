@@ -149,23 +149,24 @@ __global__ void k_assemble(DevTree t, const T* __restrict__ pot, const ApplyIO* 
 // compressed multipole, rhs): the leaf's weighted charges go to LDS (and, from
 // the first row chunk, to q in leaf order for the near-field products), then
 // W = leaf_in q (leaf_in = Ut P, R x S) with one lane per row, read through the
-// transposed copy [S][R] so that a wave's loads are contiguous; the eight waves
-// take consecutive eighths of the S charges and their partial sums are added in
-// wave order.
+// transposed copy [S][R] so that a wave's loads are contiguous; the sixteen
+// waves take consecutive sixteenths of the S charges and their partial sums are
+// added in wave order.
 constexpr int kLeafWaves = 8;
 
-constexpr int kLeafMaxPairs = 64;    // pairs per target on a one-level tree (at most 4^3 boxes)
+constexpr int kLeafMaxPairs = kPadPairs;   // pairs per target on a one-level tree (at most 4^3 boxes)
+constexpr int kLeafInWaves = 16;
 
 template <typename T>
-__global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(ApplyIO a, ApplyIO* io, DevTree t,
+__global__ __launch_bounds__(64 * kLeafInWaves) void k_leaf_in(ApplyIO a, ApplyIO* io, DevTree t,
                                                              const double* __restrict__ ss, long N,
                                                              const T* __restrict__ linT, int R, int rch,
                                                              T* __restrict__ q, T* __restrict__ W)
 {
     store_io(a, io);
     extern __shared__ __align__(16) unsigned char smem[];
-    T* part = (T*)smem;                          // [kLeafWaves][64]
-    T* sq = part + kLeafWaves * 64;              // [S]
+    T* part = (T*)smem;                          // [kLeafInWaves][64]
+    T* sq = part + kLeafInWaves * 64;              // [S]
     const long pos = xcd_position(blockIdx.x, gridDim.x);
     const long leafi = pos / rch;
     const int chunk = (int)(pos % rch);
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(ApplyIO a, ApplyIO*
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = chunk * 64 + lane;
-    const int per = (t.S + kLeafWaves - 1) / kLeafWaves;
+    const int per = (t.S + kLeafInWaves - 1) / kLeafInWaves;
     const int k0 = wave * per, k1 = min(t.S, k0 + per);
     T acc = T(0);
     if (r < R) {
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_in(ApplyIO a, ApplyIO*
     __syncthreads();
     if (wave != 0 || r >= R) return;
     T s = part[lane];
-    for (int w = 1; w < kLeafWaves; ++w) s += part[w * 64 + lane];
+    for (int w = 1; w < kLeafInWaves; ++w) s += part[w * 64 + lane];
     W[((long)b * t.nleaf + leafi) * R + r] = s;
 }
 
@@ -225,6 +226,21 @@ __device__ __forceinline__ T staged_sum(const T* __restrict__ St, int M, const i
     return s;
 }
 
+// The same sum with all loads in flight at once when the range holds at most MAXK.
+template <typename T, int MAXK>
+__device__ __forceinline__ T staged_sum_one(const T* __restrict__ St, int M, const int* tp, int k0, int k1)
+{
+    if (k1 - k0 > MAXK) return staged_sum(St, M, tp, k0, k1);
+    T v[MAXK];
+#pragma unroll
+    for (int u = 0; u < MAXK; ++u) v[u] = (k0 + u < k1) ? St[(long)tp[k0 + u] * M] : T(0);
+    T s = T(0);
+#pragma unroll
+    for (int u = 0; u < MAXK; ++u)
+        if (k0 + u < k1) s += v[u];
+    return s;
+}
+
 // One-level homogeneous apply, last kernel.  Workgroup (leaf, 64 cells of the
 // leaf, rhs): the leaf's far-field local expansion is the sum of its staged
 // translation products (the pair list cut into as many consecutive parts as
@@ -237,8 +253,8 @@ __device__ __forceinline__ T staged_sum(const T* __restrict__ St, int M, const i
 template <typename T>
 __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
     DevTree t, const ApplyIO* __restrict__ io, const double* __restrict__ ss, const double* __restrict__ diag,
-    double hd, long N, const T* __restrict__ stn, const int* __restrict__ tsn, const int* __restrict__ tpn, long npn,
-    const T* __restrict__ stf, const int* __restrict__ tsf, const int* __restrict__ tpf, long npf, int R,
+    double hd, long N, const T* __restrict__ stn, const int* __restrict__ tcn, const int* __restrict__ tpn, long npn,
+    const T* __restrict__ stf, const int* __restrict__ tcf, const int* __restrict__ tpf, long npf, int R,
     const T* __restrict__ loutT, int sch)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -254,10 +270,11 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = chunk * 64 + lane;
     const bool ok = li < t.S;
-    const int n0 = tsn[leafi], nn = tsn[leafi + 1] - n0;
-    const int f0 = tsf[leafi], nf = tsf[leafi + 1] - f0;
-    if (threadIdx.x < nn) pl_n[threadIdx.x] = tpn[n0 + threadIdx.x];
-    if (threadIdx.x < nf) pl_f[threadIdx.x] = tpf[f0 + threadIdx.x];
+    // pair lists padded to kLeafMaxPairs per target, and their lengths: one round of loads
+    const int nn = tcn[leafi], nf = tcf[leafi];
+    if (threadIdx.x < kLeafMaxPairs) pl_n[threadIdx.x] = tpn[leafi * kLeafMaxPairs + threadIdx.x];
+    else if (threadIdx.x < 2 * kLeafMaxPairs)
+        pl_f[threadIdx.x - kLeafMaxPairs] = tpf[leafi * kLeafMaxPairs + threadIdx.x - kLeafMaxPairs];
     // the assembly's operands, loaded early
     int c[3];
     long j = -1;
@@ -277,7 +294,7 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
         const int per = (nf + G - 1) / G;
         if (g < G) {
             const int a0 = min(nf, g * per), a1 = min(nf, a0 + per);
-            fpart[g * R + r] = staged_sum(stf + (long)b * npf * R + r, R, pl_f, a0, a1);
+            fpart[g * R + r] = staged_sum_one<T, 24>(stf + (long)b * npf * R + r, R, pl_f, a0, a1);
         }
     }
     {
@@ -935,7 +952,7 @@ struct GemmSite {
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
         f(pl.pt); f(pl.ps); f(pl.gstart); f(pl.gop); f(pl.tile_group); f(pl.tile_col0); f(pl.tstart); f(pl.tpairs);
-        f(pl.tile_group4); f(pl.tile_col04);
+        f(pl.tile_group4); f(pl.tile_col04); f(pl.tpad); f(pl.tcnt);
         pl = PairTiles();
     }
 };
@@ -990,6 +1007,15 @@ ert_status build_site(hipStream_t s, int D, const int nl[3], bool far, GemmSite&
     ERT_TRY(upload<int>(s, &site.pl.gop, gop));
     ERT_TRY(upload<int>(s, &site.pl.tstart, tstart));
     ERT_TRY(upload<int>(s, &site.pl.tpairs, tpairs));
+    if (nbox <= kPadPairs) {
+        std::vector<int> pad((size_t)nbox * kPadPairs, -1), cnt(nbox);
+        for (long t = 0; t < nbox; ++t) {
+            cnt[t] = tstart[t + 1] - tstart[t];
+            for (int k = 0; k < cnt[t]; ++k) pad[(size_t)t * kPadPairs + k] = tpairs[tstart[t] + k];
+        }
+        ERT_TRY(upload<int>(s, &site.pl.tpad, pad));
+        ERT_TRY(upload<int>(s, &site.pl.tcnt, cnt));
+    }
     site.used = true;
     return ERT_OK;
 }
@@ -1182,6 +1208,7 @@ struct FmmImpl : FmmData {
     bool grouped_form(int bk) const
     {
         return !hetero && leaf_inT && leaf_outT && nearops && tr.L == 2 && tr.nbox[2] <= kLeafMaxPairs &&
+               near_site.pl.tpad && far_site[2].pl.tpad &&
                rp[2] <= 64 * kLeafWaves && near_site.used && far_site[2].used &&
                near_site.choice[bk] >= 1 && far_site[2].choice[bk] >= 1;
     }
@@ -1790,8 +1817,8 @@ ert_status FmmImpl<T>::enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs
         first.kind = 2;
         first.func = (const void*)k_leaf_in<T>;
         first.grid = dim3((unsigned)(tr.nbox[L] * rch), (unsigned)nrhs);
-        first.block = dim3(64 * kLeafWaves);
-        first.shmem = (kLeafWaves * 64 + tr.S) * sizeof(T);
+        first.block = dim3(64 * kLeafInWaves);
+        first.shmem = (kLeafInWaves * 64 + tr.S) * sizeof(T);
         first.l = LeafInArgs{cur, io, dt, p->d_ss, N, leaf_inT, R, rch, q, Wc[L]};
         const LeafInArgs& A = first.l;
         hipLaunchKernelGGL(k_leaf_in<T>, first.grid, first.block, first.shmem, s, A.a, A.io, A.t, A.ss, A.N, A.linT,
@@ -1825,8 +1852,8 @@ ert_status FmmImpl<T>::enqueue_grouped(ert_plan_impl* p, hipStream_t s, int nrhs
     hipLaunchKernelGGL(k_leaf_out<T>, dim3((unsigned)(tr.nbox[L] * sch), (unsigned)nrhs), dim3(64 * kLeafWaves),
                        (2 * kLeafWaves * 64 + R + (64 * kLeafWaves / R) * R) * sizeof(T), s, dt, io, p->d_ss,
                        p->d_diag, hd, N,
-                       (const T*)on.stage, on.pl.tstart, on.pl.tpairs, on.pl.npairs, (const T*)of.stage,
-                       of.pl.tstart, of.pl.tpairs, of.pl.npairs, R, leaf_outT, sch);
+                       (const T*)on.stage, on.pl.tcnt, on.pl.tpad, on.pl.npairs, (const T*)of.stage,
+                       of.pl.tcnt, of.pl.tpad, of.pl.npairs, R, leaf_outT, sch);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }

@@ -80,7 +80,12 @@ struct PairTiles {
     int* tile_col04 = nullptr;
     int* tstart = nullptr;    // [nbox + 1] pairs of each target (CSR, increasing group order)
     int* tpairs = nullptr;    // [npairs]
+    // lattices of at most kPadPairs boxes: the same lists padded to kPadPairs entries per
+    // target (-1 past the end) and their lengths, so that one round of loads fetches them
+    int* tpad = nullptr;      // [nbox][kPadPairs]
+    int* tcnt = nullptr;      // [nbox]
 };
+constexpr int kPadPairs = 64;
 
 // Workgroups are handed to the eight XCDs (each with its own L2) in turn by
 // linear id.  For the n workgroups with linear ids s + b, b in [0, n), this
