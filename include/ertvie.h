@@ -307,7 +307,8 @@ typedef struct {
     long near_pairs;      /* point pairs of the near field (self pairs excluded) */
     int form_near;        /* execution form of the homogeneous near-field product for one
                              right-hand side: -1 not tuned yet / not a box-offset product,
-                             0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64, 3 16x64 */
+                             0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64, 3 16x64,
+                             4 (FP32) 64x16 tiles with the source columns staged in LDS */
     int form_far[16];     /* per level: the same for the far-field translations */
     long near_table;      /* homogeneous media, leaf a power of two >= 4: the offset-stationary
                              near-field products read one table of (4 leaf - 1)^dim values over

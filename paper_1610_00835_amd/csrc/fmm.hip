@@ -947,7 +947,7 @@ struct GemmSite {
     // per rhs bucket (1, >1): 0 class GEMM; offset-stationary with 1: 32 x 16 tiles per
     // workgroup wave set, 2: 32 x 64, 3: 16 x 64 (twice the workgroups of 2)
     int choice[2] = {-1, -1};
-    float tuned_ms[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    float tuned_ms[2][kForms] = {};
     void release()
     {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
@@ -1157,8 +1157,9 @@ struct FmmImpl : FmmData {
         o.L = b.L;
         o.stage = stg;
         o.accumulate = b.accumulate;
-        o.tn = form >= 2 ? 4 : 1;
+        o.tn = (form == 2 || form == 3) ? 4 : 1;
         o.tm = form == 3 ? 1 : 2;
+        o.lds = form == 4 ? 1 : 0;
         o.pl = gs.pl;
         if (&gs == &near_site && neartab && b.ops == nearops) {
             o.atab = neartab;
@@ -1743,23 +1744,22 @@ template <typename T>
 ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, int gprec, const BoxGemm& g, int nrhs,
                                 StageTimer* outer, T* stg)
 {
-    auto as_offset = [&](const BoxGemm& b) { return offset_of(gs, b, stg, 1); };
     if (!gs.used) return box_gemm(s, gprec, g);
     const int bucket = nrhs > 1 ? 1 : 0;
     if (gs.choice[bucket] < 0) {
         BoxGemm gt = g;
         gt.L = tune;
         gt.accumulate = 0;
-        OffsetGemm ot[4] = {as_offset(gt), as_offset(gt), as_offset(gt), as_offset(gt)};
-        ot[2].tn = 4;
-        ot[3].tn = 4;
-        ot[3].tm = 1;
+        OffsetGemm ot[kForms];
+        for (int f = 1; f < kForms; ++f) ot[f] = offset_of(gs, gt, stg, f);
+        // form 4 (LDS-staged source columns) where it applies
+        const int nforms = offset_lds_ok(gprec, ot[4]) ? kForms : kForms - 1;
         hipEvent_t e[3];
         for (auto& ev : e) ERT_HIP(hipEventCreate(&ev));
-        float ms[4] = {0.f, 0.f, 0.f, 0.f};
+        float ms[kForms] = {0.f, 0.f, 0.f, 0.f, 0.f};
         ert_status st = ERT_OK;
         auto run = [&](int form) { return form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot[form]); };
-        for (int form = 0; form < 4 && st == ERT_OK; ++form) {
+        for (int form = 0; form < nforms && st == ERT_OK; ++form) {
             st = run(form);   // warm-up
             if (st != ERT_OK) break;
             (void)hipEventRecord(e[0], s);
@@ -1771,7 +1771,7 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         for (auto& ev : e) (void)hipEventDestroy(ev);
         ERT_TRY(st);
         int best = 0;
-        for (int form = 0; form < 4; ++form) {
+        for (int form = 0; form < nforms; ++form) {
             gs.tuned_ms[bucket][form] = ms[form] / 3;
             if (ms[form] < ms[best]) best = form;
         }
@@ -1779,18 +1779,16 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         // block once instead of once per 16 columns (less HBM traffic at the same speed)
         if (best == 1 && ms[2] <= 1.05f * ms[1]) best = 2;
         // fixed forms for reproducible profiles: ERT_VIE_FORM="a" (every product) or
-        // "a,b" (a for the near field, b for the far field), each 0..3
+        // "a,b" (a for the near field, b for the far field), each 0..4 (4 where it applies)
         if (const char* f = std::getenv("ERT_VIE_FORM")) {
             const char* comma = std::strchr(f, ',');
             const int v = std::atoi((&gs == &near_site || !comma) ? f : comma + 1);
-            if (v >= 0 && v <= 3) best = v;
+            if (v >= 0 && v < nforms) best = v;
         }
         gs.choice[bucket] = best;
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
-    OffsetGemm og = as_offset(g);
-    og.tn = gs.choice[bucket] >= 2 ? 4 : 1;
-    og.tm = gs.choice[bucket] == 3 ? 1 : 2;
+    OffsetGemm og = offset_of(gs, g, stg, gs.choice[bucket]);
     ERT_TRY(offset_gemm_products(s, gprec, og));
     if (outer) outer->stop();
     StageTimer sr_(&p->prof, s, ERT_STAGE_REDUCE);

@@ -405,6 +405,107 @@ __global__ __launch_bounds__(64 * kWaves) void k_offset_gemm2(OffsetGemm a, int 
     }
 }
 
+// Execution form 4 (FP32).  Workgroup = (16-column tile, 64 rows): the tile's 16
+// source columns are staged in LDS once (row stride Kd + 4 floats, so that the 16
+// lanes of a k-group read distinct banks); each wave reduces its 16 rows over the
+// whole reduction length, the operator streamed from memory (or read from the
+// offset table), kLdsU chunks of 16 in flight, even and odd chunks in two
+// accumulators added at the end; no cross-wave sums.
+constexpr int kLdsU = 4;
+
+template <bool TAB>
+__device__ __forceinline__ void lds_tile(const OffsetGemm& g, long tile, int rblk, float* sB)
+{
+    typedef v4f V;
+    const int grpi = g.pl.tile_group[tile];
+    const long col0 = g.pl.tile_col0[tile];
+    const int p0 = g.pl.gstart[grpi], np = g.pl.gstart[grpi + 1] - p0;
+    if (col0 >= (long)np * g.B) return;                 // uniform over the block
+    const int op = g.pl.gop[grpi];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4;
+    const int ld = g.Kd + 4, kq = g.Kd >> 2;
+    for (int e = threadIdx.x; e < 16 * kq; e += blockDim.x) {
+        const int c = e / kq, k4 = e - c * kq;
+        const long col = col0 + c;
+        V v = V{0.f, 0.f, 0.f, 0.f};
+        if (col < (long)np * g.B) {
+            const int pb = (int)(col / np);
+            const long pidx = p0 + (col - (long)pb * np);
+            v = *(const V*)((const float*)g.W + ((long)pb * g.nbox + g.pl.ps[pidx]) * g.Kd + 4 * k4);
+        }
+        *(V*)(sB + c * ld + 4 * k4) = v;
+    }
+    __syncthreads();
+    const int row0 = rblk * 64 + wave * 16;
+    if (row0 >= g.M) return;                            // uniform over the wave; no barrier follows
+    const float* bl = sB + (lane & 15) * ld + 4 * grp;
+    V acc0 = V{0.f, 0.f, 0.f, 0.f}, acc1 = V{0.f, 0.f, 0.f, 0.f};
+    int tb = 0;
+    const float* ar = nullptr;
+    if constexpr (TAB) {
+        const int o0 = op % 3 - 1, o1 = (op / 3) % 3 - 1, o2 = g.dim == 3 ? op / 9 - 1 : 0;
+        const int c = 2 * g.leaf - 1;
+        const int base = (c + g.leaf * o0) + g.tw * (c + g.leaf * o1) + g.tw * g.tw * (g.dim == 3 ? c + g.leaf * o2 : 0);
+        tb = base - tab_lin(g, row0 + (lane & 15));
+    } else {
+        ar = (const float*)g.ops + ((long)op * g.M + row0 + (lane & 15)) * g.Kd + 4 * grp;
+    }
+    for (int k0 = 0; k0 < g.Kd; k0 += 16 * kLdsU) {
+        V a[kLdsU], b[kLdsU];
+#pragma unroll
+        for (int u = 0; u < kLdsU; ++u) {
+            const int kk = k0 + 16 * u;
+            if (kk < g.Kd) {
+                if constexpr (TAB) {
+                    const int idx = tb + tab_lin(g, kk + 4 * grp);
+                    const int r = idx & 3;
+                    a[u] = *(const V*)((const float*)g.atab + r * g.tlen + (idx - r));
+                } else {
+                    a[u] = *(const V*)(ar + kk);
+                }
+                b[u] = *(const V*)(bl + kk);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLdsU; ++u) {
+            if (k0 + 16 * u < g.Kd) {
+                V& acc = (u & 1) ? acc1 : acc0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b[u][e], acc, 0, 0, 0);
+            }
+        }
+    }
+    const long col = col0 + (lane & 15);
+    if (col < (long)np * g.B) {
+        const int pb = (int)(col / np);
+        const long pidx = p0 + (col - (long)pb * np);
+        *(V*)((float*)g.stage + ((long)pb * g.pl.npairs + pidx) * g.M + row0 + 4 * grp) = acc0 + acc1;
+    }
+}
+
+template <bool TAB>
+__global__ __launch_bounds__(256) void k_offset_lds(OffsetGemm g)
+{
+    extern __shared__ __align__(16) float lds_b[];
+    lds_tile<TAB>(g, blockIdx.x, blockIdx.y, lds_b);
+}
+
+// both products of a one-level tree in form 4, in one launch
+template <bool TABA>
+__global__ __launch_bounds__(256) void k_offset_lds2(OffsetGemm a, int rows_a, long na, OffsetGemm b, int rows_b)
+{
+    extern __shared__ __align__(16) float lds_b[];
+    const long bid = blockIdx.x;
+    if (bid < na) {
+        const long p = xcd_position(bid, na);
+        lds_tile<TABA>(a, p / rows_a, (int)(p % rows_a), lds_b);
+    } else {
+        const long nb = (long)gridDim.x - na;
+        const long p = xcd_position(bid - na, nb, (int)(na & 7));
+        lds_tile<false>(b, p / rows_b, (int)(p % rows_b), lds_b);
+    }
+}
+
 // Per-target sums of the staged pair products, in a fixed order: one workgroup
 // per (target, 64-row slab, rhs); its four waves sum four consecutive quarters
 // of the target's pair list (8 row loads in flight per lane) and wave 0 adds
@@ -792,11 +893,30 @@ ert_status box_gemm(hipStream_t s, int prec, const BoxGemm& g)
     return ERT_OK;
 }
 
+bool offset_lds_ok(int prec, const OffsetGemm& g)
+{
+    return prec == ERT_FP32 && g.M % 16 == 0 && g.Kd % 16 == 0 && 16L * (g.Kd + 4) * 4 <= 65536;
+}
+
 ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
 {
     if (g.M % (16 * kTM) != 0 || g.Kd % 32 != 0) {
         record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
         return ERT_EINVAL;
+    }
+    if (g.lds) {
+        if (!offset_lds_ok(prec, g)) {
+            record_error("offset_gemm: execution form 4 needs FP32 and a reduction length of at most 1020");
+            return ERT_EINVAL;
+        }
+        if (g.pl.ntiles > 0) {
+            const dim3 grid((unsigned)g.pl.ntiles, (unsigned)((g.M + 63) / 64));
+            const size_t sh = 16 * (size_t)(g.Kd + 4) * sizeof(float);
+            if (g.atab) hipLaunchKernelGGL(k_offset_lds<true>, grid, dim3(256), sh, s, g);
+            else hipLaunchKernelGGL(k_offset_lds<false>, grid, dim3(256), sh, s, g);
+            ERT_HIP(hipGetLastError());
+        }
+        return ERT_OK;
     }
     if (g.tn == 4) {
         if (g.pl.ntiles4 > 0) {
@@ -900,7 +1020,7 @@ void launch_pair(hipStream_t s, const OffsetGemm& a, int ra, long na, int fa, co
     launch_pair_a<PREC, false>(s, a, ra, na, fa, b, rb, nb, fb);
 }
 
-int form_of(const OffsetGemm& g) { return g.tn == 4 ? (g.tm == 1 ? 3 : 2) : 1; }
+int form_of(const OffsetGemm& g) { return g.lds ? 4 : g.tn == 4 ? (g.tm == 1 ? 3 : 2) : 1; }
 
 }  // namespace
 
@@ -914,6 +1034,26 @@ ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& 
     if (b.atab || (a.atab && prec == ERT_BF16X3)) {
         record_error("offset_gemm: only the first product of a pair, in FP32/FP64, reads an offset table");
         return ERT_EINVAL;
+    }
+    if (a.lds != b.lds) {                       // forms of both kinds: two launches
+        ERT_TRY(offset_gemm_products(s, prec, a));
+        return offset_gemm_products(s, prec, b);
+    }
+    if (a.lds) {
+        if (!offset_lds_ok(prec, a) || !offset_lds_ok(prec, b)) {
+            record_error("offset_gemm: execution form 4 needs FP32 and a reduction length of at most 1020");
+            return ERT_EINVAL;
+        }
+        const int ra4 = (a.M + 63) / 64, rb4 = (b.M + 63) / 64;
+        const long na4 = a.pl.ntiles * ra4, nb4 = b.pl.ntiles * rb4;
+        if (na4 + nb4 == 0) return ERT_OK;
+        const size_t sh = 16 * (size_t)(std::max(a.Kd, b.Kd) + 4) * sizeof(float);
+        if (a.atab)
+            hipLaunchKernelGGL(k_offset_lds2<true>, dim3((unsigned)(na4 + nb4)), dim3(256), sh, s, a, ra4, na4, b, rb4);
+        else
+            hipLaunchKernelGGL(k_offset_lds2<false>, dim3((unsigned)(na4 + nb4)), dim3(256), sh, s, a, ra4, na4, b, rb4);
+        ERT_HIP(hipGetLastError());
+        return ERT_OK;
     }
     int ra, rb;
     long na, nb;
