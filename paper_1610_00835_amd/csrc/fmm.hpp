@@ -130,10 +130,9 @@ bool offset_lds_ok(int prec, const OffsetGemm& g);   // execution form 4 applies
 // 4 16-column tiles with the source columns in LDS (FP32)
 constexpr int kForms = 5;
 ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    // per-target sums only
-// two independent products (each in its own form, with its own staging rows) in one launch,
-// and their per-target sums in one launch
+// two independent products (each in its own form, with its own staging rows) in one launch
+// (two launches when only one of them is in form 4)
 ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b);
-ert_status offset_gemm_pair_reduce(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b);
 
 // Streaming form of cached-pair products (heterogeneous far field and near
 // field): one workgroup per pair streams its matrix once (16-byte loads along

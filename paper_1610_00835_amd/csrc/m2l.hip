@@ -550,17 +550,6 @@ __global__ __launch_bounds__(256) void k_stage_reduce(OffsetGemm g, int rslabs)
     stage_reduce_block<T>(g, rslabs, blockIdx.x);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_stage_reduce2(OffsetGemm a, int rslabs_a, long na, OffsetGemm b,
-                                                       int rslabs_b)
-{
-    const long bid = blockIdx.x;
-    if (bid < na)
-        stage_reduce_block<T>(a, rslabs_a, bid);
-    else
-        stage_reduce_block<T>(b, rslabs_b, bid - na);
-}
-
 // ----------------------------------------------------- streaming pairs ----
 
 template <typename T, int RPT>
@@ -1062,18 +1051,6 @@ ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& 
     if (prec == ERT_FP64) launch_pair<ERT_FP64>(s, ga, ra, na, form_of(a), gb, rb, nb, form_of(b));
     else if (prec == ERT_FP32) launch_pair<ERT_FP32>(s, ga, ra, na, form_of(a), gb, rb, nb, form_of(b));
     else launch_pair<ERT_BF16X3>(s, ga, ra, na, form_of(a), gb, rb, nb, form_of(b));
-    ERT_HIP(hipGetLastError());
-    return ERT_OK;
-}
-
-ert_status offset_gemm_pair_reduce(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b)
-{
-    const int sa = (a.M + 63) / 64, sb = (b.M + 63) / 64;
-    const long na = a.nbox * sa * a.B, nb = b.nbox * sb * b.B;
-    if (prec == ERT_FP64)
-        hipLaunchKernelGGL(k_stage_reduce2<double>, dim3((unsigned)(na + nb)), dim3(256), 0, s, a, sa, na, b, sb);
-    else
-        hipLaunchKernelGGL(k_stage_reduce2<float>, dim3((unsigned)(na + nb)), dim3(256), 0, s, a, sa, na, b, sb);
     ERT_HIP(hipGetLastError());
     return ERT_OK;
 }
