@@ -626,6 +626,15 @@ def main():
         cpu = {"value": N / dt / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
                "sample": "%d full dense FP64 applies of (I - K) on the 32^3 workload, %.2f s each" % (reps, dt)}
         log("cpu oracle:", json.dumps(cpu))
+        # one thread, as the paper's own timings: a row sample, extrapolated to the whole apply
+        rows1 = np.random.default_rng(11).choice(N, size=2048, replace=False)
+        t = time.perf_counter()
+        P.apply_rows(case["f"], rows1, op=2, nthreads=1)
+        dt1 = (time.perf_counter() - t) * N / len(rows1)
+        extra["cpu_oracle_one_thread"] = {
+            "value": N / dt1 / 1e6, "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+            "sample": "2048 sampled rows of the dense FP64 apply, extrapolated by N/rows to %.1f s per apply" % dt1}
+        log("cpu oracle, one thread:", json.dumps(extra["cpu_oracle_one_thread"]))
 
     out = {"metric": "FMM matvec Mpts/s; time to 1e-8 solve, plain FP64 GMRES vs mixed+learned (1 GPU)",
            "value": value, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
