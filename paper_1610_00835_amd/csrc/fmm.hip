@@ -171,6 +171,18 @@ __global__ __launch_bounds__(64 * kLeafInWaves) void k_leaf_in(ApplyIO a, ApplyI
     const long leafi = pos / rch;
     const int chunk = (int)(pos % rch);
     const int b = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = chunk * 64 + lane;
+    const int per = (t.S + kLeafInWaves - 1) / kLeafInWaves;
+    const int k0 = wave * per, k1 = min(t.S, k0 + per);
+    const T* col = linT + r;
+    // a lane's first 16 operator entries, requested before the charges are gathered
+    const bool pre = r < R && k1 - k0 >= 16;
+    T v0[16];
+    if (pre) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v0[u] = col[(long)(k0 + u) * R];
+    }
     const double* x = a.x;
     const int weighted = a.op != ERT_OP_G;
     for (int li = threadIdx.x; li < t.S; li += blockDim.x) {
@@ -184,14 +196,14 @@ __global__ __launch_bounds__(64 * kLeafInWaves) void k_leaf_in(ApplyIO a, ApplyI
         if (chunk == 0) q[(long)b * t.nslot + slot] = tv;
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = chunk * 64 + lane;
-    const int per = (t.S + kLeafInWaves - 1) / kLeafInWaves;
-    const int k0 = wave * per, k1 = min(t.S, k0 + per);
     T acc = T(0);
     if (r < R) {
-        const T* col = linT + r;
         int k = k0;
+        if (pre) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v0[u] * sq[k0 + u];
+            k += 16;
+        }
         for (; k + 16 <= k1; k += 16) {
             T v[16];
 #pragma unroll
@@ -275,6 +287,16 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
     if (threadIdx.x < kLeafMaxPairs) pl_n[threadIdx.x] = tpn[leafi * kLeafMaxPairs + threadIdx.x];
     else if (threadIdx.x < 2 * kLeafMaxPairs)
         pl_f[threadIdx.x - kLeafMaxPairs] = tpf[leafi * kLeafMaxPairs + threadIdx.x - kLeafMaxPairs];
+    // a lane's first 16 L2P operator entries, requested before the staged sums
+    const int perR = (R + kLeafWaves - 1) / kLeafWaves;
+    const int r0 = min(R, wave * perR), r1 = min(R, r0 + perR);
+    const T* lcol = loutT + li;
+    const bool pre = ok && r1 - r0 >= 16;
+    T lv[16];
+    if (pre) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = lcol[(long)(r0 + u) * t.S];
+    }
     // the assembly's operands, loaded early
     int c[3];
     long j = -1;
@@ -310,20 +332,22 @@ __global__ __launch_bounds__(64 * kLeafWaves) void k_leaf_out(
     }
     __syncthreads();
     {
-        const int per = (R + kLeafWaves - 1) / kLeafWaves;
-        const int r0 = min(R, wave * per), r1 = min(R, r0 + per);
         T acc = T(0);
         if (ok) {
-            const T* col = loutT + li;
             int r = r0;
+            if (pre) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc += lv[u] * sl[r0 + u];
+                r += 16;
+            }
             for (; r + 16 <= r1; r += 16) {
                 T v[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = col[(long)(r + u) * t.S];
+                for (int u = 0; u < 16; ++u) v[u] = lcol[(long)(r + u) * t.S];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) acc += v[u] * sl[r + u];
             }
-            for (; r < r1; ++r) acc += col[(long)r * t.S] * sl[r];
+            for (; r < r1; ++r) acc += lcol[(long)r * t.S] * sl[r];
         }
         pf[wave * 64 + lane] = acc;
     }
