@@ -145,6 +145,10 @@ __global__ void k_assemble(DevTree t, const T* __restrict__ pot, const ApplyIO* 
     y[i] = (op == ERT_OP_A) ? xj - v : v;
 }
 
+constexpr int kLeafInWaves = 16;               // waves per workgroup of k_leaf_in
+constexpr int kLeafWaves = 8;                  // waves per workgroup of k_leaf_out
+constexpr int kLeafMaxPairs = kPadPairs;       // pairs per target on a one-level tree (at most 4^3 boxes)
+
 // One-level homogeneous apply, first kernel.  Workgroup (leaf, 64 rows of the
 // compressed multipole, rhs): the leaf's weighted charges go to LDS (and, from
 // the first row chunk, to q in leaf order for the near-field products), then
@@ -152,11 +156,6 @@ __global__ void k_assemble(DevTree t, const T* __restrict__ pot, const ApplyIO* 
 // transposed copy [S][R] so that a wave's loads are contiguous; the sixteen
 // waves take consecutive sixteenths of the S charges and their partial sums are
 // added in wave order.
-constexpr int kLeafWaves = 8;
-
-constexpr int kLeafMaxPairs = kPadPairs;   // pairs per target on a one-level tree (at most 4^3 boxes)
-constexpr int kLeafInWaves = 16;
-
 template <typename T>
 __global__ __launch_bounds__(64 * kLeafInWaves) void k_leaf_in(ApplyIO a, ApplyIO* io, DevTree t,
                                                              const double* __restrict__ ss, long N,
