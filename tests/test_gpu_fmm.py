@@ -187,6 +187,44 @@ def test_fmm_graph_replays_match_eager(ev, oracle_mod):
         assert np.max(np.abs(Ys[2][:, 0] - eager[0])) <= 1e-6 * np.max(np.abs(eager[0]))
 
 
+@pytest.mark.parametrize("recipe,n,leaf", [("c2", (32, 32, 32), 8), ("c3", (16, 16, 16), 4)])
+def test_fmm_graph_back_to_back_applies(ev, oracle_mod, recipe, n, leaf):
+    """Replays of the captured apply queued back to back behind other work on the plan's
+    stream, each with its own vectors (a replay replaces the root kernel node's arguments,
+    the rest of the apply reads them from device memory): every result equals the eager
+    apply of its vector bit for bit.  The one-level homogeneous tree and a heterogeneous
+    tree have different root kernels."""
+    import torch
+    from tests.gpu_util import to_dev, to_host
+    case = inputs.make_case(recipe, n=n, seed=8)
+    N = case["f"].size
+    xs = [to_dev(inputs.random_vector(N, 40 + i)) for i in range(4)]
+    with ev.plan_from_case(case, method="fmm", prec="fp32", leaf=leaf) as plan:
+        plan.profile(True)                # eager applies while profiling
+        eager = []
+        for x in xs:
+            y = torch.empty_like(x)
+            plan.apply(x, y, op=ev.OP_A)
+            eager.append(to_host(y))
+        plan.profile(False)
+        ys = [torch.empty_like(x) for x in xs]
+        for _ in range(2):                # capture, then replay
+            for x, y in zip(xs, ys):
+                plan.apply(x, y, op=ev.OP_A)
+            torch.cuda.synchronize()
+        for rep in range(3):
+            for y in ys:
+                y.zero_()
+            a = torch.randn(4096, 4096, device="cuda")
+            b = a @ a                     # keeps the stream busy while the applies are queued
+            for x, y in zip(xs, ys):
+                plan.apply(x, y, op=ev.OP_A)
+            torch.cuda.synchronize()
+            del a, b
+            for i, y in enumerate(ys):
+                assert np.array_equal(to_host(y), eager[i]), (rep, i)
+
+
 @pytest.mark.parametrize("svd_tol", [1e-6, 1e-5])
 def test_fmm_compression_tolerance(ev, oracle_mod, svd_tol):
     """Looser singular-value cutoffs keep the 32^3 apply within the 1e-6 bar."""
