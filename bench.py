@@ -59,7 +59,7 @@ SVD_TOL = 1e-5
 # scaled by the readings of a 256 MiB device copy (profiles/near_m2l_c2_32cubed_fp32_hbm_traffic.md).
 # Keyed by (workload, precision, kernel, execution forms "near,far" the autotuner chose); a
 # combination without counters, or a kernel changed since they were taken, reports null.
-MEASURED_TRAFFIC = {("c2", "fp32", "near+m2l", "1,1"): 39.19e6}
+MEASURED_TRAFFIC = {("c2", "fp32", "near+m2l", "1,1"): 39.20e6}
 
 
 def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None, forms=None):
