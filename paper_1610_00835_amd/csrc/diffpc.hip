@@ -175,21 +175,87 @@ __global__ void k_prolong_add(int f0, int f1, int f2, double* __restrict__ Uf, i
     Uf[j] += Ec[(i[0] / 2) + (long)c0 * ((i[1] / 2) + (long)c1 * (i[2] / 2))];
 }
 
-// Coarsest level: kCoarseSweeps red-black sweeps from U = 0, one workgroup.
-__global__ __launch_bounds__(256) void k_coarsest(LvArgs a, double* __restrict__ U, const double* __restrict__ B)
+// The V-cycle below a level of at most kSmallCells cells, in one workgroup: the
+// same steps as the per-level launches (smoothing, residual, restriction, the
+// coarser cycle, prolongation, smoothing), each a workgroup-stride loop closed by
+// a barrier.  Red-black colours, residuals, averages and prolongations are per
+// cell, so the results equal the per-level launches bit for bit.
+constexpr int kSmallCells = 256;
+constexpr int kMaxSmall = 12;
+
+struct SmallLevel {
+    LvArgs a;
+    long N;
+    double* U;
+    double* B;
+    double* R;
+};
+
+struct SmallCycle {
+    int nl;                       // levels k0 .. k0 + nl - 1, the last the coarsest
+    SmallLevel lv[kMaxSmall];
+};
+
+__device__ __forceinline__ void small_rbgs(const SmallLevel& L, int sweeps)
 {
-    const long N = (long)a.n0 * a.n1 * a.n2;
-    for (long j = threadIdx.x; j < N; j += blockDim.x) U[j] = 0.0;
-    __syncthreads();
-    for (int sweep = 0; sweep < kCoarseSweeps; ++sweep)
+    for (int sw = 0; sw < sweeps; ++sw)
         for (int colour = 0; colour < 2; ++colour) {
-            for (long j = threadIdx.x; j < N; j += blockDim.x) {
+            for (long j = threadIdx.x; j < L.N; j += blockDim.x) {
                 int i[3];
-                unravel(j, a.n0, a.n1, i);
-                if (((i[0] + i[1] + i[2]) & 1) == colour) U[j] = (B[j] + offdiag(a, U, j, i)) / a.diag[j];
+                unravel(j, L.a.n0, L.a.n1, i);
+                if (((i[0] + i[1] + i[2]) & 1) == colour) L.U[j] = (L.B[j] + offdiag(L.a, L.U, j, i)) / L.a.diag[j];
             }
             __syncthreads();
         }
+}
+
+__global__ __launch_bounds__(256) void k_small_cycle(SmallCycle c)
+{
+    // down: smooth, residual, restrict (the first level's U is the caller's)
+    for (int k = 0; k + 1 < c.nl; ++k) {
+        const SmallLevel& L = c.lv[k];
+        const SmallLevel& C = c.lv[k + 1];
+        small_rbgs(L, kPre);
+        for (long j = threadIdx.x; j < L.N; j += blockDim.x) {
+            int i[3];
+            unravel(j, L.a.n0, L.a.n1, i);
+            L.R[j] = L.B[j] - (L.a.diag[j] * L.U[j] - offdiag(L.a, L.U, j, i));
+        }
+        __syncthreads();
+        for (long q = threadIdx.x; q < C.N; q += blockDim.x) {
+            int ic[3];
+            unravel(q, C.a.n0, C.a.n1, ic);
+            double s = 0.0;
+            int cnt = 0;
+            for (int oz = 0; oz < (L.a.dim > 2 ? 2 : 1); ++oz)
+                for (int oy = 0; oy < 2; ++oy)
+                    for (int ox = 0; ox < 2; ++ox) {
+                        const int x = 2 * ic[0] + ox, y = 2 * ic[1] + oy, z = 2 * ic[2] + oz;
+                        if (x < L.a.n0 && y < L.a.n1 && z < L.a.n2) {
+                            s += L.R[x + (long)L.a.n0 * (y + (long)L.a.n1 * z)];
+                            ++cnt;
+                        }
+                    }
+            C.B[q] = s / cnt;
+            C.U[q] = 0.0;
+        }
+        __syncthreads();
+    }
+    // coarsest: sweeps on the correction equation from zero (zeroed above); a single-level
+    // hierarchy's only level is the finest, whose cycles continue from the current iterate
+    small_rbgs(c.lv[c.nl - 1], kCoarseSweeps);
+    // up: prolongate and smooth
+    for (int k = c.nl - 2; k >= 0; --k) {
+        const SmallLevel& L = c.lv[k];
+        const SmallLevel& C = c.lv[k + 1];
+        for (long j = threadIdx.x; j < L.N; j += blockDim.x) {
+            int i[3];
+            unravel(j, L.a.n0, L.a.n1, i);
+            L.U[j] += C.U[(i[0] / 2) + (long)C.a.n0 * ((i[1] / 2) + (long)C.a.n1 * (i[2] / 2))];
+        }
+        __syncthreads();
+        small_rbgs(L, kPost);
+    }
 }
 
 __global__ void k_scaled(const double* __restrict__ r, const double* __restrict__ ss, long N, double* __restrict__ b)
@@ -228,8 +294,16 @@ ert_status vcycle(hipStream_t s, DiffPc* d, int k)
 {
     DiffLevel& L = d->lv[k];
     const LvArgs a = args_of(d, L);
-    if (k + 1 == (int)d->lv.size()) {
-        hipLaunchKernelGGL(k_coarsest, dim3(1), dim3(256), 0, s, a, L.U, (const double*)L.B);
+    const int nl = (int)d->lv.size() - k;
+    if (k + 1 == (int)d->lv.size() || (L.N <= kSmallCells && nl <= kMaxSmall)) {
+        // this level and the coarser ones in one workgroup (the coarsest level always goes here)
+        SmallCycle c{};
+        c.nl = nl;
+        for (int q = 0; q < nl; ++q) {
+            DiffLevel& Q = d->lv[k + q];
+            c.lv[q] = SmallLevel{args_of(d, Q), Q.N, Q.U, Q.B, Q.R};
+        }
+        hipLaunchKernelGGL(k_small_cycle, dim3(1), dim3(256), 0, s, c);
         ERT_HIP(hipGetLastError());
         return ERT_OK;
     }
@@ -240,7 +314,7 @@ ert_status vcycle(hipStream_t s, DiffPc* d, int k)
     hipLaunchKernelGGL(k_avg_children, dim3(nblk(C.N)), dim3(256), 0, s, d->dim, L.n[0], L.n[1], L.n[2],
                        (const double*)L.R, C.n[0], C.n[1], C.n[2], C.B);
     ERT_HIP(hipGetLastError());
-    if (k + 2 < (int)d->lv.size()) ERT_TRY(zero(s, C.U, C.N));    // the coarsest level clears its own
+    ERT_TRY(zero(s, C.U, C.N));                  // the coarser correction starts from zero
     ERT_TRY(vcycle(s, d, k + 1));
     hipLaunchKernelGGL(k_prolong_add, dim3(nblk(L.N)), dim3(256), 0, s, L.n[0], L.n[1], L.n[2], L.U, C.n[0], C.n[1],
                        (const double*)C.U);

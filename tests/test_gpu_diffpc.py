@@ -21,7 +21,8 @@ def ev():
     return ertvie
 
 
-@pytest.mark.parametrize("name,n", [("c1", (20, 16)), ("c3", (12, 10, 9)), ("c5", (16, 16, 16)), ("c1", (37, 5))])
+@pytest.mark.parametrize("name,n", [("c1", (20, 16)), ("c3", (12, 10, 9)), ("c5", (16, 16, 16)), ("c1", (37, 5)),
+                                    ("c1", (4, 3)), ("c5", (40, 36, 33))])
 def test_diff_precond_matches_reference(ev, name, n):
     case = inputs.make_case(name, n=n, seed=1)
     N = int(np.prod(n))
