@@ -30,7 +30,6 @@ struct DiffLevel {
     double* df[3] = {nullptr, nullptr, nullptr};   // face to the upper neighbour along axis a
     double* U = nullptr;
     double* B = nullptr;
-    double* R = nullptr;
 };
 
 struct DiffPc {
@@ -154,15 +153,36 @@ __global__ __launch_bounds__(256) void k_rbgs(LvArgs a, double* __restrict__ U, 
     U[j] = (B[j] + offdiag(a, U, j, i)) / a.diag[j];
 }
 
-__global__ __launch_bounds__(256) void k_residual(LvArgs a, const double* __restrict__ U, const double* __restrict__ B,
-                                                  double* __restrict__ R)
+// B_c = average over the children of the fine residual B - (diag U - offdiag U), and
+// U_c = 0 (the coarser correction starts from zero): coarse cell q
+__device__ __forceinline__ void restrict_residual(const LvArgs& a, const double* __restrict__ U,
+                                                  const double* __restrict__ B, long q, int c0, int c1,
+                                                  double* __restrict__ Bc, double* __restrict__ Uc)
 {
-    const long N = (long)a.n0 * a.n1 * a.n2;
-    const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    int i[3];
-    unravel(j, a.n0, a.n1, i);
-    R[j] = B[j] - (a.diag[j] * U[j] - offdiag(a, U, j, i));
+    int ic[3];
+    unravel(q, c0, c1, ic);
+    double s = 0.0;
+    int cnt = 0;
+    for (int oz = 0; oz < (a.dim > 2 ? 2 : 1); ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+            for (int ox = 0; ox < 2; ++ox) {
+                const int i[3] = {2 * ic[0] + ox, 2 * ic[1] + oy, 2 * ic[2] + oz};
+                if (i[0] < a.n0 && i[1] < a.n1 && i[2] < a.n2) {
+                    const long j = i[0] + (long)a.n0 * (i[1] + (long)a.n1 * i[2]);
+                    s += B[j] - (a.diag[j] * U[j] - offdiag(a, U, j, i));
+                    ++cnt;
+                }
+            }
+    Bc[q] = s / cnt;
+    Uc[q] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_restrict_residual(LvArgs a, const double* __restrict__ U,
+                                                           const double* __restrict__ B, int c0, int c1, int c2,
+                                                           double* __restrict__ Bc, double* __restrict__ Uc)
+{
+    const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (q < (long)c0 * c1 * c2) restrict_residual(a, U, B, q, c0, c1, Bc, Uc);
 }
 
 __global__ void k_prolong_add(int f0, int f1, int f2, double* __restrict__ Uf, int c0, int c1,
@@ -188,7 +208,6 @@ struct SmallLevel {
     long N;
     double* U;
     double* B;
-    double* R;
 };
 
 struct SmallCycle {
@@ -216,29 +235,7 @@ __global__ __launch_bounds__(256) void k_small_cycle(SmallCycle c)
         const SmallLevel& L = c.lv[k];
         const SmallLevel& C = c.lv[k + 1];
         small_rbgs(L, kPre);
-        for (long j = threadIdx.x; j < L.N; j += blockDim.x) {
-            int i[3];
-            unravel(j, L.a.n0, L.a.n1, i);
-            L.R[j] = L.B[j] - (L.a.diag[j] * L.U[j] - offdiag(L.a, L.U, j, i));
-        }
-        __syncthreads();
-        for (long q = threadIdx.x; q < C.N; q += blockDim.x) {
-            int ic[3];
-            unravel(q, C.a.n0, C.a.n1, ic);
-            double s = 0.0;
-            int cnt = 0;
-            for (int oz = 0; oz < (L.a.dim > 2 ? 2 : 1); ++oz)
-                for (int oy = 0; oy < 2; ++oy)
-                    for (int ox = 0; ox < 2; ++ox) {
-                        const int x = 2 * ic[0] + ox, y = 2 * ic[1] + oy, z = 2 * ic[2] + oz;
-                        if (x < L.a.n0 && y < L.a.n1 && z < L.a.n2) {
-                            s += L.R[x + (long)L.a.n0 * (y + (long)L.a.n1 * z)];
-                            ++cnt;
-                        }
-                    }
-            C.B[q] = s / cnt;
-            C.U[q] = 0.0;
-        }
+        for (long q = threadIdx.x; q < C.N; q += blockDim.x) restrict_residual(L.a, L.U, L.B, q, C.a.n0, C.a.n1, C.B, C.U);
         __syncthreads();
     }
     // coarsest: sweeps on the correction equation from zero (zeroed above); a single-level
@@ -301,7 +298,7 @@ ert_status vcycle(hipStream_t s, DiffPc* d, int k)
         c.nl = nl;
         for (int q = 0; q < nl; ++q) {
             DiffLevel& Q = d->lv[k + q];
-            c.lv[q] = SmallLevel{args_of(d, Q), Q.N, Q.U, Q.B, Q.R};
+            c.lv[q] = SmallLevel{args_of(d, Q), Q.N, Q.U, Q.B};
         }
         hipLaunchKernelGGL(k_small_cycle, dim3(1), dim3(256), 0, s, c);
         ERT_HIP(hipGetLastError());
@@ -309,12 +306,10 @@ ert_status vcycle(hipStream_t s, DiffPc* d, int k)
     }
     for (int sw = 0; sw < kPre; ++sw)
         for (int c = 0; c < 2; ++c) hipLaunchKernelGGL(k_rbgs, dim3(nblk(L.N)), dim3(256), 0, s, a, L.U, L.B, c);
-    hipLaunchKernelGGL(k_residual, dim3(nblk(L.N)), dim3(256), 0, s, a, L.U, L.B, L.R);
     DiffLevel& C = d->lv[k + 1];
-    hipLaunchKernelGGL(k_avg_children, dim3(nblk(C.N)), dim3(256), 0, s, d->dim, L.n[0], L.n[1], L.n[2],
-                       (const double*)L.R, C.n[0], C.n[1], C.n[2], C.B);
+    hipLaunchKernelGGL(k_restrict_residual, dim3(nblk(C.N)), dim3(256), 0, s, a, (const double*)L.U,
+                       (const double*)L.B, C.n[0], C.n[1], C.n[2], C.B, C.U);
     ERT_HIP(hipGetLastError());
-    ERT_TRY(zero(s, C.U, C.N));                  // the coarser correction starts from zero
     ERT_TRY(vcycle(s, d, k + 1));
     hipLaunchKernelGGL(k_prolong_add, dim3(nblk(L.N)), dim3(256), 0, s, L.n[0], L.n[1], L.n[2], L.U, C.n[0], C.n[1],
                        (const double*)C.U);
@@ -352,7 +347,6 @@ ert_status diffpc_build(ert_plan_impl* p)
         for (int a = 0; a < 3; ++a) alloc(&L.df[a], L.N);
         alloc(&L.U, L.N);
         alloc(&L.B, L.N);
-        alloc(&L.R, L.N);
         d->lv.push_back(L);
         if (st != ERT_OK) break;
         const int mx = std::max(n[0], std::max(n[1], n[2]));
@@ -403,7 +397,6 @@ void diffpc_destroy(DiffPc* d)
         for (auto* q : L.df) (void)hipFree(q);
         (void)hipFree(L.U);
         (void)hipFree(L.B);
-        (void)hipFree(L.R);
     }
     (void)hipFree(d->rhs);
     delete d;
