@@ -9,7 +9,8 @@
 //
 // One thread per (cell, direction), FP64; the medium and the source are read
 // through the d-linear interpolation the kernel's ray rule uses (L2-resident
-// gathers).  exp(-tau) is carried as a running product of the steps' factors.
+// gathers of the two fields interleaved per cell).  exp(-tau) is carried as a
+// running product of the steps' factors.
 #include "common.hpp"
 
 #include <cmath>
@@ -19,15 +20,54 @@ namespace ertvie {
 
 namespace {
 
+// (sigma_t, Q) per cell, interleaved so that one 16-byte load serves both fields
 __global__ __launch_bounds__(256) void k_source(const double* __restrict__ U, const double* __restrict__ f,
-                                                const double* __restrict__ ss, long N, double* __restrict__ q)
+                                                const double* __restrict__ st, const double* __restrict__ ss, long N,
+                                                double2* __restrict__ sq)
 {
     const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= N) return;
-    q[i] = (U ? ss[i] * U[i] : 0.0) + (f ? f[i] : 0.0);
+    sq[i] = make_double2(st[i], (U ? ss[i] * U[i] : 0.0) + (f ? f[i] : 0.0));
 }
 
-__global__ __launch_bounds__(256) void k_sweep(Geo g, const double* __restrict__ st, const double* __restrict__ q,
+// The clamped d-linear interpolation of the ray rule (as for sigma_t alone), applied to
+// both interleaved fields with one set of weights: the same operations per field.
+__device__ __forceinline__ double2 pair_at(const double2* __restrict__ v, const Geo& g, double inv_h, double p0,
+                                           double p1, double p2)
+{
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const double p[3] = {p0, p1, p2};
+    int i0[3] = {0, 0, 0};
+    double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < g.dim && n[a] > 1) {
+            double u = p[a] * inv_h - 0.5;
+            const double hi = (double)(n[a] - 1);
+            u = u < 0.0 ? 0.0 : (u > hi ? hi : u);
+            int k = (int)floor(u);
+            k = k > n[a] - 2 ? n[a] - 2 : k;
+            i0[a] = k;
+            t[a] = u - (double)k;
+        }
+    }
+    const int b0 = i0[0] + n[0] * (i0[1] + n[1] * i0[2]);
+    const int d0 = n[0] > 1 ? 1 : 0;
+    const int d1 = n[1] > 1 ? n[0] : 0;
+    const int d2 = (g.dim > 2 && n[2] > 1) ? n[0] * n[1] : 0;
+    auto lerp2 = [&](int b) {
+        const double2 a = v[b], c = v[b + d0];
+        return make_double2(a.x + t[0] * (c.x - a.x), a.y + t[0] * (c.y - a.y));
+    };
+    const double2 c00 = lerp2(b0), c10 = lerp2(b0 + d1);
+    const double2 c0 = make_double2(c00.x + t[1] * (c10.x - c00.x), c00.y + t[1] * (c10.y - c00.y));
+    if (g.dim == 2) return c0;
+    const double2 c01 = lerp2(b0 + d2), c11 = lerp2(b0 + d2 + d1);
+    const double2 c1 = make_double2(c01.x + t[1] * (c11.x - c01.x), c01.y + t[1] * (c11.y - c01.y));
+    return make_double2(c0.x + t[2] * (c1.x - c0.x), c0.y + t[2] * (c1.y - c0.y));
+}
+
+__global__ __launch_bounds__(256) void k_sweep(Geo g, const double2* __restrict__ sq,
                                                const double* __restrict__ dirs, long N, double* __restrict__ phi)
 {
     const long j = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -53,8 +93,8 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, const double* __restrict__
     for (long k = 1; k <= m; ++k) {
         const double t = ((double)k - 0.5) * D;
         const double p0 = x[0] - t * v[0], p1 = x[1] - t * v[1], p2 = x[2] - t * v[2];
-        const double s = sigma_at<double>(st, g, inv_h, p0, p1, p2);
-        const double qk = sigma_at<double>(q, g, inv_h, p0, p1, p2);
+        const double2 sqk = pair_at(sq, g, inv_h, p0, p1, p2);
+        const double s = sqk.x, qk = sqk.y;
         const double sd = s * D;
         const double em = expm1(-sd);                 // exp(-sigma D) - 1
         const double step = sd > 1e-300 ? -em / s : D;
@@ -86,20 +126,21 @@ ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, c
         }
     }
     double* buf = nullptr;
-    ERT_HIP(hipMalloc(&buf, sizeof(double) * (N + 3 * (size_t)ndir)));
-    double* q = buf;
-    double* dd = buf + N;
+    ERT_HIP(hipMalloc(&buf, sizeof(double) * (2 * N + 3 * (size_t)ndir)));
+    double2* sq = reinterpret_cast<double2*>(buf);
+    double* dd = buf + 2 * N;
     ert_status st = ERT_HIPST(hipMemcpyAsync(dd, dv.data(), sizeof(double) * 3 * ndir, hipMemcpyHostToDevice,
                                              p->stream));
     if (st == ERT_OK) {
-        hipLaunchKernelGGL(k_source, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, U, f, p->d_ss, N, q);
+        hipLaunchKernelGGL(k_source, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, U, f, p->d_st,
+                           p->d_ss, N, sq);
         st = ERT_HIPST(hipGetLastError());
     }
     // directions in slabs of at most 65535 (grid.y)
     for (int d0 = 0; d0 < ndir && st == ERT_OK; d0 += 65535) {
         const int nd = std::min(65535, ndir - d0);
         hipLaunchKernelGGL(k_sweep, dim3((unsigned)((N + 255) / 256), (unsigned)nd), dim3(256), 0, p->stream, p->geo,
-                           p->d_st, q, dd + (size_t)3 * d0, N, phi + (size_t)d0 * N);
+                           sq, dd + (size_t)3 * d0, N, phi + (size_t)d0 * N);
         st = ERT_HIPST(hipGetLastError());
     }
     (void)hipStreamSynchronize(p->stream);
