@@ -195,7 +195,8 @@ def many_scattering_128(torch, ertvie, inputs, O, stream, args):
             steps += int(np.maximum(1, np.ceil(sb / (0.5 / 128) * (1 - 1e-12))).sum())
         out["recover_phi"] = {"directions": len(dirs), "seconds": ts, "cell_directions_per_s": N * len(dirs) / ts,
                               "ray_steps": steps, "steps_per_s": steps / ts,
-                              "l2_gather_bytes_per_s": steps * 16 * 8 / ts}
+                              # eight interpolation corners of one (sigma_t, Q) pair, 16 bytes each
+                              "l2_gather_bytes_per_s": steps * 8 * 16 / ts}
         log("128^3 S.3:", json.dumps(out["recover_phi"]))
     return out
 
