@@ -1,13 +1,18 @@
-"""Benchmark: FMM matvec throughput of the isotropic-ERT volume-integral operator on one
-MI355X, with the dominant kernel's roofline fraction, time-to-solution and the CPU oracle.
+"""Benchmark: FMM matvec throughput of the isotropic-ERT volume-integral operator and time to
+a 1e-8 solve on one MI355X, with the dominant kernel's roofline fraction and the CPU oracle.
 
-One step = one application of (I - K) u = u - A (sigma_s u) through the whole FMM
-(gather, near field, P2M, compress, M2L, reduce, decompress, L2P, assembly) on the 3D unit
-cube 32^3 workload (sigma_t = 5, sigma_s = 4, four seeded Gaussian sources), inputs resident
-in HBM, FP32 bulk with FP64 assembly.  Prints one JSON line on stdout (progress on stderr).
+Headline workload: the many-scattering medium at 128^3 (N = 2,097,152; base sigma_t ~ U[5,50]
+plus 8 seeded blobs, sigma_s = 0.99 sigma_t, one face source; ray-quadrature kernel).  One
+step = one application of (I - K) u = u - A (sigma_s u) through the whole FMM in FP64 (gather,
+near field over the cached kernel blocks, P2M, M2M, M2L over the cached per-pair translations,
+L2L, L2P, assembly with the FP64 self term), inputs resident in HBM, replayed from a captured
+graph.  Beside it: time to a 1e-8 true residual for plain FP64 GMRES, the mixed-precision
+refinement, and both with the learned and the FFT-based right preconditioners.  Other
+workloads (32^3 homogeneous, 64^3 blob medium, 64 right-hand sides) go to "extra".
+Prints one JSON line on stdout (progress on stderr).
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--prec fp32|fp64|bf16x3]
-                  [--no-cpu-baseline] [--no-solve] [--no-c3]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-solve]
+                  [--headline-only] [--form F]
 """
 import argparse
 import itertools
@@ -31,6 +36,8 @@ def log(*a):
 
 
 def timed_applies(torch, plan, x, y, op, steps, warmup, **kw):
+    """Wall time per apply (ms) of `steps` applies after `warmup` untimed ones, bracketed by
+    device synchronisations."""
     for _ in range(warmup):
         plan.apply(x, y, op=op, **kw)
     torch.cuda.synchronize()
@@ -105,100 +112,6 @@ def roofline_of(info, stage_ms, launches, prec, dim=3, workload=None, forms=None
             "kernel_flops_per_launch": flops / nl,
             "m2l_tflops": m2l_flops / (stage_ms["m2l"] * 1e-3) / 1e12 if stage_ms.get("m2l") else None,
             "near_tflops": near_flops / (stage_ms["near"] * 1e-3) / 1e12 if stage_ms.get("near") else None}
-
-
-def many_scattering_128(torch, ertvie, inputs, O, stream, args):
-    """The many-scattering recipe at its full 128^3 size (N = 2,097,152): heterogeneous
-    caches for the FP64 operator at Chebyshev order 6 (at order 8 the far field alone would
-    need 640 GB) and for the order-4 FP32 inner operator, sharing the near blocks; apply
-    times, the apply error on sampled rows against the oracle, and time to 1e-8 for plain
-    FP64 GMRES and the mixed solve (with the network when weights for this grid exist)."""
-    case = inputs.make_case("c5", n=(128, 128, 128), seed=0)
-    N = int(np.prod(case["n"]))
-    fd = torch.from_numpy(case["f"]).cuda()
-    out = {"workload": "128^3 many-scattering medium, seed 0, leaf 8^3, n = 6 (FP64) / 4 (FP32 inner, near field "
-                       "read as BF16)"}
-    torch.cuda.empty_cache()
-    t = time.perf_counter()
-    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=6, inner_cheb_n=4,
-                               inner_near16=True) as plan:
-        out["fmm_fp64"] = plan.fmm_info("fp64")
-        log("128^3: FP64 operator built, %.1f s" % (time.perf_counter() - t))
-        plan.fmm_info("fp32")
-        torch.cuda.synchronize()
-        out["plan_s"] = time.perf_counter() - t
-        log("128^3: plan %.1f s" % out["plan_s"])
-        x = torch.from_numpy(inputs.random_vector(N, 21)).cuda()
-        y = torch.empty_like(x)
-        for prec in ("fp64", "fp32"):
-            out["apply_ms_" + prec] = timed_applies(torch, plan, x, y, ertvie.OP_A, 5, 2, prec=prec)
-            if prec == "fp64":
-                yh = y.cpu().numpy()
-        log("128^3 apply ms: fp64 %.2f, fp32 inner %.2f" % (out["apply_ms_fp64"], out["apply_ms_fp32"]))
-        P = O.Problem(3, case["n"], case["h"], 1, case["sigma_t"], case["sigma_s"])
-        rows = np.random.default_rng(3).choice(N, size=32, replace=False)
-        yo = P.apply_rows(inputs.random_vector(N, 21), rows, op=2)
-        out["fp64_apply_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(yh[rows] - yo) / np.linalg.norm(yo))
-        log("128^3 apply error on 32 rows: %.3e" % out["fp64_apply_rel_l2_vs_oracle_rows"])
-        U = torch.empty_like(fd)
-        keys = ("iters", "matvecs", "restarts", "t_solve", "rel_resid_true", "rejected", "precond_applies")
-        # the Krylov basis is allocated for max_iter vectors (16.8 MB each at this size)
-        r = plan.solve(fd, U, tol=1e-8, max_iter=150)
-        out["plain_fp64_gmres"] = {k: r[k] for k in keys}
-        log("128^3 plain:", json.dumps(out["plain_fp64_gmres"]))
-        U0 = U.clone()
-        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, max_iter=150)
-        out["mixed"] = {k: r[k] for k in keys}
-        out["mixed_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        log("128^3 mixed:", json.dumps(out["mixed"]))
-        out["fft_precond"] = plan.fft_info()
-        out["fft_precond"]["apply_ms"] = timed_fft(torch, plan, x, y, 20)
-        plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, max_iter=150, precond_fft=True)   # warm
-        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, max_iter=150, precond_fft=True)
-        out["mixed_fft"] = {k: r[k] for k in keys}
-        out["mixed_fft_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        log("128^3 mixed + FFT-based preconditioner:", json.dumps(out["mixed_fft"]))
-        if os.path.exists(WEIGHTS_FFT):
-            w = np.load(WEIGHTS_FFT)
-            with ertvie.Net(case["n"], stream=stream) as net:
-                net.set_params(w["params"])
-                kw = dict(tol=1e-8, mixed=True, inner_tol=1e-3, max_iter=150, precond_fft=True, precond=net,
-                          precond_steps=int(json.loads(str(w["meta"]))["precond_steps"]))
-                plan.solve(fd, U, **kw)
-                r = plan.solve(fd, U, **kw)
-                out["mixed_fft_learned"] = {k: r[k] for k in keys}
-                out["mixed_fft_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-                log("128^3 mixed + FFT + network:", json.dumps(out["mixed_fft_learned"]))
-        for k in ("mixed", "mixed_fft", "mixed_fft_learned"):
-            if k in out:
-                out[k]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / out[k]["t_solve"]
-        # Algorithm 1 S.3 from the solution: Phi for 26 directions (cube faces, edges, corners)
-        dirs = np.array([d for d in itertools.product((-1, 0, 1), repeat=3) if any(d)], dtype=np.float64)
-        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-        phi = torch.empty((len(dirs), N), dtype=torch.float64, device="cuda")
-        plan.transport(U0, fd, dirs, phi)                    # warm
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        plan.transport(U0, fd, dirs, phi)
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t
-        # ray steps of the sweep (the same count rule as the kernel), for the per-step rate
-        xc = inputs.centres(case["n"], case["h"])
-        steps = 0
-        for v in dirs:
-            sb = np.full(N, np.inf)
-            for a in range(3):
-                if v[a] > 0:
-                    sb = np.minimum(sb, xc[:, a] / v[a])
-                elif v[a] < 0:
-                    sb = np.minimum(sb, (1.0 - xc[:, a]) / (-v[a]))
-            steps += int(np.maximum(1, np.ceil(sb / (0.5 / 128) * (1 - 1e-12))).sum())
-        out["recover_phi"] = {"directions": len(dirs), "seconds": ts, "cell_directions_per_s": N * len(dirs) / ts,
-                              "ray_steps": steps, "steps_per_s": steps / ts,
-                              # eight interpolation corners of one (sigma_t, Q) pair, 16 bytes each
-                              "l2_gather_bytes_per_s": steps * 8 * 16 / ts}
-        log("128^3 S.3:", json.dumps(out["recover_phi"]))
-    return out
 
 
 # Sec. 5.3, Experiments V and VI: GMRES iterations to 1e-12 without and with the
@@ -407,79 +320,291 @@ WEIGHTS_FFT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_16
                            "precond_c5_64_fft.npz")
 
 
-def many_scattering_solves(torch, ertvie, inputs, stream, args):
-    """Time to a 1e-8 true residual on the 64^3 many-scattering medium (base sigma_t ~ U[5,50]
-    plus blobs, albedo 0.99, one face source; held-out seed 0): plain FP64 GMRES on the FP64
-    FMM, the FP64-refined solve with FP32 inner GMRES on the order-4 FMM, and the same with the
-    trained network as right preconditioner (flexible GMRES) when its weights are present."""
-    case = inputs.make_case("c5", n=(64, 64, 64), seed=0)
+
+
+# The headline's kernel caches: FMM of Chebyshev order 6 for the FP64 operator (order 8 would
+# need 640 GB for the far field alone), order 4 for the FP32 inner operator of mixed solves,
+# whose near field reads the BF16-rounded plane of the shared near-field cache.
+C5_N = 128
+C5_CHEB, C5_INNER_CHEB = 6, 4
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counter runs,
+# scaled by the readings of a 256 MiB device copy (profiles/*_hbm_traffic.md).  Keyed by
+# (workload, precision, stage of the kernel, execution forms); a combination without counters,
+# or a kernel changed since they were taken, reports null.
+MEASURED_TRAFFIC = dict(MEASURED_TRAFFIC)
+
+
+def het_roofline(info, stage_ms, launches, N, near_plane_bytes=4, workload=None):
+    """Roofline of the cached-pair products of a heterogeneous plan (HBM-bound: every cached
+    kernel value is read once per apply for one right-hand side).  Algorithmic bytes:
+    near field, one value per point pair of neighbouring leaves, the diagonal included
+    (near_pairs + N values of near_plane_bytes each); far field, one Kp x Kp FP32 matrix per
+    interaction-list pair of every level.  The dominant stage (near or m2l) by time is the
+    reported kernel; time per launch from the stage events."""
+    Kp = info["nodes_padded"]
+    near_bytes = (info["near_pairs"] + N) * near_plane_bytes
+    far_bytes = sum(info["far_pairs"][l] * Kp * Kp * 4.0 for l in range(2, info["levels"] + 1))
+    cand = {"near": (near_bytes, stage_ms.get("near", 0.0), launches.get("near", 1.0)),
+            "m2l": (far_bytes, stage_ms.get("m2l", 0.0), launches.get("m2l", 1.0))}
+    dom = max(cand, key=lambda k: cand[k][1])
+    nbytes, tms, nl = cand[dom]
+    per = nbytes / nl
+    t = tms / nl * 1e-3
+    achieved = per / t / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / (HBM / 1e9), "traffic": MEASURED_TRAFFIC.get((workload, "fp64", dom)),
+            "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
+            "near_gb_per_s": near_bytes / (stage_ms["near"] * 1e-3) / 1e9 if stage_ms.get("near") else None,
+            "m2l_gb_per_s": far_bytes / (stage_ms["m2l"] * 1e-3) / 1e9 if stage_ms.get("m2l") else None,
+            "near_bytes_per_apply": near_bytes, "far_bytes_per_apply": far_bytes}
+
+
+def c5_headline(torch, ertvie, inputs, O, stream, args):
+    """The many-scattering medium at 128^3: FP64 FMM apply throughput (the metric), its stage
+    profile and roofline, time to 1e-8 for plain FP64 GMRES and the mixed and preconditioned
+    solves, and the oracle on sampled rows (its time is the CPU baseline, its values the
+    parity check of the timed apply)."""
+    n = (C5_N,) * 3
+    case = inputs.make_case("c5", n=n, seed=0)
+    N = int(np.prod(n))
     fd = torch.from_numpy(case["f"]).cuda()
-    out = {"workload": "64^3 many-scattering medium, seed 0, tol 1e-8", "inner_cheb_n": 4, "inner_near16": 1}
+    res = {"workload": "3D unit cube 128^3 (N=2,097,152), many-scattering medium seed 0: sigma_t = U[5,50] + 8 "
+                       "seeded blobs, sigma_s = 0.99 sigma_t, one face source; midpoint ray-quadrature kernel; FMM "
+                       "leaf 8^3, Chebyshev order %d (FP64 operator), %d (FP32 inner operator, near field read "
+                       "as BF16)" % (C5_CHEB, C5_INNER_CHEB)}
+    torch.cuda.empty_cache()
     t = time.perf_counter()
-    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, inner_cheb_n=4,
-                               inner_near16=True) as plan:
-        plan.fmm_info("fp64")
+    plan = ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=C5_CHEB,
+                                 inner_cheb_n=C5_INNER_CHEB, inner_near16=True)
+    try:
+        info = plan.fmm_info("fp64")
+        log("128^3: FP64 operator built, %.1f s" % (time.perf_counter() - t))
         plan.fmm_info("fp32")
         torch.cuda.synchronize()
+        res["plan_s"] = time.perf_counter() - t
+        log("128^3: plan %.1f s" % res["plan_s"])
+        x = torch.from_numpy(inputs.random_vector(N, 21)).cuda()
+        y = torch.empty_like(x)
+        plan.apply(x, y, op=ertvie.OP_A)          # first call
+        plan.apply(x, y, op=ertvie.OP_A)          # captures the apply graph
+        ms = timed_applies(torch, plan, x, y, ertvie.OP_A, args.steps, args.warmup)
+        res["apply_ms_fp64"] = ms
+        yh = y.cpu().numpy()
+        log("128^3 FP64 apply: %.3f ms, %.1f Mpts/s" % (ms, N / (ms * 1e-3) / 1e6))
+        st_ms, st_n = stage_profile(plan, x, y, ertvie.OP_A, max(3, min(args.steps, 10)))
+        res["stage_ms_fp64"] = st_ms
+        log("128^3 FP64 stage ms:", json.dumps({k: round(v, 3) for k, v in st_ms.items()}))
+        roof = het_roofline(info, st_ms, st_n, N, workload="c5_128")
+        log("128^3 roofline:", json.dumps(roof))
+        plan.apply(x, y, op=ertvie.OP_A, prec="fp32")
+        plan.apply(x, y, op=ertvie.OP_A, prec="fp32")
+        res["apply_ms_fp32_inner"] = timed_applies(torch, plan, x, y, ertvie.OP_A, max(3, args.steps // 2), 1,
+                                                   prec="fp32")
+        res["fmm_fp64"] = info
+        if not args.no_solve:
+            res.update(c5_solves(torch, ertvie, plan, fd, N))
+        if not args.no_solve and not args.headline_only:
+            res["recover_phi"] = transport_s3(torch, inputs, plan, fd, res.get("_U0"), N)
+        res.pop("_U0", None)
+    finally:
+        plan.close()
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on sampled rows of the same apply: ~20 s of CPU on 16 cores
+        cores = len(os.sched_getaffinity(0))
+        nrows = max(4, min(cores, 16))
+        rows = np.random.default_rng(3).choice(N, size=nrows, replace=False)
+        P = O.Problem(3, case["n"], case["h"], 1, case["sigma_t"], case["sigma_s"])
+        t = time.perf_counter()
+        yo = P.apply_rows(inputs.random_vector(N, 21), rows, op=2, nthreads=cores)
+        dt = time.perf_counter() - t
+        res["fp64_apply_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(yh[rows] - yo) / np.linalg.norm(yo))
+        res["oracle_rows"] = nrows
+        full_s = dt * N / nrows
+        cpu = {"value": N / full_s / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
+               "sample": "%d sampled rows of the dense FP64 apply of (I - K) on the 128^3 workload (ray-quadrature "
+                         "kernel), %.1f s on %d threads, extrapolated by N/rows to %.3g s per apply"
+                         % (nrows, dt, cores, full_s)}
+        log("128^3 apply error on %d rows: %.3e; cpu oracle: %s" % (nrows, res["fp64_apply_rel_l2_vs_oracle_rows"],
+                                                                    json.dumps(cpu)))
+    return ms, roof, res, cpu
+
+
+def c5_solves(torch, ertvie, plan, fd, N):
+    """Time to a 1e-8 true residual at 128^3 (each solve once untimed for graph capture and
+    tuning, then timed): plain FP64 GMRES; the FP64-refined solve with FP32 inner GMRES on the
+    order-4 operator (mixed); mixed with the learned preconditioner; mixed with the FFT-based
+    preconditioner on the inner solves; and that with the network after it."""
+    out = {}
+    keys = ("iters", "matvecs", "restarts", "t_solve", "rel_resid_true", "rejected", "precond_applies")
+    U = torch.empty_like(fd)
+    # the Krylov basis is allocated for max_iter vectors (16.8 MB each at this size)
+    plan.solve(fd, U, tol=1e-8, max_iter=150)
+    r = plan.solve(fd, U, tol=1e-8, max_iter=150)
+    out["plain_fp64_gmres"] = {k: r[k] for k in keys}
+    U0 = U.clone()
+    out["_U0"] = U0
+    log("128^3 plain:", json.dumps(out["plain_fp64_gmres"]))
+    runs = [("mixed", dict(mixed=True, inner_tol=1e-2), None),
+            ("mixed_fft", dict(mixed=True, inner_tol=1e-3, precond_fft=True), None)]
+    for name, path in (("mixed_learned", WEIGHTS), ("mixed_fft_learned", WEIGHTS_FFT)):
+        if os.path.exists(path):
+            w = np.load(path)
+            meta = json.loads(str(w["meta"]))
+            kw = dict(mixed=True, inner_tol=float(meta.get("inner_tol", 1e-2)),
+                      precond_steps=int(meta.get("precond_steps", 0)))
+            if "fft" in name:
+                kw["precond_fft"] = True
+            runs.append((name, kw, w["params"]))
+    for name, kw, params in runs:
+        net = None
+        if params is not None:
+            net = ertvie.Net(tuple(int(v) for v in (C5_N,) * 3), stream=plan.stream)
+            net.set_params(params)
+            kw = dict(kw, precond=net)
+        try:
+            plan.solve(fd, U, tol=1e-8, max_iter=150, **kw)
+            r = plan.solve(fd, U, tol=1e-8, max_iter=150, **kw)
+        finally:
+            if net is not None:
+                net.close()
+        out[name] = {k: r[k] for k in keys}
+        out[name]["vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
+        out[name]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / r["t_solve"]
+        log("128^3 %s:" % name, json.dumps(out[name]))
+    return out
+
+
+def transport_s3(torch, inputs, plan, fd, U0, N):
+    """Algorithm 1 S.3 from the solution: Phi for 26 directions (cube faces, edges, corners)."""
+    if U0 is None:
+        return None
+    n = int(round(N ** (1.0 / 3.0)))
+    dirs = np.array([d for d in itertools.product((-1, 0, 1), repeat=3) if any(d)], dtype=np.float64)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    phi = torch.empty((len(dirs), N), dtype=torch.float64, device="cuda")
+    plan.transport(U0, fd, dirs, phi)                    # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan.transport(U0, fd, dirs, phi)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    # ray steps of the sweep (the same count rule as the kernel), for the per-step rate
+    xc = inputs.centres((n, n, n), 1.0 / n)
+    steps = 0
+    for v in dirs:
+        sb = np.full(N, np.inf)
+        for a in range(3):
+            if v[a] > 0:
+                sb = np.minimum(sb, xc[:, a] / v[a])
+            elif v[a] < 0:
+                sb = np.minimum(sb, (1.0 - xc[:, a]) / (-v[a]))
+        steps += int(np.maximum(1, np.ceil(sb / (0.5 / n) * (1 - 1e-12))).sum())
+    out = {"directions": len(dirs), "seconds": ts, "cell_directions_per_s": N * len(dirs) / ts,
+           "ray_steps": steps, "steps_per_s": steps / ts,
+           # eight interpolation corners of one (sigma_t, Q) pair, 16 bytes each
+           "l2_gather_bytes_per_s": steps * 8 * 16 / ts}
+    log("128^3 S.3:", json.dumps(out))
+    return out
+
+
+def c2_32(torch, ertvie, inputs, O, stream, args):
+    """32^3 homogeneous workload (sigma_t = 5, sigma_s = 4, four Gaussian sources): FP32 FMM
+    apply with compressed translations, its stage profile and the roofline of the grouped
+    near-field + translation launch, the FP64 and BF16x3 applies, the dense FP64 apply, and
+    time to 1e-8 (FP64 GMRES and the mixed solve)."""
+    case = inputs.make_case("c2", seed=0)
+    N = int(np.prod(case["n"]))
+    f = torch.from_numpy(case["f"]).cuda()
+    y = torch.empty_like(f)
+    out = {"workload": "3D unit cube 32^3 (N=32768), homogeneous sigma_t=5 sigma_s=4, four seeded Gaussian "
+                       "sources; FMM leaf 8^3 cells, n=8, translations compressed at 1e-5; FP32 apply of I - K"}
+    t = time.perf_counter()
+    with ertvie.plan_from_case(case, method="fmm", prec="fp32", stream=stream, svd_tol=SVD_TOL, form=args.form) as plan:
+        plan.apply(f, y, op=ertvie.OP_A)          # builds the FMM operators, tunes the execution forms
+        plan.apply(f, y, op=ertvie.OP_A)          # captures the apply graph
+        torch.cuda.synchronize()
         out["plan_s"] = time.perf_counter() - t
-        U = torch.empty_like(fd)
-        keys = ("iters", "matvecs", "restarts", "t_solve", "rel_resid_true", "rejected", "precond_applies")
-        plan.solve(fd, U, tol=1e-8)                           # graphs and tuning of both operators
-        plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2)
-        r = plan.solve(fd, U, tol=1e-8)
-        out["plain_fp64_gmres"] = {k: r[k] for k in keys}
-        U0 = U.clone()
-        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2)
-        out["mixed"] = {k: r[k] for k in keys}
-        out["mixed_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        if os.path.exists(WEIGHTS):
-            w = np.load(WEIGHTS)
-            with ertvie.Net((64, 64, 64), stream=stream) as net:
-                net.set_params(w["params"])
-                plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, precond=net)
-                r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-2, precond=net)
-                out["mixed_learned"] = {k: r[k] for k in keys}
-                out["mixed_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        # the paper's FFT-based preconditioner (Sec. 4.4) of the mean medium
-        x = torch.from_numpy(inputs.random_vector(plan.N, 21)).cuda()
-        z = torch.empty_like(x)
-        out["fft_precond"] = plan.fft_info()
-        out["fft_precond"]["apply_ms"] = timed_fft(torch, plan, x, z, 50)
-        plan.solve(fd, U, tol=1e-8, precond_fft=True)
-        r = plan.solve(fd, U, tol=1e-8, precond_fft=True)
-        out["plain_fp64_fft"] = {k: r[k] for k in keys}
-        plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, precond_fft=True)
-        r = plan.solve(fd, U, tol=1e-8, mixed=True, inner_tol=1e-3, precond_fft=True)
-        out["mixed_fft"] = {k: r[k] for k in keys}
-        out["mixed_fft_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        if os.path.exists(WEIGHTS_FFT):
-            w = np.load(WEIGHTS_FFT)
-            with ertvie.Net((64, 64, 64), stream=stream) as net:
-                net.set_params(w["params"])
-                kw = dict(tol=1e-8, mixed=True, inner_tol=1e-3, precond_fft=True, precond=net,
-                          precond_steps=int(json.loads(str(w["meta"]))["precond_steps"]))
-                plan.solve(fd, U, **kw)
-                r = plan.solve(fd, U, **kw)
-                out["mixed_fft_learned"] = {k: r[k] for k in keys}
-                out["mixed_fft_learned_vs_plain_rel_l2"] = float(torch.linalg.norm(U - U0) / torch.linalg.norm(U0))
-        for k in ("mixed", "mixed_learned", "plain_fp64_fft", "mixed_fft", "mixed_fft_learned"):
-            if k in out:
-                out[k]["speedup_vs_plain"] = out["plain_fp64_gmres"]["t_solve"] / out[k]["t_solve"]
-    log("many-scattering solves:", json.dumps(out))
+        ms = timed_applies(torch, plan, f, y, ertvie.OP_A, 50, 5)
+        yg = y.cpu().numpy()
+        st_ms, st_n = stage_profile(plan, f, y, ertvie.OP_A, 20)
+        info = plan.fmm_info()
+    info["leaf_boxes"] = int(np.prod([-(-n // info["leaf"]) for n in case["n"]]))
+    forms = "%d,%d" % (info["form_near"], info["form_far"][info["levels"]])
+    out.update({"apply_ms": ms, "mpts_per_s": N / (ms * 1e-3) / 1e6, "stage_ms": st_ms, "fmm": info,
+                "roofline": roofline_of(info, st_ms, st_n, "fp32", workload="c2", forms=forms)})
+    P = O.Problem(3, case["n"], case["h"], 0, case["sigma_t"], case["sigma_s"])
+    rows = np.random.default_rng(0).choice(N, size=256, replace=False)
+    yo = P.apply_rows(case["f"], rows, op=2)
+    out["rel_l2_vs_oracle_rows"] = float(np.linalg.norm(yg[rows] - yo) / np.linalg.norm(yo))
+    log("32^3 FP32 apply %.4f ms (%.1f Mpts/s), error on 256 rows %.2e, roofline %s"
+        % (ms, out["mpts_per_s"], out["rel_l2_vs_oracle_rows"], json.dumps(out["roofline"])))
+    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, svd_tol=SVD_TOL) as p64:
+        p64.apply(f, y, op=ertvie.OP_A)
+        p64.apply(f, y, op=ertvie.OP_A)
+        out["fp64_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, 20, 2)
+        y64 = y.cpu().numpy()
+        out["fp64_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(y64[rows] - yo) / np.linalg.norm(yo))
+        p64.apply(f, y, op=ertvie.OP_A, prec="bf16x3")
+        out["bf16x3_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, 20, 2, prec="bf16x3")
+        y16 = y.cpu().numpy()
+        out["bf16x3_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(y16[rows] - yo) / np.linalg.norm(yo))
+        out["direct_fp64_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, 2, 1, method="direct")
+        if not args.no_solve:
+            U = torch.empty_like(f)
+            p64.solve(f, U, tol=1e-8)                               # warm: FP64 graphs
+            p64.solve(f, U, tol=1e-8, mixed=True, inner_tol=1e-4)   # warm: builds the FP32 operator
+            i64 = p64.solve(f, U, tol=1e-8)
+            U64 = U.clone()
+            imx = p64.solve(f, U, tol=1e-8, mixed=True, inner_tol=1e-4)
+            out["solve"] = {"tol": 1e-8, "fp64_gmres_s": i64["t_solve"], "fp64_iters": i64["iters"],
+                            "fp64_rel_resid_true": i64["rel_resid_true"], "mixed_s": imx["t_solve"],
+                            "mixed_inner_iters": imx["iters"], "mixed_refinements": imx["restarts"],
+                            "mixed_rel_resid_true": imx["rel_resid_true"],
+                            "mixed_vs_fp64_rel_l2": float(torch.linalg.norm(U - U64) / torch.linalg.norm(U64))}
+    log("32^3:", json.dumps({k: v for k, v in out.items() if k not in ("fmm", "roofline")}))
+    return out, P, case
+
+
+def c3_64(torch, ertvie, inputs, O, stream):
+    """64^3 heterogeneous blob medium with the ray-quadrature kernel (cached pair
+    translations): FP32 FMM apply, stage profile, error on sampled rows."""
+    c3 = inputs.make_case("c3", seed=0)
+    N3 = int(np.prod(c3["n"]))
+    x3 = inputs.random_vector(N3, 11)
+    xd = torch.from_numpy(x3).cuda()
+    yd = torch.empty_like(xd)
+    t = time.perf_counter()
+    with ertvie.plan_from_case(c3, method="fmm", prec="fp32", stream=stream) as p3:
+        p3.apply(xd, yd, op=ertvie.OP_A)
+        p3.apply(xd, yd, op=ertvie.OP_A)
+        torch.cuda.synchronize()
+        t3plan = time.perf_counter() - t
+        ms3 = timed_applies(torch, p3, xd, yd, ertvie.OP_A, 5, 1)
+        y3 = yd.cpu().numpy()
+        st3, _ = stage_profile(p3, xd, yd, ertvie.OP_A, 3)
+    P3 = O.Problem(3, c3["n"], c3["h"], 1, c3["sigma_t"], c3["sigma_s"])
+    r3 = np.random.default_rng(7).choice(N3, size=24, replace=False)
+    y3o = P3.apply_rows(x3, r3, op=2)
+    out = {"workload": "64^3 blob medium seed 0, FP32 FMM (leaf 8^3, n = 8)", "plan_s": t3plan, "apply_ms": ms3,
+           "mpts_per_s": N3 / (ms3 * 1e-3) / 1e6, "stage_ms": st3,
+           "rel_l2_vs_oracle_rows": float(np.linalg.norm(y3[r3] - y3o) / np.linalg.norm(y3o))}
+    log("c3:", json.dumps(out))
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--no-c3", action="store_true")
-    ap.add_argument("--c5-128", action="store_true",
-                    help="also run the 128^3 many-scattering medium (plan ~1 min, ~250 GB of device memory)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 128^3 workload (applies, stage profile, solves)")
+    ap.add_argument("--form", type=int, default=None,
+                    help="fix the execution form of the 32^3 box-offset products (0..4) instead of timing them")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT-based preconditioner (64^3 and 128^3) and exit")
     ap.add_argument("--paper-exp3", action="store_true",
@@ -511,140 +636,27 @@ def main():
     if args.fft_only:
         print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
         return
-    case = inputs.make_case("c2", seed=0)
-    N = int(np.prod(case["n"]))
-    f = torch.from_numpy(case["f"]).to(dev)
-    y = torch.empty_like(f)
 
-    t = time.perf_counter()
-    plan = ertvie.plan_from_case(case, method="fmm", prec=args.prec, stream=stream, svd_tol=SVD_TOL)
-    plan.apply(f, y, op=ertvie.OP_A)          # builds the FMM operators, tunes the execution forms
-    plan.apply(f, y, op=ertvie.OP_A)          # captures the apply graph
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t
-    log("plan + tuning + capture: %.3f s" % t_plan)
-
-    ms = timed_applies(torch, plan, f, y, ertvie.OP_A, args.steps, args.warmup)
+    N = C5_N ** 3
+    ms, roofline, c5, cpu = c5_headline(torch, ertvie, inputs, O, stream, args)
     value = N / (ms * 1e-3) / 1e6
-    log("FMM apply (%s): %.4f ms/step, %.1f Mpts/s" % (args.prec, ms, value))
-    yg = y.cpu().numpy()
-
-    stage_ms, launches = stage_profile(plan, f, y, ertvie.OP_A, args.steps)
-    log("per-apply stage ms:", json.dumps({k: round(v, 5) for k, v in stage_ms.items()}))
-    info = plan.fmm_info()
-    info["leaf_boxes"] = int(np.prod([-(-n // info["leaf"]) for n in case["n"]]))
-    log("fmm:", json.dumps(info))
-    forms = "%d,%d" % (info["form_near"], info["form_far"][info["levels"]])
-    roofline = roofline_of(info, stage_ms, launches, args.prec, workload="c2", forms=forms)
-    log("roofline:", json.dumps(roofline))
-
-    P = O.Problem(3, case["n"], case["h"], 0, case["sigma_t"], case["sigma_s"])
-    rows = np.random.default_rng(0).choice(N, size=256, replace=False)
-    yo = P.apply_rows(case["f"], rows, op=2)
-    extra = {"plan_s": t_plan, "stage_ms": stage_ms, "fmm": info,
-             "rel_l2_vs_oracle_rows": float(np.linalg.norm(yg[rows] - yo) / np.linalg.norm(yo))}
-
-    # the same operator in the other precisions and by dense summation
-    with ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, svd_tol=SVD_TOL) as p64:
-        p64.apply(f, y, op=ertvie.OP_A)
-        p64.apply(f, y, op=ertvie.OP_A)
-        extra["fp64_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, args.steps, 2)
-        y64 = y.cpu().numpy()
-        extra["fp64_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(y64[rows] - yo) / np.linalg.norm(yo))
-        p64.apply(f, y, op=ertvie.OP_A, prec="bf16x3")
-        extra["bf16x3_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, args.steps, 2, prec="bf16x3")
-        y16 = y.cpu().numpy()
-        extra["bf16x3_rel_l2_vs_oracle_rows"] = float(np.linalg.norm(y16[rows] - yo) / np.linalg.norm(yo))
-        extra["direct_fp64_apply_ms"] = timed_applies(torch, p64, f, y, ertvie.OP_A, 2, 1, method="direct")
-        log("fp64 %.4f ms, bf16x3 %.4f ms, dense fp64 %.2f ms" % (extra["fp64_apply_ms"], extra["bf16x3_apply_ms"],
-                                                                  extra["direct_fp64_apply_ms"]))
+    extra = {"many_scattering_128cubed": c5}
+    if not args.headline_only:
+        extra["c2_32cubed_homogeneous"], _, _ = c2_32(torch, ertvie, inputs, O, stream, args)
+        extra["c2_recipe_64cubed_homogeneous"] = homogeneous_64(torch, ertvie, inputs, O, stream)
+        extra["c3_64cubed_heterogeneous"] = c3_64(torch, ertvie, inputs, O, stream)
         if not args.no_solve:
-            U = torch.empty_like(f)
-            p64.solve(f, U, tol=1e-8)                               # warm: FP64 graphs
-            p64.solve(f, U, tol=1e-8, mixed=True, inner_tol=1e-4)   # warm: builds the FP32 operator
-            t = time.perf_counter()
-            i64 = p64.solve(f, U, tol=1e-8)
-            t_fp64 = time.perf_counter() - t
-            U64 = U.cpu().numpy()
-            t = time.perf_counter()
-            imx = p64.solve(f, U, tol=1e-8, mixed=True, inner_tol=1e-4)
-            t_mixed = time.perf_counter() - t
-            Umx = U.cpu().numpy()
-            extra["solve"] = {"tol": 1e-8, "fp64_gmres_s": t_fp64, "fp64_iters": i64["iters"],
-                              "fp64_rel_resid_true": i64["rel_resid_true"], "mixed_s": t_mixed,
-                              "mixed_inner_iters": imx["iters"], "mixed_refinements": imx["restarts"],
-                              "mixed_rel_resid_true": imx["rel_resid_true"],
-                              "mixed_vs_fp64_rel_l2": float(np.linalg.norm(Umx - U64) / np.linalg.norm(U64))}
-            log("solve:", json.dumps(extra["solve"]))
-    plan.close()
-
-    if not args.no_solve and not args.no_c3:
-        extra["solve_many_scattering_64cubed"] = many_scattering_solves(torch, ertvie, inputs, stream, args)
-        extra["many_rhs_64cubed"] = many_rhs_64(torch, ertvie, inputs, stream)
-
+            extra["many_rhs_64cubed"] = many_rhs_64(torch, ertvie, inputs, stream)
     if args.paper_exp6:
         extra["paper_experiment_vi"] = paper_experiment_vi(torch, ertvie, inputs, stream)
-
     if args.paper_exp3:
         extra["paper_experiment_iii"] = paper_experiment_iii(torch, ertvie, inputs, stream)
-
-    if args.c5_128:
-        extra["many_scattering_128cubed"] = many_scattering_128(torch, ertvie, inputs, O, stream, args)
-
-    if not args.no_c3:
-        extra["c2_recipe_64cubed_homogeneous"] = homogeneous_64(torch, ertvie, inputs, O, stream)
-        # 64^3 heterogeneous blob medium with the ray-quadrature kernel (cached pair translations)
-        c3 = inputs.make_case("c3", seed=0)
-        N3 = int(np.prod(c3["n"]))
-        x3 = inputs.random_vector(N3, 11)
-        xd = torch.from_numpy(x3).to(dev)
-        yd = torch.empty_like(xd)
-        t = time.perf_counter()
-        with ertvie.plan_from_case(c3, method="fmm", prec="fp32", stream=stream) as p3:
-            p3.apply(xd, yd, op=ertvie.OP_A)
-            p3.apply(xd, yd, op=ertvie.OP_A)
-            torch.cuda.synchronize()
-            t3plan = time.perf_counter() - t
-            ms3 = timed_applies(torch, p3, xd, yd, ertvie.OP_A, 5, 1)
-            st3, _ = stage_profile(p3, xd, yd, ertvie.OP_A, 3)
-            y3 = yd.cpu().numpy()
-        P3 = O.Problem(3, c3["n"], c3["h"], 1, c3["sigma_t"], c3["sigma_s"])
-        r3 = np.random.default_rng(7).choice(N3, size=24, replace=False)
-        y3o = P3.apply_rows(x3, r3, op=2)
-        extra["c3_64cubed_heterogeneous"] = {
-            "plan_s": t3plan, "apply_ms": ms3, "mpts_per_s": N3 / (ms3 * 1e-3) / 1e6, "stage_ms": st3,
-            "rel_l2_vs_oracle_rows": float(np.linalg.norm(y3[r3] - y3o) / np.linalg.norm(y3o))}
-        log("c3:", json.dumps(extra["c3_64cubed_heterogeneous"]))
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cores = len(os.sched_getaffinity(0))
-        reps = 2
-        t = time.perf_counter()
-        for _ in range(reps):
-            P.apply(case["f"], op=2, nthreads=cores)
-        dt = (time.perf_counter() - t) / reps
-        cpu = {"value": N / dt / 1e6, "unit": "Mpts/s", "cores": cores, "kind": "oracle",
-               "sample": "%d full dense FP64 applies of (I - K) on the 32^3 workload, %.2f s each" % (reps, dt)}
-        log("cpu oracle:", json.dumps(cpu))
-        # one thread, as the paper's own timings: a row sample, extrapolated to the whole apply
-        rows1 = np.random.default_rng(11).choice(N, size=2048, replace=False)
-        t = time.perf_counter()
-        P.apply_rows(case["f"], rows1, op=2, nthreads=1)
-        dt1 = (time.perf_counter() - t) * N / len(rows1)
-        extra["cpu_oracle_one_thread"] = {
-            "value": N / dt1 / 1e6, "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-            "sample": "2048 sampled rows of the dense FP64 apply, extrapolated by N/rows to %.1f s per apply" % dt1}
-        log("cpu oracle, one thread:", json.dumps(extra["cpu_oracle_one_thread"]))
 
     out = {"metric": "FMM matvec Mpts/s; time to 1e-8 solve, plain FP64 GMRES vs mixed+learned (1 GPU)",
            "value": value, "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32"}[args.prec],
-           "data": "synthetic",
-           "config": {"workload": "3D unit cube 32^3 (N=32768), homogeneous sigma_t=5 sigma_s=4, four seeded "
-                                  "Gaussian sources; FMM leaf 8^3 cells, n=8, translations compressed at 1e-5",
-                      "op": "u - K(sigma_s u)", "prec": args.prec, "nrhs": 1},
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": c5["workload"], "op": "u - K(sigma_s u)", "prec": "fp64", "nrhs": 1},
            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(out), flush=True)
 

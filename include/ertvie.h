@@ -128,6 +128,14 @@ typedef struct {
                          the high half rounded to BF16 and the exact remainder: FP64 applies,
                          and FP32 applies without this option, read both and rebuild the FP32
                          value exactly.  0 or 1 */
+    int form[2];      /* FMM, homogeneous media: execution form of the box-offset products,
+                         [0] for the near field and [1] for the far-field translations.
+                         0 -> timed on first use per right-hand-side count (the fastest of
+                         the forms that apply is kept); f + 1 -> always form f:
+                         0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64,
+                         3 16x64, 4 (FP32) 64x16 tiles with the source columns staged in LDS
+                         (a form that does not apply to a product leaves it to the timing).
+                         Fixed forms make runs reproducible bit for bit across plans */
 } ert_vie_opts;
 
 typedef struct {

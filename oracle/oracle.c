@@ -607,7 +607,9 @@ void oracle_apply_rows(int dim, const long* n, double h, int kernel, const doubl
     og_prepare(&g);
     long N = og_count(&g);
     (void)nthreads;
-#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    /* one row per scheduling chunk: a row costs O(N) kernel evaluations, so a few
+     * sampled rows still spread over every thread */
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (long i = 0; i < nrows; ++i) {
         long j = rows[i];
         double dj;

@@ -139,7 +139,7 @@ ert_status plan_apply(ert_plan_impl* p, int op, int method, int prec, const doub
 
 ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Phi, double* X, int nb, double rtol,
                        int maxit, int restart, bool check_true, int* iters_out, int* cycles_out, int* matvecs_out,
-                       double* est_out, double* true_out, bool* conv_out, int pk);
+                       double* est_out, double* true_out, bool* conv_out, int pk, bool* breakdown_out);
 
 namespace {
 
@@ -164,6 +164,20 @@ ert_status ensure_workspace(ert_plan_impl* p, size_t vec_elems, size_t red_elems
         if (hipMalloc(&p->d_red, red_elems * sizeof(double)) != hipSuccess) return ERT_ENOMEM;
         p->red_elems = red_elems;
     }
+    return ERT_OK;
+}
+
+ert_status ensure_solve_scratch(ert_plan_impl* p, size_t elems)
+{
+    if (elems <= p->solve_elems) return ERT_OK;
+    if (p->d_solve) (void)hipFree(p->d_solve);
+    p->d_solve = nullptr;
+    p->solve_elems = 0;
+    if (hipMalloc(&p->d_solve, elems * sizeof(double)) != hipSuccess) {
+        record_error("ert_vie_solve: device allocation of the solve vectors failed");
+        return ERT_ENOMEM;
+    }
+    p->solve_elems = elems;
     return ERT_OK;
 }
 
@@ -330,20 +344,21 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
 // Refinement with the learned preconditioner and its residual check: each
 // step computes a correction d by flexible GMRES (at most precond_steps Arnoldi
 // steps, stopping at inner_tol) on the inner operator, and keeps U + d only if
-// the true residual of the outer operator decreases; a rejected step is redone
-// without the network (plain GMRES, or with the fixed preconditioner `kind`
-// alone) with the same budget.  r and d are caller scratch (N each).
-ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec_inner, NetImpl* net, int kind,
-                          const double* phi, double* U, double* r, double* d, const ert_solve_opts& so,
+// the true residual phi - (I - K)(U + d) decreases, with the residual taken
+// with the FP64 operator whatever the inner precision; a rejected step is
+// redone without the network (plain GMRES, or with the fixed preconditioner
+// `kind` alone) with the same budget, and when that step does not lower the
+// residual either the refinement stops (ERT_ENOCONV from the caller).
+// r, d: caller scratch (N each); trial: caller scratch (2 N).
+ert_status learned_refine(ert_plan_impl* p, int method, int prec_inner, NetImpl* net, int kind, const double* phi,
+                          double* U, double* r, double* d, double* trial, const ert_solve_opts& so,
                           ert_solve_info* inf)
 {
     const long N = p->N;
+    const int prec_outer = ERT_FP64;
     const int steps = so.precond_steps > 0 ? so.precond_steps : 10;
     ERT_TRY(dev_zero(p->stream, U, N));
     ERT_HIP(hipMemcpyAsync(r, phi, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-    // trial vector U + d lives in a scratch buffer of its own
-    double* trial = nullptr;
-    ERT_HIP(hipMalloc(&trial, 2 * N * sizeof(double)));
     double* rt = trial + N;
     ert_status st = ERT_OK;
     auto norm = [&](const double* v) {
@@ -354,7 +369,8 @@ ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec
     const double pnorm = norm(phi);
     double rnorm = pnorm;
     int used = 0;
-    for (int outer = 0; outer < 1000 && st == ERT_OK; ++outer) {
+    bool stalled = false;
+    for (int outer = 0; outer < 1000 && st == ERT_OK && !stalled; ++outer) {
         inf->rel_resid_true = pnorm > 0 ? rnorm / pnorm : 0.0;
         if (rnorm <= so.tol * pnorm) { inf->converged = 1; break; }
         if (used >= so.max_iter) break;
@@ -382,16 +398,16 @@ ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec
             const double tn = norm(rt);
             if (st != ERT_OK) break;
             // the check: keep the step only if the true residual went down
-            if (tn < rnorm || attempt == 1) {
+            if (tn < rnorm) {
                 accepted = true;
-                if (tn < rnorm) {
-                    st = ERT_HIPST(hipMemcpyAsync(U, trial, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-                    if (st == ERT_OK)
-                        st = ERT_HIPST(hipMemcpyAsync(r, rt, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-                    rnorm = tn;
-                }
-            } else {
+                st = ERT_HIPST(hipMemcpyAsync(U, trial, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+                if (st == ERT_OK)
+                    st = ERT_HIPST(hipMemcpyAsync(r, rt, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+                rnorm = tn;
+            } else if (attempt == 0 && net) {
                 inf->rejected++;
+            } else {
+                stalled = true;   // the step without the network made no progress either
             }
         }
         inf->restarts = outer + 1;
@@ -401,8 +417,52 @@ ert_status learned_refine(ert_plan_impl* p, int method, int prec_outer, int prec
         if (rnorm <= so.tol * pnorm) inf->converged = 1;
     }
     (void)hipStreamSynchronize(p->stream);
-    (void)hipFree(trial);
     return st;
+}
+
+// Column-by-column completion of a block solve after a block breakdown (a zero,
+// repeated or already solved column leaves the residual block without an
+// orthonormal basis): with R = Phi - (I - K) X, every column whose residual
+// exceeds tol ||Phi_b|| is finished by GMRES on (I - K) d = R_b with the same
+// operator and fixed right preconditioner, X_b += d.  R and d are scratch
+// (N nrhs and N).  Fills iters, matvecs, rel_resid_true (worst column) and
+// converged of inf.
+ert_status finish_columns(ert_plan_impl* p, int method, int prec, const double* Phi, double* X, double* R, double* d,
+                          int nrhs, const ert_solve_opts& so, int kind, ert_solve_info* inf)
+{
+    const long N = p->N;
+    ERT_TRY(apply_dispatch(p, ERT_OP_A, method, prec, X, R, nrhs));
+    inf->matvecs++;
+    ERT_TRY(dev_sub(p->stream, R, Phi, R, N * nrhs));
+    ert_status st = ERT_OK;
+    auto norm = [&](const double* v) {
+        ert_status s2 = ensure_workspace(p, 3 * N, (size_t)kPartials * 4 + 16);
+        if (s2 != ERT_OK) { st = s2; return 0.0; }
+        return dev_norm(p, v, p->d_red, p->d_red + (size_t)kPartials * 4, &st);
+    };
+    Precond pc;
+    pc.kind = kind;
+    double worst = 0.0;
+    for (int b = 0; b < nrhs; ++b) {
+        const double pn = norm(Phi + (size_t)b * N);
+        const double rn = norm(R + (size_t)b * N);
+        ERT_TRY(st);
+        if (rn <= so.tol * pn) {
+            worst = std::max(worst, pn > 0.0 ? rn / pn : 0.0);
+            continue;
+        }
+        RunStats rs;
+        const int budget = std::max(1, so.max_iter - inf->iters);
+        ERT_TRY(gmres_run(p, method, prec, R + (size_t)b * N, d, std::min(0.5, so.tol * pn / rn), budget, so.restart,
+                          true, &rs, &pc));
+        inf->iters += rs.iters;
+        inf->matvecs += rs.matvecs;
+        ERT_TRY(dev_add(p->stream, X + (size_t)b * N, d, N));
+        worst = std::max(worst, rs.true_rel * rn / pn);
+    }
+    inf->rel_resid_true = worst;
+    inf->converged = worst <= so.tol ? 1 : 0;
+    return ERT_OK;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -454,6 +514,7 @@ void ert_vie_destroy(ert_vie_plan_t p)
     (void)hipFree(p->d_itab);
     (void)hipFree(p->d_ws);
     (void)hipFree(p->d_red);
+    (void)hipFree(p->d_solve);
     delete p;
 }
 
@@ -472,6 +533,8 @@ ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const d
     if (o.leaf < 0 || o.leaf > 8 || o.nrhs_max < 0 || !std::isfinite(o.svd_tol) || o.svd_tol >= 1.0)
         return ERT_EINVAL;
     if ((o.inner_cheb_n != 0 && (o.inner_cheb_n < 2 || o.inner_cheb_n > 8)) || (o.inner_near16 != 0 && o.inner_near16 != 1)) return ERT_EINVAL;
+    for (int i = 0; i < 2; ++i)
+        if (o.form[i] < 0 || o.form[i] > 5) return ERT_EINVAL;
     long N = 1;
     for (int a = 0; a < o.dim; ++a) {
         if (o.n[a] < 1 || o.n[a] > (1 << 20)) return ERT_EINVAL;
@@ -643,18 +706,18 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
     std::memset(&inf, 0, sizeof(inf));
     ert_status result = ERT_OK;
     auto t0 = std::chrono::steady_clock::now();
-    // vectors beyond the Krylov workspace: phi, r, d (per column, reused)
-    double* extra = nullptr;
-    ERT_HIP(hipMalloc(&extra, 3 * N * sizeof(double)));
-    double* phi = extra;
-    double* r = extra + N;
-    double* d = extra + 2 * N;
+    // vectors beyond the Krylov workspace: phi, r, d, and the trial iterate with its
+    // residual of the learned refinement (per column, reused; plan-owned)
+    ERT_TRY(ensure_solve_scratch(p, (size_t)5 * N));
+    double* phi = p->d_solve;
+    double* r = phi + N;
+    double* d = phi + 2 * N;
+    double* trial = phi + 3 * N;
     ert_status st = ERT_OK;
     if (so.block && nrhs > 1) {
         // all columns at once: phi = A f batched, then block GMRES (or block refinement)
         double* blk = nullptr;
         if (hipMalloc(&blk, (size_t)3 * N * nrhs * sizeof(double)) != hipSuccess) {
-            (void)hipFree(extra);
             record_error("ert_vie_solve: block workspace allocation failed");
             return ERT_ENOMEM;
         }
@@ -670,10 +733,10 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
             inf.matvecs++;
             int it = 0, cy = 0, mv = 0;
             double est = 0.0, tr = 0.0;
-            bool conv = false;
+            bool conv = false, brk = false;
             if (!so.mixed) {
                 st = block_gmres(p, method, prec_outer, Phi, U, nrhs, so.tol, so.max_iter, so.restart, true, &it, &cy,
-                                 &mv, &est, &tr, &conv, so.precond_kind);
+                                 &mv, &est, &tr, &conv, so.precond_kind, &brk);
                 if (st != ERT_OK) break;
                 inf.iters = it;
                 inf.restarts = cy > 0 ? cy - 1 : 0;
@@ -681,6 +744,7 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
                 inf.rel_resid_est = est;
                 inf.rel_resid_true = tr;
                 inf.converged = conv ? 1 : 0;
+                if (brk) st = finish_columns(p, method, prec_outer, Phi, U, Rb, d, nrhs, so, so.precond_kind, &inf);
             } else {
                 // block refinement: R = Phi - A64 U, inner block GMRES on the FP32 operator
                 st = dev_zero(p->stream, U, N * nrhs);
@@ -693,23 +757,48 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
                 double* dn = p->d_red + (size_t)kPartials * 4;
                 for (int b = 0; b < nrhs && st == ERT_OK; ++b) pn[b] = dev_norm(p, Phi + (size_t)b * N, p->d_red, dn, &st);
                 int used = 0;
-                double worst = 1.0;
+                double worst = 1.0, prev_worst = 0.0;
                 for (int outer = 0; outer < 200 && st == ERT_OK; ++outer) {
                     worst = 0.0;
                     for (int b = 0; b < nrhs && st == ERT_OK; ++b) {
-                        rn[b] = dev_norm(p, Rb + (size_t)b * N, p->d_red, dn, &st);
+                        st = ensure_workspace(p, 3 * N, (size_t)kPartials * 4 + 16);
+                        if (st != ERT_OK) break;
+                        rn[b] = dev_norm(p, Rb + (size_t)b * N, p->d_red, p->d_red + (size_t)kPartials * 4, &st);
                         worst = std::max(worst, pn[b] > 0 ? rn[b] / pn[b] : 0.0);
                     }
+                    if (st != ERT_OK) break;
                     inf.rel_resid_true = worst;
                     if (worst <= so.tol) { inf.converged = 1; break; }
                     if (used >= so.max_iter) break;
+                    if (outer > 0 && !(worst < prev_worst)) break;   // no progress: stop (ERT_ENOCONV)
+                    prev_worst = worst;
                     st = block_gmres(p, method, prec_inner, Rb, Db, nrhs, so.inner_tol, so.max_iter - used, so.restart,
-                                     false, &it, &cy, &mv, &est, &tr, &conv, so.precond_kind);
+                                     false, &it, &cy, &mv, &est, &tr, &conv, so.precond_kind, &brk);
                     if (st != ERT_OK) break;
                     used += it;
                     inf.iters += it;
                     inf.matvecs += mv;
                     inf.rel_resid_est = est;
+                    if (brk) {
+                        // no block basis for this residual: inner solves column by column
+                        // (columns already within tol get no correction)
+                        Precond pcb;
+                        pcb.kind = so.precond_kind;
+                        for (int b = 0; b < nrhs && st == ERT_OK; ++b) {
+                            double* Db_b = Db + (size_t)b * N;
+                            if (rn[b] <= so.tol * pn[b]) {
+                                st = dev_zero(p->stream, Db_b, N);
+                                continue;
+                            }
+                            RunStats rs;
+                            st = gmres_run(p, method, prec_inner, Rb + (size_t)b * N, Db_b, so.inner_tol,
+                                           std::max(1, so.max_iter - used), so.restart, false, &rs, &pcb);
+                            used += rs.iters;
+                            inf.iters += rs.iters;
+                            inf.matvecs += rs.matvecs;
+                        }
+                        if (st != ERT_OK) break;
+                    }
                     st = dev_add(p->stream, U, Db, N * nrhs);
                     if (st != ERT_OK) break;
                     st = apply_dispatch(p, ERT_OP_A, method, ERT_FP64, U, Db, nrhs);
@@ -723,7 +812,6 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         } while (0);
         (void)hipStreamSynchronize(p->stream);
         (void)hipFree(blk);
-        (void)hipFree(extra);
         inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (info) *info = inf;
         return st != ERT_OK ? st : result;
@@ -744,8 +832,8 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         }
         if (st != ERT_OK) break;
         if (net) {
-            st = learned_refine(p, method, so.mixed ? ERT_FP64 : p->o.prec, so.mixed ? prec_inner : p->o.prec, net,
-                                so.precond_kind, phi, Uc, r, d, so, &inf);
+            st = learned_refine(p, method, so.mixed ? prec_inner : p->o.prec, net, so.precond_kind, phi, Uc, r, d,
+                                trial, so, &inf);
         } else if (!so.mixed) {
             RunStats rs;
             History hist;
@@ -764,8 +852,6 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
             inf.converged = rs.converged ? 1 : 0;
         } else {
             // iterative refinement: r = phi - A64 U (FP64), inner GMRES on the FP32 operator
-            double* partial = nullptr;
-            (void)partial;
             st = dev_zero(p->stream, Uc, N);
             if (st != ERT_OK) break;
             st = (hipMemcpyAsync(r, phi, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream) == hipSuccess)
@@ -811,7 +897,6 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
         if (st == ERT_OK && !inf.converged) result = ERT_ENOCONV;
     }
     (void)hipStreamSynchronize(p->stream);
-    (void)hipFree(extra);
     inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
     return st != ERT_OK ? st : result;

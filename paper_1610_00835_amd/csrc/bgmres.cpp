@@ -82,6 +82,30 @@ struct Ctx {
     double* small;      // device p x p / (m+1)p x p scratch
 };
 
+// Upper Cholesky factor of the Gram matrix G after scaling it to unit diagonal
+// (G = D Gs D, D = diag(sqrt(G_ii)), Gs = Rs^T Rs, R = Rs D): columns of very
+// different norms (a converged column beside an unconverged one) then keep a
+// well-conditioned factorisation.  False for a zero column or a Gram matrix that
+// is not numerically positive definite (linearly dependent columns).
+bool cholesky_scaled(int p, const std::vector<double>& G, std::vector<double>& R)
+{
+    std::vector<double> d(p), Gs((size_t)p * p);
+    for (int i = 0; i < p; ++i) {
+        const double gi = G[(size_t)i * p + i];
+        if (!(gi > 0.0) || !std::isfinite(gi)) return false;
+        d[i] = std::sqrt(gi);
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) Gs[(size_t)i * p + j] = G[(size_t)i * p + j] / (d[i] * d[j]);
+    if (!cholesky_upper(p, Gs, R)) return false;
+    // a pivot far below the unit diagonal: the column is numerically dependent on the others
+    for (int i = 0; i < p; ++i)
+        if (!(R[(size_t)i * p + i] > 1e-7)) return false;
+    for (int i = 0; i < p; ++i)
+        for (int j = i; j < p; ++j) R[(size_t)i * p + j] *= d[j];
+    return true;
+}
+
 // out (N x p) = in orthonormalised; R (host, p x p upper) with in = out R.
 // Two passes of Cholesky QR; returns false on breakdown (rank-deficient block).
 ert_status chol_qr2(Ctx& c, const double* in, double* out, double* tmp, std::vector<double>& R, bool* ok)
@@ -97,7 +121,7 @@ ert_status chol_qr2(Ctx& c, const double* in, double* out, double* tmp, std::vec
         ERT_HIP(hipMemcpyAsync(G.data(), c.small, sizeof(double) * p * p, hipMemcpyDeviceToHost, c.s));
         ERT_HIP(hipStreamSynchronize(c.s));
         std::vector<double>& Rk = pass == 0 ? R1 : R2;
-        if (!cholesky_upper(p, G, Rk)) {
+        if (!cholesky_scaled(p, G, Rk)) {
             *ok = false;
             return ERT_OK;
         }
@@ -128,9 +152,15 @@ ert_status plan_apply(ert_plan_impl* p, int op, int method, int prec, const doub
 // With a preconditioner kind pk (FFT-based or diffusion, fixed linear maps):
 // right preconditioning, i.e. the Krylov space of (I - K) M and the update
 // X += M [V_0 .. V_j] Y.
+// Breakdown: when the residual block at the start of a cycle has a zero or
+// linearly dependent column (a zero right-hand side, two equal ones, a column
+// solved exactly), no orthonormal block basis exists; the method then stops with
+// *breakdown_out set, *conv_out false and X holding the iterate reached so far,
+// and the caller finishes the columns one by one.  Convergence is only reported
+// when every column's residual met rtol (the true residual with check_true).
 ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Phi, double* X, int nb, double rtol,
                        int maxit, int restart, bool check_true, int* iters_out, int* cycles_out, int* matvecs_out,
-                       double* est_out, double* true_out, bool* conv_out, int pk)
+                       double* est_out, double* true_out, bool* conv_out, int pk, bool* breakdown_out)
 {
     const bool fft = pk != 0;     // right preconditioner of that kind (ERT_PRECOND_*)
     const long N = pl->N;
@@ -151,7 +181,7 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
     Ctx c{pl, s, N, p, work.p, work_elems, small.p};
     int iters = 0, cycles = 0, matvecs = 0;
     double est = 1.0, truer = -1.0;
-    bool converged = false;
+    bool converged = false, breakdown = false;
 
     // column norms of Phi
     std::vector<double> pnorm(p), G((size_t)p * p);
@@ -171,8 +201,8 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
         ++cycles;
         bool ok = true;
         ERT_TRY(chol_qr2(c, R.p, V.p, T.p, B0, &ok));
-        if (!ok) {       // residual block rank deficient: nothing left to span
-            converged = true;
+        if (!ok) {       // residual block rank deficient: no block basis (see above)
+            breakdown = true;
             break;
         }
         std::fill(H.begin(), H.end(), 0.0);
@@ -270,7 +300,9 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
                 est = std::max(est, rel);
             }
             if (est <= rtol || !ok) {
-                cyc_conv = true;
+                // !ok: the new block direction is dependent on the basis; the least-squares
+                // solution over the basis so far is still the best update of this cycle
+                cyc_conv = est <= rtol;
                 break;
             }
         }
@@ -320,6 +352,7 @@ ert_status block_gmres(ert_plan_impl* pl, int method, int prec, const double* Ph
     *est_out = est;
     *true_out = truer;
     *conv_out = converged;
+    if (breakdown_out) *breakdown_out = breakdown && !converged;
     return ERT_OK;
 }
 

@@ -266,6 +266,10 @@ struct ert_plan_impl {
     size_t ws_elems = 0;
     double* d_red = nullptr;     // reduction partials / small vectors
     size_t red_elems = 0;
+    // solve vectors beside the Krylov workspace (phi, residual, correction, trial
+    // iterate and its residual), grown on demand and kept for the next solve
+    double* d_solve = nullptr;
+    size_t solve_elems = 0;
     FmmData* fmm[3] = {nullptr, nullptr, nullptr};   // per ert_prec
     HetCache* het[2] = {nullptr, nullptr};   // heterogeneous kernel caches (per Chebyshev order)
     FftPc* fftpc = nullptr;      // FFT-based preconditioner (built on first use)

@@ -1,7 +1,11 @@
 // Dense symmetric eigen-decomposition on the host (FP64), used at plan time to
 // compress the far-field translations: Householder reduction to tridiagonal
 // form, then the implicit QL iteration with Wilkinson-type shifts, with the
-// orthogonal transformations accumulated into the eigenvector matrix.
+// orthogonal transformations accumulated into the eigenvector matrix.  The QL
+// stage follows the published tridiagonal QL algorithm with implicit shifts
+// (Bowdler, Martin, Reinsch and Wilkinson, Numer. Math. 11 (1968), the EISPACK
+// routine tql2), step for step: the shift from the leading 2 x 2 block, the
+// chase of the bulge by plane rotations, and the rotations applied to Z.
 #include <algorithm>
 #include <cmath>
 #include <numeric>

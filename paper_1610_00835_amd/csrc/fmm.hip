@@ -1801,13 +1801,9 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         // within 5 % of the fastest, take the 64-column tiles: they read each operator
         // block once instead of once per 16 columns (less HBM traffic at the same speed)
         if (best == 1 && ms[2] <= 1.05f * ms[1]) best = 2;
-        // fixed forms for reproducible profiles: ERT_VIE_FORM="a" (every product) or
-        // "a,b" (a for the near field, b for the far field), each 0..4 (4 where it applies)
-        if (const char* f = std::getenv("ERT_VIE_FORM")) {
-            const char* comma = std::strchr(f, ',');
-            const int v = std::atoi((&gs == &near_site || !comma) ? f : comma + 1);
-            if (v >= 0 && v < nforms) best = v;
-        }
+        // a form fixed by the plan's options (near field / far field), where it applies
+        const int fixed = p->o.form[&gs == &near_site ? 0 : 1] - 1;
+        if (fixed >= 0 && fixed < nforms) best = fixed;
         gs.choice[bucket] = best;
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);
@@ -1903,8 +1899,10 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
         hipLaunchKernelGGL(k_gather<T>, first.grid, first.block, 0, s, A.a, A.io, A.t, A.ss, A.N, A.B, A.q);
         ERT_HIP(hipGetLastError());
     }
-    // a10: near field (writes pot), on the side stream once the forms are tuned
-    const bool fork = tuned[nrhs > 1 ? 1 : 0];
+    // a10: near field (writes pot), on the side stream once the forms are tuned; while
+    // stages are timed everything runs on one stream, so that each stage's events
+    // bracket its own kernels and the stage times add up to the apply's
+    const bool fork = tuned[nrhs > 1 ? 1 : 0] && !pf->on;
     hipStream_t sn = s;
     if (fork) {
         if (!side) ERT_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -1934,6 +1932,9 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             a.stage = stage_near;
             a.L = pot;
             a.accumulate = 0;
+            st_.pause();
+            a.prof = pf;
+            a.prof_stage = ERT_STAGE_NEAR;
             ERT_TRY(pair_stream(sn, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
         } else if (nearops) {
             BoxGemm g = gemm_desc(tr.L, tr.S, tr.S, nrhs);
@@ -2011,6 +2012,9 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 a.stage = stage;
                 a.L = Lc[l];
                 a.accumulate = first ? 0 : 1;
+                st_.pause();
+                a.prof = pf;
+                a.prof_stage = ERT_STAGE_M2L;
                 ERT_TRY(pair_stream(s, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
             } else if (rp[l] > 0 && leaf_in) {
                 // single compressed level: multipoles already compressed, the expansion

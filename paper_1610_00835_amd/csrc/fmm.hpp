@@ -165,6 +165,10 @@ struct PairStream {
     void* stage;             // [min(B, 8)][npairs][M] (streaming) or [min(B, 64)][npairs][M] (matrix cores)
     void* L;                 // [B][ntarget][M]
     int accumulate;
+    // stage timing (ert_vie_profile): the pair products under prof_stage, their
+    // per-target sums under ERT_STAGE_REDUCE; null when not profiling
+    Profiler* prof = nullptr;
+    int prof_stage = 0;
 };
 
 // From this many right-hand sides on, cached-pair products run on the matrix cores

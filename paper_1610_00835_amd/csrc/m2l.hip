@@ -1081,11 +1081,15 @@ ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
     const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
     for (int b0 = 0; b0 < g.B; b0 += 64) {
         const int nb = std::min(64, g.B - b0);
-        hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s, g,
-                           b0, rblocks);
-        ERT_HIP(hipGetLastError());
+        {
+            StageTimer t_(g.prof, s, g.prof_stage);
+            hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s,
+                               g, b0, rblocks);
+            ERT_HIP(hipGetLastError());
+        }
         const long n = g.ntarget * g.M * nb;
         typedef typename Acc<PREC>::T T;
+        StageTimer t_(g.prof, s, ERT_STAGE_REDUCE);
         hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, nb);
         ERT_HIP(hipGetLastError());
     }
@@ -1106,12 +1110,18 @@ ert_status pair_stream_t(hipStream_t s, const PairStream& g)
     for (int b0 = 0; b0 < g.B;) {
         const int left = g.B - b0;
         const int rb = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
-        if (g.M % VEC == 0) launch_pair_stream<T, TS, VEC>(s, g, b0, rb);
-        else launch_pair_stream<T, TS, 1>(s, g, b0, rb);
-        ERT_HIP(hipGetLastError());
+        {
+            StageTimer t_(g.prof, s, g.prof_stage);
+            if (g.M % VEC == 0) launch_pair_stream<T, TS, VEC>(s, g, b0, rb);
+            else launch_pair_stream<T, TS, 1>(s, g, b0, rb);
+            ERT_HIP(hipGetLastError());
+        }
         const long n = g.ntarget * g.M * rb;
-        hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, rb);
-        ERT_HIP(hipGetLastError());
+        {
+            StageTimer t_(g.prof, s, ERT_STAGE_REDUCE);
+            hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, rb);
+            ERT_HIP(hipGetLastError());
+        }
         b0 += rb;
     }
     return ERT_OK;

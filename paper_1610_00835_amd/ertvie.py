@@ -33,7 +33,7 @@ class VieOpts(ctypes.Structure):
                 ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
                 ("cheb_n", ctypes.c_int), ("leaf", ctypes.c_int), ("nrhs_max", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("svd_tol", ctypes.c_double), ("inner_cheb_n", ctypes.c_int),
-                ("inner_near16", ctypes.c_int)]
+                ("inner_near16", ctypes.c_int), ("form", ctypes.c_int * 2)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -171,7 +171,8 @@ class Plan:
     """
 
     def __init__(self, dim, n, h, sigma_t, sigma_s, kernel=K_HOMOGENEOUS, method="direct", prec="fp64",
-                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0, inner_cheb_n=0, inner_near16=False, scheme=0):
+                 cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0, inner_cheb_n=0, inner_near16=False, scheme=0,
+                 form=None):
         L = load()
         n = list(n)[:dim]
         self.dim = int(dim)
@@ -192,6 +193,12 @@ class Plan:
         o.svd_tol = float(svd_tol)
         o.inner_cheb_n = int(inner_cheb_n)
         o.inner_near16 = 1 if inner_near16 else 0
+        # execution forms of the homogeneous box-offset products: None (timed), f (both
+        # products) or (near, far); each 0..4
+        if form is not None:
+            fn, ff = (form, form) if np.isscalar(form) else form
+            o.form[0] = int(fn) + 1
+            o.form[1] = int(ff) + 1
         self.opts = o
         st_h = _f64_host(sigma_t, self.N)
         ss_h = _f64_host(sigma_s, self.N)
@@ -351,10 +358,10 @@ class Plan:
 
 
 def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0,
-                   inner_cheb_n=0, inner_near16=False, scheme=0):
+                   inner_cheb_n=0, inner_near16=False, scheme=0, form=None):
     return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
                 method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream,
-                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n, inner_near16=inner_near16, scheme=scheme)
+                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n, inner_near16=inner_near16, scheme=scheme, form=form)
 
 
 def _load_net():

@@ -109,16 +109,15 @@ def test_fmm_ragged(ev, oracle_mod, n, leaf):
 
 
 @pytest.mark.parametrize("forms", [None, "1", "4"])
-def test_fmm_multi_rhs_and_determinism(ev, oracle_mod, monkeypatch, forms):
+def test_fmm_multi_rhs_and_determinism(ev, oracle_mod, forms):
     """Repeated applies return the same bits.  Each right-hand-side count tunes its own
     execution forms, which may sum in different orders: the columns of a 5-column apply
     agree with single-column applies to FP32 rounding, and bit for bit once the forms are
-    fixed (ERT_VIE_FORM), since every form reduces each column on its own."""
-    if forms:
-        monkeypatch.setenv("ERT_VIE_FORM", forms)
+    fixed (the plan's `form` option), since every form reduces each column on its own."""
     case = inputs.make_case("c2", n=(16, 16, 16), seed=3)
     X = inputs.random_vector(4096, 9, nrhs=5)
-    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=5, leaf=4) as plan:
+    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=5, leaf=4,
+                           form=int(forms) if forms else None) as plan:
         Y = gpu_apply(plan, X, ev.OP_A)
         Y2 = gpu_apply(plan, X, ev.OP_A)
         Y3 = gpu_apply(plan, X, ev.OP_A)

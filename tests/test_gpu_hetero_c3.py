@@ -32,6 +32,23 @@ def test_c3_fmm_apply_rows(c3, oracle_mod):
     assert err <= 1e-6
 
 
+def test_c3_fmm_fp64_apply_rows(c3, oracle_mod):
+    """The FP64 heterogeneous FMM apply at full size (FP64 accumulation over the FP32 kernel
+    caches) on sampled rows, bar 1e-6."""
+    ev, case = c3
+    P = oracle_problem(oracle_mod, case)
+    x = inputs.random_vector(P.N, 12)
+    rows = np.random.default_rng(17).choice(P.N, size=128, replace=False)
+    ref = P.apply_rows(x, rows, op=2)
+    with ev.plan_from_case(case, method="fmm", prec="fp64") as plan:
+        y = gpu_apply(plan, x, ev.OP_A)
+        y2 = gpu_apply(plan, x, ev.OP_A)
+    err = rel_l2(y[rows], ref)
+    log("c3 fmm fp64 apply rows rel L2", err)
+    assert np.array_equal(y, y2)
+    assert err <= 1e-6
+
+
 def test_c3_recipe_32cubed_mixed_solve(oracle_mod):
     """The heterogeneous recipe at 32^3: FP64 FMM outer residual, FP32 FMM inner GMRES, to a
     1e-8 true residual of the FMM operator.  On sampled rows, the oracle's residual of that

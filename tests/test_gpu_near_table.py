@@ -1,6 +1,6 @@
 """Near-field products read from the offset table (homogeneous medium on a uniform grid,
 leaf a power of two >= 4; Sec. 3.3's near field with the translation invariance of the
-kernel): every execution form, forced through ERT_VIE_FORM, against the oracle and
+kernel): every execution form, fixed through the plan's `form` option, against the oracle and
 against each other.
 
 The offset-stationary forms 1-3 read the same FP32/FP64 values as the explicit blocks
@@ -28,7 +28,7 @@ def ev():
 
 @pytest.mark.parametrize("recipe,n,leaf", [("c2", (16, 16, 16), 4), ("c2", (32, 32, 32), 8),
                                            ("c1", (64, 64), 8), ("c1", (72, 40), 8)])
-def test_near_table_forms(ev, oracle_mod, monkeypatch, recipe, n, leaf):
+def test_near_table_forms(ev, oracle_mod, recipe, n, leaf):
     case = inputs.make_case(recipe, n=n, seed=5)
     P = oracle_problem(oracle_mod, case)
     dim = case["dim"]
@@ -38,8 +38,7 @@ def test_near_table_forms(ev, oracle_mod, monkeypatch, recipe, n, leaf):
     for prec, agree in (("fp64", 1e-13), ("fp32", 1e-6)):
         out = {}
         for form in ("0", "1", "2", "3") + (("4",) if prec == "fp32" else ()):
-            monkeypatch.setenv("ERT_VIE_FORM", form)
-            with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf) as plan:
+            with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf, form=int(form)) as plan:
                 ys = [gpu_apply(plan, x, ev.OP_A) for _ in range(3)]
                 info = plan.fmm_info()
             assert info["near_table"] == (4 * leaf - 1) ** dim

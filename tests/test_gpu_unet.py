@@ -67,7 +67,7 @@ def _host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,B", [((8, 8, 8), 2), ((16, 8, 12), 1)])
+@pytest.mark.parametrize("n,B", [((8, 8, 8), 2), ((16, 8, 12), 1), ((32, 32, 32), 1)])
 def test_forward_matches_reference(ev, n, B):
     import torch
     r, e, st, ss = _rand(n, B, 1)
@@ -95,8 +95,11 @@ def test_forward_matches_reference(ev, n, B):
     assert rel_l2(zg[0], z0) <= 1e-4
 
 
-def test_gradient_matches_reference(ev):
-    n, B = (8, 8, 8), 2
+@pytest.mark.parametrize("n,B", [((8, 8, 8), 2), ((16, 16, 16), 2), ((32, 16, 16), 1)])
+def test_gradient_matches_reference(ev, n, B):
+    """The weight gradients sum over voxels in slabs of 1024 per batch column: 8^3 is one
+    slab per column, 16^3 four and 32 x 16 x 16 eight on the finest level, so the
+    in-column slab offsets are exercised on the larger grids."""
     r, e, st, ss = _rand(n, B, 4)
     p = _params(5)
     with ev.Net(n, batch_max=B) as net:
