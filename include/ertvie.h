@@ -78,7 +78,10 @@ typedef enum {
 typedef enum {
     ERT_FP64 = 0,     /* everything in FP64 */
     ERT_FP32 = 1,     /* near and far field in FP32, self term and assembly in FP64 */
-    ERT_BF16X3 = 2    /* as FP32, with the far-field translations as split-BF16x3 MFMA */
+    ERT_BF16X3 = 2    /* as FP32, with the far-field translations (Sec. 3.3 eq. EQ: M2L) as
+                         split-BF16x3 MFMA products accumulated in FP32, in homogeneous media
+                         (shared per-offset operators) and heterogeneous ones (cached per-pair
+                         matrices, for any number of right-hand sides); near field in FP32 */
 } ert_prec;
 
 typedef enum {
@@ -161,9 +164,11 @@ typedef struct {
     ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
                          becomes a refinement loop.  Each step solves (I - K) d = r by flexible
                          GMRES with z_j = net(v_j) (inner operator: FP32 with `mixed`, else the
-                         plan's), and is kept only if the true residual phi - (I - K)(U + d)
-                         of the outer operator (FP64 with `mixed`, else the plan's) is smaller
-                         than before; otherwise plain GMRES with the same budget replaces it.
+                         plan's), and is kept only if the true residual phi - (I - K)(U + d),
+                         taken with the FP64 operator (phi = A f in FP64 as well), is smaller
+                         than before; otherwise plain GMRES with the same budget replaces it,
+                         and when that step does not lower the residual either the solve stops
+                         with ERT_ENOCONV.  rel_resid_true is that FP64 residual.
                          Not combined with `block`. */
     double* history;  /* NULL, or DEVICE N x 2 history_max FP64: the plain solve (no mixed,
                          block or precond) of the first column stores, at the start of every

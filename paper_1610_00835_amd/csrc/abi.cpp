@@ -827,7 +827,8 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
             st = (hipMemcpyAsync(phi, fc, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream) == hipSuccess)
                      ? ERT_OK : ERT_EDEVICE;
         } else {
-            st = apply_dispatch(p, ERT_OP_G, method, prec_outer, fc, phi, 1);
+            // the learned refinement judges its steps with the FP64 operator: phi in FP64 too
+            st = apply_dispatch(p, ERT_OP_G, method, net ? ERT_FP64 : prec_outer, fc, phi, 1);
             inf.matvecs++;
         }
         if (st != ERT_OK) break;

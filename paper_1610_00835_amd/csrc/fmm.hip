@@ -1733,7 +1733,9 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
     };
     ERT_TRY(site_need(near_site, tr.nleaf, tr.S, sn_need));
     if (hetero) {
-        const size_t rb = (size_t)std::min(nrhs, nrhs >= kPairMfmaMinRhs ? 64 : 8);
+        // staging rows per pass: 8 right-hand sides streamed, 64 on the matrix cores (from
+        // kPairMfmaMinRhs on, and always for the split-BF16x3 translations)
+        const size_t rb = (size_t)std::min(nrhs, (nrhs >= kPairMfmaMinRhs || prec == ERT_BF16X3) ? 64 : 8);
         sn_need = std::max(sn_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
         for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hc->hnp[l] * tr.Kp);
     }
@@ -2015,7 +2017,8 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 st_.pause();
                 a.prof = pf;
                 a.prof_stage = ERT_STAGE_M2L;
-                ERT_TRY(pair_stream(s, prec == ERT_FP64 ? ERT_FP64 : ERT_FP32, a));
+                // split-BF16x3 translations run on the matrix cores for any rhs count
+                ERT_TRY(pair_stream(s, prec, a));
             } else if (rp[l] > 0 && leaf_in) {
                 // single compressed level: multipoles already compressed, the expansion
                 // is folded into L2P below
@@ -2204,8 +2207,7 @@ ert_status fmm_build(ert_plan_impl* p, int prec)
             f = g;
         } else {
             auto* g = new (std::nothrow) FmmImpl<float>();
-            // the heterogeneous far field streams per-pair matrices with VALU: FP32 there
-            if (g) g->prec = (prec == ERT_BF16X3 && p->o.kernel == ERT_K_RAY_MIDPOINT) ? ERT_FP32 : prec;
+            if (g) g->prec = prec;
             f = g;
         }
         if (!f) return ERT_ENOMEM;

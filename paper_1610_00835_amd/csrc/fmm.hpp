@@ -175,6 +175,9 @@ struct PairStream {
 // (64 right-hand sides per pass over the matrices; stage then holds min(B, 64) rows).
 constexpr int kPairMfmaMinRhs = 16;
 
+// prec: ERT_FP64 or ERT_FP32 (streaming below kPairMfmaMinRhs right-hand sides, matrix
+// cores from there on), or ERT_BF16X3 (FP32-stored matrices as split-BF16x3 matrix-core
+// products with FP32 accumulation, for any right-hand-side count).
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
 
 // Heterogeneous media: kernel caches shared by the applies of every precision

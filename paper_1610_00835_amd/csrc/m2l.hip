@@ -807,6 +807,87 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rbl
     }
 }
 
+// Split-BF16x3 form of the same product (FP32-stored matrices): every cached value
+// a and source value w is split into BF16 parts (hi = bf16(v), lo = bf16(v - hi)) and
+// a w is taken as hi_a hi_w + hi_a lo_w + lo_a hi_w, three 16x16x32 BF16 products
+// accumulated in FP32 (the lo_a lo_w term, ~2^-16 relative, is dropped).  The 64
+// source vectors of a 32-long reduction chunk are split once into LDS, source-major,
+// so that a lane reads its eight reduction indices as one 16-byte vector; each lane
+// loads its eight matrix values along the reduction (one per matrix row of 16 lanes,
+// coalesced across the lanes) and splits them in registers.
+template <int RT>
+__global__ __launch_bounds__(256) void k_pair_mfma_bf16x3(PairStream g, int b0, int rblocks)
+{
+    constexpr int KC = 32;
+    constexpr int LDK = KC + 8;                   // padded LDS row (reduction indices)
+    __shared__ __bf16 whi[64 * LDK];
+    __shared__ __bf16 wlo[64 * LDK];
+    const long p = blockIdx.x / rblocks;
+    const int rblk = (int)(blockIdx.x % rblocks);
+    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
+    const int s = g.src[p];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
+    const int row0 = (rblk * 4 + wave) * 16 * RT;
+    const size_t A = (size_t)p * g.Kd * g.M;
+    const float* ops = (const float*)g.opsT;
+    v4f acc[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * KC; i += 256) {
+            const int b = i / KC, kk = i - b * KC;
+            float v = 0.f;
+            if (s >= 0 && b < nb && k0 + kk < g.Kd)
+                v = ((const float*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k0 + kk];
+            const __bf16 h = (__bf16)v;
+            whi[b * LDK + kk] = h;
+            wlo[b * LDK + kk] = (__bf16)(v - (float)h);
+        }
+        __syncthreads();
+        if (s < 0) continue;                      // empty pair: zero rows (uniform over the block)
+        v8bf ah[RT], al[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int row = row0 + 16 * rt + li;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + 8 * grp + e;
+                const float a = (k < g.Kd && row < g.M) ? ops[A + (size_t)k * g.M + row] : 0.f;
+                const __bf16 h = (__bf16)a;
+                ah[rt][e] = h;
+                al[rt][e] = (__bf16)(a - (float)h);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int b = 16 * ct + li;
+            const v8bf bh = *(const v8bf*)(whi + b * LDK + 8 * grp);
+            const v8bf bl = *(const v8bf*)(wlo + b * LDK + 8 * grp);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bh, acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bl, acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][ct], 0, 0, 0);
+            }
+        }
+    }
+    // rows 4 grp + i of column li
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int b = 16 * ct + li;
+        if (b >= nb) continue;
+        float* dst = (float*)g.stage + ((long)b * g.npairs + p) * g.M;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int base = row0 + 16 * rt;
+            if (base + 4 * grp + 3 < g.M) *(v4f*)(dst + base + 4 * grp) = acc[rt][ct];
+        }
+    }
+}
+
 // Sum of the contiguous staging rows of every target, for rhs b0..b0+nb-1.
 template <typename T>
 __global__ void k_pair_reduce(PairStream g, int b0, int nb)
@@ -1096,6 +1177,32 @@ ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
     return ERT_OK;
 }
 
+// Split-BF16x3 matrix-core form (FP32-stored matrices, FP32 vectors), 64 right-hand
+// sides per pass; any right-hand-side count (the product stays HBM-bound with one).
+ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g)
+{
+    constexpr int RT = 4;
+    if (g.M % 4 != 0 || g.ops_fmt != kOpsF32) {
+        record_error("pair_stream: split-BF16x3 products need FP32-stored matrices with rows in fours");
+        return ERT_EINVAL;
+    }
+    const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
+    for (int b0 = 0; b0 < g.B; b0 += 64) {
+        const int nb = std::min(64, g.B - b0);
+        {
+            StageTimer t_(g.prof, s, g.prof_stage);
+            hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s, g,
+                               b0, rblocks);
+            ERT_HIP(hipGetLastError());
+        }
+        const long n = g.ntarget * g.M * nb;
+        StageTimer t_(g.prof, s, ERT_STAGE_REDUCE);
+        hipLaunchKernelGGL(k_pair_reduce<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, nb);
+        ERT_HIP(hipGetLastError());
+    }
+    return ERT_OK;
+}
+
 // T: arithmetic and vectors; TS: stored matrices (FP32 caches under FP64 products).
 template <typename T, typename TS>
 ert_status pair_stream_t(hipStream_t s, const PairStream& g)
@@ -1129,6 +1236,10 @@ ert_status pair_stream_t(hipStream_t s, const PairStream& g)
 
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
 {
+    if (prec == ERT_BF16X3) {
+        if (g.npairs < 1 || g.B < 1) return ERT_OK;
+        return pair_mfma_bf16x3(s, g);
+    }
     const bool f64 = prec == ERT_FP64;
     if (f64 && g.ops_fmt == kOpsHi) {
         record_error("pair_stream: FP64 products do not read the rounded plane alone");

@@ -60,7 +60,10 @@ def test_plan_rejects_bad_arguments_before_device_use():
         sig_t = kw.pop("st", st)
         sig_s = kw.pop("ss", ss)
         for k, v in kw.items():
-            setattr(o, k, v)
+            if k == "form":
+                o.form[0], o.form[1] = v
+            else:
+                setattr(o, k, v)
         h = ctypes.c_void_p()
         return L.ert_vie_plan(ctypes.byref(o), np.ascontiguousarray(sig_t).ctypes.data_as(dp),
                               np.ascontiguousarray(sig_s).ctypes.data_as(dp), None, ctypes.byref(h))
@@ -72,6 +75,8 @@ def test_plan_rejects_bad_arguments_before_device_use():
     assert plan(inner_cheb_n=1) == ertvie.EINVAL
     assert plan(inner_cheb_n=9) == ertvie.EINVAL
     assert plan(inner_near16=2) == ertvie.EINVAL
+    assert plan(form=(6, 0)) == ertvie.EINVAL                  # execution forms 0..4, stored as f + 1
+    assert plan(form=(0, -1)) == ertvie.EINVAL
     assert plan(st=np.where(np.arange(N) == 3, -1.0, 2.0)) == ertvie.EINVAL
     assert plan(ss=np.full(N, 2.5)) == ertvie.EINVAL           # absorption < 0
     assert plan(ss=np.full(N, -0.1)) == ertvie.EINVAL
