@@ -275,6 +275,20 @@ ERT_API ert_status ert_vie_fft_info(ert_vie_plan_t plan, ert_fft_info* info);
 ERT_API ert_status ert_vie_transport(ert_vie_plan_t plan, const double* U, const double* f, const double* dirs,
                                      int ndir, double* phi);
 
+/* ert_vie_transport without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results (bit for bit) and errors as
+ * ert_vie_transport, plus ERT_EINVAL when 2 N + dim * ndir exceeds 4,259,840
+ * doubles (32.5 MiB; e.g. N = 128^3 with up to 21,845 directions in 3D).
+ * Its work buffer (the interleaved sigma_t and Q of every cell, and the
+ * directions) is one static device array per GPU, held from the first call on
+ * that GPU until the process ends and shared by every call on it: calls that
+ * overlap on one GPU (plans on different streams, several host threads) race
+ * on it and must be serialised by the caller.  Runs on the plan's device and
+ * stream and synchronises that stream before returning. */
+ERT_API ert_status ert_vie_transport_noalloc(ert_vie_plan_t plan, const double* U, const double* f,
+                                             const double* dirs, int ndir, double* phi);
+
 /* Diffusion preconditioner (Sec. 4.4, eq. EQ:DA).  The diffusion approximation
  *   -div(D grad U) + mu_a U = f,  U + l dU/dn = 0 on the boundary,
  *   D = 1 / (dim sigma_t),  mu_a = sigma_t - sigma_s,  l = 2 / (dim sigma_t),

@@ -556,10 +556,17 @@ ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const d
         return ERT_EDEVICE;
     }
 
+    int dev = 0;
+    de = hipGetDevice(&dev);
+    if (de != hipSuccess) {
+        record_hip_error("hipGetDevice", de, __FILE__, __LINE__);
+        return ERT_EDEVICE;
+    }
     record_error("");
     ert_vie_plan_s* p = new (std::nothrow) ert_vie_plan_s();
     if (!p) return ERT_ENOMEM;
     p->o = o;
+    p->device = dev;
     if (p->o.dim == 2) p->o.n[2] = 1;
     p->geo.dim = o.dim;
     p->geo.n0 = o.n[0];
@@ -648,6 +655,13 @@ ert_status ert_vie_transport(ert_vie_plan_t p, const double* U, const double* f,
 {
     if (!p || !dirs || !phi || ndir < 1) return ERT_EINVAL;
     return transport_sweep(p, U, f, dirs, ndir, phi);
+}
+
+ert_status ert_vie_transport_noalloc(ert_vie_plan_t p, const double* U, const double* f, const double* dirs,
+                                     int ndir, double* phi)
+{
+    if (!p || !dirs || !phi || ndir < 1) return ERT_EINVAL;
+    return transport_sweep_noalloc(p, U, f, dirs, ndir, phi);
 }
 
 ert_status ert_vie_diff_precond(ert_vie_plan_t p, const double* r, double* z, int nrhs)

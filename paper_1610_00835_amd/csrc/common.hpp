@@ -254,6 +254,7 @@ struct ert_plan_impl {
     long N;
     int nrhs_max;
     hipStream_t stream;
+    int device = 0;              // the device current when the plan was made (its memory lives there)
     double sigma_const;          // homogeneous kernel: the constant sigma_t
     std::vector<double> h_st, h_ss;
     double* d_st = nullptr;      // sigma_t FP64
@@ -302,6 +303,9 @@ inline ert_status precond_apply(ert_plan_impl* p, int kind, const double* r, dou
 // Algorithm 1 S.3 (transport.hip): phi[:, d] = the angular solution for direction d.
 ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host, int ndir,
                            double* phi);
+// The same with the device scratch of the library instead of an allocation.
+ert_status transport_sweep_noalloc(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host,
+                                   int ndir, double* phi);
 ert_status fftpc_info(ert_plan_impl* p, ert_fft_info* info);
 void fftpc_destroy(FftPc* f);
 

@@ -14,9 +14,17 @@
 #include "common.hpp"
 
 #include <cmath>
-#include <vector>
+#include <mutex>
 
 namespace ertvie {
+
+// Device scratch of the allocation-free entry point (ert_vie_transport_noalloc):
+// the interleaved (sigma_t, Q) pairs, 2 N doubles, then the directions, dim * ndir
+// doubles.  32.5 MiB per device, held from the library's first use of it on that
+// device until the process ends.  Host code never passes this name to a kernel
+// or a copy: it uses the device address from hipGetSymbolAddress (scratch_base).
+constexpr size_t kTransportScratch = (size_t(1) << 22) + (size_t(1) << 16);   // doubles
+static __device__ __align__(256) double scratch[kTransportScratch];
 
 namespace {
 
@@ -76,7 +84,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, const double2* __restrict_
     const double h = g.h, inv_h = 1.0 / g.h;
     const int i0 = (int)(j % g.n0), i1 = (int)((j / g.n0) % g.n1), i2 = (int)(j / ((long)g.n0 * g.n1));
     const double x[3] = {h * (i0 + 0.5), h * (i1 + 0.5), g.dim > 2 ? h * (i2 + 0.5) : 0.0};
-    const double v[3] = {dirs[3 * d], dirs[3 * d + 1], g.dim > 2 ? dirs[3 * d + 2] : 0.0};
+    const double v[3] = {dirs[g.dim * d], dirs[g.dim * d + 1], g.dim > 2 ? dirs[g.dim * d + 2] : 0.0};
     const int n[3] = {g.n0, g.n1, g.n2};
     // distance backwards along -v to the box boundary
     double sb = 1e300;
@@ -104,20 +112,17 @@ __global__ __launch_bounds__(256) void k_sweep(Geo g, const double2* __restrict_
     phi[(long)d * N + j] = acc;
 }
 
-}  // namespace
-
-ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host, int ndir,
-                           double* phi)
+// Directions (host, ndir x dim): finite unit vectors.
+ert_status check_dirs(int dim, const double* dirs_host, int ndir)
 {
-    const long N = p->N;
-    const int dim = p->o.dim;
-    std::vector<double> dv((size_t)3 * ndir, 0.0);
     for (int d = 0; d < ndir; ++d) {
         double nn = 0.0;
         for (int a = 0; a < dim; ++a) {
             const double c = dirs_host[(size_t)d * dim + a];
-            if (!std::isfinite(c)) return ERT_EINVAL;
-            dv[(size_t)3 * d + a] = c;
+            if (!std::isfinite(c)) {
+                record_error("ert_vie_transport: non-finite direction");
+                return ERT_EINVAL;
+            }
             nn += c * c;
         }
         if (std::fabs(nn - 1.0) > 1e-10) {
@@ -125,12 +130,19 @@ ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, c
             return ERT_EINVAL;
         }
     }
-    double* buf = nullptr;
-    ERT_HIP(hipMalloc(&buf, sizeof(double) * (2 * N + 3 * (size_t)ndir)));
-    double2* sq = reinterpret_cast<double2*>(buf);
-    double* dd = buf + 2 * N;
-    ert_status st = ERT_HIPST(hipMemcpyAsync(dd, dv.data(), sizeof(double) * 3 * ndir, hipMemcpyHostToDevice,
-                                             p->stream));
+    return ERT_OK;
+}
+
+// The sweep with caller-provided device buffers: sq (N pairs) and dd (dim * ndir),
+// which receives the directions.  Synchronises the plan's stream before returning
+// (the directions are copied from the caller's host array).
+ert_status sweep_into(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host, int ndir,
+                      double* phi, double2* sq, double* dd)
+{
+    const long N = p->N;
+    const int dim = p->o.dim;
+    ert_status st = ERT_HIPST(hipMemcpyAsync(dd, dirs_host, sizeof(double) * dim * (size_t)ndir,
+                                             hipMemcpyHostToDevice, p->stream));
     if (st == ERT_OK) {
         hipLaunchKernelGGL(k_source, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, U, f, p->d_st,
                            p->d_ss, N, sq);
@@ -140,11 +152,77 @@ ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, c
     for (int d0 = 0; d0 < ndir && st == ERT_OK; d0 += 65535) {
         const int nd = std::min(65535, ndir - d0);
         hipLaunchKernelGGL(k_sweep, dim3((unsigned)((N + 255) / 256), (unsigned)nd), dim3(256), 0, p->stream, p->geo,
-                           sq, dd + (size_t)3 * d0, N, phi + (size_t)d0 * N);
+                           sq, dd + (size_t)dim * d0, N, phi + (size_t)d0 * N);
         st = ERT_HIPST(hipGetLastError());
     }
-    (void)hipStreamSynchronize(p->stream);
+    const ert_status ss = ERT_HIPST(hipStreamSynchronize(p->stream));
+    return st != ERT_OK ? st : ss;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (made current by the caller), looked
+// up once per device.
+ert_status scratch_base(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        record_error("ert_vie_transport_noalloc: device index out of range");
+        return ERT_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            record_hip_error("hipGetSymbolAddress(scratch)", e != hipSuccess ? e : hipErrorInvalidSymbol, __FILE__,
+                             __LINE__);
+            return ERT_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return ERT_OK;
+}
+
+}  // namespace
+
+ert_status transport_sweep(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host, int ndir,
+                           double* phi)
+{
+    ERT_TRY(check_dirs(p->o.dim, dirs_host, ndir));
+    const long N = p->N;
+    double* buf = nullptr;
+    ERT_HIP(hipMalloc(&buf, sizeof(double) * (2 * N + (size_t)p->o.dim * ndir)));
+    const ert_status st = sweep_into(p, U, f, dirs_host, ndir, phi, reinterpret_cast<double2*>(buf), buf + 2 * N);
     (void)hipFree(buf);
+    return st;
+}
+
+ert_status transport_sweep_noalloc(ert_plan_impl* p, const double* U, const double* f, const double* dirs_host,
+                                   int ndir, double* phi)
+{
+    ERT_TRY(check_dirs(p->o.dim, dirs_host, ndir));
+    const size_t need = 2 * (size_t)p->N + (size_t)p->o.dim * ndir;
+    if (need > kTransportScratch) {
+        record_error("ert_vie_transport_noalloc: 2 N + dim * ndir exceeds the scratch of 4259840 doubles");
+        return ERT_EINVAL;
+    }
+    int cur = 0;
+    ERT_HIP(hipGetDevice(&cur));
+    if (cur != p->device) ERT_HIP(hipSetDevice(p->device));
+    double* base = nullptr;
+    ert_status st = scratch_base(p->device, &base);
+    if (st == ERT_OK)
+        st = sweep_into(p, U, f, dirs_host, ndir, phi, reinterpret_cast<double2*>(base), base + 2 * p->N);
+    if (cur != p->device) {
+        const hipError_t e = hipSetDevice(cur);
+        if (st == ERT_OK && e != hipSuccess) {
+            record_hip_error("hipSetDevice", e, __FILE__, __LINE__);
+            st = ERT_EDEVICE;
+        }
+    }
     return st;
 }
 

@@ -110,6 +110,8 @@ def load():
     L.ert_vie_fft_precond.argtypes = [_vp, _vp, _vp, ctypes.c_int]
     L.ert_vie_transport.restype = ctypes.c_int
     L.ert_vie_transport.argtypes = [_vp, _vp, _vp, _dp, ctypes.c_int, _vp]
+    L.ert_vie_transport_noalloc.restype = ctypes.c_int
+    L.ert_vie_transport_noalloc.argtypes = [_vp, _vp, _vp, _dp, ctypes.c_int, _vp]
     L.ert_vie_diff_precond.restype = ctypes.c_int
     L.ert_vie_diff_precond.argtypes = [_vp, _vp, _vp, ctypes.c_int]
     L.ert_vie_fft_info.restype = ctypes.c_int
@@ -243,9 +245,10 @@ class Plan:
         _check(load().ert_vie_fft_precond(self.handle, rp, zp, nr), "ert_vie_fft_precond")
         return z
 
-    def transport(self, U, f, dirs, phi):
+    def transport(self, U, f, dirs, phi, noalloc=False):
         """Algorithm 1 S.3: phi[k] = Phi(., dirs[k]) for Q = sigma_s U + f (U or f may be None).
-        dirs: host (ndir, dim) unit vectors; phi: float64 CUDA tensor (ndir, N)."""
+        dirs: host (ndir, dim) unit vectors; phi: float64 CUDA tensor (ndir, N).
+        noalloc: use ert_vie_transport_noalloc (the library's static device scratch)."""
         dirs = np.ascontiguousarray(dirs, dtype=np.float64)
         if dirs.ndim != 2 or dirs.shape[1] != self.opts.dim:
             raise ValueError("dirs must have shape (ndir, dim)")
@@ -254,7 +257,9 @@ class Plan:
             raise ValueError("phi must have one row per direction")
         up = _dev_ptr(U, self.N, "U")[0] if U is not None else None
         fp = _dev_ptr(f, self.N, "f")[0] if f is not None else None
-        _check(load().ert_vie_transport(self.handle, up, fp, dirs.ctypes.data_as(_dp), nd, pp), "ert_vie_transport")
+        fn = load().ert_vie_transport_noalloc if noalloc else load().ert_vie_transport
+        _check(fn(self.handle, up, fp, dirs.ctypes.data_as(_dp), nd, pp),
+               "ert_vie_transport_noalloc" if noalloc else "ert_vie_transport")
         return phi
 
     def diff_precond(self, r, z):
