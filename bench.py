@@ -334,16 +334,23 @@ C5_CHEB, C5_INNER_CHEB = 6, 4
 MEASURED_TRAFFIC = dict(MEASURED_TRAFFIC)
 
 
-def het_roofline(info, stage_ms, launches, N, near_plane_bytes=4, workload=None):
+def het_roofline(info, stage_ms, launches, n, near_plane_bytes=4, workload=None):
     """Roofline of the cached-pair products of a heterogeneous plan (HBM-bound: every cached
-    kernel value is read once per apply for one right-hand side).  Algorithmic bytes:
-    near field, one value per point pair of neighbouring leaves, the diagonal included
-    (near_pairs + N values of near_plane_bytes each); far field, one Kp x Kp FP32 matrix per
-    interaction-list pair of every level.  The dominant stage (near or m2l) by time is the
-    reported kernel; time per launch from the stage events."""
+    kernel value is read once per apply for one right-hand side).  The kernel is symmetric,
+    so one block is stored per unordered pair of boxes and serves both directions.
+    Algorithmic bytes: near field, the S x S block of every leaf with itself and one block per
+    unordered pair of neighbouring leaves (grid of whole leaves), near_plane_bytes per value;
+    far field, one Kp x Kp FP32 matrix per unordered interaction-list pair of every level.  The
+    dominant stage (near or m2l) by time is the reported kernel; time per launch from the stage
+    events."""
     Kp = info["nodes_padded"]
-    near_bytes = (info["near_pairs"] + N) * near_plane_bytes
-    far_bytes = sum(info["far_pairs"][l] * Kp * Kp * 4.0 for l in range(2, info["levels"] + 1))
+    S = info["leaf"] ** len(n)
+    nb = [-(-v // info["leaf"]) for v in n]
+    nleaf = int(np.prod(nb))
+    directed = int(np.prod([3 * v - 2 for v in nb]))           # leaf pairs at offsets in [-1, 1]^d
+    near_blocks = nleaf + (directed - nleaf) // 2
+    near_bytes = near_blocks * S * S * near_plane_bytes
+    far_bytes = sum(info["far_pairs"][l] // 2 * Kp * Kp * 4.0 for l in range(2, info["levels"] + 1))
     cand = {"near": (near_bytes, stage_ms.get("near", 0.0), launches.get("near", 1.0)),
             "m2l": (far_bytes, stage_ms.get("m2l", 0.0), launches.get("m2l", 1.0))}
     dom = max(cand, key=lambda k: cand[k][1])
@@ -356,7 +363,8 @@ def het_roofline(info, stage_ms, launches, N, near_plane_bytes=4, workload=None)
             "per_launch": per, "launch_ms": tms / nl, "launches_per_apply": nl,
             "near_gb_per_s": near_bytes / (stage_ms["near"] * 1e-3) / 1e9 if stage_ms.get("near") else None,
             "m2l_gb_per_s": far_bytes / (stage_ms["m2l"] * 1e-3) / 1e9 if stage_ms.get("m2l") else None,
-            "near_bytes_per_apply": near_bytes, "far_bytes_per_apply": far_bytes}
+            "near_bytes_per_apply": near_bytes, "far_bytes_per_apply": far_bytes, "near_blocks": near_blocks,
+            "far_blocks": [info["far_pairs"][l] // 2 for l in range(info["levels"] + 1)]}
 
 
 def c5_headline(torch, ertvie, inputs, O, stream, args):
@@ -394,7 +402,7 @@ def c5_headline(torch, ertvie, inputs, O, stream, args):
         st_ms, st_n = stage_profile(plan, x, y, ertvie.OP_A, max(3, min(args.steps, 10)))
         res["stage_ms_fp64"] = st_ms
         log("128^3 FP64 stage ms:", json.dumps({k: round(v, 3) for k, v in st_ms.items()}))
-        roof = het_roofline(info, st_ms, st_n, N, workload="c5_128")
+        roof = het_roofline(info, st_ms, st_n, n, workload="c5_128")
         log("128^3 roofline:", json.dumps(roof))
         plan.apply(x, y, op=ertvie.OP_A, prec="fp32")
         plan.apply(x, y, op=ertvie.OP_A, prec="fp32")

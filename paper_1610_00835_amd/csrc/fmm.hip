@@ -430,42 +430,87 @@ __global__ __launch_bounds__(kB) void k_p2m(DevTree t, const T* __restrict__ q, 
     for (int i = threadIdx.x; i < t.K; i += blockDim.x) dst[i] = r[i];
 }
 
-// M2M: one block per (parent box, rhs); sums the transfers of its 2^d children.
-// M1[c][m][m'] = S_n(child node m' in the parent frame, p_m).
+// M2M: one block per (parent box, rhs), the transfer factorised axis by axis over the
+// children: W_p = sum_c (M_{c_z} (x) M_{c_y} (x) M_{c_x}) W_c, with M_o[m][m'] =
+// S_n(node m' of the child at offset o in the parent frame, p_m).  The x contraction
+// of all 2^d children is summed over c_x (2^(d-1) tensors), then the y contraction
+// over c_y (2^(d-2)), then z: 2^d + 2^(d-1) + 2^(d-2) one-axis contractions instead
+// of 3 per child, three barriers in all.  Children outside the lattice are zero.
 template <typename T>
 __global__ __launch_bounds__(kB) void k_m2m(int D, int nc, int K, int Kp, int nlp0, int nlp1, int nlp2, long nboxp,
                                             int nlc0, int nlc1, int nlc2, long nboxc, const T* __restrict__ Wc,
                                             const T* __restrict__ M1, T* __restrict__ Wp)
 {
-    __shared__ T in[kSepBuf], b0[kSepBuf], b1[kSepBuf], acc[kSepBuf], mat[128];
+    __shared__ T ch[8 * kSepBuf];       // children (x-contracted pairs reuse it)
+    __shared__ T zc[4 * kSepBuf];       // x-contracted, summed over c_x
+    __shared__ T mat[128];
     const long pbox = blockIdx.x;
     const int b = blockIdx.y;
     const int nlp[3] = {nlp0, nlp1, nlp2}, nlc[3] = {nlc0, nlc1, nlc2};
+    const int nchild = 1 << D;
     int pc[3];
     unravel3(pbox, nlp, pc);
     for (int i = threadIdx.x; i < 2 * nc * nc; i += blockDim.x) mat[i] = M1[i];
-    for (int i = threadIdx.x; i < K; i += blockDim.x) acc[i] = T(0);
-    __syncthreads();
-    for (int ch = 0; ch < (1 << D); ++ch) {
-        int cc[3], off[3];
+    for (int i = threadIdx.x; i < nchild * K; i += blockDim.x) {
+        const int c = i / K, m = i - c * K;
+        int cc[3];
         bool inside = true;
         for (int a = 0; a < 3; ++a) {
-            off[a] = (a < D) ? (ch >> a) & 1 : 0;
-            cc[a] = 2 * pc[a] + off[a];
+            cc[a] = (a < D) ? 2 * pc[a] + ((c >> a) & 1) : 0;
             if (a < D && cc[a] >= nlc[a]) inside = false;
         }
-        if (!inside) continue;   // uniform over the block
-        long cb = cc[0] + (long)nlc[0] * (cc[1] + (long)nlc[1] * cc[2]);
-        const T* src = Wc + ((long)b * nboxc + cb) * Kp;
-        for (int i = threadIdx.x; i < K; i += blockDim.x) in[i] = src[i];
-        __syncthreads();
-        const T* r = sep_all<T>(in, b0, b1, D, nc, nc, mat + off[0] * nc * nc, mat + off[1] * nc * nc,
-                                mat + off[2] * nc * nc, false);
-        for (int i = threadIdx.x; i < K; i += blockDim.x) acc[i] += r[i];
-        __syncthreads();
+        const long cb = cc[0] + (long)nlc[0] * (cc[1] + (long)nlc[1] * cc[2]);
+        ch[i] = inside ? Wc[((long)b * nboxc + cb) * Kp + m] : T(0);
     }
+    __syncthreads();
+    const int n1 = D > 1 ? nc : 1, n2 = D > 2 ? nc : 1;
+    // x: zc[c >> 1][m] = sum_{cx} sum_k M_cx[m0][k] ch[c][.., k]
+    for (int i = threadIdx.x; i < (nchild >> 1) * K; i += blockDim.x) {
+        const int q = i / K, m = i - q * K;
+        const int m0 = m % nc, rest = m - m0;
+        T sum = T(0);
+        for (int cx = 0; cx < 2; ++cx) {
+            const T* mx = mat + cx * nc * nc + m0 * nc;
+            const T* in = ch + (2 * q + cx) * K + rest;
+            for (int k = 0; k < nc; ++k) sum += mx[k] * in[k];
+        }
+        zc[i] = sum;
+    }
+    __syncthreads();
+    if (D == 1) {
+        T* dst = Wp + ((long)b * nboxp + pbox) * Kp;
+        for (int i = threadIdx.x; i < K; i += blockDim.x) dst[i] = zc[i];
+        return;
+    }
+    // y: ch[q >> 1][m] = sum_{cy} sum_k M_cy[m1][k] zc[q][.., k, ..]
+    for (int i = threadIdx.x; i < (nchild >> 2) * K; i += blockDim.x) {
+        const int q = i / K, m = i - q * K;
+        const int m0 = m % nc, m1 = (m / nc) % n1, m2 = m / (nc * n1);
+        T sum = T(0);
+        for (int cy = 0; cy < 2; ++cy) {
+            const T* my = mat + cy * nc * nc + m1 * nc;
+            const T* in = zc + (2 * q + cy) * K + m2 * nc * n1 + m0;
+            for (int k = 0; k < nc; ++k) sum += my[k] * in[k * nc];
+        }
+        ch[i] = sum;
+    }
+    __syncthreads();
     T* dst = Wp + ((long)b * nboxp + pbox) * Kp;
-    for (int i = threadIdx.x; i < K; i += blockDim.x) dst[i] = acc[i];
+    if (D == 2) {
+        for (int i = threadIdx.x; i < K; i += blockDim.x) dst[i] = ch[i];
+        return;
+    }
+    // z: W_p[m] = sum_{cz} sum_k M_cz[m2][k] ch[cz][k, m1, m0]
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+        const int m01 = i % (nc * n1), m2 = i / (nc * n1);
+        T sum = T(0);
+        for (int cz = 0; cz < 2; ++cz) {
+            const T* mz = mat + cz * nc * nc + m2 * nc;
+            const T* in = ch + cz * K + m01;
+            for (int k = 0; k < n2; ++k) sum += mz[k] * in[k * nc * n1];
+        }
+        dst[i] = sum;
+    }
 }
 
 // L2L: one block per (child box, rhs): the child's locals are the parent's
@@ -588,69 +633,54 @@ __global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__
 }
 
 // Cached near-field blocks for the ray kernel, FP64 arithmetic: the same rule
-// as the dense apply (exact integer step count, marched from the lower index).
-// blk points at the block of leaf leaf0.
-template <typename T>
+// as the dense apply (exact integer step count, marched from the lower index,
+// so the value of a cell pair does not depend on its order).  One block per
+// stored pair u (blocks u0 .. u0 + nu - 1; blk and lo_plane point at block u0):
+// element [si][ti] = G(cell ti of leaf ua[u], cell si of leaf ub[u]), zero for a
+// cell with itself (the diagonal's term).  FP32 values as a BF16-rounded high
+// plane and the exact remainder.
 __global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, const double* __restrict__ itab,
-                              long leaf0, long nleaves, T* __restrict__ blk, int16_t* __restrict__ lo_plane)
+                              const int* __restrict__ ua, const int* __restrict__ ub, long u0, long nu,
+                              uint16_t* __restrict__ blk, int16_t* __restrict__ lo_plane)
 {
-    const int nn = (t.D == 3) ? 27 : 9;
-    const long per = (long)nn * t.S * t.S;
+    const long per = (long)t.S * t.S;
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i >= nleaves * per) return;
-    long leafi = leaf0 + i / per;
+    if (i >= nu * per) return;
+    const long u = u0 + i / per;
     long rem = i % per;
-    int k = (int)(rem / ((long)t.S * t.S));
-    rem -= (long)k * t.S * t.S;
-    int si = (int)(rem / t.S), ti = (int)(rem % t.S);
-    int lb[3];
-    unravel3(leafi, t.nb, lb);
-    int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, t.D == 3 ? k / 9 - 1 : 0};
-    int sb[3];
-    bool ok = true;
-    for (int a = 0; a < 3; ++a) {
-        sb[a] = lb[a] + ((a < t.D) ? o[a] : 0);
-        if (sb[a] < 0 || sb[a] >= t.nb[a]) ok = false;
-    }
+    const int si = (int)(rem / t.S), ti = (int)(rem % t.S);
     double v = 0.0;
-    if (ok) {
-        long sl = sb[0] + (long)t.nb[0] * (sb[1] + (long)t.nb[1] * sb[2]);
-        int ct[3], cs[3];
-        long jt = slot_cell(t, leafi * t.S + ti, ct);
-        long js = slot_cell(t, sl * t.S + si, cs);
-        if (jt >= 0 && js >= 0 && jt != js) {
-            int K = 0;
-            for (int a = 0; a < 3; ++a) K += (ct[a] - cs[a]) * (ct[a] - cs[a]);
-            const double r = g.h * sqrt((double)K);
-            const int* lo = (jt < js) ? ct : cs;
-            const int* hi = (jt < js) ? cs : ct;
-            const double inv_h = 1.0 / g.h;
-            const bool d3 = t.D > 2;
-            double tau = tau_march<double>(st, g, inv_h, g.h * (lo[0] + 0.5), g.h * (lo[1] + 0.5),
-                                           d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5),
-                                           g.h * (hi[1] + 0.5), d3 ? g.h * (hi[2] + 0.5) : 0.0,
-                                           steps_grid(K), r);
-            if (itab) {
-                // (M-ii): cell integral at the integer offset, per unit cell, over h^{d-1}
-                const int a0 = abs(ct[0] - cs[0]), a1 = abs(ct[1] - cs[1]), a2 = abs(ct[2] - cs[2]);
-                const double hp = (t.D == 2) ? g.h : g.h * g.h;
-                v = exp(-tau) * itab[a0 + (long)g.n0 * (a1 + (long)g.n1 * a2)] / (surface_area(t.D) * hp);
-            } else {
-                const double rp = (t.D == 2) ? r : r * r;
-                v = exp(-tau) / (surface_area(t.D) * rp);
-            }
+    int ct[3], cs[3];
+    const long jt = slot_cell(t, (long)ua[u] * t.S + ti, ct);
+    const long js = slot_cell(t, (long)ub[u] * t.S + si, cs);
+    if (jt >= 0 && js >= 0 && jt != js) {
+        int K = 0;
+        for (int a = 0; a < 3; ++a) K += (ct[a] - cs[a]) * (ct[a] - cs[a]);
+        const double r = g.h * sqrt((double)K);
+        const int* lo = (jt < js) ? ct : cs;
+        const int* hi = (jt < js) ? cs : ct;
+        const double inv_h = 1.0 / g.h;
+        const bool d3 = t.D > 2;
+        double tau = tau_march<double>(st, g, inv_h, g.h * (lo[0] + 0.5), g.h * (lo[1] + 0.5),
+                                       d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5),
+                                       g.h * (hi[1] + 0.5), d3 ? g.h * (hi[2] + 0.5) : 0.0,
+                                       steps_grid(K), r);
+        if (itab) {
+            // (M-ii): cell integral at the integer offset, per unit cell, over h^{d-1}
+            const int a0 = abs(ct[0] - cs[0]), a1 = abs(ct[1] - cs[1]), a2 = abs(ct[2] - cs[2]);
+            const double hp = (t.D == 2) ? g.h : g.h * g.h;
+            v = exp(-tau) * itab[a0 + (long)g.n0 * (a1 + (long)g.n1 * a2)] / (surface_area(t.D) * hp);
+        } else {
+            const double rp = (t.D == 2) ? r : r * r;
+            v = exp(-tau) / (surface_area(t.D) * rp);
         }
     }
-    if constexpr (std::is_same<T, uint16_t>::value) {
-        // FP32 value X as the high half rounded to BF16 and the exact signed remainder:
-        // X = (hi << 16) + lo, lo in [-2^15, 2^15) (values are >= 0)
-        const unsigned X = __float_as_uint((float)v);
-        const unsigned hi = (X + 0x8000u) >> 16;
-        blk[i] = (uint16_t)hi;
-        lo_plane[i] = (int16_t)(int)(X - (hi << 16));
-    } else {
-        blk[i] = T(v);
-    }
+    // FP32 value X as the high half rounded to BF16 and the exact signed remainder:
+    // X = (hi << 16) + lo, lo in [-2^15, 2^15) (values are >= 0)
+    const unsigned X = __float_as_uint((float)v);
+    const unsigned hi = (X + 0x8000u) >> 16;
+    blk[i] = (uint16_t)hi;
+    lo_plane[i] = (int16_t)(int)(X - (hi << 16));
 }
 
 // ----------------------------------------------- far-field operators ----
@@ -709,12 +739,13 @@ __global__ void k_ops_hom(int D, int nc, int K, int Kp, double w, double sigma, 
     }
 }
 
-// Heterogeneous translation matrices, one per (target, source) pair of a
+// Heterogeneous translation matrices, one per stored (target, source) pair of a
 // level, stored source-node major: opsT[pair][c][r] (opsT points at pair p0).  Midpoint ray rule with
-// step <= h/2 between the Chebyshev nodes (FP64 arithmetic).
+// step <= h/2 between the Chebyshev nodes (FP64 arithmetic).  The rule samples the
+// same points from either end, so the matrix of (source, target) is the transpose.
 template <typename T>
 __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, int K, int Kp, double w,
-                          int nl0, int nl1, int nl2, const double* __restrict__ cheb, const long* __restrict__ pair_t,
+                          int nl0, int nl1, int nl2, const double* __restrict__ cheb, const int* __restrict__ pair_t,
                           const int* __restrict__ pair_s, long p0, long np, T* __restrict__ opsT, int mii)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -1409,12 +1440,14 @@ ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
     return ERT_OK;
 }
 
-// Heterogeneous far field of level l: one matrix per (target, source) pair.
+// Heterogeneous far field of level l: the directed interaction-list pairs grouped by
+// target (the staging rows), and one stored matrix per unordered pair {t, s}, t < s,
+// for target t and source s (the transpose serves target s).
 ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb, HetCache* hc, int l)
 {
     hipStream_t s = p->stream;
     const long KpKp = (long)tr.Kp * tr.Kp;
-    std::vector<long> start(tr.nbox[l] + 1, 0), ptgt;
+    std::vector<long> start(tr.nbox[l] + 1, 0);
     std::vector<int> src;
     const int* nl = tr.nl[l];
     for (long tb = 0; tb < tr.nbox[l]; ++tb) {
@@ -1434,18 +1467,41 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
                     }
                     if (!ok || adjacent) continue;
                     src.push_back((int)(s3[0] + (long)nl[0] * (s3[1] + (long)nl[1] * s3[2])));
-                    ptgt.push_back(tb);
                 }
     }
     start[tr.nbox[l]] = (long)src.size();
-    const long np = (long)src.size();
+    const long nd = (long)src.size();
+    // unordered pairs: the directed pair (t, s) with t < s, and the row of (s, t)
+    std::vector<int> ua, ub;
+    std::vector<long> fwd, bwd;
+    for (long tb = 0; tb < tr.nbox[l]; ++tb)
+        for (long k = start[tb]; k < start[tb + 1]; ++k) {
+            const int sb = src[k];
+            if (sb <= tb) continue;
+            long back = -1;
+            for (long q = start[sb]; q < start[sb + 1]; ++q)
+                if (src[q] == (int)tb) back = q;
+            if (back < 0) {
+                record_error("FMM: interaction lists are not symmetric");
+                return ERT_EINVAL;
+            }
+            ua.push_back((int)tb);
+            ub.push_back(sb);
+            fwd.push_back(k);
+            bwd.push_back(back);
+        }
+    const long np = (long)ua.size();
+    if (2 * np != nd) {
+        record_error("FMM: interaction lists are not symmetric");
+        return ERT_EINVAL;
+    }
     hc->hnp[l] = np;
+    hc->hnd[l] = nd;
     ERT_TRY(upload<long>(s, &hc->pstart[l], start));
-    ERT_TRY(upload<int>(s, &hc->psrc[l], src));
-    DevPtrs tmp;
-    long* ptd = nullptr;
-    ERT_TRY(tmp.alloc(&ptd, (size_t)np));
-    ERT_HIP(hipMemcpyAsync(ptd, ptgt.data(), np * sizeof(long), hipMemcpyHostToDevice, s));
+    ERT_TRY(upload<int>(s, &hc->hua[l], ua));
+    ERT_TRY(upload<int>(s, &hc->hub[l], ub));
+    ERT_TRY(upload<long>(s, &hc->hfwd[l], fwd));
+    ERT_TRY(upload<long>(s, &hc->hbwd[l], bwd));
     size_t bytes = (size_t)np * KpKp * sizeof(float);
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
@@ -1460,7 +1516,7 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
     for (long p0 = 0; p0 < np; p0 += pchunk) {
         long cnt = std::min(pchunk, np - p0);
         hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, tr.nc,
-                           tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, ptd, hc->psrc[l], p0, cnt,
+                           tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], p0, cnt,
                            hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
         ERT_HIP(hipGetLastError());
     }
@@ -1509,6 +1565,11 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
         c->near_lo = other->near_lo;
         c->near_src = other->near_src;
         c->near_tstart = other->near_tstart;
+        c->near_np = other->near_np;
+        c->near_ua = other->near_ua;
+        c->near_ub = other->near_ub;
+        c->near_fwd = other->near_fwd;
+        c->near_bwd = other->near_bwd;
         for (int l = 2; l <= tr.L; ++l) {
             ert_status st = het_far_level(p, tr, cheb, c, l);
             if (st != ERT_OK) return fail(st);
@@ -1518,26 +1579,7 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
         hc = c;
         return ERT_OK;
     }
-    const long per = (long)nn * tr.S * tr.S;
-    const size_t plane = (size_t)tr.nleaf * per * sizeof(uint16_t);
-    const size_t bytes = 2 * plane;
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
-        record_error("FMM: heterogeneous near-field cache does not fit in device memory");
-        return fail(ERT_ENOMEM);
-    }
-    if (hipMalloc(&c->near_hi, plane) != hipSuccess || hipMalloc(&c->near_lo, plane) != hipSuccess) {
-        record_error("FMM: near-field cache allocation failed");
-        return fail(ERT_ENOMEM);
-    }
-    c->bytes += bytes;
-    const long chunk = std::max<long>(1, (1L << 26) / per);
-    for (long l0 = 0; l0 < tr.nleaf; l0 += chunk) {
-        long cnt = std::min(chunk, tr.nleaf - l0);
-        hipLaunchKernelGGL(k_near_blocks<uint16_t>, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st,
-                           p->d_itab, l0, cnt, c->near_hi + (size_t)l0 * per, c->near_lo + (size_t)l0 * per);
-        if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
-    }
+    // directed rows: every leaf and each of its 3^d neighbour offsets (-1 outside the grid)
     std::vector<int> src((size_t)tr.nleaf * nn);
     std::vector<long> ts(tr.nleaf + 1);
     for (long lf = 0; lf < tr.nleaf; ++lf) {
@@ -1556,8 +1598,50 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
         }
     }
     ts[tr.nleaf] = tr.nleaf * nn;
+    // stored blocks: the self offset (nn / 2) and the offsets after it; offset index k
+    // and nn - 1 - k are opposite offsets
+    std::vector<int> ua, ub;
+    std::vector<long> fwd, bwd;
+    for (long lf = 0; lf < tr.nleaf; ++lf)
+        for (int k = nn / 2; k < nn; ++k) {
+            const int sl = src[(size_t)lf * nn + k];
+            if (sl < 0) continue;
+            ua.push_back((int)lf);
+            ub.push_back(sl);
+            fwd.push_back(lf * nn + k);
+            bwd.push_back(k == nn / 2 ? -1 : (long)sl * nn + (nn - 1 - k));
+        }
+    const long np = (long)ua.size();
+    const long per = (long)tr.S * tr.S;
+    const size_t plane = (size_t)np * per * sizeof(uint16_t);
+    const size_t bytes = 2 * plane;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
+        record_error("FMM: heterogeneous near-field cache does not fit in device memory");
+        return fail(ERT_ENOMEM);
+    }
+    if (hipMalloc(&c->near_hi, std::max<size_t>(1, plane)) != hipSuccess ||
+        hipMalloc(&c->near_lo, std::max<size_t>(1, plane)) != hipSuccess) {
+        record_error("FMM: near-field cache allocation failed");
+        return fail(ERT_ENOMEM);
+    }
+    c->bytes += bytes;
+    c->near_np = np;
     ert_status st = upload<int>(s, &c->near_src, src);
     if (st == ERT_OK) st = upload<long>(s, &c->near_tstart, ts);
+    if (st == ERT_OK) st = upload<int>(s, &c->near_ua, ua);
+    if (st == ERT_OK) st = upload<int>(s, &c->near_ub, ub);
+    if (st == ERT_OK) st = upload<long>(s, &c->near_fwd, fwd);
+    if (st == ERT_OK) st = upload<long>(s, &c->near_bwd, bwd);
+    if (st != ERT_OK) return fail(st);
+    const long chunk = std::max<long>(1, (1L << 26) / per);
+    for (long u0 = 0; u0 < np; u0 += chunk) {
+        const long cnt = std::min(chunk, np - u0);
+        hipLaunchKernelGGL(k_near_blocks, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, p->d_itab,
+                           c->near_ua, c->near_ub, u0, cnt, c->near_hi + (size_t)u0 * per,
+                           c->near_lo + (size_t)u0 * per);
+        if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
+    }
     for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, c, l);
     if (st == ERT_OK && hipStreamSynchronize(s) != hipSuccess) st = ERT_EDEVICE;
     if (st != ERT_OK) return fail(st);
@@ -1733,11 +1817,13 @@ ert_status FmmImpl<T>::ensure_buffers(int nrhs)
     };
     ERT_TRY(site_need(near_site, tr.nleaf, tr.S, sn_need));
     if (hetero) {
-        // staging rows per pass: 8 right-hand sides streamed, 64 on the matrix cores (from
-        // kPairMfmaMinRhs on, and always for the split-BF16x3 translations)
-        const size_t rb = (size_t)std::min(nrhs, (nrhs >= kPairMfmaMinRhs || prec == ERT_BF16X3) ? 64 : 8);
+        // staging rows (one per directed pair) per pass: kPairStreamRhs right-hand sides
+        // streamed, 64 on the matrix cores (from kPairMfmaMinRhs on, and always for the
+        // split-BF16x3 translations)
+        const size_t rb = (size_t)std::min(nrhs, nrhs >= kPairMfmaMinRhs ? 64 : kPairStreamRhs);
+        const size_t rbf = (size_t)std::min(nrhs, (nrhs >= kPairMfmaMinRhs || prec == ERT_BF16X3) ? 64 : kPairStreamRhs);
         sn_need = std::max(sn_need, rb * tr.nleaf * (tr.D == 3 ? 27 : 9) * tr.S);
-        for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rb * hc->hnp[l] * tr.Kp);
+        for (int l = 2; l <= tr.L; ++l) st_need = std::max(st_need, rbf * hc->hnd[l] * tr.Kp);
     }
     for (int l = 2; l <= tr.L; ++l)
         ERT_TRY(site_need(far_site[l], tr.nbox[l], rp[l] > 0 ? rp[l] : tr.Kp, st_need));
@@ -1921,15 +2007,20 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             PairStream a;
             // the FP32 applies of a plan with inner_near16 read the BF16-rounded plane alone
             a.ops_fmt = (prec != ERT_FP64 && p->o.inner_near16) ? kOpsHi : kOpsSplit;
+            a.opsT = hc->near_hi;
             a.opsT_lo = hc->near_lo;
-            a.npairs = tr.nleaf * nn;
+            a.npairs = hc->near_np;
+            a.ua = hc->near_ua;
+            a.ub = hc->near_ub;
+            a.fwd_row = hc->near_fwd;
+            a.bwd_row = hc->near_bwd;
+            a.nrows = tr.nleaf * nn;
+            a.row_src = hc->near_src;
+            a.tstart = hc->near_tstart;
             a.ntarget = tr.nleaf;
             a.B = nrhs;
-            a.M = a.Kd = tr.S;
-            a.opsT = hc->near_hi;
-            a.src = hc->near_src;
+            a.M = tr.S;
             a.nsrc = tr.nleaf;
-            a.tstart = hc->near_tstart;
             a.W = q;
             a.stage = stage_near;
             a.L = pot;
@@ -2001,15 +2092,20 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
             if (hetero) {
                 PairStream a;
                 a.ops_fmt = kOpsF32;
+                a.opsT = hc->hops[l];
                 a.opsT_lo = nullptr;
                 a.npairs = hc->hnp[l];
+                a.ua = hc->hua[l];
+                a.ub = hc->hub[l];
+                a.fwd_row = hc->hfwd[l];
+                a.bwd_row = hc->hbwd[l];
+                a.nrows = hc->hnd[l];
+                a.row_src = nullptr;
+                a.tstart = hc->pstart[l];
                 a.ntarget = tr.nbox[l];
                 a.B = nrhs;
-                a.M = a.Kd = tr.Kp;
-                a.opsT = hc->hops[l];
-                a.src = hc->psrc[l];
+                a.M = tr.Kp;
                 a.nsrc = tr.nbox[l];
-                a.tstart = hc->pstart[l];
                 a.W = W[l];
                 a.stage = stage;
                 a.L = Lc[l];
@@ -2285,9 +2381,10 @@ HetCache::~HetCache()
     auto f = [](void* q) { if (q) (void)hipFree(q); };
     if (owns_near) {
         f(near_hi); f(near_lo); f(near_src); f(near_tstart);
+        f(near_ua); f(near_ub); f(near_fwd); f(near_bwd);
     }
     for (int l = 0; l <= kMaxLevels; ++l) {
-        f(hops[l]); f(pstart[l]); f(psrc[l]);
+        f(hops[l]); f(pstart[l]); f(hua[l]); f(hub[l]); f(hfwd[l]); f(hbwd[l]);
     }
 }
 

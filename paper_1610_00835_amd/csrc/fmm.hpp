@@ -134,15 +134,9 @@ ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    
 // (two launches when only one of them is in form 4)
 ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& a, const OffsetGemm& b);
 
-// Streaming form of cached-pair products (heterogeneous far field and near
-// field): one workgroup per pair streams its matrix once (16-byte loads along
-// the output rows, the reduction split between thread groups) for up to 8
-// right-hand sides at a time and writes a staging row; a second pass sums the
-// contiguous pairs of every target in a fixed order.  The staging buffer holds
-// 8 right-hand sides (min(B, 8) x npairs x M elements).
-// Storage of the cached matrices read by the pair products.
+// Storage of the cached blocks read by the pair products.
 enum {
-    kOpsNative = 0,          // values of the arithmetic type
+    kOpsNative = 0,          // values of the arithmetic type (not used by the heterogeneous caches)
     kOpsF32 = 1,             // FP32 values (FP64 products read FP32 caches)
     kOpsSplit = 2,           // FP32 values as two 16-bit planes: opsT = high halves rounded to
                              // BF16 (bits (X + 0x8000) >> 16), opsT_lo = signed remainders; the
@@ -150,19 +144,32 @@ enum {
     kOpsHi = 3               // the high plane alone: the FP32 values rounded to BF16
 };
 
+// Cached-pair products of a heterogeneous medium (pairs.hip).  The kernel is
+// symmetric, so one block is stored per unordered pair of boxes {a, b}:
+// B[j][i] = G(x_i in a, y_j in b), i fastest (M x M, M = nodes or cells per box).
+// It gives the forward product for target a (sources of b) and, unless a = b, the
+// backward product for target b (sources of a, through B transposed); each goes
+// to the staging row of its directed pair, and a second pass sums the contiguous
+// directed rows of every target in a fixed order.
 struct PairStream {
     int ops_fmt;             // kOps*
-    const void* opsT_lo;     // kOpsSplit: remainder plane (same layout as opsT)
-    long npairs;
+    const void* opsT;        // [npairs][M][M] stored blocks
+    const void* opsT_lo;     // kOpsSplit: remainder plane (same layout)
+    long npairs;             // stored blocks
+    const int* ua;           // [npairs] box a: target of the forward product
+    const int* ub;           // [npairs] box b: source of the forward product
+    const long* fwd_row;     // [npairs] staging row of the forward product
+    const long* bwd_row;     // [npairs] staging row of the backward product, -1 for a self block
+    long nrows;              // staging rows: directed pairs
+    const int* row_src;      // [nrows] source box of each directed pair, -1: no such pair (skipped);
+                             // null: every row exists
+    const long* tstart;      // [ntarget + 1] contiguous directed rows of each target
     long ntarget;
     int B;
-    int M, Kd;
-    const void* opsT;        // [npairs][Kd][M] (output rows fastest)
-    const int* src;          // [npairs] source box (-1: empty pair)
-    long nsrc;               // source boxes (W is [B][nsrc][Kd])
-    const long* tstart;      // [ntarget + 1] contiguous pair range of each target
+    int M;
+    long nsrc;               // boxes (W is [B][nsrc][M])
     const void* W;
-    void* stage;             // [min(B, 8)][npairs][M] (streaming) or [min(B, 64)][npairs][M] (matrix cores)
+    void* stage;             // [rows per pass][nrows][M]: 4 per streaming pass, 64 on the matrix cores
     void* L;                 // [B][ntarget][M]
     int accumulate;
     // stage timing (ert_vie_profile): the pair products under prof_stage, their
@@ -172,29 +179,43 @@ struct PairStream {
 };
 
 // From this many right-hand sides on, cached-pair products run on the matrix cores
-// (64 right-hand sides per pass over the matrices; stage then holds min(B, 64) rows).
+// (64 right-hand sides per pass over the blocks; stage then holds min(B, 64) rows).
 constexpr int kPairMfmaMinRhs = 16;
+// Staging rows per pass of the streaming form.
+constexpr int kPairStreamRhs = 4;
 
 // prec: ERT_FP64 or ERT_FP32 (streaming below kPairMfmaMinRhs right-hand sides, matrix
-// cores from there on), or ERT_BF16X3 (FP32-stored matrices as split-BF16x3 matrix-core
+// cores from there on), or ERT_BF16X3 (FP32-stored blocks as split-BF16x3 matrix-core
 // products with FP32 accumulation, for any right-hand-side count).
 ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
 
 // Heterogeneous media: kernel caches shared by the applies of every precision
 // of a plan, in FP32 (the FP64 apply reads them and accumulates in FP64; the
 // rounding of the stored kernel values, 6e-8 relative, sits far below the
-// interpolation error of the far field).
+// interpolation error of the far field).  One block per unordered pair of boxes.
 struct HetCache {
     int nc = 0, leaf = 0;                   // tree the cache was built for
     bool owns_near = true;                  // false: the near part belongs to another order's cache
-    uint16_t* near_hi = nullptr;            // [leaf][3^d][S][S] (target fastest), FP32 values as
-    int16_t* near_lo = nullptr;             // a BF16-rounded high plane and a remainder plane
-    int* near_src = nullptr;                // [leaf * 3^d] source leaf, -1 outside the grid
+    // near field: stored blocks of the self pairs and of the neighbours at offsets
+    // after the self in the 3^d order (the other half are their transposes)
+    uint16_t* near_hi = nullptr;            // [near_np][S][S] BF16-rounded high halves of the FP32 values
+    int16_t* near_lo = nullptr;             // [near_np][S][S] signed remainders
+    long near_np = 0;
+    int* near_ua = nullptr;                 // [near_np] target leaf of the forward product
+    int* near_ub = nullptr;                 // [near_np] source leaf of the forward product
+    long* near_fwd = nullptr;               // [near_np] directed row (leaf * 3^d + offset index)
+    long* near_bwd = nullptr;               // [near_np] directed row of the transpose, -1 for a self block
+    int* near_src = nullptr;                // [leaf * 3^d] source leaf of each directed row, -1 outside the grid
     long* near_tstart = nullptr;            // [nleaf + 1]
-    float* hops[kMaxLevels + 1] = {};       // [pair][Kp][Kp], source-node major
-    long* pstart[kMaxLevels + 1] = {};      // [nbox + 1] pairs of each target
-    int* psrc[kMaxLevels + 1] = {};         // [pair] source box
-    long hnp[kMaxLevels + 1] = {};          // pairs per level
+    // far field, per level: one block per unordered interaction-list pair
+    float* hops[kMaxLevels + 1] = {};       // [pair][Kp][Kp]
+    long hnp[kMaxLevels + 1] = {};          // stored blocks
+    int* hua[kMaxLevels + 1] = {};
+    int* hub[kMaxLevels + 1] = {};
+    long* hfwd[kMaxLevels + 1] = {};
+    long* hbwd[kMaxLevels + 1] = {};
+    long hnd[kMaxLevels + 1] = {};          // directed pairs (staging rows)
+    long* pstart[kMaxLevels + 1] = {};      // [nbox + 1] directed pairs of each target
     size_t bytes = 0;
     ~HetCache();
 };

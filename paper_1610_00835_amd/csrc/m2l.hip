@@ -19,8 +19,7 @@
 // gfx950): 16x16x4 f32 and 16x16x32 bf16 hold rows 4*(lane/16)+i of column
 // lane%16; 16x16x4 f64 holds rows lane/16 + 4*i.
 //
-// Heterogeneous media: every (target, source) pair has its own cached matrix;
-// the translation streams those matrices once per apply (HBM-bound).
+// Heterogeneous media (every box pair with its own cached matrix) are in pairs.hip.
 #include <algorithm>
 #include <type_traits>
 
@@ -550,371 +549,6 @@ __global__ __launch_bounds__(256) void k_stage_reduce(OffsetGemm g, int rslabs)
     stage_reduce_block<T>(g, rslabs, blockIdx.x);
 }
 
-// ----------------------------------------------------- streaming pairs ----
-
-template <typename T, int RPT>
-__device__ __forceinline__ void load_rows(const T* p, T (&o)[RPT])
-{
-    if constexpr (RPT == 4 && sizeof(T) == 4) {
-        const v4f v = *(const v4f*)p;
-        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
-    } else if constexpr (RPT == 2 && sizeof(T) == 8) {
-        const v2d v = *(const v2d*)p;
-        o[0] = v[0]; o[1] = v[1];
-    } else {
-#pragma unroll
-        for (int e = 0; e < RPT; ++e) o[e] = p[e];
-    }
-}
-
-template <typename T, int RPT>
-__device__ __forceinline__ void store_rows(T* p, const T (&o)[RPT])
-{
-    if constexpr (RPT == 4 && sizeof(T) == 4) {
-        v4f v;
-        v[0] = o[0]; v[1] = o[1]; v[2] = o[2]; v[3] = o[3];
-        *(v4f*)p = v;
-    } else if constexpr (RPT == 2 && sizeof(T) == 8) {
-        v2d v;
-        v[0] = o[0]; v[1] = o[1];
-        *(v2d*)p = v;
-    } else {
-#pragma unroll
-        for (int e = 0; e < RPT; ++e) p[e] = o[e];
-    }
-}
-
-// Tags for the 16-bit plane storage of cached matrices (kOpsSplit, kOpsHi).
-struct OpsSplit {};
-struct OpsHi {};
-
-template <typename TS> struct OpsVal { typedef TS T; };
-template <> struct OpsVal<OpsSplit> { typedef float T; };
-template <> struct OpsVal<OpsHi> { typedef float T; };
-
-template <typename TS>
-constexpr bool ops_planes() { return std::is_same<TS, OpsSplit>::value || std::is_same<TS, OpsHi>::value; }
-
-// One value from 16-bit planes: high half (BF16 bits) plus, for the split form,
-// the signed remainder, i.e. the FP32 bit pattern (hi << 16) + lo.
-template <typename TS>
-__device__ __forceinline__ float plane_value(unsigned hi, int lo)
-{
-    const unsigned bits = std::is_same<TS, OpsSplit>::value ? (hi << 16) + (unsigned)lo : hi << 16;
-    return __uint_as_float(bits);
-}
-
-// RPT consecutive cached values starting at element idx.
-template <typename TS, int RPT>
-__device__ __forceinline__ void load_ops(const PairStream& g, size_t idx, typename OpsVal<TS>::T (&o)[RPT])
-{
-    if constexpr (ops_planes<TS>()) {
-        const unsigned short* hp = (const unsigned short*)g.opsT + idx;
-        const short* lp = (const short*)g.opsT_lo + idx;
-        if constexpr (RPT == 4) {
-            const uint2 h = *(const uint2*)hp;                 // four high halves, 8 bytes
-            unsigned hv[4] = {h.x & 0xffffu, h.x >> 16, h.y & 0xffffu, h.y >> 16};
-            int lv[4] = {0, 0, 0, 0};
-            if constexpr (std::is_same<TS, OpsSplit>::value) {
-                const uint2 l = *(const uint2*)lp;
-                lv[0] = (short)(l.x & 0xffffu);
-                lv[1] = (short)(l.x >> 16);
-                lv[2] = (short)(l.y & 0xffffu);
-                lv[3] = (short)(l.y >> 16);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] = plane_value<TS>(hv[e], lv[e]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < RPT; ++e)
-                o[e] = plane_value<TS>(hp[e], std::is_same<TS, OpsSplit>::value ? (int)lp[e] : 0);
-        }
-    } else {
-        load_rows<TS, RPT>((const TS*)g.opsT + idx, o);
-    }
-}
-
-// One cached value as FP32 (the matrix-core form reads FP32-stored caches).
-template <typename TS>
-__device__ __forceinline__ float load_op1(const PairStream& g, size_t idx)
-{
-    if constexpr (ops_planes<TS>())
-        return plane_value<TS>(((const unsigned short*)g.opsT)[idx],
-                               std::is_same<TS, OpsSplit>::value ? (int)((const short*)g.opsT_lo)[idx] : 0);
-    else
-        return ((const float*)g.opsT)[idx];
-}
-
-// One workgroup (256 threads) per pair.  Each thread owns RPT consecutive
-// output rows (one 16-byte load per matrix row when the row count allows);
-// when the rows need fewer than 256 threads the reduction dimension is split
-// between thread groups, whose partial sums are combined in a fixed order.
-template <typename T, typename TS, int RB, int RPT>
-__global__ __launch_bounds__(256) void k_pair_stream(PairStream g, int b0)
-{
-    extern __shared__ unsigned char smem[];
-    T* ws = (T*)smem;                              // [RB][Kd] source vectors
-    T* red = ws + RB * g.Kd;                       // [RB][M] group sums (only when the reduction is split)
-    const long p = blockIdx.x;
-    const int nb = (g.B - b0) < RB ? (g.B - b0) : RB;
-    const int s = g.src[p];
-    const int rows = g.M / RPT;                    // row groups of RPT rows
-    const int rt = rows < 256 ? rows : 256;        // threads along the rows per chunk
-    const int kgroups = 256 / rt;
-    const int tr = threadIdx.x % rt, kg = threadIdx.x / rt;
-    for (int i = threadIdx.x; i < RB * g.Kd; i += blockDim.x) {
-        const int b = i / g.Kd, k = i - b * g.Kd;
-        ws[i] = (s >= 0 && b < nb) ? ((const T*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k] : T(0);
-    }
-    __syncthreads();
-    const int kchunk = (g.Kd + kgroups - 1) / kgroups;
-    const int k0 = kg * kchunk, k1 = (k0 + kchunk) < g.Kd ? (k0 + kchunk) : g.Kd;
-    for (int rc = 0; rc < rows; rc += rt) {        // uniform over the workgroup
-        const int rg = rc + tr;
-        const bool act = s >= 0 && kg < kgroups && rg < rows;
-        T acc[RB][RPT];
-#pragma unroll
-        for (int b = 0; b < RB; ++b)
-#pragma unroll
-            for (int e = 0; e < RPT; ++e) acc[b][e] = T(0);
-        if (act) {
-            typedef typename OpsVal<TS>::T TV;
-            const size_t col = (size_t)p * g.Kd * g.M + (size_t)rg * RPT;
-            int k = k0;
-            for (; k + 8 <= k1; k += 8) {
-                TV m[8][RPT];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) load_ops<TS, RPT>(g, col + (size_t)(k + u) * g.M, m[u]);
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int b = 0; b < RB; ++b) {
-                        const T w = ws[b * g.Kd + k + u];
-#pragma unroll
-                        for (int e = 0; e < RPT; ++e) acc[b][e] += (T)m[u][e] * w;
-                    }
-            }
-            for (; k < k1; ++k) {
-                TV m[RPT];
-                load_ops<TS, RPT>(g, col + (size_t)k * g.M, m);
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-#pragma unroll
-                    for (int e = 0; e < RPT; ++e) acc[b][e] += (T)m[e] * ws[b * g.Kd + k];
-            }
-        }
-        // kgroups > 1 only when all rows fit one chunk (rows < 256)
-        for (int kgi = 1; kgi < kgroups; ++kgi) {
-            if (kg == kgi && rg < rows) {
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-#pragma unroll
-                    for (int e = 0; e < RPT; ++e) red[b * g.M + rg * RPT + e] = acc[b][e];
-            }
-            __syncthreads();
-            if (kg == 0 && rg < rows) {
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-#pragma unroll
-                    for (int e = 0; e < RPT; ++e) acc[b][e] += red[b * g.M + rg * RPT + e];
-            }
-            __syncthreads();
-        }
-        if (kg == 0 && rg < rows) {
-#pragma unroll
-            for (int b = 0; b < RB; ++b)
-                if (b < nb) store_rows<T, RPT>((T*)g.stage + ((long)b * g.npairs + p) * g.M + rg * RPT, acc[b]);
-        }
-    }
-}
-
-// Many right-hand sides: per pair, stage[b][p][:] = opsT[p]^T-stored matrix times
-// W[b][src], i.e. an (M x Kd) x (Kd x 64) product on the matrix cores, reading the
-// FP32 matrix once for 64 right-hand sides (FP32 or FP64 accumulation; the FP64
-// form converts the stored FP32 values).  Workgroup: one pair and 64 RT rows per
-// wave-row block; the 64 source vectors are staged through LDS, 32 k at a time,
-// transposed so that lanes read consecutive columns.
-template <int PREC, int RT, typename TS>
-__global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rblocks)
-{
-    typedef typename Acc<PREC>::V V;
-    typedef typename Acc<PREC>::T T;
-    constexpr int KC = 32;
-    constexpr int LDW = 80;                       // padded LDS row (columns)
-    __shared__ T wsh[KC * LDW];
-    const long p = blockIdx.x / rblocks;
-    const int rblk = (int)(blockIdx.x % rblocks);
-    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
-    const int s = g.src[p];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
-    const int row0 = (rblk * 4 + wave) * 16 * RT;
-    const size_t A = (size_t)p * g.Kd * g.M;
-    V acc[RT][4];
-#pragma unroll
-    for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
-    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 64 * KC; i += 256) {
-            const int b = i / KC, kk = i - b * KC;
-            T v = T(0);
-            if (s >= 0 && b < nb && k0 + kk < g.Kd) v = ((const T*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k0 + kk];
-            wsh[kk * LDW + b] = v;
-        }
-        __syncthreads();
-        if (s < 0) continue;                      // empty pair: zero rows (uniform over the block)
-#pragma unroll 2
-        for (int kk = 0; kk < KC; kk += 4) {
-            const int k = k0 + kk + grp;
-            T a[RT];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const int row = row0 + 16 * rt + li;
-                a[rt] = (k < g.Kd && row < g.M) ? (T)load_op1<TS>(g, A + (size_t)k * g.M + row) : T(0);
-            }
-            T bf[4];
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) bf[ct] = wsh[(kk + grp) * LDW + 16 * ct + li];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
-                    if constexpr (PREC == ERT_FP64)
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], bf[ct], acc[rt][ct], 0, 0, 0);
-                    else
-                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt], bf[ct], acc[rt][ct], 0, 0, 0);
-                }
-        }
-    }
-    // FP32 tiles: rows 4 grp + i; FP64 tiles: rows grp + 4 i (column li in both)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int b = 16 * ct + li;
-        if (b >= nb) continue;
-        T* dst = (T*)g.stage + ((long)b * g.npairs + p) * g.M;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int base = row0 + 16 * rt;
-            if constexpr (PREC == ERT_FP64) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (base + grp + 4 * i < g.M) dst[base + grp + 4 * i] = acc[rt][ct][i];
-            } else {
-                if (base + 4 * grp + 3 < g.M) *(V*)(dst + base + 4 * grp) = acc[rt][ct];
-            }
-        }
-    }
-}
-
-// Split-BF16x3 form of the same product (FP32-stored matrices): every cached value
-// a and source value w is split into BF16 parts (hi = bf16(v), lo = bf16(v - hi)) and
-// a w is taken as hi_a hi_w + hi_a lo_w + lo_a hi_w, three 16x16x32 BF16 products
-// accumulated in FP32 (the lo_a lo_w term, ~2^-16 relative, is dropped).  The 64
-// source vectors of a 32-long reduction chunk are split once into LDS, source-major,
-// so that a lane reads its eight reduction indices as one 16-byte vector; each lane
-// loads its eight matrix values along the reduction (one per matrix row of 16 lanes,
-// coalesced across the lanes) and splits them in registers.
-template <int RT>
-__global__ __launch_bounds__(256) void k_pair_mfma_bf16x3(PairStream g, int b0, int rblocks)
-{
-    constexpr int KC = 32;
-    constexpr int LDK = KC + 8;                   // padded LDS row (reduction indices)
-    __shared__ __bf16 whi[64 * LDK];
-    __shared__ __bf16 wlo[64 * LDK];
-    const long p = blockIdx.x / rblocks;
-    const int rblk = (int)(blockIdx.x % rblocks);
-    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
-    const int s = g.src[p];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
-    const int row0 = (rblk * 4 + wave) * 16 * RT;
-    const size_t A = (size_t)p * g.Kd * g.M;
-    const float* ops = (const float*)g.opsT;
-    v4f acc[RT][4];
-#pragma unroll
-    for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
-    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 64 * KC; i += 256) {
-            const int b = i / KC, kk = i - b * KC;
-            float v = 0.f;
-            if (s >= 0 && b < nb && k0 + kk < g.Kd)
-                v = ((const float*)g.W)[((long)(b0 + b) * g.nsrc + s) * g.Kd + k0 + kk];
-            const __bf16 h = (__bf16)v;
-            whi[b * LDK + kk] = h;
-            wlo[b * LDK + kk] = (__bf16)(v - (float)h);
-        }
-        __syncthreads();
-        if (s < 0) continue;                      // empty pair: zero rows (uniform over the block)
-        v8bf ah[RT], al[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int row = row0 + 16 * rt + li;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = k0 + 8 * grp + e;
-                const float a = (k < g.Kd && row < g.M) ? ops[A + (size_t)k * g.M + row] : 0.f;
-                const __bf16 h = (__bf16)a;
-                ah[rt][e] = h;
-                al[rt][e] = (__bf16)(a - (float)h);
-            }
-        }
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const int b = 16 * ct + li;
-            const v8bf bh = *(const v8bf*)(whi + b * LDK + 8 * grp);
-            const v8bf bl = *(const v8bf*)(wlo + b * LDK + 8 * grp);
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bh, acc[rt][ct], 0, 0, 0);
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bl, acc[rt][ct], 0, 0, 0);
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][ct], 0, 0, 0);
-            }
-        }
-    }
-    // rows 4 grp + i of column li
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int b = 16 * ct + li;
-        if (b >= nb) continue;
-        float* dst = (float*)g.stage + ((long)b * g.npairs + p) * g.M;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const int base = row0 + 16 * rt;
-            if (base + 4 * grp + 3 < g.M) *(v4f*)(dst + base + 4 * grp) = acc[rt][ct];
-        }
-    }
-}
-
-// Sum of the contiguous staging rows of every target, for rhs b0..b0+nb-1.
-template <typename T>
-__global__ void k_pair_reduce(PairStream g, int b0, int nb)
-{
-    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    const long per = g.ntarget * g.M;
-    if (i >= per * nb) return;
-    const int b = (int)(i / per);
-    const long rem = i - (long)b * per;
-    const long t = rem / g.M;
-    const int r = (int)(rem - t * g.M);
-    const T* St = (const T*)g.stage + (long)b * g.npairs * g.M + r;
-    const long k1 = g.tstart[t + 1];
-    long k = g.tstart[t];
-    T sum = T(0);
-    for (; k + 8 <= k1; k += 8) {
-        T v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = St[(k + u) * g.M];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) sum += v[u];
-    }
-    for (; k < k1; ++k) sum += St[k * g.M];
-    T* d = (T*)g.L + (long)(b0 + b) * per + rem;
-    *d = g.accumulate ? *d + sum : sum;
-}
-
 constexpr int kTM = 2, kTN = 2;
 
 }  // namespace
@@ -1140,124 +774,6 @@ ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g)
 {
     ERT_TRY(offset_gemm_products(s, prec, g));
     return offset_gemm_reduce(s, prec, g);
-}
-
-template <typename T, typename TS, int RPT>
-void launch_pair_stream(hipStream_t s, const PairStream& g, int b0, int rb)
-{
-    const int rows = g.M / RPT;
-    const size_t sh = (size_t)rb * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T);
-    const dim3 grid((unsigned)g.npairs);
-    if (rb == 8) hipLaunchKernelGGL((k_pair_stream<T, TS, 8, RPT>), grid, dim3(256), sh, s, g, b0);
-    else if (rb == 4) hipLaunchKernelGGL((k_pair_stream<T, TS, 4, RPT>), grid, dim3(256), sh, s, g, b0);
-    else if (rb == 2) hipLaunchKernelGGL((k_pair_stream<T, TS, 2, RPT>), grid, dim3(256), sh, s, g, b0);
-    else hipLaunchKernelGGL((k_pair_stream<T, TS, 1, RPT>), grid, dim3(256), sh, s, g, b0);
-}
-
-// Matrix-core form for many right-hand sides (FP32 storage, whole or in planes), 64 per pass.
-template <int PREC, typename TS>
-ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
-{
-    constexpr int RT = (PREC == ERT_FP64) ? 4 : 8;
-    const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
-    for (int b0 = 0; b0 < g.B; b0 += 64) {
-        const int nb = std::min(64, g.B - b0);
-        {
-            StageTimer t_(g.prof, s, g.prof_stage);
-            hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s,
-                               g, b0, rblocks);
-            ERT_HIP(hipGetLastError());
-        }
-        const long n = g.ntarget * g.M * nb;
-        typedef typename Acc<PREC>::T T;
-        StageTimer t_(g.prof, s, ERT_STAGE_REDUCE);
-        hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, nb);
-        ERT_HIP(hipGetLastError());
-    }
-    return ERT_OK;
-}
-
-// Split-BF16x3 matrix-core form (FP32-stored matrices, FP32 vectors), 64 right-hand
-// sides per pass; any right-hand-side count (the product stays HBM-bound with one).
-ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g)
-{
-    constexpr int RT = 4;
-    if (g.M % 4 != 0 || g.ops_fmt != kOpsF32) {
-        record_error("pair_stream: split-BF16x3 products need FP32-stored matrices with rows in fours");
-        return ERT_EINVAL;
-    }
-    const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
-    for (int b0 = 0; b0 < g.B; b0 += 64) {
-        const int nb = std::min(64, g.B - b0);
-        {
-            StageTimer t_(g.prof, s, g.prof_stage);
-            hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT>), dim3((unsigned)(g.npairs * rblocks)), dim3(256), 0, s, g,
-                               b0, rblocks);
-            ERT_HIP(hipGetLastError());
-        }
-        const long n = g.ntarget * g.M * nb;
-        StageTimer t_(g.prof, s, ERT_STAGE_REDUCE);
-        hipLaunchKernelGGL(k_pair_reduce<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, nb);
-        ERT_HIP(hipGetLastError());
-    }
-    return ERT_OK;
-}
-
-// T: arithmetic and vectors; TS: stored matrices (FP32 caches under FP64 products).
-template <typename T, typename TS>
-ert_status pair_stream_t(hipStream_t s, const PairStream& g)
-{
-    constexpr int VEC = ops_planes<TS>() ? 4 : 16 / (int)sizeof(TS);
-    const int rows = g.M % VEC == 0 ? g.M / VEC : g.M;
-    if (g.M < 1 || g.Kd < 1 || (size_t)8 * (g.Kd + (rows < 256 ? g.M : 0)) * sizeof(T) > 64 * 1024) {
-        record_error("pair_stream: unsupported operator shape");
-        return ERT_EINVAL;
-    }
-    if (g.npairs < 1 || g.B < 1) return ERT_OK;
-    for (int b0 = 0; b0 < g.B;) {
-        const int left = g.B - b0;
-        const int rb = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
-        {
-            StageTimer t_(g.prof, s, g.prof_stage);
-            if (g.M % VEC == 0) launch_pair_stream<T, TS, VEC>(s, g, b0, rb);
-            else launch_pair_stream<T, TS, 1>(s, g, b0, rb);
-            ERT_HIP(hipGetLastError());
-        }
-        const long n = g.ntarget * g.M * rb;
-        {
-            StageTimer t_(g.prof, s, ERT_STAGE_REDUCE);
-            hipLaunchKernelGGL(k_pair_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, b0, rb);
-            ERT_HIP(hipGetLastError());
-        }
-        b0 += rb;
-    }
-    return ERT_OK;
-}
-
-ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
-{
-    if (prec == ERT_BF16X3) {
-        if (g.npairs < 1 || g.B < 1) return ERT_OK;
-        return pair_mfma_bf16x3(s, g);
-    }
-    const bool f64 = prec == ERT_FP64;
-    if (f64 && g.ops_fmt == kOpsHi) {
-        record_error("pair_stream: FP64 products do not read the rounded plane alone");
-        return ERT_EINVAL;
-    }
-    if (g.B >= kPairMfmaMinRhs && g.ops_fmt != kOpsNative && g.M % 4 == 0 && g.npairs > 0) {
-        switch (g.ops_fmt) {
-        case kOpsSplit: return f64 ? pair_mfma_t<ERT_FP64, OpsSplit>(s, g) : pair_mfma_t<ERT_FP32, OpsSplit>(s, g);
-        case kOpsHi: return pair_mfma_t<ERT_FP32, OpsHi>(s, g);
-        default: return f64 ? pair_mfma_t<ERT_FP64, float>(s, g) : pair_mfma_t<ERT_FP32, float>(s, g);
-        }
-    }
-    switch (g.ops_fmt) {
-    case kOpsSplit: return f64 ? pair_stream_t<double, OpsSplit>(s, g) : pair_stream_t<float, OpsSplit>(s, g);
-    case kOpsHi: return pair_stream_t<float, OpsHi>(s, g);
-    case kOpsF32: return f64 ? pair_stream_t<double, float>(s, g) : pair_stream_t<float, float>(s, g);
-    default: return f64 ? pair_stream_t<double, double>(s, g) : pair_stream_t<float, float>(s, g);
-    }
 }
 
 }  // namespace ertvie
