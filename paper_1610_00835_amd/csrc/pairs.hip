@@ -99,7 +99,8 @@ __global__ __launch_bounds__(256) void k_pair_sym(PairStream g, int b0, int R)
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = g.M;
     T* wb = (T*)smem;                                   // [RB][M] forward sources (box b)
-    T* bacc = wb + RB * M;                              // [RB][M] backward sums
+    T* wa = wb + RB * M;                                // [RB][M] backward sources (box a)
+    T* bacc = wa + RB * M;                              // [RB][M] backward sums
     T* red = bacc + RB * M;                             // [2][4 waves][RB][SW] forward partials of a strip
     const long u = blockIdx.x;
     const int a = g.ua[u], bs = g.ub[u];
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(256) void k_pair_sym(PairStream g, int b0, int R)
     for (int i = tid; i < RB * M; i += 256) {
         const int b = i / M, k = i - b * M;
         wb[i] = b < nb ? W[((long)(b0 + b) * g.nsrc + bs) * M + k] : T(0);
+        wa[i] = (back && b < nb) ? W[((long)(b0 + b) * g.nsrc + a) * M + k] : T(0);
         bacc[i] = T(0);
     }
     const int CH = RG * R;                              // rows per chunk
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(256) void k_pair_sym(PairStream g, int b0, int R)
 #pragma unroll
             for (int e = 0; e < CPL; ++e) {
                 accf[b][e] = T(0);
-                war[b][e] = (back && b < nb && i0 + e < M) ? W[((long)(b0 + b) * g.nsrc + a) * M + i0 + e] : T(0);
+                war[b][e] = i0 + e < M ? wa[b * M + i0 + e] : T(0);
             }
         for (int c = 0; c < nchunk; ++c) {
             // the next chunk (of this strip, or the first of the next) in flight
@@ -469,11 +471,11 @@ ert_status launch_reduce(hipStream_t s, const PairStream& g, int b0, int nb)
     return ERT_OK;
 }
 
-// LDS of the streaming form: forward sources, backward sums, two strips of the four
-// waves' forward partials (strip width 64 columns at most).
+// LDS of the streaming form: forward and backward sources, backward sums, two strips
+// of the four waves' forward partials (strip width 64 columns at most).
 size_t sym_lds(int M, int rb, size_t tsize)
 {
-    return tsize * (2 * (size_t)rb * M + 2 * 4 * (size_t)rb * 64);
+    return tsize * (3 * (size_t)rb * M + 2 * 4 * (size_t)rb * 64);
 }
 
 template <typename T, typename TS, int VEC>
