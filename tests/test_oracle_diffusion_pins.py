@@ -91,3 +91,35 @@ def test_preconditioner_in_diffusive_regime(oracle_mod):
     res_pc = np.linalg.norm(r - P.apply(z, op=2)) / np.linalg.norm(r)
     res_id = np.linalg.norm(r - P.apply(r, op=2)) / np.linalg.norm(r)
     assert res_pc < 0.25 * res_id
+
+
+@pytest.mark.parametrize("n", [(8, 6), (7, 5), (6, 4, 5), (5, 5, 3)])
+def test_transfers_against_their_definition(n):
+    """The V-cycle's grid transfers, cell by cell: restriction = the average over the (up to
+    2^d) fine cells whose indices halve to the coarse cell (ragged grids: fewer children at
+    the far edge), prolongation = the coarse parent's value; so restricting a prolonged
+    field returns it (to the rounding of the sum of its copies), constants stay constant, and
+    on even grids the total is kept up to the factor 2^d."""
+    st, ss = _medium(n, 5)
+    lv = Dm.Level(n, 1.0 / max(n), st, ss)
+    shp = n[::-1]
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(shp)
+    nc = tuple((v + 1) // 2 for v in n)
+    ref = np.zeros(nc[::-1])
+    cnt = np.zeros(nc[::-1])
+    for idx in np.ndindex(*shp):
+        c = tuple(i // 2 for i in idx)
+        ref[c] += x[idx]
+        cnt[c] += 1
+    ref /= cnt
+    r = Dm._restrict(lv, x)
+    assert r.shape == ref.shape and np.allclose(r, ref, rtol=0, atol=1e-14)
+    e = rng.standard_normal(nc[::-1])
+    p = Dm._prolong(lv, e)
+    for idx in np.ndindex(*shp):
+        assert p[idx] == e[tuple(i // 2 for i in idx)]
+    assert np.allclose(Dm._restrict(lv, Dm._prolong(lv, e)), e, rtol=1e-15, atol=0)
+    assert np.allclose(Dm._restrict(lv, np.full(shp, 2.5)), 2.5, rtol=0, atol=1e-15)
+    if all(v % 2 == 0 for v in n):
+        assert abs(r.sum() * 2 ** len(n) - x.sum()) <= 1e-12 * np.abs(x).sum()
