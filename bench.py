@@ -313,8 +313,10 @@ def many_rhs_64(torch, ertvie, inputs, stream):
     return out
 
 
+# network on the 32^3 coarse grid (trained on the cell averages of 64^3 solves' pairs); the
+# solver applies it to the cell averages of its vectors over 4^3 blocks at 128^3
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
-                       "precond_c5_64.npz")
+                       "precond_c5_32c.npz")
 # network trained on the FFT-based preconditioner's output (it acts after that preconditioner)
 WEIGHTS_FFT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_00835_amd", "weights",
                            "precond_c5_64_fft.npz")
@@ -454,8 +456,8 @@ def c5_solves(torch, ertvie, plan, fd, N):
     U0 = U.clone()
     out["_U0"] = U0
     log("128^3 plain:", json.dumps(out["plain_fp64_gmres"]))
-    runs = [("mixed", dict(mixed=True, inner_tol=1e-2), None),
-            ("mixed_fft", dict(mixed=True, inner_tol=1e-3, precond_fft=True), None)]
+    runs = [("mixed", dict(mixed=True, inner_tol=1e-2), None, None),
+            ("mixed_fft", dict(mixed=True, inner_tol=1e-3, precond_fft=True), None, None)]
     for name, path in (("mixed_learned", WEIGHTS), ("mixed_fft_learned", WEIGHTS_FFT)):
         if os.path.exists(path):
             w = np.load(path)
@@ -464,11 +466,14 @@ def c5_solves(torch, ertvie, plan, fd, N):
                       precond_steps=int(meta.get("precond_steps", 0)))
             if "fft" in name:
                 kw["precond_fft"] = True
-            runs.append((name, kw, w["params"]))
-    for name, kw, params in runs:
+            # a coarse-grid network keeps its grid; a full-grid one takes the plan's
+            f = int(meta.get("coarsen", 1))
+            ngrid = tuple(int(v) for v in meta["n"]) if f > 1 else (C5_N,) * 3
+            runs.append((name, kw, w["params"], ngrid))
+    for name, kw, params, ngrid in runs:
         net = None
         if params is not None:
-            net = ertvie.Net(tuple(int(v) for v in (C5_N,) * 3), stream=plan.stream)
+            net = ertvie.Net(ngrid, stream=plan.stream)
             net.set_params(params)
             kw = dict(kw, precond=net)
         try:

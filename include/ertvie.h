@@ -161,7 +161,11 @@ typedef struct {
                          network acts on M's output, z_j = net(M v_j), and the fallback of a
                          rejected step keeps M; with `block`, block GMRES on (I - K) M with
                          U = M Y.  ERT_PRECOND_NONE (0): none */
-    ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3, same grid): the solve
+    ert_net_t precond;/* NULL, or a learned right preconditioner (dim 3) on the plan's grid or on
+                         that grid coarsened by one integer factor f on every axis (the network
+                         then sees the cell averages of the vector and of the media over f^3
+                         blocks, and its correction is extended piecewise constant:
+                         z = v + P(s y(R v))): the solve
                          becomes a refinement loop.  Each step solves (I - K) d = r by flexible
                          GMRES with z_j = net(v_j) (inner operator: FP32 with `mixed`, else the
                          plan's), and is kept only if the true residual phi - (I - K)(U + d),
@@ -288,6 +292,22 @@ ERT_API ert_status ert_vie_transport(ert_vie_plan_t plan, const double* U, const
  * stream and synchronises that stream before returning. */
 ERT_API ert_status ert_vie_transport_noalloc(ert_vie_plan_t plan, const double* U, const double* f,
                                              const double* dirs, int ndir, double* phi);
+
+/* The learned right preconditioner as the solver applies it (ert_solve_opts.precond): z =
+ * M(r) for one column on the plan's media, with the network on the plan's grid or on that
+ * grid coarsened by one integer factor f (cell averages of r and the media over f^3 blocks
+ * in, the correction extended piecewise constant out).  r, z: device N FP64 (may not
+ * overlap).  Stream-ordered on the plan's stream.  Not part of the paper's method. */
+ERT_API ert_status ert_vie_net_apply(ert_vie_plan_t plan, ert_net_t net, const double* r, double* z);
+
+/* Cell averages over blocks of factor^3 cells (3D grids whose sides are multiples of
+ * factor): y[c] = factor^-3 * sum of x over the cells of coarse cell c, the coarse grid
+ * (n_a / factor per axis) in the same x-fastest order; the restriction a coarse-grid
+ * learned preconditioner applies to its inputs (not part of the paper's method).
+ * x: device N x nrhs, y: device (N / factor^3) x nrhs, column-major FP64; nrhs >= 1
+ * (any count: no plan buffer is used).  Stream-ordered, asynchronous.  ERT_EUNSUPPORTED
+ * in 2D. */
+ERT_API ert_status ert_vie_restrict(ert_vie_plan_t plan, int factor, const double* x, double* y, int nrhs);
 
 /* Diffusion preconditioner (Sec. 4.4, eq. EQ:DA).  The diffusion approximation
  *   -div(D grad U) + mu_a U = f,  U + l dU/dn = 0 on the boundary,

@@ -274,6 +274,30 @@ def precondition(params, r, sigma_t, sigma_s, n, widths=(16, 32, 64), bf16=False
     return np.asarray(r, dtype=np.float64) + s * y.ravel()
 
 
+def restrict(x, n, f):
+    """Cell averages of a flat field on an n0 x n1 x n2 grid (x fastest) over f x f x f blocks."""
+    X = np.asarray(x, dtype=np.float64).reshape(n[2] // f, f, n[1] // f, f, n[0] // f, f)
+    return X.mean(axis=(1, 3, 5)).ravel()
+
+
+def prolong(y, nc, f):
+    """A coarse field (nc0 x nc1 x nc2) extended piecewise constant to the grid refined by f."""
+    Y = np.asarray(y, dtype=np.float64).reshape(nc[2], nc[1], nc[0])
+    return np.repeat(np.repeat(np.repeat(Y, f, axis=0), f, axis=1), f, axis=2).ravel()
+
+
+def precondition_coarse(params, r, sigma_t, sigma_s, n, f, widths=(16, 32, 64), bf16=False):
+    """The network on the grid coarsened by f: z = r + P(s_c net(features(R r, R sigma_t,
+    R sigma_s))), R the cell averages over f^3 blocks, P the piecewise-constant extension."""
+    nc = tuple(v // f for v in n)
+    rc = restrict(r, n, f)
+    F, s = features(rc, restrict(sigma_t, n, f), restrict(sigma_s, n, f), nc)
+    if bf16:
+        F = F.astype(np.float32).astype(np.float64)
+    y = forward(params, F[None], widths, bf16)[0]
+    return np.asarray(r, dtype=np.float64) + prolong(s * y.ravel(), nc, f)
+
+
 def target(r, e):
     """Training target (e - r) / rms(r) for a pair (r, e), flat."""
     s = float(np.sqrt(np.mean(np.asarray(r) ** 2)))

@@ -274,11 +274,11 @@ ert_status gmres_run(ert_plan_impl* p, int method, int prec, const double* b, do
                 double* zj = Z + (size_t)j * N;
                 if (pc->kind && pc->net) {
                     ERT_TRY(precond_apply(p, pc->kind, vj, w, 1));
-                    ERT_TRY(net_precond(pc->net, w, p->d_st, p->d_ss, zj, p->stream));
+                    ERT_TRY(net_precond(pc->net, w, p->d_st, p->d_ss, zj, p->stream, p->o.n));
                 } else if (pc->kind) {
                     ERT_TRY(precond_apply(p, pc->kind, vj, zj, 1));
                 } else {
-                    ERT_TRY(net_precond(pc->net, vj, p->d_st, p->d_ss, zj, p->stream));
+                    ERT_TRY(net_precond(pc->net, vj, p->d_st, p->d_ss, zj, p->stream, p->o.n));
                 }
                 if (pc->net) rs->precond++;
                 vj = zj;
@@ -664,6 +664,35 @@ ert_status ert_vie_transport_noalloc(ert_vie_plan_t p, const double* U, const do
     return transport_sweep_noalloc(p, U, f, dirs, ndir, phi);
 }
 
+ert_status ert_vie_net_apply(ert_vie_plan_t p, ert_net_t net, const double* r, double* z)
+{
+    if (!p || !net || !r || !z) return ERT_EINVAL;
+    NetImpl* n = net_impl(net);
+    const int* g = net_grid(n);
+    const int f = p->o.dim == 3 && g[0] > 0 ? p->geo.n0 / g[0] : 0;
+    if (p->o.dim != 3 || f < 1 || g[0] * f != p->geo.n0 || g[1] * f != p->geo.n1 || g[2] * f != p->geo.n2) {
+        record_error("ert_vie_net_apply: the network's grid is not the plan's grid coarsened by one factor");
+        return ERT_EINVAL;
+    }
+    return net_precond(n, r, p->d_st, p->d_ss, z, p->stream, p->o.n);
+}
+
+ert_status ert_vie_restrict(ert_vie_plan_t p, int factor, const double* x, double* y, int nrhs)
+{
+    if (!p || !x || !y || nrhs < 1 || factor < 1) return ERT_EINVAL;
+    if (p->o.dim != 3) {
+        record_error("ert_vie_restrict: three-dimensional grids only");
+        return ERT_EUNSUPPORTED;
+    }
+    const int n[3] = {p->geo.n0, p->geo.n1, p->geo.n2};
+    for (int a = 0; a < 3; ++a)
+        if (n[a] % factor != 0) {
+            record_error("ert_vie_restrict: the grid is not a multiple of the factor");
+            return ERT_EINVAL;
+        }
+    return restrict_avg(p->stream, x, n, factor, y, nrhs);
+}
+
 ert_status ert_vie_diff_precond(ert_vie_plan_t p, const double* r, double* z, int nrhs)
 {
     if (!p || !r || !z || nrhs < 1 || nrhs > p->nrhs_max) return ERT_EINVAL;
@@ -702,8 +731,9 @@ ert_status ert_vie_solve(ert_vie_plan_t p, const double* f, double* U, int nrhs,
     NetImpl* net = so.precond ? net_impl(so.precond) : nullptr;
     if (net) {
         const int* g = net_grid(net);
-        if (p->o.dim != 3 || g[0] != p->geo.n0 || g[1] != p->geo.n1 || g[2] != p->geo.n2) {
-            record_error("ert_vie_solve: the preconditioner's grid differs from the plan's");
+        const int f = p->o.dim == 3 && g[0] > 0 ? p->geo.n0 / g[0] : 0;
+        if (p->o.dim != 3 || f < 1 || g[0] * f != p->geo.n0 || g[1] * f != p->geo.n1 || g[2] * f != p->geo.n2) {
+            record_error("ert_vie_solve: the preconditioner's grid is not the plan's grid coarsened by one factor");
             return ERT_EINVAL;
         }
         if (so.block && nrhs > 1) {

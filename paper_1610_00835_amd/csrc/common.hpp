@@ -340,7 +340,12 @@ ert_status dev_dgemm(hipStream_t s, int M, int N, long K, double alpha, const do
 // one column), ordered on stream s.
 struct NetImpl;
 NetImpl* net_impl(ert_net_t net);
-ert_status net_precond(NetImpl* n, const double* r, const double* st, const double* ss, double* z, hipStream_t s);
+// pn: the plan's grid, the network's grid times f >= 1 on every axis (f > 1: the network acts
+// on cell averages over f^3 blocks and its output is extended piecewise constant).
+ert_status net_precond(NetImpl* n, const double* r, const double* st, const double* ss, double* z, hipStream_t s,
+                       const int* pn);
+// y = cell averages of x over f^3 blocks of the grid n (nrhs columns; unet.hip).
+ert_status restrict_avg(hipStream_t s, const double* x, const int n[3], int f, double* y, int nrhs);
 const int* net_grid(const NetImpl* n);
 
 // Gauss-Legendre nodes/weights on [-1,1] (host).

@@ -19,7 +19,8 @@
 // (HBM-bound: each stored value is read once per pass).  From
 // kPairMfmaMinRhs right-hand sides on, and for the split-BF16x3 products always,
 // the matrix cores take 64 right-hand sides per pass, the forward and the
-// backward products as two launches over the blocks.
+// backward products as two launches over the blocks (the backward one reads the
+// blocks row-wise through LDS).
 #include <algorithm>
 #include <type_traits>
 
@@ -261,13 +262,12 @@ __device__ __forceinline__ float load_one(const PairStream& g, size_t idx)
 }
 
 // Matrix-core form, 64 right-hand sides per pass: per block, the (M x M) x (M x 64)
-// product of the forward (TRANS = false: A[r][k] = B[k][r], sources of box b, row
-// fwd_row) or the backward direction (TRANS = true: A[r][k] = B[r][k], sources of
-// box a, row bwd_row; nothing for a self block), FP32 or FP64 accumulation over the
-// FP32 values.  Workgroup: one block and 64 RT output rows per wave-row block; the
-// 64 source vectors pass through LDS, 32 reduction indices at a time, transposed
-// so that lanes read consecutive columns.
-template <int PREC, int RT, typename TS, bool TRANS>
+// product of the forward direction (A[r][k] = B[k][r], sources of box b, row
+// fwd_row), FP32 or FP64 accumulation over the FP32 values.  Workgroup: one block
+// and 64 RT output rows per wave-row block; the 64 source vectors pass through LDS,
+// 32 reduction indices at a time, transposed so that lanes read consecutive columns;
+// lanes read the block along its rows (consecutive r), coalesced.
+template <int PREC, int RT, typename TS>
 __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rblocks)
 {
     typedef typename Acc<PREC>::V V;
@@ -276,11 +276,10 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rbl
     constexpr int LDW = 80;                       // padded LDS row (columns)
     __shared__ T wsh[KC * LDW];
     const long p = blockIdx.x / rblocks;
-    const long row = TRANS ? g.bwd_row[p] : g.fwd_row[p];
-    if (row < 0) return;                          // self block: no backward product (uniform)
+    const long row = g.fwd_row[p];
     const int rblk = (int)(blockIdx.x % rblocks);
     const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
-    const int s = TRANS ? g.ua[p] : g.ub[p];
+    const int s = g.ub[p];
     const int M = g.M;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
     const int row0 = (rblk * 4 + wave) * 16 * RT;
@@ -306,8 +305,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rbl
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int r = row0 + 16 * rt + li;
-                const size_t idx = TRANS ? A + (size_t)r * M + k : A + (size_t)k * M + r;
-                av[rt] = (k < M && r < M) ? (T)load_one<TS>(g, idx) : T(0);
+                av[rt] = (k < M && r < M) ? (T)load_one<TS>(g, A + (size_t)k * M + r) : T(0);
             }
             T bf[4];
 #pragma unroll
@@ -332,6 +330,92 @@ __global__ __launch_bounds__(256) void k_pair_mfma(PairStream g, int b0, int rbl
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int base = row0 + 16 * rt;
+            if constexpr (PREC == ERT_FP64) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (base + grp + 4 * i < M) dst[base + grp + 4 * i] = acc[rt][ct][i];
+            } else {
+                if (base + 4 * grp + 3 < M) *(V*)(dst + base + 4 * grp) = acc[rt][ct];
+            }
+        }
+    }
+}
+
+// The backward direction of the matrix-core form: out[j][b] = sum_i B[j][i] W_a[i][b],
+// whose A operand runs along the stored rows (A[r][k] = B[r][k]).  A tile of the
+// workgroup's 64 RT rows and 32 reduction indices is read row-wise (eight lanes per
+// 128-byte row piece) into LDS, and the lanes take their operands from there.
+template <int PREC, int RT, typename TS>
+__global__ __launch_bounds__(256) void k_pair_mfma_back(PairStream g, int b0, int rblocks)
+{
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    constexpr int KC = 32;
+    constexpr int LDW = 80;                       // padded LDS row of the sources (columns)
+    constexpr int ROWS = 64 * RT;                 // rows of the workgroup
+    constexpr int TP = KC + 4;                    // tile pitch (floats)
+    __shared__ T wsh[KC * LDW];
+    __shared__ __align__(16) float tile[ROWS * TP];
+    const long p = blockIdx.x / rblocks;
+    const long row = g.bwd_row[p];
+    if (row < 0) return;                          // self block: no backward product (uniform)
+    const int rblk = (int)(blockIdx.x % rblocks);
+    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
+    const int s = g.ua[p];
+    const int M = g.M;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
+    const int rw0 = rblk * ROWS;                  // first row of the workgroup
+    const int row0 = wave * 16 * RT;              // first row of the wave (in the tile)
+    const size_t A = (size_t)p * M * M;
+    V acc[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
+    for (int k0 = 0; k0 < M; k0 += KC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * KC; i += 256) {
+            const int b = i / KC, kk = i - b * KC;
+            T v = T(0);
+            if (b < nb && k0 + kk < M) v = ((const T*)g.W)[((long)(b0 + b) * g.nsrc + s) * M + k0 + kk];
+            wsh[kk * LDW + b] = v;
+        }
+        // the tile: ROWS rows x KC columns, 16-byte pieces (M is a multiple of 4)
+        for (int c = threadIdx.x; c < ROWS * (KC / 4); c += 256) {
+            const int rr = c / (KC / 4), c4 = (c - rr * (KC / 4)) * 4;
+            const int r = rw0 + rr, k = k0 + c4;
+            float o[4] = {0.f, 0.f, 0.f, 0.f};
+            if (r < M && k < M) load_vals<TS, 4>(g, A + (size_t)r * M + k, o);
+            *(v4f*)(tile + rr * TP + c4) = v4f{o[0], o[1], o[2], o[3]};
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < KC; kk += 4) {
+            T av[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) av[rt] = (T)tile[(row0 + 16 * rt + li) * TP + kk + grp];
+            T bf[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) bf[ct] = wsh[(kk + grp) * LDW + 16 * ct + li];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    if constexpr (PREC == ERT_FP64)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+                    else
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+                }
+        }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int b = 16 * ct + li;
+        if (b >= nb) continue;
+        T* dst = (T*)g.stage + ((long)b * g.nrows + row) * M;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int base = rw0 + row0 + 16 * rt;
             if constexpr (PREC == ERT_FP64) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -525,16 +609,18 @@ template <int PREC, typename TS>
 ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
 {
     constexpr int RT = (PREC == ERT_FP64) ? 4 : 8;
+    constexpr int RTB = 4;                        // backward: 256 rows per workgroup (LDS tile)
     typedef typename Acc<PREC>::T T;
     const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
-    const dim3 grid((unsigned)(g.npairs * rblocks));
+    const int rblocksb = (g.M + 64 * RTB - 1) / (64 * RTB);
+    const dim3 grid((unsigned)(g.npairs * rblocks)), gridb((unsigned)(g.npairs * rblocksb));
     for (int b0 = 0; b0 < g.B; b0 += 64) {
         const int nb = std::min(64, g.B - b0);
         {
             StageTimer t_(g.prof, s, g.prof_stage);
-            hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS, false>), grid, dim3(256), 0, s, g, b0, rblocks);
+            hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), grid, dim3(256), 0, s, g, b0, rblocks);
             ERT_HIP(hipGetLastError());
-            hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS, true>), grid, dim3(256), 0, s, g, b0, rblocks);
+            hipLaunchKernelGGL((k_pair_mfma_back<PREC, RTB, TS>), gridb, dim3(256), 0, s, g, b0, rblocksb);
             ERT_HIP(hipGetLastError());
         }
         ERT_TRY(launch_reduce<T>(s, g, b0, nb));

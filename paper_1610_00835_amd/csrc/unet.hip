@@ -455,9 +455,50 @@ __global__ void k_out(const float* y, const double* r, const double* scale, long
     z[(long)b * V + i] = r[(long)b * V + i] + (double)y[(long)b * V + i] * scale[b];
 }
 
+// z = r + scale * y(parent cell) on the fine grid (n0 x n1 x n2, x fastest): the
+// network's output on the grid coarsened by f, extended piecewise constant.
+__global__ void k_out_prolong(const float* y, const double* r, const double* scale, int n0, int n1, int n2, int f,
+                              double* z)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long N = (long)n0 * n1 * n2;
+    if (i >= N) return;
+    const int i0 = (int)(i % n0), i1 = (int)((i / n0) % n1), i2 = (int)(i / ((long)n0 * n1));
+    const int c0 = n0 / f, c1 = n1 / f;
+    const long c = i0 / f + (long)c0 * (i1 / f + (long)c1 * (i2 / f));
+    z[i] = r[i] + (double)y[c] * scale[0];
+}
+
 inline unsigned nblocks(long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+// Cell averages over f x f x f blocks: y[c] = f^-3 sum of x over the fine cells of coarse
+// cell c (fine grid n0 x n1 x n2, every n_a a multiple of f, x fastest; fixed summation
+// order: z, then y, then x).  nrhs columns of N fine / N / f^3 coarse values.
+__global__ void k_restrict(const double* __restrict__ x, int n0, int n1, int n2, int f, double* __restrict__ y)
+{
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    const int c0 = n0 / f, c1 = n1 / f, c2 = n2 / f;
+    const long Nc = (long)c0 * c1 * c2, N = (long)n0 * n1 * n2;
+    if (i >= Nc) return;
+    const int j0 = (int)(i % c0) * f, j1 = (int)((i / c0) % c1) * f, j2 = (int)(i / ((long)c0 * c1)) * f;
+    const double* xb = x + (long)b * N;
+    double s = 0.0;
+    for (int dz = 0; dz < f; ++dz)
+        for (int dy = 0; dy < f; ++dy)
+            for (int dx = 0; dx < f; ++dx) s += xb[(j0 + dx) + (long)n0 * ((j1 + dy) + (long)n1 * (j2 + dz))];
+    y[(long)b * Nc + i] = s / (double)(f * f * f);
+}
+
+ert_status restrict_avg(hipStream_t s, const double* x, const int n[3], int f, double* y, int nrhs)
+{
+    const long Nc = (long)(n[0] / f) * (n[1] / f) * (n[2] / f);
+    hipLaunchKernelGGL(k_restrict, dim3(nblocks(Nc), nrhs), dim3(256), 0, s, x, n[0], n[1], n[2], f, y);
+    ERT_HIP(hipGetLastError());
+    return ERT_OK;
+}
 
 // ----------------------------------------------------------------- host ----
 
@@ -490,6 +531,7 @@ struct NetImpl {
     size_t part_elems = 0;
     double *scale = nullptr, *red = nullptr, *tt = nullptr, *loss = nullptr;
     int red_blk = 64;
+    double* coarse = nullptr;   // restricted residual and media (3 V) for use on a finer plan grid
     std::vector<void*> allocs;
 
     ert_status alloc(void* pp, size_t bytes)
@@ -698,17 +740,37 @@ ert_status backward(NetImpl* n, const double* r, const double* e)
 
 }  // namespace
 
-// Solver-side use: z = M(r) for one residual column on the plan's media.
-ert_status net_precond(NetImpl* n, const double* r, const double* st, const double* ss, double* z, hipStream_t s)
+// Solver-side use: z = M(r) for one residual column on the plan's media (grid pn).
+// A network on the plan's grid coarsened by f (pn = f n) acts on the cell averages of
+// r, sigma_t and sigma_s over f^3 blocks, and its output is extended piecewise
+// constant: z = r + P(s_c y(R r)).
+ert_status net_precond(NetImpl* n, const double* r, const double* st, const double* ss, double* z, hipStream_t s,
+                       const int* pn)
 {
+    const int f = pn[0] / n->n[0];
     hipStream_t keep = n->s;
     n->s = s;
     n->B_run = 1;
-    ert_status st_ = features(n, r, st, ss, 0);
+    ert_status st_ = ERT_OK;
+    if (f > 1) {
+        if (!n->coarse) st_ = n->alloc(&n->coarse, 3 * (size_t)n->V * sizeof(double));
+        if (st_ == ERT_OK) st_ = restrict_avg(s, r, pn, f, n->coarse, 1);
+        if (st_ == ERT_OK) st_ = restrict_avg(s, st, pn, f, n->coarse + n->V, 1);
+        if (st_ == ERT_OK) st_ = restrict_avg(s, ss, pn, f, n->coarse + 2 * n->V, 1);
+        if (st_ == ERT_OK) st_ = features(n, n->coarse, n->coarse + n->V, n->coarse + 2 * n->V, 0);
+    } else {
+        st_ = features(n, r, st, ss, 0);
+    }
     if (st_ == ERT_OK) st_ = forward(n);
     if (st_ == ERT_OK) {
-        hipLaunchKernelGGL(k_out, dim3(nblocks(n->V), 1), dim3(256), 0, s, (const float*)n->Y, r,
-                           (const double*)n->scale, n->V, z);
+        if (f > 1) {
+            const long N = (long)pn[0] * pn[1] * pn[2];
+            hipLaunchKernelGGL(k_out_prolong, dim3(nblocks(N), 1), dim3(256), 0, s, (const float*)n->Y, r,
+                               (const double*)n->scale, pn[0], pn[1], pn[2], f, z);
+        } else {
+            hipLaunchKernelGGL(k_out, dim3(nblocks(n->V), 1), dim3(256), 0, s, (const float*)n->Y, r,
+                               (const double*)n->scale, n->V, z);
+        }
         if (hipGetLastError() != hipSuccess) st_ = ERT_EDEVICE;
     }
     n->s = keep;

@@ -110,6 +110,10 @@ def load():
     L.ert_vie_fft_precond.argtypes = [_vp, _vp, _vp, ctypes.c_int]
     L.ert_vie_transport.restype = ctypes.c_int
     L.ert_vie_transport.argtypes = [_vp, _vp, _vp, _dp, ctypes.c_int, _vp]
+    L.ert_vie_net_apply.restype = ctypes.c_int
+    L.ert_vie_net_apply.argtypes = [_vp, _vp, _vp, _vp]
+    L.ert_vie_restrict.restype = ctypes.c_int
+    L.ert_vie_restrict.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
     L.ert_vie_transport_noalloc.restype = ctypes.c_int
     L.ert_vie_transport_noalloc.argtypes = [_vp, _vp, _vp, _dp, ctypes.c_int, _vp]
     L.ert_vie_diff_precond.restype = ctypes.c_int
@@ -261,6 +265,27 @@ class Plan:
         _check(fn(self.handle, up, fp, dirs.ctypes.data_as(_dp), nd, pp),
                "ert_vie_transport_noalloc" if noalloc else "ert_vie_transport")
         return phi
+
+    def net_apply(self, net, r, z):
+        """z = M(r): the learned preconditioner `net` (on this grid or a coarsened one) as the
+        solver applies it, on this plan's media (r, z: (N,) float64 CUDA tensors)."""
+        rp, nr = _dev_ptr(r, self.N, "r")
+        zp, nz = _dev_ptr(z, self.N, "z")
+        if nr != 1 or nz != 1:
+            raise ValueError("one column")
+        _check(load().ert_vie_net_apply(self.handle, net.handle, rp, zp), "ert_vie_net_apply")
+        return z
+
+    def restrict(self, x, y, factor):
+        """y = cell averages of x over factor^3 blocks (x: (nrhs, N) or (N,) float64 CUDA tensor
+        on this grid, y: the same on the grid coarsened by factor)."""
+        xp, nx = _dev_ptr(x, self.N, "x")
+        nc = self.N // factor ** 3
+        yp, ny = _dev_ptr(y, nc, "y")
+        if nx != ny:
+            raise ValueError("x and y differ in nrhs")
+        _check(load().ert_vie_restrict(self.handle, int(factor), xp, yp, nx), "ert_vie_restrict")
+        return y
 
     def diff_precond(self, r, z):
         """z = r + (two V-cycles for the diffusion approximation with source sigma_s r)."""

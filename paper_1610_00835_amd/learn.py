@@ -4,7 +4,8 @@ Training pairs come from the method's own solves: a plain restarted GMRES solve
 of (I - K) U = phi records, at the start of every cycle k, the iterate U_k and
 its residual r_k = phi - (I - K) U_k; once converged, the correction of U_k is
 e_k = U - U_k, and (I - K) e_k = r_k up to the solve tolerance.  The network
-learns r -> e on those pairs (with the medium as extra input channels).
+learns r -> e on those pairs (with the medium as extra input channels); a network on
+a coarser grid learns the cell averages of the pairs (restrict_pairs).
 
 All arithmetic of the solve and of training runs in libertvie.so; this module
 draws the seeded initial parameters and batches, and copies vectors between
@@ -48,6 +49,24 @@ def collect_pairs(plan, f, restart=5, tol=1e-10, max_pairs=64, max_iter=3000, ff
         for i in range(k):
             plan.fft_precond(R[i], R[i])
     return R, E, info
+
+
+def restrict_pairs(plan, R, E, sigma_t, sigma_s, f):
+    """The pairs (R, E) and the medium of `plan` averaged over f^3 blocks (ert_vie_restrict):
+    the training data of a network on the plan's grid coarsened by f.  Returns (Rc, Ec,
+    sigma_t_c, sigma_s_c), the media as host arrays."""
+    import torch
+    nc = plan.N // f ** 3
+    Rc = torch.empty((R.shape[0], nc), dtype=torch.float64, device="cuda")
+    Ec = torch.empty_like(Rc)
+    plan.restrict(R.contiguous(), Rc, f)
+    plan.restrict(E.contiguous(), Ec, f)
+    med = torch.as_tensor(np.stack([np.asarray(sigma_t, dtype=np.float64), np.asarray(sigma_s, dtype=np.float64)])).cuda()
+    medc = torch.empty((2, nc), dtype=torch.float64, device="cuda")
+    plan.restrict(med, medc, f)
+    torch.cuda.synchronize()
+    mc = medc.cpu().numpy()
+    return Rc, Ec, mc[0], mc[1]
 
 
 class PairSet:

@@ -42,6 +42,8 @@ def test_strerror_and_null_plan_without_gpu():
     assert L.ert_vie_fft_info(None, None) == ertvie.EINVAL
     assert L.ert_vie_transport(None, None, None, None, 1, None) == ertvie.EINVAL
     assert L.ert_vie_transport_noalloc(None, None, None, None, 1, None) == ertvie.EINVAL
+    assert L.ert_vie_restrict(None, 2, None, None, 1) == ertvie.EINVAL
+    assert L.ert_vie_net_apply(None, None, None, None) == ertvie.EINVAL
     assert L.ert_vie_diff_precond(None, None, None, 1) == ertvie.EINVAL
 
 

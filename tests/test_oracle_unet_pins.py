@@ -168,3 +168,38 @@ def test_features():
     assert F.shape == (3, 4, 8, 4)
     assert np.isclose(np.mean(F[0] ** 2), 1.0)
     assert np.isclose(F[1].ravel()[17], np.log(st[17])) and np.allclose(F[2], 0.9)
+
+
+def test_restriction_and_extension_invariants():
+    """Cell averages: a constant stays constant, the total (times f^3) is kept, averaging a
+    piecewise-constant extension gives the coarse field back, and the averages of a
+    linear field are its values at the block centres."""
+    rng = np.random.default_rng(3)
+    n, f = (8, 12, 4), 2
+    nc = (4, 6, 2)
+    x = rng.standard_normal(int(np.prod(n)))
+    assert np.allclose(U.restrict(np.full(x.size, 3.5), n, f), 3.5, rtol=0, atol=1e-15)
+    assert abs(U.restrict(x, n, f).sum() * f ** 3 - x.sum()) <= 1e-12 * np.abs(x).sum()
+    y = rng.standard_normal(int(np.prod(nc)))
+    assert np.allclose(U.restrict(U.prolong(y, nc, f), n, f), y, rtol=1e-15, atol=0)
+    # linear field a + b.x at cell centres (i + 1/2): block averages sit at the block centres
+    i2, i1, i0 = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    lin = (1.0 + 0.5 * (i0 + 0.5) - 0.25 * (i1 + 0.5) + 2.0 * (i2 + 0.5)).ravel()
+    c2, c1, c0 = np.meshgrid(np.arange(nc[2]), np.arange(nc[1]), np.arange(nc[0]), indexing="ij")
+    ctr = (1.0 + 0.5 * f * (c0 + 0.5) - 0.25 * f * (c1 + 0.5) + 2.0 * f * (c2 + 0.5)).ravel()
+    assert np.allclose(U.restrict(lin, n, f), ctr, rtol=0, atol=1e-12)
+
+
+def test_coarse_preconditioner_reduces_to_the_network_when_f_is_one():
+    """With f = 1 the coarse-grid composition is the network itself; with zero parameters it
+    is the identity for any f."""
+    rng = np.random.default_rng(5)
+    n = (8, 8, 8)
+    N = 512
+    p = rng.standard_normal(U.param_count()) * 0.05
+    r = rng.standard_normal(N)
+    st = rng.uniform(1.0, 20.0, N)
+    ss = st * 0.9
+    assert np.allclose(U.precondition_coarse(p, r, st, ss, n, 1), U.precondition(p, r, st, ss, n), rtol=0, atol=1e-13)
+    z0 = U.precondition_coarse(np.zeros(U.param_count()), r, st, ss, n, 2)
+    assert np.array_equal(z0, r)
