@@ -309,6 +309,21 @@ def many_rhs_64(torch, ertvie, inputs, stream):
         r = plan.solve(F[:4].contiguous(), U4, tol=1e-8)
         out["columns_fp64_4_of_64"] = {k: r[k] for k in keys}
         out["columns_fp64_64_extrapolated_s"] = r["t_solve"] * 16
+    # the far-field translations as split-BF16x3 against FP32, both at order 8 on 64 columns
+    with ertvie.plan_from_case(case, method="fmm", prec="fp32", stream=stream, nrhs_max=64) as plan:
+        X = torch.from_numpy(np.ascontiguousarray(inputs.random_vector(plan.N, 5, nrhs=64).T)).cuda()
+        Y = torch.empty_like(X)
+        res = {}
+        for prec in ("fp32", "bf16x3"):
+            ms = timed_applies(torch, plan, X, Y, ertvie.OP_A, 3, 2, prec=prec)
+            res[prec] = Y.clone()
+            plan.apply(X, Y, op=ertvie.OP_A, prec=prec)
+            plan.profile(True)
+            plan.apply(X, Y, op=ertvie.OP_A, prec=prec)
+            st = {k: v[0] for k, v in plan.profile(False).items() if v[1]}
+            out["apply_64rhs_order8_" + prec] = {"apply_ms": ms, "m2l_ms": st.get("m2l"), "near_ms": st.get("near")}
+        out["bf16x3_vs_fp32_rel_l2"] = float(torch.linalg.norm(res["bf16x3"] - res["fp32"]) /
+                                             torch.linalg.norm(res["fp32"]))
     log("64 right-hand sides:", json.dumps(out))
     return out
 
@@ -334,6 +349,10 @@ C5_CHEB, C5_INNER_CHEB = 6, 4
 # (workload, precision, stage of the kernel, execution forms); a combination without counters,
 # or a kernel changed since they were taken, reports null.
 MEASURED_TRAFFIC = dict(MEASURED_TRAFFIC)
+# 128^3 FP64 operator (k_pair_sym over the symmetric caches): far field 66.13 GB per apply in
+# 3 launches, near field 53.90 GB in one (profiles/pair_sym_c5_128cubed_hbm_traffic.md)
+MEASURED_TRAFFIC[("c5_128", "fp64", "m2l")] = 22.043e9
+MEASURED_TRAFFIC[("c5_128", "fp64", "near")] = 53.902e9
 
 
 def het_roofline(info, stage_ms, launches, n, near_plane_bytes=4, workload=None):
