@@ -349,10 +349,6 @@ C5_CHEB, C5_INNER_CHEB = 6, 4
 # (workload, precision, stage of the kernel, execution forms); a combination without counters,
 # or a kernel changed since they were taken, reports null.
 MEASURED_TRAFFIC = dict(MEASURED_TRAFFIC)
-# 128^3 FP64 operator (k_pair_sym over the symmetric caches): far field 66.13 GB per apply in
-# 3 launches, near field 53.90 GB in one (profiles/pair_sym_c5_128cubed_hbm_traffic.md)
-MEASURED_TRAFFIC[("c5_128", "fp64", "m2l")] = 22.043e9
-MEASURED_TRAFFIC[("c5_128", "fp64", "near")] = 53.902e9
 
 
 def het_roofline(info, stage_ms, launches, n, near_plane_bytes=4, workload=None):

@@ -78,169 +78,269 @@ __device__ __forceinline__ void load_vals(const PairStream& g, size_t idx, float
     }
 }
 
-// Streaming form, RB right-hand sides per pass.  Workgroup = one stored block.
-// The block is read in strips of SW = CG CPL columns (one 128-byte piece of a row
-// per plane); in a strip, lane (rg, cg) holds the CPL columns i = CPL cg + e of rows
-// rg R + r of every chunk of CH = RG R rows, straight from HBM into registers (the
-// next chunk in flight while one is used).  Forward: each lane sums its columns over
-// its rows in registers; at the strip end the row groups of a wave are combined by a
-// butterfly and the four waves in LDS, in a fixed order.  Backward: each row's
-// partial over the lane's columns is combined over the CG lanes of the row by a
-// butterfly (IEEE addition commutes, so every lane holds the same bits) and added by
-// the row's owner lane (cg = 0, the same lane in every strip) to its LDS
-// accumulator, strips in order.  R <= RMAX rows per lane.
-template <typename T, typename TS, int RB, int VEC>
-__global__ __launch_bounds__(256) void k_pair_sym(PairStream g, int b0, int R)
+// Lane permutations of the DPP butterflies (within rows of 16 lanes).
+constexpr int kDppXor1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
 {
-    constexpr int CPL = std::is_same<TS, float>::value ? 4 : 8;   // columns per lane: 16 bytes per plane
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 8 lanes 8k..8k+7: quad partners, then the other quad of the
+// 8-lane group (its mirror image).  IEEE addition commutes, so all 8 lanes end
+// with the same bits.
+template <typename T>
+__device__ __forceinline__ T sum8_lanes(T v)
+{
+    v += dpp_move<kDppXor1>(v);
+    v += dpp_move<kDppXor2>(v);
+    v += dpp_move<kDppHalfMirror>(v);
+    return v;
+}
+
+// Sum over the lanes of a wave that agree in lane % 8 (the 8 row groups of a
+// column group): the other half of the 16-lane row, then lanes 16 and 32 away.
+template <typename T>
+__device__ __forceinline__ T sum_rowgroups(T v)
+{
+    v += dpp_move<kDppRor8>(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+constexpr unsigned kBufOob = 0x80000000u;   // buffer offset past every block: the load returns 0
+constexpr int kBufFlags = 0x00020000;       // raw buffer, 32-bit data format
+
+// Streaming form, RB right-hand sides per pass.  Workgroup = one stored block.
+// The block is read in strips of SW = CG CPL columns (16 bytes of a row per plane
+// and lane); in a strip, lane (rg, cg) holds the CPL columns i = CPL cg + e of rows
+// rg R + r of every chunk of CH = RG R rows.  The loads go through a buffer
+// resource spanning the block, unconditionally: rows and columns outside the block
+// (and steps past the last) take an offset beyond it and read as zero.  Two
+// register buffers alternate, so the next chunk is in flight while one is used and
+// the wait before each use leaves the newer loads outstanding.  Forward: each lane
+// sums its columns over its rows in registers; at the strip end the row groups of
+// a wave are combined by a butterfly and the four waves in LDS, in a fixed order,
+// into the LDS row of forward sums.  Backward: each row's partial over the lane's
+// columns is combined over the CG lanes of the row by a butterfly and added by the
+// row's owner lane (cg = 0) to its LDS accumulator, strips in order; with one
+// chunk and one right-hand side (NC1) a lane meets the same rows in every strip, so
+// their partials stay in registers and the butterfly runs once per row at the end.
+// Both LDS rows go to the staging rows once the block is done.  The LDS rows are MP
+// long (MP >= rows and columns the chunks and strips cover), zero past M.
+template <typename T, typename TS, int RB, int VEC, bool NC1>
+__global__ __launch_bounds__(256) void k_pair_sym(PairStream g, int b0, int R, int MP)
+{
+    static_assert(!NC1 || RB == 1, "register backward partials hold one right-hand side");
+    constexpr bool F32 = std::is_same<TS, float>::value;
+    constexpr bool SPLIT = std::is_same<TS, OpsSplit>::value;
+    constexpr int CPL = F32 ? 4 : 8;                    // columns per lane: 16 bytes per plane
     constexpr int CG = 8;                               // lanes per row
     constexpr int RG = 256 / CG;                        // row groups (8 per wave)
     constexpr int SW = CPL * CG;                        // strip width (columns)
     constexpr int RMAX = CPL == 4 ? 8 : 4;
+    // registers per row and lane: VEC 4, the raw 16-byte pieces (4 words per plane);
+    // VEC 1, one FP32 value per column
+    constexpr int NWD = VEC == 4 ? (SPLIT ? 8 : 4) : CPL;
+    constexpr int ESZ = F32 ? 4 : 2;                    // bytes per stored value and plane
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = g.M;
-    T* wb = (T*)smem;                                   // [RB][M] forward sources (box b)
-    T* wa = wb + RB * M;                                // [RB][M] backward sources (box a)
-    T* bacc = wa + RB * M;                              // [RB][M] backward sums
-    T* red = bacc + RB * M;                             // [2][4 waves][RB][SW] forward partials of a strip
+    T* wb = (T*)smem;                                   // [RB][MP] forward sources (box b)
+    T* wa = wb + RB * MP;                               // [RB][MP] backward sources (box a)
+    T* bacc = wa + RB * MP;                             // [RB][MP] backward sums
+    T* facc = bacc + RB * MP;                           // [RB][MP] forward sums
+    T* red = facc + RB * MP;                            // [2][4 waves][RB][SW] forward partials of a strip
     const long u = blockIdx.x;
     const int a = g.ua[u], bs = g.ub[u];
     const long frow = g.fwd_row[u], brow = g.bwd_row[u];
     const bool back = brow >= 0;                        // uniform over the workgroup
     const int nb = (g.B - b0) < RB ? (g.B - b0) : RB;
     const int tid = threadIdx.x, cg = tid % CG, rg = tid / CG, wave = tid >> 6;
-    const T* W = (const T*)g.W;
-    for (int i = tid; i < RB * M; i += 256) {
-        const int b = i / M, k = i - b * M;
-        wb[i] = b < nb ? W[((long)(b0 + b) * g.nsrc + bs) * M + k] : T(0);
-        wa[i] = (back && b < nb) ? W[((long)(b0 + b) * g.nsrc + a) * M + k] : T(0);
-        bacc[i] = T(0);
-    }
     const int CH = RG * R;                              // rows per chunk
     const int nchunk = (M + CH - 1) / CH;
     const int nstrip = (M + SW - 1) / SW;
+    const int nstep = nchunk * nstrip;
     const size_t base = (size_t)u * M * M;
-    // one chunk of the lane: rows c CH + rg R + r, columns s SW + CPL cg + e
-    auto load_chunk = [&](int s, int c, float (&v)[RMAX][CPL]) {
+    const unsigned nbytes = (unsigned)((size_t)M * M * ESZ);
+    const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const unsigned char*)g.opsT + base * ESZ), 0, (int)nbytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const unsigned char*)(SPLIT ? g.opsT_lo : g.opsT) + base * ESZ), 0, (int)nbytes, kBufFlags);
+
+    // step t = (strip t / nchunk, chunk t % nchunk) of the lane: rows c CH + rg R + r,
+    // columns s SW + CPL cg + e
+    auto load_step = [&](int t, unsigned (&v)[RMAX][NWD]) {
+        const int s = t / nchunk, c = t - s * nchunk;
         const int i0 = s * SW + CPL * cg;
         const int j0 = c * CH + rg * R;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             const int j = j0 + r;
-            if (r < R && j < M && i0 < M) {
-                if constexpr (VEC == 4) {
-#pragma unroll
-                    for (int h = 0; h < CPL / 4; ++h) {
-                        float o[4];
-                        load_vals<TS, 4>(g, base + (size_t)j * M + i0 + 4 * h, o);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) v[r][4 * h + e] = o[e];
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < CPL; ++e) {
-                        float o[1] = {0.f};
-                        if (i0 + e < M) load_vals<TS, 1>(g, base + (size_t)j * M + i0 + e, o);
-                        v[r][e] = o[0];
-                    }
+            const bool ok = t < nstep && r < R && j < M;
+            if constexpr (VEC == 4) {
+                const unsigned off = ok && i0 < M ? (unsigned)(((size_t)j * M + i0) * ESZ) : kBufOob;
+                typedef unsigned v4u __attribute__((ext_vector_type(4)));
+                const v4u h = __builtin_amdgcn_raw_buffer_load_b128(rs0, off, 0, 0);
+                v[r][0] = h[0]; v[r][1] = h[1]; v[r][2] = h[2]; v[r][3] = h[3];
+                if constexpr (SPLIT) {
+                    const v4u l = __builtin_amdgcn_raw_buffer_load_b128(rs1, off, 0, 0);
+                    v[r][4] = l[0]; v[r][5] = l[1]; v[r][6] = l[2]; v[r][7] = l[3];
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < CPL; ++e) v[r][e] = 0.f;
+                for (int e = 0; e < CPL; ++e) {
+                    const unsigned off = ok && i0 + e < M ? (unsigned)(((size_t)j * M + i0 + e) * ESZ) : kBufOob;
+                    if constexpr (F32) {
+                        v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(rs0, off, 0, 0);
+                    } else {
+                        const unsigned hi = __builtin_amdgcn_raw_buffer_load_b16(rs0, off, 0, 0);
+                        const int lo = SPLIT ? (int)(short)__builtin_amdgcn_raw_buffer_load_b16(rs1, off, 0, 0) : 0;
+                        v[r][e] = (hi << 16) + (unsigned)lo;
+                    }
+                }
             }
         }
     };
-    float cur[RMAX][CPL], nxt[RMAX][CPL];
-    T accf[RB][CPL], war[RB][CPL];
-    T* stage = (T*)g.stage;
-    load_chunk(0, 0, cur);
-    __syncthreads();                                    // wb and bacc staged
-    for (int s = 0; s < nstrip; ++s) {
-        const int i0 = s * SW + CPL * cg;
+    // row r of a register buffer as FP32 values (planes: (hi << 16) + lo, lo signed)
+    auto row_vals = [&](const unsigned (&v)[RMAX][NWD], int r, T (&x)[CPL]) {
+        if constexpr (VEC == 4 && !F32) {
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) {
-                accf[b][e] = T(0);
-                war[b][e] = i0 + e < M ? wa[b * M + i0 + e] : T(0);
-            }
-        for (int c = 0; c < nchunk; ++c) {
-            // the next chunk (of this strip, or the first of the next) in flight
-            const int cn = c + 1 < nchunk ? c + 1 : 0;
-            const int sn = c + 1 < nchunk ? s : s + 1;
-            if (sn < nstrip) load_chunk(sn, cn, nxt);
-            const int j0 = c * CH + rg * R;
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r >= R) break;                      // uniform
-                const int j = j0 + r;
-                T x[CPL];
-#pragma unroll
-                for (int e = 0; e < CPL; ++e) x[e] = (T)cur[r][e];
-                // forward: the lane's columns
-#pragma unroll
-                for (int b = 0; b < RB; ++b) {
-                    const T w = j < M ? wb[b * M + j] : T(0);
-#pragma unroll
-                    for (int e = 0; e < CPL; ++e) accf[b][e] += x[e] * w;
+            for (int k = 0; k < 4; ++k) {
+                const unsigned h = v[r][k];
+                unsigned e0 = h << 16, e1 = h & 0xffff0000u;
+                if constexpr (SPLIT) {
+                    const int l = (int)v[r][4 + k];
+                    e0 += (unsigned)((l << 16) >> 16);
+                    e1 += (unsigned)(l >> 16);
                 }
-                // backward: row j over the strip's columns
-                if (back) {
-                    T pb[RB];
+                x[2 * k] = (T)__uint_as_float(e0);
+                x[2 * k + 1] = (T)__uint_as_float(e1);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) x[e] = (T)__uint_as_float(v[r][e]);
+        }
+    };
+
+    unsigned bufA[RMAX][NWD], bufB[RMAX][NWD];
+    load_step(0, bufA);
+    const T* W = (const T*)g.W;
+    for (int i = tid; i < RB * MP; i += 256) {
+        const int b = i / MP, k = i - b * MP;
+        const bool in = b < nb && k < M;
+        wb[i] = in ? W[((long)(b0 + b) * g.nsrc + bs) * M + k] : T(0);
+        wa[i] = (back && in) ? W[((long)(b0 + b) * g.nsrc + a) * M + k] : T(0);
+        bacc[i] = T(0);
+        facc[i] = T(0);
+    }
+    T accf[RB][CPL], war[RB][CPL];
+    T bpart[NC1 ? RMAX : 1];                            // NC1: backward partials of the lane's rows
+#pragma unroll
+    for (int r = 0; r < (NC1 ? RMAX : 1); ++r) bpart[r] = T(0);
+    __syncthreads();                                    // sources and sums staged
+
+    // step t: strip t / nchunk, chunk t % nchunk
+    auto use_step = [&](int t, const unsigned (&v)[RMAX][NWD]) {
+        const int s = t / nchunk, c = t - s * nchunk;
+        if (c == 0) {
+            const int i0 = s * SW + CPL * cg;
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) {
+                    accf[b][e] = T(0);
+                    war[b][e] = wa[b * MP + i0 + e];
+                }
+        }
+        const int j0 = c * CH + rg * R;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r >= R) break;                          // uniform
+            const int j = j0 + r;
+            T x[CPL];
+            row_vals(v, r, x);
+            // forward: the lane's columns
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                const T w = wb[b * MP + j];
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) accf[b][e] += x[e] * w;
+            }
+            // backward: row j over the lane's columns of the strip
+            if (back) {
+                if constexpr (NC1) {
+                    T t = bpart[r];
+#pragma unroll
+                    for (int e = 0; e < CPL; ++e) t += x[e] * war[0][e];
+                    bpart[r] = t;
+                } else {
 #pragma unroll
                     for (int b = 0; b < RB; ++b) {
                         T t = T(0);
 #pragma unroll
                         for (int e = 0; e < CPL; ++e) t += x[e] * war[b][e];
-                        pb[b] = t;
-                    }
-#pragma unroll
-                    for (int off = CG / 2; off >= 1; off >>= 1)
-#pragma unroll
-                        for (int b = 0; b < RB; ++b) pb[b] += __shfl_xor(pb[b], off, CG);
-                    if (cg == 0 && j < M) {
-#pragma unroll
-                        for (int b = 0; b < RB; ++b) bacc[b * M + j] += pb[b];
+                        t = sum8_lanes(t);
+                        if (cg == 0) bacc[b * MP + j] += t;
                     }
                 }
             }
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r)
-#pragma unroll
-                for (int e = 0; e < CPL; ++e) cur[r][e] = nxt[r][e];
         }
-        // forward sums of the strip: the 8 row groups of a wave by a butterfly over
-        // the lanes of one column group, then the four waves in order (two LDS buffers
-        // by strip parity, so one barrier per strip separates writes from reads)
-#pragma unroll
-        for (int b = 0; b < RB; ++b)
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) {
-                T v = accf[b][e];
-#pragma unroll
-                for (int off = 32; off >= CG; off >>= 1) v += __shfl_xor(v, off, 64);
-                accf[b][e] = v;
-            }
-        T* rs = red + (size_t)(s & 1) * 4 * RB * SW;
-        if ((tid & 63) < CG) {
+        if (c == nchunk - 1) {
+            // forward sums of the strip: the 8 row groups of a wave, then the four
+            // waves in order (two LDS buffers by strip parity: one barrier per strip)
+            T* rs = red + (size_t)(s & 1) * 4 * RB * SW;
 #pragma unroll
             for (int b = 0; b < RB; ++b)
 #pragma unroll
-                for (int e = 0; e < CPL; ++e) rs[(wave * RB + b) * SW + CPL * cg + e] = accf[b][e];
+                for (int e = 0; e < CPL; ++e) {
+                    const T v8 = sum_rowgroups(accf[b][e]);
+                    if ((tid & 63) < CG) rs[(wave * RB + b) * SW + CPL * cg + e] = v8;
+                }
+            __syncthreads();
+            for (int idx = tid; idx < RB * SW; idx += 256) {
+                const int b = idx / SW, col = idx - b * SW;
+                facc[b * MP + s * SW + col] = ((rs[(0 * RB + b) * SW + col] + rs[(1 * RB + b) * SW + col]) +
+                                               rs[(2 * RB + b) * SW + col]) + rs[(3 * RB + b) * SW + col];
+            }
         }
-        __syncthreads();
-        for (int idx = tid; idx < RB * SW; idx += 256) {
-            const int b = idx / SW, col = idx - b * SW, i = s * SW + col;
-            const T sum = ((rs[(0 * RB + b) * SW + col] + rs[(1 * RB + b) * SW + col]) + rs[(2 * RB + b) * SW + col]) +
-                          rs[(3 * RB + b) * SW + col];
-            if (b < nb && i < M) stage[((long)b * g.nrows + frow) * M + i] = sum;
+    };
+    for (int t = 0; t < nstep; t += 2) {
+        load_step(t + 1, bufB);
+        use_step(t, bufA);
+        if (t + 1 >= nstep) break;                      // uniform
+        load_step(t + 2, bufA);
+        use_step(t + 1, bufB);
+    }
+    if constexpr (NC1) {
+        // each row's partials over the CG lanes of its row group (one chunk: row rg R + r)
+        if (back) {
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r >= R) break;                      // uniform
+                const T v = sum8_lanes(bpart[r]);
+                if (cg == 0) bacc[rg * R + r] = v;
+            }
         }
     }
-    if (back) {
-        __syncthreads();                                // every row's owner lane is done
-        for (int idx = tid; idx < RB * M; idx += 256) {
-            const int b = idx / M, j = idx - b * M;
-            if (b < nb) stage[((long)b * g.nrows + brow) * M + j] = bacc[idx];
+    __syncthreads();                                    // every forward and backward sum is in LDS
+    T* stage = (T*)g.stage;
+    for (int idx = tid; idx < RB * M; idx += 256) {
+        const int b = idx / M, j = idx - b * M;
+        if (b < nb) {
+            stage[((long)b * g.nrows + frow) * M + j] = facc[b * MP + j];
+            if (back) stage[((long)b * g.nrows + brow) * M + j] = bacc[b * MP + j];
         }
     }
 }
@@ -555,20 +655,23 @@ ert_status launch_reduce(hipStream_t s, const PairStream& g, int b0, int nb)
     return ERT_OK;
 }
 
-// LDS of the streaming form: forward and backward sources, backward sums, two strips
-// of the four waves' forward partials (strip width 64 columns at most).
-size_t sym_lds(int M, int rb, size_t tsize)
+// LDS of the streaming form: forward and backward sources, backward and forward
+// sums (MP each), two strips of the four waves' forward partials (strip width 64
+// columns at most).
+size_t sym_lds(int MP, int rb, size_t tsize)
 {
-    return tsize * (3 * (size_t)rb * M + 2 * 4 * (size_t)rb * 64);
+    return tsize * (4 * (size_t)rb * MP + 2 * 4 * (size_t)rb * 64);
 }
 
+// One right-hand side in one chunk keeps the backward partials in registers.
 template <typename T, typename TS, int VEC>
-void launch_sym(hipStream_t s, const PairStream& g, int b0, int rb, int R, size_t sh)
+void launch_sym(hipStream_t s, const PairStream& g, int b0, int rb, int R, int nchunk, int MP, size_t sh)
 {
     const dim3 grid((unsigned)g.npairs);
-    if (rb == 4) hipLaunchKernelGGL((k_pair_sym<T, TS, 4, VEC>), grid, dim3(256), sh, s, g, b0, R);
-    else if (rb == 2) hipLaunchKernelGGL((k_pair_sym<T, TS, 2, VEC>), grid, dim3(256), sh, s, g, b0, R);
-    else hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC>), grid, dim3(256), sh, s, g, b0, R);
+    if (rb == 4) hipLaunchKernelGGL((k_pair_sym<T, TS, 4, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
+    else if (rb == 2) hipLaunchKernelGGL((k_pair_sym<T, TS, 2, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
+    else if (nchunk == 1) hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC, true>), grid, dim3(256), sh, s, g, b0, R, MP);
+    else hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
 }
 
 constexpr size_t kSymLdsMax = 64 * 1024;
@@ -577,25 +680,29 @@ constexpr size_t kSymLdsMax = 64 * 1024;
 template <typename T, typename TS>
 ert_status pair_sym_t(hipStream_t s, const PairStream& g)
 {
+    constexpr bool F32 = std::is_same<TS, float>::value;
     const int M = g.M;
-    if (M < 1 || M > 4096 || sym_lds(M, 1, sizeof(T)) > kSymLdsMax) {
+    // rows per lane: the fewest chunks of 32 R rows (R <= 8 for FP32 storage, 4 for
+    // planes) that cover M, then the smallest R; LDS rows cover the chunks and strips
+    const int rmax = F32 ? 8 : 4;
+    const int cpl = F32 ? 4 : 8, sw = 8 * cpl;
+    const int nchunk = M >= 1 ? (M + 32 * rmax - 1) / (32 * rmax) : 1;
+    const int R = std::max(1, std::min(rmax, (M + 32 * nchunk - 1) / (32 * nchunk)));
+    const int MP = std::max(nchunk * 32 * R, (M + sw - 1) / sw * sw);
+    if (M < 1 || M > 4096 || sym_lds(MP, 1, sizeof(T)) > kSymLdsMax) {
         record_error("pair_stream: unsupported block size");
         return ERT_EINVAL;
     }
-    // rows per lane: the fewest chunks of 32 R rows (R <= 8 for FP32 storage, 4 for
-    // planes) that cover M, then the smallest R
-    const int rmax = std::is_same<TS, float>::value ? 8 : 4;
-    const int nchunk = (M + 32 * rmax - 1) / (32 * rmax);
-    const int R = std::max(1, std::min(rmax, (M + 32 * nchunk - 1) / (32 * nchunk)));
     for (int b0 = 0; b0 < g.B;) {
         const int left = g.B - b0;
         int rb = left >= 4 ? 4 : (left >= 2 ? 2 : 1);
-        while (rb > 1 && sym_lds(M, rb, sizeof(T)) > kSymLdsMax) rb /= 2;
-        const size_t sh = sym_lds(M, rb, sizeof(T));
+        while (rb > 1 && sym_lds(MP, rb, sizeof(T)) > kSymLdsMax) rb /= 2;
+        const size_t sh = sym_lds(MP, rb, sizeof(T));
         {
             StageTimer t_(g.prof, s, g.prof_stage);
-            if (M % 4 == 0) launch_sym<T, TS, 4>(s, g, b0, rb, R, sh);
-            else launch_sym<T, TS, 1>(s, g, b0, rb, R, sh);
+            // whole 16-byte pieces (CPL values per plane) when rows hold a multiple of CPL
+            if (M % cpl == 0) launch_sym<T, TS, 4>(s, g, b0, rb, R, nchunk, MP, sh);
+            else launch_sym<T, TS, 1>(s, g, b0, rb, R, nchunk, MP, sh);
             ERT_HIP(hipGetLastError());
         }
         ERT_TRY(launch_reduce<T>(s, g, b0, rb));
