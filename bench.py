@@ -349,6 +349,32 @@ C5_CHEB, C5_INNER_CHEB = 6, 4
 # (workload, precision, stage of the kernel, execution forms); a combination without counters,
 # or a kernel changed since they were taken, reports null.
 MEASURED_TRAFFIC = dict(MEASURED_TRAFFIC)
+# 128^3 FP64 operator (k_pair_sym over the symmetric caches): far field 66.13 GB per apply in
+# 3 launches, near field 53.95 GB in one (profiles/pair_sym_c5_128cubed_hbm_traffic.md)
+MEASURED_TRAFFIC[("c5_128", "fp64", "m2l")] = 22.044e9
+MEASURED_TRAFFIC[("c5_128", "fp64", "near")] = 53.948e9
+
+
+def hbm_read_reference(torch, dev, gib=16, reps=5):
+    """What a library reduction over a large buffer reads per second on this GPU (torch's sum
+    of a 16 GiB FP32 tensor, fastest of 5): the attainable streaming rate next to which the
+    HBM-bound products are judged, besides the 8 TB/s peak."""
+    a = torch.zeros(gib * (1 << 28), dtype=torch.float32, device=dev)
+    a.sum()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        a.sum()
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    nbytes = a.numel() * 4
+    del a
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "ms": best, "gb_per_s": nbytes / (best * 1e-3) / 1e9}
 
 
 def het_roofline(info, stage_ms, launches, n, near_plane_bytes=4, workload=None):
@@ -665,10 +691,13 @@ def main():
         print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
         return
 
+    read_ref = hbm_read_reference(torch, dev)
+    log("HBM read reference (torch sum over 16 GiB):", json.dumps(read_ref))
     N = C5_N ** 3
     ms, roofline, c5, cpu = c5_headline(torch, ertvie, inputs, O, stream, args)
+    roofline["attainable_read_gb_per_s"] = read_ref["gb_per_s"]
     value = N / (ms * 1e-3) / 1e6
-    extra = {"many_scattering_128cubed": c5}
+    extra = {"many_scattering_128cubed": c5, "hbm_read_reference": read_ref}
     if not args.headline_only:
         extra["c2_32cubed_homogeneous"], _, _ = c2_32(torch, ertvie, inputs, O, stream, args)
         extra["c2_recipe_64cubed_homogeneous"] = homogeneous_64(torch, ertvie, inputs, O, stream)

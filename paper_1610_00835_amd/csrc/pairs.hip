@@ -663,15 +663,24 @@ size_t sym_lds(int MP, int rb, size_t tsize)
     return tsize * (4 * (size_t)rb * MP + 2 * 4 * (size_t)rb * 64);
 }
 
-// One right-hand side in one chunk keeps the backward partials in registers.
+// One right-hand side in one chunk keeps the backward partials in registers when
+// they fit without costing occupancy (FP32 sums; the FP64 ones would drop the
+// kernel from 4 to 3 waves per SIMD, slower than the per-row LDS sums).
 template <typename T, typename TS, int VEC>
 void launch_sym(hipStream_t s, const PairStream& g, int b0, int rb, int R, int nchunk, int MP, size_t sh)
 {
     const dim3 grid((unsigned)g.npairs);
     if (rb == 4) hipLaunchKernelGGL((k_pair_sym<T, TS, 4, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
     else if (rb == 2) hipLaunchKernelGGL((k_pair_sym<T, TS, 2, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
-    else if (nchunk == 1) hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC, true>), grid, dim3(256), sh, s, g, b0, R, MP);
-    else hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
+    else {
+        if constexpr (sizeof(T) == 4) {
+            if (nchunk == 1) {
+                hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC, true>), grid, dim3(256), sh, s, g, b0, R, MP);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_pair_sym<T, TS, 1, VEC, false>), grid, dim3(256), sh, s, g, b0, R, MP);
+    }
 }
 
 constexpr size_t kSymLdsMax = 64 * 1024;

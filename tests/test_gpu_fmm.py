@@ -278,14 +278,15 @@ def test_fmm_heterogeneous_2d(ev, oracle_mod):
         assert err <= 1e-5
 
 
-def test_fmm_heterogeneous_many_rhs(ev, oracle_mod):
-    """11 right-hand sides (rhs blocks of 8, 2 and 1 in the streaming products): every column
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fmm_heterogeneous_many_rhs(ev, oracle_mod, prec):
+    """11 right-hand sides (passes of 4, 4, 2 and 1 in the streaming products): every column
     equals its single-column apply, and the batch equals the oracle (bar 2e-5 as for the other
     small heterogeneous grids; 1.01e-5 measured)."""
     case = inputs.make_case("c3", n=(16, 16, 16), seed=6)
     P = oracle_problem(oracle_mod, case)
     X = inputs.random_vector(P.N, 14, nrhs=11)
-    with ev.plan_from_case(case, method="fmm", prec="fp32", leaf=4, nrhs_max=11) as plan:
+    with ev.plan_from_case(case, method="fmm", prec=prec, leaf=4, nrhs_max=11) as plan:
         Y = gpu_apply(plan, X, ev.OP_A)
         for b in (0, 7, 8, 10):
             yb = gpu_apply(plan, X[:, b], ev.OP_A)
@@ -311,3 +312,42 @@ def test_fmm_heterogeneous_many_rhs_matrix_cores(ev, oracle_mod, prec, nrhs):
             log("many rhs", prec, nrhs, "column", b, "max rel diff vs single column", d)
             assert d <= tol
     assert rel_l2(Y[:, 3], P.apply(X[:, 3], op=2)) <= 2e-5
+
+
+@pytest.mark.parametrize("n,leaf", [((6, 6, 6), 3), ((10, 9, 7), 5)])
+def test_fmm_heterogeneous_odd_leaves_near_only(ev, oracle_mod, n, leaf):
+    """Two leaves per axis, so every pair of leaves is a near pair and the FMM is the
+    dense sum over FP32-stored kernel values: blocks of 27 and 125 points (element-wise
+    loads in the streaming products), FP64 and FP32 applies of 3 right-hand sides against
+    the oracle within the FP32 rounding of the stored values (bar 1e-6)."""
+    case = inputs.make_case("c3", n=n, seed=8)
+    P = oracle_problem(oracle_mod, case)
+    X = inputs.random_vector(P.N, 18, nrhs=3)
+    for prec in ("fp64", "fp32"):
+        with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf, nrhs_max=3) as plan:
+            Y = gpu_apply(plan, X, ev.OP_A)
+        err = max(rel_l2(Y[:, b], P.apply(X[:, b], op=2)) for b in range(3))
+        log("odd leaves, near field only", n, leaf, prec, "rel L2", err)
+        assert err <= 1e-6
+
+
+@pytest.mark.parametrize("n,leaf", [((12, 12, 12), 3), ((20, 20, 20), 5), ((24, 24, 24), 6)])
+def test_fmm_heterogeneous_odd_leaves(ev, oracle_mod, n, leaf):
+    """Leaves of 3^3, 5^3 and 6^3 cells with a far field: the streaming products (3
+    right-hand sides; element-wise loads for 27 and 125 points) equal the matrix-core
+    products of the same plan (16 right-hand sides) to accumulation order, and the oracle
+    to the FMM error of these small boxes (bar 5e-5; 2.6e-5 measured at 12^3 with 3^3
+    leaves, where the far pairs take as few as 12 ray steps)."""
+    case = inputs.make_case("c3", n=n, seed=8)
+    P = oracle_problem(oracle_mod, case)
+    X = inputs.random_vector(P.N, 18, nrhs=3)
+    X16 = np.asfortranarray(np.tile(X, (1, 6))[:, :16])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+        with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf, nrhs_max=16) as plan:
+            Y = gpu_apply(plan, X, ev.OP_A)
+            Y16 = gpu_apply(plan, X16, ev.OP_A)
+        d = max(np.max(np.abs(Y16[:, b] - Y[:, b])) / np.max(np.abs(Y[:, b])) for b in range(3))
+        err = max(rel_l2(Y[:, b], P.apply(X[:, b], op=2)) for b in (0, 2))
+        log("odd leaves", n, leaf, prec, "streaming vs matrix cores", d, "rel L2 vs oracle", err)
+        assert d <= tol
+        assert err <= 5e-5
