@@ -37,6 +37,8 @@
 #ifndef ERTVIE_H
 #define ERTVIE_H
 
+#include <stddef.h>
+
 #if defined(__GNUC__) || defined(__clang__)
 #define ERT_API __attribute__((visibility("default")))
 #else
@@ -390,6 +392,19 @@ ERT_API const char* ert_vie_last_error(void);
 
 /* Static, human-readable text for a status code. */
 ERT_API const char* ert_vie_strerror(ert_status status);
+
+/* Diagnostic, for stating the attainable HBM read rate beside the published
+ * peak (the cached-pair products are HBM-bound): streams the first
+ * floor(bytes / piece) * piece bytes of the DEVICE buffer `buf` once per
+ * repetition, one workgroup of 256 lanes per contiguous `piece` (16-byte loads,
+ * eight in flight per lane: the access pattern of the cached-pair products),
+ * and writes the fastest of `reps` timed passes (after one untimed pass) in
+ * milliseconds to *ms_out (HOST).  buf: 16-byte aligned, owned by the caller,
+ * only read.  piece: a multiple of 16, at most bytes.  Runs on `hip_stream`
+ * (NULL: the null stream) and synchronises.  ERT_EINVAL for bad arguments,
+ * ERT_EDEVICE for a failed HIP call. */
+ERT_API ert_status ert_vie_read_rate(const void* buf, size_t bytes, size_t piece, int reps, void* hip_stream,
+                                     double* ms_out);
 
 
 /* ------------------------------------------------------------------------

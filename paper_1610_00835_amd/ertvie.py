@@ -114,6 +114,9 @@ def load():
     L.ert_vie_net_apply.argtypes = [_vp, _vp, _vp, _vp]
     L.ert_vie_restrict.restype = ctypes.c_int
     L.ert_vie_restrict.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int]
+    L.ert_vie_read_rate.restype = ctypes.c_int
+    L.ert_vie_read_rate.argtypes = [_vp, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, _vp,
+                                    ctypes.POINTER(ctypes.c_double)]
     L.ert_vie_transport_noalloc.restype = ctypes.c_int
     L.ert_vie_transport_noalloc.argtypes = [_vp, _vp, _vp, _dp, ctypes.c_int, _vp]
     L.ert_vie_diff_precond.restype = ctypes.c_int
@@ -140,6 +143,17 @@ def load():
 
 def strerror(status):
     return load().ert_vie_strerror(int(status)).decode()
+
+
+def read_rate(buf, piece, reps=5, stream=None):
+    """Fastest streaming pass over the torch CUDA tensor `buf` in pieces of `piece` bytes per
+    workgroup (ert_vie_read_rate): returns (bytes read, milliseconds)."""
+    nbytes = buf.numel() * buf.element_size()
+    ms = ctypes.c_double(0.0)
+    st = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    _check(load().ert_vie_read_rate(ctypes.c_void_p(buf.data_ptr()), nbytes, int(piece), int(reps), st,
+                                    ctypes.byref(ms)), "ert_vie_read_rate")
+    return nbytes // int(piece) * int(piece), ms.value
 
 
 def _check(status, where):

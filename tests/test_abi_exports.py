@@ -45,6 +45,9 @@ def test_strerror_and_null_plan_without_gpu():
     assert L.ert_vie_restrict(None, 2, None, None, 1) == ertvie.EINVAL
     assert L.ert_vie_net_apply(None, None, None, None) == ertvie.EINVAL
     assert L.ert_vie_diff_precond(None, None, None, 1) == ertvie.EINVAL
+    ms = ctypes.c_double(0.0)
+    assert L.ert_vie_read_rate(None, 1 << 20, 4096, 3, None, ctypes.byref(ms)) == ertvie.EINVAL
+    assert L.ert_vie_read_rate(ctypes.c_void_p(4096), 1 << 20, 4008, 3, None, ctypes.byref(ms)) == ertvie.EINVAL
 
 
 def test_plan_rejects_bad_arguments_before_device_use():

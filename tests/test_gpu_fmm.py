@@ -351,3 +351,14 @@ def test_fmm_heterogeneous_odd_leaves(ev, oracle_mod, n, leaf):
         log("odd leaves", n, leaf, prec, "streaming vs matrix cores", d, "rel L2 vs oracle", err)
         assert d <= tol
         assert err <= 5e-5
+
+
+def test_read_rate_diagnostic(ev):
+    """ert_vie_read_rate streams a buffer (whole pieces only) and reports a positive time;
+    the rate it implies stays below the 8 TB/s peak."""
+    import torch
+    a = torch.zeros(1 << 26, dtype=torch.float32, device="cuda")   # 256 MiB
+    nbytes, ms = ev.read_rate(a, 224 * 224 * 4, reps=3)
+    assert nbytes == (a.numel() * 4) // (224 * 224 * 4) * (224 * 224 * 4)
+    assert ms > 0 and nbytes / (ms * 1e-3) < 8.0e12
+    log("read rate, 256 MiB in 200704-byte pieces:", nbytes / (ms * 1e-3) / 1e9, "GB/s")
