@@ -138,7 +138,9 @@ typedef struct {
                          0 -> timed on first use per right-hand-side count (the fastest of
                          the forms that apply is kept); f + 1 -> always form f:
                          0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64,
-                         3 16x64, 4 (FP32) 64x16 tiles with the source columns staged in LDS
+                         3 16x64, 4 (FP32) 64x16 tiles with the source columns staged in LDS,
+                         5 (FP32, reduction length <= 252) 64-column tiles over all rows with
+                         the source columns staged in LDS
                          (a form that does not apply to a product leaves it to the timing).
                          Fixed forms make runs reproducible bit for bit across plans */
 } ert_vie_opts;
@@ -357,7 +359,8 @@ typedef struct {
     int form_near;        /* execution form of the homogeneous near-field product for one
                              right-hand side: -1 not tuned yet / not a box-offset product,
                              0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64, 3 16x64,
-                             4 (FP32) 64x16 tiles with the source columns staged in LDS */
+                             4 (FP32) 64x16 tiles with the source columns staged in LDS,
+                             5 (FP32) 64-column tiles over all rows, source columns in LDS */
     int form_far[16];     /* per level: the same for the far-field translations */
     long near_table;      /* homogeneous media, leaf a power of two >= 4: the offset-stationary
                              near-field products read one table of (4 leaf - 1)^dim values over

@@ -1197,7 +1197,7 @@ struct FmmImpl : FmmData {
 
     ert_status run_site(ert_plan_impl* p, hipStream_t s, GemmSite& site, int gprec, const BoxGemm& g, int nrhs,
                         StageTimer* outer, T* stg);
-    // offset-stationary description of a box-offset product in the form `form` (1..3)
+    // offset-stationary description of a box-offset product in the form `form` (1..5)
     OffsetGemm offset_of(const GemmSite& gs, const BoxGemm& b, T* stg, int form) const
     {
         OffsetGemm o;
@@ -1213,7 +1213,7 @@ struct FmmImpl : FmmData {
         o.accumulate = b.accumulate;
         o.tn = (form == 2 || form == 3) ? 4 : 1;
         o.tm = form == 3 ? 1 : 2;
-        o.lds = form == 4 ? 1 : 0;
+        o.lds = form == 4 ? 1 : form == 5 ? 2 : 0;
         o.pl = gs.pl;
         if (&gs == &near_site && neartab && b.ops == nearops) {
             o.atab = neartab;
@@ -1863,14 +1863,18 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         gt.accumulate = 0;
         OffsetGemm ot[kForms];
         for (int f = 1; f < kForms; ++f) ot[f] = offset_of(gs, gt, stg, f);
-        // form 4 (LDS-staged source columns) where it applies
-        const int nforms = offset_lds_ok(gprec, ot[4]) ? kForms : kForms - 1;
+        // forms 4 and 5 (LDS-staged source columns) where they apply
+        bool ok[kForms];
+        for (int f = 0; f < kForms; ++f) ok[f] = f < 4;
+        ok[4] = offset_lds_ok(gprec, ot[4]);
+        ok[5] = offset_lds64_ok(gprec, ot[5]);
         hipEvent_t e[3];
         for (auto& ev : e) ERT_HIP(hipEventCreate(&ev));
-        float ms[kForms] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float ms[kForms] = {};
         ert_status st = ERT_OK;
         auto run = [&](int form) { return form == 0 ? box_gemm(s, gprec, gt) : offset_gemm(s, gprec, ot[form]); };
-        for (int form = 0; form < nforms && st == ERT_OK; ++form) {
+        for (int form = 0; form < kForms && st == ERT_OK; ++form) {
+            if (!ok[form]) continue;
             st = run(form);   // warm-up
             if (st != ERT_OK) break;
             (void)hipEventRecord(e[0], s);
@@ -1882,7 +1886,8 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         for (auto& ev : e) (void)hipEventDestroy(ev);
         ERT_TRY(st);
         int best = 0;
-        for (int form = 0; form < nforms; ++form) {
+        for (int form = 0; form < kForms; ++form) {
+            if (!ok[form]) continue;
             gs.tuned_ms[bucket][form] = ms[form] / 3;
             if (ms[form] < ms[best]) best = form;
         }
@@ -1891,7 +1896,7 @@ ert_status FmmImpl<T>::run_site(ert_plan_impl* p, hipStream_t s, GemmSite& gs, i
         if (best == 1 && ms[2] <= 1.05f * ms[1]) best = 2;
         // a form fixed by the plan's options (near field / far field), where it applies
         const int fixed = p->o.form[&gs == &near_site ? 0 : 1] - 1;
-        if (fixed >= 0 && fixed < nforms) best = fixed;
+        if (fixed >= 0 && fixed < kForms && ok[fixed]) best = fixed;
         gs.choice[bucket] = best;
     }
     if (gs.choice[bucket] == 0) return box_gemm(s, gprec, g);

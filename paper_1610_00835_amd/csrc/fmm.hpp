@@ -113,7 +113,9 @@ struct OffsetGemm {
     int tn;                   // column blocks of 16 per workgroup: 1 or 4
     int tm;                   // row blocks of 16 per wave: 2 or 1 (with tn = 4)
     int lds = 0;              // 1 (FP32, tn = 1): the tile's source columns staged in LDS, each
-                              // wave 16 rows over the whole reduction, 64 rows per workgroup
+                              // wave 16 rows over the whole reduction, 64 rows per workgroup;
+                              // 2 (FP32): 64-column tiles staged in LDS, each wave every fourth
+                              // block of 16 rows, all rows per workgroup
     PairTiles pl;
     // operator from a table over cell offsets instead of ops (the near field of a
     // homogeneous medium; FP32/FP64, leaf a power of two >= 4): four copies of the
@@ -125,10 +127,12 @@ struct OffsetGemm {
 
 ert_status offset_gemm(hipStream_t s, int prec, const OffsetGemm& g);           // products + reduction
 ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g);  // staged products only
-bool offset_lds_ok(int prec, const OffsetGemm& g);   // execution form 4 applies to this product
+bool offset_lds_ok(int prec, const OffsetGemm& g);     // execution form 4 applies to this product
+bool offset_lds64_ok(int prec, const OffsetGemm& g);   // execution form 5 applies to this product
 // execution forms: 0 target-tile GEMM, 1 offset-stationary 32x16 tiles, 2 32x64, 3 16x64,
-// 4 16-column tiles with the source columns in LDS (FP32)
-constexpr int kForms = 5;
+// 4 16-column tiles with the source columns in LDS (FP32), 5 64-column tiles over all rows
+// with the source columns in LDS (FP32)
+constexpr int kForms = 6;
 ert_status offset_gemm_reduce(hipStream_t s, int prec, const OffsetGemm& g);    // per-target sums only
 // two independent products (each in its own form, with its own staging rows) in one launch
 // (two launches when only one of them is in form 4)

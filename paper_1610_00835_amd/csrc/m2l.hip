@@ -505,6 +505,132 @@ __global__ __launch_bounds__(256) void k_offset_lds2(OffsetGemm a, int rows_a, l
     }
 }
 
+// Execution form 5 (FP32).  Workgroup = one 64-column tile over all rows of the
+// product: the tile's 64 source columns are staged in LDS once (row stride Kd + 4
+// floats); wave w takes the 16-row blocks w, w + 4, ... and reduces each over the
+// whole reduction length against all 64 columns, so every operator fragment feeds
+// four MFMA column blocks (a quarter of the operator reads of form 4).  A wave holds
+// its block's operator rows in registers (Kd / 16 fragments per lane, read from
+// memory or from the offset table) and loads the next block's while it multiplies
+// this one; the loads are unconditional (a wave past its last block re-reads that
+// block's rows), so the wait before a block leaves the next block's loads in flight.
+constexpr int kLds64K = 15;   // fragments of 16 reduction indices per lane: Kd <= 240
+
+// KS = Kd / 16 reduction fragments per lane (a compile-time count: no branch around a load)
+template <bool TAB, int KS>
+__device__ __forceinline__ void lds64_tile(const OffsetGemm& g, long tile, float* sB)
+{
+    typedef v4f V;
+    const int grpi = g.pl.tile_group4[tile];
+    const long col0 = g.pl.tile_col04[tile];
+    const int p0 = g.pl.gstart[grpi], np = g.pl.gstart[grpi + 1] - p0;
+    if (col0 >= (long)np * g.B) return;                 // uniform over the block
+    const int op = g.pl.gop[grpi];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: a scalar loop
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
+    const int ld = g.Kd + 4, kq = g.Kd >> 2, MB = g.M >> 4;
+    int tbase = 0;
+    if constexpr (TAB) {
+        const int o0 = op % 3 - 1, o1 = (op / 3) % 3 - 1, o2 = g.dim == 3 ? op / 9 - 1 : 0;
+        const int c = 2 * g.leaf - 1;
+        tbase = (c + g.leaf * o0) + g.tw * (c + g.leaf * o1) + g.tw * g.tw * (g.dim == 3 ? c + g.leaf * o2 : 0);
+    }
+    // the operator fragments of row block rb (rows 16 rb + lane % 16, reduction indices
+    // 16 ks + 4 grp .. + 3)
+    auto load_a = [&](int rb, V (&a)[KS]) {
+        const int row = 16 * rb + (lane & 15);
+        if constexpr (TAB) {
+            const int tb = tbase - tab_lin(g, row);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int idx = tb + tab_lin(g, 16 * ks + 4 * grp);
+                const int r = idx & 3;
+                a[ks] = *(const V*)((const float*)g.atab + r * g.tlen + (idx - r));
+            }
+        } else {
+            const float* ar = (const float*)g.ops + ((long)op * g.M + row) * g.Kd + 4 * grp;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) a[ks] = *(const V*)(ar + 16 * ks);
+        }
+    };
+    V a0[KS], a1[KS];
+    load_a(wave < MB ? wave : MB - 1, a0);
+    for (int e = threadIdx.x; e < 64 * kq; e += blockDim.x) {
+        const int c = e / kq, k4 = e - c * kq;
+        const long col = col0 + c;
+        V v = V{0.f, 0.f, 0.f, 0.f};
+        if (col < (long)np * g.B) {
+            const int pb = (int)(col / np);
+            const long pidx = p0 + (col - (long)pb * np);
+            v = *(const V*)((const float*)g.W + ((long)pb * g.nbox + g.pl.ps[pidx]) * g.Kd + 4 * k4);
+        }
+        *(V*)(sB + c * ld + 4 * k4) = v;
+    }
+    __syncthreads();
+    long pidx[4];
+    int pb[4];
+#pragma unroll
+    for (int tn = 0; tn < 4; ++tn) {
+        const long col = col0 + 16 * tn + (lane & 15);
+        const bool ok = col < (long)np * g.B;
+        const long cc = ok ? col : 0;
+        pb[tn] = (int)(cc / np);
+        pidx[tn] = ok ? p0 + (cc - (long)pb[tn] * np) : -1;
+    }
+    const float* bl = sB + (lane & 15) * ld + 4 * grp;
+    auto block = [&](int rb, const V (&a)[KS]) {
+        V acc[4];
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn) acc[tn] = V{0.f, 0.f, 0.f, 0.f};
+        // the source fragments are read from LDS anew for every row block: an offset the
+        // compiler cannot see through keeps it from hoisting all KS x 4 of them into
+        // registers (which would leave one wave per SIMD)
+        int off = 0;
+        asm volatile("" : "+v"(off));
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            V b[4];
+#pragma unroll
+            for (int tn = 0; tn < 4; ++tn) b[tn] = *(const V*)(bl + off + tn * 16 * ld + 16 * ks);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int tn = 0; tn < 4; ++tn)
+                    acc[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][e], b[tn][e], acc[tn], 0, 0, 0);
+        }
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn)
+            if (pidx[tn] >= 0)
+                *(V*)((float*)g.stage + ((long)pb[tn] * g.pl.npairs + pidx[tn]) * g.M + 16 * rb + 4 * grp) = acc[tn];
+    };
+    for (int rb = wave; rb < MB; rb += 2 * kWaves) {
+        const int r1 = rb + kWaves;
+        load_a(r1 < MB ? r1 : rb, a1);
+        block(rb, a0);
+        if (r1 >= MB) break;                            // uniform over the wave
+        const int r2 = r1 + kWaves;
+        load_a(r2 < MB ? r2 : r1, a0);
+        block(r1, a1);
+    }
+}
+
+// tiles of one offset group are consecutive: keep them on one XCD (its L2 holds the operator)
+template <bool TAB, int KS>
+__global__ __launch_bounds__(256) void k_offset_lds64(OffsetGemm g)
+{
+    extern __shared__ __align__(16) float lds_b[];
+    lds64_tile<TAB, KS>(g, xcd_position(blockIdx.x, gridDim.x), lds_b);
+}
+
+template <bool TAB, int KS = 1>
+void launch_lds64(hipStream_t s, const OffsetGemm& g, size_t sh)
+{
+    if constexpr (KS <= kLds64K) {
+        if (g.Kd == 16 * KS) hipLaunchKernelGGL((k_offset_lds64<TAB, KS>), dim3((unsigned)g.pl.ntiles4), dim3(256), sh, s, g);
+        else launch_lds64<TAB, KS + 1>(s, g, sh);
+    }
+}
+
 // Per-target sums of the staged pair products, in a fixed order: one workgroup
 // per (target, 64-row slab, rhs); its four waves sum four consecutive quarters
 // of the target's pair list (8 row loads in flight per lane) and wave 0 adds
@@ -602,11 +728,30 @@ bool offset_lds_ok(int prec, const OffsetGemm& g)
     return prec == ERT_FP32 && g.M % 16 == 0 && g.Kd % 16 == 0 && 16L * (g.Kd + 4) * 4 <= 65536;
 }
 
+bool offset_lds64_ok(int prec, const OffsetGemm& g)
+{
+    return prec == ERT_FP32 && g.M % 16 == 0 && g.Kd % 16 == 0 && g.Kd <= 16 * kLds64K &&
+           64L * (g.Kd + 4) * 4 <= 65536;
+}
+
 ert_status offset_gemm_products(hipStream_t s, int prec, const OffsetGemm& g)
 {
     if (g.M % (16 * kTM) != 0 || g.Kd % 32 != 0) {
         record_error("offset_gemm: row count must be a multiple of 32 and the reduction length of 32");
         return ERT_EINVAL;
+    }
+    if (g.lds == 2) {
+        if (!offset_lds64_ok(prec, g)) {
+            record_error("offset_gemm: execution form 5 needs FP32 and a reduction length of at most 240");
+            return ERT_EINVAL;
+        }
+        if (g.pl.ntiles4 > 0) {
+            const size_t sh = 64 * (size_t)(g.Kd + 4) * sizeof(float);
+            if (g.atab) launch_lds64<true>(s, g, sh);
+            else launch_lds64<false>(s, g, sh);
+            ERT_HIP(hipGetLastError());
+        }
+        return ERT_OK;
     }
     if (g.lds) {
         if (!offset_lds_ok(prec, g)) {
@@ -724,7 +869,7 @@ void launch_pair(hipStream_t s, const OffsetGemm& a, int ra, long na, int fa, co
     launch_pair_a<PREC, false>(s, a, ra, na, fa, b, rb, nb, fb);
 }
 
-int form_of(const OffsetGemm& g) { return g.lds ? 4 : g.tn == 4 ? (g.tm == 1 ? 3 : 2) : 1; }
+int form_of(const OffsetGemm& g) { return g.lds == 2 ? 5 : g.lds ? 4 : g.tn == 4 ? (g.tm == 1 ? 3 : 2) : 1; }
 
 }  // namespace
 
@@ -739,7 +884,7 @@ ert_status offset_gemm_pair_products(hipStream_t s, int prec, const OffsetGemm& 
         record_error("offset_gemm: only the first product of a pair, in FP32/FP64, reads an offset table");
         return ERT_EINVAL;
     }
-    if (a.lds != b.lds) {                       // forms of both kinds: two launches
+    if (a.lds != b.lds || a.lds == 2) {         // forms of both kinds, or form 5: two launches
         ERT_TRY(offset_gemm_products(s, prec, a));
         return offset_gemm_products(s, prec, b);
     }

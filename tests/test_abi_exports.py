@@ -81,7 +81,7 @@ def test_plan_rejects_bad_arguments_before_device_use():
     assert plan(inner_cheb_n=1) == ertvie.EINVAL
     assert plan(inner_cheb_n=9) == ertvie.EINVAL
     assert plan(inner_near16=2) == ertvie.EINVAL
-    assert plan(form=(6, 0)) == ertvie.EINVAL                  # execution forms 0..4, stored as f + 1
+    assert plan(form=(7, 0)) == ertvie.EINVAL                  # execution forms 0..5, stored as f + 1
     assert plan(form=(0, -1)) == ertvie.EINVAL
     assert plan(st=np.where(np.arange(N) == 3, -1.0, 2.0)) == ertvie.EINVAL
     assert plan(ss=np.full(N, 2.5)) == ertvie.EINVAL           # absorption < 0

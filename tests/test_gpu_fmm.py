@@ -108,7 +108,7 @@ def test_fmm_ragged(ev, oracle_mod, n, leaf):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("forms", [None, "1", "4"])
+@pytest.mark.parametrize("forms", [None, "1", "4", "5"])
 def test_fmm_multi_rhs_and_determinism(ev, oracle_mod, forms):
     """Repeated applies return the same bits.  Each right-hand-side count tunes its own
     execution forms, which may sum in different orders: the columns of a 5-column apply
@@ -362,3 +362,28 @@ def test_read_rate_diagnostic(ev):
     assert nbytes == (a.numel() * 4) // (224 * 224 * 4) * (224 * 224 * 4)
     assert ms > 0 and nbytes / (ms * 1e-3) < 8.0e12
     log("read rate, 256 MiB in 200704-byte pieces:", nbytes / (ms * 1e-3) / 1e9, "GB/s")
+
+
+def test_fmm_homogeneous_64cubed_lds64_form(ev, oracle_mod):
+    """The 64^3 homogeneous recipe (two far-field levels, translations compressed at 1e-6 to
+    ranks 256 and 224): execution form 5 (64-column tiles over all rows, source columns in
+    LDS) where it applies (rank 224 <= 252) against form 1, to FP32 rounding (bar 1e-6), and
+    the oracle on sampled rows (the FMM bar 1e-6); repeated applies return the same bits."""
+    case = inputs.make_case("c2", n=(64, 64, 64), seed=0)
+    P = oracle_problem(oracle_mod, case)
+    x = inputs.random_vector(P.N, 13)
+    rows = np.random.default_rng(2).choice(P.N, size=64, replace=False)
+    out = {}
+    for form in (1, 5):
+        with ev.plan_from_case(case, method="fmm", prec="fp32", form=(1, form)) as plan:
+            ys = [gpu_apply(plan, x, ev.OP_A) for _ in range(3)]
+            info = plan.fmm_info()
+        assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+        out[form] = (ys[0], info)
+    info5 = out[5][1]
+    log("64^3 forms", info5["rank"], info5["form_far"])
+    assert info5["form_far"][3] == 5 and info5["rank"][3] <= 252
+    d = rel_l2(out[5][0], out[1][0])
+    err = rel_l2(out[5][0][rows], P.apply_rows(x, rows, op=2))
+    log("64^3 form 5 vs form 1", d, "vs oracle rows", err)
+    assert d <= 1e-6 and err <= 1e-6

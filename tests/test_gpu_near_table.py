@@ -5,8 +5,9 @@ against each other.
 
 The offset-stationary forms 1-3 read the same FP32/FP64 values as the explicit blocks
 and reduce each output in the same order, so they agree bit for bit; the target-tile
-form 0 (explicit blocks, another summation order) and, in FP32, form 4 (source
-columns staged in LDS, one wave per 16 rows) agree to rounding.  Repeated
+form 0 (explicit blocks, another summation order) and, in FP32, forms 4 and 5 (source
+columns staged in LDS; one wave per 16 rows, or 64 columns per wave over every fourth
+block of 16 rows) agree to rounding.  Repeated
 calls (the second captures a graph, the third replays it) return the same bits.
 Bars against the oracle: the FMM bar of 1e-6 at n = 8 for both precisions.
 """
@@ -37,7 +38,8 @@ def test_near_table_forms(ev, oracle_mod, recipe, n, leaf):
     ref = P.apply_rows(x, rows, op=2)
     for prec, agree in (("fp64", 1e-13), ("fp32", 1e-6)):
         out = {}
-        for form in ("0", "1", "2", "3") + (("4",) if prec == "fp32" else ()):
+        lds64 = prec == "fp32" and leaf ** dim <= 252       # form 5 stages 64 columns of leaf^dim values
+        for form in ("0", "1", "2", "3") + (("4",) if prec == "fp32" else ()) + (("5",) if lds64 else ()):
             with ev.plan_from_case(case, method="fmm", prec=prec, leaf=leaf, form=int(form)) as plan:
                 ys = [gpu_apply(plan, x, ev.OP_A) for _ in range(3)]
                 info = plan.fmm_info()
@@ -49,7 +51,8 @@ def test_near_table_forms(ev, oracle_mod, recipe, n, leaf):
         log("near table", recipe, n, leaf, prec, "vs oracle", err, "form 0 vs 1", rel_l2(out["0"], out["1"]))
         assert np.array_equal(out["1"], out["2"]) and np.array_equal(out["1"], out["3"])
         assert rel_l2(out["0"], out["1"]) <= agree
-        if "4" in out:
-            log("near table", recipe, n, leaf, "form 4 vs 1", rel_l2(out["4"], out["1"]))
-            assert rel_l2(out["4"], out["1"]) <= agree
+        for f in ("4", "5"):
+            if f in out:
+                log("near table", recipe, n, leaf, "form", f, "vs 1", rel_l2(out[f], out["1"]))
+                assert rel_l2(out[f], out["1"]) <= agree
         assert err <= 1e-6
