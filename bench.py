@@ -651,7 +651,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 128^3 workload (applies, stage profile, solves)")
     ap.add_argument("--form", type=int, default=None,
-                    help="fix the execution form of the 32^3 box-offset products (0..4) instead of timing them")
+                    help="fix the execution form of the 32^3 box-offset products (0..5) instead of timing them")
+    ap.add_argument("--homogeneous-only", action="store_true",
+                    help="only the homogeneous 32^3 and 64^3 sections (one JSON line of their results)")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT-based preconditioner (64^3 and 128^3) and exit")
     ap.add_argument("--paper-exp3", action="store_true",
@@ -682,6 +684,12 @@ def main():
         del a, b
     if args.fft_only:
         print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
+        return
+    if args.homogeneous_only:
+        out = {}
+        out["c2_32cubed_homogeneous"], _, _ = c2_32(torch, ertvie, inputs, O, stream, args)
+        out["c2_recipe_64cubed_homogeneous"] = homogeneous_64(torch, ertvie, inputs, O, stream)
+        print(json.dumps(out), flush=True)
         return
 
     ertvie.load()
