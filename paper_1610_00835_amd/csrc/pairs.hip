@@ -527,6 +527,172 @@ __global__ __launch_bounds__(256) void k_pair_mfma_back(PairStream g, int b0, in
     }
 }
 
+// Matrix-core form with both operands staged in LDS and the next chunk in flight:
+// per reduction chunk of KC = 32 (FP64: 16) indices the workgroup holds the 64 source
+// vectors (wsh, FP32/FP64) and the block's tile (FP32) in LDS; the next chunk's
+// values are loaded into registers (through a buffer resource spanning the block:
+// rows and columns outside it read as zero) while the MFMAs run on this one, and
+// stored to LDS after a barrier.  BACK = false: the forward product (A[r][k] =
+// B[k][r], sources of box b, the tile is KC stored rows x the workgroup's 64 RT
+// columns); BACK = true: the backward one (A[r][k] = B[r][k], sources of box a,
+// the tile is the workgroup's 64 RT stored rows x KC columns).  M is a multiple of 4.
+template <int PREC, int RT, typename TS, bool BACK>
+__global__ __launch_bounds__(256) void k_pair_mma(PairStream g, int b0, int rblocks)
+{
+    typedef typename Acc<PREC>::V V;
+    typedef typename Acc<PREC>::T T;
+    constexpr bool SPLIT = std::is_same<TS, OpsSplit>::value;
+    constexpr bool F32 = std::is_same<TS, float>::value;
+    constexpr int ESZ = F32 ? 4 : 2;
+    constexpr int KC = PREC == ERT_FP64 ? 16 : 32;   // FP64: fewer registers in flight, 2 waves per SIMD
+    constexpr int LDW = 80;                       // padded LDS row of the sources (columns)
+    constexpr int ROWS = 64 * RT;                 // output rows of the workgroup
+    constexpr int TPB = KC + 4;                   // backward tile pitch (rows of KC values)
+    constexpr int TPF = ROWS + 4;                 // forward tile pitch (rows of ROWS values)
+    constexpr int TILE = BACK ? ROWS * TPB : KC * TPF;
+    constexpr int NP = ROWS * KC / 4 / 256;       // 4-value pieces of the tile per thread
+    constexpr int NW = 64 * KC / 256;             // source values per thread
+    __shared__ T wsh[KC * LDW];
+    __shared__ __align__(16) float tile[TILE];
+    const long p = blockIdx.x / rblocks;
+    const long row = BACK ? g.bwd_row[p] : g.fwd_row[p];
+    if (row < 0) return;                          // self block: no backward product (uniform)
+    const int rblk = (int)(blockIdx.x % rblocks);
+    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
+    const int s = BACK ? g.ua[p] : g.ub[p];
+    const int M = g.M;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
+    const int rw0 = rblk * ROWS;                  // first output row of the workgroup
+    const int row0 = wave * 16 * RT;              // first output row of the wave (in the tile)
+    const size_t base = (size_t)p * M * M;
+    const unsigned nbytes = (unsigned)((size_t)M * M * ESZ);
+    const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const unsigned char*)g.opsT + base * ESZ), 0, (int)nbytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const unsigned char*)(SPLIT ? g.opsT_lo : g.opsT) + base * ESZ), 0, (int)nbytes, kBufFlags);
+    const T* Ws = (const T*)g.W + ((long)b0 * g.nsrc + s) * M;
+    const long wstride = (long)g.nsrc * M;
+
+    // registers of the next chunk: the tile's pieces (raw words) and the source values
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    v4u pr[NP];
+    v2u pl[SPLIT ? NP : 1];
+    T wr[NW];
+    // piece q of the thread: tile row tr, first column tc (4 values)
+    auto piece = [&](int q, int& tr, int& tc) {
+        const int e = threadIdx.x + 256 * q;
+        if constexpr (BACK) { tr = e / (KC / 4); tc = 4 * (e - tr * (KC / 4)); }
+        else { tr = e / (ROWS / 4); tc = 4 * (e - tr * (ROWS / 4)); }
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            int tr, tc;
+            piece(q, tr, tc);
+            // stored element (j, i): backward j = rw0 + tr, i = k0 + tc; forward j = k0 + tr, i = rw0 + tc
+            const int j = BACK ? rw0 + tr : k0 + tr, i = BACK ? k0 + tc : rw0 + tc;
+            const unsigned off = (j < M && i < M) ? (unsigned)(((size_t)j * M + i) * ESZ) : kBufOob;
+            if constexpr (F32) {
+                pr[q] = __builtin_amdgcn_raw_buffer_load_b128(rs0, off, 0, 0);
+            } else {
+                const v2u h = __builtin_amdgcn_raw_buffer_load_b64(rs0, off, 0, 0);
+                pr[q] = v4u{h[0], h[1], 0u, 0u};
+                if constexpr (SPLIT) pl[q] = __builtin_amdgcn_raw_buffer_load_b64(rs1, off, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int e = threadIdx.x + 256 * q, b = e / KC, kk = e - b * KC;
+            wr[q] = (b < nb && k0 + kk < M) ? Ws[(long)b * wstride + k0 + kk] : T(0);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            int tr, tc;
+            piece(q, tr, tc);
+            v4f v;
+            if constexpr (F32) {
+                v = v4f{__uint_as_float(pr[q][0]), __uint_as_float(pr[q][1]), __uint_as_float(pr[q][2]),
+                        __uint_as_float(pr[q][3])};
+            } else {
+                const unsigned h0 = pr[q][0], h1 = pr[q][1];
+                unsigned e0 = h0 << 16, e1 = h0 & 0xffff0000u, e2 = h1 << 16, e3 = h1 & 0xffff0000u;
+                if constexpr (SPLIT) {
+                    const int l0 = (int)pl[q][0], l1 = (int)pl[q][1];
+                    e0 += (unsigned)((l0 << 16) >> 16);
+                    e1 += (unsigned)(l0 >> 16);
+                    e2 += (unsigned)((l1 << 16) >> 16);
+                    e3 += (unsigned)(l1 >> 16);
+                }
+                v = v4f{__uint_as_float(e0), __uint_as_float(e1), __uint_as_float(e2), __uint_as_float(e3)};
+            }
+            *(v4f*)(tile + (BACK ? tr * TPB : tr * TPF) + tc) = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int e = threadIdx.x + 256 * q, b = e / KC, kk = e - b * KC;
+            wsh[kk * LDW + b] = wr[q];
+        }
+    };
+    V acc[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < M; k0 += KC) {
+        const bool more = k0 + KC < M;            // uniform
+        if (more) fetch(k0 + KC);
+#pragma unroll 2
+        for (int kk = 0; kk < KC; kk += 4) {
+            T av[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const int r = row0 + 16 * rt + li;
+                av[rt] = (T)(BACK ? tile[r * TPB + kk + grp] : tile[(kk + grp) * TPF + r]);
+            }
+            T bf[4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) bf[ct] = wsh[(kk + grp) * LDW + 16 * ct + li];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    if constexpr (PREC == ERT_FP64)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+                    else
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], bf[ct], acc[rt][ct], 0, 0, 0);
+                }
+        }
+        if (!more) break;
+        __syncthreads();                          // every wave is done with this chunk
+        stash();
+        __syncthreads();
+    }
+    // FP32 tiles: rows 4 grp + i; FP64 tiles: rows grp + 4 i (column li in both)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int b = 16 * ct + li;
+        if (b >= nb) continue;
+        T* dst = (T*)g.stage + ((long)b * g.nrows + row) * M;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int rb = rw0 + row0 + 16 * rt;
+            if constexpr (PREC == ERT_FP64) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (rb + grp + 4 * i < M) dst[rb + grp + 4 * i] = acc[rt][ct][i];
+            } else {
+                if (rb + 4 * grp + 3 < M) *(V*)(dst + rb + 4 * grp) = acc[rt][ct];
+            }
+        }
+    }
+}
+
 // Split-BF16x3 form of the same products (FP32-stored blocks, FP32 vectors): every
 // block value a and source value w is split into BF16 parts (hi = bf16(v), lo =
 // bf16(v - hi)) and a w is taken as hi_a hi_w + hi_a lo_w + lo_a hi_w, three
@@ -734,9 +900,23 @@ ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
         const int nb = std::min(64, g.B - b0);
         {
             StageTimer t_(g.prof, s, g.prof_stage);
-            hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), grid, dim3(256), 0, s, g, b0, rblocks);
+            // whole 4-value pieces of the stored rows: both operands staged in LDS, the
+            // next chunk in flight (the FP32 forward product keeps its 512-row tiles, whose
+            // operators come straight from memory: already near the matrix-core peak)
+            const bool piecewise = g.M % 4 == 0;
+            bool fwd_done = false;
+            if constexpr (PREC == ERT_FP64) {
+                if (piecewise) {
+                    hipLaunchKernelGGL((k_pair_mma<PREC, RT, TS, false>), grid, dim3(256), 0, s, g, b0, rblocks);
+                    fwd_done = true;
+                }
+            }
+            if (!fwd_done) hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), grid, dim3(256), 0, s, g, b0, rblocks);
             ERT_HIP(hipGetLastError());
-            hipLaunchKernelGGL((k_pair_mfma_back<PREC, RTB, TS>), gridb, dim3(256), 0, s, g, b0, rblocksb);
+            if (piecewise)
+                hipLaunchKernelGGL((k_pair_mma<PREC, RTB, TS, true>), gridb, dim3(256), 0, s, g, b0, rblocksb);
+            else
+                hipLaunchKernelGGL((k_pair_mfma_back<PREC, RTB, TS>), gridb, dim3(256), 0, s, g, b0, rblocksb);
             ERT_HIP(hipGetLastError());
         }
         ERT_TRY(launch_reduce<T>(s, g, b0, nb));
