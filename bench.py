@@ -652,6 +652,8 @@ def main():
                     help="only the 128^3 workload (applies, stage profile, solves)")
     ap.add_argument("--form", type=int, default=None,
                     help="fix the execution form of the 32^3 box-offset products (0..5) instead of timing them")
+    ap.add_argument("--many-rhs-only", action="store_true",
+                    help="only the 64-right-hand-side section on the 64^3 blob medium (one JSON line)")
     ap.add_argument("--homogeneous-only", action="store_true",
                     help="only the homogeneous 32^3 and 64^3 sections (one JSON line of their results)")
     ap.add_argument("--fft-only", action="store_true",
@@ -684,6 +686,9 @@ def main():
         del a, b
     if args.fft_only:
         print(json.dumps({"fft_precond": fft_only(torch, ertvie, inputs, stream, args.steps)}), flush=True)
+        return
+    if args.many_rhs_only:
+        print(json.dumps({"many_rhs_64cubed": many_rhs_64(torch, ertvie, inputs, stream)}), flush=True)
         return
     if args.homogeneous_only:
         out = {}

@@ -790,6 +790,142 @@ __global__ __launch_bounds__(256) void k_pair_mfma_bf16x3(PairStream g, int b0, 
     }
 }
 
+// Split-BF16x3 products with both operands staged in LDS and the next reduction
+// chunk in flight (the structure of k_pair_mma): the block tile is kept in FP32 and
+// split where it is read; the 64 source vectors are split once per chunk into LDS.
+template <int RT, bool TRANS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_b3(PairStream g, int b0, int rblocks)
+{
+    constexpr int KC = 32;
+    constexpr int LDK = KC + 8;                   // padded LDS row of the split sources (bf16)
+    constexpr int ROWS = 64 * RT;                 // output rows of the workgroup
+    constexpr int TPB = KC + 4;                   // backward tile pitch (rows of KC values)
+    constexpr int TPF = ROWS + 4;                 // forward tile pitch (rows of ROWS values)
+    constexpr int TILE = TRANS ? ROWS * TPB : KC * TPF;
+    constexpr int NP = ROWS * KC / 4 / 256;       // 4-value pieces of the tile per thread
+    constexpr int NW = 64 * KC / 256;             // source values per thread
+    __shared__ __align__(16) __bf16 whi[64 * LDK];
+    __shared__ __align__(16) __bf16 wlo[64 * LDK];
+    __shared__ __align__(16) float tile[TILE];
+    const long p = blockIdx.x / rblocks;
+    const long row = TRANS ? g.bwd_row[p] : g.fwd_row[p];
+    if (row < 0) return;                          // self block: no backward product (uniform)
+    const int rblk = (int)(blockIdx.x % rblocks);
+    const int nb = (g.B - b0) < 64 ? (g.B - b0) : 64;
+    const int s = TRANS ? g.ua[p] : g.ub[p];
+    const int M = g.M;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane >> 4, li = lane & 15;
+    const int rw0 = rblk * ROWS;
+    const int row0 = wave * 16 * RT;
+    const size_t base = (size_t)p * M * M;
+    const unsigned nbytes = (unsigned)((size_t)M * M * 4);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const float*)g.opsT + base), 0, (int)nbytes, kBufFlags);
+    const float* Ws = (const float*)g.W + ((long)b0 * g.nsrc + s) * M;
+    const long wstride = (long)g.nsrc * M;
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    v4u pr[NP];
+    float wr[NW];
+    auto piece = [&](int q, int& tr, int& tc) {
+        const int e = threadIdx.x + 256 * q;
+        if constexpr (TRANS) { tr = e / (KC / 4); tc = 4 * (e - tr * (KC / 4)); }
+        else { tr = e / (ROWS / 4); tc = 4 * (e - tr * (ROWS / 4)); }
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            int tr, tc;
+            piece(q, tr, tc);
+            const int j = TRANS ? rw0 + tr : k0 + tr, i = TRANS ? k0 + tc : rw0 + tc;
+            const unsigned off = (j < M && i < M) ? (unsigned)(((size_t)j * M + i) * 4) : kBufOob;
+            pr[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int e = threadIdx.x + 256 * q, b = e / KC, kk = e - b * KC;
+            wr[q] = (b < nb && k0 + kk < M) ? Ws[(long)b * wstride + k0 + kk] : 0.f;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            int tr, tc;
+            piece(q, tr, tc);
+            *(v4u*)(tile + (TRANS ? tr * TPB : tr * TPF) + tc) = pr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int e = threadIdx.x + 256 * q, b = e / KC, kk = e - b * KC;
+            const __bf16 h = (__bf16)wr[q];
+            whi[b * LDK + kk] = h;
+            wlo[b * LDK + kk] = (__bf16)(wr[q] - (float)h);
+        }
+    };
+    v4f acc[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < M; k0 += KC) {
+        const bool more = k0 + KC < M;            // uniform
+        if (more) fetch(k0 + KC);
+        v8bf ah[RT], al[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int r = row0 + 16 * rt + li;
+            float av[8];
+            if constexpr (TRANS) {
+                const v4f x0 = *(const v4f*)(tile + r * TPB + 8 * grp);
+                const v4f x1 = *(const v4f*)(tile + r * TPB + 8 * grp + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    av[e] = x0[e];
+                    av[4 + e] = x1[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) av[e] = tile[(8 * grp + e) * TPF + r];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const __bf16 h = (__bf16)av[e];
+                ah[rt][e] = h;
+                al[rt][e] = (__bf16)(av[e] - (float)h);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int b = 16 * ct + li;
+            const v8bf bh = *(const v8bf*)(whi + b * LDK + 8 * grp);
+            const v8bf bl = *(const v8bf*)(wlo + b * LDK + 8 * grp);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bh, acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bl, acc[rt][ct], 0, 0, 0);
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][ct], 0, 0, 0);
+            }
+        }
+        if (!more) break;
+        __syncthreads();
+        stash();
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int b = 16 * ct + li;
+        if (b >= nb) continue;
+        float* dst = (float*)g.stage + ((long)b * g.nrows + row) * M;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int rb = rw0 + row0 + 16 * rt;
+            if (rb + 4 * grp + 3 < M) *(v4f*)(dst + rb + 4 * grp) = acc[rt][ct];
+        }
+    }
+}
+
 // Per-target sums of the staging rows (rhs b0..b0+nb-1), over the target's
 // contiguous directed rows in order, skipping rows of pairs that do not exist.
 template <typename T>
@@ -939,9 +1075,15 @@ ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g)
         const int nb = std::min(64, g.B - b0);
         {
             StageTimer t_(g.prof, s, g.prof_stage);
-            hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, false>), grid, dim3(256), 0, s, g, b0, rblocks);
-            ERT_HIP(hipGetLastError());
-            hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, true>), grid, dim3(256), 0, s, g, b0, rblocks);
+            if (g.M % 4 == 0) {           // whole 4-value pieces: LDS-staged, next chunk in flight
+                hipLaunchKernelGGL((k_pair_b3<RT, false>), grid, dim3(256), 0, s, g, b0, rblocks);
+                ERT_HIP(hipGetLastError());
+                hipLaunchKernelGGL((k_pair_b3<RT, true>), grid, dim3(256), 0, s, g, b0, rblocks);
+            } else {
+                hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, false>), grid, dim3(256), 0, s, g, b0, rblocks);
+                ERT_HIP(hipGetLastError());
+                hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, true>), grid, dim3(256), 0, s, g, b0, rblocks);
+            }
             ERT_HIP(hipGetLastError());
         }
         ERT_TRY(launch_reduce<float>(s, g, b0, nb));
