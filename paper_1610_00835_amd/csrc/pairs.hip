@@ -1037,13 +1037,15 @@ ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
         {
             StageTimer t_(g.prof, s, g.prof_stage);
             // whole 4-value pieces of the stored rows: both operands staged in LDS, the
-            // next chunk in flight (the FP32 forward product keeps its 512-row tiles, whose
-            // operators come straight from memory: already near the matrix-core peak)
+            // next chunk in flight (the FP32 forward product over FP32-stored blocks keeps its
+            // 512-row tiles, whose operators come straight from memory: it keeps the matrix
+            // cores about 60 % busy already)
             const bool piecewise = g.M % 4 == 0;
             bool fwd_done = false;
-            if constexpr (PREC == ERT_FP64) {
+            if constexpr (PREC == ERT_FP64 || !std::is_same<TS, float>::value) {
+                // FP64, or values in 16-bit planes (decoded once into the LDS tile)
                 if (piecewise) {
-                    hipLaunchKernelGGL((k_pair_mma<PREC, RT, TS, false>), grid, dim3(256), 0, s, g, b0, rblocks);
+                    hipLaunchKernelGGL((k_pair_mma<PREC, RTB, TS, false>), gridb, dim3(256), 0, s, g, b0, rblocksb);
                     fwd_done = true;
                 }
             }
