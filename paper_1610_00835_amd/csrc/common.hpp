@@ -86,6 +86,115 @@ __device__ __forceinline__ T sigma_at(const T* __restrict__ st, const Geo& g, T 
     return c0 + t[2] * (c1 - c0);
 }
 
+// The same interpolant read from a table of corner octets: entry b holds the
+// eight values st[b], st[b + d0], st[b + d1], st[b + d1 + d0], st[b + d2],
+// st[b + d2 + d0], st[b + d2 + d1], st[b + d2 + d1 + d0] (64 bytes, aligned),
+// so that a sample costs four 16-byte loads from one cache line instead of
+// eight gathers over four lines.  The arithmetic is sigma_at's, term for term.
+__device__ __forceinline__ double sigma_at8(const double* __restrict__ st8, const Geo& g, double inv_h, double p0,
+                                            double p1, double p2)
+{
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const double p[3] = {p0, p1, p2};
+    int i0[3] = {0, 0, 0};
+    double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < g.dim && n[a] > 1) {
+            double u = p[a] * inv_h - 0.5;
+            double hi = double(n[a] - 1);
+            u = u < 0.0 ? 0.0 : (u > hi ? hi : u);
+            int k = (int)floor(u);
+            k = k > n[a] - 2 ? n[a] - 2 : k;
+            i0[a] = k;
+            t[a] = u - double(k);
+        }
+    }
+    const long b0 = i0[0] + (long)n[0] * (i0[1] + (long)n[1] * i0[2]);
+    const double2* q = reinterpret_cast<const double2*>(st8) + 4 * b0;
+    const double2 v01 = q[0], v23 = q[1];
+    double c00 = v01.x + t[0] * (v01.y - v01.x);
+    double c10 = v23.x + t[0] * (v23.y - v23.x);
+    double c0 = c00 + t[1] * (c10 - c00);
+    if (g.dim == 2) return c0;
+    const double2 v45 = q[2], v67 = q[3];
+    double c01 = v45.x + t[0] * (v45.y - v45.x);
+    double c11 = v67.x + t[0] * (v67.y - v67.x);
+    double c1 = c01 + t[1] * (c11 - c01);
+    return c0 + t[2] * (c1 - c0);
+}
+
+// Midpoint-rule optical depth from the corner-octet table (tau_march's rule and
+// sum order, the same values bit for bit).  On a 3D grid with every side > 1
+// the cell searches of U consecutive samples come first and their 4U loads are
+// issued together, so the march does not wait one memory latency per sample;
+// samples past m repeat the last one and are added with weight 0.  The clamp
+// and floor are done in FP64 (max, min, floor: the same integers and
+// fractions as sigma_at's compare-select form and integer minimum).
+template <int U = 2>
+__device__ __forceinline__ double tau_march8(const double* __restrict__ st8, const Geo& g, double inv_h, double a0,
+                                             double a1, double a2, double b0, double b1, double b2, int m, double r)
+{
+    double e0 = b0 - a0, e1 = b1 - a1, e2 = b2 - a2;
+    double inv_m = 1.0 / double(m);
+    double s = 0.0;
+    const long ncell = (long)g.n0 * g.n1 * g.n2;
+    if (g.dim != 3 || g.n0 < 2 || g.n1 < 2 || g.n2 < 2 || ncell > (0x7fffffffL >> 6)) {
+        for (int q = 1; q <= m; ++q) {
+            double f = (double(q) - 0.5) * inv_m;
+            s += sigma_at8(st8, g, inv_h, a0 + f * e0, a1 + f * e1, a2 + f * e2);
+        }
+        return r * inv_m * s;
+    }
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)st8, 0, (int)(ncell << 6), 0x00020000);
+    const double hi0 = double(g.n0 - 1), hi1 = double(g.n1 - 1), hi2 = double(g.n2 - 1);
+    const double km0 = double(g.n0 - 2), km1 = double(g.n1 - 2), km2 = double(g.n2 - 2);
+    const double nxd = double(g.n0), nyd = double(g.n1);
+    const double last = double(m) - 0.5;
+    double hq = 0.5;  // q0 - 0.5
+    for (int q0 = 1; q0 <= m; q0 += U, hq += double(U)) {
+        double t0[U], t1[U], t2[U];
+        v4u raw[U][4];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const double hj = fmin(hq + double(j), last);
+            const double f = hj * inv_m;
+            const double u0 = fmin(fmax((a0 + f * e0) * inv_h - 0.5, 0.0), hi0);
+            const double u1 = fmin(fmax((a1 + f * e1) * inv_h - 0.5, 0.0), hi1);
+            const double u2 = fmin(fmax((a2 + f * e2) * inv_h - 0.5, 0.0), hi2);
+            const double k0 = fmin(floor(u0), km0), k1 = fmin(floor(u1), km1), k2 = fmin(floor(u2), km2);
+            t0[j] = u0 - k0;
+            t1[j] = u1 - k1;
+            t2[j] = u2 - k2;
+            const unsigned c = (unsigned)fma(nxd, fma(nyd, k2, k1), k0);  // exact: integers below 2^25
+#pragma unroll
+            for (int w = 0; w < 4; ++w) raw[j][w] = __builtin_amdgcn_raw_buffer_load_b128(rs, (c << 6) + 16 * w, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // every load of the group issued before the first use
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            double v[8];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const double2 d = __builtin_bit_cast(double2, raw[j][w]);
+                v[2 * w] = d.x;
+                v[2 * w + 1] = d.y;
+            }
+            double c00 = v[0] + t0[j] * (v[1] - v[0]);
+            double c10 = v[2] + t0[j] * (v[3] - v[2]);
+            double c0 = c00 + t1[j] * (c10 - c00);
+            double c01 = v[4] + t0[j] * (v[5] - v[4]);
+            double c11 = v[6] + t0[j] * (v[7] - v[6]);
+            double c1 = c01 + t1[j] * (c11 - c01);
+            const double sv = c0 + t2[j] * (c1 - c0);
+            s = fma(sv, q0 + j <= m ? 1.0 : 0.0, s);
+        }
+    }
+    return r * inv_m * s;
+}
+
 // Smallest m >= 1 with m*m >= 4K: steps of the midpoint rule between two
 // collocation points whose integer offsets square-sum to K (step <= h/2).
 __host__ __device__ inline int steps_grid(int K)

@@ -19,9 +19,48 @@ constexpr int kTile = 256;
 
 // ---------------------------------------------------------- self cell -----
 
+// sigma_at for points inside cell c, reading the cell's 3^3 neighbourhood nb
+// (nb[a0 + 3 a1 + 9 a2] = sigma_t of cell c + a - 1, indices clamped to the grid):
+// every interpolation cell such a point can fall in has its corners there.  The
+// clamp, cell search and interpolation are sigma_at's, so the values agree bit
+// for bit.
+__device__ __forceinline__ double sigma_nb(const double* nb, const Geo& g, double inv_h, const int c[3], double p0,
+                                           double p1, double p2)
+{
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const double p[3] = {p0, p1, p2};
+    int l[3] = {1, 1, 1};  // local index of the lower corner
+    double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < g.dim && n[a] > 1) {
+            double u = p[a] * inv_h - 0.5;
+            double hi = double(n[a] - 1);
+            u = u < 0.0 ? 0.0 : (u > hi ? hi : u);
+            int k = (int)floor(u);
+            k = k > n[a] - 2 ? n[a] - 2 : k;
+            l[a] = k - c[a] + 1;
+            t[a] = u - double(k);
+        }
+    }
+    const int b0 = l[0] + 3 * (l[1] + 3 * l[2]);
+    const int d0 = n[0] > 1 ? 1 : 0;
+    const int d1 = n[1] > 1 ? 3 : 0;
+    const int d2 = (g.dim > 2 && n[2] > 1) ? 9 : 0;
+    double c00 = nb[b0] + t[0] * (nb[b0 + d0] - nb[b0]);
+    double c10 = nb[b0 + d1] + t[0] * (nb[b0 + d1 + d0] - nb[b0 + d1]);
+    double c0 = c00 + t[1] * (c10 - c00);
+    if (g.dim == 2) return c0;
+    double c01 = nb[b0 + d2] + t[0] * (nb[b0 + d2 + d0] - nb[b0 + d2]);
+    double c11 = nb[b0 + d2 + d1] + t[0] * (nb[b0 + d2 + d1 + d0] - nb[b0 + d2 + d1]);
+    double c1 = c01 + t[1] * (c11 - c01);
+    return c0 + t[2] * (c1 - c0);
+}
+
 // integral_0^rho E(x, x + r v) dr (same step rule as the off-diagonal kernel:
-// one midpoint step for r <= h/2, two beyond; rho < h always).
-__device__ double radial_integral(const Geo& g, int ray, double sigma, const double* __restrict__ st,
+// one midpoint step for r <= h/2, two beyond; rho < h always).  Every sample
+// lies in the cell of x, whose neighbourhood nb holds sigma_t.
+__device__ double radial_integral(const Geo& g, int ray, double sigma, const double* nb, const int cell[3],
                                   const double x[3], const double v[3], double rho,
                                   const double* __restrict__ rx, const double* __restrict__ rw, int nrad)
 {
@@ -34,7 +73,7 @@ __device__ double radial_integral(const Geo& g, int ray, double sigma, const dou
     double b0 = rho < half ? rho : half;
     for (int q = 0; q < nrad; ++q) {
         double r = 0.5 * b0 * (rx[q] + 1.0);
-        double s = sigma_at<double>(st, g, inv_h, x[0] + 0.5 * r * v[0], x[1] + 0.5 * r * v[1],
+        double s = sigma_nb(nb, g, inv_h, cell, x[0] + 0.5 * r * v[0], x[1] + 0.5 * r * v[1],
                                     x[2] + 0.5 * r * v[2]);
         acc += 0.5 * b0 * rw[q] * exp(-r * s);
     }
@@ -42,9 +81,9 @@ __device__ double radial_integral(const Geo& g, int ray, double sigma, const dou
         double len = rho - half;
         for (int q = 0; q < nrad; ++q) {
             double r = half + 0.5 * len * (rx[q] + 1.0);
-            double s1 = sigma_at<double>(st, g, inv_h, x[0] + 0.25 * r * v[0], x[1] + 0.25 * r * v[1],
+            double s1 = sigma_nb(nb, g, inv_h, cell, x[0] + 0.25 * r * v[0], x[1] + 0.25 * r * v[1],
                                          x[2] + 0.25 * r * v[2]);
-            double s2 = sigma_at<double>(st, g, inv_h, x[0] + 0.75 * r * v[0], x[1] + 0.75 * r * v[1],
+            double s2 = sigma_nb(nb, g, inv_h, cell, x[0] + 0.75 * r * v[0], x[1] + 0.75 * r * v[1],
                                          x[2] + 0.75 * r * v[2]);
             acc += 0.5 * len * rw[q] * exp(-0.5 * r * (s1 + s2));
         }
@@ -63,10 +102,22 @@ __global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, 
                                                   double* __restrict__ diag)
 {
     __shared__ double red[256];
+    __shared__ double nb[27];
     const long j = j0 + blockIdx.x;
     const int i0 = (int)(j % g.n0);
     const int i1 = (int)((j / g.n0) % g.n1);
     const int i2 = (int)(j / ((long)g.n0 * g.n1));
+    const int cell[3] = {i0, i1, i2};
+    if (ray && threadIdx.x < 27) {
+        const int n[3] = {g.n0, g.n1, g.n2};
+        int q[3];
+        for (int a = 0; a < 3; ++a) {
+            const int k = cell[a] + (int)(a == 0 ? threadIdx.x % 3 : a == 1 ? (threadIdx.x / 3) % 3 : threadIdx.x / 9) - 1;
+            q[a] = k < 0 ? 0 : (k > n[a] - 1 ? n[a] - 1 : k);
+        }
+        nb[threadIdx.x] = st[q[0] + (long)g.n0 * (q[1] + (long)g.n1 * q[2])];
+    }
+    __syncthreads();
     const double half = 0.5 * g.h;
     const double x[3] = {g.h * (i0 + 0.5), g.h * (i1 + 0.5), g.dim > 2 ? g.h * (i2 + 0.5) : 0.0};
     double acc = 0.0;
@@ -78,7 +129,7 @@ __global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, 
             double th = t0 + (kPi / 8.0) * (ax[q] + 1.0);
             double v[3] = {cos(th), sin(th), 0.0};
             double c = fabs(v[0]) > fabs(v[1]) ? fabs(v[0]) : fabs(v[1]);
-            acc += (kPi / 8.0) * aw[q] * radial_integral(g, ray, sigma, st, x, v, half / c, rx, rw, nrad);
+            acc += (kPi / 8.0) * aw[q] * radial_integral(g, ray, sigma, nb, cell, x, v, half / c, rx, rw, nrad);
         }
     } else {
         const int per = nang * nang;
@@ -95,7 +146,7 @@ __global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, 
             v[(axis + 1) % 3] = u / R;
             v[(axis + 2) % 3] = w / R;
             double wq = 0.25 * half * half * aw[qa] * aw[qb] * half / (R * R * R);
-            acc += wq * radial_integral(g, ray, sigma, st, x, v, R, rx, rw, nrad);
+            acc += wq * radial_integral(g, ray, sigma, nb, cell, x, v, R, rx, rw, nrad);
         }
     }
     red[threadIdx.x] = acc;

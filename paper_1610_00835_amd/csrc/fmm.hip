@@ -632,6 +632,25 @@ __global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__
     }
 }
 
+// Corner-octet table of sigma_t for the ray march of the cache builds (layout
+// in sigma_at8).  Cells on the upper face of an axis are never the lower
+// corner of an interpolation cell; their octets repeat the face values.
+__global__ void k_corner8(Geo g, const double* __restrict__ st, double* __restrict__ st8, long ncell)
+{
+    const long b = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (b >= ncell) return;
+    const int i0 = (int)(b % g.n0), i1 = (int)((b / g.n0) % g.n1);
+    const int i2 = (int)(b / ((long)g.n0 * g.n1));
+    const long d0 = (g.n0 > 1 && i0 < g.n0 - 1) ? 1 : 0;
+    const long d1 = (g.n1 > 1 && i1 < g.n1 - 1) ? g.n0 : 0;
+    const long d2 = (g.dim > 2 && g.n2 > 1 && i2 < g.n2 - 1) ? (long)g.n0 * g.n1 : 0;
+    double2* q = reinterpret_cast<double2*>(st8) + 4 * b;
+    q[0] = make_double2(st[b], st[b + d0]);
+    q[1] = make_double2(st[b + d1], st[b + d1 + d0]);
+    q[2] = make_double2(st[b + d2], st[b + d2 + d0]);
+    q[3] = make_double2(st[b + d2 + d1], st[b + d2 + d1 + d0]);
+}
+
 // Cached near-field blocks for the ray kernel, FP64 arithmetic: the same rule
 // as the dense apply (exact integer step count, marched from the lower index,
 // so the value of a cell pair does not depend on its order).  One block per
@@ -639,7 +658,7 @@ __global__ __launch_bounds__(kB) void k_p2p_hom(DevTree t, const T* __restrict__
 // element [si][ti] = G(cell ti of leaf ua[u], cell si of leaf ub[u]), zero for a
 // cell with itself (the diagonal's term).  FP32 values as a BF16-rounded high
 // plane and the exact remainder.
-__global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, const double* __restrict__ itab,
+__global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st8, const double* __restrict__ itab,
                               const int* __restrict__ ua, const int* __restrict__ ub, long u0, long nu,
                               uint16_t* __restrict__ blk, int16_t* __restrict__ lo_plane)
 {
@@ -661,10 +680,9 @@ __global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, c
         const int* hi = (jt < js) ? cs : ct;
         const double inv_h = 1.0 / g.h;
         const bool d3 = t.D > 2;
-        double tau = tau_march<double>(st, g, inv_h, g.h * (lo[0] + 0.5), g.h * (lo[1] + 0.5),
-                                       d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5),
-                                       g.h * (hi[1] + 0.5), d3 ? g.h * (hi[2] + 0.5) : 0.0,
-                                       steps_grid(K), r);
+        double tau = tau_march8(st8, g, inv_h, g.h * (lo[0] + 0.5), g.h * (lo[1] + 0.5),
+                                d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5), g.h * (hi[1] + 0.5),
+                                d3 ? g.h * (hi[2] + 0.5) : 0.0, steps_grid(K), r);
         if (itab) {
             // (M-ii): cell integral at the integer offset, per unit cell, over h^{d-1}
             const int a0 = abs(ct[0] - cs[0]), a1 = abs(ct[1] - cs[1]), a2 = abs(ct[2] - cs[2]);
@@ -681,6 +699,110 @@ __global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st, c
     const unsigned hi = (X + 0x8000u) >> 16;
     blk[i] = (uint16_t)hi;
     lo_plane[i] = (int16_t)(int)(X - (hi << 16));
+}
+
+// The same blocks with one workgroup per stored pair: sigma_t over the cells
+// spanned by the two leaves, plus one layer above (the upper corner of a
+// sample on the top face), is staged in LDS, and the march reads it there.
+// Samples lie between the two cell centres, so every corner they need is in
+// the box; cell search and interpolation are sigma_at's, so the blocks agree
+// bit for bit with k_near_blocks.  Needs leaf <= kNearLdsLeaf.
+constexpr int kNearLdsLeaf = 8;
+constexpr int kNearLdsSide = 2 * kNearLdsLeaf + 1;
+constexpr int kNearLdsThreads = 512;
+
+__global__ __launch_bounds__(kNearLdsThreads) void k_near_blocks_lds(
+    DevTree t, Geo g, const double* __restrict__ st, const double* __restrict__ itab, const int* __restrict__ ua,
+    const int* __restrict__ ub, long u0, uint16_t* __restrict__ blk, int16_t* __restrict__ lo_plane)
+{
+    __shared__ double sl[kNearLdsSide * kNearLdsSide * kNearLdsSide];
+    const long u = u0 + blockIdx.x;
+    const long per = (long)t.S * t.S;
+    int bt[3], bs[3], lo[3], ext[3];
+    unravel3(ua[u], t.nb, bt);
+    unravel3(ub[u], t.nb, bs);
+    for (int a = 0; a < 3; ++a) {
+        if (a < t.D) {
+            lo[a] = (bt[a] < bs[a] ? bt[a] : bs[a]) * t.leaf;
+            int hi = ((bt[a] > bs[a] ? bt[a] : bs[a]) + 1) * t.leaf + 1;
+            hi = hi < t.n[a] ? hi : t.n[a];
+            ext[a] = hi - lo[a];
+        } else {
+            lo[a] = 0;
+            ext[a] = 1;
+        }
+    }
+    const int nst = ext[0] * ext[1] * ext[2];
+    for (int e = threadIdx.x; e < nst; e += kNearLdsThreads) {
+        const int x0 = e % ext[0], x1 = (e / ext[0]) % ext[1], x2 = e / (ext[0] * ext[1]);
+        sl[e] = st[(lo[0] + x0) + (long)g.n0 * ((lo[1] + x1) + (long)g.n1 * (lo[2] + x2))];
+    }
+    __syncthreads();
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const int dd0 = n[0] > 1 ? 1 : 0;
+    const int dd1 = n[1] > 1 ? ext[0] : 0;
+    const int dd2 = (g.dim > 2 && n[2] > 1) ? ext[0] * ext[1] : 0;
+    const double inv_h = 1.0 / g.h;
+    const bool d3 = t.D > 2;
+    // An axis of one cell (or the third axis in 2D) takes k = 0, t = 0 and a zero
+    // corner offset: its terms add exact zeros, so a 2D value is sigma_at's c0.
+    const double hiA[3] = {double(n[0] - 1), double(n[1] - 1), double(n[2] - 1)};
+    const double kmA[3] = {double(n[0] > 1 ? n[0] - 2 : 0), double(n[1] > 1 ? n[1] - 2 : 0),
+                           double(n[2] > 1 ? n[2] - 2 : 0)};
+    const double lod[3] = {double(lo[0]), double(lo[1]), double(lo[2])};
+    const double ex0 = double(ext[0]), ex1 = double(ext[1]);
+    uint16_t* bo = blk + (u - u0) * per;
+    int16_t* lp = lo_plane + (u - u0) * per;
+    for (long i = threadIdx.x; i < per; i += kNearLdsThreads) {
+        const int si = (int)(i / t.S), ti = (int)(i % t.S);
+        double v = 0.0;
+        int ct[3], cs[3];
+        const long jt = slot_cell(t, (long)ua[u] * t.S + ti, ct);
+        const long js = slot_cell(t, (long)ub[u] * t.S + si, cs);
+        if (jt >= 0 && js >= 0 && jt != js) {
+            int K = 0;
+            for (int a = 0; a < 3; ++a) K += (ct[a] - cs[a]) * (ct[a] - cs[a]);
+            const double r = g.h * sqrt((double)K);
+            const int* pa = (jt < js) ? ct : cs;
+            const int* pb = (jt < js) ? cs : ct;
+            const double a0 = g.h * (pa[0] + 0.5), a1 = g.h * (pa[1] + 0.5), a2 = d3 ? g.h * (pa[2] + 0.5) : 0.0;
+            const double e0 = g.h * (pb[0] + 0.5) - a0, e1 = g.h * (pb[1] + 0.5) - a1;
+            const double e2 = (d3 ? g.h * (pb[2] + 0.5) : 0.0) - a2;
+            const int m = steps_grid(K);
+            const double inv_m = 1.0 / double(m);
+            double s = 0.0;
+            for (int q = 1; q <= m; ++q) {
+                const double f = (double(q) - 0.5) * inv_m;
+                const double u0 = fmin(fmax((a0 + f * e0) * inv_h - 0.5, 0.0), hiA[0]);
+                const double u1 = fmin(fmax((a1 + f * e1) * inv_h - 0.5, 0.0), hiA[1]);
+                const double u2 = fmin(fmax((a2 + f * e2) * inv_h - 0.5, 0.0), hiA[2]);
+                const double k0 = fmin(floor(u0), kmA[0]), k1 = fmin(floor(u1), kmA[1]);
+                const double k2 = fmin(floor(u2), kmA[2]);
+                const double t0 = u0 - k0, t1 = u1 - k1, t2 = u2 - k2;
+                const int b0 = (int)fma(ex0, fma(ex1, k2 - lod[2], k1 - lod[1]), k0 - lod[0]);
+                double c00 = sl[b0] + t0 * (sl[b0 + dd0] - sl[b0]);
+                double c10 = sl[b0 + dd1] + t0 * (sl[b0 + dd1 + dd0] - sl[b0 + dd1]);
+                double c0 = c00 + t1 * (c10 - c00);
+                double c01 = sl[b0 + dd2] + t0 * (sl[b0 + dd2 + dd0] - sl[b0 + dd2]);
+                double c11 = sl[b0 + dd2 + dd1] + t0 * (sl[b0 + dd2 + dd1 + dd0] - sl[b0 + dd2 + dd1]);
+                double c1 = c01 + t1 * (c11 - c01);
+                s += c0 + t2 * (c1 - c0);
+            }
+            const double tau = r * inv_m * s;
+            if (itab) {
+                const int o0 = abs(ct[0] - cs[0]), o1 = abs(ct[1] - cs[1]), o2 = abs(ct[2] - cs[2]);
+                const double hp = (t.D == 2) ? g.h : g.h * g.h;
+                v = exp(-tau) * itab[o0 + (long)g.n0 * (o1 + (long)g.n1 * o2)] / (surface_area(t.D) * hp);
+            } else {
+                const double rp = (t.D == 2) ? r : r * r;
+                v = exp(-tau) / (surface_area(t.D) * rp);
+            }
+        }
+        const unsigned X = __float_as_uint((float)v);
+        const unsigned hi = (X + 0x8000u) >> 16;
+        bo[i] = (uint16_t)hi;
+        lp[i] = (int16_t)(int)(X - (hi << 16));
+    }
 }
 
 // ----------------------------------------------- far-field operators ----
@@ -739,12 +861,20 @@ __global__ void k_ops_hom(int D, int nc, int K, int Kp, double w, double sigma, 
     }
 }
 
+// Coordinate of Chebyshev node value c in the box of index b (width w), written
+// as one fused product so that every kernel building a matrix entry rounds it
+// the same way.
+__device__ __forceinline__ double node_coord(double w, int b, double c)
+{
+    return fma(w, double(b) + 0.5, (0.5 * w) * c);
+}
+
 // Heterogeneous translation matrices, one per stored (target, source) pair of a
 // level, stored source-node major: opsT[pair][c][r] (opsT points at pair p0).  Midpoint ray rule with
 // step <= h/2 between the Chebyshev nodes (FP64 arithmetic).  The rule samples the
 // same points from either end, so the matrix of (source, target) is the transpose.
 template <typename T>
-__global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, int K, int Kp, double w,
+__global__ void k_ops_het(Geo g, const double* __restrict__ st8, int D, int nc, int K, int Kp, double w,
                           int nl0, int nl1, int nl2, const double* __restrict__ cheb, const int* __restrict__ pair_t,
                           const int* __restrict__ pair_s, long p0, long np, T* __restrict__ opsT, int mii)
 {
@@ -765,14 +895,14 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, i
         double X[3] = {0, 0, 0}, Y[3] = {0, 0, 0};
         double r2 = 0.0;
         for (int a = 0; a < D; ++a) {
-            X[a] = w * (tb[a] + 0.5) + 0.5 * w * cheb[mr[a]];
-            Y[a] = w * (sb[a] + 0.5) + 0.5 * w * cheb[mc[a]];
-            r2 += (Y[a] - X[a]) * (Y[a] - X[a]);
+            X[a] = node_coord(w, tb[a], cheb[mr[a]]);
+            Y[a] = node_coord(w, sb[a], cheb[mc[a]]);
+            r2 = fma(Y[a] - X[a], Y[a] - X[a], r2);
         }
         double rr = sqrt(r2);
         double q = ceil(rr / (0.5 * g.h));
         int m = q < 1.0 ? 1 : (int)q;
-        double tau = tau_march<double>(st, g, 1.0 / g.h, X[0], X[1], X[2], Y[0], Y[1], Y[2], m, rr);
+        double tau = tau_march8(st8, g, 1.0 / g.h, X[0], X[1], X[2], Y[0], Y[1], Y[2], m, rr);
         if (mii) {
             const double hp = (D == 2) ? g.h : g.h * g.h;
             v = exp(-tau) * cell_int(D, (Y[0] - X[0]) / g.h, (Y[1] - X[1]) / g.h, (Y[2] - X[2]) / g.h, 64.0) /
@@ -785,6 +915,184 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st, int D, int nc, i
     opsT[i] = T(v);
 }
 
+
+// The same matrices (3D, every grid side > 1) with sigma_t read from LDS.  A
+// workgroup takes kOpsLdsRays x kOpsLdsThreads entries of one pair and marches
+// them window by window in the ray parameter: window w holds, for a ray of m
+// steps, the samples q in (w m / nwin, (w + 1) m / nwin].  Their points lie in
+// the box swept by (1 - f) A + f B for f in [w / nwin - 1/(2m), (w + 1) / nwin]
+// (A, B the two boxes; the shift below w / nwin is at most half a step, a
+// quarter cell), so sigma_t over that box plus one cell of margin on each side
+// is staged before the window.  Each ray keeps its running sum across windows:
+// the samples are added in the order q = 1 .. m and every value matches
+// k_ops_het bit for bit.  A window whose box exceeds the LDS capacity reads
+// the corner-octet table instead.
+constexpr int kOpsLdsThreads = 512;
+constexpr int kOpsLdsRays = 2;
+constexpr int kOpsLdsCap = 6144;  // doubles (48 KB)
+
+template <typename T>
+__global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
+    Geo g, const double* __restrict__ st, const double* __restrict__ st8, int nc, int K, int Kp, double w, int nl0,
+    int nl1, int nl2, const double* __restrict__ cheb, const int* __restrict__ pair_t, const int* __restrict__ pair_s,
+    long p0, int ngroup, int nwin, T* __restrict__ opsT, int mii)
+{
+    constexpr int R = kOpsLdsRays;
+    __shared__ double sl[kOpsLdsCap];
+    const long pl = blockIdx.x / ngroup;
+    const long p = p0 + pl;
+    const int gi = (int)(blockIdx.x - pl * ngroup);
+    const int per = Kp * Kp;
+    const int nl[3] = {nl0, nl1, nl2};
+    int tb[3], sb[3];
+    unravel3(pair_t[p], nl, tb);
+    unravel3(pair_s[p], nl, sb);
+    const double inv_h = 1.0 / g.h;
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const double hi0 = double(n[0] - 1), hi1 = double(n[1] - 1), hi2 = double(n[2] - 1);
+    const double km0 = double(n[0] - 2), km1 = double(n[1] - 2), km2 = double(n[2] - 2);
+
+    double ra[R][3], re[R][3], rinv[R], rs[R], rlen[R], r2s[R];
+    int rm[R], ri[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int e = gi * (R * kOpsLdsThreads) + j * kOpsLdsThreads + (int)threadIdx.x;
+        ri[j] = e;
+        rm[j] = 0;
+        rs[j] = 0.0;
+        rinv[j] = 1.0;
+        rlen[j] = 0.0;
+        r2s[j] = 0.0;
+        for (int a = 0; a < 3; ++a) ra[j][a] = re[j][a] = 0.0;
+        const int c = e / Kp, r = e - (e / Kp) * Kp;
+        if (e < per && r < K && c < K) {
+            int mr[3], mc[3];
+            node_multi(r, nc, 3, mr);
+            node_multi(c, nc, 3, mc);
+            double X[3], Y[3], r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                X[a] = node_coord(w, tb[a], cheb[mr[a]]);
+                Y[a] = node_coord(w, sb[a], cheb[mc[a]]);
+                r2 = fma(Y[a] - X[a], Y[a] - X[a], r2);
+            }
+            const double rr = sqrt(r2);
+            const double q = ceil(rr / (0.5 * g.h));
+            const int m = q < 1.0 ? 1 : (int)q;
+            for (int a = 0; a < 3; ++a) {
+                ra[j][a] = X[a];
+                re[j][a] = Y[a] - X[a];
+            }
+            rm[j] = m;
+            rinv[j] = 1.0 / double(m);
+            rlen[j] = rr;
+            r2s[j] = r2;
+        }
+    }
+
+    const double2* q8 = reinterpret_cast<const double2*>(st8);
+    for (int wi = 0; wi < nwin; ++wi) {
+        const double F0 = double(wi) / nwin, F1 = double(wi + 1) / nwin;
+        int kmin[3], ext[3];
+        for (int a = 0; a < 3; ++a) {
+            const double Al = w * tb[a], d = w * (sb[a] - tb[a]);
+            const double l0 = Al + F0 * d, l1 = Al + F1 * d;
+            const double lo_pos = l0 < l1 ? l0 : l1;
+            const double hi_pos = (l0 > l1 ? l0 : l1) + w;
+            int k0 = (int)floor(lo_pos * inv_h - 0.5) - 1;
+            int k1 = (int)floor(hi_pos * inv_h - 0.5) + 2;
+            k0 = k0 < 0 ? 0 : (k0 > n[a] - 2 ? n[a] - 2 : k0);
+            k1 = k1 > n[a] - 1 ? n[a] - 1 : k1;
+            k1 = k1 < k0 + 1 ? k0 + 1 : k1;
+            kmin[a] = k0;
+            ext[a] = k1 - k0 + 1;
+        }
+        const int nst = ext[0] * ext[1] * ext[2];
+        const bool lds = nst <= kOpsLdsCap;
+        __syncthreads();  // the previous window's reads are done
+        if (lds) {
+            for (int e = threadIdx.x; e < nst; e += kOpsLdsThreads) {
+                const int x0 = e % ext[0], x1 = (e / ext[0]) % ext[1], x2 = e / (ext[0] * ext[1]);
+                sl[e] = st[(kmin[0] + x0) + (long)n[0] * ((kmin[1] + x1) + (long)n[1] * (kmin[2] + x2))];
+            }
+        }
+        __syncthreads();
+        const double lo0 = double(kmin[0]), lo1 = double(kmin[1]), lo2 = double(kmin[2]);
+        const double ex0 = double(ext[0]), ex1 = double(ext[1]);
+        const int dd1 = ext[0], dd2 = ext[0] * ext[1];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int m = rm[j];
+            const int qa = (wi * m) / nwin + 1, qb = ((wi + 1) * m) / nwin;
+            double s = rs[j];
+            for (int q = qa; q <= qb; ++q) {
+                const double f = (double(q) - 0.5) * rinv[j];
+                const double u0 = fmin(fmax((ra[j][0] + f * re[j][0]) * inv_h - 0.5, 0.0), hi0);
+                const double u1 = fmin(fmax((ra[j][1] + f * re[j][1]) * inv_h - 0.5, 0.0), hi1);
+                const double u2 = fmin(fmax((ra[j][2] + f * re[j][2]) * inv_h - 0.5, 0.0), hi2);
+                const double k0 = fmin(floor(u0), km0), k1 = fmin(floor(u1), km1), k2 = fmin(floor(u2), km2);
+                const double t0 = u0 - k0, t1 = u1 - k1, t2 = u2 - k2;
+                double v[8];
+                if (lds) {
+                    const int b0 = (int)fma(ex0, fma(ex1, k2 - lo2, k1 - lo1), k0 - lo0);
+                    v[0] = sl[b0];
+                    v[1] = sl[b0 + 1];
+                    v[2] = sl[b0 + dd1];
+                    v[3] = sl[b0 + dd1 + 1];
+                    v[4] = sl[b0 + dd2];
+                    v[5] = sl[b0 + dd2 + 1];
+                    v[6] = sl[b0 + dd2 + dd1];
+                    v[7] = sl[b0 + dd2 + dd1 + 1];
+                } else {
+                    const unsigned cc = (unsigned)fma(double(n[0]), fma(double(n[1]), k2, k1), k0);
+                    const double2* pq = q8 + 4 * (size_t)cc;
+                    for (int x = 0; x < 4; ++x) {
+                        const double2 d = pq[x];
+                        v[2 * x] = d.x;
+                        v[2 * x + 1] = d.y;
+                    }
+                }
+                double c00 = v[0] + t0 * (v[1] - v[0]);
+                double c10 = v[2] + t0 * (v[3] - v[2]);
+                double c0 = c00 + t1 * (c10 - c00);
+                double c01 = v[4] + t0 * (v[5] - v[4]);
+                double c11 = v[6] + t0 * (v[7] - v[6]);
+                double c1 = c01 + t1 * (c11 - c01);
+                s += c0 + t2 * (c1 - c0);
+            }
+            rs[j] = s;
+        }
+    }
+
+    T* out = opsT + pl * (long)per;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int e = ri[j];
+        if (e >= per) continue;
+        double v = 0.0;
+        if (rm[j] > 0) {
+            const double tau = rlen[j] * rinv[j] * rs[j];
+            if (mii) {
+                const double hp = g.h * g.h;
+                v = exp(-tau) * cell_int(3, re[j][0] / g.h, re[j][1] / g.h, re[j][2] / g.h, 64.0) /
+                    (surface_area(3) * hp);
+            } else {
+                v = exp(-tau) / (surface_area(3) * r2s[j]);
+            }
+        }
+        out[e] = T(v);
+    }
+}
+
+// Windows per pair for k_ops_het_lds at box width w (in cells): the fewest whose
+// boxes fit the LDS capacity for offsets up to 3 boxes; 0 when none up to 32 do.
+inline int ops_lds_windows(int wc)
+{
+    for (int nw = 1; nw <= 32; ++nw) {
+        const long side = wc + (3L * wc + nw - 1) / nw + 5;
+        if (side * side * side <= kOpsLdsCap) return nw;
+    }
+    return 0;
+}
 
 // Near-field coupling of two cells of a homogeneous medium at cell offset dv
 // (zero for the self pair, whose term is the diagonal's).
@@ -1443,7 +1751,33 @@ ert_status FmmImpl<T>::setup_far_hom(ert_plan_impl* p, int l, double svd_tol)
 // Heterogeneous far field of level l: the directed interaction-list pairs grouped by
 // target (the staging rows), and one stored matrix per unordered pair {t, s}, t < s,
 // for target t and source s (the transpose serves target s).
-ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb, HetCache* hc, int l)
+// The corner-octet table of the plan's sigma_t, held while the caches are built
+// (8 doubles per cell); the stream is drained before it is released.
+struct CornerTable {
+    double* st8 = nullptr;
+    hipStream_t s = nullptr;
+    ert_status build(ert_plan_impl* p)
+    {
+        s = p->stream;
+        const long n = p->N;
+        if (hipMalloc(&st8, std::max<size_t>(1, (size_t)n * 8 * sizeof(double))) != hipSuccess) {
+            st8 = nullptr;
+            record_error("FMM: sigma_t corner table allocation failed");
+            return ERT_ENOMEM;
+        }
+        hipLaunchKernelGGL(k_corner8, dim3(blocks(n)), dim3(kB), 0, s, p->geo, p->d_st, st8, n);
+        return hipGetLastError() == hipSuccess ? ERT_OK : ERT_EDEVICE;
+    }
+    ~CornerTable()
+    {
+        if (!st8) return;
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(st8);
+    }
+};
+
+ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb, const double* st8, HetCache* hc,
+                         int l)
 {
     hipStream_t s = p->stream;
     const long KpKp = (long)tr.Kp * tr.Kp;
@@ -1513,11 +1847,20 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
         return ERT_ENOMEM;
     }
     const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
+    const Geo& g = p->geo;
+    const int nwin = (tr.D == 3 && g.n0 > 1 && g.n1 > 1 && g.n2 > 1) ? ops_lds_windows(tr.leaf << (tr.L - l)) : 0;
+    const long ngroup = (KpKp + kOpsLdsRays * kOpsLdsThreads - 1) / (kOpsLdsRays * kOpsLdsThreads);
     for (long p0 = 0; p0 < np; p0 += pchunk) {
         long cnt = std::min(pchunk, np - p0);
-        hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, p->geo, p->d_st, tr.D, tr.nc,
-                           tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], p0, cnt,
-                           hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
+        if (nwin > 0) {
+            hipLaunchKernelGGL(k_ops_het_lds<float>, dim3((unsigned)(cnt * ngroup)), dim3(kOpsLdsThreads), 0, s, g,
+                               p->d_st, st8, tr.nc, tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l],
+                               hc->hub[l], p0, (int)ngroup, nwin, hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
+        } else {
+            hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, g, st8, tr.D, tr.nc,
+                               tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], p0, cnt,
+                               hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
+        }
         ERT_HIP(hipGetLastError());
     }
     hc->bytes += bytes;
@@ -1570,10 +1913,10 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
         c->near_ub = other->near_ub;
         c->near_fwd = other->near_fwd;
         c->near_bwd = other->near_bwd;
-        for (int l = 2; l <= tr.L; ++l) {
-            ert_status st = het_far_level(p, tr, cheb, c, l);
-            if (st != ERT_OK) return fail(st);
-        }
+        CornerTable t8;
+        ert_status st = t8.build(p);
+        for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, t8.st8, c, l);
+        if (st != ERT_OK) return fail(st);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(ERT_EDEVICE);
         p->het[slot] = c;
         hc = c;
@@ -1633,16 +1976,30 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     if (st == ERT_OK) st = upload<int>(s, &c->near_ub, ub);
     if (st == ERT_OK) st = upload<long>(s, &c->near_fwd, fwd);
     if (st == ERT_OK) st = upload<long>(s, &c->near_bwd, bwd);
+    CornerTable t8;
+    if (st == ERT_OK) st = t8.build(p);
     if (st != ERT_OK) return fail(st);
-    const long chunk = std::max<long>(1, (1L << 26) / per);
-    for (long u0 = 0; u0 < np; u0 += chunk) {
-        const long cnt = std::min(chunk, np - u0);
-        hipLaunchKernelGGL(k_near_blocks, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, p->d_st, p->d_itab,
-                           c->near_ua, c->near_ub, u0, cnt, c->near_hi + (size_t)u0 * per,
-                           c->near_lo + (size_t)u0 * per);
-        if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
+    if (tr.leaf <= kNearLdsLeaf) {
+        // one workgroup per stored pair, sigma_t of the two leaves in LDS
+        const long chunk = std::max<long>(1, (1L << 28) / per);
+        for (long u0 = 0; u0 < np; u0 += chunk) {
+            const long cnt = std::min(chunk, np - u0);
+            hipLaunchKernelGGL(k_near_blocks_lds, dim3((unsigned)cnt), dim3(kNearLdsThreads), 0, s, dt, p->geo,
+                               p->d_st, p->d_itab, c->near_ua, c->near_ub, u0, c->near_hi + (size_t)u0 * per,
+                               c->near_lo + (size_t)u0 * per);
+            if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
+        }
+    } else {
+        const long chunk = std::max<long>(1, (1L << 26) / per);
+        for (long u0 = 0; u0 < np; u0 += chunk) {
+            const long cnt = std::min(chunk, np - u0);
+            hipLaunchKernelGGL(k_near_blocks, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, t8.st8,
+                               p->d_itab, c->near_ua, c->near_ub, u0, cnt, c->near_hi + (size_t)u0 * per,
+                               c->near_lo + (size_t)u0 * per);
+            if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
+        }
     }
-    for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, c, l);
+    for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, t8.st8, c, l);
     if (st == ERT_OK && hipStreamSynchronize(s) != hipSuccess) st = ERT_EDEVICE;
     if (st != ERT_OK) return fail(st);
     p->het[slot] = c;
