@@ -22,35 +22,49 @@ constexpr int kTile = 256;
 // sigma_at for points inside cell c, reading the cell's 3^3 neighbourhood nb
 // (nb[a0 + 3 a1 + 9 a2] = sigma_t of cell c + a - 1, indices clamped to the grid):
 // every interpolation cell such a point can fall in has its corners there.  The
-// clamp, cell search and interpolation are sigma_at's, so the values agree bit
-// for bit.
-__device__ __forceinline__ double sigma_nb(const double* nb, const Geo& g, double inv_h, const int c[3], double p0,
-                                           double p1, double p2)
+// clamp, cell search and interpolation are sigma_at's, done in FP64 (max, min,
+// floor give the same integers and fractions), so the values agree bit for bit.
+// An axis of one cell (or the third axis in 2D) takes k = 0, t = 0 and a zero
+// corner offset: its terms add exact zeros.
+struct NbAxes {
+    double hi[3], km[3], cl[3];  // n - 1, max(n - 2, 0), c - 1 (inactive axis: 0, 0, -1)
+    int d0, d1, d2;              // corner offsets in nb
+};
+
+__device__ __forceinline__ NbAxes nb_axes(const Geo& g, const int c[3])
 {
     const int n[3] = {g.n0, g.n1, g.n2};
-    const double p[3] = {p0, p1, p2};
-    int l[3] = {1, 1, 1};  // local index of the lower corner
-    double t[3] = {0.0, 0.0, 0.0};
+    NbAxes A;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (a < g.dim && n[a] > 1) {
-            double u = p[a] * inv_h - 0.5;
-            double hi = double(n[a] - 1);
-            u = u < 0.0 ? 0.0 : (u > hi ? hi : u);
-            int k = (int)floor(u);
-            k = k > n[a] - 2 ? n[a] - 2 : k;
-            l[a] = k - c[a] + 1;
-            t[a] = u - double(k);
-        }
+        const bool on = a < g.dim && n[a] > 1;
+        A.hi[a] = on ? double(n[a] - 1) : 0.0;
+        A.km[a] = on ? double(n[a] - 2) : 0.0;
+        A.cl[a] = on ? double(c[a] - 1) : -1.0;
     }
-    const int b0 = l[0] + 3 * (l[1] + 3 * l[2]);
-    const int d0 = n[0] > 1 ? 1 : 0;
-    const int d1 = n[1] > 1 ? 3 : 0;
-    const int d2 = (g.dim > 2 && n[2] > 1) ? 9 : 0;
+    A.d0 = n[0] > 1 ? 1 : 0;
+    A.d1 = n[1] > 1 ? 3 : 0;
+    A.d2 = (g.dim > 2 && n[2] > 1) ? 9 : 0;
+    return A;
+}
+
+__device__ __forceinline__ double sigma_nb(const double* nb, const NbAxes& A, double inv_h, double p0, double p1,
+                                           double p2)
+{
+    const double p[3] = {p0, p1, p2};
+    double t[3], l[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double u = fmin(fmax(p[a] * inv_h - 0.5, 0.0), A.hi[a]);
+        const double k = fmin(floor(u), A.km[a]);
+        t[a] = u - k;
+        l[a] = k - A.cl[a];
+    }
+    const int b0 = (int)fma(9.0, l[2], fma(3.0, l[1], l[0]));
+    const int d0 = A.d0, d1 = A.d1, d2 = A.d2;
     double c00 = nb[b0] + t[0] * (nb[b0 + d0] - nb[b0]);
     double c10 = nb[b0 + d1] + t[0] * (nb[b0 + d1 + d0] - nb[b0 + d1]);
     double c0 = c00 + t[1] * (c10 - c00);
-    if (g.dim == 2) return c0;
     double c01 = nb[b0 + d2] + t[0] * (nb[b0 + d2 + d0] - nb[b0 + d2]);
     double c11 = nb[b0 + d2 + d1] + t[0] * (nb[b0 + d2 + d1 + d0] - nb[b0 + d2 + d1]);
     double c1 = c01 + t[1] * (c11 - c01);
@@ -60,7 +74,7 @@ __device__ __forceinline__ double sigma_nb(const double* nb, const Geo& g, doubl
 // integral_0^rho E(x, x + r v) dr (same step rule as the off-diagonal kernel:
 // one midpoint step for r <= h/2, two beyond; rho < h always).  Every sample
 // lies in the cell of x, whose neighbourhood nb holds sigma_t.
-__device__ double radial_integral(const Geo& g, int ray, double sigma, const double* nb, const int cell[3],
+__device__ double radial_integral(const Geo& g, int ray, double sigma, const double* nb, const NbAxes& A,
                                   const double x[3], const double v[3], double rho,
                                   const double* __restrict__ rx, const double* __restrict__ rw, int nrad)
 {
@@ -73,7 +87,7 @@ __device__ double radial_integral(const Geo& g, int ray, double sigma, const dou
     double b0 = rho < half ? rho : half;
     for (int q = 0; q < nrad; ++q) {
         double r = 0.5 * b0 * (rx[q] + 1.0);
-        double s = sigma_nb(nb, g, inv_h, cell, x[0] + 0.5 * r * v[0], x[1] + 0.5 * r * v[1],
+        double s = sigma_nb(nb, A, inv_h, x[0] + 0.5 * r * v[0], x[1] + 0.5 * r * v[1],
                                     x[2] + 0.5 * r * v[2]);
         acc += 0.5 * b0 * rw[q] * exp(-r * s);
     }
@@ -81,9 +95,9 @@ __device__ double radial_integral(const Geo& g, int ray, double sigma, const dou
         double len = rho - half;
         for (int q = 0; q < nrad; ++q) {
             double r = half + 0.5 * len * (rx[q] + 1.0);
-            double s1 = sigma_nb(nb, g, inv_h, cell, x[0] + 0.25 * r * v[0], x[1] + 0.25 * r * v[1],
+            double s1 = sigma_nb(nb, A, inv_h, x[0] + 0.25 * r * v[0], x[1] + 0.25 * r * v[1],
                                          x[2] + 0.25 * r * v[2]);
-            double s2 = sigma_nb(nb, g, inv_h, cell, x[0] + 0.75 * r * v[0], x[1] + 0.75 * r * v[1],
+            double s2 = sigma_nb(nb, A, inv_h, x[0] + 0.75 * r * v[0], x[1] + 0.75 * r * v[1],
                                          x[2] + 0.75 * r * v[2]);
             acc += 0.5 * len * rw[q] * exp(-0.5 * r * (s1 + s2));
         }
@@ -118,6 +132,7 @@ __global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, 
         nb[threadIdx.x] = st[q[0] + (long)g.n0 * (q[1] + (long)g.n1 * q[2])];
     }
     __syncthreads();
+    const NbAxes A = nb_axes(g, cell);
     const double half = 0.5 * g.h;
     const double x[3] = {g.h * (i0 + 0.5), g.h * (i1 + 0.5), g.dim > 2 ? g.h * (i2 + 0.5) : 0.0};
     double acc = 0.0;
@@ -129,7 +144,7 @@ __global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, 
             double th = t0 + (kPi / 8.0) * (ax[q] + 1.0);
             double v[3] = {cos(th), sin(th), 0.0};
             double c = fabs(v[0]) > fabs(v[1]) ? fabs(v[0]) : fabs(v[1]);
-            acc += (kPi / 8.0) * aw[q] * radial_integral(g, ray, sigma, nb, cell, x, v, half / c, rx, rw, nrad);
+            acc += (kPi / 8.0) * aw[q] * radial_integral(g, ray, sigma, nb, A, x, v, half / c, rx, rw, nrad);
         }
     } else {
         const int per = nang * nang;
@@ -146,7 +161,7 @@ __global__ __launch_bounds__(256) void k_selfcell(Geo g, int ray, double sigma, 
             v[(axis + 1) % 3] = u / R;
             v[(axis + 2) % 3] = w / R;
             double wq = 0.25 * half * half * aw[qa] * aw[qb] * half / (R * R * R);
-            acc += wq * radial_integral(g, ray, sigma, nb, cell, x, v, R, rx, rw, nrad);
+            acc += wq * radial_integral(g, ray, sigma, nb, A, x, v, R, rx, rw, nrad);
         }
     }
     red[threadIdx.x] = acc;

@@ -653,113 +653,81 @@ __global__ void k_corner8(Geo g, const double* __restrict__ st, double* __restri
 
 // Cached near-field blocks for the ray kernel, FP64 arithmetic: the same rule
 // as the dense apply (exact integer step count, marched from the lower index,
-// so the value of a cell pair does not depend on its order).  One block per
-// stored pair u (blocks u0 .. u0 + nu - 1; blk and lo_plane point at block u0):
-// element [si][ti] = G(cell ti of leaf ua[u], cell si of leaf ub[u]), zero for a
-// cell with itself (the diagonal's term).  FP32 values as a BF16-rounded high
-// plane and the exact remainder.
-__global__ void k_near_blocks(DevTree t, Geo g, const double* __restrict__ st8, const double* __restrict__ itab,
-                              const int* __restrict__ ua, const int* __restrict__ ub, long u0, long nu,
-                              uint16_t* __restrict__ blk, int16_t* __restrict__ lo_plane)
-{
-    const long per = (long)t.S * t.S;
-    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i >= nu * per) return;
-    const long u = u0 + i / per;
-    long rem = i % per;
-    const int si = (int)(rem / t.S), ti = (int)(rem % t.S);
-    double v = 0.0;
-    int ct[3], cs[3];
-    const long jt = slot_cell(t, (long)ua[u] * t.S + ti, ct);
-    const long js = slot_cell(t, (long)ub[u] * t.S + si, cs);
-    if (jt >= 0 && js >= 0 && jt != js) {
-        int K = 0;
-        for (int a = 0; a < 3; ++a) K += (ct[a] - cs[a]) * (ct[a] - cs[a]);
-        const double r = g.h * sqrt((double)K);
-        const int* lo = (jt < js) ? ct : cs;
-        const int* hi = (jt < js) ? cs : ct;
-        const double inv_h = 1.0 / g.h;
-        const bool d3 = t.D > 2;
-        double tau = tau_march8(st8, g, inv_h, g.h * (lo[0] + 0.5), g.h * (lo[1] + 0.5),
-                                d3 ? g.h * (lo[2] + 0.5) : 0.0, g.h * (hi[0] + 0.5), g.h * (hi[1] + 0.5),
-                                d3 ? g.h * (hi[2] + 0.5) : 0.0, steps_grid(K), r);
-        if (itab) {
-            // (M-ii): cell integral at the integer offset, per unit cell, over h^{d-1}
-            const int a0 = abs(ct[0] - cs[0]), a1 = abs(ct[1] - cs[1]), a2 = abs(ct[2] - cs[2]);
-            const double hp = (t.D == 2) ? g.h : g.h * g.h;
-            v = exp(-tau) * itab[a0 + (long)g.n0 * (a1 + (long)g.n1 * a2)] / (surface_area(t.D) * hp);
-        } else {
-            const double rp = (t.D == 2) ? r : r * r;
-            v = exp(-tau) / (surface_area(t.D) * rp);
-        }
-    }
-    // FP32 value X as the high half rounded to BF16 and the exact signed remainder:
-    // X = (hi << 16) + lo, lo in [-2^15, 2^15) (values are >= 0)
-    const unsigned X = __float_as_uint((float)v);
-    const unsigned hi = (X + 0x8000u) >> 16;
-    blk[i] = (uint16_t)hi;
-    lo_plane[i] = (int16_t)(int)(X - (hi << 16));
-}
-
-// The same blocks with one workgroup per stored pair: sigma_t over the cells
-// spanned by the two leaves, plus one layer above (the upper corner of a
-// sample on the top face), is staged in LDS, and the march reads it there.
-// Samples lie between the two cell centres, so every corner they need is in
-// the box; cell search and interpolation are sigma_at's, so the blocks agree
-// bit for bit with k_near_blocks.  Needs leaf <= kNearLdsLeaf.
+// so the value of a cell pair does not depend on its order).  One workgroup per
+// stored pair u (blocks u0 .. ; blk and lo_plane point at block u0): element
+// [si][ti] = G(cell ti of leaf ua[u], cell si of leaf ub[u]), zero for a cell
+// with itself (the diagonal's term).  FP32 values as a BF16-rounded high plane
+// and the exact remainder.  sigma_t over the cells spanned by the two leaves,
+// plus one layer above (the upper corner of a sample on the top face), is
+// staged in LDS and the march reads it there: samples lie between the two cell
+// centres, so every corner they need is in the box.  Cell search and
+// interpolation are sigma_at's, term for term.  Leaves have at most
+// kNearLdsLeaf cells per side (the plan's limit).
 constexpr int kNearLdsLeaf = 8;
 constexpr int kNearLdsSide = 2 * kNearLdsLeaf + 1;
 constexpr int kNearLdsThreads = 512;
 
-__global__ __launch_bounds__(kNearLdsThreads) void k_near_blocks_lds(
+__global__ __launch_bounds__(kNearLdsThreads) void k_near_blocks(
     DevTree t, Geo g, const double* __restrict__ st, const double* __restrict__ itab, const int* __restrict__ ua,
     const int* __restrict__ ub, long u0, uint16_t* __restrict__ blk, int16_t* __restrict__ lo_plane)
 {
-    __shared__ double sl[kNearLdsSide * kNearLdsSide * kNearLdsSide];
+    constexpr int P = kNearLdsSide;  // LDS pitch of a row and (P * P) of a plane
+    __shared__ double sl[P * P * P];
     const long u = u0 + blockIdx.x;
-    const long per = (long)t.S * t.S;
+    const int per = t.S * t.S;
+    const int n[3] = {g.n0, g.n1, g.n2};
     int bt[3], bs[3], lo[3], ext[3];
     unravel3(ua[u], t.nb, bt);
     unravel3(ub[u], t.nb, bs);
     for (int a = 0; a < 3; ++a) {
         if (a < t.D) {
-            lo[a] = (bt[a] < bs[a] ? bt[a] : bs[a]) * t.leaf;
+            // lowest cell: the leaves' first, or n - 2 when the clamped search
+            // (k <= n - 2) reaches below a one-cell leaf on the top face
+            int l0 = (bt[a] < bs[a] ? bt[a] : bs[a]) * t.leaf;
+            l0 = (n[a] > 1 && l0 > n[a] - 2) ? n[a] - 2 : l0;
             int hi = ((bt[a] > bs[a] ? bt[a] : bs[a]) + 1) * t.leaf + 1;
-            hi = hi < t.n[a] ? hi : t.n[a];
-            ext[a] = hi - lo[a];
+            hi = hi < n[a] ? hi : n[a];
+            lo[a] = l0;
+            ext[a] = hi - l0;
         } else {
             lo[a] = 0;
             ext[a] = 1;
         }
     }
-    const int nst = ext[0] * ext[1] * ext[2];
-    for (int e = threadIdx.x; e < nst; e += kNearLdsThreads) {
-        const int x0 = e % ext[0], x1 = (e / ext[0]) % ext[1], x2 = e / (ext[0] * ext[1]);
-        sl[e] = st[(lo[0] + x0) + (long)g.n0 * ((lo[1] + x1) + (long)g.n1 * (lo[2] + x2))];
+    // staged box: at least two layers per axis (an axis of one cell repeats it,
+    // so its upper corner reads the same value as sigma_at's zero offset)
+    const int sx0 = ext[0] > 1 ? ext[0] : 2, sx1 = ext[1] > 1 ? ext[1] : 2, sx2 = ext[2] > 1 ? ext[2] : 2;
+    for (int e = threadIdx.x; e < sx0 * sx1 * sx2; e += kNearLdsThreads) {
+        const int x0 = e % sx0, x1 = (e / sx0) % sx1, x2 = e / (sx0 * sx1);
+        const int c0 = lo[0] + (x0 < ext[0] ? x0 : ext[0] - 1), c1 = lo[1] + (x1 < ext[1] ? x1 : ext[1] - 1);
+        const int c2 = lo[2] + (x2 < ext[2] ? x2 : ext[2] - 1);
+        sl[x0 + P * (x1 + P * x2)] = st[c0 + (long)g.n0 * (c1 + (long)g.n1 * c2)];
     }
     __syncthreads();
-    const int n[3] = {g.n0, g.n1, g.n2};
-    const int dd0 = n[0] > 1 ? 1 : 0;
-    const int dd1 = n[1] > 1 ? ext[0] : 0;
-    const int dd2 = (g.dim > 2 && n[2] > 1) ? ext[0] * ext[1] : 0;
     const double inv_h = 1.0 / g.h;
     const bool d3 = t.D > 2;
-    // An axis of one cell (or the third axis in 2D) takes k = 0, t = 0 and a zero
-    // corner offset: its terms add exact zeros, so a 2D value is sigma_at's c0.
+    // An axis of one cell (or the third axis in 2D) takes k = 0 and t = 0: its
+    // terms add exact zeros, so a 2D value is sigma_at's c0.
     const double hiA[3] = {double(n[0] - 1), double(n[1] - 1), double(n[2] - 1)};
     const double kmA[3] = {double(n[0] > 1 ? n[0] - 2 : 0), double(n[1] > 1 ? n[1] - 2 : 0),
                            double(n[2] > 1 ? n[2] - 2 : 0)};
-    const double lod[3] = {double(lo[0]), double(lo[1]), double(lo[2])};
-    const double ex0 = double(ext[0]), ex1 = double(ext[1]);
-    uint16_t* bo = blk + (u - u0) * per;
-    int16_t* lp = lo_plane + (u - u0) * per;
-    for (long i = threadIdx.x; i < per; i += kNearLdsThreads) {
-        const int si = (int)(i / t.S), ti = (int)(i % t.S);
+    const double off = fma(double(P * P), double(lo[2]), fma(double(P), double(lo[1]), double(lo[0])));
+    const int L = t.leaf, L1 = t.D > 1 ? t.leaf : 1;
+    uint16_t* bo = blk + (u - u0) * (long)per;
+    int16_t* lp = lo_plane + (u - u0) * (long)per;
+    for (int i = threadIdx.x; i < per; i += kNearLdsThreads) {
+        const int si = i / t.S, ti = i - (i / t.S) * t.S;
         double v = 0.0;
-        int ct[3], cs[3];
-        const long jt = slot_cell(t, (long)ua[u] * t.S + ti, ct);
-        const long js = slot_cell(t, (long)ub[u] * t.S + si, cs);
-        if (jt >= 0 && js >= 0 && jt != js) {
+        // cells of slot ti of the target leaf and slot si of the source leaf
+        const int ct[3] = {bt[0] * L + ti % L, t.D > 1 ? bt[1] * L + (ti / L) % L1 : 0,
+                           t.D > 2 ? bt[2] * L + ti / (L * L1) : 0};
+        const int cs[3] = {bs[0] * L + si % L, t.D > 1 ? bs[1] * L + (si / L) % L1 : 0,
+                           t.D > 2 ? bs[2] * L + si / (L * L1) : 0};
+        const bool in = ct[0] < n[0] && ct[1] < n[1] && ct[2] < n[2] && cs[0] < n[0] && cs[1] < n[1] &&
+                        cs[2] < n[2];
+        const long jt = ct[0] + (long)n[0] * (ct[1] + (long)n[1] * ct[2]);
+        const long js = cs[0] + (long)n[0] * (cs[1] + (long)n[1] * cs[2]);
+        if (in && jt != js) {
             int K = 0;
             for (int a = 0; a < 3; ++a) K += (ct[a] - cs[a]) * (ct[a] - cs[a]);
             const double r = g.h * sqrt((double)K);
@@ -779,12 +747,12 @@ __global__ __launch_bounds__(kNearLdsThreads) void k_near_blocks_lds(
                 const double k0 = fmin(floor(u0), kmA[0]), k1 = fmin(floor(u1), kmA[1]);
                 const double k2 = fmin(floor(u2), kmA[2]);
                 const double t0 = u0 - k0, t1 = u1 - k1, t2 = u2 - k2;
-                const int b0 = (int)fma(ex0, fma(ex1, k2 - lod[2], k1 - lod[1]), k0 - lod[0]);
-                double c00 = sl[b0] + t0 * (sl[b0 + dd0] - sl[b0]);
-                double c10 = sl[b0 + dd1] + t0 * (sl[b0 + dd1 + dd0] - sl[b0 + dd1]);
+                const double* c = sl + (int)(fma(double(P * P), k2, fma(double(P), k1, k0)) - off);
+                double c00 = c[0] + t0 * (c[1] - c[0]);
+                double c10 = c[P] + t0 * (c[P + 1] - c[P]);
                 double c0 = c00 + t1 * (c10 - c00);
-                double c01 = sl[b0 + dd2] + t0 * (sl[b0 + dd2 + dd0] - sl[b0 + dd2]);
-                double c11 = sl[b0 + dd2 + dd1] + t0 * (sl[b0 + dd2 + dd1 + dd0] - sl[b0 + dd2 + dd1]);
+                double c01 = c[P * P] + t0 * (c[P * P + 1] - c[P * P]);
+                double c11 = c[P * P + P] + t0 * (c[P * P + P + 1] - c[P * P + P]);
                 double c1 = c01 + t1 * (c11 - c01);
                 s += c0 + t2 * (c1 - c0);
             }
@@ -1979,25 +1947,17 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     CornerTable t8;
     if (st == ERT_OK) st = t8.build(p);
     if (st != ERT_OK) return fail(st);
-    if (tr.leaf <= kNearLdsLeaf) {
-        // one workgroup per stored pair, sigma_t of the two leaves in LDS
-        const long chunk = std::max<long>(1, (1L << 28) / per);
-        for (long u0 = 0; u0 < np; u0 += chunk) {
-            const long cnt = std::min(chunk, np - u0);
-            hipLaunchKernelGGL(k_near_blocks_lds, dim3((unsigned)cnt), dim3(kNearLdsThreads), 0, s, dt, p->geo,
-                               p->d_st, p->d_itab, c->near_ua, c->near_ub, u0, c->near_hi + (size_t)u0 * per,
-                               c->near_lo + (size_t)u0 * per);
-            if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
-        }
-    } else {
-        const long chunk = std::max<long>(1, (1L << 26) / per);
-        for (long u0 = 0; u0 < np; u0 += chunk) {
-            const long cnt = std::min(chunk, np - u0);
-            hipLaunchKernelGGL(k_near_blocks, dim3(blocks(cnt * per)), dim3(kB), 0, s, dt, p->geo, t8.st8,
-                               p->d_itab, c->near_ua, c->near_ub, u0, cnt, c->near_hi + (size_t)u0 * per,
-                               c->near_lo + (size_t)u0 * per);
-            if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
-        }
+    if (tr.leaf > kNearLdsLeaf) {
+        record_error("FMM: leaf larger than the near-field block kernel supports");
+        return fail(ERT_EINVAL);
+    }
+    const long chunk = std::max<long>(1, (1L << 28) / per);
+    for (long u0 = 0; u0 < np; u0 += chunk) {
+        const long cnt = std::min(chunk, np - u0);
+        hipLaunchKernelGGL(k_near_blocks, dim3((unsigned)cnt), dim3(kNearLdsThreads), 0, s, dt, p->geo, p->d_st,
+                           p->d_itab, c->near_ua, c->near_ub, u0, c->near_hi + (size_t)u0 * per,
+                           c->near_lo + (size_t)u0 * per);
+        if (hipGetLastError() != hipSuccess) return fail(ERT_EDEVICE);
     }
     for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, t8.st8, c, l);
     if (st == ERT_OK && hipStreamSynchronize(s) != hipSuccess) st = ERT_EDEVICE;

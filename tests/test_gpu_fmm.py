@@ -314,12 +314,14 @@ def test_fmm_heterogeneous_many_rhs_matrix_cores(ev, oracle_mod, prec, nrhs):
     assert rel_l2(Y[:, 3], P.apply(X[:, 3], op=2)) <= 2e-5
 
 
-@pytest.mark.parametrize("n,leaf", [((6, 6, 6), 3), ((10, 9, 7), 5)])
+@pytest.mark.parametrize("n,leaf", [((6, 6, 6), 3), ((10, 9, 7), 5), ((9, 9, 9), 8), ((5, 7, 3), 4)])
 def test_fmm_heterogeneous_odd_leaves_near_only(ev, oracle_mod, n, leaf):
-    """Two leaves per axis, so every pair of leaves is a near pair and the FMM is the
-    dense sum over FP32-stored kernel values: blocks of 27 and 125 points (element-wise
-    loads in the streaming products), FP64 and FP32 applies of 3 right-hand sides against
-    the oracle within the FP32 rounding of the stored values (bar 1e-6)."""
+    """At most two leaves per axis, so every pair of leaves is a near pair and the FMM is
+    the dense sum over FP32-stored kernel values: blocks of 27, 125 and 512 points
+    (element-wise loads in the streaming products), and grids whose last leaf holds one
+    cell along an axis (rays between cells of that layer interpolate from the cell below,
+    outside the leaf); FP64 and FP32 applies of 3 right-hand sides against the oracle
+    within the FP32 rounding of the stored values (bar 1e-6)."""
     case = inputs.make_case("c3", n=n, seed=8)
     P = oracle_problem(oracle_mod, case)
     X = inputs.random_vector(P.N, 18, nrhs=3)
