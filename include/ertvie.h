@@ -143,6 +143,17 @@ typedef struct {
                          the source columns staged in LDS
                          (a form that does not apply to a product leaves it to the timing).
                          Fixed forms make runs reproducible bit for bit across plans */
+    double far_cache_gb; /* heterogeneous media, FMM: device memory, in GB (1e9 bytes), that
+                         the plan's stored far-field translation matrices (of every order the
+                         plan builds) may take; 0 -> 90 % of the device memory free when a level
+                         is built.  A level that does not fit is not stored: every apply
+                         rebuilds its matrices by the same ray march (Sec. 4.2's kernel
+                         evaluations), in chunks of whole box pairs (at most 2 GB, or what is
+                         left of the budget, at least one pair) written to a scratch buffer
+                         and used right away.  The results are those of the stored level bit
+                         for bit; each apply then costs that level's ray marches (seconds at
+                         128^3 instead of milliseconds).  The near-field blocks are always
+                         stored (ERT_ENOMEM when they do not fit).  >= 0 and finite */
 } ert_vie_opts;
 
 typedef struct {
@@ -366,6 +377,12 @@ typedef struct {
                              near-field products read one table of (4 leaf - 1)^dim values over
                              cell offsets (this count) instead of the 3^dim explicit blocks;
                              0 = no table */
+    int far_rebuilt[16];  /* heterogeneous media, per level: 1 when the level's translation
+                             matrices are not stored and every apply rebuilds them
+                             (ert_vie_opts.far_cache_gb) */
+    double cache_bytes;   /* heterogeneous media: device bytes of the kernel caches this
+                             precision's operator uses (near blocks, stored translation
+                             matrices, scratch and corner table of rebuilt levels) */
 } ert_fmm_info;
 
 /* Device timing of applies by stage, with HIP events recorded on the plan's

@@ -535,6 +535,7 @@ ert_status ert_vie_plan(const ert_vie_opts* opts, const double* sigma_t, const d
     if ((o.inner_cheb_n != 0 && (o.inner_cheb_n < 2 || o.inner_cheb_n > 8)) || (o.inner_near16 != 0 && o.inner_near16 != 1)) return ERT_EINVAL;
     for (int i = 0; i < 2; ++i)
         if (o.form[i] < 0 || o.form[i] > 6) return ERT_EINVAL;   // execution forms 0..5, stored as f + 1
+    if (!std::isfinite(o.far_cache_gb) || o.far_cache_gb < 0.0) return ERT_EINVAL;
     long N = 1;
     for (int a = 0; a < o.dim; ++a) {
         if (o.n[a] < 1 || o.n[a] > (1 << 20)) return ERT_EINVAL;

@@ -35,6 +35,8 @@ struct FmmData {
     virtual int rank_of(int l) const = 0;
     virtual int form_of(int site) const = 0;   // site -1: near field, l >= 0: far field of level l
     virtual long near_table() const = 0;       // entries of the near-field offset table, 0 = none
+    virtual bool far_rebuilt(int l) const = 0; // heterogeneous level l rebuilt by every apply
+    virtual double cache_bytes() const = 0;    // device bytes of the heterogeneous caches in use
     virtual ert_status apply(ert_plan_impl* p, int op, const double* x, double* y, int nrhs) = 0;
     virtual ert_status setup(ert_plan_impl* p) = 0;
     FmmTree tr;
@@ -1517,6 +1519,8 @@ struct FmmImpl : FmmData {
     }
 
     int rank_of(int l) const override { return rp[l]; }
+    bool far_rebuilt(int l) const override { return hc && l >= 0 && l <= kMaxLevels && hc->rebuilt[l]; }
+    double cache_bytes() const override { return hc ? (double)hc->bytes : 0.0; }
     long near_table() const override
     {
         const long W = 4L * tr.leaf - 1;
@@ -1736,6 +1740,13 @@ struct CornerTable {
         hipLaunchKernelGGL(k_corner8, dim3(blocks(n)), dim3(kB), 0, s, p->geo, p->d_st, st8, n);
         return hipGetLastError() == hipSuccess ? ERT_OK : ERT_EDEVICE;
     }
+    // hand the table to the caller (levels rebuilt by every apply keep it)
+    double* release()
+    {
+        double* q = st8;
+        st8 = nullptr;
+        return q;
+    }
     ~CornerTable()
     {
         if (!st8) return;
@@ -1743,6 +1754,50 @@ struct CornerTable {
         (void)hipFree(st8);
     }
 };
+
+// Translation matrices of stored pairs p0 .. p0 + cnt - 1 of level l into dst
+// ([cnt][Kp][Kp]): kernel launches on the stream only (also used inside applies
+// for the levels that are rebuilt each time).
+ert_status het_fill(ert_plan_impl* p, hipStream_t s, const FmmTree& tr, const double* cheb, const double* st8,
+                    const HetCache* hc, int l, long p0, long cnt, float* dst)
+{
+    const long KpKp = (long)tr.Kp * tr.Kp;
+    const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
+    const Geo& g = p->geo;
+    const int nl[3] = {tr.nl[l][0], tr.nl[l][1], tr.nl[l][2]};
+    const int nwin = (tr.D == 3 && g.n0 > 1 && g.n1 > 1 && g.n2 > 1) ? ops_lds_windows(tr.leaf << (tr.L - l)) : 0;
+    const long ngroup = (KpKp + kOpsLdsRays * kOpsLdsThreads - 1) / (kOpsLdsRays * kOpsLdsThreads);
+    for (long q0 = p0; q0 < p0 + cnt; q0 += pchunk) {
+        const long c = std::min(pchunk, p0 + cnt - q0);
+        float* out = dst + (size_t)(q0 - p0) * KpKp;
+        if (nwin > 0) {
+            hipLaunchKernelGGL(k_ops_het_lds<float>, dim3((unsigned)(c * ngroup)), dim3(kOpsLdsThreads), 0, s, g,
+                               p->d_st, st8, tr.nc, tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l],
+                               hc->hub[l], q0, (int)ngroup, nwin, out, p->o.scheme);
+        } else {
+            hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(c * KpKp)), dim3(kB), 0, s, g, st8, tr.D, tr.nc, tr.K,
+                               tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], q0, c, out,
+                               p->o.scheme);
+        }
+        ERT_HIP(hipGetLastError());
+    }
+    return ERT_OK;
+}
+
+// On-demand translation matrices of a rebuilt level, for pair_stream.
+struct HetGenCtx {
+    ert_plan_impl* p;
+    const FmmTree* tr;
+    const double* cheb;
+    const HetCache* hc;
+    int l;
+};
+
+ert_status het_gen_fill(const void* ctx, hipStream_t s, long p0, long cnt, float* dst)
+{
+    const HetGenCtx* c = static_cast<const HetGenCtx*>(ctx);
+    return het_fill(c->p, s, *c->tr, c->cheb, c->hc->st8, c->hc, c->l, p0, cnt, dst);
+}
 
 ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb, const double* st8, HetCache* hc,
                          int l)
@@ -1804,34 +1859,47 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
     ERT_TRY(upload<int>(s, &hc->hub[l], ub));
     ERT_TRY(upload<long>(s, &hc->hfwd[l], fwd));
     ERT_TRY(upload<long>(s, &hc->hbwd[l], bwd));
-    size_t bytes = (size_t)np * KpKp * sizeof(float);
+    const size_t bytes = (size_t)np * KpKp * sizeof(float);
+    // budget of the stored translation matrices: the plan's option, else 90 % of the
+    // free device memory; both orders' caches count against it
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess && bytes > fr / 10 * 9) {
-        record_error("FMM: heterogeneous translation cache does not fit in device memory");
-        return ERT_ENOMEM;
+    size_t avail = (hipMemGetInfo(&fr, &tot) == hipSuccess) ? fr / 10 * 9 : 0;
+    if (p->o.far_cache_gb > 0.0) {
+        size_t used = hc->far_bytes;
+        for (int i = 0; i < 2; ++i)
+            if (p->het[i] && p->het[i] != hc) used += p->het[i]->far_bytes;
+        const double lim = p->o.far_cache_gb * 1e9;
+        const size_t left = lim > (double)used ? (size_t)(lim - (double)used) : 0;
+        avail = std::min(avail, left);
     }
-    if (hipMalloc(&hc->hops[l], std::max<size_t>(1, bytes)) != hipSuccess) {
-        record_error("FMM: heterogeneous translation cache allocation failed");
-        return ERT_ENOMEM;
-    }
-    const long pchunk = std::max<long>(1, (1L << 27) / KpKp);
-    const Geo& g = p->geo;
-    const int nwin = (tr.D == 3 && g.n0 > 1 && g.n1 > 1 && g.n2 > 1) ? ops_lds_windows(tr.leaf << (tr.L - l)) : 0;
-    const long ngroup = (KpKp + kOpsLdsRays * kOpsLdsThreads - 1) / (kOpsLdsRays * kOpsLdsThreads);
-    for (long p0 = 0; p0 < np; p0 += pchunk) {
-        long cnt = std::min(pchunk, np - p0);
-        if (nwin > 0) {
-            hipLaunchKernelGGL(k_ops_het_lds<float>, dim3((unsigned)(cnt * ngroup)), dim3(kOpsLdsThreads), 0, s, g,
-                               p->d_st, st8, tr.nc, tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l],
-                               hc->hub[l], p0, (int)ngroup, nwin, hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
-        } else {
-            hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(cnt * KpKp)), dim3(kB), 0, s, g, st8, tr.D, tr.nc,
-                               tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], p0, cnt,
-                               hc->hops[l] + (size_t)p0 * KpKp, p->o.scheme);
+    if (bytes <= avail && hipMalloc(&hc->hops[l], std::max<size_t>(1, bytes)) == hipSuccess) {
+        ERT_TRY(het_fill(p, s, tr, cheb, st8, hc, l, 0, np, hc->hops[l]));
+        hc->bytes += bytes;
+        hc->far_bytes += bytes;
+    } else {
+        // rebuilt by every apply through a scratch buffer of whole blocks (at most 2 GB,
+        // or what is left of the budget, at least one block)
+        (void)hipGetLastError();
+        hc->hops[l] = nullptr;
+        hc->rebuilt[l] = true;
+        const size_t block = (size_t)KpKp * sizeof(float);
+        const size_t want = std::max(block, std::min<size_t>(avail, size_t(2) << 30));
+        const long chunk = (long)std::min<size_t>((size_t)np, want / block);
+        if (chunk > hc->chunk) {
+            if (hc->scratch) {
+                (void)hipFree(hc->scratch);
+                hc->bytes -= (size_t)hc->chunk * block;
+            }
+            hc->scratch = nullptr;
+            hc->chunk = 0;
+            if (hipMalloc(&hc->scratch, (size_t)chunk * block) != hipSuccess) {
+                record_error("FMM: scratch for the rebuilt translation matrices could not be allocated");
+                return ERT_ENOMEM;
+            }
+            hc->chunk = chunk;
+            hc->bytes += (size_t)chunk * block;
         }
-        ERT_HIP(hipGetLastError());
     }
-    hc->bytes += bytes;
     ERT_HIP(hipStreamSynchronize(s));
     return ERT_OK;
 }
@@ -1885,6 +1953,10 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
         ert_status st = t8.build(p);
         for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, t8.st8, c, l);
         if (st != ERT_OK) return fail(st);
+        if (c->chunk > 0) {
+            c->st8 = t8.release();
+            c->bytes += (size_t)p->N * 8 * sizeof(double);
+        }
         if (hipStreamSynchronize(s) != hipSuccess) return fail(ERT_EDEVICE);
         p->het[slot] = c;
         hc = c;
@@ -1962,6 +2034,10 @@ ert_status FmmImpl<T>::setup_het(ert_plan_impl* p)
     for (int l = 2; l <= tr.L && st == ERT_OK; ++l) st = het_far_level(p, tr, cheb, t8.st8, c, l);
     if (st == ERT_OK && hipStreamSynchronize(s) != hipSuccess) st = ERT_EDEVICE;
     if (st != ERT_OK) return fail(st);
+    if (c->chunk > 0) {
+        c->st8 = t8.release();
+        c->bytes += (size_t)p->N * 8 * sizeof(double);
+    }
     p->het[slot] = c;
     hc = c;
     return ERT_OK;
@@ -2436,7 +2512,18 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 a.prof = pf;
                 a.prof_stage = ERT_STAGE_M2L;
                 // split-BF16x3 translations run on the matrix cores for any rhs count
-                ERT_TRY(pair_stream(s, prec, a));
+                if (hc->rebuilt[l]) {
+                    // not stored: the matrices are rebuilt chunk by chunk for these products
+                    const HetGenCtx ctx{p, &tr, cheb, hc, l};
+                    PairGen gen;
+                    gen.chunk = hc->chunk;
+                    gen.scratch = hc->scratch;
+                    gen.fill = het_gen_fill;
+                    gen.ctx = &ctx;
+                    ERT_TRY(pair_stream(s, prec, a, &gen));
+                } else {
+                    ERT_TRY(pair_stream(s, prec, a));
+                }
             } else if (rp[l] > 0 && leaf_in) {
                 // single compressed level: multipoles already compressed, the expansion
                 // is folded into L2P below
@@ -2660,6 +2747,8 @@ ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info)
     info->form_near = f->form_of(-1);
     info->near_table = f->near_table();
     for (int l = 0; l < 16; ++l) info->form_far[l] = (l <= t.L && l >= 2) ? f->form_of(l) : -1;
+    for (int l = 0; l < 16; ++l) info->far_rebuilt[l] = (l <= t.L && l >= 2 && f->far_rebuilt(l)) ? 1 : 0;
+    info->cache_bytes = f->cache_bytes();
     // interaction-list pairs per level (separable per axis) and near point pairs
     for (int l = 2; l <= t.L && l < 16; ++l) {
         long par = 1, nr = 1;
@@ -2708,6 +2797,8 @@ HetCache::~HetCache()
     for (int l = 0; l <= kMaxLevels; ++l) {
         f(hops[l]); f(pstart[l]); f(hua[l]); f(hub[l]); f(hfwd[l]); f(hbwd[l]);
     }
+    f(scratch);
+    f(st8);
 }
 
 void het_destroy(HetCache* c) { delete c; }

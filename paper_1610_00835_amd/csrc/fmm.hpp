@@ -188,10 +188,22 @@ constexpr int kPairMfmaMinRhs = 16;
 // Staging rows per pass of the streaming form.
 constexpr int kPairStreamRhs = 4;
 
+// Blocks made on demand (FP32 storage): the products take the pairs in chunks of
+// `chunk`, each written into `scratch` by `fill` (kernel launches on the stream only)
+// just before its products; the per-target sums follow all chunks, so the results
+// are those of the stored blocks.
+struct PairGen {
+    long chunk = 0;                 // pairs per chunk
+    float* scratch = nullptr;       // [chunk][M][M]
+    ert_status (*fill)(const void* ctx, hipStream_t s, long p0, long cnt, float* dst) = nullptr;
+    const void* ctx = nullptr;
+};
+
 // prec: ERT_FP64 or ERT_FP32 (streaming below kPairMfmaMinRhs right-hand sides, matrix
 // cores from there on), or ERT_BF16X3 (FP32-stored blocks as split-BF16x3 matrix-core
-// products with FP32 accumulation, for any right-hand-side count).
-ert_status pair_stream(hipStream_t s, int prec, const PairStream& g);
+// products with FP32 accumulation, for any right-hand-side count).  gen: null when
+// g.opsT holds every block.
+ert_status pair_stream(hipStream_t s, int prec, const PairStream& g, const PairGen* gen = nullptr);
 
 // Heterogeneous media: kernel caches shared by the applies of every precision
 // of a plan, in FP32 (the FP64 apply reads them and accumulates in FP64; the
@@ -220,7 +232,15 @@ struct HetCache {
     long* hbwd[kMaxLevels + 1] = {};
     long hnd[kMaxLevels + 1] = {};          // directed pairs (staging rows)
     long* pstart[kMaxLevels + 1] = {};      // [nbox + 1] directed pairs of each target
+    // levels whose translation matrices exceed the plan's cache budget are not stored
+    // (hops[l] null): every apply rebuilds them, `chunk` pairs at a time, into `scratch`
+    // from the corner-octet table of sigma_t (kept for this)
+    bool rebuilt[kMaxLevels + 1] = {};
+    float* scratch = nullptr;               // [chunk][Kp][Kp]
+    long chunk = 0;
+    double* st8 = nullptr;                  // [N][8] corner octets of sigma_t
     size_t bytes = 0;
+    size_t far_bytes = 0;                   // stored translation matrices
     ~HetCache();
 };
 

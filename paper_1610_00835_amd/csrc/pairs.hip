@@ -988,8 +988,34 @@ void launch_sym(hipStream_t s, const PairStream& g, int b0, int rb, int R, int n
 constexpr size_t kSymLdsMax = 64 * 1024;
 
 // Streaming form: passes of 4, 2 or 1 right-hand sides (as many as the LDS allows).
+// Runs launch(c) over the stored blocks (c = g), or over the chunks of on-demand
+// blocks: each chunk filled into the scratch buffer, then c = the chunk's pairs.
+template <typename F>
+ert_status for_each_chunk(hipStream_t s, const PairStream& g, const PairGen* gen, F&& launch)
+{
+    if (!gen) return launch(g);
+    if (gen->chunk < 1 || !gen->scratch || !gen->fill || g.ops_fmt != kOpsF32) {
+        record_error("pair_stream: on-demand blocks need a scratch buffer, a fill step and FP32 storage");
+        return ERT_EINVAL;
+    }
+    for (long p0 = 0; p0 < g.npairs; p0 += gen->chunk) {
+        const long cnt = std::min(gen->chunk, g.npairs - p0);
+        ERT_TRY(gen->fill(gen->ctx, s, p0, cnt, gen->scratch));
+        PairStream c = g;
+        c.opsT = gen->scratch;
+        c.opsT_lo = nullptr;
+        c.npairs = cnt;
+        c.ua = g.ua + p0;
+        c.ub = g.ub + p0;
+        c.fwd_row = g.fwd_row + p0;
+        c.bwd_row = g.bwd_row + p0;
+        ERT_TRY(launch(c));
+    }
+    return ERT_OK;
+}
+
 template <typename T, typename TS>
-ert_status pair_sym_t(hipStream_t s, const PairStream& g)
+ert_status pair_sym_t(hipStream_t s, const PairStream& g, const PairGen* gen)
 {
     constexpr bool F32 = std::is_same<TS, float>::value;
     const int M = g.M;
@@ -1011,10 +1037,13 @@ ert_status pair_sym_t(hipStream_t s, const PairStream& g)
         const size_t sh = sym_lds(MP, rb, sizeof(T));
         {
             StageTimer t_(g.prof, s, g.prof_stage);
-            // whole 16-byte pieces (CPL values per plane) when rows hold a multiple of CPL
-            if (M % cpl == 0) launch_sym<T, TS, 4>(s, g, b0, rb, R, nchunk, MP, sh);
-            else launch_sym<T, TS, 1>(s, g, b0, rb, R, nchunk, MP, sh);
-            ERT_HIP(hipGetLastError());
+            ERT_TRY(for_each_chunk(s, g, gen, [&](const PairStream& c) -> ert_status {
+                // whole 16-byte pieces (CPL values per plane) when rows hold a multiple of CPL
+                if (M % cpl == 0) launch_sym<T, TS, 4>(s, c, b0, rb, R, nchunk, MP, sh);
+                else launch_sym<T, TS, 1>(s, c, b0, rb, R, nchunk, MP, sh);
+                ERT_HIP(hipGetLastError());
+                return ERT_OK;
+            }));
         }
         ERT_TRY(launch_reduce<T>(s, g, b0, rb));
         b0 += rb;
@@ -1024,39 +1053,41 @@ ert_status pair_sym_t(hipStream_t s, const PairStream& g)
 
 // Matrix-core form (FP32 storage, whole or in planes), 64 right-hand sides per pass.
 template <int PREC, typename TS>
-ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
+ert_status pair_mfma_t(hipStream_t s, const PairStream& g, const PairGen* gen)
 {
     constexpr int RT = (PREC == ERT_FP64) ? 4 : 8;
     constexpr int RTB = 4;                        // backward: 256 rows per workgroup (LDS tile)
     typedef typename Acc<PREC>::T T;
     const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
     const int rblocksb = (g.M + 64 * RTB - 1) / (64 * RTB);
-    const dim3 grid((unsigned)(g.npairs * rblocks)), gridb((unsigned)(g.npairs * rblocksb));
     for (int b0 = 0; b0 < g.B; b0 += 64) {
         const int nb = std::min(64, g.B - b0);
-        {
-            StageTimer t_(g.prof, s, g.prof_stage);
+        StageTimer t_(g.prof, s, g.prof_stage);
+        ERT_TRY(for_each_chunk(s, g, gen, [&](const PairStream& c) -> ert_status {
+            const dim3 grid((unsigned)(c.npairs * rblocks)), gridb((unsigned)(c.npairs * rblocksb));
             // whole 4-value pieces of the stored rows: both operands staged in LDS, the
             // next chunk in flight (the FP32 forward product over FP32-stored blocks keeps its
             // 512-row tiles, whose operators come straight from memory: it keeps the matrix
             // cores about 60 % busy already)
-            const bool piecewise = g.M % 4 == 0;
+            const bool piecewise = c.M % 4 == 0;
             bool fwd_done = false;
             if constexpr (PREC == ERT_FP64 || !std::is_same<TS, float>::value) {
                 // FP64, or values in 16-bit planes (decoded once into the LDS tile)
                 if (piecewise) {
-                    hipLaunchKernelGGL((k_pair_mma<PREC, RTB, TS, false>), gridb, dim3(256), 0, s, g, b0, rblocksb);
+                    hipLaunchKernelGGL((k_pair_mma<PREC, RTB, TS, false>), gridb, dim3(256), 0, s, c, b0, rblocksb);
                     fwd_done = true;
                 }
             }
-            if (!fwd_done) hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), grid, dim3(256), 0, s, g, b0, rblocks);
+            if (!fwd_done) hipLaunchKernelGGL((k_pair_mfma<PREC, RT, TS>), grid, dim3(256), 0, s, c, b0, rblocks);
             ERT_HIP(hipGetLastError());
             if (piecewise)
-                hipLaunchKernelGGL((k_pair_mma<PREC, RTB, TS, true>), gridb, dim3(256), 0, s, g, b0, rblocksb);
+                hipLaunchKernelGGL((k_pair_mma<PREC, RTB, TS, true>), gridb, dim3(256), 0, s, c, b0, rblocksb);
             else
-                hipLaunchKernelGGL((k_pair_mfma_back<PREC, RTB, TS>), gridb, dim3(256), 0, s, g, b0, rblocksb);
+                hipLaunchKernelGGL((k_pair_mfma_back<PREC, RTB, TS>), gridb, dim3(256), 0, s, c, b0, rblocksb);
             ERT_HIP(hipGetLastError());
-        }
+            return ERT_OK;
+        }));
+        t_.stop();
         ERT_TRY(launch_reduce<T>(s, g, b0, nb));
     }
     return ERT_OK;
@@ -1064,7 +1095,7 @@ ert_status pair_mfma_t(hipStream_t s, const PairStream& g)
 
 // Split-BF16x3 matrix-core form (FP32-stored blocks, FP32 vectors), 64 right-hand
 // sides per pass, for any right-hand-side count (it stays HBM-bound with one).
-ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g)
+ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g, const PairGen* gen)
 {
     constexpr int RT = 4;
     if (g.ops_fmt != kOpsF32) {
@@ -1072,21 +1103,24 @@ ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g)
         return ERT_EINVAL;
     }
     const int rblocks = (g.M + 64 * RT - 1) / (64 * RT);
-    const dim3 grid((unsigned)(g.npairs * rblocks));
     for (int b0 = 0; b0 < g.B; b0 += 64) {
         const int nb = std::min(64, g.B - b0);
         {
             StageTimer t_(g.prof, s, g.prof_stage);
-            if (g.M % 4 == 0) {           // whole 4-value pieces: LDS-staged, next chunk in flight
-                hipLaunchKernelGGL((k_pair_b3<RT, false>), grid, dim3(256), 0, s, g, b0, rblocks);
+            ERT_TRY(for_each_chunk(s, g, gen, [&](const PairStream& c) -> ert_status {
+                const dim3 grid((unsigned)(c.npairs * rblocks));
+                if (c.M % 4 == 0) {           // whole 4-value pieces: LDS-staged, next chunk in flight
+                    hipLaunchKernelGGL((k_pair_b3<RT, false>), grid, dim3(256), 0, s, c, b0, rblocks);
+                    ERT_HIP(hipGetLastError());
+                    hipLaunchKernelGGL((k_pair_b3<RT, true>), grid, dim3(256), 0, s, c, b0, rblocks);
+                } else {
+                    hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, false>), grid, dim3(256), 0, s, c, b0, rblocks);
+                    ERT_HIP(hipGetLastError());
+                    hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, true>), grid, dim3(256), 0, s, c, b0, rblocks);
+                }
                 ERT_HIP(hipGetLastError());
-                hipLaunchKernelGGL((k_pair_b3<RT, true>), grid, dim3(256), 0, s, g, b0, rblocks);
-            } else {
-                hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, false>), grid, dim3(256), 0, s, g, b0, rblocks);
-                ERT_HIP(hipGetLastError());
-                hipLaunchKernelGGL((k_pair_mfma_bf16x3<RT, true>), grid, dim3(256), 0, s, g, b0, rblocks);
-            }
-            ERT_HIP(hipGetLastError());
+                return ERT_OK;
+            }));
         }
         ERT_TRY(launch_reduce<float>(s, g, b0, nb));
     }
@@ -1095,7 +1129,7 @@ ert_status pair_mfma_bf16x3(hipStream_t s, const PairStream& g)
 
 }  // namespace
 
-ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
+ert_status pair_stream(hipStream_t s, int prec, const PairStream& g, const PairGen* gen)
 {
     if (g.npairs < 1 || g.B < 1) return ERT_OK;
     if (g.ops_fmt != kOpsF32 && g.ops_fmt != kOpsSplit && g.ops_fmt != kOpsHi) {
@@ -1112,19 +1146,20 @@ ert_status pair_stream(hipStream_t s, int prec, const PairStream& g)
             record_error("pair_stream: split-BF16x3 products need blocks of a multiple of 4 rows");
             return ERT_EINVAL;
         }
-        return pair_mfma_bf16x3(s, g);
+        return pair_mfma_bf16x3(s, g, gen);
     }
     if (g.B >= kPairMfmaMinRhs && g.M % 4 == 0) {
         switch (g.ops_fmt) {
-        case kOpsSplit: return f64 ? pair_mfma_t<ERT_FP64, OpsSplit>(s, g) : pair_mfma_t<ERT_FP32, OpsSplit>(s, g);
-        case kOpsHi: return pair_mfma_t<ERT_FP32, OpsHi>(s, g);
-        default: return f64 ? pair_mfma_t<ERT_FP64, float>(s, g) : pair_mfma_t<ERT_FP32, float>(s, g);
+        case kOpsSplit:
+            return f64 ? pair_mfma_t<ERT_FP64, OpsSplit>(s, g, gen) : pair_mfma_t<ERT_FP32, OpsSplit>(s, g, gen);
+        case kOpsHi: return pair_mfma_t<ERT_FP32, OpsHi>(s, g, gen);
+        default: return f64 ? pair_mfma_t<ERT_FP64, float>(s, g, gen) : pair_mfma_t<ERT_FP32, float>(s, g, gen);
         }
     }
     switch (g.ops_fmt) {
-    case kOpsSplit: return f64 ? pair_sym_t<double, OpsSplit>(s, g) : pair_sym_t<float, OpsSplit>(s, g);
-    case kOpsHi: return pair_sym_t<float, OpsHi>(s, g);
-    default: return f64 ? pair_sym_t<double, float>(s, g) : pair_sym_t<float, float>(s, g);
+    case kOpsSplit: return f64 ? pair_sym_t<double, OpsSplit>(s, g, gen) : pair_sym_t<float, OpsSplit>(s, g, gen);
+    case kOpsHi: return pair_sym_t<float, OpsHi>(s, g, gen);
+    default: return f64 ? pair_sym_t<double, float>(s, g, gen) : pair_sym_t<float, float>(s, g, gen);
     }
 }
 

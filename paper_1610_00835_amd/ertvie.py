@@ -33,7 +33,7 @@ class VieOpts(ctypes.Structure):
                 ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
                 ("cheb_n", ctypes.c_int), ("leaf", ctypes.c_int), ("nrhs_max", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("svd_tol", ctypes.c_double), ("inner_cheb_n", ctypes.c_int),
-                ("inner_near16", ctypes.c_int), ("form", ctypes.c_int * 2)]
+                ("inner_near16", ctypes.c_int), ("form", ctypes.c_int * 2), ("far_cache_gb", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -64,7 +64,8 @@ class FmmInfo(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("leaf", ctypes.c_int), ("cheb_n", ctypes.c_int),
                 ("nodes", ctypes.c_int), ("nodes_padded", ctypes.c_int), ("rank", ctypes.c_int * 16),
                 ("far_pairs", ctypes.c_long * 16), ("near_pairs", ctypes.c_long), ("form_near", ctypes.c_int),
-                ("form_far", ctypes.c_int * 16), ("near_table", ctypes.c_long)]
+                ("form_far", ctypes.c_int * 16), ("near_table", ctypes.c_long), ("far_rebuilt", ctypes.c_int * 16),
+                ("cache_bytes", ctypes.c_double)]
 
 
 class FftInfo(ctypes.Structure):
@@ -187,12 +188,14 @@ class Plan:
 
     dim, n, h: grid (cell-centred, x fastest); sigma_t, sigma_s: host arrays of N values.
     kernel: 0 homogeneous / 1 midpoint ray rule; method 'direct' | 'fmm';
-    prec 'fp64' | 'fp32' | 'bf16x3'.
+    prec 'fp64' | 'fp32' | 'bf16x3'.  far_cache_gb: budget of the stored heterogeneous
+    translation matrices (0: 90 % of the free device memory); levels over it are rebuilt by
+    every apply.
     """
 
     def __init__(self, dim, n, h, sigma_t, sigma_s, kernel=K_HOMOGENEOUS, method="direct", prec="fp64",
                  cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0, inner_cheb_n=0, inner_near16=False, scheme=0,
-                 form=None):
+                 form=None, far_cache_gb=0.0):
         L = load()
         n = list(n)[:dim]
         self.dim = int(dim)
@@ -214,11 +217,12 @@ class Plan:
         o.inner_cheb_n = int(inner_cheb_n)
         o.inner_near16 = 1 if inner_near16 else 0
         # execution forms of the homogeneous box-offset products: None (timed), f (both
-        # products) or (near, far); each 0..4
+        # products) or (near, far); each 0..5
         if form is not None:
             fn, ff = (form, form) if np.isscalar(form) else form
             o.form[0] = int(fn) + 1
             o.form[1] = int(ff) + 1
+        o.far_cache_gb = float(far_cache_gb)
         self.opts = o
         st_h = _f64_host(sigma_t, self.N)
         ss_h = _f64_host(sigma_s, self.N)
@@ -373,7 +377,8 @@ class Plan:
                 "nodes_padded": inf.nodes_padded, "rank": [inf.rank[l] for l in range(L + 1)],
                 "far_pairs": [inf.far_pairs[l] for l in range(L + 1)], "near_pairs": inf.near_pairs,
                 "form_near": inf.form_near, "form_far": [inf.form_far[l] for l in range(L + 1)],
-                "near_table": inf.near_table}
+                "near_table": inf.near_table, "far_rebuilt": [inf.far_rebuilt[l] for l in range(L + 1)],
+                "cache_bytes": inf.cache_bytes}
 
     def diag(self):
         d = np.empty(self.N)
@@ -402,10 +407,11 @@ class Plan:
 
 
 def plan_from_case(case, method="direct", prec="fp64", cheb_n=0, leaf=0, nrhs_max=1, stream=None, svd_tol=0.0,
-                   inner_cheb_n=0, inner_near16=False, scheme=0, form=None):
+                   inner_cheb_n=0, inner_near16=False, scheme=0, form=None, far_cache_gb=0.0):
     return Plan(case["dim"], case["n"], case["h"], case["sigma_t"], case["sigma_s"], kernel=case["kernel"],
                 method=method, prec=prec, cheb_n=cheb_n, leaf=leaf, nrhs_max=nrhs_max, stream=stream,
-                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n, inner_near16=inner_near16, scheme=scheme, form=form)
+                svd_tol=svd_tol, inner_cheb_n=inner_cheb_n, inner_near16=inner_near16, scheme=scheme, form=form,
+                far_cache_gb=far_cache_gb)
 
 
 def _load_net():

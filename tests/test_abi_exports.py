@@ -83,6 +83,9 @@ def test_plan_rejects_bad_arguments_before_device_use():
     assert plan(inner_near16=2) == ertvie.EINVAL
     assert plan(form=(7, 0)) == ertvie.EINVAL                  # execution forms 0..5, stored as f + 1
     assert plan(form=(0, -1)) == ertvie.EINVAL
+    assert plan(far_cache_gb=-1.0) == ertvie.EINVAL            # translation-cache budget >= 0, finite
+    assert plan(far_cache_gb=float("nan")) == ertvie.EINVAL
+    assert plan(far_cache_gb=float("inf")) == ertvie.EINVAL
     assert plan(st=np.where(np.arange(N) == 3, -1.0, 2.0)) == ertvie.EINVAL
     assert plan(ss=np.full(N, 2.5)) == ertvie.EINVAL           # absorption < 0
     assert plan(ss=np.full(N, -0.1)) == ertvie.EINVAL
