@@ -475,6 +475,50 @@ def c5_headline(torch, ertvie, inputs, O, stream, args):
     return ms, roof, res, cpu
 
 
+def c5_order8_rebuilt(torch, ertvie, inputs, O, stream):
+    """The 128^3 many-scattering medium with the FP64 operator at Chebyshev order 8: its
+    translation matrices (about 330 GB) exceed the device, so the plan stores what fits and
+    every apply rebuilds the leaf-level matrices by the ray march (far_cache_gb default).
+    Reports the plan, the apply time and the error on sampled rows against the oracle."""
+    n = (C5_N,) * 3
+    case = inputs.make_case("c5", n=n, seed=0)
+    N = int(np.prod(n))
+    torch.cuda.empty_cache()
+    t = time.perf_counter()
+    plan = ertvie.plan_from_case(case, method="fmm", prec="fp64", stream=stream, cheb_n=8)
+    try:
+        info = plan.fmm_info("fp64")
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t
+        log("128^3 order 8: plan %.1f s, rebuilt levels %s, caches %.1f GB"
+            % (plan_s, info["far_rebuilt"], info["cache_bytes"] / 1e9))
+        x = torch.from_numpy(inputs.random_vector(N, 21)).cuda()
+        y = torch.empty_like(x)
+        times = []
+        for _ in range(3):          # eager, captured, replayed
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan.apply(x, y, op=ertvie.OP_A)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            log("128^3 order 8 apply: %.3f s" % times[-1])
+        yh = y.cpu().numpy()
+    finally:
+        plan.close()
+        torch.cuda.empty_cache()
+    cores = len(os.sched_getaffinity(0))
+    nrows = max(4, min(cores, 16))
+    rows = np.random.default_rng(3).choice(N, size=nrows, replace=False)
+    P = O.Problem(3, case["n"], case["h"], 1, case["sigma_t"], case["sigma_s"])
+    yo = P.apply_rows(inputs.random_vector(N, 21), rows, op=2, nthreads=cores)
+    err = float(np.linalg.norm(yh[rows] - yo) / np.linalg.norm(yo))
+    log("128^3 order 8: error on %d rows %.3e" % (nrows, err))
+    return {"workload": "128^3 many-scattering medium seed 0, FP64 FMM apply of I - K, leaf 8^3, Chebyshev order 8",
+            "plan_s": plan_s, "apply_s": times, "far_rebuilt": info["far_rebuilt"],
+            "cache_gb": info["cache_bytes"] / 1e9, "far_pairs": info["far_pairs"],
+            "rel_l2_vs_oracle_rows": err, "oracle_rows": nrows}
+
+
 def c5_solves(torch, ertvie, plan, fd, N):
     """Time to a 1e-8 true residual at 128^3 (each solve once untimed for graph capture and
     tuning, then timed): plain FP64 GMRES; the FP64-refined solve with FP32 inner GMRES on the
@@ -662,6 +706,9 @@ def main():
                     help="also run the paper's accuracy experiment ((M-ii) vs (M-iii), 2D, 12 grids, three media)")
     ap.add_argument("--paper-exp6", action="store_true",
                     help="also run the paper's preconditioning experiment (2D 512^2, four media)")
+    ap.add_argument("--rebuilt-only", action="store_true",
+                    help="only the 128^3 order-8 FP64 apply whose leaf-level translation matrices do not fit "
+                         "and are rebuilt by every apply (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three 256 MiB device copies (reference for memory-traffic counters)")
     args = ap.parse_args()
@@ -689,6 +736,10 @@ def main():
         return
     if args.many_rhs_only:
         print(json.dumps({"many_rhs_64cubed": many_rhs_64(torch, ertvie, inputs, stream)}), flush=True)
+        return
+    if args.rebuilt_only:
+        print(json.dumps({"order8_128cubed_rebuilt": c5_order8_rebuilt(torch, ertvie, inputs, O, stream)}),
+              flush=True)
         return
     if args.homogeneous_only:
         out = {}
