@@ -146,14 +146,15 @@ typedef struct {
     double far_cache_gb; /* heterogeneous media, FMM: device memory, in GB (1e9 bytes), that
                          the plan's stored far-field translation matrices (of every order the
                          plan builds) may take; 0 -> 90 % of the device memory free when a level
-                         is built.  A level that does not fit is not stored: every apply
-                         rebuilds its matrices by the same ray march (Sec. 4.2's kernel
-                         evaluations), in chunks of whole box pairs (at most 2 GB, or what is
-                         left of the budget, at least one pair) written to a scratch buffer
-                         and used right away.  The results are those of the stored level bit
-                         for bit; each apply then costs that level's ray marches (seconds at
-                         128^3 instead of milliseconds).  The near-field blocks are always
-                         stored (ERT_ENOMEM when they do not fit).  >= 0 and finite */
+                         is built.  A level that does not fit keeps the box pairs that fit
+                         stored; every apply rebuilds the others by the same ray march (Sec.
+                         4.2's kernel evaluations), in chunks of whole pairs written to a
+                         scratch buffer (a sixteenth of the level's room, at least one pair,
+                         at most 2 GB) and used right away.  The results are those of a fully
+                         stored level bit for bit; each apply then costs the rebuilt pairs' ray
+                         marches (seconds at 128^3 instead of milliseconds).  The near-field
+                         blocks are always stored (ERT_ENOMEM when they do not fit).  >= 0 and
+                         finite */
 } ert_vie_opts;
 
 typedef struct {

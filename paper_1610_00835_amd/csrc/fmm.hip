@@ -1872,19 +1872,21 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
         const size_t left = lim > (double)used ? (size_t)(lim - (double)used) : 0;
         avail = std::min(avail, left);
     }
+    const size_t block = (size_t)KpKp * sizeof(float);
     if (bytes <= avail && hipMalloc(&hc->hops[l], std::max<size_t>(1, bytes)) == hipSuccess) {
         ERT_TRY(het_fill(p, s, tr, cheb, st8, hc, l, 0, np, hc->hops[l]));
+        hc->hstored[l] = np;
         hc->bytes += bytes;
         hc->far_bytes += bytes;
     } else {
-        // rebuilt by every apply through a scratch buffer of whole blocks (at most 2 GB,
-        // or what is left of the budget, at least one block)
+        // the first pairs that fit are stored; every apply rebuilds the others through
+        // a scratch buffer of whole blocks (1/16 of the room, at least one block, at
+        // most 2 GB, shared by the levels)
         (void)hipGetLastError();
         hc->hops[l] = nullptr;
         hc->rebuilt[l] = true;
-        const size_t block = (size_t)KpKp * sizeof(float);
-        const size_t want = std::max(block, std::min<size_t>(avail, size_t(2) << 30));
-        const long chunk = (long)std::min<size_t>((size_t)np, want / block);
+        const size_t sbytes = std::max(block, std::min<size_t>(avail / 16, size_t(2) << 30));
+        const long chunk = (long)std::min<size_t>((size_t)np, sbytes / block);
         if (chunk > hc->chunk) {
             if (hc->scratch) {
                 (void)hipFree(hc->scratch);
@@ -1899,6 +1901,19 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
             hc->chunk = chunk;
             hc->bytes += (size_t)chunk * block;
         }
+        const size_t room = avail > (size_t)chunk * block ? avail - (size_t)chunk * block : 0;
+        long ns = (long)std::min<size_t>((size_t)(np - 1), room / block);
+        if (ns > 0 && hipMalloc(&hc->hops[l], (size_t)ns * block) != hipSuccess) {
+            (void)hipGetLastError();
+            hc->hops[l] = nullptr;
+            ns = 0;
+        }
+        if (ns > 0) {
+            ERT_TRY(het_fill(p, s, tr, cheb, st8, hc, l, 0, ns, hc->hops[l]));
+            hc->bytes += (size_t)ns * block;
+            hc->far_bytes += (size_t)ns * block;
+        }
+        hc->hstored[l] = ns;
     }
     ERT_HIP(hipStreamSynchronize(s));
     return ERT_OK;
@@ -2513,9 +2528,11 @@ ert_status FmmImpl<T>::enqueue(ert_plan_impl* p, hipStream_t s, int nrhs)
                 a.prof_stage = ERT_STAGE_M2L;
                 // split-BF16x3 translations run on the matrix cores for any rhs count
                 if (hc->rebuilt[l]) {
-                    // not stored: the matrices are rebuilt chunk by chunk for these products
+                    // pairs past the stored ones: rebuilt chunk by chunk for these products
                     const HetGenCtx ctx{p, &tr, cheb, hc, l};
                     PairGen gen;
+                    gen.stored = hc->hstored[l];
+                    gen.stored_ops = hc->hops[l];
                     gen.chunk = hc->chunk;
                     gen.scratch = hc->scratch;
                     gen.fill = het_gen_fill;

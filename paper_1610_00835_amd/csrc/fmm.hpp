@@ -193,7 +193,9 @@ constexpr int kPairStreamRhs = 4;
 // just before its products; the per-target sums follow all chunks, so the results
 // are those of the stored blocks.
 struct PairGen {
-    long chunk = 0;                 // pairs per chunk
+    long stored = 0;                // pairs 0 .. stored - 1 are in stored_ops (no fill)
+    const float* stored_ops = nullptr;
+    long chunk = 0;                 // pairs per chunk of the others
     float* scratch = nullptr;       // [chunk][M][M]
     ert_status (*fill)(const void* ctx, hipStream_t s, long p0, long cnt, float* dst) = nullptr;
     const void* ctx = nullptr;
@@ -232,10 +234,11 @@ struct HetCache {
     long* hbwd[kMaxLevels + 1] = {};
     long hnd[kMaxLevels + 1] = {};          // directed pairs (staging rows)
     long* pstart[kMaxLevels + 1] = {};      // [nbox + 1] directed pairs of each target
-    // levels whose translation matrices exceed the plan's cache budget are not stored
-    // (hops[l] null): every apply rebuilds them, `chunk` pairs at a time, into `scratch`
-    // from the corner-octet table of sigma_t (kept for this)
+    // levels whose translation matrices exceed the plan's cache budget keep the first
+    // hstored[l] pairs in hops[l]; every apply rebuilds the others, `chunk` pairs at a
+    // time, into `scratch` from the corner-octet table of sigma_t (kept for this)
     bool rebuilt[kMaxLevels + 1] = {};
+    long hstored[kMaxLevels + 1] = {};
     float* scratch = nullptr;               // [chunk][Kp][Kp]
     long chunk = 0;
     double* st8 = nullptr;                  // [N][8] corner octets of sigma_t

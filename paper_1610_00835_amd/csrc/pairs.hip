@@ -988,17 +988,26 @@ void launch_sym(hipStream_t s, const PairStream& g, int b0, int rb, int R, int n
 constexpr size_t kSymLdsMax = 64 * 1024;
 
 // Streaming form: passes of 4, 2 or 1 right-hand sides (as many as the LDS allows).
-// Runs launch(c) over the stored blocks (c = g), or over the chunks of on-demand
-// blocks: each chunk filled into the scratch buffer, then c = the chunk's pairs.
+// Runs launch(c) over the stored blocks (c = g), or over the stored prefix and then
+// the chunks of on-demand blocks: each chunk filled into the scratch buffer, then
+// c = the chunk's pairs.
 template <typename F>
 ert_status for_each_chunk(hipStream_t s, const PairStream& g, const PairGen* gen, F&& launch)
 {
     if (!gen) return launch(g);
-    if (gen->chunk < 1 || !gen->scratch || !gen->fill || g.ops_fmt != kOpsF32) {
+    if (gen->chunk < 1 || !gen->scratch || !gen->fill || g.ops_fmt != kOpsF32 || gen->stored < 0 ||
+        gen->stored > g.npairs || (gen->stored > 0 && !gen->stored_ops)) {
         record_error("pair_stream: on-demand blocks need a scratch buffer, a fill step and FP32 storage");
         return ERT_EINVAL;
     }
-    for (long p0 = 0; p0 < g.npairs; p0 += gen->chunk) {
+    if (gen->stored > 0) {
+        PairStream c = g;
+        c.opsT = gen->stored_ops;
+        c.opsT_lo = nullptr;
+        c.npairs = gen->stored;
+        ERT_TRY(launch(c));
+    }
+    for (long p0 = gen->stored; p0 < g.npairs; p0 += gen->chunk) {
         const long cnt = std::min(gen->chunk, g.npairs - p0);
         ERT_TRY(gen->fill(gen->ctx, s, p0, cnt, gen->scratch));
         PairStream c = g;

@@ -1,7 +1,7 @@
 """Heterogeneous translation levels over the plan's cache budget (ert_vie_opts.far_cache_gb)
-are not stored: every apply rebuilds their matrices chunk by chunk, by the same ray march
-(Sec. 4.2's kernel evaluations), and streams each chunk through the same pair products, with
-the per-target sums after all chunks.  Such a plan gives the stored plan's results bit for
+keep the pairs that fit stored; every apply rebuilds the others chunk by chunk, by the same
+ray march (Sec. 4.2's kernel evaluations), and streams each chunk through the same pair
+products, with the per-target sums after all chunks.  Such a plan gives the stored plan's results bit for
 bit: the streaming (1 and 3 right-hand sides), matrix-core (16) and split-BF16x3 products,
 eager applies and graph replays, and a mixed-precision solve whose two operators are both
 rebuilt.  The stored plans are the ones the oracle parity tests check."""
@@ -29,7 +29,8 @@ def _vectors(N, nrhs, seed):
 @pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp32", 3), ("fp32", 16), ("fp64", 16), ("bf16x3", 1)])
 def test_rebuilt_level_equals_stored(ev, prec, nrhs):
     """32^3 blob medium, leaf 4^3, order 4 (far field on levels 2 and 3): a budget that holds
-    level 2 and about 100 blocks leaves level 3 to be rebuilt in chunks of 100 box pairs."""
+    level 2 and 100 more blocks keeps 94 pairs of level 3 stored (a sixteenth of the room goes
+    to the scratch buffer) and rebuilds the others in chunks of 6 box pairs."""
     case = inputs.make_case("c3", n=(32, 32, 32), seed=5)
     N = int(np.prod(case["n"]))
     X = _vectors(N, nrhs, 31)
