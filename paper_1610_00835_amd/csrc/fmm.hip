@@ -901,11 +901,11 @@ constexpr int kOpsLdsThreads = 512;
 constexpr int kOpsLdsRays = 2;
 constexpr int kOpsLdsCap = 6144;  // doubles (48 KB)
 
-template <typename T>
+template <typename T, bool MII>
 __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
     Geo g, const double* __restrict__ st, const double* __restrict__ st8, int nc, int K, int Kp, double w, int nl0,
     int nl1, int nl2, const double* __restrict__ cheb, const int* __restrict__ pair_t, const int* __restrict__ pair_s,
-    long p0, int ngroup, int nwin, T* __restrict__ opsT, int mii)
+    long p0, int ngroup, int nwin, T* __restrict__ opsT)
 {
     constexpr int R = kOpsLdsRays;
     __shared__ double sl[kOpsLdsCap];
@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
         double v = 0.0;
         if (rm[j] > 0) {
             const double tau = rlen[j] * rinv[j] * rs[j];
-            if (mii) {
+            if constexpr (MII) {
                 const double hp = g.h * g.h;
                 v = exp(-tau) * cell_int(3, re[j][0] / g.h, re[j][1] / g.h, re[j][2] / g.h, 64.0) /
                     (surface_area(3) * hp);
@@ -1771,9 +1771,10 @@ ert_status het_fill(ert_plan_impl* p, hipStream_t s, const FmmTree& tr, const do
         const long c = std::min(pchunk, p0 + cnt - q0);
         float* out = dst + (size_t)(q0 - p0) * KpKp;
         if (nwin > 0) {
-            hipLaunchKernelGGL(k_ops_het_lds<float>, dim3((unsigned)(c * ngroup)), dim3(kOpsLdsThreads), 0, s, g,
-                               p->d_st, st8, tr.nc, tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l],
-                               hc->hub[l], q0, (int)ngroup, nwin, out, p->o.scheme);
+            auto kern = p->o.scheme ? k_ops_het_lds<float, true> : k_ops_het_lds<float, false>;
+            hipLaunchKernelGGL(kern, dim3((unsigned)(c * ngroup)), dim3(kOpsLdsThreads), 0, s, g, p->d_st, st8, tr.nc,
+                               tr.K, tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], q0,
+                               (int)ngroup, nwin, out);
         } else {
             hipLaunchKernelGGL(k_ops_het<float>, dim3(blocks(c * KpKp)), dim3(kB), 0, s, g, st8, tr.D, tr.nc, tr.K,
                                tr.Kp, tr.width[l], nl[0], nl[1], nl[2], cheb, hc->hua[l], hc->hub[l], q0, c, out,

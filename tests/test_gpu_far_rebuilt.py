@@ -1,10 +1,10 @@
 """Heterogeneous translation levels over the plan's cache budget (ert_vie_opts.far_cache_gb)
 keep the pairs that fit stored; every apply rebuilds the others chunk by chunk, by the same
 ray march (Sec. 4.2's kernel evaluations), and streams each chunk through the same pair
-products, with the per-target sums after all chunks.  Such a plan gives the stored plan's results bit for
-bit: the streaming (1 and 3 right-hand sides), matrix-core (16) and split-BF16x3 products,
-eager applies and graph replays, and a mixed-precision solve whose two operators are both
-rebuilt.  The stored plans are the ones the oracle parity tests check."""
+products, with the per-target sums after all chunks.  Such a plan gives the fully stored
+plan's results bit for bit: the streaming (1 and 3 right-hand sides), matrix-core (16) and
+split-BF16x3 products, eager applies and graph replays, and a mixed-precision solve whose two
+operators are both rebuilt.  The stored plans are the ones the oracle parity tests check."""
 import numpy as np
 import pytest
 
