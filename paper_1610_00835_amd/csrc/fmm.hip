@@ -899,7 +899,7 @@ __global__ void k_ops_het(Geo g, const double* __restrict__ st8, int D, int nc, 
 // the corner-octet table instead.
 constexpr int kOpsLdsThreads = 512;
 constexpr int kOpsLdsRays = 2;
-constexpr int kOpsLdsCap = 6144;  // doubles (48 KB)
+constexpr int kOpsLdsSide = 18;   // cells per axis of a staged box (LDS pitch; 18^3 doubles = 46.7 KB)
 
 template <typename T, bool MII>
 __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
@@ -908,7 +908,8 @@ __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
     long p0, int ngroup, int nwin, T* __restrict__ opsT)
 {
     constexpr int R = kOpsLdsRays;
-    __shared__ double sl[kOpsLdsCap];
+    constexpr int P = kOpsLdsSide;
+    __shared__ double sl[P * P * P];
     const long pl = blockIdx.x / ngroup;
     const long p = p0 + pl;
     const int gi = (int)(blockIdx.x - pl * ngroup);
@@ -977,24 +978,25 @@ __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
             ext[a] = k1 - k0 + 1;
         }
         const int nst = ext[0] * ext[1] * ext[2];
-        const bool lds = nst <= kOpsLdsCap;
+        const bool lds = ext[0] <= P && ext[1] <= P && ext[2] <= P;
         __syncthreads();  // the previous window's reads are done
         if (lds) {
             for (int e = threadIdx.x; e < nst; e += kOpsLdsThreads) {
                 const int x0 = e % ext[0], x1 = (e / ext[0]) % ext[1], x2 = e / (ext[0] * ext[1]);
-                sl[e] = st[(kmin[0] + x0) + (long)n[0] * ((kmin[1] + x1) + (long)n[1] * (kmin[2] + x2))];
+                sl[x0 + P * (x1 + P * x2)] =
+                    st[(kmin[0] + x0) + (long)n[0] * ((kmin[1] + x1) + (long)n[1] * (kmin[2] + x2))];
             }
         }
         __syncthreads();
-        const double lo0 = double(kmin[0]), lo1 = double(kmin[1]), lo2 = double(kmin[2]);
-        const double ex0 = double(ext[0]), ex1 = double(ext[1]);
-        const int dd1 = ext[0], dd2 = ext[0] * ext[1];
+        const double off = fma(double(P * P), double(kmin[2]), fma(double(P), double(kmin[1]), double(kmin[0])));
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int m = rm[j];
             const int qa = (wi * m) / nwin + 1, qb = ((wi + 1) * m) / nwin;
             double s = rs[j];
-            for (int q = qa; q <= qb; ++q) {
+            // one sample: the cell search of sigma_at and its interpolation over the
+            // corners c[0], c[dx], c[dy], c[dy + dx], c[dz], ... (LDS box or octet table)
+            auto sample = [&](int q, auto corners) {
                 const double f = (double(q) - 0.5) * rinv[j];
                 const double u0 = fmin(fmax((ra[j][0] + f * re[j][0]) * inv_h - 0.5, 0.0), hi0);
                 const double u1 = fmin(fmax((ra[j][1] + f * re[j][1]) * inv_h - 0.5, 0.0), hi1);
@@ -1002,25 +1004,7 @@ __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
                 const double k0 = fmin(floor(u0), km0), k1 = fmin(floor(u1), km1), k2 = fmin(floor(u2), km2);
                 const double t0 = u0 - k0, t1 = u1 - k1, t2 = u2 - k2;
                 double v[8];
-                if (lds) {
-                    const int b0 = (int)fma(ex0, fma(ex1, k2 - lo2, k1 - lo1), k0 - lo0);
-                    v[0] = sl[b0];
-                    v[1] = sl[b0 + 1];
-                    v[2] = sl[b0 + dd1];
-                    v[3] = sl[b0 + dd1 + 1];
-                    v[4] = sl[b0 + dd2];
-                    v[5] = sl[b0 + dd2 + 1];
-                    v[6] = sl[b0 + dd2 + dd1];
-                    v[7] = sl[b0 + dd2 + dd1 + 1];
-                } else {
-                    const unsigned cc = (unsigned)fma(double(n[0]), fma(double(n[1]), k2, k1), k0);
-                    const double2* pq = q8 + 4 * (size_t)cc;
-                    for (int x = 0; x < 4; ++x) {
-                        const double2 d = pq[x];
-                        v[2 * x] = d.x;
-                        v[2 * x + 1] = d.y;
-                    }
-                }
+                corners(k0, k1, k2, v);
                 double c00 = v[0] + t0 * (v[1] - v[0]);
                 double c10 = v[2] + t0 * (v[3] - v[2]);
                 double c0 = c00 + t1 * (c10 - c00);
@@ -1028,6 +1012,31 @@ __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
                 double c11 = v[6] + t0 * (v[7] - v[6]);
                 double c1 = c01 + t1 * (c11 - c01);
                 s += c0 + t2 * (c1 - c0);
+            };
+            if (lds) {
+                auto from_lds = [&](double k0, double k1, double k2, double* v) {
+                    const double* c = sl + (int)(fma(double(P * P), k2, fma(double(P), k1, k0)) - off);
+                    v[0] = c[0];
+                    v[1] = c[1];
+                    v[2] = c[P];
+                    v[3] = c[P + 1];
+                    v[4] = c[P * P];
+                    v[5] = c[P * P + 1];
+                    v[6] = c[P * P + P];
+                    v[7] = c[P * P + P + 1];
+                };
+                for (int q = qa; q <= qb; ++q) sample(q, from_lds);
+            } else {
+                auto from_table = [&](double k0, double k1, double k2, double* v) {
+                    const unsigned cc = (unsigned)fma(double(n[0]), fma(double(n[1]), k2, k1), k0);
+                    const double2* pq = q8 + 4 * (size_t)cc;
+                    for (int x = 0; x < 4; ++x) {
+                        const double2 d = pq[x];
+                        v[2 * x] = d.x;
+                        v[2 * x + 1] = d.y;
+                    }
+                };
+                for (int q = qa; q <= qb; ++q) sample(q, from_table);
             }
             rs[j] = s;
         }
@@ -1054,12 +1063,13 @@ __global__ __launch_bounds__(kOpsLdsThreads) void k_ops_het_lds(
 }
 
 // Windows per pair for k_ops_het_lds at box width w (in cells): the fewest whose
-// boxes fit the LDS capacity for offsets up to 3 boxes; 0 when none up to 32 do.
+// boxes fit kOpsLdsSide cells per axis for offsets up to 3 boxes; 0 when none up
+// to 32 do.
 inline int ops_lds_windows(int wc)
 {
     for (int nw = 1; nw <= 32; ++nw) {
         const long side = wc + (3L * wc + nw - 1) / nw + 5;
-        if (side * side * side <= kOpsLdsCap) return nw;
+        if (side <= kOpsLdsSide) return nw;
     }
     return 0;
 }
