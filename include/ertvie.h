@@ -204,10 +204,14 @@ typedef struct {
     int restarts;         /* GMRES cycles after the first (refinement steps for mixed) */
     double rel_resid_est; /* last Arnoldi estimate */
     double rel_resid_true;/* ||phi - (I - K) U|| / ||phi|| with the plan's operator */
-    double t_solve;       /* seconds, host wall clock, phi included */
+    double t_solve;       /* seconds, host wall clock, phi included (FMM data built before) */
     int rejected;         /* preconditioned corrections rejected by the residual check */
     int precond_applies;  /* network applications */
     int history_count;    /* (iterate, residual) pairs written to opts->history */
+    double t_setup;       /* seconds this call spent building FMM data for its operators
+                             (first use of a precision: the inner operator of mixed solves,
+                             or an FMM not yet built by an apply or ert_vie_fmm_info); not
+                             part of t_solve */
 } ert_solve_info;
 
 /* Build a plan: validate and copy the media, place the collocation grid and

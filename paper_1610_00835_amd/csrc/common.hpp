@@ -396,6 +396,8 @@ ert_status selfcell_constant(ert_plan_impl* p, double sigma, double* value);
 ert_status direct_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
 ert_status fmm_apply(ert_plan_impl* p, int op, int prec, const double* x, double* y, int nrhs);
 ert_status fmm_info(ert_plan_impl* p, int prec, ert_fmm_info* info);
+// Build the FMM data of precision `prec` if not built yet (tree, operators, caches).
+ert_status fmm_build(ert_plan_impl* p, int prec);
 void fmm_destroy(FmmData* f);
 void het_destroy(HetCache* c);
 // FFT-based preconditioner of the mean medium (fftpc.hip): z = M r for nrhs

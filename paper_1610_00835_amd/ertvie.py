@@ -47,7 +47,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("rel_resid_est", ctypes.c_double),
                 ("rel_resid_true", ctypes.c_double), ("t_solve", ctypes.c_double),
-                ("rejected", ctypes.c_int), ("precond_applies", ctypes.c_int), ("history_count", ctypes.c_int)]
+                ("rejected", ctypes.c_int), ("precond_applies", ctypes.c_int), ("history_count", ctypes.c_int),
+                ("t_setup", ctypes.c_double)]
 
 
 class NetOpts(ctypes.Structure):

@@ -148,11 +148,17 @@ def test_block_gmres_mixed(ev, oracle_mod):
 
 
 def test_solve_fmm_mixed_c2(ev, oracle_mod):
-    """32^3: FP64 FMM outer residual with FP32 FMM inner solves, against the oracle's solve on sampled rows."""
+    """32^3: FP64 FMM outer residual with FP32 FMM inner solves, against the oracle's solve on
+    sampled rows.  The first solve on the fresh plan builds both FMMs before its clock starts
+    (t_setup); the second reuses them and takes the same steps to the same solution."""
     case = inputs.make_case("c2", seed=0)
     P = oracle_problem(oracle_mod, case)
     with ev.plan_from_case(case, method="fmm", prec="fp64") as plan:
         Ug, ig = _solve(plan, case["f"], tol=1e-9, mixed=True, inner_tol=1e-4)
+        U2, i2 = _solve(plan, case["f"], tol=1e-9, mixed=True, inner_tol=1e-4)
+    log("setup of the first solve", ig["t_setup"], "of the second", i2["t_setup"])
+    assert ig["t_setup"] > 0.0 and i2["t_setup"] < 0.1 * ig["t_setup"]
+    assert i2["iters"] == ig["iters"] and np.array_equal(U2, Ug)
     assert ig["converged"] == 1
     # the oracle's residual of the GPU solution on sampled rows: r = phi - (U - A S U)
     rows = np.random.default_rng(5).choice(P.N, size=300, replace=False)
