@@ -108,20 +108,28 @@ def test_fmm_ragged(ev, oracle_mod, n, leaf):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("forms", [None, "1", "4", "5"])
+@pytest.mark.parametrize("forms", [None, (1, 1), (4, 4), (5, 4)])
 def test_fmm_multi_rhs_and_determinism(ev, oracle_mod, forms):
     """Repeated applies return the same bits.  Each right-hand-side count tunes its own
     execution forms, which may sum in different orders: the columns of a 5-column apply
     agree with single-column applies to FP32 rounding, and bit for bit once the forms are
-    fixed (the plan's `form` option), since every form reduces each column on its own."""
+    fixed (the plan's `form` option, (near field, translations)), since every form reduces
+    each column on its own.  A form that does not apply to a product leaves it to the timing
+    (form 5 takes reduction lengths up to 240, shorter than this plan's compressed
+    translations at order 8), so the forms in use are checked to be the requested ones."""
     case = inputs.make_case("c2", n=(16, 16, 16), seed=3)
     X = inputs.random_vector(4096, 9, nrhs=5)
-    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=5, leaf=4,
-                           form=int(forms) if forms else None) as plan:
+    with ev.plan_from_case(case, method="fmm", prec="fp32", nrhs_max=5, leaf=4, form=forms) as plan:
         Y = gpu_apply(plan, X, ev.OP_A)
         Y2 = gpu_apply(plan, X, ev.OP_A)
         Y3 = gpu_apply(plan, X, ev.OP_A)
         assert np.array_equal(Y, Y2) and np.array_equal(Y, Y3)
+        if forms:
+            gpu_apply(plan, X[:, 0], ev.OP_A)
+            info = plan.fmm_info()
+            log("fixed forms", forms, "in use: near", info["form_near"], "far", info["form_far"])
+            assert info["form_near"] == forms[0]
+            assert all(f == forms[1] for f in info["form_far"][2:])
         bar = 1e-12 if forms else 1e-6
         for b in range(5):
             yb = gpu_apply(plan, X[:, b], ev.OP_A)
