@@ -1874,7 +1874,8 @@ ert_status het_far_level(ert_plan_impl* p, const FmmTree& tr, const double* cheb
     // budget of the stored translation matrices: the plan's option, else 90 % of the
     // free device memory; both orders' caches count against it
     size_t fr = 0, tot = 0;
-    size_t avail = (hipMemGetInfo(&fr, &tot) == hipSuccess) ? fr / 10 * 9 : 0;
+    ERT_HIP(hipMemGetInfo(&fr, &tot));
+    size_t avail = fr / 10 * 9;
     if (p->o.far_cache_gb > 0.0) {
         size_t used = hc->far_bytes;
         for (int i = 0; i < 2; ++i)
